@@ -1,0 +1,339 @@
+"""Pins of the FP64 oracle against things other than itself: published values,
+library routines (scipy, pandas), closed forms, invariants and hand-worked
+fixtures.  CPU only."""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.cluster.vq import vq
+from scipy.spatial import cKDTree
+from scipy.spatial.distance import cdist
+
+from oracle import exact, gkmeans, knng, metrics, rng, twomeans
+from paper_1705_01813_amd import datagen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- RNG ----
+
+def test_splitmix64_published_sequence():
+    vals = [int(l, 16) for l in open(os.path.join(GOLD, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    got = [rng.draw(0, c) for c in range(len(vals))]
+    assert got == vals
+    got_np = [int(rng.draw_np(np.zeros(1, np.uint64), c)[0]) for c in range(len(vals))]
+    assert got_np == vals
+
+
+def test_below_and_floyd_are_uniform_and_distinct():
+    key = rng.stream_key(7, rng.stream_id(rng.PURPOSE_GRAPH_INIT, 0, 3))
+    s = rng.floyd_sample(key, 1000, 1000)
+    assert sorted(s) == list(range(1000))
+    # chi-square on below(): 64 bins, 64k draws
+    r = rng.draw_np(np.full(65536, rng.stream_key(1, 2), np.uint64), 0)
+    keys = rng.mix64_np(np.arange(65536, dtype=np.uint64))
+    v = rng.below_np(rng.draw_np(keys, 0), 64).astype(np.int64)
+    h = np.bincount(v, minlength=64)
+    chi2 = ((h - 1024.0) ** 2 / 1024.0).sum()
+    assert chi2 < 120  # 63 dof: p ~ 1e-5 threshold
+    # Floyd: every value equally likely to be chosen (m=20, cnt=5, 20000 rows)
+    keys = rng.mix64_np(np.arange(20000, dtype=np.uint64) + np.uint64(99))
+    rows = rng.floyd_sample_rows(keys, 20, 5)
+    assert all(len(set(r)) == 5 for r in rows[:200])
+    cnt = np.bincount(rows.ravel(), minlength=20)
+    exp = 20000 * 5 / 20
+    assert (((cnt - exp) ** 2) / exp).sum() < 50
+    # vectorised rows equal the scalar algorithm
+    for r in range(5):
+        assert list(rows[r]) == rng.floyd_sample(int(keys[r]), 20, 5)
+
+
+# ------------------------------------------------------- assignment ----
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_assign_hand_worked(case):
+    c = _gold("assign_1d.json")["cases"][case]
+    lab, best, moved = gkmeans.gk_assign(np.array(c["X"], np.float32), np.array(c["C"], np.float32),
+                                         np.array(c["labels_in"]), np.array(c["G"]))
+    assert lab.tolist() == c["labels_out"]
+    assert np.allclose(best, c["best_d2"])
+    assert moved == c["moved"]
+
+
+def test_assign_kappa_ge_k_is_lloyd():
+    X = datagen.mixture(600, 8, 12, seed=3, sigma=1.5)
+    rs = np.random.default_rng(0)
+    C = X[rs.choice(600, 10, replace=False)] + 0.1
+    labels_in = rs.integers(0, 10, 600)
+    G = np.stack([rs.choice(np.delete(np.arange(600), i), 10, replace=False) for i in range(600)])
+    lab, _, _ = gkmeans.gk_assign(X, C, labels_in, G)
+    ref = cdist(X.astype(np.float64), C.astype(np.float64), "sqeuclidean").argmin(1)
+    assert (lab == ref).all()
+
+
+def test_assign_complete_graph_is_lloyd_over_nonempty():
+    X = datagen.mixture(120, 5, 6, seed=5, sigma=2.0)
+    k = 40
+    rs = np.random.default_rng(1)
+    C = rs.normal(size=(k, 5)).astype(np.float32) * 8
+    labels_in = rs.integers(0, 25, 120)  # clusters 25..39 hold no sample
+    G = np.stack([np.delete(np.arange(120), i) for i in range(120)])  # kappa = n-1 = 119 >= k
+    G = G[:, :119]
+    # kappa >= k: candidates are all clusters -> plain Lloyd
+    lab_all, _, _ = gkmeans.gk_assign(X, C, labels_in, G)
+    assert (lab_all == cdist(X.astype(np.float64), C.astype(np.float64), "sqeuclidean").argmin(1)).all()
+    # kappa < k with the complete graph (k raised above n-1): candidates are the
+    # non-empty clusters, so the sweep is Lloyd restricted to them
+    k2 = 200
+    C2 = np.concatenate([C, rs.normal(size=(k2 - k, 5)).astype(np.float32)])
+    lab, _, _ = gkmeans.gk_assign(X, C2, labels_in, G)
+    D = cdist(X.astype(np.float64), C2.astype(np.float64), "sqeuclidean")
+    allowed = np.unique(labels_in)
+    ref = allowed[D[:, allowed].argmin(1)]
+    assert (lab == ref).all()
+
+
+def test_assign_tiny_enumeration():
+    """n <= 12: Q_i written out element by element with Python sets."""
+    rs = np.random.default_rng(2)
+    for trial in range(20):
+        n, d, k, kappa = 12, 3, 5, 3
+        X = rs.normal(size=(n, d)).astype(np.float32)
+        C = rs.normal(size=(k, d)).astype(np.float32)
+        lab_in = rs.integers(0, k, n)
+        G = np.stack([rs.choice(np.delete(np.arange(n), i), kappa, replace=False) for i in range(n)])
+        lab, _, _ = gkmeans.gk_assign(X, C, lab_in, G)
+        for i in range(n):
+            Q = {int(lab_in[i])} | {int(lab_in[j]) for j in G[i]}
+            dist = {q: float(sum((float(X[i, t]) - float(C[q, t])) ** 2 for t in range(d))) for q in Q}
+            m = min(dist.values())
+            want = int(lab_in[i]) if dist[int(lab_in[i])] == m else min(q for q in Q if dist[q] == m)
+            assert lab[i] == want
+
+
+# ----------------------------------------------------------- update ----
+
+def test_update_hand_worked_and_identity():
+    u = _gold("assign_1d.json")["update"]
+    X = np.array(u["X"], np.float32)
+    C, counts, sums = gkmeans.centroid_update(X, np.array(u["labels"]), 4, np.array(u["C_prev"], np.float32))
+    assert np.allclose(C, np.array(u["C"], np.float32))
+    assert counts.tolist() == u["counts"]
+    E_exact_means = gkmeans.distortion(X, np.where(counts[:, None] > 0, sums / np.maximum(counts, 1)[:, None], 0),
+                                       np.array(u["labels"]))
+    assert abs(E_exact_means - u["E"]) < 1e-12
+    assert abs(gkmeans.distortion_identity(X, sums, counts) - u["E"]) < 1e-12
+
+
+def test_update_matches_pandas_groupby():
+    import pandas as pd
+
+    X = datagen.mixture(3000, 7, 20, seed=8)
+    labels = np.random.default_rng(3).integers(0, 50, 3000)
+    labels[labels == 17] = 18  # make cluster 17 empty
+    Cprev = np.full((50, 7), -1.0, np.float32)
+    C, counts, sums = gkmeans.centroid_update(X, labels, 50, Cprev)
+    df = pd.DataFrame(X.astype(np.float64))
+    df["l"] = labels
+    g = df.groupby("l")
+    mean = g.mean()
+    assert (counts[mean.index] == g.size().values).all()
+    assert counts.sum() == 3000 and counts[17] == 0
+    assert np.array_equal(C[mean.index], mean.values.astype(np.float32))
+    assert (C[17] == -1).all()
+    assert np.allclose(counts[:, None] * C.astype(np.float64), sums, rtol=1e-6)
+
+
+def test_update_integer_data_sums_exact():
+    import pandas as pd
+
+    X = datagen.integer_grid(5000, 16, seed=4)
+    labels = np.random.default_rng(5).integers(0, 64, 5000)
+    _, counts, sums = gkmeans.centroid_update(X, labels, 64, np.zeros((64, 16), np.float32))
+    df = pd.DataFrame(X.astype(np.int64))
+    df["l"] = labels
+    ref = df.groupby("l").sum().values.astype(np.float64)
+    assert np.array_equal(sums, ref)  # integer sums far below 2^53 are exact
+
+
+# -------------------------------------------------------- distortion ----
+
+def test_distortion_matches_vq_and_identity():
+    X = datagen.mixture(4000, 12, 30, seed=9)
+    labels = np.random.default_rng(6).integers(0, 30, 4000)
+    C, counts, sums = gkmeans.centroid_update(X, labels, 30, np.zeros((30, 12), np.float32))
+    E = gkmeans.distortion(X, C, labels)
+    # scipy.cluster.vq: distance of each sample to its own code (a code book of one row each)
+    dist = np.array([vq(X[i:i + 1].astype(np.float64), C[labels[i]:labels[i] + 1].astype(np.float64))[1][0]
+                     for i in range(0, 4000, 1)])
+    assert abs(E - (dist ** 2).mean()) <= 1e-10 * E
+    means = sums / counts[:, None]
+    assert abs(gkmeans.distortion(X, means, labels) - gkmeans.distortion_identity(X, sums, counts)) <= 1e-12 * E
+
+
+def test_fit_distortion_never_increases():
+    X = datagen.mixture(2000, 6, 25, seed=10)
+    G, _ = exact.brute_knn(X, 8)
+    for init in (gkmeans.INIT_RANDOM, gkmeans.INIT_TWOMEANS):
+        lab, C, counts, trace, it, moved = gkmeans.fit(X, 25, G, 10, seed=3, init=init)
+        assert (np.diff(trace) <= 1e-12 * trace[0]).all(), trace
+        assert counts.sum() == 2000
+        # every centroid equals the mean of its members
+        C2, _, _ = gkmeans.centroid_update(X, lab, 25, C)
+        assert np.array_equal(C, C2)
+        # a further sweep from a fixed point moves nothing
+        if moved[-1] == 0:
+            l2, _, m2 = gkmeans.gk_assign(X, C, lab, G)
+            assert m2 == 0 and (l2 == lab).all()
+
+
+def test_random_init_labels_are_exhaustive_argmin():
+    X = datagen.mixture(500, 4, 10, seed=11)
+    lab0, C0 = gkmeans.init_labels(X, 10, 5, gkmeans.INIT_RANDOM)
+    ids = gkmeans.random_init_ids(500, 10, 5)
+    assert len(set(ids.tolist())) == 10
+    assert np.array_equal(C0, X[ids])
+    assert (lab0 == cdist(X.astype(np.float64), C0.astype(np.float64), "sqeuclidean").argmin(1)).all()
+
+
+# ---------------------------------------------------------- TwoMeans ----
+
+def _check_tree(X, k, seed):
+    lab, nodes = twomeans.twomeans(X, k, seed, 0, return_nodes=True)
+    n = X.shape[0]
+    assert len(nodes) == k
+    assert np.array_equal(np.sort(np.concatenate(nodes)), np.arange(n))
+    sizes = sorted({len(S) for S in nodes})
+    assert len(sizes) <= 4
+    # shape predicted from (n, k) alone
+    shape = twomeans.tree_shape(n, k)
+    return lab, nodes, shape
+
+
+@pytest.mark.parametrize("n,k", [(1000, 7), (1000, 16), (777, 100), (64, 64), (50, 1), (300, 299)])
+def test_twomeans_balanced(n, k):
+    X = datagen.mixture(n, 5, 9, seed=n + k)
+    lab, nodes, shape = _check_tree(X, k, seed=1)
+    sizes = [len(S) for S in nodes]
+    if k == n:
+        assert sizes == [1] * n
+    if k == 1:
+        assert (lab == 0).all()
+    assert np.bincount(lab, minlength=k).tolist() == sizes
+
+
+def test_twomeans_split_invariant():
+    X = datagen.mixture(500, 6, 5, seed=3).astype(np.float32)
+    X64 = X.astype(np.float64)
+    S = np.arange(500)
+    L, R, cu, cv = twomeans.bisect(X64, S, seed=4, rnd=0, depth=0, node=0)
+    assert len(L) == 250 and len(R) == 250
+    du = ((X64 - cu.astype(np.float64)) ** 2).sum(1)
+    dv = ((X64 - cv.astype(np.float64)) ** 2).sum(1)
+    delta = du - dv
+    assert delta[L].max() <= delta[R].min()
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 5])
+def test_twomeans_1d_quantile_bins(L):
+    """d=1, k=2^L: delta is monotone in x, so every leaf is a run of consecutive
+    values of the sorted data with the balanced sizes."""
+    rs = np.random.default_rng(L)
+    n = 1000 + 37 * L
+    X = rs.normal(size=(n, 1)).astype(np.float32)
+    lab = twomeans.twomeans(X, 2 ** L, seed=9, rnd=0)
+    order = np.argsort(X[:, 0], kind="stable")
+    runs = lab[order]
+    changes = np.count_nonzero(np.diff(runs))
+    assert changes == 2 ** L - 1  # each leaf is one contiguous run
+    sizes = np.bincount(lab)
+    expected = [n]
+    for _ in range(L):
+        expected = [s for e in expected for s in ((e + 1) // 2, e // 2)]
+    assert sorted(sizes.tolist()) == sorted(expected)
+
+
+# ------------------------------------------------------------- graph ----
+
+def test_graph_hand_worked():
+    g = _gold("assign_1d.json")["graph"]
+    X = np.array(g["X"], np.float32)
+    ids, d2 = knng.knn_build(X, g["kappa"], xi=50, tau=1, seed=3)
+    assert ids.tolist() == g["ids"]
+    assert d2.tolist() == g["d2"]
+
+
+def _check_rows(X, ids, d2):
+    X64 = X.astype(np.float64)
+    n, kappa = ids.shape
+    for i in range(n):
+        assert i not in ids[i]
+        assert len(set(ids[i].tolist())) == kappa
+        key = list(zip(d2[i].tolist(), ids[i].tolist()))
+        assert key == sorted(key)
+        rec = ((X64[ids[i]] - X64[i]) ** 2).sum(1).astype(np.float32)
+        assert np.array_equal(rec, d2[i])
+
+
+def test_graph_init_rows_valid():
+    X = datagen.mixture(300, 4, 5, seed=12)
+    ids, d2 = knng.graph_init(X, 10, seed=2)
+    _check_rows(X, ids, d2)
+    ids2, _ = knng.graph_init(X[:11], 10, seed=2)  # kappa = n-1: everybody else
+    for i in range(11):
+        assert sorted(ids2[i].tolist()) == [j for j in range(11) if j != i]
+
+
+def test_one_round_with_one_cluster_is_exact_knn():
+    X = datagen.mixture(90, 6, 4, seed=13)  # n < 2*xi -> k0 = 1
+    ids, d2 = knng.knn_build(X, 7, xi=50, tau=1, seed=4)
+    _check_rows(X, ids, d2)
+    tree = cKDTree(X.astype(np.float64))
+    dd, ii = tree.query(X.astype(np.float64), k=8)
+    assert np.array_equal(ids, ii[:, 1:].astype(np.int32))  # continuous data: no ties
+    assert np.allclose(d2, (dd[:, 1:] ** 2), rtol=1e-6)
+    e_ids, e_d2 = exact.brute_knn(X, 7)
+    assert np.array_equal(ids, e_ids) and np.array_equal(d2, e_d2)
+
+
+def test_build_rounds_monotone_and_tau0():
+    X = datagen.mixture(1500, 8, 30, seed=14)
+    G0 = knng.graph_init(X, 10, seed=6)
+    ids0, d20 = knng.knn_build(X, 10, xi=50, tau=0, seed=6)
+    assert np.array_equal(ids0, G0[0]) and np.array_equal(d20, G0[1])
+    _, _, hist = knng.knn_build(X, 10, xi=50, tau=4, seed=6, history=True)
+    for (a_i, a_d), (b_i, b_d) in zip(hist, hist[1:]):
+        assert (b_d[:, -1] <= a_d[:, -1]).all()
+        assert (b_d[:, 0] <= a_d[:, 0]).all()
+    _check_rows(X, *hist[-1])
+    e_ids, e_d2 = exact.brute_knn(X, 10)
+    rec = metrics.recall_top1(hist[-1][1], e_d2[:, 0])
+    assert rec > 0.6  # Sec. 4.3: recall rises above 0.6 within a few rounds
+    assert metrics.recall_top1(hist[0][1], e_d2[:, 0]) < 0.05
+
+
+def test_exact_refs_match_scipy():
+    X = datagen.mixture(400, 5, 6, seed=15)
+    ids, d2 = exact.brute_knn(X, 5)
+    tree = cKDTree(X.astype(np.float64))
+    dd, ii = tree.query(X.astype(np.float64), k=6)
+    assert np.array_equal(ids, ii[:, 1:])
+    C = X[:9] + 0.5
+    assert (exact.lloyd_assign(X, C) == cdist(X.astype(np.float64), C.astype(np.float64), "sqeuclidean").argmin(1)).all()
+
+
+def test_gap_mask_flags_near_ties():
+    X = np.array([[0.0], [1.0]], np.float32)
+    C = np.array([[-1.0], [1.0], [3.0]], np.float32)
+    dec, best = metrics.assign_gap_mask(X, C, np.array([2, 2]), np.array([[1], [0]]))
+    # Q = {2} only (both neighbours are in cluster 2): a single candidate is decided
+    assert dec.tolist() == [True, True]
+    dec, _ = metrics.assign_gap_mask(X, C, np.array([0, 1]), np.array([[1], [0]]))
+    assert dec.tolist() == [False, True]  # x=0 is equidistant from -1 and 1
