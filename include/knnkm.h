@@ -1,0 +1,177 @@
+/*
+ * knnkm.h — C ABI of the MI355X (gfx950) library for KNN-graph-supported
+ * k-means (C.-H. Deng and W.-L. Zhao, "Fast k-means based on KNN Graph",
+ * arXiv 1705.01813).
+ *
+ * Problem statement (Sec. 1, Eqn. 1): n samples x_i in R^d and an integer k;
+ * minimise the sum of squared distances from every sample to the centroid of
+ * its cluster.  The method (Sec. 4) restricts each sample's nearest-centroid
+ * search to the clusters its kappa graph neighbours belong to (Alg. 2), and
+ * builds that graph by repeatedly clustering the data into small clusters of
+ * about xi samples and comparing all pairs inside each one (Alg. 3).
+ *
+ * Conventions for every entry point
+ *  - X is float32, row-major, n rows of d values with leading dimension
+ *    ldx >= d (elements).  Sample ids and cluster labels are int32, so
+ *    n <= 2^31-1; sizes are int64.
+ *  - All pointers named X, C, G_ids, G_d2, labels*, counts, sums, best_d2,
+ *    n_moved, E are DEVICE pointers on the context's device, owned by the
+ *    caller, contiguous.  Pointers named *_host are host memory.
+ *  - Distances are squared L2 (Eqn. 1, Eqn. 4).  Graph rows hold kappa
+ *    (id, d2) entries ordered by (d2, id) ascending; d2 is the float32
+ *    rounding of the pair's squared distance.
+ *  - Kernel-level calls (knn_assign, centroid_update, distortion,
+ *    knnkm_twomeans, knnkm_graph_init, knnkm_graph_refine, knn_build) are
+ *    asynchronous on the context's HIP stream.  knn_kmeans_fit synchronises
+ *    the stream before returning because it writes host memory.
+ *  - Every call returns a knnkm_status; nothing throws or aborts across the
+ *    ABI.  Arguments are validated on the host before any launch; on a
+ *    non-OK status the outputs are unspecified and knnkm_last_error() holds a
+ *    message.  A HIP runtime error makes the context unusable
+ *    (KNNKM_EDEVICE is sticky).
+ *  - The library owns only its context workspace (device memory grown on
+ *    demand, released by knnkm_destroy).
+ */
+#ifndef KNNKM_H
+#define KNNKM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KNNKM_OK = 0,
+  KNNKM_EINVAL = 1,      /* invalid argument (checked before any launch) */
+  KNNKM_ENOMEM = 2,      /* workspace allocation failed */
+  KNNKM_EDEVICE = 3,     /* HIP runtime error; sticky for the context */
+  KNNKM_EUNSUPPORTED = 4 /* valid request outside the implemented limits */
+} knnkm_status;
+
+enum { KNNKM_FP32 = 0, KNNKM_BF16_RERANK = 1 };
+enum { KNNKM_INIT_TWOMEANS = 0, KNNKM_INIT_RANDOM = 1 };
+
+/* Limits of this implementation (KNNKM_EUNSUPPORTED beyond them). */
+#define KNNKM_MAX_D 512     /* dimensions per sample */
+#define KNNKM_MAX_KAPPA 128 /* neighbours per graph row */
+
+typedef struct {
+  uint32_t struct_size; /* sizeof(knnkm_params) */
+  int32_t kappa;        /* graph width kappa (Alg. 2 / Alg. 3); paper default 50 (Sec. 4.4) */
+  int32_t xi;           /* cluster size of graph construction (Sec. 4.3); default 50 */
+  int32_t tau;          /* graph construction rounds (Alg. 3); default 10 */
+  int32_t bisect_iters; /* Lloyd 2-means steps per bisection of Alg. 1; default 2 */
+  int32_t precision;    /* KNNKM_FP32 or KNNKM_BF16_RERANK (pair filter of knn_build) */
+  int32_t init;         /* KNNKM_INIT_TWOMEANS (Alg. 2 start) or KNNKM_INIT_RANDOM */
+  int32_t max_iters;    /* fit iterations T; the paper runs 30 (Sec. 5.4) */
+  int32_t early_stop;   /* 1: stop after an iteration that moved no sample (Sec. 1 convergence) */
+  uint64_t seed;        /* keys every random draw (graph init, bisection seeds, random init) */
+} knnkm_params;
+
+typedef struct knnkm_ctx knnkm_ctx;
+
+/* Create a context on HIP device `device`, launching on `hip_stream`
+ * (a hipStream_t, or NULL for the null stream).  device = -1 creates a dry
+ * context that validates arguments and returns before any device work. */
+knnkm_status knnkm_create(int device, void* hip_stream, knnkm_ctx** out);
+knnkm_status knnkm_destroy(knnkm_ctx* ctx);
+/* Switch the launch stream of an existing context. */
+knnkm_status knnkm_set_stream(knnkm_ctx* ctx, void* hip_stream);
+const char* knnkm_last_error(const knnkm_ctx* ctx);
+knnkm_status knnkm_default_params(knnkm_params* p);
+/* Device bytes currently held by the context workspace. */
+knnkm_status knnkm_workspace_bytes(const knnkm_ctx* ctx, int64_t* out);
+
+/* Graph-restricted assignment, one Jacobi sweep (Alg. 2 candidate collection,
+ * Lloyd form of Sec. 4.2 "GK-means^-").
+ *  Q_i = {labels_in[i]} U {labels_in[G_ids[i*kappa + j]] : j < kappa}; if
+ *  kappa >= k, Q_i = {0..k-1}.  labels_out[i] = the closest centroid in Q_i;
+ *  the sample stays unless some candidate is strictly closer, and among equal
+ *  minima the smallest id wins.  Decisions are exact up to float64 rounding
+ *  (float32 evaluation, float64 re-evaluation of near ties).
+ *  C: k x d float32, row-major (leading dimension d).  G_ids: n x kappa int32
+ *  with ids in [0,n).  labels_in must not alias labels_out.
+ *  best_d2 (nullable): n floats, squared distance to the chosen centroid.
+ *  n_moved (nullable, device int64): receives the number of i with
+ *  labels_out[i] != labels_in[i] (overwritten, not accumulated).
+ *  G_ids may be NULL when kappa >= k. */
+knnkm_status knn_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                        const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
+                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
+                        int64_t* n_moved);
+
+/* Centroid update (Sec. 1: each centroid becomes the average of its
+ * members; Eqn. 2 composite vectors D_r).  counts[r] = n_r; sums (nullable)
+ * receives D_r as float64 k x d; C[r] (in: previous centroids, out: new) is
+ * the float64 mean rounded to float32, and is left unchanged when n_r = 0.
+ * Labels must lie in [0,k). */
+knnkm_status centroid_update(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                             const int32_t* labels, int32_t k, float* C, int32_t* counts,
+                             double* sums);
+
+/* Average distortion, Eqn. 4: E = sum_i ||x_i - C_{labels[i]}||^2 / n,
+ * evaluated in float64 with a fixed reduction order; *E (device double). */
+knnkm_status distortion(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                        const float* C, int32_t k, const int32_t* labels, double* E);
+
+/* Two-means tree, Alg. 1: labels in [0,k) from a level-synchronous balanced
+ * bisection.  Every split seeds two centroids from two distinct members
+ * (counter-based draws keyed by seed, round_tag and the node), runs
+ * bisect_iters Lloyd 2-means steps, then orders the members by
+ * delta = ||x-c_u||^2 - ||x-c_v||^2 (ties by id) and gives the first
+ * ceil(s/2) to the left child.  Leaves are numbered left to right.
+ * round_tag: 0..tau-1 for the calls inside knn_build, 0xFFFF for the fit. */
+knnkm_status knnkm_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                            int32_t k, uint64_t seed, int32_t round_tag, int32_t bisect_iters,
+                            int32_t* labels);
+
+/* Random initial KNN lists (Alg. 3 initialisation): row i holds kappa
+ * distinct ids != i (Floyd's sampling on a counter-based stream keyed by
+ * seed and i), with their squared distances, ordered by (d2, id).
+ * Requires 1 <= kappa <= n-1. */
+knnkm_status knnkm_graph_init(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                              int32_t kappa, uint64_t seed, int32_t* G_ids, float* G_d2);
+
+/* Alg. 3 inner loops for one partition: for every cluster S_m of `labels`
+ * (values in [0,k)), every pair <i,j> of S_m updates G[i] and G[j]: a pair
+ * whose id is not yet in the row enters it if its (d2, id) is among the
+ * kappa smallest.  Pair distances are screened on MFMA (float32, or bfloat16
+ * with precision = KNNKM_BF16_RERANK) with a rigorous error margin against
+ * the row's current kappa-th distance; survivors are re-evaluated exactly.
+ * Both precisions give identical graphs.  G_ids/G_d2 are updated in place. */
+knnkm_status knnkm_graph_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                                const int32_t* labels, int32_t k, int32_t precision,
+                                int32_t* G_ids, float* G_d2, int32_t kappa);
+
+/* KNN graph construction, Alg. 3: random initial lists, then tau rounds of
+ * {TwoMeans into k0 = max(1, floor(n/xi)) clusters; one GK-means^- sweep
+ * with the current graph; exhaustive comparison inside each cluster}.
+ * Uses params->kappa, xi, tau, bisect_iters, precision, seed.
+ * G_ids: n x kappa int32, G_d2: n x kappa float32 (outputs). */
+knnkm_status knn_build(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                       const knnkm_params* params, int32_t* G_ids, float* G_d2);
+
+/* GK-means^- fit (Alg. 2, Lloyd form): initial labels from Alg. 1 (or, with
+ * init = KNNKM_INIT_RANDOM, k distinct rows as seeds and an exhaustive
+ * assignment), C_0 = their means; then for t = 1..max_iters: knn_assign with
+ * G_ids, centroid update, distortion.  trace_host (max_iters+1 doubles, host)
+ * receives E_0..E_T (Eqn. 4); iters_run_host the number of sweeps done.
+ * Outputs labels (n), C (k x d), counts (k) on the device.  Synchronous. */
+knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                            int32_t k, const int32_t* G_ids, const knnkm_params* params,
+                            int32_t* labels, float* C, int32_t* counts, double* trace_host,
+                            int32_t* iters_run_host);
+
+/* Counter-based generator used for every random draw of the method
+ * (SplitMix64 output function applied to key + (ctr+1)*0x9E3779B97F4A7C15,
+ * key = mix(seed ^ mix(stream))).  Writes out[c] = draw(ctr0 + c) for
+ * c < count into a device uint64 buffer.  Exposed so both implementations of
+ * the generator can be compared. */
+knnkm_status knnkm_rng_draw(knnkm_ctx* ctx, uint64_t seed, uint64_t stream, uint64_t ctr0,
+                            int64_t count, uint64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KNNKM_H */

@@ -1,0 +1,152 @@
+// Shared host/device definitions of the knnkm HIP library (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/knnkm.h"
+
+// ------------------------------------------------------------------ context --
+
+struct knnkm_buf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct knnkm_ctx {
+  int device = -1;
+  bool dry = false;
+  hipStream_t stream = nullptr;
+  bool sticky = false;
+  std::string err;
+  int num_cus = 256;
+  std::unordered_map<std::string, knnkm_buf> ws;  // named workspace buffers
+  // cached two-means tree metadata (depends on n and k only)
+  struct TMPlan* tm_plan = nullptr;
+};
+void tm_plan_free(struct TMPlan* p);
+
+// Set the context error and return the status.
+knnkm_status knnkm_fail(knnkm_ctx* ctx, knnkm_status st, const char* fmt, ...);
+// Device buffer of at least `bytes` bytes, grown on demand (contents are not
+// preserved across growth).  Returns nullptr and sets ENOMEM on failure.
+void* knnkm_ws(knnkm_ctx* ctx, const char* name, size_t bytes);
+// Check the HIP status of the last launches; sets the sticky error.
+knnkm_status knnkm_check(knnkm_ctx* ctx, const char* where);
+
+#define KNNKM_TRY(expr)                         \
+  do {                                          \
+    knnkm_status _st = (expr);                  \
+    if (_st != KNNKM_OK) return _st;            \
+  } while (0)
+
+#define KNNKM_HIP(ctx, expr)                                                           \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess) {                                                            \
+      (ctx)->sticky = true;                                                            \
+      return knnkm_fail((ctx), KNNKM_EDEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
+    }                                                                                  \
+  } while (0)
+
+#define KNNKM_WS(ctx, var, type, name, count)                                      \
+  type* var = (type*)knnkm_ws((ctx), (name), sizeof(type) * (size_t)(count));      \
+  if (!(var)) return KNNKM_ENOMEM
+
+// ---------------------------------------------------------- random numbers --
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output c of a generator with
+// state `key` is mix(key + (c+1) * GAMMA).  Keys: mix(seed ^ mix(stream)).
+#define KNNKM_GAMMA 0x9E3779B97F4A7C15ull
+enum { RNG_GRAPH_INIT = 1, RNG_TWOMEANS = 2, RNG_RANDOM_INIT = 3 };
+#define KNNKM_ROUND_FIT 0xFFFF
+
+__host__ __device__ inline uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t sm_stream(uint64_t purpose, uint64_t round, uint64_t index) {
+  return (purpose << 56) | ((round & 0xFFFFull) << 40) | (index & ((1ull << 40) - 1));
+}
+__host__ __device__ inline uint64_t sm_key(uint64_t seed, uint64_t stream) {
+  return sm_mix(seed ^ sm_mix(stream));
+}
+__host__ __device__ inline uint64_t sm_draw(uint64_t key, uint64_t ctr) {
+  return sm_mix(key + (ctr + 1) * KNNKM_GAMMA);
+}
+// Integer in [0, m) from the high 32 bits (multiply-shift, no rejection).
+__host__ __device__ inline uint32_t sm_below(uint64_t r, uint32_t m) {
+  return (uint32_t)(((r >> 32) * (uint64_t)m) >> 32);
+}
+
+// --------------------------------------------------------- wave utilities --
+#define WAVE 64
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+__device__ inline int lane_id() { return threadIdx.x & (WAVE - 1); }
+__device__ inline uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
+
+// Order-preserving map of a double to uint64 (+0 and -0 map to the same key).
+__device__ inline uint64_t dkey(double v) {
+  if (v == 0.0) v = 0.0;
+  uint64_t b = (uint64_t)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// Blocks per launch for grid-stride kernels.
+inline int grid_for(int64_t work, int per_block, int cap) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+// ------------------------------------------------- internal building blocks --
+// (defined in the .hip files; all enqueue on ctx->stream)
+
+// Exclusive prefix sum of `count` int32 values (in may equal out); out[count]
+// receives the total when `with_total`.
+knnkm_status ks_scan_exclusive(knnkm_ctx* ctx, const int32_t* in, int32_t* out, int64_t count,
+                               bool with_total);
+// Stable sort of sample ids by label: offsets[k+1] and members[n] (ids of
+// cluster r at members[offsets[r] .. offsets[r+1]), ascending).
+knnkm_status ks_label_sort(knnkm_ctx* ctx, const int32_t* labels, int64_t n, int32_t k,
+                           int32_t* counts, int32_t* offsets, int32_t* members);
+// Segmented float64 sums over the CSR partition; means into C (unchanged
+// where empty); Iterm[r] = ||D_r||^2 / n_r (0 where empty).
+knnkm_status ks_segsum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                       int32_t k, const int32_t* counts, const int32_t* offsets,
+                       const int32_t* members, float* C, double* sums, double* Iterm);
+// Deterministic float64 sum of count values into *out (device).
+knnkm_status ks_sum_f64(knnkm_ctx* ctx, const double* in, int64_t count, double* out);
+// Assignment kernel launcher (order: optional visiting order of samples).
+knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                       const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
+                       const int32_t* labels_in, int32_t* labels_out, float* best_d2,
+                       int64_t* n_moved, const int32_t* order, bool dense);
+knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                         int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
+                         int32_t* labels);
+knnkm_status ks_graph_init(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                           int32_t kappa, uint64_t seed, int32_t* G_ids, float* G_d2);
+knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                       const int32_t* labels, int32_t k, int32_t precision, int32_t* G_ids,
+                       float* G_d2, int32_t kappa);
+// sum_i ||x_i - C_{labels[i]}||^2 * scale into *out (C null: sum of ||x_i||^2).
+knnkm_status ks_sqdist_sum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                           const float* C, const int32_t* labels, double* out, double scale);
+knnkm_status ks_fill_i64(knnkm_ctx* ctx, int64_t* p, int64_t count, int64_t v);
+knnkm_status ks_fill_i32(knnkm_ctx* ctx, int32_t* p, int64_t count, int32_t v);

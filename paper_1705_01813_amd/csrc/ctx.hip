@@ -1,0 +1,299 @@
+// Context, workspace, error handling and generic device primitives (fills,
+// exclusive scan, deterministic float64 sum, the counter-based generator).
+#include <cstdarg>
+#include <cstring>
+
+#include "common.h"
+
+knnkm_status knnkm_fail(knnkm_ctx* ctx, knnkm_status st, const char* fmt, ...) {
+  if (!ctx) return st;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  ctx->err = buf;
+  return st;
+}
+
+void* knnkm_ws(knnkm_ctx* ctx, const char* name, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  knnkm_buf& b = ctx->ws[name];
+  if (b.bytes >= bytes) return b.ptr;
+  if (b.ptr) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = bytes + bytes / 8;  // headroom against repeated growth
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    knnkm_fail(ctx, KNNKM_ENOMEM, "workspace '%s': cannot allocate %zu bytes", name, want);
+    return nullptr;
+  }
+  b.ptr = p;
+  b.bytes = want;
+  return p;
+}
+
+knnkm_status knnkm_check(knnkm_ctx* ctx, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    ctx->sticky = true;
+    return knnkm_fail(ctx, KNNKM_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+  }
+  return KNNKM_OK;
+}
+
+extern "C" knnkm_status knnkm_create(int device, void* hip_stream, knnkm_ctx** out) {
+  if (!out) return KNNKM_EINVAL;
+  *out = nullptr;
+  knnkm_ctx* ctx = new (std::nothrow) knnkm_ctx();
+  if (!ctx) return KNNKM_ENOMEM;
+  ctx->device = device;
+  ctx->dry = device < 0;
+  ctx->stream = (hipStream_t)hip_stream;
+  if (!ctx->dry) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+      (void)hipGetLastError();
+      delete ctx;
+      return KNNKM_EDEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+      delete ctx;
+      return KNNKM_EDEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
+  }
+  *out = ctx;
+  return KNNKM_OK;
+}
+
+extern "C" knnkm_status knnkm_destroy(knnkm_ctx* ctx) {
+  if (!ctx) return KNNKM_EINVAL;
+  if (!ctx->dry) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->ws)
+      if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+  }
+  tm_plan_free(ctx->tm_plan);
+  delete ctx;
+  return KNNKM_OK;
+}
+
+extern "C" knnkm_status knnkm_set_stream(knnkm_ctx* ctx, void* hip_stream) {
+  if (!ctx) return KNNKM_EINVAL;
+  ctx->stream = (hipStream_t)hip_stream;
+  return KNNKM_OK;
+}
+
+extern "C" const char* knnkm_last_error(const knnkm_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+extern "C" knnkm_status knnkm_default_params(knnkm_params* p) {
+  if (!p) return KNNKM_EINVAL;
+  memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(knnkm_params);
+  p->kappa = 50;
+  p->xi = 50;
+  p->tau = 10;
+  p->bisect_iters = 2;
+  p->precision = KNNKM_FP32;
+  p->init = KNNKM_INIT_TWOMEANS;
+  p->max_iters = 30;
+  p->early_stop = 0;
+  p->seed = 0;
+  return KNNKM_OK;
+}
+
+extern "C" knnkm_status knnkm_workspace_bytes(const knnkm_ctx* ctx, int64_t* out) {
+  if (!ctx || !out) return KNNKM_EINVAL;
+  int64_t s = 0;
+  for (auto& kv : ctx->ws) s += (int64_t)kv.second.bytes;
+  *out = s;
+  return KNNKM_OK;
+}
+
+// ------------------------------------------------------------------ fills --
+__global__ void k_fill_i64(int64_t* p, int64_t count, int64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+knnkm_status ks_fill_i64(knnkm_ctx* ctx, int64_t* p, int64_t count, int64_t v) {
+  if (count <= 0) return KNNKM_OK;
+  k_fill_i64<<<grid_for(count, 256, 4096), 256, 0, ctx->stream>>>(p, count, v);
+  return knnkm_check(ctx, "fill_i64");
+}
+knnkm_status ks_fill_i32(knnkm_ctx* ctx, int32_t* p, int64_t count, int32_t v) {
+  if (count <= 0) return KNNKM_OK;
+  k_fill_i32<<<grid_for(count, 256, 4096), 256, 0, ctx->stream>>>(p, count, v);
+  return knnkm_check(ctx, "fill_i32");
+}
+
+// ------------------------------------------------------- exclusive scan --
+// Tiles of SCAN_TILE values per 256-thread block; tile totals are scanned
+// recursively, then added back.
+#define SCAN_TILE 1024
+
+__device__ inline int32_t block_scan_excl_256(int32_t v, int32_t* sh /*[8]*/, int32_t* total) {
+  // inclusive wave scan
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  int32_t base = 0, tot = 0;
+  for (int j = 0; j < 4; ++j) {
+    if (j < w) base += sh[j];
+    tot += sh[j];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t* in, int32_t* out, int64_t count,
+                                                    int32_t* tile_sums) {
+  __shared__ int32_t sh[8];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 4;
+  int32_t v[4];
+  int32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    v[j] = (base + j < count) ? in[base + j] : 0;
+    s += v[j];
+  }
+  int32_t tot;
+  int32_t ex = block_scan_excl_256(s, sh, &tot);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < count) out[base + j] = ex;
+    ex += v[j];
+  }
+  if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_add(int32_t* out, int64_t count, const int32_t* tile_offsets) {
+  int64_t i = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 4;
+  int32_t add = tile_offsets[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (i + j < count) out[i + j] += add;
+}
+
+__global__ void k_write_total(const int32_t* in, const int32_t* out, int64_t count, int32_t* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = (count ? out[count - 1] + in[count - 1] : 0);
+}
+
+static knnkm_status scan_rec(knnkm_ctx* ctx, const int32_t* in, int32_t* out, int64_t count,
+                             int depth) {
+  int64_t tiles = (count + SCAN_TILE - 1) / SCAN_TILE;
+  if (tiles <= 1) {
+    k_scan_tiles<<<1, 256, 0, ctx->stream>>>(in, out, count, nullptr);
+    return knnkm_check(ctx, "scan");
+  }
+  char name[32];
+  snprintf(name, sizeof(name), "scan_sums%d", depth);
+  KNNKM_WS(ctx, sums, int32_t, name, tiles + 1);
+  k_scan_tiles<<<(unsigned)tiles, 256, 0, ctx->stream>>>(in, out, count, sums);
+  KNNKM_TRY(knnkm_check(ctx, "scan tiles"));
+  KNNKM_TRY(scan_rec(ctx, sums, sums, tiles, depth + 1));
+  k_scan_add<<<(unsigned)tiles, 256, 0, ctx->stream>>>(out, count, sums);
+  return knnkm_check(ctx, "scan add");
+}
+
+knnkm_status ks_scan_exclusive(knnkm_ctx* ctx, const int32_t* in, int32_t* out, int64_t count,
+                               bool with_total) {
+  if (count <= 0) {
+    if (with_total) return ks_fill_i32(ctx, out, 1, 0);
+    return KNNKM_OK;
+  }
+  // The total needs the last input value, which an in-place scan overwrites.
+  if (with_total) {
+    KNNKM_WS(ctx, last, int32_t, "scan_last", 1);
+    hipMemcpyAsync(last, in + count - 1, sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream);
+    KNNKM_TRY(scan_rec(ctx, in, out, count, 0));
+    k_write_total<<<1, 64, 0, ctx->stream>>>(last, out + count - 1, 1, out + count);
+    return knnkm_check(ctx, "scan total");
+  }
+  return scan_rec(ctx, in, out, count, 0);
+}
+
+// ------------------------------------------------ deterministic f64 sum --
+// Each of 256 threads sums a fixed strided subset in order; the block then
+// combines the 256 partials in a fixed tree.  Same order on every run.
+__global__ __launch_bounds__(256) void k_sum_f64(const double* in, int64_t count, double* out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) s += in[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_f64_tiles(const double* in, int64_t count,
+                                                       double* partial) {
+  __shared__ double sh[256];
+  int64_t base = (int64_t)blockIdx.x * 8192;
+  double s = 0.0;
+  for (int j = threadIdx.x; j < 8192; j += 256)
+    if (base + j < count) s += in[base + j];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+knnkm_status ks_sum_f64(knnkm_ctx* ctx, const double* in, int64_t count, double* out) {
+  if (count > 65536) {
+    int64_t tiles = (count + 8191) / 8192;
+    KNNKM_WS(ctx, part, double, "sum_f64_part", tiles);
+    k_sum_f64_tiles<<<(unsigned)tiles, 256, 0, ctx->stream>>>(in, count, part);
+    KNNKM_TRY(knnkm_check(ctx, "sum_f64 tiles"));
+    k_sum_f64<<<1, 256, 0, ctx->stream>>>(part, tiles, out);
+    return knnkm_check(ctx, "sum_f64");
+  }
+  k_sum_f64<<<1, 256, 0, ctx->stream>>>(in, count, out);
+  return knnkm_check(ctx, "sum_f64");
+}
+
+// --------------------------------------------------- generator exposure --
+__global__ void k_rng_draw(uint64_t key, uint64_t ctr0, int64_t count, uint64_t* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = sm_draw(key, ctr0 + (uint64_t)i);
+}
+
+extern "C" knnkm_status knnkm_rng_draw(knnkm_ctx* ctx, uint64_t seed, uint64_t stream,
+                                       uint64_t ctr0, int64_t count, uint64_t* out) {
+  if (!ctx) return KNNKM_EINVAL;
+  if (count < 0 || (count > 0 && !out)) return knnkm_fail(ctx, KNNKM_EINVAL, "rng_draw: bad args");
+  if (ctx->sticky) return KNNKM_EDEVICE;
+  if (ctx->dry || count == 0) return KNNKM_OK;
+  k_rng_draw<<<grid_for(count, 256, 4096), 256, 0, ctx->stream>>>(sm_key(seed, stream), ctr0, count,
+                                                                   out);
+  return knnkm_check(ctx, "rng_draw");
+}

