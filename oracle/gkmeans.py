@@ -39,10 +39,11 @@ def _dist_to(X64, C64, cand):
     return np.einsum("ijk,ijk->ij", diff, diff)
 
 
-def candidates(labels_in, G_ids, k):
-    """Q_i as a padded array: column 0 is the current label, then the labels of
-    the kappa neighbours (duplicates kept; they do not change the argmin)."""
-    return np.concatenate([labels_in[:, None], labels_in[G_ids]], axis=1)
+def candidates(cur, labels_all, G_rows):
+    """Q_i as a padded array for a block of rows: column 0 is the row's current
+    label ``cur``, then the labels (looked up in the full label array) of its
+    kappa neighbours; duplicates are kept, they do not change the argmin."""
+    return np.concatenate([cur[:, None], labels_all[G_rows]], axis=1)
 
 
 def gk_assign(X, C, labels_in, G_ids):
@@ -63,7 +64,7 @@ def gk_assign(X, C, labels_in, G_ids):
         if kappa >= k:
             cand = np.broadcast_to(np.arange(k), (e - s, k))
         else:
-            cand = candidates(labels_in[s:e], G_ids[s:e], k)
+            cand = candidates(labels_in[s:e], labels_in, G_ids[s:e])
         d = _dist_to(X64[s:e], C64, cand)
         cur = labels_in[s:e]
         dcur = np.einsum("ij,ij->i", X64[s:e] - C64[cur], X64[s:e] - C64[cur])

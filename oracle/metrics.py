@@ -27,7 +27,7 @@ def assign_gap_mask(X, C, labels_in, G_ids, rel=1e-5):
         if G_ids.shape[1] >= k:
             cand = np.broadcast_to(np.arange(k), (e - s, k))
         else:
-            cand = candidates(labels_in[s:e], G_ids[s:e], k)
+            cand = candidates(labels_in[s:e], labels_in, G_ids[s:e])
         diff = X64[s:e, None, :] - C64[cand]
         d = np.einsum("ijk,ijk->ij", diff, diff)
         # distinct clusters only: duplicates of the minimum are not a second value

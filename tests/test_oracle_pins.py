@@ -118,6 +118,25 @@ def test_assign_tiny_enumeration():
             assert lab[i] == want
 
 
+def test_assign_enumeration_beyond_one_block():
+    """n spans several of the oracle's row blocks: sampled rows enumerated by
+    hand must agree (neighbour labels come from the whole label array)."""
+    rs = np.random.default_rng(12)
+    n, d, k, kappa = 9000, 4, 300, 6
+    X = rs.normal(size=(n, d)).astype(np.float32)
+    C = rs.normal(size=(k, d)).astype(np.float32)
+    lab_in = rs.integers(0, k, n)
+    G = rs.integers(0, n, size=(n, kappa))
+    lab, _, moved = gkmeans.gk_assign(X, C, lab_in, G)
+    for i in list(rs.choice(n, 200, replace=False)) + [0, 4095, 4096, 8191, 8192, n - 1]:
+        Q = {int(lab_in[i])} | {int(lab_in[j]) for j in G[i]}
+        dist = {q: float(sum((float(X[i, t]) - float(C[q, t])) ** 2 for t in range(d))) for q in Q}
+        m = min(dist.values())
+        want = int(lab_in[i]) if dist[int(lab_in[i])] == m else min(q for q in Q if dist[q] == m)
+        assert lab[i] == want
+    assert moved == int((lab != lab_in).sum())
+
+
 # ----------------------------------------------------------- update ----
 
 def test_update_hand_worked_and_identity():
