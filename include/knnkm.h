@@ -78,6 +78,8 @@ knnkm_status knnkm_create(int device, void* hip_stream, knnkm_ctx** out);
 knnkm_status knnkm_destroy(knnkm_ctx* ctx);
 /* Switch the launch stream of an existing context. */
 knnkm_status knnkm_set_stream(knnkm_ctx* ctx, void* hip_stream);
+/* Message of the last failed call on ctx; with ctx = NULL, of the last failed
+ * knnkm_create on this thread.  Owned by the library. */
 const char* knnkm_last_error(const knnkm_ctx* ctx);
 knnkm_status knnkm_default_params(knnkm_params* p);
 /* Device bytes currently held by the context workspace. */
@@ -162,6 +164,19 @@ knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d
                             int32_t k, const int32_t* G_ids, const knnkm_params* params,
                             int32_t* labels, float* C, int32_t* counts, double* trace_host,
                             int32_t* iters_run_host);
+
+/* Opt-in phase timing.  While enabled, knn_build and knn_kmeans_fit record
+ * HIP events on the context stream around their phases (a few microseconds
+ * of overhead per iteration).  knnkm_phase_times waits for those events and
+ * writes up to `count` values (milliseconds unless noted), -1 where a phase
+ * was not recorded:
+ *   out[0] last knn_build, start to end
+ *   out[1] last knn_kmeans_fit initialisation (partition, means, E_0)
+ *   out[2] last knn_kmeans_fit iterations (assign + update + distortion)
+ *   out[3] sum of the knn_assign launches inside those iterations
+ *   out[4] iterations timed (count), out[5] assignment launches timed (count) */
+knnkm_status knnkm_enable_timing(knnkm_ctx* ctx, int32_t on);
+knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t count);
 
 /* Counter-based generator used for every random draw of the method
  * (SplitMix64 output function applied to key + (ctr+1)*0x9E3779B97F4A7C15,

@@ -27,7 +27,15 @@ struct knnkm_ctx {
   std::unordered_map<std::string, knnkm_buf> ws;  // named workspace buffers
   // cached two-means tree metadata (depends on n and k only)
   struct TMPlan* tm_plan = nullptr;
+  // opt-in phase timing (HIP events on the context stream)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pool
+  int build_ev = -1;           // index of the build start event (end = +1)
+  int fit_ev = -1;             // fit start, init end, iterations end = +0, +1, +2
+  int assign_ev0 = -1, assign_n = 0;  // pairs around the assignment launches of the fit
 };
+// Event `i` of the context pool (created on first use); nullptr on failure.
+hipEvent_t knnkm_event(knnkm_ctx* ctx, int i);
 void tm_plan_free(struct TMPlan* p);
 
 // Set the context error and return the status.

@@ -47,8 +47,14 @@ knnkm_status knnkm_check(knnkm_ctx* ctx, const char* where) {
   return KNNKM_OK;
 }
 
+// Message of the last failed call that had no context (knnkm_create).
+static thread_local std::string g_create_err;
+
 extern "C" knnkm_status knnkm_create(int device, void* hip_stream, knnkm_ctx** out) {
-  if (!out) return KNNKM_EINVAL;
+  if (!out) {
+    g_create_err = "knnkm_create: out is null";
+    return KNNKM_EINVAL;
+  }
   *out = nullptr;
   knnkm_ctx* ctx = new (std::nothrow) knnkm_ctx();
   if (!ctx) return KNNKM_ENOMEM;
@@ -57,12 +63,19 @@ extern "C" knnkm_status knnkm_create(int device, void* hip_stream, knnkm_ctx** o
   ctx->stream = (hipStream_t)hip_stream;
   if (!ctx->dry) {
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || device >= ndev) {
+      char buf[256];
+      snprintf(buf, sizeof(buf), "knnkm_create: device %d unavailable (%d devices, %s)", device, ndev,
+               hipGetErrorString(e));
+      g_create_err = buf;
       (void)hipGetLastError();
       delete ctx;
       return KNNKM_EDEVICE;
     }
-    if (hipSetDevice(device) != hipSuccess) {
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+      g_create_err = std::string("knnkm_create: hipSetDevice: ") + hipGetErrorString(e);
       delete ctx;
       return KNNKM_EDEVICE;
     }
@@ -82,6 +95,8 @@ extern "C" knnkm_status knnkm_destroy(knnkm_ctx* ctx) {
       if (kv.second.ptr) (void)hipFree(kv.second.ptr);
   }
   tm_plan_free(ctx->tm_plan);
+  for (hipEvent_t e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
   return KNNKM_OK;
 }
@@ -93,7 +108,7 @@ extern "C" knnkm_status knnkm_set_stream(knnkm_ctx* ctx, void* hip_stream) {
 }
 
 extern "C" const char* knnkm_last_error(const knnkm_ctx* ctx) {
-  return ctx ? ctx->err.c_str() : "null context";
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
 }
 
 extern "C" knnkm_status knnkm_default_params(knnkm_params* p) {
@@ -117,6 +132,52 @@ extern "C" knnkm_status knnkm_workspace_bytes(const knnkm_ctx* ctx, int64_t* out
   int64_t s = 0;
   for (auto& kv : ctx->ws) s += (int64_t)kv.second.bytes;
   *out = s;
+  return KNNKM_OK;
+}
+
+hipEvent_t knnkm_event(knnkm_ctx* ctx, int i) {
+  if ((int)ctx->ev.size() <= i) ctx->ev.resize(i + 1, nullptr);
+  if (!ctx->ev[i] && hipEventCreate(&ctx->ev[i]) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->ev[i] = nullptr;
+  }
+  return ctx->ev[i];
+}
+
+extern "C" knnkm_status knnkm_enable_timing(knnkm_ctx* ctx, int32_t on) {
+  if (!ctx) return KNNKM_EINVAL;
+  ctx->timing = on != 0;
+  ctx->build_ev = ctx->fit_ev = ctx->assign_ev0 = -1;
+  ctx->assign_n = 0;
+  return KNNKM_OK;
+}
+
+static double ev_ms(knnkm_ctx* ctx, int a) {
+  float ms = 0.f;
+  if (a < 0 || a + 1 >= (int)ctx->ev.size() || !ctx->ev[a] || !ctx->ev[a + 1]) return -1.0;
+  if (hipEventSynchronize(ctx->ev[a + 1]) != hipSuccess) return -1.0;
+  if (hipEventElapsedTime(&ms, ctx->ev[a], ctx->ev[a + 1]) != hipSuccess) return -1.0;
+  return (double)ms;
+}
+
+extern "C" knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t count) {
+  if (!ctx || !out || count < 1) return KNNKM_EINVAL;
+  double v[6] = {-1.0, -1.0, -1.0, -1.0, 0.0, 0.0};
+  if (!ctx->dry) {
+    (void)hipSetDevice(ctx->device);
+    v[0] = ev_ms(ctx, ctx->build_ev);
+    v[1] = ev_ms(ctx, ctx->fit_ev);
+    v[2] = ev_ms(ctx, ctx->fit_ev + 1);
+    if (ctx->assign_ev0 >= 0) {
+      double s = 0.0;
+      for (int j = 0; j < ctx->assign_n; ++j) s += ev_ms(ctx, ctx->assign_ev0 + 2 * j);
+      v[3] = s;
+    }
+    v[4] = ctx->fit_ev >= 0 ? (double)ctx->assign_n : 0.0;
+    v[5] = (double)ctx->assign_n;
+  }
+  for (int i = 0; i < count && i < 6; ++i) out[i] = v[i];
+  for (int i = 6; i < count; ++i) out[i] = 0.0;
   return KNNKM_OK;
 }
 

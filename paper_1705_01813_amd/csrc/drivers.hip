@@ -85,6 +85,20 @@ extern "C" knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n
   KNNKM_WS(ctx, scal, double, "fit_scalars", 2);
   KNNKM_WS(ctx, trace, double, "fit_trace", (int64_t)T + 1);
   KNNKM_WS(ctx, moved, int64_t, "fit_moved", (int64_t)T + 1);
+  // phase events: 2 fit start, 3 initialisation done, 4 iterations done,
+  // 6+2j / 7+2j around the assignment of iteration j+1
+  auto mark = [&](int e) {
+    if (ctx->timing) {
+      hipEvent_t h = knnkm_event(ctx, e);
+      if (h) (void)hipEventRecord(h, ctx->stream);
+    }
+  };
+  if (ctx->timing) {
+    ctx->fit_ev = 2;
+    ctx->assign_ev0 = 6;
+    ctx->assign_n = 0;
+  }
+  mark(2);
 
   // initial partition
   if (p->init == KNNKM_INIT_RANDOM) {
@@ -105,12 +119,16 @@ extern "C" knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n
   KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, k, counts, off, mem, C, nullptr, Iterm));
   KNNKM_TRY(ks_sum_f64(ctx, Iterm, k, scal + 1));
   k_trace<<<1, 64, 0, ctx->stream>>>(scal, scal + 1, 1.0 / (double)n, trace);
+  mark(3);
 
   int32_t* cur = labels;
   int32_t* nxt = lab2;
   int it = 0;
   for (int t = 1; t <= T; ++t) {
+    mark(6 + 2 * (t - 1));
     KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, k, G_ids, kappa, cur, nxt, nullptr, moved + t, mem, dense));
+    mark(7 + 2 * (t - 1));
+    if (ctx->timing) ctx->assign_n = t;
     KNNKM_TRY(ks_label_sort(ctx, nxt, n, k, counts, off, mem));
     KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, k, counts, off, mem, C, nullptr, Iterm));
     KNNKM_TRY(ks_sum_f64(ctx, Iterm, k, scal + 1));
@@ -125,6 +143,7 @@ extern "C" knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n
       if (mv == 0) break;
     }
   }
+  mark(4);
   if (cur != labels)
     KNNKM_HIP(ctx, hipMemcpyAsync(labels, cur, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice,
                                   ctx->stream));
@@ -150,8 +169,20 @@ extern "C" knnkm_status knn_build(knnkm_ctx* ctx, const float* X, int64_t n, int
   if (ctx->dry) return KNNKM_OK;
   KNNKM_HIP(ctx, hipSetDevice(ctx->device));
   const int32_t k0 = (int32_t)std::max<int64_t>(1, n / p->xi);
+  // phase events 0 (start) and 1 (end)
+  auto mark = [&](int e) {
+    if (ctx->timing) {
+      hipEvent_t h = knnkm_event(ctx, e);
+      if (h) (void)hipEventRecord(h, ctx->stream);
+    }
+  };
+  if (ctx->timing) ctx->build_ev = 0;
+  mark(0);
   KNNKM_TRY(ks_graph_init(ctx, X, n, d, ldx, kappa, p->seed, G_ids, G_d2));
-  if (p->tau == 0) return KNNKM_OK;
+  if (p->tau == 0) {
+    mark(1);
+    return KNNKM_OK;
+  }
   KNNKM_WS(ctx, lab, int32_t, "kb_labels", n);
   KNNKM_WS(ctx, lab2, int32_t, "kb_labels2", n);
   KNNKM_WS(ctx, counts, int32_t, "kb_counts", k0);
@@ -166,5 +197,6 @@ extern "C" knnkm_status knn_build(knnkm_ctx* ctx, const float* X, int64_t n, int
     KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, k0, G_ids, kappa, lab, lab2, nullptr, nullptr, mem, dense));
     KNNKM_TRY(ks_refine(ctx, X, n, d, ldx, lab2, k0, p->precision, G_ids, G_d2, kappa));
   }
+  mark(1);
   return KNNKM_OK;
 }

@@ -23,7 +23,7 @@ EXPORTS = [
     "knnkm_create", "knnkm_destroy", "knnkm_set_stream", "knnkm_last_error",
     "knnkm_default_params", "knnkm_workspace_bytes", "knn_assign", "centroid_update",
     "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
-    "knn_kmeans_fit", "knnkm_rng_draw",
+    "knn_kmeans_fit", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times",
 ]
 
 
@@ -54,6 +54,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname; load it first so
+        # the library binds to the runtime that owns the caller's streams/memory.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with `python -m paper_1705_01813_amd.build`")
@@ -75,6 +81,8 @@ def lib():
             "knn_build": [P, P, i64, i32, i64, ctypes.POINTER(Params), P, P],
             "knn_kmeans_fit": [P, P, i64, i32, i64, i32, P, ctypes.POINTER(Params), P, P, P, P, P],
             "knnkm_rng_draw": [P, u64, u64, u64, i64, P],
+            "knnkm_enable_timing": [P, i32],
+            "knnkm_phase_times": [P, P, i32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -98,8 +106,7 @@ def default_params(**kw):
 
 def _chk(ctx, st):
     if st != OK:
-        msg = lib().knnkm_last_error(ctx).decode() if ctx else ""
-        raise KnnkmError(st, msg)
+        raise KnnkmError(st, lib().knnkm_last_error(ctx).decode())
 
 
 def _ptr(t, dtype=None, name="tensor"):
@@ -251,6 +258,19 @@ def knn_kmeans_fit(ctx, X, k, G_ids, params, labels, C, counts):
                               trace.ctypes.data_as(ctypes.c_void_p), ctypes.byref(it))
     _chk(ctx.handle, st)
     return trace[: it.value + 1], it.value
+
+
+def knnkm_enable_timing(ctx, on=True):
+    _chk(ctx.handle, lib().knnkm_enable_timing(ctx.handle, 1 if on else 0))
+
+
+PHASES = ("build_ms", "fit_init_ms", "fit_iters_ms", "assign_ms", "iters", "assign_launches")
+
+
+def knnkm_phase_times(ctx):
+    out = np.zeros(len(PHASES), np.float64)
+    _chk(ctx.handle, lib().knnkm_phase_times(ctx.handle, out.ctypes.data_as(ctypes.c_void_p), len(PHASES)))
+    return dict(zip(PHASES, out.tolist()))
 
 
 def knnkm_rng_draw(ctx, seed, stream, ctr0, out):
