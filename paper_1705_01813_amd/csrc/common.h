@@ -114,6 +114,29 @@ __device__ inline uint64_t dkey(double v) {
   return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
+// Exclusive scan of one int per thread over a 256-thread block (all threads
+// must call it); *total receives the block sum.  sh: 8 ints of LDS.
+__device__ inline int32_t block_scan_excl_256(int32_t v, int32_t* sh /*[8]*/, int32_t* total) {
+  // inclusive wave scan
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  int32_t base = 0, tot = 0;
+  for (int j = 0; j < 4; ++j) {
+    if (j < w) base += sh[j];
+    tot += sh[j];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
 // Blocks per launch for grid-stride kernels.
 inline int grid_for(int64_t work, int per_block, int cap) {
   int64_t g = (work + per_block - 1) / per_block;

@@ -208,27 +208,6 @@ knnkm_status ks_fill_i32(knnkm_ctx* ctx, int32_t* p, int64_t count, int32_t v) {
 // recursively, then added back.
 #define SCAN_TILE 1024
 
-__device__ inline int32_t block_scan_excl_256(int32_t v, int32_t* sh /*[8]*/, int32_t* total) {
-  // inclusive wave scan
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[w] = x;
-  __syncthreads();
-  int32_t base = 0, tot = 0;
-  for (int j = 0; j < 4; ++j) {
-    if (j < w) base += sh[j];
-    tot += sh[j];
-  }
-  __syncthreads();
-  *total = tot;
-  return base + x - v;
-}
-
 __global__ __launch_bounds__(256) void k_scan_tiles(const int32_t* in, int32_t* out, int64_t count,
                                                     int32_t* tile_sums) {
   __shared__ int32_t sh[8];

@@ -7,23 +7,25 @@
 //   the row is ordered by (d2, id) through per-lane ranks.
 //
 // refine: the exhaustive comparison inside every cluster and the list
-//   update.  Work item = (cluster, block of 32 rows); the block walks all
-//   32-member column blocks of its cluster:
-//     1. the 32 row and 32 column samples are staged in LDS (float32);
-//     2. their 32 x 32 Gram block runs on MFMA (float32 16x16x4, or bfloat16
-//        16x16x32 in the precision form), four 16 x 16 tiles, one per wave;
+//   update.  A cluster of at most 64 members is one tile handled by one
+//   512-thread block; a larger cluster is cut into blocks of 64 (32 for
+//   d > 256) rows, each walking the cluster's column blocks.  Per tile:
+//     1. the samples are staged in LDS (float32, 16-byte aligned rows);
+//     2. the Gram block runs on MFMA (float32 16x16x4, or bfloat16 16x16x32
+//        in the precision form), 16 x 16 tiles spread over the 8 waves;
 //     3. d^2 estimates ||x||^2 + ||y||^2 - 2 x.y minus a rigorous error bound
-//        are compared with the row's current kappa-th distance; pairs already
-//        in the row (visited) are dropped;
+//        are compared with the row's current kappa-th distance; survivors go
+//        to a compact list;
 //     4. survivors get their exact distance (float64 direct difference from
-//        LDS, rounded to float32);
-//     5. each row merges its survivors into its sorted list (per-lane ranks).
+//        LDS by row groups, rounded to float32);
+//     5. each row (one wave) drops survivors already in its list (visited
+//        pairs) and merges the rest by per-lane ranks, writing the graph row.
 //   Every row belongs to exactly one cluster, so rows are updated without
 //   atomics.  Both precisions produce the same graph: the screen only removes
 //   pairs that provably cannot enter.
 #include <cfloat>
 
-#include "common.h"
+#include "rowgroup.h"
 
 // ------------------------------------------------------------- graph init --
 template <int T>
@@ -128,274 +130,404 @@ knnkm_status ks_graph_init(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d,
 }
 
 // ----------------------------------------------------------------- refine --
-#define RB 32  // rows / columns per block
-
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
-
-struct RefineLDS {
-  // layout (dynamic LDS):
-  //   xi[RB][ld], xj[RB][ld]   float32 samples, ld = dpad + 1
-  //   rk[RB][kappa], ri[RB][kappa]  current row lists
-  //   ck[RB][RB], ci[RB][RB]   survivors per row
-  //   ni[RB], nj[RB], cnt[RB], thr[RB]
-  //   ids_i[RB], ids_j[RB]
-};
 
 __device__ inline bool key_lt(float ka, int ia, float kb, int ib) {
   return ka < kb || (ka == kb && ia < ib);
 }
 
-template <bool BF16>
-__global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int d, int64_t ldx,
-                                                int dpad, int kappa, int32_t k,
-                                                const int32_t* __restrict__ offsets,
-                                                const int32_t* __restrict__ members,
-                                                const int32_t* __restrict__ wb_off,
-                                                int64_t max_items, float err_c,
-                                                int32_t* __restrict__ G_ids,
-                                                float* __restrict__ G_d2) {
-  extern __shared__ __align__(16) char smem[];
-  const int ld = dpad + 1;
-  float* xi = (float*)smem;
-  float* xj = xi + RB * ld;
-  float* rk = xj + RB * ld;
-  int32_t* ri = (int32_t*)(rk + RB * kappa);
-  float* ck = (float*)(ri + RB * kappa);
-  int32_t* ci = (int32_t*)(ck + RB * RB);
-  float* ni = (float*)(ci + RB * RB);
-  float* nj = ni + RB;
-  float* thr = nj + RB;
-  int32_t* cnt = (int32_t*)(thr + RB);
-  int32_t* ids_i = cnt + RB;
-  int32_t* ids_j = ids_i + RB;
+#define SMALL_CL 64  // clusters up to this size are one tile
 
+// LDS layout of a refine tile (byte offsets, regions laid end to end):
+//   xi [RB][ld] float rows, xj [RB][ld] (the same region when `single`),
+//   km [RB][RB] float exact keys, ni/nj/thr [RB] float, ids_i/ids_j [RB] int,
+//   pcount [4] int, plist [RB*RB] uint16 survivors, rk/ri [RB][kappa] the
+//   graph rows of the block (float keys, int ids).
+struct TileLayout {
+  int ld;
+  size_t xi, xj, km, ni, nj, thr, ids_i, ids_j, pcount, plist, rk, ri, bytes;
+  __host__ __device__ TileLayout(int RB, int dpad, bool single, int kappa) {
+    ld = dpad + 4;  // 16-byte aligned rows
+    const size_t rows = (size_t)RB * ld * 4;
+    size_t at = 0;
+    xi = at;
+    at += rows;
+    xj = single ? xi : at;
+    if (!single) at += rows;
+    km = at;
+    at += (size_t)RB * RB * 4;
+    ni = at;
+    at += (size_t)RB * 4;
+    nj = single ? ni : at;
+    if (!single) at += (size_t)RB * 4;
+    thr = at;
+    at += (size_t)RB * 4;
+    ids_i = at;
+    at += (size_t)RB * 4;
+    ids_j = at;
+    at += (size_t)RB * 4;
+    pcount = at;
+    at += 16;
+    plist = at;
+    at += (size_t)RB * RB * 2;
+    at = (at + 15) & ~(size_t)15;
+    rk = at;
+    at += (size_t)RB * kappa * 4;
+    ri = at;
+    at += (size_t)RB * kappa * 4;
+    bytes = at;
+  }
+};
+
+// Stage rows [r0, r0 + nr) of a cluster (members c0 + r) into LDS, zero
+// padded to RB rows of dpad floats.
+template <int RB>
+__device__ inline void stage_rows(float* __restrict__ xs, int ld, const float* __restrict__ X, int64_t ldx,
+                                  const int32_t* __restrict__ members, int c0, int r0, int nr, int d,
+                                  int dpad, bool vec) {
+  const int q4 = dpad / 4;
+  for (int e = threadIdx.x; e < RB * q4; e += blockDim.x) {
+    const int r = e / q4, t = 4 * (e % q4);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r < nr) {
+      const float* row = X + (int64_t)members[c0 + r0 + r] * ldx;
+      if (vec && t < d) {
+        v = *reinterpret_cast<const float4*>(row + t);
+      } else {
+        v.x = t < d ? row[t] : 0.f;
+        v.y = t + 1 < d ? row[t + 1] : 0.f;
+        v.z = t + 2 < d ? row[t + 2] : 0.f;
+        v.w = t + 3 < d ? row[t + 3] : 0.f;
+      }
+    }
+    *reinterpret_cast<float4*>(xs + r * ld + t) = v;
+  }
+}
+
+// float32 squared norms of RB staged rows, one row group per row.
+template <int RB, int L, int V>
+__device__ inline void row_norms(const float* __restrict__ xs, int ld, int dpad, float* __restrict__ nrm) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t item = blockIdx.x;
-  if (item >= max_items) return;
-  const int32_t total = wb_off[k];
-  if (item >= total) return;
-  int lo = 0, hi = k;
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (wb_off[mid] <= item) lo = mid; else hi = mid;
-  }
-  const int cl = lo;
-  const int c0 = offsets[cl], s = offsets[cl + 1] - c0;
-  const int rb0 = (int)(item - wb_off[cl]) * RB;
-  const int nrows = min(RB, s - rb0);
-
-  // stage rows, their lists and norms
-  for (int r = threadIdx.x; r < RB; r += 256) {
-    ids_i[r] = r < nrows ? members[c0 + rb0 + r] : -1;
-    cnt[r] = 0;
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < RB * dpad; e += 256) {
-    const int r = e / dpad, t = e % dpad;
-    xi[r * ld + t] = (r < nrows && t < d) ? X[(int64_t)ids_i[r] * ldx + t] : 0.f;
-  }
-  for (int e = threadIdx.x; e < RB * kappa; e += 256) {
-    const int r = e / kappa, c = e % kappa;
-    if (r < nrows) {
-      rk[e] = G_d2[(int64_t)ids_i[r] * kappa + c];
-      ri[e] = G_ids[(int64_t)ids_i[r] * kappa + c];
-    }
-  }
-  __syncthreads();
-  for (int r = w; r < RB; r += 4) {
+  constexpr int NG = 512 / L;
+  const int j = lane % L, gid = w * (64 / L) + lane / L;
+  for (int r = gid; r < RB; r += NG) {
     float a = 0.f;
-    for (int t = lane; t < dpad; t += 64) a = fmaf(xi[r * ld + t], xi[r * ld + t], a);
-    a = wave_sum(a);
-    if (lane == 0) {
-      ni[r] = a;
-      thr[r] = r < nrows ? rk[r * kappa + kappa - 1] : -FLT_MAX;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const int t = j * V + e;
+      const float v = t < dpad ? xs[r * ld + t] : 0.f;
+      a = fmaf(v, v, a);
     }
+    a = group_sum<L>(a);
+    if (j == 0) nrm[r] = a;
+  }
+}
+
+// Exhaustive comparison inside clusters (Alg. 3 inner loops), one block of
+// 512 threads per (cluster, block of RB rows).  SINGLE: the whole cluster
+// (2 <= s <= RB) is one tile, its rows serve as both sides of the Gram block.
+// Otherwise (clusters larger than SMALL_CL) the block walks the cluster's
+// column blocks of RB members.  Per (row block, column block):
+//   Gram on MFMA (16 x 16 tiles over 8 waves) -> screen against the rows'
+//   current kappa-th distance with a rigorous margin -> survivor list ->
+//   exact float64 squared distances (row groups) -> per-row merge (one wave
+//   per row, lane c = candidate column c) written straight to the graph.
+template <bool BF16, int L, int V, int RB, bool SINGLE>
+__global__ __launch_bounds__(512) void k_refine_tile(const float* __restrict__ X, int d, int64_t ldx, int dpad,
+                                                     int kappa, int32_t k, const int32_t* __restrict__ offsets,
+                                                     const int32_t* __restrict__ members,
+                                                     const int32_t* __restrict__ wb_off, int64_t max_items,
+                                                     float err_c, int vec, int32_t* __restrict__ G_ids,
+                                                     float* __restrict__ G_d2) {
+  extern __shared__ __align__(16) char smem[];
+  const TileLayout lay(RB, dpad, SINGLE, kappa);
+  const int ld = lay.ld;
+  float* rk = (float*)(smem + lay.rk);
+  int32_t* ri = (int32_t*)(smem + lay.ri);
+  float* xi = (float*)(smem + lay.xi);
+  float* xj = (float*)(smem + lay.xj);
+  float* km = (float*)(smem + lay.km);
+  float* ni = (float*)(smem + lay.ni);
+  float* nj = (float*)(smem + lay.nj);
+  float* thr = (float*)(smem + lay.thr);
+  int32_t* ids_i = (int32_t*)(smem + lay.ids_i);
+  int32_t* ids_j = (int32_t*)(smem + lay.ids_j);
+  int32_t* pcount = (int32_t*)(smem + lay.pcount);
+  uint16_t* plist = (uint16_t*)(smem + lay.plist);
+
+  int cl, i0, s;
+  if (SINGLE) {
+    cl = blockIdx.x;
+    i0 = 0;
+    s = offsets[cl + 1] - offsets[cl];
+    if (s < 2 || s > RB) return;
+  } else {
+    const int64_t item = blockIdx.x;
+    if (item >= max_items || item >= wb_off[k]) return;
+    int lo = 0, hi = k;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (wb_off[mid] <= item) lo = mid; else hi = mid;
+    }
+    cl = lo;
+    s = offsets[cl + 1] - offsets[cl];
+    i0 = (int)(item - wb_off[cl]) * RB;
+  }
+  const int c0 = offsets[cl];
+  const int nrows = min(RB, s - i0);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int NG = 512 / L;
+  const int j = lane % L, gid = w * (64 / L) + lane / L;
+
+  if (tid < RB) {
+    const int id = tid < nrows ? members[c0 + i0 + tid] : -1;
+    ids_i[tid] = id;
+    thr[tid] = tid < nrows ? G_d2[(int64_t)id * kappa + kappa - 1] : -FLT_MAX;
+  }
+  stage_rows<RB>(xi, ld, X, ldx, members, c0, i0, nrows, d, dpad, vec);
+  for (int e = tid; e < nrows * kappa; e += 512) {
+    const int r = e / kappa, q = e % kappa;
+    const int64_t g = (int64_t)members[c0 + i0 + r] * kappa + q;
+    rk[e] = G_d2[g];
+    ri[e] = G_ids[g];
   }
   __syncthreads();
+  row_norms<RB, L, V>(xi, ld, dpad, ni);
 
-  for (int cb0 = 0; cb0 < s; cb0 += RB) {
-    const int ncols = min(RB, s - cb0);
-    for (int r = threadIdx.x; r < RB; r += 256) ids_j[r] = r < ncols ? members[c0 + cb0 + r] : -1;
-    __syncthreads();
-    for (int e = threadIdx.x; e < RB * dpad; e += 256) {
-      const int r = e / dpad, t = e % dpad;
-      xj[r * ld + t] = (r < ncols && t < d) ? X[(int64_t)ids_j[r] * ldx + t] : 0.f;
+  for (int j0 = 0; j0 < s; j0 += RB) {
+    const int ncols = SINGLE ? nrows : min(RB, s - j0);
+    if (!SINGLE) {
+      if (tid < RB) ids_j[tid] = tid < ncols ? members[c0 + j0 + tid] : -1;
+      stage_rows<RB>(xj, ld, X, ldx, members, c0, j0, ncols, d, dpad, vec);
+    } else if (tid < RB) {
+      ids_j[tid] = ids_i[tid];
     }
+    for (int e = tid; e < RB * RB; e += 512) km[e] = FLT_MAX;
+    if (tid == 0) pcount[0] = 0;
     __syncthreads();
-    for (int r = w; r < RB; r += 4) {
-      float a = 0.f;
-      for (int t = lane; t < dpad; t += 64) a = fmaf(xj[r * ld + t], xj[r * ld + t], a);
-      a = wave_sum(a);
-      if (lane == 0) nj[r] = a;
+    if (!SINGLE) {
+      row_norms<RB, L, V>(xj, ld, dpad, nj);
+      __syncthreads();
     }
-    __syncthreads();
-
-    // Gram tile of this wave: rows 16*(w>>1).., cols 16*(w&1)..
-    const int tr = 16 * (w >> 1), tc = 16 * (w & 1);
-    f4_t acc = {0.f, 0.f, 0.f, 0.f};
-    const float* ar = xi + (tr + (lane & 15)) * ld;
-    const float* br = xj + (tc + (lane & 15)) * ld;
-    if (BF16) {
-      for (int k0 = 0; k0 < dpad; k0 += 32) {
-        bf8_t a, b;
-        const int kb = k0 + 8 * (lane >> 4);
+    // Gram tiles and screen
+    constexpr int TPS = RB / 16;
+    for (int t = w; t < TPS * TPS; t += 8) {
+      const int tr = 16 * (t / TPS), tc = 16 * (t % TPS);
+      if (tr >= nrows || tc >= ncols) continue;  // wave-uniform
+      f4_t acc = {0.f, 0.f, 0.f, 0.f};
+      const float* ar = xi + (tr + (lane & 15)) * ld;
+      const float* br = xj + (tc + (lane & 15)) * ld;
+      if (BF16) {
+        for (int k0 = 0; k0 < dpad; k0 += 32) {
+          bf8_t a, b;
+          const int kb = k0 + 8 * (lane >> 4);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          a[e] = (__bf16)ar[kb + e];
-          b[e] = (__bf16)br[kb + e];
+          for (int e = 0; e < 8; ++e) {
+            a[e] = (__bf16)ar[kb + e];
+            b[e] = (__bf16)br[kb + e];
+          }
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+      } else {
+        for (int k0 = 0; k0 < dpad; k0 += 4) {
+          const int kk = k0 + (lane >> 4);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[kk], br[kk], acc, 0, 0, 0);
+        }
       }
-    } else {
-      for (int k0 = 0; k0 < dpad; k0 += 4) {
-        const int kk = k0 + (lane >> 4);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[kk], br[kk], acc, 0, 0, 0);
-      }
-    }
-    // screen: lane holds column tc + (lane & 15), rows tr + 4*(lane>>4) + e
-    {
       const int c = tc + (lane & 15);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = tr + 4 * (lane >> 4) + e;
-        if (r < nrows && c < ncols) {
-          const int idi = ids_i[r], idj = ids_j[c];
-          if (idi != idj) {
-            const float sn = ni[r] + nj[c];
-            const float est = sn - 2.f * acc[e];
-            const float lb = est - err_c * sn;
-            const float th = thr[r];
-            if (lb <= th + th * 0x1p-22f + 1e-30f) {
-              bool dup = false;
-              for (int q = 0; q < kappa; ++q) dup |= (ri[r * kappa + q] == idj);
-              if (!dup) {
-                const int slot = atomicAdd(&cnt[r], 1);
-                ci[r * RB + slot] = c;  // column index for now
-              }
-            }
-          }
+        if (r < nrows && c < ncols && ids_i[r] != ids_j[c]) {
+          const float sn = ni[r] + nj[c];
+          const float lb = sn - 2.f * acc[e] - err_c * sn;
+          const float th = thr[r];
+          if (lb <= th + th * 0x1p-22f + 1e-30f) plist[atomicAdd(pcount, 1)] = (uint16_t)(r * RB + c);
         }
       }
     }
     __syncthreads();
-    // exact distances of survivors: thread per (row, slot)
-    for (int e = threadIdx.x; e < RB * RB; e += 256) {
-      const int r = e / RB, slot = e % RB;
-      if (slot < cnt[r]) {
-        const int c = ci[r * RB + slot];
-        const float* a = xi + r * ld;
-        const float* b = xj + c * ld;
-        double acc2 = 0.0;
-        for (int t = 0; t < d; ++t) {
-          const double df = (double)a[t] - (double)b[t];
-          acc2 = fma(df, df, acc2);
+    // exact float64 distances of the survivors, one row group per pair
+    const int np = pcount[0];
+    for (int p = gid; p < np; p += NG) {
+      const int rc = plist[p];
+      const int r = rc / RB, c = rc % RB;
+      double a = 0.0;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const int t = j * V + e;
+        if (t < dpad) {
+          const double df = (double)xi[r * ld + t] - (double)xj[c * ld + t];
+          a = fma(df, df, a);
         }
-        ck[r * RB + slot] = (float)acc2;
-        ci[r * RB + slot] = ids_j[c];
       }
+      a = group_sum<L>(a);
+      if (j == 0) km[rc] = (float)a;
     }
     __syncthreads();
-    // merge: one wave per row
-    for (int r = w; r < RB; r += 4) {
-      const int m = cnt[r];
-      if (r < nrows && m > 0) {
-        const float cv = lane < m ? ck[r * RB + lane] : FLT_MAX;
-        const int cid = lane < m ? ci[r * RB + lane] : INT32_MAX;
-        // row entries in two slots
-        const float e0k = lane < kappa ? rk[r * kappa + lane] : FLT_MAX;
-        const int e0i = lane < kappa ? ri[r * kappa + lane] : INT32_MAX;
-        const float e1k = lane + 64 < kappa ? rk[r * kappa + lane + 64] : FLT_MAX;
-        const int e1i = lane + 64 < kappa ? ri[r * kappa + lane + 64] : INT32_MAX;
-        int pos_c = 0;  // candidate rank among row entries and other candidates
-        for (int q = 0; q < kappa; ++q) {
-          const float qk = rk[r * kappa + q];
-          const int qi = ri[r * kappa + q];
-          pos_c += key_lt(qk, qi, cv, cid) ? 1 : 0;
-        }
-        int add0 = 0, add1 = 0;
-        for (int q = 0; q < m; ++q) {
-          const float qk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv), q));
-          const int qi = __builtin_amdgcn_readlane(cid, q);
-          pos_c += key_lt(qk, qi, cv, cid) ? 1 : 0;
-          add0 += key_lt(qk, qi, e0k, e0i) ? 1 : 0;
-          add1 += key_lt(qk, qi, e1k, e1i) ? 1 : 0;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane < kappa && lane + add0 < kappa) {
-          rk[r * kappa + lane + add0] = e0k;
-          ri[r * kappa + lane + add0] = e0i;
-        }
-        if (lane + 64 < kappa && lane + 64 + add1 < kappa) {
-          rk[r * kappa + lane + 64 + add1] = e1k;
-          ri[r * kappa + lane + 64 + add1] = e1i;
-        }
-        if (lane < m && pos_c < kappa) {
-          rk[r * kappa + pos_c] = cv;
-          ri[r * kappa + pos_c] = cid;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) thr[r] = rk[r * kappa + kappa - 1];
+    // merge: one wave per row; lane c holds candidate column c
+    for (int r = w; r < nrows; r += 8) {
+      float* rowk = rk + r * kappa;
+      int32_t* rowi = ri + r * kappa;
+      const float ck = lane < RB ? km[r * RB + lane] : FLT_MAX;
+      const int cid = lane < RB ? ids_j[lane] : -1;
+      const float e0k = lane < kappa ? rowk[lane] : FLT_MAX;
+      const int e0i = lane < kappa ? rowi[lane] : INT32_MAX;
+      const float e1k = lane + 64 < kappa ? rowk[lane + 64] : FLT_MAX;
+      const int e1i = lane + 64 < kappa ? rowi[lane + 64] : INT32_MAX;
+      bool valid = ck < FLT_MAX;
+      for (int q = 0; q < kappa; ++q) {
+        const int qi = q < 64 ? __builtin_amdgcn_readlane(e0i, q) : __builtin_amdgcn_readlane(e1i, q - 64);
+        valid = valid && qi != cid;  // a visited pair is already in the row
       }
-      if (lane == 0) cnt[r] = 0;
+      uint64_t M = __ballot(valid);
+      if (!M) continue;
+      int pos_c = 0, add0 = 0, add1 = 0;
+      for (int q = 0; q < kappa; ++q) {
+        const float qk = q < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e0k), q))
+                                : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e1k), q - 64));
+        const int qi = q < 64 ? __builtin_amdgcn_readlane(e0i, q) : __builtin_amdgcn_readlane(e1i, q - 64);
+        pos_c += key_lt(qk, qi, ck, cid) ? 1 : 0;
+      }
+      while (M) {
+        const int q = (int)__builtin_ctzll(M);
+        M &= M - 1;
+        const float qk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ck), q));
+        const int qi = __builtin_amdgcn_readlane(cid, q);
+        pos_c += key_lt(qk, qi, ck, cid) ? 1 : 0;
+        add0 += key_lt(qk, qi, e0k, e0i) ? 1 : 0;
+        add1 += key_lt(qk, qi, e1k, e1i) ? 1 : 0;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (lane < kappa && lane + add0 < kappa) {
+        rowk[lane + add0] = e0k;
+        rowi[lane + add0] = e0i;
+        if (lane + add0 == kappa - 1) thr[r] = e0k;
+      }
+      if (lane + 64 < kappa && lane + 64 + add1 < kappa) {
+        rowk[lane + 64 + add1] = e1k;
+        rowi[lane + 64 + add1] = e1i;
+        if (lane + 64 + add1 == kappa - 1) thr[r] = e1k;
+      }
+      if (valid && pos_c < kappa) {
+        rowk[pos_c] = ck;
+        rowi[pos_c] = cid;
+        if (pos_c == kappa - 1) thr[r] = ck;
+      }
+      __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
   }
-  // write rows back
-  for (int e = threadIdx.x; e < RB * kappa; e += 256) {
-    const int r = e / kappa, c = e % kappa;
-    if (r < nrows) {
-      G_d2[(int64_t)ids_i[r] * kappa + c] = rk[e];
-      G_ids[(int64_t)ids_i[r] * kappa + c] = ri[e];
-    }
+  // write the block's rows back
+  for (int e = tid; e < nrows * kappa; e += 512) {
+    const int r = e / kappa, q = e % kappa;
+    const int64_t g = (int64_t)ids_i[r] * kappa + q;
+    G_d2[g] = rk[e];
+    G_ids[g] = ri[e];
   }
 }
 
-__global__ void k_row_blocks(const int32_t* __restrict__ counts, int32_t k, int32_t* wb) {
+static size_t refine_tile_lds(int d, int RB, bool single, int kappa) {
+  return TileLayout(RB, (d + 31) / 32 * 32, single, kappa).bytes;
+}
+
+#define LDS_BUDGET (160 * 1024)
+
+// Largest tile edge in {64, 32, 16} whose layout fits in LDS (0: none).
+static int pick_rb(int d, bool single, int kappa) {
+  for (int rb = 64; rb >= 16; rb >>= 1)
+    if (refine_tile_lds(d, rb, single, kappa) <= LDS_BUDGET) return rb;
+  return 0;
+}
+
+// Row blocks of the multi-tile kernel: clusters larger than one tile only.
+__global__ void k_row_blocks(const int32_t* __restrict__ counts, int32_t k, int single_max, int rb,
+                             int32_t* wb) {
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < k;
        r += (int64_t)gridDim.x * blockDim.x)
-    wb[r] = (counts[r] + RB - 1) / RB;
+    wb[r] = counts[r] > single_max ? (counts[r] + rb - 1) / rb : 0;
 }
 
-size_t refine_lds_bytes(int d, int kappa) {
-  const int dpad = (d + 31) / 32 * 32;
-  const int ld = dpad + 1;
-  return (size_t)4 * (2 * RB * ld + 2 * RB * kappa + 2 * RB * RB + 4 * RB + 2 * RB);
+template <bool BF16, int L, int V, int RB, bool SINGLE>
+static void launch_tile(knnkm_ctx* ctx, unsigned grid, const float* X, int d, int64_t ldx, int dpad,
+                        int kappa, int32_t k, const int32_t* off, const int32_t* mem, const int32_t* wb,
+                        int64_t max_items, float err_c, bool vec, int32_t* G_ids, float* G_d2) {
+  const size_t lds = refine_tile_lds(d, RB, SINGLE, kappa);
+  hipFuncSetAttribute((const void*)k_refine_tile<BF16, L, V, RB, SINGLE>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  k_refine_tile<BF16, L, V, RB, SINGLE><<<grid, 512, lds, ctx->stream>>>(
+      X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, err_c, vec ? 1 : 0, G_ids, G_d2);
+}
+
+template <bool BF16, int L, int V>
+static knnkm_status launch_refine(knnkm_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, int dpad,
+                                  int kappa, int32_t k, const int32_t* off, const int32_t* mem,
+                                  const int32_t* wb, int rb1, int rb2, float err_c, bool vec,
+                                  int32_t* G_ids, float* G_d2) {
+  // one tile per cluster of at most rb1 members
+  switch (rb1) {
+    case 64: launch_tile<BF16, L, V, 64, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, err_c, vec, G_ids, G_d2); break;
+    case 32: launch_tile<BF16, L, V, 32, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, err_c, vec, G_ids, G_d2); break;
+    default: launch_tile<BF16, L, V, 16, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, err_c, vec, G_ids, G_d2); break;
+  }
+  KNNKM_TRY(knnkm_check(ctx, "graph refine (one-tile clusters)"));
+  // larger clusters: blocks of rb2 rows walking blocks of rb2 columns; the
+  // sum over clusters of ceil(s / rb2) is at most n / rb2 + k
+  const int64_t max_items = n / rb2 + k + 1;
+  const unsigned g = (unsigned)max_items;
+  switch (rb2) {
+    case 64: launch_tile<BF16, L, V, 64, false>(ctx, g, X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, err_c, vec, G_ids, G_d2); break;
+    case 32: launch_tile<BF16, L, V, 32, false>(ctx, g, X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, err_c, vec, G_ids, G_d2); break;
+    default: launch_tile<BF16, L, V, 16, false>(ctx, g, X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, err_c, vec, G_ids, G_d2); break;
+  }
+  return knnkm_check(ctx, "graph refine (multi-tile clusters)");
 }
 
 knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        const int32_t* labels, int32_t k, int32_t precision, int32_t* G_ids,
                        float* G_d2, int32_t kappa) {
-  const size_t lds = refine_lds_bytes(d, kappa);
-  if (lds > 160 * 1024)
-    return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "graph refine: d=%d with kappa=%d needs %zu B of LDS", d,
-                      kappa, lds);
+  const int rb1 = pick_rb(d, true, kappa), rb2 = pick_rb(d, false, kappa);
+  if (!rb1 || !rb2)
+    return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "graph refine: d=%d with kappa=%d does not fit in LDS", d,
+                      kappa);
   KNNKM_WS(ctx, counts, int32_t, "rf_counts", k);
   KNNKM_WS(ctx, off, int32_t, "rf_offsets", (int64_t)k + 1);
   KNNKM_WS(ctx, mem, int32_t, "rf_members", n);
   KNNKM_WS(ctx, wb, int32_t, "rf_wb", (int64_t)k + 1);
   KNNKM_TRY(ks_label_sort(ctx, labels, n, k, counts, off, mem));
-  k_row_blocks<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, wb);
+  const int dpad = (d + 31) / 32 * 32;
+  k_row_blocks<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, rb1, rb2, wb);
   KNNKM_TRY(knnkm_check(ctx, "refine blocks"));
   KNNKM_TRY(ks_scan_exclusive(ctx, wb, wb, k, true));
-  const int64_t max_items = (int64_t)k + (n + RB - 1) / RB;
-  const int dpad = (d + 31) / 32 * 32;
-  // Screening bound (squared-distance units, relative to ||x||^2 + ||y||^2),
-  // twice the worst-case rounding analysis; see the design notes.
+  // Screening bound (squared-distance units, relative to ||x||^2 + ||y||^2):
+  // twice the worst-case rounding of the float32 Gram, the float32 norms and
+  // the final additions; plus the bfloat16 rounding of both operands.
   const double u = 0x1p-24;
   double err = (2.0 * dpad + 8.0) * u;
   if (precision == KNNKM_BF16_RERANK) err += 2.0 * (0x1p-7 + 0x1p-15);
   const float err_c = (float)(2.0 * err);
-  if (precision == KNNKM_BF16_RERANK) {
-    hipFuncSetAttribute((const void*)k_refine<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_refine<true><<<(unsigned)max_items, 256, lds, ctx->stream>>>(X, d, ldx, dpad, kappa, k, off, mem, wb,
-                                                                   max_items, err_c, G_ids, G_d2);
-  } else {
-    hipFuncSetAttribute((const void*)k_refine<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_refine<false><<<(unsigned)max_items, 256, lds, ctx->stream>>>(X, d, ldx, dpad, kappa, k, off, mem, wb,
-                                                                    max_items, err_c, G_ids, G_d2);
+  const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+  int gL, gV;
+  pick_group(d, 1, &gL, &gV);
+#define RF(BF, LL, VV)                                                                                    \
+  return launch_refine<BF, LL, VV>(ctx, X, n, d, ldx, dpad, kappa, k, off, mem, wb, rb1, rb2, err_c, vec, \
+                                   G_ids, G_d2)
+#define RF_L(BF, VV)                \
+  switch (gL) {                     \
+    case 4: RF(BF, 4, VV);          \
+    case 8: RF(BF, 8, VV);          \
+    case 16: RF(BF, 16, VV);        \
+    case 32: RF(BF, 32, VV);        \
+    default: RF(BF, 64, VV);        \
   }
-  return knnkm_check(ctx, "graph refine");
+  if (precision == KNNKM_BF16_RERANK) {
+    if (gV == 4) { RF_L(true, 4) } else { RF_L(true, 8) }
+  } else {
+    if (gV == 4) { RF_L(false, 4) } else { RF_L(false, 8) }
+  }
+#undef RF_L
+#undef RF
 }
 
 extern "C" knnkm_status knnkm_graph_init(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d,

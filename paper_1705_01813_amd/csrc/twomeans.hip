@@ -15,7 +15,7 @@
 //             of the float64 mean; an empty side keeps its centroid
 //   delta     the same delta with the final centroids, stored as an ordered key
 //   split     the first ceil(s/2) members in (delta, id) order go left:
-//             nodes of <= TM_TILE members sort (delta, id) in LDS; larger nodes
+//             nodes of <= TM_SMALL members sort (delta, id) in LDS; larger nodes
 //             find the threshold by a 12-digit radix select over the 96-bit
 //             (delta key, id) and partition tile by tile
 // Leaves are numbered left to right.
@@ -23,19 +23,23 @@
 #include <cstring>
 #include <numeric>
 
-#include "common.h"
+#include "rowgroup.h"
 
-#define TM_TILE 2048
+#define TM_TILE 1024    // positions per tile of the per-member passes
+#define TM_SMALL 2048   // nodes up to this size split inside one block
+#define TM_CHUNK 16     // tiles per chunk of the two-stage node reduction
 
 struct TMLevel {
   int depth;
   int nsplit;            // split nodes at this depth
   int split_base;        // into plan.split_* arrays
   int ntiles, tile_base; // tiles of split nodes
-  int nbig, big_base;    // split nodes with size > TM_TILE
+  int nbig, big_base;    // split nodes with size > TM_SMALL
   int nbigtiles, bigtile_base;
-  int nsmall, small_base;  // split nodes with size <= TM_TILE
+  int nsmall, small_base;  // split nodes with size <= TM_SMALL
   int ncopy, copy_base;    // unsplit nodes (copied unchanged)
+  int nchunks, chunk_base; // groups of up to TM_CHUNK tiles of one node
+  int max_node_tiles;      // largest number of tiles of one split node
 };
 
 struct TMPlan {
@@ -52,13 +56,17 @@ struct TMPlan {
   std::vector<int32_t> small_split;                       // local split index of small nodes
   std::vector<int32_t> copy_off, copy_size;               // unsplit nodes
   std::vector<int32_t> leaf_off;                          // k+1
-  int max_split = 0, max_tiles = 0, max_big = 0;
+  std::vector<int32_t> big_btb, big_bte;                  // per big node: range in the bigtile list
+  std::vector<int32_t> split_cb, split_ce;                // per split node: range of its chunks
+  std::vector<int32_t> chunk_tb, chunk_te;                // per chunk: range of its tiles
+  int max_split = 0, max_tiles = 0, max_big = 0, max_chunks = 0;
   // device copies
   void* dev = nullptr;
   size_t dev_bytes = 0;
   const int32_t *d_split_off, *d_split_size, *d_split_tile_begin, *d_split_tile_end, *d_tile_split,
       *d_tile_start, *d_tile_len, *d_big_split, *d_bigtile, *d_bigtile_big, *d_small_split,
-      *d_copy_off, *d_copy_size, *d_leaf_off;
+      *d_copy_off, *d_copy_size, *d_leaf_off, *d_big_btb, *d_big_bte, *d_split_cb, *d_split_ce,
+      *d_chunk_tb, *d_chunk_te;
   const int64_t* d_split_heap;
 };
 
@@ -92,6 +100,8 @@ static void build_plan(TMPlan& P, int64_t n, int32_t k) {
     L.bigtile_base = (int)P.bigtile.size();
     L.small_base = (int)P.small_split.size();
     L.copy_base = (int)P.copy_off.size();
+    L.chunk_base = (int)P.chunk_tb.size();
+    L.max_node_tiles = 0;
     std::vector<int64_t> noff, nsize;
     for (int i = 0; i < m; ++i) {
       if (split[i]) {
@@ -100,10 +110,14 @@ static void build_plan(TMPlan& P, int64_t n, int32_t k) {
         P.split_size.push_back((int32_t)size[i]);
         P.split_heap.push_back(((int64_t)1 << depth) + i);
         P.split_tile_begin.push_back((int32_t)P.tile_split.size() - L.tile_base);
-        const bool big = size[i] > TM_TILE;
+        const bool big = size[i] > TM_SMALL;
         const int bigl = (int)P.big_split.size() - L.big_base;
-        if (big) P.big_split.push_back(local);
-        else P.small_split.push_back(local);
+        if (big) {
+          P.big_split.push_back(local);
+          P.big_btb.push_back((int32_t)P.bigtile.size() - L.bigtile_base);
+        } else {
+          P.small_split.push_back(local);
+        }
         for (int64_t s = 0; s < size[i]; s += TM_TILE) {
           const int tl = (int)P.tile_split.size() - L.tile_base;
           P.tile_split.push_back(local);
@@ -115,6 +129,17 @@ static void build_plan(TMPlan& P, int64_t n, int32_t k) {
           }
         }
         P.split_tile_end.push_back((int32_t)P.tile_split.size() - L.tile_base);
+        if (big) P.big_bte.push_back((int32_t)P.bigtile.size() - L.bigtile_base);
+        {
+          const int tb = P.split_tile_begin.back(), te = P.split_tile_end.back();
+          L.max_node_tiles = std::max(L.max_node_tiles, te - tb);
+          P.split_cb.push_back((int32_t)P.chunk_tb.size() - L.chunk_base);
+          for (int t = tb; t < te; t += TM_CHUNK) {
+            P.chunk_tb.push_back(t);
+            P.chunk_te.push_back(std::min(te, t + TM_CHUNK));
+          }
+          P.split_ce.push_back((int32_t)P.chunk_tb.size() - L.chunk_base);
+        }
         const int64_t h = (size[i] + 1) / 2;
         noff.push_back(off[i]);
         nsize.push_back(h);
@@ -133,6 +158,8 @@ static void build_plan(TMPlan& P, int64_t n, int32_t k) {
     L.nbigtiles = (int)P.bigtile.size() - L.bigtile_base;
     L.nsmall = (int)P.small_split.size() - L.small_base;
     L.ncopy = (int)P.copy_off.size() - L.copy_base;
+    L.nchunks = (int)P.chunk_tb.size() - L.chunk_base;
+    P.max_chunks = std::max(P.max_chunks, L.nchunks);
     P.max_split = std::max(P.max_split, L.nsplit);
     P.max_tiles = std::max(P.max_tiles, L.ntiles);
     P.max_big = std::max(P.max_big, L.nbig);
@@ -156,7 +183,10 @@ static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P) {
       {P.bigtile.data(), P.bigtile.size() * 4},       {P.bigtile_big.data(), P.bigtile_big.size() * 4},
       {P.small_split.data(), P.small_split.size() * 4}, {P.copy_off.data(), P.copy_off.size() * 4},
       {P.copy_size.data(), P.copy_size.size() * 4},   {P.leaf_off.data(), P.leaf_off.size() * 4},
-      {P.split_heap.data(), P.split_heap.size() * 8}};
+      {P.split_heap.data(), P.split_heap.size() * 8},
+      {P.big_btb.data(), P.big_btb.size() * 4},       {P.big_bte.data(), P.big_bte.size() * 4},
+      {P.split_cb.data(), P.split_cb.size() * 4},     {P.split_ce.data(), P.split_ce.size() * 4},
+      {P.chunk_tb.data(), P.chunk_tb.size() * 4},     {P.chunk_te.data(), P.chunk_te.size() * 4}};
   size_t total = 0;
   std::vector<size_t> at;
   for (auto& p : parts) {
@@ -187,6 +217,12 @@ static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P) {
   P.d_copy_size = (const int32_t*)(b + at[12]);
   P.d_leaf_off = (const int32_t*)(b + at[13]);
   P.d_split_heap = (const int64_t*)(b + at[14]);
+  P.d_big_btb = (const int32_t*)(b + at[15]);
+  P.d_big_bte = (const int32_t*)(b + at[16]);
+  P.d_split_cb = (const int32_t*)(b + at[17]);
+  P.d_split_ce = (const int32_t*)(b + at[18]);
+  P.d_chunk_tb = (const int32_t*)(b + at[19]);
+  P.d_chunk_te = (const int32_t*)(b + at[20]);
   return KNNKM_OK;
 }
 
@@ -221,23 +257,33 @@ __global__ __launch_bounds__(256) void k_tm_seed(const float* __restrict__ X, in
   }
 }
 
-template <int T>
-__device__ inline double tm_delta(const float (&x)[T], const float* __restrict__ cu,
-                                  const float* __restrict__ cv, int d, int lane) {
+// delta = sum_j (c_v - c_u)_j (2 x_j - c_u - c_v)_j over the group's dims, with
+// w = c_v - c_u and s = c_u + c_v held per lane in float64 (every product of
+// these float32-derived values is exact in float64; only the sums round).
+template <int V>
+__device__ inline double tm_part(const float (&x)[V], const double (&wv)[V], const double (&sv)[V]) {
   double acc = 0.0;
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
-    int dim = lane + 64 * t;
-    if (dim < d) {
-      double u = (double)cu[dim], v = (double)cv[dim];
-      acc = fma(v - u, 2.0 * (double)x[t] - (u + v), acc);
-    }
-  }
-  return wave_sum(acc);
+  for (int e = 0; e < V; ++e) acc = fma(wv[e], fma(2.0, (double)x[e], -sv[e]), acc);
+  return acc;
 }
 
-// One block per tile: side of each member, float64 sums per side.
-template <int T>
+template <int V>
+__device__ inline void tm_node_consts(const float* __restrict__ cu, const float* __restrict__ cv, int j, int d,
+                                      double (&wv)[V], double (&sv)[V]) {
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const int dim = j * V + e;
+    const double u = dim < d ? (double)cu[dim] : 0.0, v = dim < d ? (double)cv[dim] : 0.0;
+    wv[e] = v - u;
+    sv[e] = u + v;
+  }
+}
+
+// One block per tile: side of each member, float64 sums per side.  Group gid
+// of the block takes tile positions gid, gid + NG, ...; the NG group sums are
+// then added in group order.
+template <int L, int V>
 __global__ __launch_bounds__(256) void k_tm_accum(const float* __restrict__ X, int d, int64_t ldx,
                                                   const int32_t* __restrict__ perm,
                                                   const int32_t* __restrict__ t_split,
@@ -245,109 +291,142 @@ __global__ __launch_bounds__(256) void k_tm_accum(const float* __restrict__ X, i
                                                   const int32_t* __restrict__ t_len,
                                                   const float* __restrict__ cent,
                                                   double* __restrict__ partial,
-                                                  int32_t* __restrict__ pcnt) {
-  __shared__ double sh[4][2][T * 64];
-  __shared__ int32_t shc[4][2];
+                                                  int32_t* __restrict__ pcnt, int vec) {
+  constexpr int NG = 4 * (64 / L);
+  __shared__ double sh[NG][2][L * V];
+  __shared__ int32_t shc[NG][2];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = lane % L, gid = w * (64 / L) + lane / L;
   const int tile = blockIdx.x;
   const int js = t_split[tile];
   const int start = t_start[tile], len = t_len[tile];
   const float* cu = cent + (int64_t)js * 2 * d;
-  const float* cv = cu + d;
-  double au[T], av[T];
+  double wv[V], sv[V];
+  tm_node_consts<V>(cu, cu + d, j, d, wv, sv);
+  double au[V], av[V];
 #pragma unroll
-  for (int t = 0; t < T; ++t) au[t] = av[t] = 0.0;
+  for (int e = 0; e < V; ++e) au[e] = av[e] = 0.0;
   int cnu = 0, cnv = 0;
-  for (int p = w; p < len; p += 4) {
-    const float* xr = X + (int64_t)perm[start + p] * ldx;
-    float x[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      int dim = lane + 64 * t;
-      x[t] = dim < d ? xr[dim] : 0.f;
-    }
-    const double delta = tm_delta<T>(x, cu, cv, d, lane);
+  for (int p = gid; p < len; p += NG) {
+    float x[V];
+    load_row<V>(x, X + (int64_t)perm[start + p] * ldx, j, d, vec);
+    const double delta = group_sum<L>(tm_part<V>(x, wv, sv));
     if (delta <= 0.0) {
       ++cnu;
 #pragma unroll
-      for (int t = 0; t < T; ++t) au[t] += (double)x[t];
+      for (int e = 0; e < V; ++e) au[e] += (double)x[e];
     } else {
       ++cnv;
 #pragma unroll
-      for (int t = 0; t < T; ++t) av[t] += (double)x[t];
+      for (int e = 0; e < V; ++e) av[e] += (double)x[e];
     }
   }
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
-    sh[w][0][lane + 64 * t] = au[t];
-    sh[w][1][lane + 64 * t] = av[t];
+  for (int e = 0; e < V; ++e) {
+    sh[gid][0][j * V + e] = au[e];
+    sh[gid][1][j * V + e] = av[e];
   }
-  if (lane == 0) {
-    shc[w][0] = cnu;
-    shc[w][1] = cnv;
+  if (j == 0) {
+    shc[gid][0] = cnu;
+    shc[gid][1] = cnv;
   }
   __syncthreads();
   double* out = partial + (int64_t)tile * 2 * d;
   for (int e = threadIdx.x; e < 2 * d; e += 256) {
     const int side = e / d, dim = e % d;
-    out[e] = ((sh[0][side][dim] + sh[1][side][dim]) + sh[2][side][dim]) + sh[3][side][dim];
+    double s = 0.0;
+    for (int q = 0; q < NG; ++q) s += sh[q][side][dim];
+    out[e] = s;
   }
-  if (threadIdx.x < 2)
-    pcnt[tile * 2 + threadIdx.x] =
-        shc[0][threadIdx.x] + shc[1][threadIdx.x] + shc[2][threadIdx.x] + shc[3][threadIdx.x];
+  if (threadIdx.x < 2) {
+    int c = 0;
+    for (int q = 0; q < NG; ++q) c += shc[q][threadIdx.x];
+    pcnt[tile * 2 + threadIdx.x] = c;
+  }
 }
 
-// One wave per split node: new centroids from the tile partials (tile order).
-__global__ __launch_bounds__(256) void k_tm_final(int d, int nsplit,
-                                                  const int32_t* __restrict__ s_tb,
+// Partial sums of the entries [tb, te) of `src` in a fixed order: wave w adds
+// entries w, w+4, ... in order into sh[w][.] and its counts into shc[w][.];
+// callers add the four wave sums in wave order.
+__device__ void tm_sum_range(int d, int tb, int te, const double* __restrict__ src,
+                             const int32_t* __restrict__ scnt, double* sh /*[4][2d]*/, int32_t* shc /*[4][2]*/) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int e = lane; e < 2 * d; e += 64) {
+    double s = 0.0;
+    for (int t = tb + w; t < te; t += 4) s += src[(int64_t)t * 2 * d + e];
+    sh[w * 2 * d + e] = s;
+  }
+  if (lane == 0) {
+    int nu = 0, nv = 0;
+    for (int t = tb + w; t < te; t += 4) {
+      nu += scnt[2 * t];
+      nv += scnt[2 * t + 1];
+    }
+    shc[2 * w] = nu;
+    shc[2 * w + 1] = nv;
+  }
+  __syncthreads();
+}
+
+// One block per chunk of tiles: chunk partial = ordered sum of its tiles.
+__global__ __launch_bounds__(256) void k_tm_chunk(int d, const int32_t* __restrict__ c_tb,
+                                                  const int32_t* __restrict__ c_te,
+                                                  const double* __restrict__ partial,
+                                                  const int32_t* __restrict__ pcnt,
+                                                  double* __restrict__ cpart, int32_t* __restrict__ ccnt) {
+  __shared__ double sh[4 * 2 * KNNKM_MAX_D];
+  __shared__ int32_t shc[8];
+  const int c = blockIdx.x;
+  tm_sum_range(d, c_tb[c], c_te[c], partial, pcnt, sh, shc);
+  for (int e = threadIdx.x; e < 2 * d; e += 256)
+    cpart[(int64_t)c * 2 * d + e] = ((sh[e] + sh[2 * d + e]) + sh[4 * d + e]) + sh[6 * d + e];
+  if (threadIdx.x < 2)
+    ccnt[2 * c + threadIdx.x] = shc[threadIdx.x] + shc[2 + threadIdx.x] + shc[4 + threadIdx.x] + shc[6 + threadIdx.x];
+}
+
+// One block per split node: new centroids from its partials (tiles, or
+// chunks of tiles for nodes with many tiles), added in a fixed order.
+__global__ __launch_bounds__(256) void k_tm_final(int d, const int32_t* __restrict__ s_tb,
                                                   const int32_t* __restrict__ s_te,
                                                   const double* __restrict__ partial,
                                                   const int32_t* __restrict__ pcnt,
                                                   float* __restrict__ cent) {
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= nsplit) return;
-  int nu = 0, nv = 0;
-  for (int t = s_tb[j]; t < s_te[j]; ++t) {
-    nu += pcnt[2 * t];
-    nv += pcnt[2 * t + 1];
-  }
-  for (int dim = lane; dim < d; dim += 64) {
-    double su = 0.0, sv = 0.0;
-    for (int t = s_tb[j]; t < s_te[j]; ++t) {
-      su += partial[(int64_t)t * 2 * d + dim];
-      sv += partial[(int64_t)t * 2 * d + d + dim];
-    }
-    if (nu > 0) cent[(int64_t)j * 2 * d + dim] = (float)(su / (double)nu);
-    if (nv > 0) cent[(int64_t)j * 2 * d + d + dim] = (float)(sv / (double)nv);
+  __shared__ double sh[4 * 2 * KNNKM_MAX_D];
+  __shared__ int32_t shc[8];
+  const int js = blockIdx.x;
+  tm_sum_range(d, s_tb[js], s_te[js], partial, pcnt, sh, shc);
+  const int cu_n = shc[0] + shc[2] + shc[4] + shc[6];
+  const int cv_n = shc[1] + shc[3] + shc[5] + shc[7];
+  for (int e = threadIdx.x; e < 2 * d; e += 256) {
+    const double s = ((sh[e] + sh[2 * d + e]) + sh[4 * d + e]) + sh[6 * d + e];
+    const int cnt = e < d ? cu_n : cv_n;
+    if (cnt > 0) cent[(int64_t)js * 2 * d + e] = (float)(s / (double)cnt);
   }
 }
 
 // delta keys of every member of every split node (position-indexed).
-template <int T>
+template <int L, int V>
 __global__ __launch_bounds__(256) void k_tm_delta(const float* __restrict__ X, int d, int64_t ldx,
                                                   const int32_t* __restrict__ perm,
                                                   const int32_t* __restrict__ t_split,
                                                   const int32_t* __restrict__ t_start,
                                                   const int32_t* __restrict__ t_len,
                                                   const float* __restrict__ cent,
-                                                  uint64_t* __restrict__ keys) {
+                                                  uint64_t* __restrict__ keys, int vec) {
+  constexpr int NG = 4 * (64 / L);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = lane % L, gid = w * (64 / L) + lane / L;
   const int tile = blockIdx.x;
   const int js = t_split[tile];
   const int start = t_start[tile], len = t_len[tile];
   const float* cu = cent + (int64_t)js * 2 * d;
-  const float* cv = cu + d;
-  for (int p = w; p < len; p += 4) {
-    const float* xr = X + (int64_t)perm[start + p] * ldx;
-    float x[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      int dim = lane + 64 * t;
-      x[t] = dim < d ? xr[dim] : 0.f;
-    }
-    const double delta = tm_delta<T>(x, cu, cv, d, lane);
-    if (lane == 0) keys[start + p] = dkey(delta);
+  double wv[V], sv[V];
+  tm_node_consts<V>(cu, cu + d, j, d, wv, sv);
+  for (int p = gid; p < len; p += NG) {
+    float x[V];
+    load_row<V>(x, X + (int64_t)perm[start + p] * ldx, j, d, vec);
+    const double delta = group_sum<L>(tm_part<V>(x, wv, sv));
+    if (j == 0) keys[start + p] = dkey(delta);
   }
 }
 
@@ -389,7 +468,7 @@ __device__ void tm_partition_block(const int32_t* __restrict__ perm, const uint6
   }
 }
 
-// Nodes of at most TM_TILE members: bitonic sort of (key, id) in LDS to find
+// Nodes of at most TM_SMALL members: bitonic sort of (key, id) in LDS to find
 // the ceil(s/2)-th pair, then a stable partition.
 __global__ __launch_bounds__(256) void k_tm_split_small(const int32_t* __restrict__ perm,
                                                         const uint64_t* __restrict__ keys,
@@ -397,8 +476,8 @@ __global__ __launch_bounds__(256) void k_tm_split_small(const int32_t* __restric
                                                         const int32_t* __restrict__ s_off,
                                                         const int32_t* __restrict__ s_size,
                                                         int32_t* __restrict__ perm_out) {
-  __shared__ uint64_t sk[TM_TILE];
-  __shared__ int32_t si[TM_TILE];
+  __shared__ uint64_t sk[TM_SMALL];
+  __shared__ int32_t si[TM_SMALL];
   __shared__ int32_t sh_scan[256];
   const int j = small_split[blockIdx.x];
   const int off = s_off[j], s = s_size[j];
@@ -500,24 +579,27 @@ __global__ __launch_bounds__(256) void k_tm_sel_hist(const int32_t* __restrict__
   if (c) atomicAdd(&hist[b * 256 + threadIdx.x], c);
 }
 
-__global__ void k_tm_sel_pick(int nbig, int pass, SelState* st, int32_t* hist) {
+// One 256-thread block per big node: the bucket holding the rank-h element is
+// the digit whose exclusive prefix count is < h <= inclusive count.
+__global__ __launch_bounds__(256) void k_tm_sel_pick(int pass, SelState* st, int32_t* hist) {
+  __shared__ int32_t sh[8];
   const int b = blockIdx.x;
-  if (b >= nbig || threadIdx.x != 0) return;
   int32_t* hh = hist + b * 256;
-  SelState s = st[b];
-  int run = 0, dg = 0;
-  for (dg = 0; dg < 256; ++dg) {
-    if (run + hh[dg] >= s.h) break;
-    run += hh[dg];
+  const int32_t c = hh[threadIdx.x];
+  const SelState s = st[b];
+  int32_t tot;
+  const int32_t ex = block_scan_excl_256(c, sh, &tot);
+  if (c > 0 && ex < s.h && s.h <= ex + c) {
+    SelState t = s;
+    t.h -= ex;
+    const int dg = threadIdx.x;
+    if (pass < 8)
+      t.pk |= (uint64_t)dg << (56 - 8 * pass);
+    else
+      t.pi |= (uint32_t)dg << (24 - 8 * (pass - 8));
+    st[b] = t;
   }
-  if (dg > 255) dg = 255;  // unreachable when counts are consistent
-  s.h -= run;
-  if (pass < 8)
-    s.pk |= (uint64_t)dg << (56 - 8 * pass);
-  else
-    s.pi |= (uint32_t)dg << (24 - 8 * (pass - 8));
-  st[b] = s;
-  for (int e = 0; e < 256; ++e) hh[e] = 0;
+  hh[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_tm_part_count(const int32_t* __restrict__ perm,
@@ -543,19 +625,21 @@ __global__ __launch_bounds__(256) void k_tm_part_count(const int32_t* __restrict
 }
 
 // Exclusive scan of the left counts over the tiles of each big node.
-__global__ void k_tm_part_scan(int nbig, int nbigtiles, const int32_t* __restrict__ bigtile_big,
-                               int32_t* __restrict__ tile_left) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  int prev = -1, run = 0;
-  for (int t = 0; t < nbigtiles; ++t) {
-    const int b = bigtile_big[t];
-    if (b != prev) {
-      run = 0;
-      prev = b;
-    }
-    const int c = tile_left[t];
-    tile_left[t] = run;
-    run += c;
+// One block per big node: exclusive scan of the left counts of its tiles.
+__global__ __launch_bounds__(256) void k_tm_part_scan(const int32_t* __restrict__ big_btb,
+                                                      const int32_t* __restrict__ big_bte,
+                                                      int32_t* __restrict__ tile_left) {
+  __shared__ int32_t sh[8];
+  const int b = blockIdx.x;
+  const int tb = big_btb[b], te = big_bte[b];
+  int32_t carry = 0;
+  for (int base = tb; base < te; base += 256) {
+    const int t = base + threadIdx.x;
+    const int32_t c = t < te ? tile_left[t] : 0;
+    int32_t tot;
+    const int32_t ex = block_scan_excl_256(c, sh, &tot);
+    if (t < te) tile_left[t] = carry + ex;
+    carry += tot;
   }
 }
 
@@ -620,21 +704,45 @@ __global__ void k_tm_labels(const int32_t* __restrict__ perm, const int32_t* __r
 }
 
 // ------------------------------------------------------------------ driver --
-template <int T>
-static void launch_accum(knnkm_ctx* ctx, const TMPlan& P, const TMLevel& L, const float* X, int d,
+template <int L, int V>
+static void launch_accum(knnkm_ctx* ctx, const TMPlan& P, const TMLevel& Lv, const float* X, int d,
                          int64_t ldx, const int32_t* perm, const float* cent, double* partial,
-                         int32_t* pcnt) {
-  k_tm_accum<T><<<L.ntiles, 256, 0, ctx->stream>>>(X, d, ldx, perm, P.d_tile_split + L.tile_base,
-                                                   P.d_tile_start + L.tile_base,
-                                                   P.d_tile_len + L.tile_base, cent, partial, pcnt);
+                         int32_t* pcnt, bool vec) {
+  k_tm_accum<L, V><<<Lv.ntiles, 256, 0, ctx->stream>>>(X, d, ldx, perm, P.d_tile_split + Lv.tile_base,
+                                                       P.d_tile_start + Lv.tile_base,
+                                                       P.d_tile_len + Lv.tile_base, cent, partial, pcnt,
+                                                       vec ? 1 : 0);
 }
-template <int T>
-static void launch_delta(knnkm_ctx* ctx, const TMPlan& P, const TMLevel& L, const float* X, int d,
-                         int64_t ldx, const int32_t* perm, const float* cent, uint64_t* keys) {
-  k_tm_delta<T><<<L.ntiles, 256, 0, ctx->stream>>>(X, d, ldx, perm, P.d_tile_split + L.tile_base,
-                                                   P.d_tile_start + L.tile_base,
-                                                   P.d_tile_len + L.tile_base, cent, keys);
+template <int L, int V>
+static void launch_delta(knnkm_ctx* ctx, const TMPlan& P, const TMLevel& Lv, const float* X, int d,
+                         int64_t ldx, const int32_t* perm, const float* cent, uint64_t* keys, bool vec) {
+  k_tm_delta<L, V><<<Lv.ntiles, 256, 0, ctx->stream>>>(X, d, ldx, perm, P.d_tile_split + Lv.tile_base,
+                                                       P.d_tile_start + Lv.tile_base,
+                                                       P.d_tile_len + Lv.tile_base, cent, keys,
+                                                       vec ? 1 : 0);
 }
+
+// Dispatch on the row-group shape chosen for d.
+#define TM_DISPATCH(FN, ...)                     \
+  do {                                           \
+    if (gV == 4) {                               \
+      switch (gL) {                              \
+        case 4: FN<4, 4>(__VA_ARGS__); break;    \
+        case 8: FN<8, 4>(__VA_ARGS__); break;    \
+        case 16: FN<16, 4>(__VA_ARGS__); break;  \
+        case 32: FN<32, 4>(__VA_ARGS__); break;  \
+        default: FN<64, 4>(__VA_ARGS__); break;  \
+      }                                          \
+    } else {                                     \
+      switch (gL) {                              \
+        case 4: FN<4, 8>(__VA_ARGS__); break;    \
+        case 8: FN<8, 8>(__VA_ARGS__); break;    \
+        case 16: FN<16, 8>(__VA_ARGS__); break;  \
+        case 32: FN<32, 8>(__VA_ARGS__); break;  \
+        default: FN<64, 8>(__VA_ARGS__); break;  \
+      }                                          \
+    }                                            \
+  } while (0)
 
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
@@ -648,8 +756,10 @@ knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, i
     KNNKM_TRY(upload_plan(ctx, *ctx->tm_plan));
   }
   const TMPlan& P = *ctx->tm_plan;
-  const int T = (d + 63) / 64;
-  if (T > 8) return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "twomeans: d=%d > %d", d, KNNKM_MAX_D);
+  if (d > KNNKM_MAX_D) return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "twomeans: d=%d > %d", d, KNNKM_MAX_D);
+  int gL, gV;
+  pick_group(d, 1, &gL, &gV);
+  const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
   KNNKM_WS(ctx, permbuf, int32_t, "tm_perm", 2 * n);
   KNNKM_WS(ctx, keys, uint64_t, "tm_keys", n);
   KNNKM_WS(ctx, cent, float, "tm_cent", (int64_t)P.max_split * 2 * d);
@@ -658,6 +768,8 @@ knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, i
   KNNKM_WS(ctx, sel, SelState, "tm_sel", std::max(1, P.max_big));
   KNNKM_WS(ctx, hist, int32_t, "tm_hist", (int64_t)std::max(1, P.max_big) * 256);
   KNNKM_WS(ctx, tleft, int32_t, "tm_tleft", std::max(1, P.max_tiles));
+  KNNKM_WS(ctx, cpart, double, "tm_cpart", (int64_t)std::max(1, P.max_chunks) * 2 * d);
+  KNNKM_WS(ctx, ccnt, int32_t, "tm_ccnt", (int64_t)std::max(1, P.max_chunks) * 2);
   int32_t* perm = permbuf;
   int32_t* perm_next = permbuf + n;
   k_iota<<<grid_for(n, 256, 4096), 256, 0, ctx->stream>>>(perm, n);
@@ -669,29 +781,21 @@ knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, i
     k_tm_seed<<<gw, 256, 0, ctx->stream>>>(X, d, ldx, perm, L.nsplit, s_off, s_size,
                                            P.d_split_heap + L.split_base, seed, round_tag, cent);
     for (int it = 0; it < iters; ++it) {
-      switch (T) {
-        case 1: launch_accum<1>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
-        case 2: launch_accum<2>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
-        case 3: launch_accum<3>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
-        case 4: launch_accum<4>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
-        case 5: launch_accum<5>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
-        case 6: launch_accum<6>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
-        case 7: launch_accum<7>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
-        default: launch_accum<8>(ctx, P, L, X, d, ldx, perm, cent, partial, pcnt); break;
+      TM_DISPATCH(launch_accum, ctx, P, L, X, d, ldx, perm, cent, partial, pcnt, vec);
+      if (L.max_node_tiles > TM_CHUNK) {
+        // nodes with many tiles: tiles -> chunks -> node, each stage in fixed order
+        k_tm_chunk<<<L.nchunks, 256, 0, ctx->stream>>>(d, P.d_chunk_tb + L.chunk_base,
+                                                       P.d_chunk_te + L.chunk_base, partial, pcnt, cpart,
+                                                       ccnt);
+        k_tm_final<<<L.nsplit, 256, 0, ctx->stream>>>(d, P.d_split_cb + L.split_base,
+                                                      P.d_split_ce + L.split_base, cpart, ccnt, cent);
+      } else {
+        k_tm_final<<<L.nsplit, 256, 0, ctx->stream>>>(d, P.d_split_tile_begin + L.split_base,
+                                                      P.d_split_tile_end + L.split_base, partial, pcnt,
+                                                      cent);
       }
-      k_tm_final<<<gw, 256, 0, ctx->stream>>>(d, L.nsplit, P.d_split_tile_begin + L.split_base,
-                                              P.d_split_tile_end + L.split_base, partial, pcnt, cent);
     }
-    switch (T) {
-      case 1: launch_delta<1>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
-      case 2: launch_delta<2>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
-      case 3: launch_delta<3>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
-      case 4: launch_delta<4>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
-      case 5: launch_delta<5>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
-      case 6: launch_delta<6>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
-      case 7: launch_delta<7>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
-      default: launch_delta<8>(ctx, P, L, X, d, ldx, perm, cent, keys); break;
-    }
+    TM_DISPATCH(launch_delta, ctx, P, L, X, d, ldx, perm, cent, keys, vec);
     KNNKM_TRY(knnkm_check(ctx, "twomeans level"));
     if (L.nsmall)
       k_tm_split_small<<<L.nsmall, 256, 0, ctx->stream>>>(perm, keys, P.d_small_split + L.small_base,
@@ -706,10 +810,11 @@ knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, i
                                                                                     sel, hist);
       for (int pass = 0; pass < 12; ++pass) {
         k_tm_sel_hist<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, ts, tl, pass, sel, hist);
-        k_tm_sel_pick<<<L.nbig, 64, 0, ctx->stream>>>(L.nbig, pass, sel, hist);
+        k_tm_sel_pick<<<L.nbig, 256, 0, ctx->stream>>>(pass, sel, hist);
       }
       k_tm_part_count<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, ts, tl, sel, tleft);
-      k_tm_part_scan<<<1, 64, 0, ctx->stream>>>(L.nbig, L.nbigtiles, btb, tleft);
+      k_tm_part_scan<<<L.nbig, 256, 0, ctx->stream>>>(P.d_big_btb + L.big_base, P.d_big_bte + L.big_base,
+                                                      tleft);
       k_tm_part_write<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, bs, s_off, s_size, ts, tl,
                                                             sel, tleft, perm_next);
     }

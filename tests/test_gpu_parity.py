@@ -197,9 +197,21 @@ def test_graph_init_parity(ctx, n, d, kappa):
     assert np.array_equal(host(gd), want_d)
 
 
+def _graph_diff(got_i, got_d, want_i, want_d, lab=None):
+    bad = np.flatnonzero((got_i != want_i).any(1) | (got_d != want_d).any(1))
+    if len(bad) == 0:
+        return ""
+    r = bad[0]
+    msg = f"{len(bad)} rows differ; first row {r}"
+    if lab is not None:
+        msg += f" (cluster {lab[r]} of size {(lab == lab[r]).sum()})"
+    return msg + f"\n got ids {got_i[r].tolist()}\n want    {want_i[r].tolist()}\n got d2 {got_d[r].tolist()}\n want   {want_d[r].tolist()}"
+
+
 @pytest.mark.parametrize("precision", [knnkm.FP32, knnkm.BF16_RERANK])
-@pytest.mark.parametrize("n,d,kappa,k", [(2000, 32, 10, 40), (3000, 128, 20, 60), (600, 512, 50, 10),
-                                         (1500, 20, 8, 3), (400, 64, 30, 1)])
+@pytest.mark.parametrize("n,d,kappa,k", [(2000, 32, 10, 40), (3000, 128, 20, 60), (600, 512, 20, 10),
+                                         (600, 512, 50, 10), (1000, 256, 50, 12), (1500, 20, 8, 3),
+                                         (400, 64, 30, 1)])
 def test_refine_parity(ctx, precision, n, d, kappa, k):
     say("refine", precision, n, d, kappa, k)
     X = datagen.mixture(n, d, 12, seed=d + k)
@@ -208,8 +220,9 @@ def test_refine_parity(ctx, precision, n, d, kappa, k):
     want_i, want_d = knng.refine(X, gi0, gd0, lab)
     gi, gd = dev(gi0), dev(gd0)
     knnkm.knnkm_graph_refine(ctx, dev(X), dev(lab), k, precision, gi, gd)
-    assert np.array_equal(host(gd), want_d)
-    assert np.array_equal(host(gi), want_i)
+    got_i, got_d = host(gi), host(gd)
+    msg = _graph_diff(got_i, got_d, want_i, want_d, lab)
+    assert not msg, msg
 
 
 @pytest.mark.parametrize("precision", [knnkm.FP32, knnkm.BF16_RERANK])
