@@ -165,6 +165,24 @@ knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d
                             int32_t* labels, float* C, int32_t* counts, double* trace_host,
                             int32_t* iters_run_host);
 
+/* Batching form: m independent jobs (graph build and fit, Alg. 3 then Alg. 2)
+ * in one call, every phase one launch over all jobs.
+ *  X: the jobs' rows concatenated; job q owns rows [n_off_host[q],
+ *     n_off_host[q+1]) (host int64 array of m+1 entries, n_off_host[0] = 0)
+ *     and needs kappa + 1 <= n_q rows; k_host[q] clusters (host int32);
+ *     seeds_host[q] keys its random draws (params->seed is not used).
+ *  Outputs (device): G_ids / G_d2 (sum n_q) x kappa with global row ids;
+ *  labels (sum n_q) job-local cluster ids; C (sum k_q) x d and counts (sum
+ *  k_q), job q's clusters after those of jobs 0..q-1; trace_host (host,
+ *  m x (max_iters+1)): E_0..E_T of job q at row q.  early_stop is ignored.
+ *  Each job's results are bit-identical to running it alone through
+ *  knn_build + knn_kmeans_fit with its seed.  Synchronous. */
+knnkm_status knnkm_fit_batched(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, int32_t m,
+                               const int64_t* n_off_host, const int32_t* k_host,
+                               const uint64_t* seeds_host, const knnkm_params* params, int32_t* G_ids,
+                               float* G_d2, int32_t* labels, float* C, int32_t* counts,
+                               double* trace_host);
+
 /* Opt-in phase timing.  While enabled, knn_build and knn_kmeans_fit record
  * HIP events on the context stream around their phases (a few microseconds
  * of overhead per iteration).  knnkm_phase_times waits for those events and

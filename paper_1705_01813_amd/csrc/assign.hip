@@ -82,7 +82,8 @@ __global__ __launch_bounds__(256) void k_assign(
     const float* __restrict__ X, int n, int d, int64_t ldx, const float* __restrict__ C, int k,
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
     float* __restrict__ best_out, unsigned long long* __restrict__ moved_acc,
-    const int* __restrict__ order, int dense, int nchunks, double rel, int S, int vec_x, int vec_c) {
+    const int* __restrict__ order, int dense, int nchunks, double rel, int S, int vec_x, int vec_c,
+    const int* __restrict__ job_of, const int* __restrict__ kbase) {
   constexpr int GW = 64 / L;  // samples per wavefront
   __shared__ unsigned int block_moved;
   if (threadIdx.x == 0) block_moved = 0;
@@ -102,12 +103,21 @@ __global__ __launch_bounds__(256) void k_assign(
       float x[V];
       load_row<V>(x, X + i * ldx, j, d, vec_x);
       const int cur = lab_in ? lab_in[i] : -1;
+      // clusters this sample may join: all of its job's when kappa covers them
+      int kb = 0, kc = k;
+      bool dense_i = dense;
+      if (job_of) {
+        const int q = job_of[i];
+        kb = kbase[q];
+        kc = kbase[q + 1] - kb;
+        dense_i = dense || kappa >= kc;
+      }
       int cv[MAX_SLOTS];
       bool valid[MAX_SLOTS];
 #pragma unroll
       for (int s = 0; s < MAX_SLOTS; ++s) {
         const int e = j + L * s;
-        valid[s] = !dense && s < S && e <= kappa;
+        valid[s] = !dense_i && s < S && e <= kappa;
         cv[s] = -1;
         if (valid[s]) cv[s] = e == 0 ? cur : lab_in[G[i * kappa + (e - 1)]];
       }
@@ -125,8 +135,8 @@ __global__ __launch_bounds__(256) void k_assign(
           b2 = fminf(b2, dq);
         }
       };
-      if (dense)
-        for (int q = 0; q < k; ++q) pass1(q);
+      if (dense_i)
+        for (int q = kb; q < kb + kc; ++q) pass1(q);
       else
         for_each_cand<L>(cv, valid, S, gmask, pass1);
 
@@ -149,8 +159,8 @@ __global__ __launch_bounds__(256) void k_assign(
             }
           }
         };
-        if (dense)
-          for (int q = 0; q < k; ++q) pass2(q);
+        if (dense_i)
+          for (int q = kb; q < kb + kc; ++q) pass2(q);
         else
           for_each_cand<L>(cv, valid, S, gmask, pass2);
         if (cur >= 0 && cur64 >= 0.0 && cur64 == m64) {
@@ -180,21 +190,24 @@ static void launch_assign(knnkm_ctx* ctx, int grid, const float* X, int64_t n, i
                           const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                           const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                           unsigned long long* acc, const int32_t* order, bool dense, int nchunks,
-                          double rel, int S, bool vec_x, bool vec_c) {
+                          double rel, int S, bool vec_x, bool vec_c, const int32_t* job_of,
+                          const int32_t* kbase) {
   k_assign<L, V><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out,
                                                 best_d2, acc, order, dense ? 1 : 0, nchunks, rel, S,
-                                                vec_x ? 1 : 0, vec_c ? 1 : 0);
+                                                vec_x ? 1 : 0, vec_c ? 1 : 0, job_of, kbase);
 }
 
 knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
-                       int64_t* n_moved, const int32_t* order, bool dense) {
+                       int64_t* n_moved, const int32_t* order, bool dense, const int32_t* job_of,
+                       const int32_t* kbase) {
   if (n_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
   if (n == 0) return KNNKM_OK;
+  const bool all_dense = dense;
   int L, V;
-  pick_group(d, dense ? 1 : (kappa + 1 + MAX_SLOTS - 1) / MAX_SLOTS, &L, &V);
-  const int S = dense ? 0 : (kappa + 1 + L - 1) / L;
+  pick_group(d, all_dense ? 1 : (kappa + 1 + MAX_SLOTS - 1) / MAX_SLOTS, &L, &V);
+  const int S = all_dense ? 0 : (kappa + 1 + L - 1) / L;
   const int nchunks = (int)((n + ASSIGN_PER_BLOCK - 1) / ASSIGN_PER_BLOCK);
   const int grid = ((nchunks + 7) / 8) * 8;
   // float32 evaluation: V products and sums per lane, log2(L) reduction
@@ -207,7 +220,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   unsigned long long* acc = (unsigned long long*)n_moved;
 #define LA(LL, VV)                                                                                        \
   launch_assign<LL, VV>(ctx, grid, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
-                        order, dense, nchunks, rel, S, vec_x, vec_c)
+                        order, dense, nchunks, rel, S, vec_x, vec_c, job_of, kbase)
   if (V == 4) {
     switch (L) {
       case 4: LA(4, 4); break;

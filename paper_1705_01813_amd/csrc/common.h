@@ -167,12 +167,24 @@ knnkm_status ks_sum_f64(knnkm_ctx* ctx, const double* in, int64_t count, double*
 knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
-                       int64_t* n_moved, const int32_t* order, bool dense);
+                       int64_t* n_moved, const int32_t* order, bool dense,
+                       const int32_t* job_of = nullptr, const int32_t* kbase = nullptr);
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
                          int32_t* labels);
+// TwoMeans of several independent jobs at once (job q: rows [off_q, off_q +
+// n_q) in order, k_q leaves, seed seeds_dev[q] or seed1 when seeds_dev is
+// null); labels are global leaf ids (job q's leaves follow job q-1's).
+knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx,
+                               const std::vector<int64_t>& jn, const std::vector<int32_t>& jk,
+                               const uint64_t* seeds_dev, uint64_t seed1, int32_t round_tag, int32_t iters,
+                               int32_t* labels);
+// Random lists; for a batch, job_of[i] / n_off / seeds give row i's job, the
+// job's row range and its seed (ids stay global); null for one job.
 knnkm_status ks_graph_init(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
-                           int32_t kappa, uint64_t seed, int32_t* G_ids, float* G_d2);
+                           int32_t kappa, uint64_t seed, int32_t* G_ids, float* G_d2,
+                           const int32_t* job_of = nullptr, const int64_t* n_off = nullptr,
+                           const uint64_t* seeds = nullptr);
 knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        const int32_t* labels, int32_t k, int32_t precision, int32_t* G_ids,
                        float* G_d2, int32_t kappa);

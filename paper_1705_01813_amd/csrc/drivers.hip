@@ -1,20 +1,50 @@
 // Host drivers: the GK-means^- fit (Alg. 2, Lloyd form) and the KNN graph
-// construction (Alg. 3).  Every step runs in this library's kernels on the
-// context stream; the host only sequences launches.
-#include "common.h"
+// construction (Alg. 3), for one job or a batch of independent jobs.
+//
+// A batch is a ragged concatenation: job q owns rows [n_off[q], n_off[q+1])
+// of X (graph ids stay global) and clusters [k_off[q], k_off[q+1]) of C.
+// Every phase is one launch over all jobs: neighbours and candidate clusters
+// never leave a job, so the per-sample and per-cluster kernels need no job
+// awareness; only the TwoMeans tree shapes, the random lists, the exhaustive
+// case kappa >= k_q and the per-job distortion read the job tables.  One job
+// runs through the same code (a batch of one), so a job gives bit-identical
+// results alone and inside a batch.  Every step runs in this library's
+// kernels on the context stream; the host only sequences launches.
+#include <algorithm>
 
-// k distinct sample ids by Floyd's algorithm (one thread; bitmap membership).
-__global__ void k_random_init_ids(int64_t n, int32_t k, uint64_t seed, uint32_t* __restrict__ bitmap,
+#include "rowgroup.h"
+
+// Job of every row (binary search in n_off).
+__global__ void k_job_of(const int64_t* __restrict__ n_off, int m, int64_t n, int32_t* __restrict__ job) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = m;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (n_off[mid] <= i) lo = mid; else hi = mid;
+    }
+    job[i] = lo;
+  }
+}
+
+// k_q distinct rows of every job by Floyd's algorithm (one thread per job;
+// bitmap membership over the job's rows).  ids are global row ids.
+__global__ void k_random_init_ids(const int64_t* __restrict__ n_off, const int32_t* __restrict__ k_off, int m,
+                                  const uint64_t* __restrict__ seeds, uint32_t* __restrict__ bitmap,
                                   int32_t* __restrict__ ids) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  const uint64_t key = sm_key(seed, sm_stream(RNG_RANDOM_INIT, 0, 0));
-  const int64_t base = n - k;
-  for (int64_t j = base; j < n; ++j) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const int64_t r0 = n_off[q], nq = n_off[q + 1] - r0;
+  const int32_t k0 = k_off[q], kq = k_off[q + 1] - k0;
+  const uint64_t key = sm_key(seeds[q], sm_stream(RNG_RANDOM_INIT, 0, 0));
+  const int64_t base = nq - kq;
+  for (int64_t j = base; j < nq; ++j) {
     const int64_t t = sm_below(sm_draw(key, (uint64_t)(j - base)), (uint32_t)(j + 1));
-    const bool seen = (bitmap[t >> 5] >> (t & 31)) & 1u;
-    const int64_t v = seen ? j : t;
+    const int64_t gt = r0 + t;
+    const bool seen = (bitmap[gt >> 5] >> (gt & 31)) & 1u;
+    const int64_t v = r0 + (seen ? j : t);
     bitmap[v >> 5] |= 1u << (v & 31);
-    ids[j - base] = (int32_t)v;
+    ids[k0 + (j - base)] = (int32_t)v;
   }
 }
 
@@ -27,10 +57,49 @@ __global__ void k_gather_rows(const float* __restrict__ X, int d, int64_t ldx,
   }
 }
 
-// E_t = (sum ||x||^2 - I) / n  (Eqn. 4 through the Eqn. 2 identity)
-__global__ void k_trace(const double* __restrict__ sxx, const double* __restrict__ isum, double inv_n,
-                        double* __restrict__ dst) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = (sxx[0] - isum[0]) * inv_n;
+// ||x_i||^2 in float64, one wavefront per row.
+__global__ __launch_bounds__(256) void k_row_sq64(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
+                                                  double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+    double a = 0.0;
+    for (int t = lane; t < d; t += 64) {
+      const double v = (double)X[i * ldx + t];
+      a = fma(v, v, a);
+    }
+    a = wave_sum(a);
+    if (lane == 0) out[i] = a;
+  }
+}
+
+// out[q] = sum of vals[off[q] .. off[q+1]) in a fixed order (one block per range).
+__global__ __launch_bounds__(256) void k_range_sum(const double* __restrict__ vals, const int64_t* __restrict__ off,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int q = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = off[q] + threadIdx.x; i < off[q + 1]; i += 256) s += vals[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q] = sh[0];
+}
+
+// E_t of every job = (sum ||x||^2 - I) / n_q  (Eqn. 4 through the Eqn. 2 identity)
+__global__ void k_trace_jobs(const double* __restrict__ sxx, const double* __restrict__ isum,
+                             const int64_t* __restrict__ n_off, int m, double* __restrict__ dst) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) dst[q] = (sxx[q] - isum[q]) / (double)(n_off[q + 1] - n_off[q]);
+}
+
+__global__ void k_local_labels(const int32_t* __restrict__ glab, const int32_t* __restrict__ job,
+                               const int32_t* __restrict__ k_off, int64_t n, int32_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = glab[i] - k_off[job[i]];
 }
 
 static knnkm_status check_params(knnkm_ctx* ctx, const knnkm_params* p, const char* who) {
@@ -58,32 +127,132 @@ static knnkm_status check_data(knnkm_ctx* ctx, const float* X, int64_t n, int32_
   return KNNKM_OK;
 }
 
-extern "C" knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
-                                       int32_t k, const int32_t* G_ids, const knnkm_params* p,
-                                       int32_t* labels, float* C, int32_t* counts, double* trace_host,
-                                       int32_t* iters_run_host) {
-  if (!ctx) return KNNKM_EINVAL;
-  if (ctx->sticky) return KNNKM_EDEVICE;
-  KNNKM_TRY(check_data(ctx, X, n, d, ldx, "knn_kmeans_fit"));
-  KNNKM_TRY(check_params(ctx, p, "knn_kmeans_fit"));
-  if (k < 1 || k > n) return knnkm_fail(ctx, KNNKM_EINVAL, "knn_kmeans_fit: need 1 <= k <= n");
+// Host and device copies of the job tables of one call.
+struct Jobs {
+  int m = 1;
+  std::vector<int64_t> n_host, n_off_host;   // n_q, row offsets (m+1)
+  std::vector<uint64_t> seed_host;
+  int64_t n = 0;
+  // device
+  const int64_t* n_off = nullptr;
+  const uint64_t* seeds = nullptr;
+  const int32_t* job_of = nullptr;  // null for one job
+};
+
+static knnkm_status upload_jobs(knnkm_ctx* ctx, Jobs& J, const char* tag) {
+  char name[40];
+  snprintf(name, sizeof(name), "%s_noff", tag);
+  KNNKM_WS(ctx, noff, int64_t, name, J.m + 1);
+  snprintf(name, sizeof(name), "%s_seeds", tag);
+  KNNKM_WS(ctx, seeds, uint64_t, name, J.m);
+  KNNKM_HIP(ctx, hipMemcpyAsync(noff, J.n_off_host.data(), sizeof(int64_t) * (J.m + 1), hipMemcpyHostToDevice,
+                                ctx->stream));
+  KNNKM_HIP(ctx, hipMemcpyAsync(seeds, J.seed_host.data(), sizeof(uint64_t) * J.m, hipMemcpyHostToDevice,
+                                ctx->stream));
+  J.n_off = noff;
+  J.seeds = seeds;
+  J.job_of = nullptr;
+  if (J.m > 1) {
+    snprintf(name, sizeof(name), "%s_jobof", tag);
+    KNNKM_WS(ctx, job, int32_t, name, J.n);
+    k_job_of<<<grid_for(J.n, 256, 8192), 256, 0, ctx->stream>>>(noff, J.m, J.n, job);
+    KNNKM_TRY(knnkm_check(ctx, "job table"));
+    J.job_of = job;
+  }
+  // the host copies must stay valid until the copies ran
+  KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return KNNKM_OK;
+}
+
+// Cluster offsets (int32 and int64 on the device) for per-job cluster counts.
+static knnkm_status upload_koff(knnkm_ctx* ctx, const std::vector<int32_t>& kq, const char* tag,
+                                int32_t** k32, int64_t** k64, int32_t* total) {
+  std::vector<int32_t> a(kq.size() + 1, 0);
+  std::vector<int64_t> b(kq.size() + 1, 0);
+  for (size_t q = 0; q < kq.size(); ++q) {
+    a[q + 1] = a[q] + kq[q];
+    b[q + 1] = b[q] + kq[q];
+  }
+  char name[40];
+  snprintf(name, sizeof(name), "%s_k32", tag);
+  KNNKM_WS(ctx, d32, int32_t, name, a.size());
+  snprintf(name, sizeof(name), "%s_k64", tag);
+  KNNKM_WS(ctx, d64, int64_t, name, b.size());
+  KNNKM_HIP(ctx, hipMemcpyAsync(d32, a.data(), sizeof(int32_t) * a.size(), hipMemcpyHostToDevice, ctx->stream));
+  KNNKM_HIP(ctx, hipMemcpyAsync(d64, b.data(), sizeof(int64_t) * b.size(), hipMemcpyHostToDevice, ctx->stream));
+  KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *k32 = d32;
+  *k64 = d64;
+  *total = a.back();
+  return KNNKM_OK;
+}
+
+// Alg. 3 for every job of J.
+static knnkm_status build_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, Jobs& J,
+                               const knnkm_params* p, int32_t* G_ids, float* G_d2) {
   const int kappa = p->kappa;
-  const bool dense = kappa >= k;
-  if (kappa < 1 || (!dense && kappa > n - 1))
-    return knnkm_fail(ctx, KNNKM_EINVAL, "knn_kmeans_fit: need 1 <= kappa <= n-1");
-  if (!dense && kappa > KNNKM_MAX_KAPPA)
-    return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "knn_kmeans_fit: kappa=%d > %d", kappa, KNNKM_MAX_KAPPA);
-  if (!labels || !C || !counts || (!dense && !G_ids))
-    return knnkm_fail(ctx, KNNKM_EINVAL, "knn_kmeans_fit: null pointer");
-  if (ctx->dry) return KNNKM_OK;
-  KNNKM_HIP(ctx, hipSetDevice(ctx->device));
+  const int64_t n = J.n;
+  auto mark = [&](int e) {
+    if (ctx->timing) {
+      hipEvent_t h = knnkm_event(ctx, e);
+      if (h) (void)hipEventRecord(h, ctx->stream);
+    }
+  };
+  if (ctx->timing) ctx->build_ev = 0;
+  mark(0);
+  KNNKM_TRY(ks_graph_init(ctx, X, n, d, ldx, kappa, J.seed_host[0], G_ids, G_d2, J.job_of, J.n_off, J.seeds));
+  if (p->tau > 0) {
+    // k0 = max(1, floor(n_q / xi)) clusters per job (Sec. 4.3)
+    std::vector<int32_t> k0(J.m);
+    bool all_dense = true;
+    for (int q = 0; q < J.m; ++q) {
+      k0[q] = (int32_t)std::max<int64_t>(1, J.n_host[q] / p->xi);
+      all_dense = all_dense && kappa >= k0[q];
+    }
+    int32_t *k0_32, K0;
+    int64_t* k0_64;
+    KNNKM_TRY(upload_koff(ctx, k0, "kb", &k0_32, &k0_64, &K0));
+    KNNKM_WS(ctx, lab, int32_t, "kb_labels", n);
+    KNNKM_WS(ctx, lab2, int32_t, "kb_labels2", n);
+    KNNKM_WS(ctx, counts, int32_t, "kb_counts", K0);
+    KNNKM_WS(ctx, off, int32_t, "kb_offsets", (int64_t)K0 + 1);
+    KNNKM_WS(ctx, mem, int32_t, "kb_members", n);
+    KNNKM_WS(ctx, C, float, "kb_centroids", (int64_t)K0 * d);
+    for (int t = 0; t < p->tau; ++t) {
+      KNNKM_TRY(ks_twomeans_multi(ctx, X, d, ldx, J.n_host, k0, J.m > 1 ? J.seeds : nullptr, J.seed_host[0], t,
+                                  p->bisect_iters, lab));
+      KNNKM_TRY(ks_label_sort(ctx, lab, n, K0, counts, off, mem));
+      KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K0, counts, off, mem, C, nullptr, nullptr));
+      KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, K0, G_ids, kappa, lab, lab2, nullptr, nullptr, mem,
+                          J.m == 1 && all_dense, J.job_of, k0_32));
+      KNNKM_TRY(ks_refine(ctx, X, n, d, ldx, lab2, K0, p->precision, G_ids, G_d2, kappa));
+    }
+  }
+  mark(1);
+  return KNNKM_OK;
+}
+
+// Alg. 2 (Lloyd form) for every job of J.  labels are global cluster ids;
+// trace_dev receives E_t of job q at [t * m + q]; *iters_run the sweeps done.
+static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, Jobs& J,
+                             const std::vector<int32_t>& kq, const int32_t* G_ids, const knnkm_params* p,
+                             int32_t* labels, float* C, int32_t* counts, double* trace_dev, int* iters_run) {
+  const int kappa = p->kappa;
   const int T = p->max_iters;
+  const int64_t n = J.n;
+  const int m = J.m;
+  int32_t *k32, K;
+  int64_t* k64;
+  KNNKM_TRY(upload_koff(ctx, kq, "fit", &k32, &k64, &K));
+  bool all_dense = true;
+  for (int q = 0; q < m; ++q) all_dense = all_dense && kappa >= kq[q];
   KNNKM_WS(ctx, lab2, int32_t, "fit_labels2", n);
-  KNNKM_WS(ctx, off, int32_t, "fit_offsets", (int64_t)k + 1);
+  KNNKM_WS(ctx, off, int32_t, "fit_offsets", (int64_t)K + 1);
   KNNKM_WS(ctx, mem, int32_t, "fit_members", n);
-  KNNKM_WS(ctx, Iterm, double, "fit_iterm", k);
-  KNNKM_WS(ctx, scal, double, "fit_scalars", 2);
-  KNNKM_WS(ctx, trace, double, "fit_trace", (int64_t)T + 1);
+  KNNKM_WS(ctx, Iterm, double, "fit_iterm", K);
+  KNNKM_WS(ctx, rowsq, double, "fit_rowsq", n);
+  KNNKM_WS(ctx, sxx, double, "fit_sxx", m);
+  KNNKM_WS(ctx, isum, double, "fit_isum", m);
   KNNKM_WS(ctx, moved, int64_t, "fit_moved", (int64_t)T + 1);
   // phase events: 2 fit start, 3 initialisation done, 4 iterations done,
   // 6+2j / 7+2j around the assignment of iteration j+1
@@ -103,22 +272,26 @@ extern "C" knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n
   // initial partition
   if (p->init == KNNKM_INIT_RANDOM) {
     KNNKM_WS(ctx, bitmap, uint32_t, "fit_bitmap", (n + 31) / 32);
-    KNNKM_WS(ctx, ids, int32_t, "fit_init_ids", k);
+    KNNKM_WS(ctx, ids, int32_t, "fit_init_ids", K);
     KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)bitmap, (n + 31) / 32, 0));
-    k_random_init_ids<<<1, 64, 0, ctx->stream>>>(n, k, p->seed, bitmap, ids);
-    k_gather_rows<<<grid_for((int64_t)k * d, 256, 4096), 256, 0, ctx->stream>>>(X, d, ldx, ids, k, C);
+    k_random_init_ids<<<(m + 63) / 64, 64, 0, ctx->stream>>>(J.n_off, k32, m, J.seeds, bitmap, ids);
+    k_gather_rows<<<grid_for((int64_t)K * d, 256, 4096), 256, 0, ctx->stream>>>(X, d, ldx, ids, K, C);
     KNNKM_TRY(knnkm_check(ctx, "random init"));
-    KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, k, nullptr, k, nullptr, labels, nullptr, nullptr, nullptr,
-                        true));
+    // exhaustive assignment to the seeds of the sample's own job
+    KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, K, nullptr, K, nullptr, labels, nullptr, nullptr, nullptr, true,
+                        J.job_of, k32));
   } else {
-    KNNKM_TRY(ks_twomeans(ctx, X, n, d, ldx, k, p->seed, KNNKM_ROUND_FIT, p->bisect_iters, labels));
-    KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)C, (int64_t)k * d, 0));
+    KNNKM_TRY(ks_twomeans_multi(ctx, X, d, ldx, J.n_host, kq, m > 1 ? J.seeds : nullptr, J.seed_host[0],
+                                KNNKM_ROUND_FIT, p->bisect_iters, labels));
+    KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)C, (int64_t)K * d, 0));
   }
-  KNNKM_TRY(ks_sqdist_sum(ctx, X, n, d, ldx, nullptr, nullptr, scal, 1.0));
-  KNNKM_TRY(ks_label_sort(ctx, labels, n, k, counts, off, mem));
-  KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, k, counts, off, mem, C, nullptr, Iterm));
-  KNNKM_TRY(ks_sum_f64(ctx, Iterm, k, scal + 1));
-  k_trace<<<1, 64, 0, ctx->stream>>>(scal, scal + 1, 1.0 / (double)n, trace);
+  k_row_sq64<<<grid_for(n, 4, 16384), 256, 0, ctx->stream>>>(X, n, d, ldx, rowsq);
+  k_range_sum<<<m, 256, 0, ctx->stream>>>(rowsq, J.n_off, sxx);
+  KNNKM_TRY(ks_label_sort(ctx, labels, n, K, counts, off, mem));
+  KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K, counts, off, mem, C, nullptr, Iterm));
+  k_range_sum<<<m, 256, 0, ctx->stream>>>(Iterm, k64, isum);
+  k_trace_jobs<<<(m + 255) / 256, 256, 0, ctx->stream>>>(sxx, isum, J.n_off, m, trace_dev);
+  KNNKM_TRY(knnkm_check(ctx, "fit initialisation"));
   mark(3);
 
   int32_t* cur = labels;
@@ -126,17 +299,18 @@ extern "C" knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n
   int it = 0;
   for (int t = 1; t <= T; ++t) {
     mark(6 + 2 * (t - 1));
-    KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, k, G_ids, kappa, cur, nxt, nullptr, moved + t, mem, dense));
+    KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, K, G_ids, kappa, cur, nxt, nullptr, moved + t, mem,
+                        m == 1 && all_dense, J.job_of, k32));
     mark(7 + 2 * (t - 1));
     if (ctx->timing) ctx->assign_n = t;
-    KNNKM_TRY(ks_label_sort(ctx, nxt, n, k, counts, off, mem));
-    KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, k, counts, off, mem, C, nullptr, Iterm));
-    KNNKM_TRY(ks_sum_f64(ctx, Iterm, k, scal + 1));
-    k_trace<<<1, 64, 0, ctx->stream>>>(scal, scal + 1, 1.0 / (double)n, trace + t);
+    KNNKM_TRY(ks_label_sort(ctx, nxt, n, K, counts, off, mem));
+    KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K, counts, off, mem, C, nullptr, Iterm));
+    k_range_sum<<<m, 256, 0, ctx->stream>>>(Iterm, k64, isum);
+    k_trace_jobs<<<(m + 255) / 256, 256, 0, ctx->stream>>>(sxx, isum, J.n_off, m, trace_dev + (int64_t)t * m);
     KNNKM_TRY(knnkm_check(ctx, "fit iteration"));
     std::swap(cur, nxt);
     it = t;
-    if (p->early_stop) {
+    if (p->early_stop && m == 1) {
       int64_t mv = -1;
       KNNKM_HIP(ctx, hipMemcpyAsync(&mv, moved + t, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
       KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -147,9 +321,42 @@ extern "C" knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n
   if (cur != labels)
     KNNKM_HIP(ctx, hipMemcpyAsync(labels, cur, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice,
                                   ctx->stream));
+  *iters_run = it;
+  return KNNKM_OK;
+}
+
+extern "C" knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                                       int32_t k, const int32_t* G_ids, const knnkm_params* p,
+                                       int32_t* labels, float* C, int32_t* counts, double* trace_host,
+                                       int32_t* iters_run_host) {
+  if (!ctx) return KNNKM_EINVAL;
+  if (ctx->sticky) return KNNKM_EDEVICE;
+  KNNKM_TRY(check_data(ctx, X, n, d, ldx, "knn_kmeans_fit"));
+  KNNKM_TRY(check_params(ctx, p, "knn_kmeans_fit"));
+  if (k < 1 || k > n) return knnkm_fail(ctx, KNNKM_EINVAL, "knn_kmeans_fit: need 1 <= k <= n");
+  const int kappa = p->kappa;
+  const bool dense = kappa >= k;
+  if (kappa < 1 || (!dense && kappa > n - 1))
+    return knnkm_fail(ctx, KNNKM_EINVAL, "knn_kmeans_fit: need 1 <= kappa <= n-1");
+  if (!dense && kappa > KNNKM_MAX_KAPPA)
+    return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "knn_kmeans_fit: kappa=%d > %d", kappa, KNNKM_MAX_KAPPA);
+  if (!labels || !C || !counts || (!dense && !G_ids))
+    return knnkm_fail(ctx, KNNKM_EINVAL, "knn_kmeans_fit: null pointer");
+  if (ctx->dry) return KNNKM_OK;
+  KNNKM_HIP(ctx, hipSetDevice(ctx->device));
+  Jobs J;
+  J.m = 1;
+  J.n = n;
+  J.n_host = {n};
+  J.n_off_host = {0, n};
+  J.seed_host = {p->seed};
+  KNNKM_TRY(upload_jobs(ctx, J, "one"));
+  KNNKM_WS(ctx, trace, double, "fit_trace", (int64_t)p->max_iters + 1);
+  int it = 0;
+  KNNKM_TRY(fit_impl(ctx, X, d, ldx, J, std::vector<int32_t>{k}, G_ids, p, labels, C, counts, trace, &it));
   if (trace_host)
-    KNNKM_HIP(ctx, hipMemcpyAsync(trace_host, trace, sizeof(double) * (size_t)(it + 1),
-                                  hipMemcpyDeviceToHost, ctx->stream));
+    KNNKM_HIP(ctx, hipMemcpyAsync(trace_host, trace, sizeof(double) * (size_t)(it + 1), hipMemcpyDeviceToHost,
+                                  ctx->stream));
   KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   if (iters_run_host) *iters_run_host = it;
   return knnkm_check(ctx, "knn_kmeans_fit");
@@ -168,35 +375,78 @@ extern "C" knnkm_status knn_build(knnkm_ctx* ctx, const float* X, int64_t n, int
   if (!G_ids || !G_d2) return knnkm_fail(ctx, KNNKM_EINVAL, "knn_build: null pointer");
   if (ctx->dry) return KNNKM_OK;
   KNNKM_HIP(ctx, hipSetDevice(ctx->device));
-  const int32_t k0 = (int32_t)std::max<int64_t>(1, n / p->xi);
-  // phase events 0 (start) and 1 (end)
-  auto mark = [&](int e) {
-    if (ctx->timing) {
-      hipEvent_t h = knnkm_event(ctx, e);
-      if (h) (void)hipEventRecord(h, ctx->stream);
-    }
-  };
-  if (ctx->timing) ctx->build_ev = 0;
-  mark(0);
-  KNNKM_TRY(ks_graph_init(ctx, X, n, d, ldx, kappa, p->seed, G_ids, G_d2));
-  if (p->tau == 0) {
-    mark(1);
-    return KNNKM_OK;
+  Jobs J;
+  J.m = 1;
+  J.n = n;
+  J.n_host = {n};
+  J.n_off_host = {0, n};
+  J.seed_host = {p->seed};
+  KNNKM_TRY(upload_jobs(ctx, J, "one"));
+  return build_impl(ctx, X, d, ldx, J, p, G_ids, G_d2);
+}
+
+extern "C" knnkm_status knnkm_fit_batched(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, int32_t m,
+                                          const int64_t* n_off_host, const int32_t* k_host,
+                                          const uint64_t* seeds_host, const knnkm_params* p, int32_t* G_ids,
+                                          float* G_d2, int32_t* labels, float* C, int32_t* counts,
+                                          double* trace_host) {
+  if (!ctx) return KNNKM_EINVAL;
+  if (ctx->sticky) return KNNKM_EDEVICE;
+  if (m < 1 || !n_off_host || !k_host || !seeds_host)
+    return knnkm_fail(ctx, KNNKM_EINVAL, "knnkm_fit_batched: need m >= 1 and job tables");
+  KNNKM_TRY(check_params(ctx, p, "knnkm_fit_batched"));
+  const int kappa = p->kappa;
+  if (kappa < 1 || kappa > KNNKM_MAX_KAPPA)
+    return knnkm_fail(ctx, kappa < 1 ? KNNKM_EINVAL : KNNKM_EUNSUPPORTED, "knnkm_fit_batched: kappa=%d", kappa);
+  if (n_off_host[0] != 0) return knnkm_fail(ctx, KNNKM_EINVAL, "knnkm_fit_batched: n_off[0] must be 0");
+  Jobs J;
+  J.m = m;
+  std::vector<int32_t> kq(m);
+  int64_t ktot = 0;
+  for (int q = 0; q < m; ++q) {
+    const int64_t nq = n_off_host[q + 1] - n_off_host[q];
+    if (nq < 2 || kappa > nq - 1)
+      return knnkm_fail(ctx, KNNKM_EINVAL, "knnkm_fit_batched: job %d has %lld rows (need >= kappa+1)", q,
+                        (long long)nq);
+    if (k_host[q] < 1 || k_host[q] > nq)
+      return knnkm_fail(ctx, KNNKM_EINVAL, "knnkm_fit_batched: job %d needs 1 <= k <= n", q);
+    J.n_host.push_back(nq);
+    kq[q] = k_host[q];
+    ktot += k_host[q];
   }
-  KNNKM_WS(ctx, lab, int32_t, "kb_labels", n);
-  KNNKM_WS(ctx, lab2, int32_t, "kb_labels2", n);
-  KNNKM_WS(ctx, counts, int32_t, "kb_counts", k0);
-  KNNKM_WS(ctx, off, int32_t, "kb_offsets", (int64_t)k0 + 1);
-  KNNKM_WS(ctx, mem, int32_t, "kb_members", n);
-  KNNKM_WS(ctx, C, float, "kb_centroids", (int64_t)k0 * d);
-  const bool dense = kappa >= k0;
-  for (int t = 0; t < p->tau; ++t) {
-    KNNKM_TRY(ks_twomeans(ctx, X, n, d, ldx, k0, p->seed, t, p->bisect_iters, lab));
-    KNNKM_TRY(ks_label_sort(ctx, lab, n, k0, counts, off, mem));
-    KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, k0, counts, off, mem, C, nullptr, nullptr));
-    KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, k0, G_ids, kappa, lab, lab2, nullptr, nullptr, mem, dense));
-    KNNKM_TRY(ks_refine(ctx, X, n, d, ldx, lab2, k0, p->precision, G_ids, G_d2, kappa));
+  J.n = n_off_host[m];
+  J.n_off_host.assign(n_off_host, n_off_host + m + 1);
+  J.seed_host.assign(seeds_host, seeds_host + m);
+  KNNKM_TRY(check_data(ctx, X, J.n, d, ldx, "knnkm_fit_batched"));
+  if (ktot > INT32_MAX) return knnkm_fail(ctx, KNNKM_EINVAL, "knnkm_fit_batched: too many clusters");
+  if (!G_ids || !G_d2 || !labels || !C || !counts)
+    return knnkm_fail(ctx, KNNKM_EINVAL, "knnkm_fit_batched: null pointer");
+  if (ctx->dry) return KNNKM_OK;
+  KNNKM_HIP(ctx, hipSetDevice(ctx->device));
+  KNNKM_TRY(upload_jobs(ctx, J, "batch"));
+  KNNKM_TRY(build_impl(ctx, X, d, ldx, J, p, G_ids, G_d2));
+  KNNKM_WS(ctx, trace, double, "batch_trace", ((int64_t)p->max_iters + 1) * m);
+  KNNKM_WS(ctx, glab, int32_t, "batch_labels", J.n);
+  int it = 0;
+  KNNKM_TRY(fit_impl(ctx, X, d, ldx, J, kq, G_ids, p, glab, C, counts, trace, &it));
+  // job-local labels
+  {
+    int32_t *k32, K;
+    int64_t* k64;
+    KNNKM_TRY(upload_koff(ctx, kq, "fit", &k32, &k64, &K));
+    if (J.job_of)
+      k_local_labels<<<grid_for(J.n, 256, 8192), 256, 0, ctx->stream>>>(glab, J.job_of, k32, J.n, labels);
+    else
+      KNNKM_HIP(ctx, hipMemcpyAsync(labels, glab, sizeof(int32_t) * J.n, hipMemcpyDeviceToDevice, ctx->stream));
   }
-  mark(1);
-  return KNNKM_OK;
+  if (trace_host) {
+    std::vector<double> tr((size_t)(it + 1) * m);
+    KNNKM_HIP(ctx, hipMemcpyAsync(tr.data(), trace, sizeof(double) * tr.size(), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+    KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < m; ++q)
+      for (int t = 0; t <= it; ++t) trace_host[(int64_t)q * (p->max_iters + 1) + t] = tr[(size_t)t * m + q];
+  }
+  KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return knnkm_check(ctx, "knnkm_fit_batched");
 }

@@ -32,16 +32,29 @@ template <int T>
 __global__ __launch_bounds__(256) void k_graph_init(const float* __restrict__ X, int n, int d,
                                                     int64_t ldx, int kappa, uint64_t seed,
                                                     int32_t* __restrict__ G_ids,
-                                                    float* __restrict__ G_d2) {
+                                                    float* __restrict__ G_d2,
+                                                    const int32_t* __restrict__ job_of,
+                                                    const int64_t* __restrict__ n_off,
+                                                    const uint64_t* __restrict__ seeds) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
-  const uint64_t key = sm_key(seed, sm_stream(RNG_GRAPH_INIT, 0, (uint64_t)i));
-  const uint32_t m = (uint32_t)(n - 1);
-  const uint32_t base = m - (uint32_t)kappa;
+  const int64_t gi_row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (gi_row >= n) return;
+  // job-local view: rows [row0, row0 + nj) with the job's own seed
+  int64_t row0 = 0, nj = n;
+  uint64_t jseed = seed;
+  if (job_of) {
+    const int q = job_of[gi_row];
+    row0 = n_off[q];
+    nj = n_off[q + 1] - row0;
+    jseed = seeds[q];
+  }
+  const int64_t i = gi_row - row0;
+  const uint64_t key = sm_key(jseed, sm_stream(RNG_GRAPH_INIT, 0, (uint64_t)i));
+  const uint32_t m = (uint32_t)(nj - 1);
+  const uint32_t fbase = m - (uint32_t)kappa;
   int v0 = -1, v1 = -1;  // chosen value for slot lane, lane+64
   for (int c = 0; c < kappa; ++c) {
-    const uint32_t j = base + (uint32_t)c;
+    const uint32_t j = fbase + (uint32_t)c;
     const int t = (int)sm_below(sm_draw(key, (uint64_t)c), j + 1);
     const bool seen = (__ballot(v0 == t) | __ballot(v1 == t)) != 0ull;
     const int v = seen ? (int)j : t;
@@ -51,12 +64,12 @@ __global__ __launch_bounds__(256) void k_graph_init(const float* __restrict__ X,
       v1 = v;
     }
   }
-  // shift past the row's own id
-  int id0 = v0 >= 0 ? v0 + (v0 >= i ? 1 : 0) : -1;
-  int id1 = v1 >= 0 ? v1 + (v1 >= i ? 1 : 0) : -1;
+  // shift past the row's own id, then to global ids
+  int id0 = v0 >= 0 ? (int)(v0 + (v0 >= i ? 1 : 0) + row0) : -1;
+  int id1 = v1 >= 0 ? (int)(v1 + (v1 >= i ? 1 : 0) + row0) : -1;
   // distances: one float64 reduction per entry
   float x[T];
-  const float* xr = X + i * ldx;
+  const float* xr = X + gi_row * ldx;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     int dim = lane + 64 * t;
@@ -97,8 +110,8 @@ __global__ __launch_bounds__(256) void k_graph_init(const float* __restrict__ X,
     r0 += (kc < k0 || (kc == k0 && ic < id0)) ? 1 : 0;
     r1 += (kc < k1 || (kc == k1 && ic < id1)) ? 1 : 0;
   }
-  int32_t* gi = G_ids + i * kappa;
-  float* gd = G_d2 + i * kappa;
+  int32_t* gi = G_ids + gi_row * kappa;
+  float* gd = G_d2 + gi_row * kappa;
   if (lane < kappa) {
     gi[r0] = id0;
     gd[r0] = k0;
@@ -110,10 +123,13 @@ __global__ __launch_bounds__(256) void k_graph_init(const float* __restrict__ X,
 }
 
 knnkm_status ks_graph_init(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
-                           int32_t kappa, uint64_t seed, int32_t* G_ids, float* G_d2) {
+                           int32_t kappa, uint64_t seed, int32_t* G_ids, float* G_d2,
+                           const int32_t* job_of, const int64_t* n_off, const uint64_t* seeds) {
   const int T = (d + 63) / 64;
   const unsigned grid = (unsigned)((n + 3) / 4);
-#define GI(TT) k_graph_init<TT><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, kappa, seed, G_ids, G_d2)
+#define GI(TT)                                                                                    \
+  k_graph_init<TT><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, kappa, seed, G_ids, G_d2, job_of, \
+                                                  n_off, seeds)
   switch (T) {
     case 1: GI(1); break;
     case 2: GI(2); break;

@@ -49,6 +49,8 @@ struct TMPlan {
   // host arrays (uploaded into one device buffer)
   std::vector<int32_t> split_off, split_size, split_tile_begin, split_tile_end;  // per split node
   std::vector<int64_t> split_heap;
+  std::vector<int32_t> split_job;                          // job of each split node
+  std::vector<int64_t> key;                                // (n_j, k_j) of every job
   std::vector<int32_t> tile_split, tile_start, tile_len;  // per tile: local split index, range
   std::vector<int32_t> big_split;                         // local split index of big nodes
   std::vector<int32_t> bigtile;                           // tile index (global) of big-node tiles
@@ -66,7 +68,7 @@ struct TMPlan {
   const int32_t *d_split_off, *d_split_size, *d_split_tile_begin, *d_split_tile_end, *d_tile_split,
       *d_tile_start, *d_tile_len, *d_big_split, *d_bigtile, *d_bigtile_big, *d_small_split,
       *d_copy_off, *d_copy_size, *d_leaf_off, *d_big_btb, *d_big_bte, *d_split_cb, *d_split_ce,
-      *d_chunk_tb, *d_chunk_te;
+      *d_chunk_tb, *d_chunk_te, *d_split_job;
   const int64_t* d_split_heap;
 };
 
@@ -76,22 +78,36 @@ void tm_plan_free(TMPlan* p) {
   delete p;
 }
 
-static void build_plan(TMPlan& P, int64_t n, int32_t k) {
+// Tree shapes of several independent jobs (job j: rows [off_j, off_j + n_j),
+// k_j leaves), merged depth by depth so one launch per step covers every job
+// that still splits; a job whose tree is complete is carried over as a copy.
+static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vector<int32_t>& jk) {
   P = TMPlan();
-  P.n = n;
-  P.k = k;
-  std::vector<int64_t> off{0}, size{n};
-  int depth = 0;
-  while ((int64_t)off.size() < k) {
-    const int m = (int)off.size();
-    std::vector<char> split(m, 1);
-    if (2 * (int64_t)m > k) {
-      std::vector<int> ord(m);
-      std::iota(ord.begin(), ord.end(), 0);
-      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return size[a] > size[b]; });
-      std::fill(split.begin(), split.end(), 0);
-      for (int j = 0; j < k - m; ++j) split[ord[j]] = 1;
+  const int nj = (int)jn.size();
+  P.key.clear();
+  int64_t total = 0;
+  for (int q = 0; q < nj; ++q) {
+    P.key.push_back(jn[q]);
+    P.key.push_back(jk[q]);
+    total += jn[q];
+  }
+  P.n = total;
+  std::vector<std::vector<int64_t>> joff(nj), jsize(nj);
+  {
+    int64_t at = 0;
+    for (int q = 0; q < nj; ++q) {
+      joff[q] = {at};
+      jsize[q] = {jn[q]};
+      at += jn[q];
     }
+  }
+  auto unfinished = [&]() {
+    for (int q = 0; q < nj; ++q)
+      if ((int64_t)joff[q].size() < jk[q]) return true;
+    return false;
+  };
+  int depth = 0;
+  while (unfinished()) {
     TMLevel L{};
     L.depth = depth;
     L.split_base = (int)P.split_off.size();
@@ -102,6 +118,26 @@ static void build_plan(TMPlan& P, int64_t n, int32_t k) {
     L.copy_base = (int)P.copy_off.size();
     L.chunk_base = (int)P.chunk_tb.size();
     L.max_node_tiles = 0;
+    for (int q = 0; q < nj; ++q) {
+    std::vector<int64_t>& off = joff[q];
+    std::vector<int64_t>& size = jsize[q];
+    const int m = (int)off.size();
+    const int32_t k = jk[q];
+    if ((int64_t)m >= k) {  // this job's tree is complete: carry its rows over
+      P.copy_off.push_back((int32_t)off[0]);
+      int64_t sz = 0;
+      for (int64_t v : size) sz += v;
+      P.copy_size.push_back((int32_t)sz);
+      continue;
+    }
+    std::vector<char> split(m, 1);
+    if (2 * (int64_t)m > k) {
+      std::vector<int> ord(m);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return size[a] > size[b]; });
+      std::fill(split.begin(), split.end(), 0);
+      for (int j = 0; j < k - m; ++j) split[ord[j]] = 1;
+    }
     std::vector<int64_t> noff, nsize;
     for (int i = 0; i < m; ++i) {
       if (split[i]) {
@@ -109,6 +145,7 @@ static void build_plan(TMPlan& P, int64_t n, int32_t k) {
         P.split_off.push_back((int32_t)off[i]);
         P.split_size.push_back((int32_t)size[i]);
         P.split_heap.push_back(((int64_t)1 << depth) + i);
+        P.split_job.push_back(q);
         P.split_tile_begin.push_back((int32_t)P.tile_split.size() - L.tile_base);
         const bool big = size[i] > TM_SMALL;
         const int bigl = (int)P.big_split.size() - L.big_base;
@@ -152,6 +189,9 @@ static void build_plan(TMPlan& P, int64_t n, int32_t k) {
         nsize.push_back(size[i]);
       }
     }
+    off.swap(noff);
+    size.swap(nsize);
+    }
     L.nsplit = (int)P.split_off.size() - L.split_base;
     L.ntiles = (int)P.tile_split.size() - L.tile_base;
     L.nbig = (int)P.big_split.size() - L.big_base;
@@ -164,13 +204,14 @@ static void build_plan(TMPlan& P, int64_t n, int32_t k) {
     P.max_tiles = std::max(P.max_tiles, L.ntiles);
     P.max_big = std::max(P.max_big, L.nbig);
     P.levels.push_back(L);
-    off.swap(noff);
-    size.swap(nsize);
     ++depth;
   }
-  P.leaf_off.resize(off.size() + 1);
-  for (size_t i = 0; i < off.size(); ++i) P.leaf_off[i] = (int32_t)off[i];
-  P.leaf_off[off.size()] = (int32_t)n;
+  // leaves of all jobs, left to right, job after job
+  P.leaf_off.clear();
+  for (int q = 0; q < nj; ++q)
+    for (int64_t v : joff[q]) P.leaf_off.push_back((int32_t)v);
+  P.k = (int32_t)P.leaf_off.size();
+  P.leaf_off.push_back((int32_t)total);
 }
 
 static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P) {
@@ -186,7 +227,8 @@ static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P) {
       {P.split_heap.data(), P.split_heap.size() * 8},
       {P.big_btb.data(), P.big_btb.size() * 4},       {P.big_bte.data(), P.big_bte.size() * 4},
       {P.split_cb.data(), P.split_cb.size() * 4},     {P.split_ce.data(), P.split_ce.size() * 4},
-      {P.chunk_tb.data(), P.chunk_tb.size() * 4},     {P.chunk_te.data(), P.chunk_te.size() * 4}};
+      {P.chunk_tb.data(), P.chunk_tb.size() * 4},     {P.chunk_te.data(), P.chunk_te.size() * 4},
+      {P.split_job.data(), P.split_job.size() * 4}};
   size_t total = 0;
   std::vector<size_t> at;
   for (auto& p : parts) {
@@ -223,6 +265,7 @@ static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P) {
   P.d_split_ce = (const int32_t*)(b + at[18]);
   P.d_chunk_tb = (const int32_t*)(b + at[19]);
   P.d_chunk_te = (const int32_t*)(b + at[20]);
+  P.d_split_job = (const int32_t*)(b + at[21]);
   return KNNKM_OK;
 }
 
@@ -238,12 +281,15 @@ __global__ __launch_bounds__(256) void k_tm_seed(const float* __restrict__ X, in
                                                  const int32_t* __restrict__ perm, int nsplit,
                                                  const int32_t* __restrict__ s_off,
                                                  const int32_t* __restrict__ s_size,
-                                                 const int64_t* __restrict__ s_heap, uint64_t seed,
+                                                 const int64_t* __restrict__ s_heap,
+                                                 const int32_t* __restrict__ s_job,
+                                                 const uint64_t* __restrict__ seeds, uint64_t seed1,
                                                  int round_tag, float* __restrict__ cent) {
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= nsplit) return;
   const uint32_t s = (uint32_t)s_size[j];
+  const uint64_t seed = seeds ? seeds[s_job[j]] : seed1;
   const uint64_t key = sm_key(seed, sm_stream(RNG_TWOMEANS, (uint64_t)round_tag, (uint64_t)s_heap[j]));
   const uint32_t r0 = sm_below(sm_draw(key, 0), s);
   uint32_t r1 = sm_below(sm_draw(key, 1), s - 1);
@@ -744,18 +790,26 @@ static void launch_delta(knnkm_ctx* ctx, const TMPlan& P, const TMLevel& Lv, con
     }                                            \
   } while (0)
 
-knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
-                         int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
-                         int32_t* labels) {
-  if (k == 1) return ks_fill_i32(ctx, labels, n, 0);
-  if (!ctx->tm_plan || ctx->tm_plan->n != n || ctx->tm_plan->k != k) {
+knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx,
+                               const std::vector<int64_t>& jn, const std::vector<int32_t>& jk,
+                               const uint64_t* seeds_dev, uint64_t seed1, int32_t round_tag, int32_t iters,
+                               int32_t* labels) {
+  std::vector<int64_t> key;
+  int64_t n = 0;
+  for (size_t q = 0; q < jn.size(); ++q) {
+    key.push_back(jn[q]);
+    key.push_back(jk[q]);
+    n += jn[q];
+  }
+  if (!ctx->tm_plan || ctx->tm_plan->key != key) {
     KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     tm_plan_free(ctx->tm_plan);
     ctx->tm_plan = new TMPlan();
-    build_plan(*ctx->tm_plan, n, k);
+    build_plan(*ctx->tm_plan, jn, jk);
     KNNKM_TRY(upload_plan(ctx, *ctx->tm_plan));
   }
   const TMPlan& P = *ctx->tm_plan;
+  const int32_t k = P.k;
   if (d > KNNKM_MAX_D) return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "twomeans: d=%d > %d", d, KNNKM_MAX_D);
   int gL, gV;
   pick_group(d, 1, &gL, &gV);
@@ -778,8 +832,10 @@ knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, i
     const int32_t* s_off = P.d_split_off + L.split_base;
     const int32_t* s_size = P.d_split_size + L.split_base;
     const unsigned gw = (unsigned)((L.nsplit + 3) / 4);
-    k_tm_seed<<<gw, 256, 0, ctx->stream>>>(X, d, ldx, perm, L.nsplit, s_off, s_size,
-                                           P.d_split_heap + L.split_base, seed, round_tag, cent);
+    if (L.nsplit)
+      k_tm_seed<<<gw, 256, 0, ctx->stream>>>(X, d, ldx, perm, L.nsplit, s_off, s_size,
+                                             P.d_split_heap + L.split_base, P.d_split_job + L.split_base,
+                                             seeds_dev, seed1, round_tag, cent);
     for (int it = 0; it < iters; ++it) {
       TM_DISPATCH(launch_accum, ctx, P, L, X, d, ldx, perm, cent, partial, pcnt, vec);
       if (L.max_node_tiles > TM_CHUNK) {
@@ -826,6 +882,13 @@ knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, i
   }
   k_tm_labels<<<grid_for(k, 1, 65536), 256, 0, ctx->stream>>>(perm, P.d_leaf_off, k, labels);
   return knnkm_check(ctx, "twomeans labels");
+}
+
+knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                         int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
+                         int32_t* labels) {
+  return ks_twomeans_multi(ctx, X, d, ldx, std::vector<int64_t>{n}, std::vector<int32_t>{k}, nullptr, seed,
+                           round_tag, iters, labels);
 }
 
 extern "C" knnkm_status knnkm_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d,

@@ -24,6 +24,7 @@ EXPORTS = [
     "knnkm_default_params", "knnkm_workspace_bytes", "knn_assign", "centroid_update",
     "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
     "knn_kmeans_fit", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times",
+    "knnkm_fit_batched",
 ]
 
 
@@ -81,6 +82,7 @@ def lib():
             "knn_build": [P, P, i64, i32, i64, ctypes.POINTER(Params), P, P],
             "knn_kmeans_fit": [P, P, i64, i32, i64, i32, P, ctypes.POINTER(Params), P, P, P, P, P],
             "knnkm_rng_draw": [P, u64, u64, u64, i64, P],
+            "knnkm_fit_batched": [P, P, i32, i64, i32, P, P, P, ctypes.POINTER(Params), P, P, P, P, P, P],
             "knnkm_enable_timing": [P, i32],
             "knnkm_phase_times": [P, P, i32],
         }
@@ -258,6 +260,29 @@ def knn_kmeans_fit(ctx, X, k, G_ids, params, labels, C, counts):
                               trace.ctypes.data_as(ctypes.c_void_p), ctypes.byref(it))
     _chk(ctx.handle, st)
     return trace[: it.value + 1], it.value
+
+
+def knnkm_fit_batched(ctx, X, n_off, ks, seeds, params, G_ids, G_d2, labels, C, counts):
+    """Batching form.  n_off: m+1 row offsets, ks: m cluster counts, seeds: m
+    seeds (host sequences).  Returns the traces as an m x (max_iters+1) array."""
+    import torch
+
+    n, d, ldx = _rows(X)
+    m = len(ks)
+    noff = np.ascontiguousarray(n_off, dtype=np.int64)
+    karr = np.ascontiguousarray(ks, dtype=np.int32)
+    sarr = np.ascontiguousarray(seeds, dtype=np.uint64)
+    if noff.shape != (m + 1,) or sarr.shape != (m,) or int(noff[-1]) != n:
+        raise ValueError("job tables do not match X")
+    trace = np.zeros((m, params.max_iters + 1), np.float64)
+    st = lib().knnkm_fit_batched(ctx.handle, _ptr(X, torch.float32, "X"), d, ldx, m,
+                                 noff.ctypes.data_as(ctypes.c_void_p), karr.ctypes.data_as(ctypes.c_void_p),
+                                 sarr.ctypes.data_as(ctypes.c_void_p), ctypes.byref(params),
+                                 _ptr(G_ids, torch.int32, "G_ids"), _ptr(G_d2, torch.float32, "G_d2"),
+                                 _ptr(labels, torch.int32, "labels"), _ptr(C, torch.float32, "C"),
+                                 _ptr(counts, torch.int32, "counts"), trace.ctypes.data_as(ctypes.c_void_p))
+    _chk(ctx.handle, st)
+    return trace
 
 
 def knnkm_enable_timing(ctx, on=True):

@@ -89,3 +89,24 @@ def test_dry_context_validation(dry):
     assert "init" in knnkm.lib().knnkm_last_error(h).decode()
     # null context
     assert _call("knn_assign", None, X, 10, 4, 4, P, 5, P, 3, P, ctypes.c_void_p(0x3000), None, None) == knnkm.EINVAL
+
+
+def test_batched_validation(dry):
+    h = dry.handle
+    X = ctypes.c_void_p(0x1000)
+    P = ctypes.c_void_p(0x2000)
+    p = knnkm.default_params(kappa=8)
+
+    def call(noff, ks, seeds, m=None):
+        m = len(ks) if m is None else m
+        a = (ctypes.c_int64 * len(noff))(*noff)
+        b = (ctypes.c_int32 * len(ks))(*ks)
+        c = (ctypes.c_uint64 * len(seeds))(*seeds)
+        return knnkm.lib().knnkm_fit_batched(h, X, 16, 16, m, a, b, c, ctypes.byref(p), P, P, P, P, P, None)
+
+    assert call([0, 64, 200], [2, 5], [1, 2]) == knnkm.OK
+    assert call([0, 64, 200], [2, 5], [1, 2], m=0) == knnkm.EINVAL
+    assert call([1, 64, 200], [2, 5], [1, 2]) == knnkm.EINVAL      # n_off[0] != 0
+    assert call([0, 5, 200], [2, 5], [1, 2]) == knnkm.EINVAL       # job with fewer than kappa+1 rows
+    assert call([0, 64, 200], [65, 5], [1, 2]) == knnkm.EINVAL     # k > n
+    assert call([0, 64, 200], [0, 5], [1, 2]) == knnkm.EINVAL      # k < 1

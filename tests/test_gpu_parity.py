@@ -269,3 +269,78 @@ def test_fit_parity(ctx, init):
     assert np.array_equal(host(cnt), cnt_w)
     np.testing.assert_allclose(tr, tr_w, rtol=1e-9)
     assert (np.diff(tr) <= 1e-12 * tr[0]).all()
+
+
+# ----------------------------------------------------------------- batching --
+def _batch(sizes, d, seed):
+    Xs = [datagen.mixture(nq, d, max(2, nq // 32), seed=seed + q) for q, nq in enumerate(sizes)]
+    n_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    ks = [max(1, -(-nq // 32)) for nq in sizes]
+    seeds = [1000 + 17 * q for q in range(len(sizes))]
+    return Xs, n_off, ks, seeds
+
+
+def _run_alone(ctx, Xq, k, p):
+    nq, d = Xq.shape
+    gi = torch.empty((nq, p.kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((nq, p.kappa), dtype=torch.float32, device=DEV)
+    Xd = dev(Xq)
+    knnkm.knn_build(ctx, Xd, p, gi, gd)
+    lab = torch.empty(nq, dtype=torch.int32, device=DEV)
+    C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+    cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+    tr, _ = knnkm.knn_kmeans_fit(ctx, Xd, k, gi, p, lab, C, cnt)
+    return host(gi), host(gd), host(lab), host(C), host(cnt), tr
+
+
+@pytest.mark.parametrize("init", [knnkm.INIT_TWOMEANS, knnkm.INIT_RANDOM])
+def test_batch_equals_alone(ctx, init):
+    sizes = [64, 97, 300, 1000, 2500, 130, 64, 777]
+    d, kappa, T = 24, 8, 6
+    say("batch vs alone", init, sizes)
+    Xs, n_off, ks, seeds = _batch(sizes, d, seed=40)
+    X = np.concatenate(Xs)
+    n, K = X.shape[0], sum(ks)
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=3, max_iters=T, init=init)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    C = torch.empty((K, d), dtype=torch.float32, device=DEV)
+    cnt = torch.empty(K, dtype=torch.int32, device=DEV)
+    tr = knnkm.knnkm_fit_batched(ctx, dev(X), n_off, ks, seeds, p, gi, gd, lab, C, cnt)
+    gi, gd, lab, C, cnt = host(gi), host(gd), host(lab), host(C), host(cnt)
+    k_off = np.concatenate([[0], np.cumsum(ks)])
+    for q, Xq in enumerate(Xs):
+        r0, r1, c0, c1 = n_off[q], n_off[q + 1], k_off[q], k_off[q + 1]
+        p.seed = seeds[q]
+        a_gi, a_gd, a_lab, a_C, a_cnt, a_tr = _run_alone(ctx, Xq, ks[q], p)
+        assert np.array_equal(gi[r0:r1] - r0, a_gi), q
+        assert np.array_equal(gd[r0:r1], a_gd), q
+        assert np.array_equal(lab[r0:r1], a_lab), q
+        assert np.array_equal(C[c0:c1], a_C), q
+        assert np.array_equal(cnt[c0:c1], a_cnt), q
+        assert np.array_equal(tr[q], a_tr), q
+
+
+def test_batch_matches_oracle(ctx):
+    sizes = [70, 200, 450]
+    d, kappa, T = 16, 8, 4
+    say("batch vs oracle", sizes)
+    Xs, n_off, ks, seeds = _batch(sizes, d, seed=77)
+    X = np.concatenate(Xs)
+    n, K = X.shape[0], sum(ks)
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=2, max_iters=T)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    C = torch.empty((K, d), dtype=torch.float32, device=DEV)
+    cnt = torch.empty(K, dtype=torch.int32, device=DEV)
+    tr = knnkm.knnkm_fit_batched(ctx, dev(X), n_off, ks, seeds, p, gi, gd, lab, C, cnt)
+    gi, lab = host(gi), host(lab)
+    for q, Xq in enumerate(Xs):
+        r0, r1 = n_off[q], n_off[q + 1]
+        w_i, w_d = knng.knn_build(Xq, kappa, xi=50, tau=2, seed=seeds[q])
+        assert np.array_equal(gi[r0:r1] - r0, w_i), q
+        w_lab, _, _, w_tr, _, _ = gkmeans.fit(Xq, ks[q], w_i, T, seed=seeds[q])
+        assert np.array_equal(lab[r0:r1], w_lab), q
+        np.testing.assert_allclose(tr[q], w_tr, rtol=1e-9)
