@@ -13,6 +13,13 @@ steps.  The end-to-end fit time (build + fit) is ms_per_step.  The roofline
 entry is the assignment kernel (knn_assign), whose algorithmic bytes per launch
 are n*(4d + 8*kappa + 12) + 4*k*d.
 
+Beside it the line carries the two added forms, measured in the same run:
+"batching" (many independent small jobs, shaped like the 4,096-job workload,
+in one batched call against the same jobs run one at a time) and "serving"
+(a Poisson stream of jobs through the request loop with continuous batching
+against the same stream served one job at a time; p50/p99 latency and jobs/s).
+--config c4 / c5 run those two at full size and print their own line.
+
 Usage: python bench.py [--config c2] [--steps K] [--warmup W] [--gpus 1]
 """
 import argparse
@@ -39,6 +46,171 @@ CONFIGS = {
 }
 
 HBM_PEAK_GBS = 8000.0
+
+# many independent small jobs: n ~ U[64, 4096], d = 128, k = ceil(n/32),
+# ceil(n/32) mixture components (centres U[-10,10], sigma 1), kappa = 8, T = 20
+C4 = dict(m=4096, d=128, kappa=8, T=20, xi=50, tau=10)
+# serving stream: Poisson arrivals at 200 jobs/s, n log-uniform in [1e3, 1e6],
+# d in {64, 128, 256}, k = n/100, kappa = 16, T = 20, budget 200 GB
+C5 = dict(rate=200.0, seconds=60.0, dims=(64, 128, 256), kappa=16, T=20, xi=50, tau=10, budget=200 * 10**9,
+          pool_rows=1_000_000)
+
+
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v, np.float64), q)) if len(v) else None
+
+
+def bench_batching(m, sample, seed, log):
+    """Batched call over m jobs against the same jobs one at a time."""
+    import torch
+
+    from paper_1705_01813_amd import datagen, knnkm
+
+    dev = "cuda:0"
+    sizes = datagen.instance_sizes(m, seed).astype(np.int64)
+    ks = [int(-(-n // 32)) for n in sizes]
+    n_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    k_off = np.concatenate([[0], np.cumsum(ks)]).astype(np.int64)
+    seeds = [seed * 7919 + q for q in range(m)]
+    d, kappa = C4["d"], C4["kappa"]
+    N, K = int(n_off[-1]), int(k_off[-1])
+    X = datagen.batch_mixture_device(sizes, d, ks, seed, device=dev)
+    p = knnkm.default_params(kappa=kappa, xi=C4["xi"], tau=C4["tau"], max_iters=C4["T"])
+
+    def outs(n, k):
+        return (torch.empty((n, kappa), dtype=torch.int32, device=dev),
+                torch.empty((n, kappa), dtype=torch.float32, device=dev),
+                torch.empty(n, dtype=torch.int32, device=dev),
+                torch.empty((k, d), dtype=torch.float32, device=dev),
+                torch.empty(k, dtype=torch.int32, device=dev))
+
+    ctx = knnkm.Context(0)
+    gi, gd, lab, C, cnt = outs(N, K)
+    knnkm.knnkm_fit_batched(ctx, X, n_off, ks, seeds, p, gi, gd, lab, C, cnt)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    knnkm.knnkm_fit_batched(ctx, X, n_off, ks, seeds, p, gi, gd, lab, C, cnt)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batched: {m} jobs, {N} rows in {t_batch:.3f} s")
+    # the same jobs one at a time (a sample of them), same entry point, m = 1
+    one = []
+    same = True
+    for q in range(-2, sample):
+        j = max(q, 0)
+        r0, r1, c0, c1 = int(n_off[j]), int(n_off[j + 1]), int(k_off[j]), int(k_off[j + 1])
+        o = outs(r1 - r0, c1 - c0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        knnkm.knnkm_fit_batched(ctx, X[r0:r1], [0, r1 - r0], [ks[j]], [seeds[j]], p, *o)
+        torch.cuda.synchronize()
+        if q >= 0:  # the first two calls warm up
+            one.append(time.perf_counter() - t0)
+            same = same and bool(torch.equal(o[2], lab[r0:r1]) and torch.equal(o[3], C[c0:c1])
+                                 and torch.equal(o[4], cnt[c0:c1]) and torch.equal(o[0] + r0, gi[r0:r1]))
+    ctx.close()
+    rows_sample = int(n_off[sample])
+    # one-at-a-time time of all m jobs, extrapolated from the sample by rows
+    t_one_all = sum(one) * N / rows_sample
+    return {
+        "workload": f"{m} independent jobs, n ~ U[64,4096] (sum {N} rows), d={d}, k=ceil(n/32) (sum {K}), "
+                    f"kappa={kappa}, T={C4['T']}, tau={C4['tau']}, xi={C4['xi']}, per-job seeds",
+        "batched_s": t_batch,
+        "batched_jobs_per_s": m / t_batch,
+        "one_at_a_time_jobs_per_s": len(one) / sum(one),
+        "one_at_a_time_s_extrapolated": t_one_all,
+        "speedup": t_one_all / t_batch,
+        "one_at_a_time_latency_ms": {"p50": 1e3 * _pct(one, 50), "p99": 1e3 * _pct(one, 99)},
+        "one_at_a_time_sample": f"first {sample} jobs ({rows_sample} rows), extrapolated to all jobs by rows",
+        "identical_on_sample": same,
+    }
+
+
+def bench_serving(seconds, seed, log, rate=None):
+    """The serving stream through the request loop (continuous batching, 4
+    slots) and through the same loop restricted to one job at a time."""
+    import threading
+
+    import torch
+
+    from paper_1705_01813_amd import datagen, knnkm
+
+    rate = rate or C5["rate"]
+    stream = datagen.serving_stream(rate, seconds, seed, dims=C5["dims"])
+    P = C5["pool_rows"]
+    pools = {}
+    for i, d in enumerate(C5["dims"]):
+        # per-d pool of mixture rows (P/100 components, centres U[-10,10],
+        # sigma 1) in pinned host memory; a job is a random slice of it
+        Xd = datagen.mixture_device(P, d, P // 100, seed + i, device="cuda:0")
+        pools[d] = torch.empty((P, d), dtype=torch.float32, pin_memory=True)
+        pools[d].copy_(Xd)
+        del Xd
+    torch.cuda.synchronize()
+    rs = np.random.default_rng(seed)
+    jobs = []
+    for j, (t, n, d) in enumerate(stream):
+        off = int(rs.integers(0, P - n + 1))
+        jobs.append((t, pools[d][off:off + n], max(1, n // 100), j))
+
+    def run(slots, max_jobs):
+        S = knnkm.Server(device=0, slots=slots, max_batch_jobs=max_jobs, hbm_budget_bytes=C5["budget"])
+        tickets = [None] * len(jobs)
+        t_start = time.perf_counter()
+
+        def client():
+            for j, (t, X, k, sd) in enumerate(jobs):
+                delay = t_start + t - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                p = knnkm.default_params(kappa=C5["kappa"], xi=C5["xi"], tau=C5["tau"], max_iters=C5["T"],
+                                         seed=sd)
+                tickets[j] = S.submit(X, k, p)
+
+        th = threading.Thread(target=client)
+        th.start()
+        infos = []
+        done = 0
+        for j in range(len(jobs)):
+            while tickets[j] is None:
+                time.sleep(0.0005)
+            r = S.wait(tickets[j])
+            infos.append(r["info"])
+            done += 1
+            if done % 100 == 0:
+                log(f"serving (slots={slots}, batch<={max_jobs}): {done}/{len(jobs)} done")
+        th.join()
+        st = S.stats()
+        S.close()
+        lat = [i["t_done"] - i["t_submit"] for i in infos]
+        span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+        return {
+            "jobs": len(infos),
+            "jobs_per_s": len(infos) / span,
+            "makespan_s": span,
+            "latency_ms": {"p50": 1e3 * _pct(lat, 50), "p99": 1e3 * _pct(lat, 99), "max": 1e3 * max(lat)},
+            "queue_wait_ms_p50": 1e3 * _pct([i["t_admit"] - i["t_submit"] for i in infos], 50),
+            "batches": st["batches"],
+            "mean_batch_jobs": len(infos) / max(1, st["batches"]),
+            "max_queued": st["max_queued"],
+            "hbm_peak_charged_gb": st["bytes_peak"] / 1e9,
+            "ws_overruns": st["ws_overruns"],
+            "keeps_up": span <= seconds * 1.05,
+        }
+
+    rows = sum(int(X.shape[0]) for _, X, _, _ in jobs)
+    log(f"serving: {len(jobs)} jobs ({rows} rows) over {seconds} s")
+    cont = run(4, 4096)
+    single = run(1, 1)
+    return {
+        "workload": f"Poisson arrivals at {rate:g} jobs/s for {seconds:g} s ({len(jobs)} jobs, {rows} rows): "
+                    f"n = round(10^U[3,6]), d in {{64,128,256}}, k = n/100, kappa={C5['kappa']}, "
+                    f"T={C5['T']}, tau={C5['tau']}, xi={C5['xi']}; rows are random slices of a per-d "
+                    f"mixture pool in pinned host memory; HBM budget {C5['budget'] / 1e9:g} GB",
+        "continuous_batching": cont,
+        "one_at_a_time": single,
+        "speedup_jobs_per_s": cont["jobs_per_s"] / single["jobs_per_s"],
+    }
 
 
 def assign_bytes(n, d, k, kappa):
@@ -95,7 +267,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS) + ["c4", "c5"])
+    ap.add_argument("--no-forms", action="store_true", help="skip the batching and serving measurements")
+    ap.add_argument("--forms-jobs", type=int, default=4096, help="jobs of the batching measurement")
+    ap.add_argument("--forms-sample", type=int, default=64, help="jobs timed one at a time")
+    ap.add_argument("--serve-seconds", type=float, default=None,
+                    help="arrival window of the serving run (default 2 s beside the main line, 60 s for c5)")
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -108,6 +285,24 @@ def main():
     import torch
 
     from paper_1705_01813_amd import knnkm
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.config == "c4":
+        b = bench_batching(C4["m"], args.forms_sample, args.seed, log)
+        print(json.dumps({"metric": "jobs/s", "value": b["batched_jobs_per_s"], "unit": "jobs/s", "n_gpus": 1,
+                          "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": b["workload"]}, "batching": b}), flush=True)
+        return 0
+    if args.config == "c5":
+        sv = bench_serving(args.serve_seconds or C5["seconds"], args.seed, log)
+        c = sv["continuous_batching"]
+        print(json.dumps({"metric": "jobs/s; p50/p99 job latency", "value": c["jobs_per_s"], "unit": "jobs/s",
+                          "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+                          "data": "synthetic", "config": {"workload": sv["workload"]}, "serving": sv}),
+              flush=True)
+        return 0
 
     cfg = CONFIGS[args.config]
     dev = "cuda:0"
@@ -178,6 +373,11 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_assign},
     }
     ctx.close()
+    del X, G_ids, G_d2, labels, C, counts
+    torch.cuda.empty_cache()
+    if not args.no_forms:
+        out["batching"] = bench_batching(args.forms_jobs, args.forms_sample, args.seed, log)
+        out["serving"] = bench_serving(args.serve_seconds or 2.0, args.seed, log)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, args.seed, args.cpu_seconds)

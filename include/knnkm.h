@@ -46,7 +46,8 @@ typedef enum {
   KNNKM_EINVAL = 1,      /* invalid argument (checked before any launch) */
   KNNKM_ENOMEM = 2,      /* workspace allocation failed */
   KNNKM_EDEVICE = 3,     /* HIP runtime error; sticky for the context */
-  KNNKM_EUNSUPPORTED = 4 /* valid request outside the implemented limits */
+  KNNKM_EUNSUPPORTED = 4, /* valid request outside the implemented limits */
+  KNNKM_EAGAIN = 5        /* knnkm_server_wait: the job has not finished yet */
 } knnkm_status;
 
 enum { KNNKM_FP32 = 0, KNNKM_BF16_RERANK = 1 };
@@ -182,6 +183,104 @@ knnkm_status knnkm_fit_batched(knnkm_ctx* ctx, const float* X, int32_t d, int64_
                                const uint64_t* seeds_host, const knnkm_params* params, int32_t* G_ids,
                                float* G_d2, int32_t* labels, float* C, int32_t* counts,
                                double* trace_host);
+
+/* ------------------------------------------------------------ serving form --
+ * A request loop over one device.  Jobs (each a graph build plus a fit, as
+ * knn_build + knn_kmeans_fit) are submitted from any host thread and return
+ * at once with a ticket.  `slots` worker threads, each with its own context
+ * and non-blocking HIP stream, take the queued jobs in arrival order: a free
+ * worker forms a batch from the oldest queued job and every later queued job
+ * of the same class (same d and the same params apart from seed), within
+ * max_batch_jobs / max_batch_rows and the HBM budget, copies their rows into
+ * device memory it allocates for the batch, runs them through
+ * knnkm_fit_batched (one launch per phase for the whole batch), copies the
+ * results to the jobs' host buffers and frees the batch's device memory.
+ * Batches of different workers overlap on the device, and jobs that arrive
+ * while batches run join the next batch a worker forms as soon as a slot and
+ * budget free up (continuous batching at batch granularity).
+ *
+ * Admission: a job's footprint is its device buffers (rows, graph, labels,
+ * centroids, counts) plus a workspace estimate; the sum over running batches
+ * plus the workspace each worker keeps must stay within hbm_budget_bytes.
+ * The oldest queued job is never overtaken by a job of another class, so a
+ * large job cannot starve; when it does not fit, workers wait (idle workers
+ * first release their workspace).  A job that does not fit the budget even
+ * alone is rejected at submit (KNNKM_ENOMEM).
+ *
+ * Results: each job's labels, centroids, counts, graph and distortion trace
+ * are bit-identical to running it alone through knnkm_fit_batched with m = 1
+ * (and to knn_build + knn_kmeans_fit with params.seed = its seed).
+ */
+typedef struct knnkm_server knnkm_server;
+
+typedef struct {
+  uint32_t struct_size;     /* sizeof(knnkm_server_config) */
+  int32_t device;           /* HIP device; -1: a dry server that validates and
+                               schedules but runs nothing and writes no output */
+  int32_t slots;            /* batches in flight at once, 1..16 */
+  int32_t max_batch_jobs;   /* jobs per batch, >= 1 */
+  int64_t max_batch_rows;   /* rows per batch, >= 1 (a larger job runs alone) */
+  int64_t hbm_budget_bytes; /* device memory the server may hold, > 0 */
+} knnkm_server_config;
+
+typedef struct {
+  uint32_t struct_size; /* sizeof(knnkm_job) */
+  int32_t d;            /* dimensions, 1..KNNKM_MAX_D */
+  int64_t n;            /* samples, kappa + 1 <= n < 2^31 */
+  int64_t ldx;          /* row stride of X_host in elements, >= d */
+  const float* X_host;  /* host rows; read until the job completes */
+  int32_t k;            /* clusters, 1 <= k <= n */
+  int32_t pad_;
+  knnkm_params params;  /* kappa, xi, tau, bisect_iters, precision, init,
+                           max_iters, seed (early_stop is not used) */
+  /* host outputs, written before the job completes; may be null */
+  int32_t* labels_host; /* n, cluster ids 0..k-1 */
+  float* C_host;        /* k x d */
+  int32_t* counts_host; /* k */
+  int32_t* G_ids_host;  /* n x kappa, row ids 0..n-1 */
+  double* trace_host;   /* max_iters + 1: E_0..E_T (Eqn. 4) */
+} knnkm_job;
+
+typedef struct {
+  int32_t status;          /* knnkm_status of the job */
+  int32_t slot;            /* worker that ran it */
+  int64_t batch;           /* serial number of its batch */
+  int32_t batch_jobs;      /* jobs in that batch */
+  int32_t pad_;
+  int64_t footprint_bytes; /* bytes charged to the budget for this job */
+  double t_submit;         /* seconds on the server clock (monotonic, 0 at create) */
+  double t_admit;          /* batch formed */
+  double t_done;           /* outputs in host memory */
+} knnkm_job_info;
+
+typedef struct {
+  int64_t submitted, completed, failed, rejected;
+  int64_t batches;          /* batches run */
+  int64_t queued;           /* waiting for admission now */
+  int64_t running;          /* admitted, not finished */
+  int64_t max_queued;       /* largest queue seen */
+  int64_t max_batch_jobs_seen;
+  int64_t bytes_in_use;     /* charged now (running batches + kept workspace) */
+  int64_t bytes_peak;       /* largest charge seen */
+  int64_t ws_overruns;      /* batches whose workspace exceeded its estimate */
+} knnkm_server_stats;
+
+/* Start the workers.  The server owns its contexts, streams and threads. */
+knnkm_status knnkm_server_create(const knnkm_server_config* config, knnkm_server** out);
+/* Validate and queue a job (the job struct is copied; X_host and the output
+ * buffers must stay valid until knnkm_server_wait has returned for it).
+ * *ticket identifies it.  Thread-safe. */
+knnkm_status knnkm_server_submit(knnkm_server* srv, const knnkm_job* job, uint64_t* ticket);
+/* Wait up to timeout_ms (< 0: no limit) for a job.  Returns KNNKM_EAGAIN if
+ * it has not finished, else the job's own status, fills *info (may be null)
+ * and forgets the ticket.  Thread-safe. */
+knnkm_status knnkm_server_wait(knnkm_server* srv, uint64_t ticket, int64_t timeout_ms,
+                               knnkm_job_info* info);
+knnkm_status knnkm_server_stats_get(knnkm_server* srv, knnkm_server_stats* out);
+/* Message of the last failed server call made by the calling thread. */
+const char* knnkm_server_last_error(void);
+/* Run every queued job to completion, stop the workers, free everything. */
+knnkm_status knnkm_server_destroy(knnkm_server* srv);
 
 /* Opt-in phase timing.  While enabled, knn_build and knn_kmeans_fit record
  * HIP events on the context stream around their phases (a few microseconds

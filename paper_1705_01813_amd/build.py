@@ -11,12 +11,13 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libknnkm.so")
 OBJ = os.path.join(PKG, "_build")
-SOURCES = ["ctx.hip", "assign.hip", "update.hip", "twomeans.hip", "graph.hip", "drivers.hip"]
+SOURCES = ["ctx.hip", "assign.hip", "update.hip", "twomeans.hip", "graph.hip", "drivers.hip",
+           "server.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # packed FP32 instructions stay off (see the design notes)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-result",
+    "-Wno-unused-result", "-pthread",
 ]
 
 
@@ -34,7 +35,7 @@ def build(verbose=False):
     with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -43,6 +43,8 @@ knnkm_status knnkm_fail(knnkm_ctx* ctx, knnkm_status st, const char* fmt, ...);
 // Device buffer of at least `bytes` bytes, grown on demand (contents are not
 // preserved across growth).  Returns nullptr and sets ENOMEM on failure.
 void* knnkm_ws(knnkm_ctx* ctx, const char* name, size_t bytes);
+// Release every workspace buffer (after the work queued on the context stream).
+knnkm_status knnkm_ws_release(knnkm_ctx* ctx);
 // Check the HIP status of the last launches; sets the sticky error.
 knnkm_status knnkm_check(knnkm_ctx* ctx, const char* where);
 

@@ -20,15 +20,16 @@ void* knnkm_ws(knnkm_ctx* ctx, const char* name, size_t bytes) {
   if (bytes == 0) bytes = 8;
   knnkm_buf& b = ctx->ws[name];
   if (b.bytes >= bytes) return b.ptr;
+  // Stream-ordered: the old buffer is released after the work already queued
+  // on the context stream, and growth never waits for other streams.
   if (b.ptr) {
-    (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(b.ptr);
+    (void)hipFreeAsync(b.ptr, ctx->stream);
     b.ptr = nullptr;
     b.bytes = 0;
   }
   size_t want = bytes + bytes / 8;  // headroom against repeated growth
   void* p = nullptr;
-  if (hipMalloc(&p, want) != hipSuccess) {
+  if (hipMallocAsync(&p, want, ctx->stream) != hipSuccess) {
     (void)hipGetLastError();
     knnkm_fail(ctx, KNNKM_ENOMEM, "workspace '%s': cannot allocate %zu bytes", name, want);
     return nullptr;
@@ -36,6 +37,17 @@ void* knnkm_ws(knnkm_ctx* ctx, const char* name, size_t bytes) {
   b.ptr = p;
   b.bytes = want;
   return p;
+}
+
+knnkm_status knnkm_ws_release(knnkm_ctx* ctx) {
+  if (ctx->dry) return KNNKM_OK;
+  for (auto& kv : ctx->ws)
+    if (kv.second.ptr) (void)hipFreeAsync(kv.second.ptr, ctx->stream);
+  ctx->ws.clear();
+  tm_plan_free(ctx->tm_plan);  // its device tables were workspace
+  ctx->tm_plan = nullptr;
+  KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return KNNKM_OK;
 }
 
 knnkm_status knnkm_check(knnkm_ctx* ctx, const char* where) {
@@ -90,9 +102,9 @@ extern "C" knnkm_status knnkm_destroy(knnkm_ctx* ctx) {
   if (!ctx) return KNNKM_EINVAL;
   if (!ctx->dry) {
     (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
     for (auto& kv : ctx->ws)
-      if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+      if (kv.second.ptr) (void)hipFreeAsync(kv.second.ptr, ctx->stream);
+    (void)hipStreamSynchronize(ctx->stream);
   }
   tm_plan_free(ctx->tm_plan);
   for (hipEvent_t e : ctx->ev)
@@ -103,6 +115,14 @@ extern "C" knnkm_status knnkm_destroy(knnkm_ctx* ctx) {
 
 extern "C" knnkm_status knnkm_set_stream(knnkm_ctx* ctx, void* hip_stream) {
   if (!ctx) return KNNKM_EINVAL;
+  // workspace buffers are stream-ordered allocations of the old stream
+  if (!ctx->dry && ctx->stream != (hipStream_t)hip_stream) {
+    (void)hipSetDevice(ctx->device);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      ctx->sticky = true;
+      return knnkm_fail(ctx, KNNKM_EDEVICE, "knnkm_set_stream: synchronising the old stream failed");
+    }
+  }
   ctx->stream = (hipStream_t)hip_stream;
   return KNNKM_OK;
 }

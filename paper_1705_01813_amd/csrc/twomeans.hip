@@ -72,11 +72,8 @@ struct TMPlan {
   const int64_t* d_split_heap;
 };
 
-void tm_plan_free(TMPlan* p) {
-  if (!p) return;
-  if (p->dev) (void)hipFree(p->dev);
-  delete p;
-}
+// The device tables live in the context workspace ("tm_plan").
+void tm_plan_free(TMPlan* p) { delete p; }
 
 // Tree shapes of several independent jobs (job j: rows [off_j, off_j + n_j),
 // k_j leaves), merged depth by depth so one launch per step covers every job
@@ -237,12 +234,15 @@ static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P) {
     total += p.second;
   }
   total += 16;
-  KNNKM_HIP(ctx, hipMalloc(&P.dev, total));
+  P.dev = knnkm_ws(ctx, "tm_plan", total);
+  if (!P.dev) return KNNKM_ENOMEM;
   P.dev_bytes = total;
   std::vector<char> host(total, 0);
   for (size_t i = 0; i < parts.size(); ++i)
     if (parts[i].second) std::memcpy(host.data() + at[i], parts[i].first, parts[i].second);
-  KNNKM_HIP(ctx, hipMemcpy(P.dev, host.data(), total, hipMemcpyHostToDevice));
+  KNNKM_HIP(ctx, hipMemcpyAsync(P.dev, host.data(), total, hipMemcpyHostToDevice, ctx->stream));
+  // `host` is released on return
+  KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   const char* b = (const char*)P.dev;
   P.d_split_off = (const int32_t*)(b + at[0]);
   P.d_split_size = (const int32_t*)(b + at[1]);

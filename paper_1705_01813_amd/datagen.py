@@ -94,3 +94,39 @@ def instance_sizes(m, seed, lo=64, hi=4096):
     """Sizes of m independent small clustering jobs, n ~ U[lo, hi]."""
     rs = np.random.Generator(np.random.PCG64(seed))
     return rs.integers(lo, hi + 1, size=m)
+
+
+def batch_mixture_device(sizes, d, comps, seed, lo=-10.0, hi=10.0, sigma=1.0, device="cuda"):
+    """Independent mixtures, one per job, concatenated: job q has sizes[q] rows
+    from comps[q] equal-weight components with centres U[lo, hi]^d and noise
+    sigma (drawn with torch on ``device`` in one pass)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    sizes_t = torch.as_tensor(np.asarray(sizes, np.int64), device=device)
+    comps_t = torch.as_tensor(np.asarray(comps, np.int64), device=device)
+    c_off = torch.cumsum(comps_t, 0) - comps_t
+    centres = torch.rand((int(comps_t.sum()), d), generator=g, device=device) * (hi - lo) + lo
+    job = torch.repeat_interleave(torch.arange(len(sizes), device=device), sizes_t)
+    u = torch.rand(job.shape[0], generator=g, device=device, dtype=torch.float64)
+    comp = c_off[job] + (u * comps_t[job]).long().minimum(comps_t[job] - 1)
+    X = torch.empty((job.shape[0], d), dtype=torch.float32, device=device)
+    step = 1 << 20
+    for s in range(0, X.shape[0], step):
+        e = min(X.shape[0], s + step)
+        X[s:e] = centres[comp[s:e]] + sigma * torch.randn((e - s, d), generator=g, device=device)
+    return X
+
+
+def serving_stream(rate, seconds, seed, n_lo=1e3, n_hi=1e6, dims=(64, 128, 256)):
+    """Poisson arrivals: (arrival time s, n, d) with n = round(10^U[log10 n_lo,
+    log10 n_hi]) and d uniform over ``dims``."""
+    rs = np.random.Generator(np.random.PCG64(seed))
+    t, out = 0.0, []
+    while True:
+        t += rs.exponential(1.0 / rate)
+        if t >= seconds:
+            return out
+        n = int(round(10 ** rs.uniform(np.log10(n_lo), np.log10(n_hi))))
+        out.append((t, n, int(rs.choice(dims))))

@@ -12,7 +12,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libknnkm.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, 1, 2, 3, 4
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EAGAIN = 0, 1, 2, 3, 4, 5
 FP32, BF16_RERANK = 0, 1
 INIT_TWOMEANS, INIT_RANDOM = 0, 1
 ROUND_FIT = 0xFFFF
@@ -24,7 +24,8 @@ EXPORTS = [
     "knnkm_default_params", "knnkm_workspace_bytes", "knn_assign", "centroid_update",
     "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
     "knn_kmeans_fit", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times",
-    "knnkm_fit_batched",
+    "knnkm_fit_batched", "knnkm_server_create", "knnkm_server_submit", "knnkm_server_wait",
+    "knnkm_server_stats_get", "knnkm_server_last_error", "knnkm_server_destroy",
 ]
 
 
@@ -41,6 +42,55 @@ class Params(ctypes.Structure):
         ("early_stop", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("device", ctypes.c_int32),
+        ("slots", ctypes.c_int32),
+        ("max_batch_jobs", ctypes.c_int32),
+        ("max_batch_rows", ctypes.c_int64),
+        ("hbm_budget_bytes", ctypes.c_int64),
+    ]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("d", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("ldx", ctypes.c_int64),
+        ("X_host", ctypes.c_void_p),
+        ("k", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("params", Params),
+        ("labels_host", ctypes.c_void_p),
+        ("C_host", ctypes.c_void_p),
+        ("counts_host", ctypes.c_void_p),
+        ("G_ids_host", ctypes.c_void_p),
+        ("trace_host", ctypes.c_void_p),
+    ]
+
+
+class JobInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("slot", ctypes.c_int32),
+        ("batch", ctypes.c_int64),
+        ("batch_jobs", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("footprint_bytes", ctypes.c_int64),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in (
+        "submitted", "completed", "failed", "rejected", "batches", "queued", "running", "max_queued",
+        "max_batch_jobs_seen", "bytes_in_use", "bytes_peak", "ws_overruns")]
 
 
 class KnnkmError(RuntimeError):
@@ -85,6 +135,11 @@ def lib():
             "knnkm_fit_batched": [P, P, i32, i64, i32, P, P, P, ctypes.POINTER(Params), P, P, P, P, P, P],
             "knnkm_enable_timing": [P, i32],
             "knnkm_phase_times": [P, P, i32],
+            "knnkm_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)],
+            "knnkm_server_submit": [P, ctypes.POINTER(Job), ctypes.POINTER(u64)],
+            "knnkm_server_wait": [P, u64, i64, ctypes.POINTER(JobInfo)],
+            "knnkm_server_stats_get": [P, ctypes.POINTER(ServerStats)],
+            "knnkm_server_destroy": [P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -92,6 +147,8 @@ def lib():
             f.restype = ctypes.c_int
         L.knnkm_last_error.argtypes = [P]
         L.knnkm_last_error.restype = ctypes.c_char_p
+        L.knnkm_server_last_error.argtypes = []
+        L.knnkm_server_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -303,3 +360,95 @@ def knnkm_rng_draw(ctx, seed, stream, ctr0, out):
 
     st = lib().knnkm_rng_draw(ctx.handle, seed, stream, ctr0, out.numel(), _ptr(out, torch.uint64, "out"))
     _chk(ctx.handle, st)
+
+
+# ------------------------------------------------------------- serving form --
+def _server_chk(st):
+    if st != OK:
+        raise KnnkmError(st, lib().knnkm_server_last_error().decode())
+
+
+def _host_rows(X):
+    """(pointer, n, d, ldx) of a host float32 matrix with unit column stride."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(X, torch.Tensor):
+        if X.is_cuda or X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
+            raise ValueError("X must be a 2-D float32 host tensor with unit column stride")
+        return X.data_ptr(), X.shape[0], X.shape[1], X.stride(0)
+    X = np.asarray(X)
+    if X.dtype != np.float32 or X.ndim != 2 or X.strides[1] != 4 or X.strides[0] % 4:
+        raise ValueError("X must be a 2-D float32 array with unit column stride")
+    return X.ctypes.data, X.shape[0], X.shape[1], X.strides[0] // 4
+
+
+class Server:
+    """Request loop of the library (knnkm_server_*).  submit() queues a job and
+    returns its ticket; wait() returns its result.  The host rows and the
+    result arrays of a job are kept alive here until it has been waited for."""
+
+    def __init__(self, device=0, slots=4, max_batch_jobs=4096, max_batch_rows=1 << 24,
+                 hbm_budget_bytes=200 * 10**9):
+        cfg = ServerConfig(ctypes.sizeof(ServerConfig), device, slots, max_batch_jobs, max_batch_rows,
+                           int(hbm_budget_bytes))
+        self._h = ctypes.c_void_p()
+        _server_chk(lib().knnkm_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._live = {}
+
+    def submit(self, X, k, params, want_graph=False):
+        ptr, n, d, ldx = _host_rows(X)
+        out = {
+            "labels": np.empty(n, np.int32),
+            "C": np.empty((k, d), np.float32),
+            "counts": np.empty(k, np.int32),
+            "trace": np.empty(params.max_iters + 1, np.float64),
+            "G_ids": np.empty((n, params.kappa), np.int32) if want_graph else None,
+        }
+
+        def p(a):
+            return None if a is None else a.ctypes.data
+
+        job = Job(ctypes.sizeof(Job), d, n, ldx, ptr, k, 0, params, p(out["labels"]), p(out["C"]),
+                  p(out["counts"]), p(out["G_ids"]), p(out["trace"]))
+        t = ctypes.c_uint64()
+        _server_chk(lib().knnkm_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)))
+        self._live[t.value] = (X, out)
+        return t.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        """The job's outputs and timing, or None if it has not finished within
+        timeout_ms.  Raises KnnkmError if the job failed."""
+        info = JobInfo()
+        st = lib().knnkm_server_wait(self._h, ticket, timeout_ms, ctypes.byref(info))
+        if st == EAGAIN:
+            return None
+        held = self._live.pop(ticket, None)
+        _server_chk(st)
+        out = held[1]
+        out["info"] = {f: getattr(info, f) for f, _ in JobInfo._fields_ if f != "pad_"}
+        return out
+
+    def stats(self):
+        s = ServerStats()
+        _server_chk(lib().knnkm_server_stats_get(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().knnkm_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
