@@ -57,6 +57,49 @@ __global__ void k_gather_rows(const float* __restrict__ X, int d, int64_t ldx,
   }
 }
 
+// Working copy of the data in the cluster order of a partition: row p of the
+// copy is row perm[p] of X (contiguous, leading dimension d).
+__global__ void k_permute_rows(const float* __restrict__ X, int d, int64_t ldx, const int32_t* __restrict__ perm,
+                               int64_t n, int vec, float* __restrict__ Xp) {
+  if (vec) {
+    const int q4 = d >> 2;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * q4;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t p = e / q4, t = (e - p * q4) * 4;
+      *reinterpret_cast<float4*>(Xp + p * d + t) = *reinterpret_cast<const float4*>(X + (int64_t)perm[p] * ldx + t);
+    }
+  } else {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * d;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t p = e / d, t = e - p * d;
+      Xp[e] = X[(int64_t)perm[p] * ldx + t];
+    }
+  }
+}
+__global__ void k_perm_inverse(const int32_t* __restrict__ perm, int64_t n, int32_t* __restrict__ inv) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+    inv[perm[p]] = (int32_t)p;
+}
+// Graph rows in the copy's numbering: Gp[p] = inv(G[perm[p]]).
+__global__ void k_permute_graph(const int32_t* __restrict__ G, int kappa, const int32_t* __restrict__ perm,
+                                const int32_t* __restrict__ inv, int64_t n, int32_t* __restrict__ Gp) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * kappa;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / kappa, q = e - p * kappa;
+    Gp[e] = inv[G[(int64_t)perm[p] * kappa + q]];
+  }
+}
+__global__ void k_gather_i32(const int32_t* __restrict__ src, const int32_t* __restrict__ perm, int64_t n,
+                             int32_t* __restrict__ dst) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+    dst[p] = src[perm[p]];
+}
+__global__ void k_scatter_i32(const int32_t* __restrict__ src, const int32_t* __restrict__ perm, int64_t n,
+                              int32_t* __restrict__ dst) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+    dst[perm[p]] = src[p];
+}
+
 // ||x_i||^2 in float64, one wavefront per row.
 __global__ __launch_bounds__(256) void k_row_sq64(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
                                                   double* __restrict__ out) {
@@ -294,17 +337,42 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   KNNKM_TRY(knnkm_check(ctx, "fit initialisation"));
   mark(3);
 
-  int32_t* cur = labels;
+  // The sweeps run on a working copy of X (and of the graph) in the cluster
+  // order of the initial partition: rows are then read as streams, and the
+  // neighbours of a sample, which mostly share its cluster, have nearby ids.
+  // Assignments do not depend on the numbering of the samples; the update
+  // sums each cluster's members in the copy's order.
+  const bool use_graph = !(m == 1 && all_dense) && G_ids;
+  KNNKM_WS(ctx, perm, int32_t, "fit_perm", n);
+  KNNKM_WS(ctx, inv, int32_t, "fit_inv", n);
+  KNNKM_WS(ctx, Xp, float, "fit_xp", n * (int64_t)d);
+  KNNKM_WS(ctx, labp, int32_t, "fit_labp", n);
+  int32_t* Gp = nullptr;
+  if (use_graph) {
+    Gp = (int32_t*)knnkm_ws(ctx, "fit_gp", sizeof(int32_t) * (size_t)n * kappa);
+    if (!Gp) return KNNKM_ENOMEM;
+  }
+  KNNKM_HIP(ctx, hipMemcpyAsync(perm, mem, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
+  const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+  k_permute_rows<<<grid_for(n * (vec ? d / 4 : d), 256, 16384), 256, 0, ctx->stream>>>(X, d, ldx, perm, n,
+                                                                                       vec ? 1 : 0, Xp);
+  k_perm_inverse<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(perm, n, inv);
+  if (use_graph)
+    k_permute_graph<<<grid_for(n * kappa, 256, 16384), 256, 0, ctx->stream>>>(G_ids, kappa, perm, inv, n, Gp);
+  k_gather_i32<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(labels, perm, n, labp);
+  KNNKM_TRY(knnkm_check(ctx, "fit working copy"));
+
+  int32_t* cur = labp;
   int32_t* nxt = lab2;
   int it = 0;
   for (int t = 1; t <= T; ++t) {
     mark(6 + 2 * (t - 1));
-    KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, K, G_ids, kappa, cur, nxt, nullptr, moved + t, mem,
+    KNNKM_TRY(ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cur, nxt, nullptr, moved + t, nullptr,
                         m == 1 && all_dense, J.job_of, k32));
     mark(7 + 2 * (t - 1));
     if (ctx->timing) ctx->assign_n = t;
     KNNKM_TRY(ks_label_sort(ctx, nxt, n, K, counts, off, mem));
-    KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K, counts, off, mem, C, nullptr, Iterm));
+    KNNKM_TRY(ks_segsum(ctx, Xp, n, d, d, K, counts, off, mem, C, nullptr, Iterm));
     k_range_sum<<<m, 256, 0, ctx->stream>>>(Iterm, k64, isum);
     k_trace_jobs<<<(m + 255) / 256, 256, 0, ctx->stream>>>(sxx, isum, J.n_off, m, trace_dev + (int64_t)t * m);
     KNNKM_TRY(knnkm_check(ctx, "fit iteration"));
@@ -318,9 +386,9 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     }
   }
   mark(4);
-  if (cur != labels)
-    KNNKM_HIP(ctx, hipMemcpyAsync(labels, cur, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice,
-                                  ctx->stream));
+  // labels back in the caller's numbering
+  k_scatter_i32<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(cur, perm, n, labels);
+  KNNKM_TRY(knnkm_check(ctx, "fit labels"));
   *iters_run = it;
   return KNNKM_OK;
 }

@@ -44,10 +44,11 @@ int64_t job_buffer_bytes(int64_t n, int64_t d, int64_t k, int64_t kappa) {
 // k fit clusters and k0 graph-construction clusters in total.  Sums the
 // named workspace buffers of the build, the two-means partition, the sort,
 // the segmented sums and the fit (with their growth headroom of 1/8).
-int64_t ws_estimate(int64_t n, int64_t d, int64_t k, int64_t k0, int64_t m, int64_t T) {
+int64_t ws_estimate(int64_t n, int64_t d, int64_t k, int64_t k0, int64_t kappa, int64_t m, int64_t T) {
   const int64_t kx = std::max(k, k0);
   int64_t b = 0;
   b += 100 * n;                              // per-row int32/int64/double buffers
+  b += (4 * d + 4 * kappa + 16) * n;         // the fit's cluster-ordered copy of X and the graph
   b += 8 * d * (n / 256 + kx + 2);           // segmented-sum partials
   b += 4 * d * k0;                           // graph-construction centroids
   b += 8 * d * kx;                           // two-means split centroids
@@ -122,7 +123,7 @@ struct knnkm_server {
       return j.params.tau > 0 ? std::max<int64_t>(1, j.n / j.params.xi) : 0;
     };
     auto need = [&](int64_t r, int64_t by, int64_t kk, int64_t kk0, int64_t m) {
-      const int64_t ws = ws_estimate(r, head->req.d, kk, kk0, m, head->req.params.max_iters);
+      const int64_t ws = ws_estimate(r, head->req.d, kk, kk0, head->req.params.kappa, m, head->req.params.max_iters);
       return by + std::max<int64_t>(0, ws - slots[s].ws_charged);
     };
     for (SJob* j : queue) {
@@ -141,7 +142,8 @@ struct knnkm_server {
       k = kk;
       k0 = kk0;
     }
-    const int64_t ws = ws_estimate(rows, head->req.d, k, k0, (int64_t)B.size(), head->req.params.max_iters);
+    const int64_t ws = ws_estimate(rows, head->req.d, k, k0, head->req.params.kappa, (int64_t)B.size(),
+                                   head->req.params.max_iters);
     *extra_ws = std::max<int64_t>(0, ws - slots[s].ws_charged);
     return B;
   }
@@ -394,7 +396,7 @@ extern "C" knnkm_status knnkm_server_submit(knnkm_server* srv, const knnkm_job* 
   J->req = *job;
   J->buf_bytes = job_buffer_bytes(job->n, job->d, job->k, job->params.kappa);
   const int64_t k0 = job->params.tau > 0 ? std::max<int64_t>(1, job->n / job->params.xi) : 0;
-  const int64_t alone = J->buf_bytes + ws_estimate(job->n, job->d, job->k, k0, 1, job->params.max_iters);
+  const int64_t alone = J->buf_bytes + ws_estimate(job->n, job->d, job->k, k0, job->params.kappa, 1, job->params.max_iters);
   J->info.footprint_bytes = alone;
   std::lock_guard<std::mutex> g(srv->mu);
   if (alone > srv->cfg.hbm_budget_bytes) {
