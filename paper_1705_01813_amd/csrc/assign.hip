@@ -54,37 +54,42 @@ __device__ inline double part64(const float (&x)[V], const float* __restrict__ c
 // Visit the distinct candidate labels of the group's sample in a fixed order
 // (first occurrence among entries 0..kappa, entry 0 = own label), calling
 // f(q) with a group-uniform q.
-template <int L, typename F>
-__device__ inline void for_each_cand(const int (&v)[MAX_SLOTS], const bool (&valid)[MAX_SLOTS], int S,
-                                     uint64_t gmask, F&& f) {
-  bool pend[MAX_SLOTS];
+template <int L, int SM, typename F>
+__device__ inline void for_each_cand(const int (&v)[SM], const bool (&valid)[SM], uint64_t gmask, F&& f) {
+  bool pend[SM];
 #pragma unroll
-  for (int s = 0; s < MAX_SLOTS; ++s) pend[s] = valid[s];
+  for (int s = 0; s < SM; ++s) pend[s] = valid[s];
   while (true) {
     int q = -1;
 #pragma unroll
-    for (int s = 0; s < MAX_SLOTS; ++s) {
-      if (s < S && q < 0) {
+    for (int s = 0; s < SM; ++s) {
+      if (q < 0) {
         const uint64_t m = __ballot(pend[s]) & gmask;
         if (m) q = __shfl(v[s], (int)__builtin_ctzll(m), 64);
       }
     }
     if (q < 0) break;
 #pragma unroll
-    for (int s = 0; s < MAX_SLOTS; ++s)
+    for (int s = 0; s < SM; ++s)
       if (pend[s] && v[s] == q) pend[s] = false;
     f(q);
   }
 }
 
-template <int L, int V>
+// One row group (L lanes) per sample, GS samples per group at a time: the
+// loads of each dependency level (sample ids; rows, own labels and graph
+// rows; neighbour labels) are issued for all GS samples before any is used,
+// so a wavefront keeps several sample rows in flight.  SM candidate slots
+// per lane (SM * L >= kappa + 1).
+template <int L, int V, int GS, int SM>
 __global__ __launch_bounds__(256) void k_assign(
     const float* __restrict__ X, int n, int d, int64_t ldx, const float* __restrict__ C, int k,
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
     float* __restrict__ best_out, unsigned long long* __restrict__ moved_acc,
-    const int* __restrict__ order, int dense, int nchunks, double rel, int S, int vec_x, int vec_c,
+    const int* __restrict__ order, int dense, int nchunks, double rel, int vec_x, int vec_c,
     const int* __restrict__ job_of, const int* __restrict__ kbase) {
-  constexpr int GW = 64 / L;  // samples per wavefront
+  constexpr int GW = 64 / L;           // samples per wavefront and pass
+  constexpr int PASS = 4 * GW * GS;    // samples per block and pass
   __shared__ unsigned int block_moved;
   if (threadIdx.x == 0) block_moved = 0;
   __syncthreads();
@@ -98,83 +103,111 @@ __global__ __launch_bounds__(256) void k_assign(
   if (chunk < nchunks) {
     const int64_t start = (int64_t)chunk * ASSIGN_PER_BLOCK;
     const int64_t end = min((int64_t)n, start + ASSIGN_PER_BLOCK);
-    for (int64_t idx = start + w * GW + g; idx < end; idx += 4 * GW) {
-      const int64_t i = order ? (int64_t)order[idx] : idx;
-      float x[V];
-      load_row<V>(x, X + i * ldx, j, d, vec_x);
-      const int cur = lab_in ? lab_in[i] : -1;
-      // clusters this sample may join: all of its job's when kappa covers them
-      int kb = 0, kc = k;
-      bool dense_i = dense;
-      if (job_of) {
-        const int q = job_of[i];
-        kb = kbase[q];
-        kc = kbase[q + 1] - kb;
-        dense_i = dense || kappa >= kc;
-      }
-      int cv[MAX_SLOTS];
-      bool valid[MAX_SLOTS];
+    for (int64_t base = start; base < end; base += PASS) {
+      int64_t ii[GS];
+      bool act[GS];
 #pragma unroll
-      for (int s = 0; s < MAX_SLOTS; ++s) {
-        const int e = j + L * s;
-        valid[s] = !dense_i && s < S && e <= kappa;
-        cv[s] = -1;
-        if (valid[s]) cv[s] = e == 0 ? cur : lab_in[G[i * kappa + (e - 1)]];
+      for (int p = 0; p < GS; ++p) {
+        const int64_t idx = base + w * GW + g + p * 4 * GW;
+        act[p] = idx < end;
+        ii[p] = act[p] ? (order ? (int64_t)order[idx] : idx) : 0;
       }
-
-      // pass 1: float32 distances, best and second best
-      float b1 = FLT_MAX, b2 = FLT_MAX;
-      int q1 = -1;
-      auto pass1 = [&](int q) {
-        const float dq = group_sum<L>(part32<V>(x, C + (int64_t)q * d, j, d, vec_c));
-        if (dq < b1 || (dq == b1 && q < q1)) {
-          if (q1 >= 0) b2 = fminf(b2, b1);
-          b1 = dq;
-          q1 = q;
+      float x[GS][V];
+      int cur[GS], kb[GS], kc[GS], nb[GS][SM];
+      bool dense_i[GS];
+#pragma unroll
+      for (int p = 0; p < GS; ++p) {
+        const int64_t i = ii[p];
+        if (act[p]) {
+          load_row<V>(x[p], X + i * ldx, j, d, vec_x);
         } else {
-          b2 = fminf(b2, dq);
+#pragma unroll
+          for (int e = 0; e < V; ++e) x[p][e] = 0.f;
         }
-      };
-      if (dense_i)
-        for (int q = kb; q < kb + kc; ++q) pass1(q);
-      else
-        for_each_cand<L>(cv, valid, S, gmask, pass1);
+        cur[p] = (act[p] && lab_in) ? lab_in[i] : -1;
+        kb[p] = 0;
+        kc[p] = k;
+        dense_i[p] = dense;
+        if (job_of && act[p]) {
+          const int q = job_of[i];
+          kb[p] = kbase[q];
+          kc[p] = kbase[q + 1] - kb[p];
+          dense_i[p] = dense || kappa >= kc[p];
+        }
+#pragma unroll
+        for (int s = 0; s < SM; ++s) {
+          const int e = j + L * s;
+          nb[p][s] = (act[p] && !dense_i[p] && e >= 1 && e <= kappa) ? G[i * kappa + (e - 1)] : -1;
+        }
+      }
+      int cv[GS][SM];
+      bool valid[GS][SM];
+#pragma unroll
+      for (int p = 0; p < GS; ++p)
+#pragma unroll
+        for (int s = 0; s < SM; ++s) {
+          const int e = j + L * s;
+          valid[p][s] = act[p] && !dense_i[p] && e <= kappa;
+          cv[p][s] = !valid[p][s] ? -1 : (e == 0 ? cur[p] : lab_in[nb[p][s]]);
+        }
 
-      const double thr = (double)b1 * (1.0 + rel) / (1.0 - rel) + 1e-30;
-      int result = q1;
-      float bestv = b1;
-      if ((double)b2 <= thr) {
-        // pass 2: float64 re-evaluation of every candidate inside the margin
-        double m64 = DBL_MAX, cur64 = -1.0;
-        int q64 = -1;
-        auto pass2 = [&](int q) {
-          const float* cr = C + (int64_t)q * d;
-          const float dq = group_sum<L>(part32<V>(x, cr, j, d, vec_c));
-          if ((double)dq <= thr) {
-            const double e = group_sum<L>(part64<V>(x, cr, j, d, vec_c));
-            if (q == cur) cur64 = e;
-            if (e < m64 || (e == m64 && q < q64)) {
-              m64 = e;
-              q64 = q;
-            }
+#pragma unroll
+      for (int p = 0; p < GS; ++p) {
+        if (!act[p]) continue;  // group-uniform
+        // pass 1: float32 distances, best and second best
+        float b1 = FLT_MAX, b2 = FLT_MAX;
+        int q1 = -1;
+        auto pass1 = [&](int q) {
+          const float dq = group_sum<L>(part32<V>(x[p], C + (int64_t)q * d, j, d, vec_c));
+          if (dq < b1 || (dq == b1 && q < q1)) {
+            if (q1 >= 0) b2 = fminf(b2, b1);
+            b1 = dq;
+            q1 = q;
+          } else {
+            b2 = fminf(b2, dq);
           }
         };
-        if (dense_i)
-          for (int q = kb; q < kb + kc; ++q) pass2(q);
+        if (dense_i[p])
+          for (int q = kb[p]; q < kb[p] + kc[p]; ++q) pass1(q);
         else
-          for_each_cand<L>(cv, valid, S, gmask, pass2);
-        if (cur >= 0 && cur64 >= 0.0 && cur64 == m64) {
-          result = cur;
-          bestv = (float)cur64;
-        } else {
-          result = q64;
-          bestv = (float)m64;
+          for_each_cand<L, SM>(cv[p], valid[p], gmask, pass1);
+
+        const double thr = (double)b1 * (1.0 + rel) / (1.0 - rel) + 1e-30;
+        int result = q1;
+        float bestv = b1;
+        if ((double)b2 <= thr) {
+          // pass 2: float64 re-evaluation of every candidate inside the margin
+          double m64 = DBL_MAX, cur64 = -1.0;
+          int q64 = -1;
+          auto pass2 = [&](int q) {
+            const float* cr = C + (int64_t)q * d;
+            const float dq = group_sum<L>(part32<V>(x[p], cr, j, d, vec_c));
+            if ((double)dq <= thr) {
+              const double e = group_sum<L>(part64<V>(x[p], cr, j, d, vec_c));
+              if (q == cur[p]) cur64 = e;
+              if (e < m64 || (e == m64 && q < q64)) {
+                m64 = e;
+                q64 = q;
+              }
+            }
+          };
+          if (dense_i[p])
+            for (int q = kb[p]; q < kb[p] + kc[p]; ++q) pass2(q);
+          else
+            for_each_cand<L, SM>(cv[p], valid[p], gmask, pass2);
+          if (cur[p] >= 0 && cur64 >= 0.0 && cur64 == m64) {
+            result = cur[p];
+            bestv = (float)cur64;
+          } else {
+            result = q64;
+            bestv = (float)m64;
+          }
         }
-      }
-      if (j == 0) {
-        lab_out[i] = result;
-        if (best_out) best_out[i] = bestv;
-        if (cur >= 0 && result != cur) my_moved++;
+        if (j == 0) {
+          lab_out[ii[p]] = result;
+          if (best_out) best_out[ii[p]] = bestv;
+          if (cur[p] >= 0 && result != cur[p]) my_moved++;
+        }
       }
     }
   }
@@ -185,16 +218,40 @@ __global__ __launch_bounds__(256) void k_assign(
   }
 }
 
-template <int L, int V>
+// samples per group and pass: enough to keep several rows in flight, within
+// the registers of GS rows of V floats
+#define ASSIGN_GS(L) ((L) <= 4 ? 1 : ((L) == 8 ? 2 : 4))
+
+template <int L, int V, int SM>
 static void launch_assign(knnkm_ctx* ctx, int grid, const float* X, int64_t n, int32_t d, int64_t ldx,
                           const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                           const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                           unsigned long long* acc, const int32_t* order, bool dense, int nchunks,
-                          double rel, int S, bool vec_x, bool vec_c, const int32_t* job_of,
-                          const int32_t* kbase) {
-  k_assign<L, V><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out,
-                                                best_d2, acc, order, dense ? 1 : 0, nchunks, rel, S,
-                                                vec_x ? 1 : 0, vec_c ? 1 : 0, job_of, kbase);
+                          double rel, bool vec_x, bool vec_c, const int32_t* job_of, const int32_t* kbase) {
+  constexpr int GS = ASSIGN_GS(L);
+  k_assign<L, V, GS, SM><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in,
+                                                        labels_out, best_d2, acc, order, dense ? 1 : 0, nchunks,
+                                                        rel, vec_x ? 1 : 0, vec_c ? 1 : 0, job_of, kbase);
+}
+
+template <int L, int V>
+static void launch_assign_sm(knnkm_ctx* ctx, int S, int grid, const float* X, int64_t n, int32_t d, int64_t ldx,
+                             const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
+                             const int32_t* labels_in, int32_t* labels_out, float* best_d2,
+                             unsigned long long* acc, const int32_t* order, bool dense, int nchunks,
+                             double rel, bool vec_x, bool vec_c, const int32_t* job_of, const int32_t* kbase) {
+#define LS(SS)                                                                                             \
+  launch_assign<L, V, SS>(ctx, grid, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
+                          order, dense, nchunks, rel, vec_x, vec_c, job_of, kbase)
+  if (S <= 1)
+    LS(1);
+  else if (S <= 2)
+    LS(2);
+  else if (S <= 4)
+    LS(4);
+  else
+    LS(8);
+#undef LS
 }
 
 knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
@@ -207,7 +264,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   const bool all_dense = dense;
   int L, V;
   pick_group(d, all_dense ? 1 : (kappa + 1 + MAX_SLOTS - 1) / MAX_SLOTS, &L, &V);
-  const int S = all_dense ? 0 : (kappa + 1 + L - 1) / L;
+  const int S = all_dense ? 1 : (kappa + 1 + L - 1) / L;
   const int nchunks = (int)((n + ASSIGN_PER_BLOCK - 1) / ASSIGN_PER_BLOCK);
   const int grid = ((nchunks + 7) / 8) * 8;
   // float32 evaluation: V products and sums per lane, log2(L) reduction
@@ -218,9 +275,9 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   const bool vec_x = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
   const bool vec_c = (d % 4 == 0) && ((uintptr_t)C % 16 == 0);
   unsigned long long* acc = (unsigned long long*)n_moved;
-#define LA(LL, VV)                                                                                        \
-  launch_assign<LL, VV>(ctx, grid, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
-                        order, dense, nchunks, rel, S, vec_x, vec_c, job_of, kbase)
+#define LA(LL, VV)                                                                                          \
+  launch_assign_sm<LL, VV>(ctx, S, grid, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
+                           order, dense, nchunks, rel, vec_x, vec_c, job_of, kbase)
   if (V == 4) {
     switch (L) {
       case 4: LA(4, 4); break;

@@ -4,21 +4,39 @@
 //  * label sort: stable LSD radix sort of sample ids by label (8-bit digits,
 //    1024 ids per block, per-wave match masks for stable ranks) giving the CSR
 //    partition offsets[k+1] / members[n] with ids ascending inside a cluster.
-//  * segmented sums: every cluster is cut into chunks of 256 members; one
-//    wavefront sums a chunk in float64 in member order (lane l owns dims
-//    l, l+64, ...); a second kernel adds the chunk partials of a cluster in
-//    chunk order, so the result is identical on every run.
+//  * segmented sums: every cluster is cut into chunks of 64 members; one
+//    wavefront sums a chunk in float64 (rows read as float4, 64/LR rows at a
+//    time with LR lanes per row; each lane adds its rows in member order and
+//    the row slots are combined by a fixed butterfly); a second kernel adds
+//    the chunk partials of a cluster in chunk order, so the result is
+//    identical on every run.
 //  * distortion: float64 per sample, fixed per-block order, fixed final sum.
 #include "common.h"
 
 #define RS_TILE 1024
-#define SEG_CHUNK 256
+#define SEG_CHUNK 64
 
 // ------------------------------------------------------------ label sort --
+// Cluster sizes.  Runs of equal labels inside a wavefront's 64 consecutive
+// samples are counted with one atomic (labels of cluster-ordered data come in
+// long runs).
 __global__ void k_label_hist(const int32_t* __restrict__ labels, int64_t n, int32_t* counts) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&counts[labels[i]], 1);
+  const int lane = threadIdx.x & 63;
+  for (int64_t base = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) - lane; base < n;
+       base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + lane;
+    const bool valid = i < n;
+    const int lab = valid ? labels[i] : -1;
+    const int prev = __shfl_up(lab, 1, 64);
+    const bool head = valid && (lane == 0 || lab != prev);
+    const uint64_t heads = __ballot(head);
+    const uint64_t alive = __ballot(valid);
+    if (head) {
+      const uint64_t later = lane == 63 ? 0ull : (heads >> (lane + 1));
+      const int run_end = later ? lane + 1 + (int)__builtin_ctzll(later) : 64 - (int)__builtin_clzll(alive);
+      atomicAdd(&counts[lab], run_end - lane);
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_rs_count(const int32_t* __restrict__ keys, int64_t n,
@@ -190,6 +208,73 @@ __global__ __launch_bounds__(256) void k_seg_partial(const float* __restrict__ X
   }
 }
 
+// Chunk sums with float4 row loads: LR lanes per row, RPW = 64/LR rows per
+// pass, Q float4 per lane and row; 8 passes of rows are requested before any
+// is added.
+template <int LR, int Q>
+__global__ __launch_bounds__(256) void k_seg_partial4(const float* __restrict__ X, int d, int64_t ldx,
+                                                      int32_t k, const int32_t* __restrict__ offsets,
+                                                      const int32_t* __restrict__ members,
+                                                      const int32_t* __restrict__ chunk_off,
+                                                      int64_t max_chunks, double* __restrict__ partial) {
+  constexpr int RPW = 64 / LR, B = 8;
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= max_chunks || c >= chunk_off[k]) return;
+  int lo = 0, hi = k;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (chunk_off[mid] <= c) lo = mid; else hi = mid;
+  }
+  const int r = lo;
+  const int64_t p0 = offsets[r] + (c - chunk_off[r]) * SEG_CHUNK;
+  const int64_t p1 = min((int64_t)offsets[r + 1], p0 + SEG_CHUNK);
+  const int sl = lane / LR, j = lane % LR;
+  double acc[Q][4];
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[q][e] = 0.0;
+  for (int64_t pb = p0; pb < p1; pb += RPW * B) {
+    float4 v[B][Q];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int64_t row = pb + sl + RPW * b;
+      const float* xr = row < p1 ? X + (int64_t)members[row] * ldx : nullptr;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int f = 4 * (j + LR * q);
+        v[b][q] = (xr && f < d) ? *reinterpret_cast<const float4*>(xr + f) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        acc[q][0] += (double)v[b][q].x;
+        acc[q][1] += (double)v[b][q].y;
+        acc[q][2] += (double)v[b][q].z;
+        acc[q][3] += (double)v[b][q].w;
+      }
+  }
+#pragma unroll
+  for (int o = LR; o < 64; o <<= 1)
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[q][e] += __shfl_xor(acc[q][e], o, 64);
+  if (sl == 0) {
+    double* out = partial + c * d;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int f = 4 * (j + LR * q);
+      if (f < d)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[f + e] = acc[q][e];
+    }
+  }
+}
+
 template <int T>
 __global__ __launch_bounds__(256) void k_seg_final(int d, int32_t k, const int32_t* __restrict__ counts,
                                                    const int32_t* __restrict__ chunk_off,
@@ -236,9 +321,30 @@ knnkm_status ks_segsum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   KNNKM_WS(ctx, partial, double, "seg_partial", max_chunks * d);
   const int T = (d + 63) / 64;
   const unsigned gp = (unsigned)((max_chunks + 3) / 4), gf = (unsigned)((k + 3) / 4);
-#define SEG(TT)                                                                                   \
-  k_seg_partial<TT><<<gp, 256, 0, ctx->stream>>>(X, d, ldx, k, offsets, members, cc, max_chunks, \
-                                                 partial);                                        \
+  const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+  if (vec) {
+    const int ql = d / 4;
+    int lr = 1;
+    while (lr < ql && lr < 64) lr <<= 1;
+#define SP4(LRR, QQ) \
+  k_seg_partial4<LRR, QQ><<<gp, 256, 0, ctx->stream>>>(X, d, ldx, k, offsets, members, cc, max_chunks, partial)
+    switch (lr) {
+      case 1: SP4(1, 1); break;
+      case 2: SP4(2, 1); break;
+      case 4: SP4(4, 1); break;
+      case 8: SP4(8, 1); break;
+      case 16: SP4(16, 1); break;
+      case 32: SP4(32, 1); break;
+      default:
+        if (ql <= 64) SP4(64, 1); else SP4(64, 2);
+        break;
+    }
+#undef SP4
+  }
+#define SEG(TT)                                                                                        \
+  if (!vec)                                                                                            \
+    k_seg_partial<TT><<<gp, 256, 0, ctx->stream>>>(X, d, ldx, k, offsets, members, cc, max_chunks,    \
+                                                   partial);                                           \
   k_seg_final<TT><<<gf, 256, 0, ctx->stream>>>(d, k, counts, cc, partial, C, sums, Iterm)
   switch (T) {
     case 1: SEG(1); break;
