@@ -218,9 +218,9 @@ __global__ __launch_bounds__(256) void k_assign(
   }
 }
 
-// samples per group and pass: enough to keep several rows in flight, within
-// the registers of GS rows of V floats
-#define ASSIGN_GS(L) ((L) <= 4 ? 1 : ((L) == 8 ? 2 : 4))
+// samples per group and pass: two rows of V floats in flight per group (more
+// registers lower the occupancy more than they add; measured at 1M x 128)
+#define ASSIGN_GS(L) 2
 
 template <int L, int V, int SM>
 static void launch_assign(knnkm_ctx* ctx, int grid, const float* X, int64_t n, int32_t d, int64_t ldx,
