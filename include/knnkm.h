@@ -282,16 +282,26 @@ const char* knnkm_server_last_error(void);
 /* Run every queued job to completion, stop the workers, free everything. */
 knnkm_status knnkm_server_destroy(knnkm_server* srv);
 
-/* Opt-in phase timing.  While enabled, knn_build and knn_kmeans_fit record
- * HIP events on the context stream around their phases (a few microseconds
- * of overhead per iteration).  knnkm_phase_times waits for those events and
- * writes up to `count` values (milliseconds unless noted), -1 where a phase
- * was not recorded:
+/* Replay of the fit iterations from a HIP graph (default on).  Without
+ * early stopping, knn_kmeans_fit and knnkm_fit_batched run the first two
+ * sweeps eagerly and capture two sweeps (assignment, update, distortion)
+ * once into a graph that is launched for the remaining pairs; results are the
+ * same with graphs on or off.  A capture that fails falls back to eager
+ * launches. */
+knnkm_status knnkm_enable_graphs(knnkm_ctx* ctx, int32_t on);
+
+/* Opt-in phase timing.  With on = 1, knn_build and knn_kmeans_fit record HIP
+ * events on the context stream around their phases (a few microseconds of
+ * overhead); with on = 2 they also record events around every assignment
+ * launch of the fit, whose sweeps then run eagerly (no graph).
+ * knnkm_phase_times waits for those events and writes up to `count` values
+ * (milliseconds unless noted), -1 where a phase was not recorded:
  *   out[0] last knn_build, start to end
- *   out[1] last knn_kmeans_fit initialisation (partition, means, E_0)
+ *   out[1] last knn_kmeans_fit initialisation (partition, means, E_0, the
+ *          working copy of the data in cluster order)
  *   out[2] last knn_kmeans_fit iterations (assign + update + distortion)
- *   out[3] sum of the knn_assign launches inside those iterations
- *   out[4] iterations timed (count), out[5] assignment launches timed (count) */
+ *   out[3] sum of the timed assignment launches of those iterations (on = 2)
+ *   out[4] iterations run (count), out[5] assignment launches timed (count) */
 knnkm_status knnkm_enable_timing(knnkm_ctx* ctx, int32_t on);
 knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t count);
 

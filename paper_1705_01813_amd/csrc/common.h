@@ -28,11 +28,17 @@ struct knnkm_ctx {
   // cached two-means tree metadata (depends on n and k only)
   struct TMPlan* tm_plan = nullptr;
   // opt-in phase timing (HIP events on the context stream)
-  bool timing = false;
+  int timing = 0;  // 1: phases; 2: also every assignment of the fit (sweeps run eagerly)
   std::vector<hipEvent_t> ev;  // pool
   int build_ev = -1;           // index of the build start event (end = +1)
   int fit_ev = -1;             // fit start, init end, iterations end = +0, +1, +2
   int assign_ev0 = -1, assign_n = 0;  // pairs around the assignment launches of the fit
+  int fit_iters = 0;                  // sweeps of the last fit
+  // fit iterations replayed from a captured HIP graph (captured on a private
+  // stream, launched on `stream`)
+  bool graphs = true;
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
 };
 // Event `i` of the context pool (created on first use); nullptr on failure.
 hipEvent_t knnkm_event(knnkm_ctx* ctx, int i);

@@ -20,6 +20,10 @@ void* knnkm_ws(knnkm_ctx* ctx, const char* name, size_t bytes) {
   if (bytes == 0) bytes = 8;
   knnkm_buf& b = ctx->ws[name];
   if (b.bytes >= bytes) return b.ptr;
+  if (ctx->capturing) {
+    knnkm_fail(ctx, KNNKM_ENOMEM, "workspace '%s' would grow inside a graph capture", name);
+    return nullptr;
+  }
   // Stream-ordered: the old buffer is released after the work already queued
   // on the context stream, and growth never waits for other streams.
   if (b.ptr) {
@@ -109,6 +113,7 @@ extern "C" knnkm_status knnkm_destroy(knnkm_ctx* ctx) {
   tm_plan_free(ctx->tm_plan);
   for (hipEvent_t e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return KNNKM_OK;
 }
@@ -164,11 +169,18 @@ hipEvent_t knnkm_event(knnkm_ctx* ctx, int i) {
   return ctx->ev[i];
 }
 
+extern "C" knnkm_status knnkm_enable_graphs(knnkm_ctx* ctx, int32_t on) {
+  if (!ctx) return KNNKM_EINVAL;
+  ctx->graphs = on != 0;
+  return KNNKM_OK;
+}
+
 extern "C" knnkm_status knnkm_enable_timing(knnkm_ctx* ctx, int32_t on) {
   if (!ctx) return KNNKM_EINVAL;
-  ctx->timing = on != 0;
+  ctx->timing = on < 0 ? 0 : (on > 2 ? 2 : on);
   ctx->build_ev = ctx->fit_ev = ctx->assign_ev0 = -1;
   ctx->assign_n = 0;
+  ctx->fit_iters = 0;
   return KNNKM_OK;
 }
 
@@ -193,7 +205,7 @@ extern "C" knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t c
       for (int j = 0; j < ctx->assign_n; ++j) s += ev_ms(ctx, ctx->assign_ev0 + 2 * j);
       v[3] = s;
     }
-    v[4] = ctx->fit_ev >= 0 ? (double)ctx->assign_n : 0.0;
+    v[4] = ctx->fit_ev >= 0 ? (double)ctx->fit_iters : 0.0;
     v[5] = (double)ctx->assign_n;
   }
   for (int i = 0; i < count && i < 6; ++i) out[i] = v[i];

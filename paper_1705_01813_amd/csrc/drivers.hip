@@ -100,6 +100,18 @@ __global__ void k_scatter_i32(const int32_t* __restrict__ src, const int32_t* __
     dst[perm[p]] = src[p];
 }
 
+// Per-iteration bookkeeping inside a captured fit: the moved count and the
+// distortions of iteration *it go to their slots, then *it advances.
+__global__ void k_fit_book(const int64_t* __restrict__ mv_slot, int64_t* __restrict__ moved,
+                           const double* __restrict__ tr_slot, double* __restrict__ trace, int m,
+                           int32_t* __restrict__ it) {
+  const int t = *it;
+  for (int q = threadIdx.x; q < m; q += blockDim.x) trace[(int64_t)t * m + q] = tr_slot[q];
+  if (threadIdx.x == 0) moved[t] = *mv_slot;
+  __syncthreads();
+  if (threadIdx.x == 0) *it = t + 1;
+}
+
 // ||x_i||^2 in float64, one wavefront per row.
 __global__ __launch_bounds__(256) void k_row_sq64(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
                                                   double* __restrict__ out) {
@@ -335,7 +347,6 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   k_range_sum<<<m, 256, 0, ctx->stream>>>(Iterm, k64, isum);
   k_trace_jobs<<<(m + 255) / 256, 256, 0, ctx->stream>>>(sxx, isum, J.n_off, m, trace_dev);
   KNNKM_TRY(knnkm_check(ctx, "fit initialisation"));
-  mark(3);
 
   // The sweeps run on a working copy of X (and of the graph) in the cluster
   // order of the initial partition: rows are then read as streams, and the
@@ -361,35 +372,107 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     k_permute_graph<<<grid_for(n * kappa, 256, 16384), 256, 0, ctx->stream>>>(G_ids, kappa, perm, inv, n, Gp);
   k_gather_i32<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(labels, perm, n, labp);
   KNNKM_TRY(knnkm_check(ctx, "fit working copy"));
+  mark(3);
 
+  // one sweep: assignment, update, distortion of every job
+  auto sweep = [&](const int32_t* cu, int32_t* nx, int64_t* mv) -> knnkm_status {
+    return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
+                     J.job_of, k32);
+  };
+  auto update = [&](const int32_t* nx, double* tr) -> knnkm_status {
+    KNNKM_TRY(ks_label_sort(ctx, nx, n, K, counts, off, mem));
+    KNNKM_TRY(ks_segsum(ctx, Xp, n, d, d, K, counts, off, mem, C, nullptr, Iterm));
+    k_range_sum<<<m, 256, 0, ctx->stream>>>(Iterm, k64, isum);
+    k_trace_jobs<<<(m + 255) / 256, 256, 0, ctx->stream>>>(sxx, isum, J.n_off, m, tr);
+    return knnkm_check(ctx, "fit iteration");
+  };
+  const bool time_all = ctx->timing >= 2;
   int32_t* cur = labp;
   int32_t* nxt = lab2;
   int it = 0;
-  for (int t = 1; t <= T; ++t) {
-    mark(6 + 2 * (t - 1));
-    KNNKM_TRY(ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cur, nxt, nullptr, moved + t, nullptr,
-                        m == 1 && all_dense, J.job_of, k32));
-    mark(7 + 2 * (t - 1));
-    if (ctx->timing) ctx->assign_n = t;
-    KNNKM_TRY(ks_label_sort(ctx, nxt, n, K, counts, off, mem));
-    KNNKM_TRY(ks_segsum(ctx, Xp, n, d, d, K, counts, off, mem, C, nullptr, Iterm));
-    k_range_sum<<<m, 256, 0, ctx->stream>>>(Iterm, k64, isum);
-    k_trace_jobs<<<(m + 255) / 256, 256, 0, ctx->stream>>>(sxx, isum, J.n_off, m, trace_dev + (int64_t)t * m);
-    KNNKM_TRY(knnkm_check(ctx, "fit iteration"));
+  auto eager = [&](int t) -> knnkm_status {
+    if (time_all) mark(6 + 2 * (t - 1));
+    KNNKM_TRY(sweep(cur, nxt, moved + t));
+    if (time_all) {
+      mark(7 + 2 * (t - 1));
+      ctx->assign_n = t;
+    }
+    KNNKM_TRY(update(nxt, trace_dev + (int64_t)t * m));
     std::swap(cur, nxt);
     it = t;
-    if (p->early_stop && m == 1) {
+    return KNNKM_OK;
+  };
+  const bool early = p->early_stop && m == 1;
+  // Iterations 1-2 run eagerly (they size every workspace buffer); without
+  // early stopping the rest replays a captured graph of two sweeps, whose
+  // bookkeeping kernel files the moved count and the distortions of each
+  // sweep under a device-side iteration counter.
+  int t = 1;
+  bool converged = false;
+  for (; t <= T && (early || t <= 2) && !converged; ++t) {
+    KNNKM_TRY(eager(t));
+    if (early) {
       int64_t mv = -1;
       KNNKM_HIP(ctx, hipMemcpyAsync(&mv, moved + t, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
       KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-      if (mv == 0) break;
+      converged = mv == 0;
     }
   }
+  if (!early && t + 1 <= T && ctx->graphs && !time_all) {
+    KNNKM_WS(ctx, book_it, int32_t, "fit_book_it", 1);
+    KNNKM_WS(ctx, mv_slot, int64_t, "fit_mv_slot", 1);
+    KNNKM_WS(ctx, tr_slot, double, "fit_tr_slot", m);
+    KNNKM_TRY(ks_fill_i32(ctx, book_it, 1, t));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool ok = true;
+    if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->cap_stream = nullptr;
+      ok = false;
+    }
+    if (ok) {
+      hipStream_t user = ctx->stream;
+      ctx->stream = ctx->cap_stream;
+      ok = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        ctx->capturing = true;
+        knnkm_status st = sweep(cur, nxt, mv_slot);
+        if (st == KNNKM_OK) st = update(nxt, tr_slot);
+        if (st == KNNKM_OK) {
+          k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
+          st = sweep(nxt, cur, mv_slot);
+        }
+        if (st == KNNKM_OK) st = update(cur, tr_slot);
+        if (st == KNNKM_OK) k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
+        ctx->capturing = false;
+        ok = hipStreamEndCapture(ctx->stream, &graph) == hipSuccess && st == KNNKM_OK && graph;
+      }
+      ctx->stream = user;
+      (void)hipGetLastError();
+      if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      (void)hipGetLastError();
+    }
+    if (ok) {
+      // pairs of sweeps; cur/nxt end where they started
+      for (; t + 1 <= T; t += 2) {
+        KNNKM_HIP(ctx, hipGraphLaunch(exec, ctx->stream));
+        it = t + 1;
+      }
+      KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    // a capture that could not be made leaves the remaining sweeps to the
+    // eager path below (same kernels, same results)
+  }
+  for (; t <= T && !converged; ++t) KNNKM_TRY(eager(t));
   mark(4);
   // labels back in the caller's numbering
   k_scatter_i32<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(cur, perm, n, labels);
   KNNKM_TRY(knnkm_check(ctx, "fit labels"));
   *iters_run = it;
+  ctx->fit_iters = it;
   return KNNKM_OK;
 }
 

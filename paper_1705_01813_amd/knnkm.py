@@ -24,7 +24,7 @@ EXPORTS = [
     "knnkm_default_params", "knnkm_workspace_bytes", "knn_assign", "centroid_update",
     "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
     "knn_kmeans_fit", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times",
-    "knnkm_fit_batched", "knnkm_server_create", "knnkm_server_submit", "knnkm_server_wait",
+    "knnkm_fit_batched", "knnkm_enable_graphs", "knnkm_server_create", "knnkm_server_submit", "knnkm_server_wait",
     "knnkm_server_stats_get", "knnkm_server_last_error", "knnkm_server_destroy",
 ]
 
@@ -134,6 +134,7 @@ def lib():
             "knnkm_rng_draw": [P, u64, u64, u64, i64, P],
             "knnkm_fit_batched": [P, P, i32, i64, i32, P, P, P, ctypes.POINTER(Params), P, P, P, P, P, P],
             "knnkm_enable_timing": [P, i32],
+            "knnkm_enable_graphs": [P, i32],
             "knnkm_phase_times": [P, P, i32],
             "knnkm_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)],
             "knnkm_server_submit": [P, ctypes.POINTER(Job), ctypes.POINTER(u64)],
@@ -342,8 +343,13 @@ def knnkm_fit_batched(ctx, X, n_off, ks, seeds, params, G_ids, G_d2, labels, C, 
     return trace
 
 
+def knnkm_enable_graphs(ctx, on=True):
+    _chk(ctx.handle, lib().knnkm_enable_graphs(ctx.handle, 1 if on else 0))
+
+
 def knnkm_enable_timing(ctx, on=True):
-    _chk(ctx.handle, lib().knnkm_enable_timing(ctx.handle, 1 if on else 0))
+    """on: False/0 off, True/1 phases, 2 phases and every fit assignment."""
+    _chk(ctx.handle, lib().knnkm_enable_timing(ctx.handle, int(on)))
 
 
 PHASES = ("build_ms", "fit_init_ms", "fit_iters_ms", "assign_ms", "iters", "assign_launches")

@@ -271,6 +271,43 @@ def test_fit_parity(ctx, init):
     assert (np.diff(tr) <= 1e-12 * tr[0]).all()
 
 
+def test_fit_graph_equals_eager(ctx):
+    """Sweeps 3..T replay a captured graph; every replay matches the eager
+    launches (odd T leaves one eager sweep after the pairs), with eager work
+    and synchronisations between the runs."""
+    n, d, k, kappa, T = 5000, 24, 70, 10, 9
+    say("fit graph vs eager", n, d, k, kappa, T)
+    X = dev(datagen.mixture(n, d, 70, seed=12))
+    G = dev(rand_graph(n, kappa, 5))
+    p = knnkm.default_params(kappa=kappa, max_iters=T, seed=3)
+
+    def run(graphs):
+        knnkm.knnkm_enable_graphs(ctx, graphs)
+        lab = torch.empty(n, dtype=torch.int32, device=DEV)
+        C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+        cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+        tr, it = knnkm.knn_kmeans_fit(ctx, X, k, G, p, lab, C, cnt)
+        return host(lab), host(C), host(cnt), tr, it
+
+    try:
+        ref = run(False)
+        for rep in range(3):
+            got = run(True)
+            for a, b in zip(ref[:4], got[:4]):
+                assert np.array_equal(a, b), rep
+            assert got[4] == ref[4] == T
+            # unrelated eager work on the same stream between replays (one
+            # more sweep from the final state, twice: deterministic)
+            Cd, Ld = torch.from_numpy(ref[1]).to(DEV), torch.from_numpy(ref[0]).to(DEV)
+            t1 = torch.empty(n, dtype=torch.int32, device=DEV)
+            t2 = torch.empty(n, dtype=torch.int32, device=DEV)
+            knnkm.knn_assign(ctx, X, Cd, G, Ld, t1)
+            knnkm.knn_assign(ctx, X, Cd, G, Ld, t2)
+            assert np.array_equal(host(t1), host(t2))
+    finally:
+        knnkm.knnkm_enable_graphs(ctx, True)
+
+
 # ----------------------------------------------------------------- batching --
 def _batch(sizes, d, seed):
     Xs = [datagen.mixture(nq, d, max(2, nq // 32), seed=seed + q) for q, nq in enumerate(sizes)]
@@ -320,6 +357,33 @@ def test_batch_equals_alone(ctx, init):
         assert np.array_equal(C[c0:c1], a_C), q
         assert np.array_equal(cnt[c0:c1], a_cnt), q
         assert np.array_equal(tr[q], a_tr), q
+
+
+def test_batch_graph_equals_eager(ctx):
+    sizes = [80, 400, 1200, 90]
+    d, kappa, T = 16, 8, 8
+    say("batch graph vs eager", sizes)
+    Xs, n_off, ks, seeds = _batch(sizes, d, seed=21)
+    X = dev(np.concatenate(Xs))
+    n, K = int(n_off[-1]), sum(ks)
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=2, max_iters=T)
+
+    def run(graphs):
+        knnkm.knnkm_enable_graphs(ctx, graphs)
+        out = [torch.empty((n, kappa), dtype=torch.int32, device=DEV),
+               torch.empty((n, kappa), dtype=torch.float32, device=DEV),
+               torch.empty(n, dtype=torch.int32, device=DEV),
+               torch.empty((K, d), dtype=torch.float32, device=DEV),
+               torch.empty(K, dtype=torch.int32, device=DEV)]
+        tr = knnkm.knnkm_fit_batched(ctx, X, n_off, ks, seeds, p, *out)
+        return [host(t) for t in out] + [tr]
+
+    try:
+        a, b = run(False), run(True)
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+    finally:
+        knnkm.knnkm_enable_graphs(ctx, True)
 
 
 def test_batch_matches_oracle(ctx):
