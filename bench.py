@@ -56,6 +56,69 @@ C5 = dict(rate=200.0, seconds=60.0, dims=(64, 128, 256), kappa=16, T=20, xi=50, 
           pool_rows=1_000_000)
 
 
+def precision_report(ctx, X, p, G_ids, G_d2, labels, C, trace, samples, seed, log):
+    """Quality of a precision-form result, against references computed with
+    plain PyTorch in float64 on the GPU (independent of the library's kernels):
+    recall@kappa of the graph on sampled rows against exact neighbours, the
+    relative error of the reported final distortion against the float64
+    distortion of the returned labels, and whether the FP32-screened build gives
+    the same graph as the BF16-screened one."""
+    import torch
+
+    from paper_1705_01813_amd import knnkm
+
+    n, d = X.shape
+    kappa = G_ids.shape[1]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    rows = torch.randint(0, n, (samples,), generator=g).to(X.device)
+    q = X[rows].double()
+    qn = (q * q).sum(1, keepdim=True)
+    best_d, best_i = None, None
+    step = 1 << 20
+    for s0 in range(0, n, step):
+        xb = X[s0:s0 + step].double()
+        dd = qn + (xb * xb).sum(1)[None, :] - 2.0 * (q @ xb.T)
+        ids = torch.arange(s0, s0 + xb.shape[0], device=X.device)
+        dd[ids[None, :] == rows[:, None]] = float("inf")
+        if best_d is None:
+            cd, ci = dd, ids[None, :].expand_as(dd)
+        else:
+            cd, ci = torch.cat([best_d, dd], 1), torch.cat([best_i, ids[None, :].expand_as(dd)], 1)
+        best_d, pos = torch.topk(cd, kappa, dim=1, largest=False)
+        best_i = torch.gather(ci, 1, pos)
+    got = G_ids[rows].long()
+    hits = sum(len(set(a.tolist()) & set(b.tolist())) for a, b in zip(got, best_i))
+    recall = hits / float(samples * kappa)
+    # distortion of the returned labels in float64 (means recomputed)
+    lab = labels.long()
+    k = C.shape[0]
+    sums = torch.zeros((k, d), dtype=torch.float64, device=X.device)
+    cnt = torch.bincount(lab, minlength=k).double()
+    for s0 in range(0, n, step):
+        sums.index_add_(0, lab[s0:s0 + step], X[s0:s0 + step].double())
+    means = sums / cnt.clamp(min=1)[:, None]
+    e = 0.0
+    for s0 in range(0, n, step):
+        diff = X[s0:s0 + step].double() - means[lab[s0:s0 + step]]
+        e += float((diff * diff).sum())
+    e /= n
+    log(f"precision report: recall@{kappa} {recall:.4f} on {samples} rows, E {trace[-1]:.9g} vs {e:.9g}")
+    # the same build with the FP32 screen
+    pf = knnkm.Params.from_buffer_copy(p)
+    pf.precision = knnkm.FP32
+    gi2 = torch.empty_like(G_ids)
+    gd2 = torch.empty_like(G_d2)
+    knnkm.knn_build(ctx, X, pf, gi2, gd2)
+    same = bool(torch.equal(gi2, G_ids) and torch.equal(gd2, G_d2))
+    del gi2, gd2
+    return {"recall_at_kappa_sampled": recall, "recall_rows": samples,
+            "distortion_reported": float(trace[-1]), "distortion_fp64_of_labels": e,
+            "distortion_rel_error": abs(float(trace[-1]) - e) / e,
+            "bf16_graph_equals_fp32_graph": same,
+            "reference": "plain PyTorch float64 on the GPU (exact neighbours of sampled rows; means and "
+                         "distortion of the returned labels)"}
+
+
 def measured_traffic(config):
     """HBM bytes per fit assignment launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a plain copy
@@ -372,10 +435,10 @@ def main():
     mean = {key: float(np.mean([ph[key] for ph in phases])) for key in phases[0]}
     iter_ms = mean["fit_iters_ms"] / max(1.0, mean["iters"])
     value = n / (iter_ms / 1000.0)
-    # kernel pass (after the timed steps): the same step with HIP events around
-    # every assignment launch of the fit, which then runs its sweeps eagerly
+    # kernel pass (after the timed steps): the fit again, with HIP events around
+    # every assignment launch, which then runs its sweeps eagerly
     knnkm.knnkm_enable_timing(ctx, 2)
-    step()
+    knnkm.knn_kmeans_fit(ctx, X, k, G_ids, p, labels, C, counts)
     kp = knnkm.knnkm_phase_times(ctx)
     knnkm.knnkm_enable_timing(ctx, 1)
     assign_ms = kp["assign_ms"] / max(1.0, kp["assign_launches"])
@@ -408,6 +471,8 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_assign,
                      "launches_timed": kp["assign_launches"]},
     }
+    if cfg["precision"] and not args.counters:
+        out["precision"] = precision_report(ctx, X, p, G_ids, G_d2, labels, C, trace, 64, args.seed, log)
     ctx.close()
     del X, G_ids, G_d2, labels, C, counts
     torch.cuda.empty_cache()

@@ -193,9 +193,12 @@ knnkm_status ks_graph_init(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d,
                            int32_t kappa, uint64_t seed, int32_t* G_ids, float* G_d2,
                            const int32_t* job_of = nullptr, const int64_t* n_off = nullptr,
                            const uint64_t* seeds = nullptr);
+// norms: float32 squared norms of the rows, or null (computed here)
 knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        const int32_t* labels, int32_t k, int32_t precision, int32_t* G_ids,
-                       float* G_d2, int32_t kappa);
+                       float* G_d2, int32_t kappa, const float* norms = nullptr);
+// float32 squared norms of the rows into out[n]
+knnkm_status ks_row_norms(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, float* out);
 // sum_i ||x_i - C_{labels[i]}||^2 * scale into *out (C null: sum of ||x_i||^2).
 knnkm_status ks_sqdist_sum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                            const float* C, const int32_t* labels, double* out, double scale);

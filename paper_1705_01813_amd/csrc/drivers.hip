@@ -273,6 +273,8 @@ static knnkm_status build_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
     KNNKM_WS(ctx, off, int32_t, "kb_offsets", (int64_t)K0 + 1);
     KNNKM_WS(ctx, mem, int32_t, "kb_members", n);
     KNNKM_WS(ctx, C, float, "kb_centroids", (int64_t)K0 * d);
+    KNNKM_WS(ctx, nrm, float, "kb_norms", n);
+    KNNKM_TRY(ks_row_norms(ctx, X, n, d, ldx, nrm));
     for (int t = 0; t < p->tau; ++t) {
       KNNKM_TRY(ks_twomeans_multi(ctx, X, d, ldx, J.n_host, k0, J.m > 1 ? J.seeds : nullptr, J.seed_host[0], t,
                                   p->bisect_iters, lab));
@@ -280,7 +282,7 @@ static knnkm_status build_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
       KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K0, counts, off, mem, C, nullptr, nullptr));
       KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, K0, G_ids, kappa, lab, lab2, nullptr, nullptr, mem,
                           J.m == 1 && all_dense, J.job_of, k0_32));
-      KNNKM_TRY(ks_refine(ctx, X, n, d, ldx, lab2, K0, p->precision, G_ids, G_d2, kappa));
+      KNNKM_TRY(ks_refine(ctx, X, n, d, ldx, lab2, K0, p->precision, G_ids, G_d2, kappa, nrm));
     }
   }
   mark(1);

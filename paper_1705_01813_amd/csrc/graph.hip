@@ -221,6 +221,14 @@ __device__ inline void stage_rows(float* __restrict__ xs, int ld, const float* _
   }
 }
 
+// Lane j of a row group reads the staged row in float4 chunks j, j + L, ...
+// (consecutive lanes, consecutive 16 bytes: no LDS bank conflicts).
+template <int L, int V>
+__device__ inline float4 row_chunk(const float* __restrict__ row, int j, int u, int dpad) {
+  const int c = 4 * (j + L * u);
+  return c < dpad ? *reinterpret_cast<const float4*>(row + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 // float32 squared norms of RB staged rows, one row group per row.
 template <int RB, int L, int V>
 __device__ inline void row_norms(const float* __restrict__ xs, int ld, int dpad, float* __restrict__ nrm) {
@@ -230,10 +238,12 @@ __device__ inline void row_norms(const float* __restrict__ xs, int ld, int dpad,
   for (int r = gid; r < RB; r += NG) {
     float a = 0.f;
 #pragma unroll
-    for (int e = 0; e < V; ++e) {
-      const int t = j * V + e;
-      const float v = t < dpad ? xs[r * ld + t] : 0.f;
-      a = fmaf(v, v, a);
+    for (int u = 0; u < V / 4; ++u) {
+      const float4 v = row_chunk<L, V>(xs + r * ld, j, u, dpad);
+      a = fmaf(v.x, v.x, a);
+      a = fmaf(v.y, v.y, a);
+      a = fmaf(v.z, v.z, a);
+      a = fmaf(v.w, v.w, a);
     }
     a = group_sum<L>(a);
     if (j == 0) nrm[r] = a;
@@ -371,12 +381,17 @@ __global__ __launch_bounds__(512) void k_refine_tile(const float* __restrict__ X
       const int r = rc / RB, c = rc % RB;
       double a = 0.0;
 #pragma unroll
-      for (int e = 0; e < V; ++e) {
-        const int t = j * V + e;
-        if (t < dpad) {
-          const double df = (double)xi[r * ld + t] - (double)xj[c * ld + t];
-          a = fma(df, df, a);
-        }
+      for (int u = 0; u < V / 4; ++u) {
+        const float4 p4 = row_chunk<L, V>(xi + r * ld, j, u, dpad);
+        const float4 q4 = row_chunk<L, V>(xj + c * ld, j, u, dpad);
+        double df = (double)p4.x - (double)q4.x;
+        a = fma(df, df, a);
+        df = (double)p4.y - (double)q4.y;
+        a = fma(df, df, a);
+        df = (double)p4.z - (double)q4.z;
+        a = fma(df, df, a);
+        df = (double)p4.w - (double)q4.w;
+        a = fma(df, df, a);
       }
       a = group_sum<L>(a);
       if (j == 0) km[rc] = (float)a;
@@ -387,6 +402,7 @@ __global__ __launch_bounds__(512) void k_refine_tile(const float* __restrict__ X
       float* rowk = rk + r * kappa;
       int32_t* rowi = ri + r * kappa;
       const float ck = lane < RB ? km[r * RB + lane] : FLT_MAX;
+      if (!__ballot(ck < FLT_MAX)) continue;  // no survivor for this row
       const int cid = lane < RB ? ids_j[lane] : -1;
       const float e0k = lane < kappa ? rowk[lane] : FLT_MAX;
       const int e0i = lane < kappa ? rowi[lane] : INT32_MAX;
@@ -441,6 +457,295 @@ __global__ __launch_bounds__(512) void k_refine_tile(const float* __restrict__ X
     const int64_t g = (int64_t)ids_i[r] * kappa + q;
     G_d2[g] = rk[e];
     G_ids[g] = ri[e];
+  }
+}
+
+// ------------------------------------------- large clusters: screen + merge --
+// Clusters larger than one tile are processed in two kernels per round.
+//  screen: one item per (cluster, row block I, column block J) of 64 x 64
+//    members, taken by a persistent grid.  The Gram block is accumulated on
+//    MFMA over 64-dimension slices staged in LDS; every pair whose lower bound
+//    passes the row's kappa-th distance at the start of the round is appended
+//    to the row's survivor slots (at most SC_CAP per row; a row with more
+//    survivors is compared with its whole cluster by the merge).
+//  merge: one wavefront per row with survivors: exact float64 distances of
+//    the survivors not yet in the row, merged into the row by (d2, id).
+// The merged row is the kappa smallest (d2, id) of the old row and the
+// cluster, whatever the order in which survivors were found, so the graph is
+// the same as with the one-block-per-tile kernel.
+#define SC_RB 64   // rows and columns per item
+#define SC_KC 64   // dimensions per staged slice
+#define SC_LD (SC_KC + 4)
+#define SC_CAP 64  // survivor slots per row and round
+
+__global__ void k_screen_items(const int32_t* __restrict__ counts, int32_t k, int lo, int hi, int32_t* items) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < k;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int s = counts[r];
+    const int t = (s + SC_RB - 1) / SC_RB;
+    items[r] = (s > lo && s <= hi) ? t * t : 0;
+  }
+}
+
+// float32 squared norms of all rows (the screening bound covers any
+// summation order of the d products)
+__global__ __launch_bounds__(256) void k_row_norms(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
+                                                   float* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+    float a = 0.f;
+    for (int t = lane; t < d; t += 64) a = fmaf(X[i * ldx + t], X[i * ldx + t], a);
+    a = wave_sum(a);
+    if (lane == 0) out[i] = a;
+  }
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_refine_screen(const float* __restrict__ X, int d, int64_t ldx, int dpad,
+                                                       int kappa, int32_t k, const int32_t* __restrict__ offsets,
+                                                       const int32_t* __restrict__ members,
+                                                       const int32_t* __restrict__ item_off,
+                                                       const float* __restrict__ nrm, float err_c, int vec,
+                                                       const float* __restrict__ G_d2, int32_t* __restrict__ cnt,
+                                                       int32_t* __restrict__ slots) {
+  __shared__ __align__(16) float xi[SC_RB * SC_LD];
+  __shared__ __align__(16) float xj[SC_RB * SC_LD];
+  __shared__ int32_t ids_i[SC_RB], ids_j[SC_RB];
+  __shared__ float thr[SC_RB], ni[SC_RB], nj[SC_RB];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t total = item_off[k];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    int lo = 0, hi = k;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (item_off[mid] <= item) lo = mid; else hi = mid;
+    }
+    const int cl = lo;
+    const int c0 = offsets[cl], s = offsets[cl + 1] - c0;
+    const int t = (s + SC_RB - 1) / SC_RB;
+    const int local = (int)(item - item_off[cl]);
+    const int i0 = (local / t) * SC_RB, j0 = (local % t) * SC_RB;
+    const int nr = min(SC_RB, s - i0), nc = min(SC_RB, s - j0);
+    __syncthreads();  // the previous item is done with the shared arrays
+    if (tid < SC_RB) {
+      const int id = tid < nr ? members[c0 + i0 + tid] : -1;
+      ids_i[tid] = id;
+      thr[tid] = id >= 0 ? G_d2[(int64_t)id * kappa + kappa - 1] : -FLT_MAX;
+      ni[tid] = id >= 0 ? nrm[id] : 0.f;
+    } else if (tid < 2 * SC_RB) {
+      const int q = tid - SC_RB;
+      const int id = q < nc ? members[c0 + j0 + q] : -1;
+      ids_j[q] = id;
+      nj[q] = id >= 0 ? nrm[id] : 0.f;
+    }
+    f4_t acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < dpad; k0 += SC_KC) {
+      __syncthreads();
+      // stage the slice [k0, k0 + SC_KC) of both row blocks (zero padded)
+      for (int e = tid; e < 2 * SC_RB * (SC_KC / 4); e += 256) {
+        const int side = e / (SC_RB * (SC_KC / 4));
+        const int rem = e - side * (SC_RB * (SC_KC / 4));
+        const int r = rem / (SC_KC / 4), c = 4 * (rem % (SC_KC / 4));
+        const int id = side ? ids_j[r] : ids_i[r];
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int col = k0 + c;
+        if (id >= 0) {
+          const float* row = X + (int64_t)id * ldx;
+          if (vec && col < d) {
+            v = *reinterpret_cast<const float4*>(row + col);
+          } else {
+            v.x = col < d ? row[col] : 0.f;
+            v.y = col + 1 < d ? row[col + 1] : 0.f;
+            v.z = col + 2 < d ? row[col + 2] : 0.f;
+            v.w = col + 3 < d ? row[col + 3] : 0.f;
+          }
+        }
+        *reinterpret_cast<float4*>((side ? xj : xi) + r * SC_LD + c) = v;
+      }
+      __syncthreads();
+      // wave w: tiles 16 x 16 of rows 16w..16w+15 and the 4 column tiles
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float* ar = xi + (16 * w + (lane & 15)) * SC_LD;
+        const float* br = xj + (16 * q + (lane & 15)) * SC_LD;
+        if (BF16) {
+#pragma unroll
+          for (int kk = 0; kk < SC_KC; kk += 32) {
+            bf8_t a, b;
+            const int kb = kk + 8 * (lane >> 4);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              a[e] = (__bf16)ar[kb + e];
+              b[e] = (__bf16)br[kb + e];
+            }
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int kk = 0; kk < SC_KC; kk += 4) {
+            const int c = kk + (lane >> 4);
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[c], br[c], acc[q], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // screen: lane holds rows 16w + 4(lane>>4) + e of column 16q + (lane&15)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 16 * q + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 16 * w + 4 * (lane >> 4) + e;
+        if (r < nr && c < nc && ids_i[r] != ids_j[c]) {
+          const float sn = ni[r] + nj[c];
+          const float lb = sn - 2.f * acc[q][e] - err_c * sn;
+          const float th = thr[r];
+          if (lb <= th + th * 0x1p-22f + 1e-30f) {
+            const int id = ids_i[r];
+            const int slot = atomicAdd(&cnt[id], 1);
+            if (slot < SC_CAP) slots[(int64_t)id * SC_CAP + slot] = ids_j[c];
+          }
+        }
+      }
+    }
+  }
+}
+
+// One wavefront per row with survivors; exact distances of 64/L candidates
+// at a time, one row group of L lanes each.
+template <int L>
+__global__ __launch_bounds__(256) void k_refine_merge(const float* __restrict__ X, int d, int64_t ldx, int kappa,
+                                                      const int32_t* __restrict__ labels,
+                                                      const int32_t* __restrict__ offsets,
+                                                      const int32_t* __restrict__ members, int64_t n,
+                                                      const int32_t* __restrict__ cnt,
+                                                      const int32_t* __restrict__ slots, int vec,
+                                                      int32_t* __restrict__ G_ids, float* __restrict__ G_d2) {
+  __shared__ float rks[4][KNNKM_MAX_KAPPA];
+  __shared__ int32_t ris[4][KNNKM_MAX_KAPPA];
+  __shared__ float kys[4][64];
+  constexpr int G = 64 / L;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane / L, j = lane % L;
+  float* rowk = rks[w];
+  int32_t* rowi = ris[w];
+  float* keys = kys[w];
+  for (int64_t i = blockIdx.x * 4 + w; i < n; i += (int64_t)gridDim.x * 4) {
+    const int c = cnt[i];
+    if (c == 0) continue;  // wave-uniform
+    for (int q = lane; q < kappa; q += 64) {
+      rowk[q] = G_d2[i * kappa + q];
+      rowi[q] = G_ids[i * kappa + q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const bool over = c > SC_CAP;
+    int64_t m0 = 0, total = c;
+    if (over) {
+      const int l = labels[i];
+      m0 = offsets[l];
+      total = offsets[l + 1] - m0;
+    }
+    const float* xr = X + i * ldx;
+    bool changed = false;
+    for (int64_t base = 0; base < total; base += 64) {
+      const int64_t tt = base + lane;
+      int cid = -1;
+      if (tt < total) cid = over ? members[m0 + tt] : slots[i * SC_CAP + tt];
+      if (cid == (int)i) cid = -1;
+      bool valid = cid >= 0;
+      if (!__ballot(valid)) continue;
+      const float e0k = lane < kappa ? rowk[lane] : FLT_MAX;
+      const int e0i = lane < kappa ? rowi[lane] : INT32_MAX;
+      const float e1k = lane + 64 < kappa ? rowk[lane + 64] : FLT_MAX;
+      const int e1i = lane + 64 < kappa ? rowi[lane + 64] : INT32_MAX;
+      for (int q = 0; q < kappa; ++q) {
+        const int qi = q < 64 ? __builtin_amdgcn_readlane(e0i, q) : __builtin_amdgcn_readlane(e1i, q - 64);
+        valid = valid && qi != cid;  // a visited pair is already in the row
+      }
+      uint64_t M = __ballot(valid);
+      if (!M) continue;
+      // exact float64 distances: group g takes the g-th pending candidate;
+      // lane j of the group reads float4 chunks j, j + L, ... of both rows
+      for (uint64_t rest = M; rest;) {
+        int q = -1;
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) {
+          if (rest) {
+            const int b = (int)__builtin_ctzll(rest);
+            rest &= rest - 1;
+            if (gg == g) q = b;
+          }
+        }
+        double a = 0.0;
+        const int jd = __shfl(cid, q < 0 ? 0 : q, 64);  // all lanes take part
+        if (q >= 0) {
+          const float* xc = X + (int64_t)jd * ldx;
+          if (vec) {
+            for (int c4 = 4 * j; c4 < d; c4 += 4 * L) {
+              const float4 p4 = *reinterpret_cast<const float4*>(xr + c4);
+              const float4 q4 = *reinterpret_cast<const float4*>(xc + c4);
+              double df = (double)p4.x - (double)q4.x;
+              a = fma(df, df, a);
+              df = (double)p4.y - (double)q4.y;
+              a = fma(df, df, a);
+              df = (double)p4.z - (double)q4.z;
+              a = fma(df, df, a);
+              df = (double)p4.w - (double)q4.w;
+              a = fma(df, df, a);
+            }
+          } else {
+            for (int t = j; t < d; t += L) {
+              const double df = (double)xr[t] - (double)xc[t];
+              a = fma(df, df, a);
+            }
+          }
+        }
+        a = group_sum<L>(a);
+        if (q >= 0 && j == 0) keys[q] = (float)a;
+      }
+      __builtin_amdgcn_wave_barrier();
+      const float ck = valid ? keys[lane] : FLT_MAX;
+      int pos_c = 0, add0 = 0, add1 = 0;
+      for (int q = 0; q < kappa; ++q) {
+        const float qk = q < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e0k), q))
+                                : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e1k), q - 64));
+        const int qi = q < 64 ? __builtin_amdgcn_readlane(e0i, q) : __builtin_amdgcn_readlane(e1i, q - 64);
+        pos_c += key_lt(qk, qi, ck, cid) ? 1 : 0;
+      }
+      while (M) {
+        const int q = (int)__builtin_ctzll(M);
+        M &= M - 1;
+        const float qk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ck), q));
+        const int qi = __builtin_amdgcn_readlane(cid, q);
+        pos_c += key_lt(qk, qi, ck, cid) ? 1 : 0;
+        add0 += key_lt(qk, qi, e0k, e0i) ? 1 : 0;
+        add1 += key_lt(qk, qi, e1k, e1i) ? 1 : 0;
+      }
+      changed = changed || __ballot(valid && pos_c < kappa);
+      __builtin_amdgcn_wave_barrier();
+      if (lane < kappa && lane + add0 < kappa) {
+        rowk[lane + add0] = e0k;
+        rowi[lane + add0] = e0i;
+      }
+      if (lane + 64 < kappa && lane + 64 + add1 < kappa) {
+        rowk[lane + 64 + add1] = e1k;
+        rowi[lane + 64 + add1] = e1i;
+      }
+      if (valid && pos_c < kappa) {
+        rowk[pos_c] = ck;
+        rowi[pos_c] = cid;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (changed) {
+      for (int q = lane; q < kappa; q += 64) {
+        G_d2[i * kappa + q] = rowk[q];
+        G_ids[i * kappa + q] = rowi[q];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -500,9 +805,14 @@ static knnkm_status launch_refine(knnkm_ctx* ctx, const float* X, int64_t n, int
   return knnkm_check(ctx, "graph refine (multi-tile clusters)");
 }
 
+knnkm_status ks_row_norms(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, float* out) {
+  k_row_norms<<<grid_for(n, 4, 16384), 256, 0, ctx->stream>>>(X, n, d, ldx, out);
+  return knnkm_check(ctx, "row norms");
+}
+
 knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        const int32_t* labels, int32_t k, int32_t precision, int32_t* G_ids,
-                       float* G_d2, int32_t kappa) {
+                       float* G_d2, int32_t kappa, const float* norms) {
   const int rb1 = pick_rb(d, true, kappa), rb2 = pick_rb(d, false, kappa);
   if (!rb1 || !rb2)
     return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "graph refine: d=%d with kappa=%d does not fit in LDS", d,
@@ -511,11 +821,23 @@ knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   KNNKM_WS(ctx, off, int32_t, "rf_offsets", (int64_t)k + 1);
   KNNKM_WS(ctx, mem, int32_t, "rf_members", n);
   KNNKM_WS(ctx, wb, int32_t, "rf_wb", (int64_t)k + 1);
+  KNNKM_WS(ctx, items, int32_t, "rf_items", (int64_t)k + 1);
+  KNNKM_WS(ctx, cnt, int32_t, "rf_survivor_counts", n);
+  KNNKM_WS(ctx, slots, int32_t, "rf_survivors", n * SC_CAP);
   KNNKM_TRY(ks_label_sort(ctx, labels, n, k, counts, off, mem));
   const int dpad = (d + 31) / 32 * 32;
-  k_row_blocks<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, rb1, rb2, wb);
+  // clusters of rb1 < s <= hi: screen + merge, with the item count within
+  // int32 (items <= t_max * (n / 64 + k)); larger ones: row blocks of the
+  // multi-tile kernel
+  const int64_t denom = n / SC_RB + k + 1;
+  const int64_t t_max = std::max<int64_t>(1, std::min<int64_t>(46340, INT32_MAX / denom));
+  const int hi = (int)std::min<int64_t>(t_max * SC_RB, INT32_MAX);
+  k_screen_items<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, rb1, hi, items);
+  k_row_blocks<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, hi, rb2, wb);
   KNNKM_TRY(knnkm_check(ctx, "refine blocks"));
+  KNNKM_TRY(ks_scan_exclusive(ctx, items, items, k, true));
   KNNKM_TRY(ks_scan_exclusive(ctx, wb, wb, k, true));
+  KNNKM_TRY(ks_fill_i32(ctx, cnt, n, 0));
   // Screening bound (squared-distance units, relative to ||x||^2 + ||y||^2):
   // twice the worst-case rounding of the float32 Gram, the float32 norms and
   // the final additions; plus the bfloat16 rounding of both operands.
@@ -524,8 +846,37 @@ knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   if (precision == KNNKM_BF16_RERANK) err += 2.0 * (0x1p-7 + 0x1p-15);
   const float err_c = (float)(2.0 * err);
   const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+  const float* nrm = norms;
+  if (!nrm) {
+    KNNKM_WS(ctx, own, float, "rf_norms", n);
+    KNNKM_TRY(ks_row_norms(ctx, X, n, d, ldx, own));
+    nrm = own;
+  }
+  const unsigned gs = (unsigned)std::max(1, ctx->num_cus * 8);
+  if (precision == KNNKM_BF16_RERANK)
+    k_refine_screen<true><<<gs, 256, 0, ctx->stream>>>(X, d, ldx, dpad, kappa, k, off, mem, items, nrm, err_c,
+                                                       vec ? 1 : 0, G_d2, cnt, slots);
+  else
+    k_refine_screen<false><<<gs, 256, 0, ctx->stream>>>(X, d, ldx, dpad, kappa, k, off, mem, items, nrm, err_c,
+                                                        vec ? 1 : 0, G_d2, cnt, slots);
+  KNNKM_TRY(knnkm_check(ctx, "graph refine screen"));
   int gL, gV;
   pick_group(d, 1, &gL, &gV);
+  {
+    const unsigned gm = (unsigned)grid_for(n, 4, 16384);
+#define RM(LL)                                                                                       \
+  k_refine_merge<LL><<<gm, 256, 0, ctx->stream>>>(X, d, ldx, kappa, labels, off, mem, n, cnt, slots, \
+                                                  vec ? 1 : 0, G_ids, G_d2)
+    switch (gL) {
+      case 4: RM(4); break;
+      case 8: RM(8); break;
+      case 16: RM(16); break;
+      case 32: RM(32); break;
+      default: RM(64); break;
+    }
+#undef RM
+  }
+  KNNKM_TRY(knnkm_check(ctx, "graph refine merge"));
 #define RF(BF, LL, VV)                                                                                    \
   return launch_refine<BF, LL, VV>(ctx, X, n, d, ldx, dpad, kappa, k, off, mem, wb, rb1, rb2, err_c, vec, \
                                    G_ids, G_d2)

@@ -48,6 +48,7 @@ int64_t ws_estimate(int64_t n, int64_t d, int64_t k, int64_t k0, int64_t kappa, 
   const int64_t kx = std::max(k, k0);
   int64_t b = 0;
   b += 100 * n;                              // per-row int32/int64/double buffers
+  b += (12 + 4 * 64) * n;                    // refinement survivors, their counts and row norms
   b += (4 * d + 4 * kappa + 16) * n;         // the fit's cluster-ordered copy of X and the graph
   b += 8 * d * (n / 64 + kx + 2);            // segmented-sum partials
   b += 4 * d * k0;                           // graph-construction centroids
