@@ -104,7 +104,7 @@ struct knnkm_server {
     knnkm_ctx* ctx = nullptr;
     hipStream_t stream = nullptr;
     bool busy = false;
-    int64_t ws_charged = 0;  // workspace bytes charged to the budget
+    int64_t ws_charged = 0;  // workspace the worker keeps between batches (its actual size)
     std::thread th;
   };
   std::vector<Slot> slots;
@@ -125,7 +125,7 @@ struct knnkm_server {
     };
     auto need = [&](int64_t r, int64_t by, int64_t kk, int64_t kk0, int64_t m) {
       const int64_t ws = ws_estimate(r, head->req.d, kk, kk0, head->req.params.kappa, m, head->req.params.max_iters);
-      return by + std::max<int64_t>(0, ws - slots[s].ws_charged);
+      return by + ws;  // the kept workspace may all be replaced while the batch grows it
     };
     for (SJob* j : queue) {
       if (!same_class(j->req, head->req)) continue;
@@ -145,7 +145,7 @@ struct knnkm_server {
     }
     const int64_t ws = ws_estimate(rows, head->req.d, k, k0, head->req.params.kappa, (int64_t)B.size(),
                                    head->req.params.max_iters);
-    *extra_ws = std::max<int64_t>(0, ws - slots[s].ws_charged);
+    *extra_ws = ws;
     return B;
   }
 
@@ -282,12 +282,12 @@ void knnkm_server::worker(int s) {
     }
     ++next_batch;
     sl.busy = true;
-    sl.ws_charged += extra_ws;
     charge(bytes + extra_ws);
     st.queued = (int64_t)queue.size();
     st.running += (int64_t)B.size();
     st.max_batch_jobs_seen = std::max<int64_t>(st.max_batch_jobs_seen, (int64_t)B.size());
     const bool was_broken = broken;
+    const int64_t ws_before = sl.ws_charged;
     lk.unlock();
 
     knnkm_status r = was_broken ? KNNKM_EDEVICE : run_batch(sl, B);
@@ -297,12 +297,13 @@ void knnkm_server::worker(int s) {
     lk.lock();
     const double td = now_s(t0);
     if (r == KNNKM_EDEVICE) broken = true;
-    if (ws_now > sl.ws_charged) {
-      ++st.ws_overruns;
-      charge(ws_now - sl.ws_charged);
+    // from now on the worker's kept workspace is charged at its actual size
+    if (!dry && r != KNNKM_EDEVICE) {
+      if (ws_now > ws_before + extra_ws) ++st.ws_overruns;
+      st.bytes_in_use += ws_now - sl.ws_charged;
       sl.ws_charged = ws_now;
     }
-    st.bytes_in_use -= bytes;
+    st.bytes_in_use -= bytes + extra_ws;
     sl.busy = false;
     ++st.batches;
     st.running -= (int64_t)B.size();
