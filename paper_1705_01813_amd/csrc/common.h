@@ -202,5 +202,16 @@ knnkm_status ks_row_norms(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, 
 // sum_i ||x_i - C_{labels[i]}||^2 * scale into *out (C null: sum of ||x_i||^2).
 knnkm_status ks_sqdist_sum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                            const float* C, const int32_t* labels, double* out, double scale);
+// Incremental update of the fit (exact fixed-point composite vectors):
+// per-cluster scale exponents from each job's largest |x|; D from float64
+// sums; one sweep's moves applied to D, sizes and the changed clusters'
+// centroids and Eqn. 2 terms.
+knnkm_status ks_fx_scales(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int m,
+                          const int64_t* n_off, const int32_t* k_off, int32_t K, int32_t* cs);
+knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32_t d, const int32_t* cs,
+                            uint64_t* D);
+knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, const int32_t* cur,
+                          const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
+                          int32_t* dirty, float* C, double* Iterm);
 knnkm_status ks_fill_i64(knnkm_ctx* ctx, int64_t* p, int64_t count, int64_t v);
 knnkm_status ks_fill_i32(knnkm_ctx* ctx, int32_t* p, int64_t count, int32_t v);

@@ -345,10 +345,19 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   k_row_sq64<<<grid_for(n, 4, 16384), 256, 0, ctx->stream>>>(X, n, d, ldx, rowsq);
   k_range_sum<<<m, 256, 0, ctx->stream>>>(rowsq, J.n_off, sxx);
   KNNKM_TRY(ks_label_sort(ctx, labels, n, K, counts, off, mem));
-  KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K, counts, off, mem, C, nullptr, Iterm));
+  KNNKM_WS(ctx, sums0, double, "fit_sums0", (int64_t)K * d);
+  KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K, counts, off, mem, C, sums0, Iterm));
   k_range_sum<<<m, 256, 0, ctx->stream>>>(Iterm, k64, isum);
   k_trace_jobs<<<(m + 255) / 256, 256, 0, ctx->stream>>>(sxx, isum, J.n_off, m, trace_dev);
   KNNKM_TRY(knnkm_check(ctx, "fit initialisation"));
+  // the sweeps update the composite vectors D_r incrementally (exact
+  // fixed point, one scale exponent per job)
+  KNNKM_WS(ctx, cs, int32_t, "fit_scale", K);
+  KNNKM_WS(ctx, Dfx, uint64_t, "fit_dfx", (int64_t)K * d * 2);
+  KNNKM_WS(ctx, dirty, int32_t, "fit_dirty", K);
+  KNNKM_TRY(ks_fx_scales(ctx, X, n, d, ldx, m, J.n_off, k32, K, cs));
+  KNNKM_TRY(ks_fx_from_f64(ctx, sums0, K, d, cs, Dfx));
+  KNNKM_TRY(ks_fill_i32(ctx, dirty, K, 0));
 
   // The sweeps run on a working copy of X (and of the graph) in the cluster
   // order of the initial partition: rows are then read as streams, and the
@@ -381,9 +390,8 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
                      J.job_of, k32);
   };
-  auto update = [&](const int32_t* nx, double* tr) -> knnkm_status {
-    KNNKM_TRY(ks_label_sort(ctx, nx, n, K, counts, off, mem));
-    KNNKM_TRY(ks_segsum(ctx, Xp, n, d, d, K, counts, off, mem, C, nullptr, Iterm));
+  auto update = [&](const int32_t* cu, const int32_t* nx, double* tr) -> knnkm_status {
+    KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty, C, Iterm));
     k_range_sum<<<m, 256, 0, ctx->stream>>>(Iterm, k64, isum);
     k_trace_jobs<<<(m + 255) / 256, 256, 0, ctx->stream>>>(sxx, isum, J.n_off, m, tr);
     return knnkm_check(ctx, "fit iteration");
@@ -399,7 +407,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       mark(7 + 2 * (t - 1));
       ctx->assign_n = t;
     }
-    KNNKM_TRY(update(nxt, trace_dev + (int64_t)t * m));
+    KNNKM_TRY(update(cur, nxt, trace_dev + (int64_t)t * m));
     std::swap(cur, nxt);
     it = t;
     return KNNKM_OK;
@@ -440,12 +448,12 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       if (ok) {
         ctx->capturing = true;
         knnkm_status st = sweep(cur, nxt, mv_slot);
-        if (st == KNNKM_OK) st = update(nxt, tr_slot);
+        if (st == KNNKM_OK) st = update(cur, nxt, tr_slot);
         if (st == KNNKM_OK) {
           k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
           st = sweep(nxt, cur, mv_slot);
         }
-        if (st == KNNKM_OK) st = update(cur, tr_slot);
+        if (st == KNNKM_OK) st = update(nxt, cur, tr_slot);
         if (st == KNNKM_OK) k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
         ctx->capturing = false;
         ok = hipStreamEndCapture(ctx->stream, &graph) == hipSuccess && st == KNNKM_OK && graph;

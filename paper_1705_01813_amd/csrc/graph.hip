@@ -7,9 +7,8 @@
 //   the row is ordered by (d2, id) through per-lane ranks.
 //
 // refine: the exhaustive comparison inside every cluster and the list
-//   update.  A cluster of at most 64 members is one tile handled by one
-//   512-thread block; a larger cluster is cut into blocks of 64 (32 for
-//   d > 256) rows, each walking the cluster's column blocks.  Per tile:
+//   update.  A cluster of at most 64 members (32 when d is large) is one tile
+//   handled by one 512-thread block:
 //     1. the samples are staged in LDS (float32, 16-byte aligned rows);
 //     2. the Gram block runs on MFMA (float32 16x16x4, or bfloat16 16x16x32
 //        in the precision form), 16 x 16 tiles spread over the 8 waves;
@@ -20,9 +19,13 @@
 //        LDS by row groups, rounded to float32);
 //     5. each row (one wave) drops survivors already in its list (visited
 //        pairs) and merges the rest by per-lane ranks, writing the graph row.
-//   Every row belongs to exactly one cluster, so rows are updated without
-//   atomics.  Both precisions produce the same graph: the screen only removes
-//   pairs that provably cannot enter.
+//   Larger clusters go through a screen over 64 x 64 member blocks and a
+//   per-row merge (below); clusters too large for that item count fall back
+//   to row blocks walking the cluster's column blocks.  Every row belongs to
+//   exactly one cluster, so rows are updated without atomics.  Both precisions
+//   produce the same graph: the screen only removes pairs that provably cannot
+//   enter, and a row's result is the kappa smallest (d2, id) of its old list
+//   and its cluster, independent of the order in which pairs are examined.
 #include <cfloat>
 
 #include "rowgroup.h"
@@ -153,8 +156,6 @@ __device__ inline bool key_lt(float ka, int ia, float kb, int ib) {
   return ka < kb || (ka == kb && ia < ib);
 }
 
-#define SMALL_CL 64  // clusters up to this size are one tile
-
 // LDS layout of a refine tile (byte offsets, regions laid end to end):
 //   xi [RB][ld] float rows, xj [RB][ld] (the same region when `single`),
 //   km [RB][RB] float exact keys, ni/nj/thr [RB] float, ids_i/ids_j [RB] int,
@@ -253,7 +254,7 @@ __device__ inline void row_norms(const float* __restrict__ xs, int ld, int dpad,
 // Exhaustive comparison inside clusters (Alg. 3 inner loops), one block of
 // 512 threads per (cluster, block of RB rows).  SINGLE: the whole cluster
 // (2 <= s <= RB) is one tile, its rows serve as both sides of the Gram block.
-// Otherwise (clusters larger than SMALL_CL) the block walks the cluster's
+// Otherwise (clusters too large for the screen items) the block walks the cluster's
 // column blocks of RB members.  Per (row block, column block):
 //   Gram on MFMA (16 x 16 tiles over 8 waves) -> screen against the rows'
 //   current kappa-th distance with a rigorous margin -> survivor list ->

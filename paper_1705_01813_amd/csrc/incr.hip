@@ -1,0 +1,224 @@
+// Incremental centroid update for the fit sweeps (Sec. 1 Lloyd update written
+// with the composite vectors D_r of Eqn. 2: a sample that moves from u to v
+// subtracts its row from D_u and adds it to D_v, as in the paper's own
+// update of D_u and D_v for a move).
+//
+// D_r is held per (cluster, dimension) as a 128-bit two's-complement fixed
+// point number, value * 2^s with one exponent s per job chosen from the
+// job's largest |x| so that no sum can overflow (n |x| 2^s < 2^125).  Adding
+// a float32 row value is exact (its 24-bit significand lands on integer bits
+// unless it is 2^71 times smaller than the job's largest value), and integer
+// additions are associative, so the sums are exact and independent of the
+// order in which the moves are applied (atomics in any order give the same
+// bits).  Only the moved samples are touched each sweep; a cluster whose
+// members changed gets C_r = float32(D_r / n_r) (rounded to float64 first)
+// and the Eqn. 2 term ||D_r||^2 / n_r.
+#include "common.h"
+
+// fixed-point value of a double times 2^s (truncated toward zero below the
+// last integer bit), as (hi, lo) two's complement
+__device__ inline void fx_of_double(double v, int s, uint64_t& hi, uint64_t& lo) {
+  hi = lo = 0;
+  if (v == 0.0) return;
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const int ex = (int)((b >> 52) & 0x7FF);
+  uint64_t mant = b & 0xFFFFFFFFFFFFFull;
+  int e;
+  if (ex == 0) {
+    e = -1074;
+  } else {
+    mant |= 1ull << 52;
+    e = ex - 1075;
+  }
+  const int sh = e + s;  // |v| 2^s = mant 2^sh, below 2^125 by the choice of s
+  uint64_t mh = 0, ml = 0;
+  if (sh >= 64) {
+    mh = mant << (sh - 64);
+  } else if (sh > 0) {
+    ml = mant << sh;
+    mh = mant >> (64 - sh);
+  } else if (sh == 0) {
+    ml = mant;
+  } else {
+    ml = -sh >= 64 ? 0 : (mant >> -sh);
+  }
+  if (b >> 63) {
+    ml = ~ml;
+    mh = ~mh;
+    ml += 1;
+    if (ml == 0) mh += 1;
+  }
+  hi = mh;
+  lo = ml;
+}
+
+__device__ inline void fx_neg(uint64_t& hi, uint64_t& lo) {
+  lo = ~lo;
+  hi = ~hi;
+  lo += 1;
+  if (lo == 0) hi += 1;
+}
+
+// Multi-word atomic add: the carry out of the low word is known from the
+// value the low-word atomic returns.
+__device__ inline void fx_atomic_add(uint64_t* p, uint64_t hi, uint64_t lo) {
+  if (lo) {
+    const uint64_t old = atomicAdd((unsigned long long*)p, (unsigned long long)lo);
+    if (old + lo < old) hi += 1;
+  }
+  if (hi) atomicAdd((unsigned long long*)(p + 1), (unsigned long long)hi);
+}
+
+// Round (hi, lo) * 2^-s to the nearest double (the top 64 significant bits
+// with a sticky bit for the rest, then one rounding).
+__device__ inline double fx_to_double(uint64_t hi, uint64_t lo, int s) {
+  const bool neg = (int64_t)hi < 0;
+  if (neg) fx_neg(hi, lo);
+  double m;
+  if (hi == 0) {
+    m = (double)lo;
+  } else {
+    const int lz = __clzll((long long)hi);
+    const int sh = 64 - lz;
+    uint64_t top = lz ? ((hi << lz) | (lo >> (64 - lz))) : hi;
+    const uint64_t rest = sh >= 64 ? lo : (lo & ((1ull << sh) - 1));
+    if (rest) top |= 1;  // sticky, 11 bits below the double's last place
+    m = ldexp((double)top, sh);
+  }
+  return ldexp(neg ? -m : m, -s);
+}
+
+// largest |x| of every row
+__global__ __launch_bounds__(256) void k_row_absmax(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
+                                                    float* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+    float a = 0.f;
+    for (int t = lane; t < d; t += 64) a = fmaxf(a, fabsf(X[i * ldx + t]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a = fmaxf(a, __shfl_xor(a, o, 64));
+    if (lane == 0) out[i] = a;
+  }
+}
+
+// scale exponent of every cluster from its job's largest |x|
+__global__ __launch_bounds__(256) void k_cluster_scale(const float* __restrict__ rowmax,
+                                                       const int64_t* __restrict__ n_off,
+                                                       const int32_t* __restrict__ k_off, int m, int32_t K,
+                                                       int32_t* __restrict__ cs) {
+  __shared__ float sh[256];
+  for (int q = blockIdx.x; q < m; q += gridDim.x) {
+    float a = 0.f;
+    for (int64_t i = n_off[q] + threadIdx.x; i < n_off[q + 1]; i += 256) a = fmaxf(a, rowmax[i]);
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + o]);
+      __syncthreads();
+    }
+    int e = 0;
+    if (sh[0] > 0.f) (void)frexpf(sh[0], &e);  // max |x| < 2^e
+    const int s = sh[0] > 0.f ? 94 - e : 0;
+    for (int r = k_off[q] + threadIdx.x; r < k_off[q + 1]; r += 256) cs[r] = s;
+    __syncthreads();
+  }
+}
+
+__global__ void k_fx_from_f64(const double* __restrict__ sums, int64_t kd, int d, const int32_t* __restrict__ cs,
+                              uint64_t* __restrict__ D) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kd; e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t hi, lo;
+    fx_of_double(sums[e], cs[e / d], hi, lo);
+    D[2 * e] = lo;
+    D[2 * e + 1] = hi;
+  }
+}
+
+// Every moved sample: its row out of D[old], into D[new]; sizes and dirty
+// flags of both clusters.  A wavefront scans 64 positions and then applies
+// its moved samples one at a time, lanes over the dimensions.
+__global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, int64_t n, int d,
+                                                  const int32_t* __restrict__ cur, const int32_t* __restrict__ nxt,
+                                                  const int32_t* __restrict__ cs, uint64_t* __restrict__ D,
+                                                  int32_t* __restrict__ counts, int32_t* __restrict__ dirty) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+    const int64_t p = base + lane;
+    int a = -1, b = -1;
+    if (p < n) {
+      a = cur[p];
+      b = nxt[p];
+    }
+    const bool moved = p < n && a != b;
+    if (moved) {
+      atomicAdd(&counts[a], -1);
+      atomicAdd(&counts[b], 1);
+      dirty[a] = 1;
+      dirty[b] = 1;
+    }
+    for (uint64_t M = __ballot(moved); M; M &= M - 1) {
+      const int q = (int)__builtin_ctzll(M);
+      const int from = __shfl(a, q, 64), to = __shfl(b, q, 64);
+      const int s = cs[to];  // both clusters belong to the sample's job
+      const float* row = X + (base + q) * (int64_t)d;
+      for (int t = lane; t < d; t += 64) {
+        uint64_t hi, lo;
+        fx_of_double((double)row[t], s, hi, lo);
+        fx_atomic_add(D + 2 * ((int64_t)to * d + t), hi, lo);
+        fx_neg(hi, lo);
+        fx_atomic_add(D + 2 * ((int64_t)from * d + t), hi, lo);
+      }
+    }
+  }
+}
+
+// Clusters whose members changed: centroid (unchanged when empty) and the
+// Eqn. 2 term; one wavefront per cluster.
+__global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict__ D, int32_t K, int d,
+                                                     const int32_t* __restrict__ cs,
+                                                     const int32_t* __restrict__ counts, int32_t* __restrict__ dirty,
+                                                     float* __restrict__ C, double* __restrict__ Iterm) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < K; r += (int64_t)gridDim.x * 4) {
+    if (!dirty[r]) continue;  // wave-uniform
+    const int cnt = counts[r];
+    const int s = cs[r];
+    double sq = 0.0;
+    for (int t = lane; t < d; t += 64) {
+      const int64_t e = r * d + t;
+      const double v = fx_to_double(D[2 * e + 1], D[2 * e], s);
+      if (cnt > 0) C[e] = (float)(v / (double)cnt);
+      sq = fma(v, v, sq);
+    }
+    sq = wave_sum(sq);
+    if (lane == 0) {
+      Iterm[r] = cnt > 0 ? sq / (double)cnt : 0.0;
+      dirty[r] = 0;
+    }
+  }
+}
+
+knnkm_status ks_fx_scales(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int m,
+                          const int64_t* n_off, const int32_t* k_off, int32_t K, int32_t* cs) {
+  KNNKM_WS(ctx, rowmax, float, "fx_rowmax", n);
+  k_row_absmax<<<grid_for(n, 4, 16384), 256, 0, ctx->stream>>>(X, n, d, ldx, rowmax);
+  k_cluster_scale<<<std::min(m, 4096), 256, 0, ctx->stream>>>(rowmax, n_off, k_off, m, K, cs);
+  return knnkm_check(ctx, "fixed-point scales");
+}
+
+knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32_t d, const int32_t* cs,
+                            uint64_t* D) {
+  const int64_t kd = (int64_t)K * d;
+  k_fx_from_f64<<<grid_for(kd, 256, 16384), 256, 0, ctx->stream>>>(sums, kd, d, cs, D);
+  return knnkm_check(ctx, "fixed-point sums");
+}
+
+knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, const int32_t* cur,
+                          const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
+                          int32_t* dirty, float* C, double* Iterm) {
+  k_fx_moves<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty);
+  k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, dirty, C, Iterm);
+  return knnkm_check(ctx, "incremental update");
+}

@@ -56,6 +56,7 @@ int64_t ws_estimate(int64_t n, int64_t d, int64_t k, int64_t k0, int64_t kappa, 
   b += 16 * d * (n / 1024 + kx + 2);         // two-means tile partials
   b += 16 * d * (n / (1024 * 16) + kx + 2);  // two-means chunk partials
   b += 200 * (k + k0);                       // per-cluster tables and the tree plan
+  b += 24 * d * k + 4 * n;                   // fit: float64 sums and fixed-point composite vectors
   b += 64 * m + 16 * (T + 1) * m;            // job tables and traces
   b += 1 << 20;                              // scans, partial sums, small tables
   return b + b / 8 + (32 << 20);
