@@ -471,6 +471,7 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_assign,
                      "launches_timed": kp["assign_launches"]},
     }
+    out["autotuned_shapes"] = [ln for ln in knnkm.knnkm_autotune_table().splitlines() if ln]
     if cfg["precision"] and not args.counters:
         out["precision"] = precision_report(ctx, X, p, G_ids, G_d2, labels, C, trace, 64, args.seed, log)
     ctx.close()

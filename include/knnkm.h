@@ -290,6 +290,16 @@ knnkm_status knnkm_server_destroy(knnkm_server* srv);
  * launches. */
 knnkm_status knnkm_enable_graphs(knnkm_ctx* ctx, int32_t on);
 
+/* Autotuner of the assignment's launch shapes (default on): the first call
+ * with at least 65,536 samples for a given group shape and size bin times
+ * every candidate shape once (samples per row group and pass, samples per
+ * block) on that call's own data, synchronising the stream, and keeps the
+ * fastest for the process.  Every shape gives the same results. */
+knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on);
+/* The process-wide table of tuned shapes as text (one line per entry) into
+ * buf (len bytes, NUL-terminated, truncated); *needed gets the full size. */
+knnkm_status knnkm_autotune_table(char* buf, int64_t len, int64_t* needed);
+
 /* Opt-in phase timing.  With on = 1, knn_build and knn_kmeans_fit record HIP
  * events on the context stream around their phases (a few microseconds of
  * overhead); with on = 2 they also record events around every assignment

@@ -18,11 +18,15 @@
 //  * Samples are visited in the order given by `order` (the previous
 //    partition's members, so neighbouring groups share candidate centroids);
 //    blocks are remapped so that each XCD walks a contiguous range of it.
+#include <algorithm>
 #include <cfloat>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "rowgroup.h"
 
-#define ASSIGN_PER_BLOCK 64
 #define MAX_SLOTS 8
 
 template <int V>
@@ -86,7 +90,7 @@ __global__ __launch_bounds__(256) void k_assign(
     const float* __restrict__ X, int n, int d, int64_t ldx, const float* __restrict__ C, int k,
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
     float* __restrict__ best_out, unsigned long long* __restrict__ moved_acc,
-    const int* __restrict__ order, int dense, int nchunks, double rel, int vec_x, int vec_c,
+    const int* __restrict__ order, int dense, int nchunks, int pb, double rel, int vec_x, int vec_c,
     const int* __restrict__ job_of, const int* __restrict__ kbase) {
   constexpr int GW = 64 / L;           // samples per wavefront and pass
   constexpr int PASS = 4 * GW * GS;    // samples per block and pass
@@ -101,8 +105,8 @@ __global__ __launch_bounds__(256) void k_assign(
   const int chunk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   unsigned int my_moved = 0;
   if (chunk < nchunks) {
-    const int64_t start = (int64_t)chunk * ASSIGN_PER_BLOCK;
-    const int64_t end = min((int64_t)n, start + ASSIGN_PER_BLOCK);
+    const int64_t start = (int64_t)chunk * pb;
+    const int64_t end = min((int64_t)n, start + pb);
     for (int64_t base = start; base < end; base += PASS) {
       int64_t ii[GS];
       bool act[GS];
@@ -218,31 +222,47 @@ __global__ __launch_bounds__(256) void k_assign(
   }
 }
 
-// samples per group and pass: two rows of V floats in flight per group (more
-// registers lower the occupancy more than they add; measured at 1M x 128)
-#define ASSIGN_GS(L) 2
+// Launch shapes (GS samples per row group and pass, pb samples per block).
+// Every shape gives the same results: a sample's arithmetic depends on (L, V)
+// only.  The default, two samples per group and 64 per block, was measured
+// best at 1M x 128; the autotuner below times the candidates on the first
+// large call of each (group shape, size bin) and keeps the fastest.
+struct AssignCfg {
+  int gs = 2, pb = 64;
+};
+static const AssignCfg kAssignCandidates[] = {{1, 64}, {2, 64}, {4, 64}, {1, 128}, {2, 128}, {4, 128}};
 
 template <int L, int V, int SM>
-static void launch_assign(knnkm_ctx* ctx, int grid, const float* X, int64_t n, int32_t d, int64_t ldx,
+static void launch_assign(knnkm_ctx* ctx, AssignCfg cfg, const float* X, int64_t n, int32_t d, int64_t ldx,
                           const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                           const int32_t* labels_in, int32_t* labels_out, float* best_d2,
-                          unsigned long long* acc, const int32_t* order, bool dense, int nchunks,
-                          double rel, bool vec_x, bool vec_c, const int32_t* job_of, const int32_t* kbase) {
-  constexpr int GS = ASSIGN_GS(L);
-  k_assign<L, V, GS, SM><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in,
-                                                        labels_out, best_d2, acc, order, dense ? 1 : 0, nchunks,
-                                                        rel, vec_x ? 1 : 0, vec_c ? 1 : 0, job_of, kbase);
+                          unsigned long long* acc, const int32_t* order, bool dense, double rel, bool vec_x,
+                          bool vec_c, const int32_t* job_of, const int32_t* kbase) {
+  const int nchunks = (int)((n + cfg.pb - 1) / cfg.pb);
+  const int grid = ((nchunks + 7) / 8) * 8;
+#define LG(GG)                                                                                              \
+  k_assign<L, V, GG, SM><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in,  \
+                                                        labels_out, best_d2, acc, order, dense ? 1 : 0,     \
+                                                        nchunks, cfg.pb, rel, vec_x ? 1 : 0, vec_c ? 1 : 0, \
+                                                        job_of, kbase)
+  if (cfg.gs == 1)
+    LG(1);
+  else if (cfg.gs == 4)
+    LG(4);
+  else
+    LG(2);
+#undef LG
 }
 
 template <int L, int V>
-static void launch_assign_sm(knnkm_ctx* ctx, int S, int grid, const float* X, int64_t n, int32_t d, int64_t ldx,
-                             const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
+static void launch_assign_sm(knnkm_ctx* ctx, int S, AssignCfg cfg, const float* X, int64_t n, int32_t d,
+                             int64_t ldx, const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                              const int32_t* labels_in, int32_t* labels_out, float* best_d2,
-                             unsigned long long* acc, const int32_t* order, bool dense, int nchunks,
-                             double rel, bool vec_x, bool vec_c, const int32_t* job_of, const int32_t* kbase) {
-#define LS(SS)                                                                                             \
-  launch_assign<L, V, SS>(ctx, grid, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
-                          order, dense, nchunks, rel, vec_x, vec_c, job_of, kbase)
+                             unsigned long long* acc, const int32_t* order, bool dense, double rel, bool vec_x,
+                             bool vec_c, const int32_t* job_of, const int32_t* kbase) {
+#define LS(SS)                                                                                            \
+  launch_assign<L, V, SS>(ctx, cfg, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
+                          order, dense, rel, vec_x, vec_c, job_of, kbase)
   if (S <= 1)
     LS(1);
   else if (S <= 2)
@@ -252,6 +272,48 @@ static void launch_assign_sm(knnkm_ctx* ctx, int S, int grid, const float* X, in
   else
     LS(8);
 #undef LS
+}
+
+// Process-wide table of tuned shapes: key (device, L, V, slots, dense,
+// size bin) -> shape and its time.
+struct AssignTuned {
+  AssignCfg cfg;
+  float us = 0.f;
+};
+static std::mutex g_tune_mu;
+static std::map<uint64_t, AssignTuned> g_tuned;
+
+static uint64_t tune_key(int dev, int L, int V, int S, bool dense, int64_t n) {
+  int bin = 0;
+  while ((int64_t)1 << (bin + 1) <= n) ++bin;
+  return ((uint64_t)(dev & 0xFF) << 40) | ((uint64_t)L << 32) | ((uint64_t)V << 24) | ((uint64_t)S << 16) |
+         ((uint64_t)(dense ? 1 : 0) << 8) | (uint64_t)bin;
+}
+
+extern "C" knnkm_status knnkm_autotune_table(char* buf, int64_t len, int64_t* needed) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  std::string out;
+  for (auto& kv : g_tuned) {
+    char line[160];
+    const uint64_t k = kv.first;
+    snprintf(line, sizeof(line), "knn_assign device=%d L=%d V=%d slots=%d dense=%d n_bin=2^%d gs=%d pb=%d us=%.1f\n",
+             (int)((k >> 40) & 0xFF), (int)((k >> 32) & 0xFF), (int)((k >> 24) & 0xFF), (int)((k >> 16) & 0xFF),
+             (int)((k >> 8) & 0xFF), (int)(k & 0xFF), kv.second.cfg.gs, kv.second.cfg.pb, kv.second.us);
+    out += line;
+  }
+  if (buf && len > 0) {
+    const size_t m = std::min<size_t>(out.size(), (size_t)len - 1);
+    std::memcpy(buf, out.data(), m);
+    buf[m] = 0;
+  }
+  if (needed) *needed = (int64_t)out.size() + 1;
+  return KNNKM_OK;
+}
+
+extern "C" knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on) {
+  if (!ctx) return KNNKM_EINVAL;
+  ctx->autotune = on != 0;
+  return KNNKM_OK;
 }
 
 knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
@@ -265,8 +327,6 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   int L, V;
   pick_group(d, all_dense ? 1 : (kappa + 1 + MAX_SLOTS - 1) / MAX_SLOTS, &L, &V);
   const int S = all_dense ? 1 : (kappa + 1 + L - 1) / L;
-  const int nchunks = (int)((n + ASSIGN_PER_BLOCK - 1) / ASSIGN_PER_BLOCK);
-  const int grid = ((nchunks + 7) / 8) * 8;
   // float32 evaluation: V products and sums per lane, log2(L) reduction
   // levels, one rounding of each difference; twice the worst-case bound.
   int lv = 0;
@@ -275,9 +335,10 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   const bool vec_x = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
   const bool vec_c = (d % 4 == 0) && ((uintptr_t)C % 16 == 0);
   unsigned long long* acc = (unsigned long long*)n_moved;
-#define LA(LL, VV)                                                                                          \
-  launch_assign_sm<LL, VV>(ctx, S, grid, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
-                           order, dense, nchunks, rel, vec_x, vec_c, job_of, kbase)
+#define LA(LL, VV)                                                                                         \
+  launch_assign_sm<LL, VV>(ctx, S, cfg, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
+                           order, dense, rel, vec_x, vec_c, job_of, kbase)
+  auto launch = [&](AssignCfg cfg) {
   if (V == 4) {
     switch (L) {
       case 4: LA(4, 4); break;
@@ -295,7 +356,51 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
       default: LA(64, 8); break;
     }
   }
+  };
 #undef LA
+  // shape: tuned entry, else (large call, tuning allowed, not inside a
+  // graph capture) time every candidate once, else the default
+  const int Sb = S <= 1 ? 1 : (S <= 2 ? 2 : (S <= 4 ? 4 : 8));
+  const uint64_t key = tune_key(ctx->device, L, V, Sb, all_dense, n);
+  AssignCfg cfg;
+  bool found = false;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      cfg = it->second.cfg;
+      found = true;
+    }
+  }
+  if (!found && ctx->autotune && !ctx->capturing && n >= (1 << 16)) {
+    for (int q = 0; q < 2; ++q)
+      if (!ctx->tune_ev[q] && hipEventCreate(&ctx->tune_ev[q]) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->tune_ev[q] = nullptr;
+      }
+    hipEvent_t e0 = ctx->tune_ev[0], e1 = ctx->tune_ev[1];
+    if (e0 && e1) {
+      float best = 1e30f;
+      for (const AssignCfg& c : kAssignCandidates) {
+        if (n_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
+        KNNKM_HIP(ctx, hipEventRecord(e0, ctx->stream));
+        launch(c);
+        KNNKM_HIP(ctx, hipEventRecord(e1, ctx->stream));
+        KNNKM_TRY(knnkm_check(ctx, "knn_assign tuning"));
+        KNNKM_HIP(ctx, hipEventSynchronize(e1));
+        float ms = 0.f;
+        KNNKM_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          cfg = c;
+        }
+      }
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      g_tuned[key] = AssignTuned{cfg, best * 1000.f};
+      if (n_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
+    }
+  }
+  launch(cfg);
   return knnkm_check(ctx, "knn_assign");
 }
 

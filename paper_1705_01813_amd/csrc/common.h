@@ -37,6 +37,9 @@ struct knnkm_ctx {
   // fit iterations replayed from a captured HIP graph (captured on a private
   // stream, launched on `stream`)
   bool graphs = true;
+  // launch shapes of the assignment chosen by timing the candidates once
+  bool autotune = true;
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
   bool capturing = false;
   hipStream_t cap_stream = nullptr;
 };

@@ -114,6 +114,8 @@ extern "C" knnkm_status knnkm_destroy(knnkm_ctx* ctx) {
   for (hipEvent_t e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  for (hipEvent_t e : ctx->tune_ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
   return KNNKM_OK;
 }

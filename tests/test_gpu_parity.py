@@ -271,6 +271,37 @@ def test_fit_parity(ctx, init):
     assert (np.diff(tr) <= 1e-12 * tr[0]).all()
 
 
+def test_assign_autotune_same_result(ctx):
+    """The autotuner times every launch shape on the call's own data; the
+    results do not depend on the shape it keeps."""
+    n, d, k, kappa = 70000, 40, 700, 12
+    say("assign autotune", n, d, k, kappa)
+    X = dev(datagen.mixture(n, d, 700, seed=44))
+    G = dev(np.random.default_rng(9).integers(0, n, (n, kappa)).astype(np.int32))
+    C = dev(datagen.mixture(k, d, 700, seed=45))
+    lab0 = dev(np.random.default_rng(3).integers(0, k, n).astype(np.int32))
+
+    def run(tune):
+        knnkm.knnkm_autotune(ctx, tune)
+        out = torch.empty(n, dtype=torch.int32, device=DEV)
+        best = torch.empty(n, dtype=torch.float32, device=DEV)
+        mv = torch.zeros(1, dtype=torch.int64, device=DEV)
+        knnkm.knn_assign(ctx, X, C, G, lab0, out, best, mv)
+        return host(out), host(best), host(mv)
+
+    try:
+        a = run(False)
+        b = run(True)
+        c = run(True)
+        for u, v, w in zip(a, b, c):
+            assert np.array_equal(u, v) and np.array_equal(u, w)
+        table = knnkm.knnkm_autotune_table()
+        say("tuned", table.strip())
+        assert "knn_assign" in table and "n_bin=2^16" in table
+    finally:
+        knnkm.knnkm_autotune(ctx, True)
+
+
 def test_fit_graph_equals_eager(ctx):
     """Sweeps 3..T replay a captured graph; every replay matches the eager
     launches (odd T leaves one eager sweep after the pairs), with eager work
