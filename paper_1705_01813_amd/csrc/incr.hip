@@ -14,50 +14,7 @@
 // members changed gets C_r = float32(D_r / n_r) (rounded to float64 first)
 // and the Eqn. 2 term ||D_r||^2 / n_r.
 #include "common.h"
-
-// fixed-point value of a double times 2^s (truncated toward zero below the
-// last integer bit), as (hi, lo) two's complement
-__device__ inline void fx_of_double(double v, int s, uint64_t& hi, uint64_t& lo) {
-  hi = lo = 0;
-  if (v == 0.0) return;
-  const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const int ex = (int)((b >> 52) & 0x7FF);
-  uint64_t mant = b & 0xFFFFFFFFFFFFFull;
-  int e;
-  if (ex == 0) {
-    e = -1074;
-  } else {
-    mant |= 1ull << 52;
-    e = ex - 1075;
-  }
-  const int sh = e + s;  // |v| 2^s = mant 2^sh, below 2^125 by the choice of s
-  uint64_t mh = 0, ml = 0;
-  if (sh >= 64) {
-    mh = mant << (sh - 64);
-  } else if (sh > 0) {
-    ml = mant << sh;
-    mh = mant >> (64 - sh);
-  } else if (sh == 0) {
-    ml = mant;
-  } else {
-    ml = -sh >= 64 ? 0 : (mant >> -sh);
-  }
-  if (b >> 63) {
-    ml = ~ml;
-    mh = ~mh;
-    ml += 1;
-    if (ml == 0) mh += 1;
-  }
-  hi = mh;
-  lo = ml;
-}
-
-__device__ inline void fx_neg(uint64_t& hi, uint64_t& lo) {
-  lo = ~lo;
-  hi = ~hi;
-  lo += 1;
-  if (lo == 0) hi += 1;
-}
+#include "fixed128.h"
 
 // Multi-word atomic add: the carry out of the low word is known from the
 // value the low-word atomic returns.
@@ -67,25 +24,6 @@ __device__ inline void fx_atomic_add(uint64_t* p, uint64_t hi, uint64_t lo) {
     if (old + lo < old) hi += 1;
   }
   if (hi) atomicAdd((unsigned long long*)(p + 1), (unsigned long long)hi);
-}
-
-// Round (hi, lo) * 2^-s to the nearest double (the top 64 significant bits
-// with a sticky bit for the rest, then one rounding).
-__device__ inline double fx_to_double(uint64_t hi, uint64_t lo, int s) {
-  const bool neg = (int64_t)hi < 0;
-  if (neg) fx_neg(hi, lo);
-  double m;
-  if (hi == 0) {
-    m = (double)lo;
-  } else {
-    const int lz = __clzll((long long)hi);
-    const int sh = 64 - lz;
-    uint64_t top = lz ? ((hi << lz) | (lo >> (64 - lz))) : hi;
-    const uint64_t rest = sh >= 64 ? lo : (lo & ((1ull << sh) - 1));
-    if (rest) top |= 1;  // sticky, 11 bits below the double's last place
-    m = ldexp((double)top, sh);
-  }
-  return ldexp(neg ? -m : m, -s);
 }
 
 // largest |x| of every row
@@ -155,8 +93,8 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
     if (moved) {
       atomicAdd(&counts[a], -1);
       atomicAdd(&counts[b], 1);
-      dirty[a] = 1;
-      dirty[b] = 1;
+      atomicOr(&dirty[a], 1);
+      atomicOr(&dirty[b], 1);
     }
     for (uint64_t M = __ballot(moved); M; M &= M - 1) {
       const int q = (int)__builtin_ctzll(M);
@@ -195,7 +133,7 @@ __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict_
     sq = wave_sum(sq);
     if (lane == 0) {
       Iterm[r] = cnt > 0 ? sq / (double)cnt : 0.0;
-      dirty[r] = 0;
+      atomicExch(&dirty[r], 0);
     }
   }
 }

@@ -339,6 +339,46 @@ def test_fit_graph_equals_eager(ctx):
         knnkm.knnkm_enable_graphs(ctx, True)
 
 
+def test_fit_update_exact_at_scale(ctx):
+    """The incremental update at a size whose composite vectors (Eqn. 2,
+    k x d x 16 bytes of fixed point) far exceed the caches: every centroid is
+    the float32 rounding of its members' mean, every traced distortion is the
+    Eqn. 2 value of its partition, and two fits give the same bits."""
+    n, d, k, kappa, T = 2_000_000, 128, 200_000, 50, 4
+    say("fit update at scale", n, d, k, kappa, T)
+    X = datagen.mixture_device(n, d, k, 1234, centre="normal", sigma=0.5, device=DEV)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    p = knnkm.default_params(kappa=kappa, tau=2, max_iters=T, seed=1234, precision=knnkm.BF16_RERANK)
+    knnkm.knn_build(ctx, X, p, gi, gd)
+    sxx = sum(float((X[i:i + 250_000].double() ** 2).sum()) for i in range(0, n, 250_000))
+    runs = []
+    for rep in range(2):
+        lab = torch.empty(n, dtype=torch.int32, device=DEV)
+        C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+        cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+        tr, it = knnkm.knn_kmeans_fit(ctx, X, k, gi, p, lab, C, cnt)
+        assert it == T
+        s = torch.zeros((k, d), dtype=torch.float64, device=DEV)
+        s.index_add_(0, lab.long(), X.double())
+        c = torch.bincount(lab.long(), minlength=k)
+        assert torch.equal(c.int(), cnt)
+        nz = c > 0
+        mean = s[nz] / c[nz, None].double()
+        # float32 rounding of the mean: within half an ulp (the float64 sum
+        # here may itself be rounded, so a hair of slack)
+        ulp = torch.abs(mean.float()).double() * 2.0**-23 + 2.0**-149
+        err = torch.abs(C[nz].double() - mean)
+        assert bool((err <= 0.5 * ulp * (1 + 1e-6)).all()), float((err / ulp).max())
+        e_last = (sxx - float(((s[nz] ** 2).sum(1) / c[nz].double()).sum())) / n
+        assert abs(tr[-1] - e_last) <= 1e-12 * e_last, (tr[-1], e_last)
+        runs.append((host(lab), host(C), tr))
+        del s, mean, err, ulp
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[0][2], runs[1][2])
+
+
 # ----------------------------------------------------------------- batching --
 def _batch(sizes, d, seed):
     Xs = [datagen.mixture(nq, d, max(2, nq // 32), seed=seed + q) for q, nq in enumerate(sizes)]
