@@ -115,6 +115,11 @@ __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
   return v;
 }
+__device__ inline float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
 __device__ inline int lane_id() { return threadIdx.x & (WAVE - 1); }
 __device__ inline uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
 
@@ -209,8 +214,10 @@ knnkm_status ks_sqdist_sum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d,
 // per-cluster scale exponents from each job's largest |x|; D from float64
 // sums; one sweep's moves applied to D, sizes and the changed clusters'
 // centroids and Eqn. 2 terms.
-knnkm_status ks_fx_scales(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int m,
-                          const int64_t* n_off, const int32_t* k_off, int32_t K, int32_t* cs);
+knnkm_status ks_row_stats(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int m,
+                          const int32_t* job_of, double* rowsq, uint32_t* jmax);
+knnkm_status ks_fx_scales(knnkm_ctx* ctx, const uint32_t* jmax, int m, const int32_t* k_off, int32_t K,
+                          int32_t* cs);
 knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32_t d, const int32_t* cs,
                             uint64_t* D);
 knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, const int32_t* cur,

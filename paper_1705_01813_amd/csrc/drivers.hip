@@ -112,42 +112,46 @@ __global__ void k_fit_book(const int64_t* __restrict__ mv_slot, int64_t* __restr
   if (threadIdx.x == 0) *it = t + 1;
 }
 
-// ||x_i||^2 in float64, one wavefront per row.
-__global__ __launch_bounds__(256) void k_row_sq64(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
-                                                  double* __restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  for (int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
-    double a = 0.0;
-    for (int t = lane; t < d; t += 64) {
-      const double v = (double)X[i * ldx + t];
-      a = fma(v, v, a);
-    }
-    a = wave_sum(a);
-    if (lane == 0) out[i] = a;
-  }
-}
-
-// out[q] = sum of vals[off[q] .. off[q+1]) in a fixed order (one block per range).
-__global__ __launch_bounds__(256) void k_range_sum(const double* __restrict__ vals, const int64_t* __restrict__ off,
-                                                   double* __restrict__ out) {
-  __shared__ double sh[256];
-  const int q = blockIdx.x;
+// Sum of vals[off[q] .. off[q+1]) for every range q, one block per range:
+// thread t adds the elements t, t + 1024, ... of the range in index order,
+// then the block reduces in a fixed tree, so the result depends on the range
+// only (a job's sums are the same alone and in a batch).
+__device__ inline double block_range_sum(const double* __restrict__ vals, int64_t a, int64_t b) {
+  __shared__ double sh[16];
   double s = 0.0;
-  for (int64_t i = off[q] + threadIdx.x; i < off[q + 1]; i += 256) s += vals[i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
+  int64_t i = a + threadIdx.x;
+  for (; i + 7 * 1024 < b; i += 8 * 1024) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = vals[i + u * 1024];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
   }
-  if (threadIdx.x == 0) out[q] = sh[0];
+  for (; i < b; i += 1024) s += vals[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < 16; ++w) t += sh[w];
+  return t;  // valid in thread 0
 }
 
-// E_t of every job = (sum ||x||^2 - I) / n_q  (Eqn. 4 through the Eqn. 2 identity)
-__global__ void k_trace_jobs(const double* __restrict__ sxx, const double* __restrict__ isum,
-                             const int64_t* __restrict__ n_off, int m, double* __restrict__ dst) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < m) dst[q] = (sxx[q] - isum[q]) / (double)(n_off[q + 1] - n_off[q]);
+__global__ __launch_bounds__(1024) void k_range_sum(const double* __restrict__ vals, const int64_t* __restrict__ off,
+                                                    double* __restrict__ out) {
+  const int q = blockIdx.x;
+  const double s = block_range_sum(vals, off[q], off[q + 1]);
+  if (threadIdx.x == 0) out[q] = s;
+}
+
+// E of every job = (sum ||x||^2 - sum of the Eqn. 2 terms) / n_q (Eqn. 4
+// through the Eqn. 2 identity), the terms summed as in k_range_sum
+__global__ __launch_bounds__(1024) void k_range_trace(const double* __restrict__ Iterm, const int64_t* __restrict__ k_off,
+                                                      const double* __restrict__ sxx,
+                                                      const int64_t* __restrict__ n_off, double* __restrict__ dst) {
+  const int q = blockIdx.x;
+  const double s = block_range_sum(Iterm, k_off[q], k_off[q + 1]);
+  if (threadIdx.x == 0) dst[q] = (sxx[q] - s) / (double)(n_off[q + 1] - n_off[q]);
 }
 
 __global__ void k_local_labels(const int32_t* __restrict__ glab, const int32_t* __restrict__ job,
@@ -309,7 +313,6 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   KNNKM_WS(ctx, Iterm, double, "fit_iterm", K);
   KNNKM_WS(ctx, rowsq, double, "fit_rowsq", n);
   KNNKM_WS(ctx, sxx, double, "fit_sxx", m);
-  KNNKM_WS(ctx, isum, double, "fit_isum", m);
   KNNKM_WS(ctx, moved, int64_t, "fit_moved", (int64_t)T + 1);
   // phase events: 2 fit start, 3 initialisation done, 4 iterations done,
   // 6+2j / 7+2j around the assignment of iteration j+1
@@ -342,21 +345,20 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
                                 KNNKM_ROUND_FIT, p->bisect_iters, labels));
     KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)C, (int64_t)K * d, 0));
   }
-  k_row_sq64<<<grid_for(n, 4, 16384), 256, 0, ctx->stream>>>(X, n, d, ldx, rowsq);
-  k_range_sum<<<m, 256, 0, ctx->stream>>>(rowsq, J.n_off, sxx);
+  KNNKM_WS(ctx, jmax, uint32_t, "fit_jmax", m);
+  KNNKM_TRY(ks_row_stats(ctx, X, n, d, ldx, m, J.job_of, rowsq, jmax));
+  k_range_sum<<<m, 1024, 0, ctx->stream>>>(rowsq, J.n_off, sxx);
   KNNKM_TRY(ks_label_sort(ctx, labels, n, K, counts, off, mem));
   KNNKM_WS(ctx, sums0, double, "fit_sums0", (int64_t)K * d);
   KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K, counts, off, mem, C, sums0, Iterm));
-  k_range_sum<<<m, 256, 0, ctx->stream>>>(Iterm, k64, isum);
-  k_trace_jobs<<<(m + 255) / 256, 256, 0, ctx->stream>>>(sxx, isum, J.n_off, m, trace_dev);
+  k_range_trace<<<m, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, trace_dev);
   KNNKM_TRY(knnkm_check(ctx, "fit initialisation"));
   // the sweeps update the composite vectors D_r incrementally (exact
   // fixed point, one scale exponent per job)
   KNNKM_WS(ctx, cs, int32_t, "fit_scale", K);
   KNNKM_WS(ctx, Dfx, uint64_t, "fit_dfx", (int64_t)K * d * 2);
   KNNKM_WS(ctx, dirty, int32_t, "fit_dirty", K);
-  KNNKM_TRY(ks_fx_scales(ctx, X, n, d, ldx, m, J.n_off, k32, K, cs));
-  KNNKM_TRY(ks_fx_from_f64(ctx, sums0, K, d, cs, Dfx));
+  KNNKM_TRY(ks_fx_scales(ctx, jmax, m, k32, K, cs));
   KNNKM_TRY(ks_fill_i32(ctx, dirty, K, 0));
 
   // The sweeps run on a working copy of X (and of the graph) in the cluster
@@ -390,10 +392,19 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
                      J.job_of, k32);
   };
-  auto update = [&](const int32_t* cu, const int32_t* nx, double* tr) -> knnkm_status {
-    KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty, C, Iterm));
-    k_range_sum<<<m, 256, 0, ctx->stream>>>(Iterm, k64, isum);
-    k_trace_jobs<<<(m + 255) / 256, 256, 0, ctx->stream>>>(sxx, isum, J.n_off, m, tr);
+  // The first sweep moves a large share of the samples away from the
+  // initial partition: its update rebuilds the sums from a label sort and
+  // the segmented float64 sums (as at initialisation) and converts them to
+  // fixed point; later sweeps apply only their moves.
+  auto update = [&](const int32_t* cu, const int32_t* nx, double* tr, bool full) -> knnkm_status {
+    if (full) {
+      KNNKM_TRY(ks_label_sort(ctx, nx, n, K, counts, off, mem));
+      KNNKM_TRY(ks_segsum(ctx, Xp, n, d, d, K, counts, off, mem, C, sums0, Iterm));
+      KNNKM_TRY(ks_fx_from_f64(ctx, sums0, K, d, cs, Dfx));
+    } else {
+      KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty, C, Iterm));
+    }
+    k_range_trace<<<m, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, tr);
     return knnkm_check(ctx, "fit iteration");
   };
   const bool time_all = ctx->timing >= 2;
@@ -407,7 +418,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       mark(7 + 2 * (t - 1));
       ctx->assign_n = t;
     }
-    KNNKM_TRY(update(cur, nxt, trace_dev + (int64_t)t * m));
+    KNNKM_TRY(update(cur, nxt, trace_dev + (int64_t)t * m, t == 1));
     std::swap(cur, nxt);
     it = t;
     return KNNKM_OK;
@@ -448,12 +459,12 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       if (ok) {
         ctx->capturing = true;
         knnkm_status st = sweep(cur, nxt, mv_slot);
-        if (st == KNNKM_OK) st = update(cur, nxt, tr_slot);
+        if (st == KNNKM_OK) st = update(cur, nxt, tr_slot, false);
         if (st == KNNKM_OK) {
           k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
           st = sweep(nxt, cur, mv_slot);
         }
-        if (st == KNNKM_OK) st = update(nxt, cur, tr_slot);
+        if (st == KNNKM_OK) st = update(nxt, cur, tr_slot, false);
         if (st == KNNKM_OK) k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
         ctx->capturing = false;
         ok = hipStreamEndCapture(ctx->stream, &graph) == hipSuccess && st == KNNKM_OK && graph;

@@ -26,39 +26,60 @@ __device__ inline void fx_atomic_add(uint64_t* p, uint64_t hi, uint64_t lo) {
   if (hi) atomicAdd((unsigned long long*)(p + 1), (unsigned long long)hi);
 }
 
-// largest |x| of every row
-__global__ __launch_bounds__(256) void k_row_absmax(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
-                                                    float* __restrict__ out) {
+// Per-row statistics in one pass over X: ||x_i||^2 in float64 (the Eqn. 2
+// identity of the distortion) and the largest |x| of every job, as the bits
+// of a non-negative float (ordered like the floats, so an atomic max of the
+// bits is exact in any order).  A wavefront takes a contiguous run of rows,
+// so the job changes rarely within it.
+__global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
+                                                   const int32_t* __restrict__ job_of, double* __restrict__ rowsq,
+                                                   uint32_t* __restrict__ jmax) {
   const int lane = threadIdx.x & 63;
-  for (int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
-    float a = 0.f;
-    for (int t = lane; t < d; t += 64) a = fmaxf(a, fabsf(X[i * ldx + t]));
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) a = fmaxf(a, __shfl_xor(a, o, 64));
-    if (lane == 0) out[i] = a;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t per = (n + nwaves - 1) / nwaves;
+  const int64_t i0 = wave * per, i1 = min(n, i0 + per);
+  float mx = 0.f;
+  int job = -1;
+  for (int64_t i = i0; i < i1; ++i) {
+    const int q = job_of ? job_of[i] : 0;
+    if (q != job) {
+      if (job >= 0) {
+        const float w = wave_max(mx);
+        if (lane == 0) atomicMax(&jmax[job], __float_as_uint(w));
+      }
+      job = q;
+      mx = 0.f;
+    }
+    double a = 0.0;
+    for (int t = lane; t < d; t += 64) {
+      const float x = X[i * ldx + t];
+      mx = fmaxf(mx, fabsf(x));
+      a = fma((double)x, (double)x, a);
+    }
+    a = wave_sum(a);
+    if (lane == 0) rowsq[i] = a;
+  }
+  if (job >= 0) {
+    const float w = wave_max(mx);
+    if (lane == 0) atomicMax(&jmax[job], __float_as_uint(w));
   }
 }
 
-// scale exponent of every cluster from its job's largest |x|
-__global__ __launch_bounds__(256) void k_cluster_scale(const float* __restrict__ rowmax,
-                                                       const int64_t* __restrict__ n_off,
-                                                       const int32_t* __restrict__ k_off, int m, int32_t K,
-                                                       int32_t* __restrict__ cs) {
-  __shared__ float sh[256];
-  for (int q = blockIdx.x; q < m; q += gridDim.x) {
-    float a = 0.f;
-    for (int64_t i = n_off[q] + threadIdx.x; i < n_off[q + 1]; i += 256) a = fmaxf(a, rowmax[i]);
-    sh[threadIdx.x] = a;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + o]);
-      __syncthreads();
+// scale exponent of every cluster from its job's largest |x|: s = 94 - e
+// with max |x| < 2^e (0 for a job of zeros)
+__global__ void k_cluster_scale(const uint32_t* __restrict__ jmax, const int32_t* __restrict__ k_off, int m,
+                                int32_t K, int32_t* __restrict__ cs) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < K; r += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = m;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (k_off[mid] <= r) lo = mid; else hi = mid;
     }
+    const float mxv = __uint_as_float(jmax[lo]);
     int e = 0;
-    if (sh[0] > 0.f) (void)frexpf(sh[0], &e);  // max |x| < 2^e
-    const int s = sh[0] > 0.f ? 94 - e : 0;
-    for (int r = k_off[q] + threadIdx.x; r < k_off[q + 1]; r += 256) cs[r] = s;
-    __syncthreads();
+    if (mxv > 0.f) (void)frexpf(mxv, &e);
+    cs[r] = mxv > 0.f ? 94 - e : 0;
   }
 }
 
@@ -138,11 +159,16 @@ __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict_
   }
 }
 
-knnkm_status ks_fx_scales(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int m,
-                          const int64_t* n_off, const int32_t* k_off, int32_t K, int32_t* cs) {
-  KNNKM_WS(ctx, rowmax, float, "fx_rowmax", n);
-  k_row_absmax<<<grid_for(n, 4, 16384), 256, 0, ctx->stream>>>(X, n, d, ldx, rowmax);
-  k_cluster_scale<<<std::min(m, 4096), 256, 0, ctx->stream>>>(rowmax, n_off, k_off, m, K, cs);
+knnkm_status ks_row_stats(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int m,
+                          const int32_t* job_of, double* rowsq, uint32_t* jmax) {
+  KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)jmax, m, 0));
+  k_row_stats<<<grid_for(n, 64, 16384), 256, 0, ctx->stream>>>(X, n, d, ldx, job_of, rowsq, jmax);
+  return knnkm_check(ctx, "row statistics");
+}
+
+knnkm_status ks_fx_scales(knnkm_ctx* ctx, const uint32_t* jmax, int m, const int32_t* k_off, int32_t K,
+                          int32_t* cs) {
+  k_cluster_scale<<<grid_for(K, 256, 4096), 256, 0, ctx->stream>>>(jmax, k_off, m, K, cs);
   return knnkm_check(ctx, "fixed-point scales");
 }
 
