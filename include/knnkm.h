@@ -291,11 +291,18 @@ knnkm_status knnkm_server_destroy(knnkm_server* srv);
 knnkm_status knnkm_enable_graphs(knnkm_ctx* ctx, int32_t on);
 
 /* Autotuner of the assignment's launch shapes (default on): the first call
- * with at least 65,536 samples for a given group shape and size bin times
- * every candidate shape once (samples per row group and pass, samples per
- * block) on that call's own data, synchronising the stream, and keeps the
- * fastest for the process.  Every shape gives the same results. */
+ * with at least 65,536 samples for a given group shape, size bin and call
+ * site (a direct knn_assign call, a graph-construction round, the fit's first
+ * sweep, later fit sweeps) times every candidate shape once (samples per row
+ * group and pass, samples per block) on that call's own data, synchronising
+ * the stream, and keeps the fastest for the process.  Every shape gives the
+ * same results. */
 knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on);
+/* Fix the assignment's launch shape for this context (overrides the
+ * autotuner): gs samples per row group and pass (1, 2 or 4), pb samples per
+ * block (64 or 128); gs = 0 returns to the automatic choice.  Results do not
+ * depend on the shape.  KNNKM_EINVAL for any other combination. */
+knnkm_status knnkm_set_assign_shape(knnkm_ctx* ctx, int32_t gs, int32_t pb);
 /* The process-wide table of tuned shapes as text (one line per entry) into
  * buf (len bytes, NUL-terminated, truncated); *needed gets the full size. */
 knnkm_status knnkm_autotune_table(char* buf, int64_t len, int64_t* needed);

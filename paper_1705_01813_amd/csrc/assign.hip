@@ -283,11 +283,13 @@ struct AssignTuned {
 static std::mutex g_tune_mu;
 static std::map<uint64_t, AssignTuned> g_tuned;
 
-static uint64_t tune_key(int dev, int L, int V, int S, bool dense, int64_t n) {
+static const char* const kUseName[4] = {"call", "build", "fit1", "fit"};
+
+static uint64_t tune_key(int dev, int L, int V, int S, bool dense, int use, int64_t n) {
   int bin = 0;
   while ((int64_t)1 << (bin + 1) <= n) ++bin;
   return ((uint64_t)(dev & 0xFF) << 40) | ((uint64_t)L << 32) | ((uint64_t)V << 24) | ((uint64_t)S << 16) |
-         ((uint64_t)(dense ? 1 : 0) << 8) | (uint64_t)bin;
+         ((uint64_t)(use & 3) << 9) | ((uint64_t)(dense ? 1 : 0) << 8) | (uint64_t)bin;
 }
 
 extern "C" knnkm_status knnkm_autotune_table(char* buf, int64_t len, int64_t* needed) {
@@ -296,9 +298,11 @@ extern "C" knnkm_status knnkm_autotune_table(char* buf, int64_t len, int64_t* ne
   for (auto& kv : g_tuned) {
     char line[160];
     const uint64_t k = kv.first;
-    snprintf(line, sizeof(line), "knn_assign device=%d L=%d V=%d slots=%d dense=%d n_bin=2^%d gs=%d pb=%d us=%.1f\n",
+    snprintf(line, sizeof(line),
+             "knn_assign device=%d L=%d V=%d slots=%d dense=%d n_bin=2^%d use=%s gs=%d pb=%d us=%.1f\n",
              (int)((k >> 40) & 0xFF), (int)((k >> 32) & 0xFF), (int)((k >> 24) & 0xFF), (int)((k >> 16) & 0xFF),
-             (int)((k >> 8) & 0xFF), (int)(k & 0xFF), kv.second.cfg.gs, kv.second.cfg.pb, kv.second.us);
+             (int)((k >> 8) & 0x1), (int)(k & 0xFF), kUseName[(k >> 9) & 0x3], kv.second.cfg.gs, kv.second.cfg.pb,
+             kv.second.us);
     out += line;
   }
   if (buf && len > 0) {
@@ -316,11 +320,20 @@ extern "C" knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on) {
   return KNNKM_OK;
 }
 
+extern "C" knnkm_status knnkm_set_assign_shape(knnkm_ctx* ctx, int32_t gs, int32_t pb) {
+  if (!ctx) return KNNKM_EINVAL;
+  const bool ok = gs == 0 || ((gs == 1 || gs == 2 || gs == 4) && (pb == 64 || pb == 128));
+  if (!ok) return knnkm_fail(ctx, KNNKM_EINVAL, "set_assign_shape: gs=%d pb=%d is not a launch shape", gs, pb);
+  ctx->assign_gs = gs;
+  ctx->assign_pb = pb;
+  return KNNKM_OK;
+}
+
 knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                        int64_t* n_moved, const int32_t* order, bool dense, const int32_t* job_of,
-                       const int32_t* kbase) {
+                       const int32_t* kbase, int use) {
   if (n_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
   if (n == 0) return KNNKM_OK;
   const bool all_dense = dense;
@@ -361,10 +374,14 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   // shape: tuned entry, else (large call, tuning allowed, not inside a
   // graph capture) time every candidate once, else the default
   const int Sb = S <= 1 ? 1 : (S <= 2 ? 2 : (S <= 4 ? 4 : 8));
-  const uint64_t key = tune_key(ctx->device, L, V, Sb, all_dense, n);
+  const uint64_t key = tune_key(ctx->device, L, V, Sb, all_dense, use, n);
   AssignCfg cfg;
   bool found = false;
-  {
+  if (ctx->assign_gs > 0) {
+    cfg.gs = ctx->assign_gs;
+    cfg.pb = ctx->assign_pb;
+    found = true;
+  } else {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {

@@ -39,6 +39,7 @@ struct knnkm_ctx {
   bool graphs = true;
   // launch shapes of the assignment chosen by timing the candidates once
   bool autotune = true;
+  int assign_gs = 0, assign_pb = 64;  // forced assignment shape (gs = 0: automatic)
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   bool capturing = false;
   hipStream_t cap_stream = nullptr;
@@ -179,12 +180,14 @@ knnkm_status ks_segsum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        const int32_t* members, float* C, double* sums, double* Iterm);
 // Deterministic float64 sum of count values into *out (device).
 knnkm_status ks_sum_f64(knnkm_ctx* ctx, const double* in, int64_t count, double* out);
-// Assignment kernel launcher (order: optional visiting order of samples).
+// Assignment kernel launcher (order: optional visiting order of samples;
+// use: where the call comes from, a key of the tuned launch shapes).
+enum { KS_USE_CALL = 0, KS_USE_BUILD = 1, KS_USE_FIT_FIRST = 2, KS_USE_FIT = 3 };
 knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                        int64_t* n_moved, const int32_t* order, bool dense,
-                       const int32_t* job_of = nullptr, const int32_t* kbase = nullptr);
+                       const int32_t* job_of = nullptr, const int32_t* kbase = nullptr, int use = KS_USE_CALL);
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
                          int32_t* labels);

@@ -285,7 +285,7 @@ static knnkm_status build_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
       KNNKM_TRY(ks_label_sort(ctx, lab, n, K0, counts, off, mem));
       KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K0, counts, off, mem, C, nullptr, nullptr));
       KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, K0, G_ids, kappa, lab, lab2, nullptr, nullptr, mem,
-                          J.m == 1 && all_dense, J.job_of, k0_32));
+                          J.m == 1 && all_dense, J.job_of, k0_32, KS_USE_BUILD));
       KNNKM_TRY(ks_refine(ctx, X, n, d, ldx, lab2, K0, p->precision, G_ids, G_d2, kappa, nrm));
     }
   }
@@ -388,9 +388,9 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   mark(3);
 
   // one sweep: assignment, update, distortion of every job
-  auto sweep = [&](const int32_t* cu, int32_t* nx, int64_t* mv) -> knnkm_status {
+  auto sweep = [&](const int32_t* cu, int32_t* nx, int64_t* mv, bool first) -> knnkm_status {
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
-                     J.job_of, k32);
+                     J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT);
   };
   // The first sweep moves a large share of the samples away from the
   // initial partition: its update rebuilds the sums from a label sort and
@@ -413,7 +413,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   int it = 0;
   auto eager = [&](int t) -> knnkm_status {
     if (time_all) mark(6 + 2 * (t - 1));
-    KNNKM_TRY(sweep(cur, nxt, moved + t));
+    KNNKM_TRY(sweep(cur, nxt, moved + t, t == 1));
     if (time_all) {
       mark(7 + 2 * (t - 1));
       ctx->assign_n = t;
@@ -458,11 +458,11 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       ok = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
         ctx->capturing = true;
-        knnkm_status st = sweep(cur, nxt, mv_slot);
+        knnkm_status st = sweep(cur, nxt, mv_slot, false);
         if (st == KNNKM_OK) st = update(cur, nxt, tr_slot, false);
         if (st == KNNKM_OK) {
           k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
-          st = sweep(nxt, cur, mv_slot);
+          st = sweep(nxt, cur, mv_slot, false);
         }
         if (st == KNNKM_OK) st = update(nxt, cur, tr_slot, false);
         if (st == KNNKM_OK) k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);

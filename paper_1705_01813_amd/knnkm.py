@@ -24,7 +24,7 @@ EXPORTS = [
     "knnkm_default_params", "knnkm_workspace_bytes", "knn_assign", "centroid_update",
     "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
     "knn_kmeans_fit", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times",
-    "knnkm_fit_batched", "knnkm_enable_graphs", "knnkm_autotune", "knnkm_autotune_table",
+    "knnkm_fit_batched", "knnkm_enable_graphs", "knnkm_autotune", "knnkm_autotune_table", "knnkm_set_assign_shape",
     "knnkm_server_create", "knnkm_server_submit", "knnkm_server_wait",
     "knnkm_server_stats_get", "knnkm_server_last_error", "knnkm_server_destroy",
 ]
@@ -137,6 +137,7 @@ def lib():
             "knnkm_enable_timing": [P, i32],
             "knnkm_enable_graphs": [P, i32],
             "knnkm_autotune": [P, i32],
+            "knnkm_set_assign_shape": [P, i32, i32],
             "knnkm_autotune_table": [P, i64, ctypes.POINTER(i64)],
             "knnkm_phase_times": [P, P, i32],
             "knnkm_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)],
@@ -352,6 +353,11 @@ def knnkm_enable_graphs(ctx, on=True):
 
 def knnkm_autotune(ctx, on=True):
     _chk(ctx.handle, lib().knnkm_autotune(ctx.handle, 1 if on else 0))
+
+
+def knnkm_set_assign_shape(ctx, gs=0, pb=64):
+    """Fix the assignment's launch shape (gs = 0: automatic)."""
+    _chk(ctx.handle, lib().knnkm_set_assign_shape(ctx.handle, int(gs), int(pb)))
 
 
 def knnkm_autotune_table():

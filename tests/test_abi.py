@@ -110,3 +110,11 @@ def test_batched_validation(dry):
     assert call([0, 5, 200], [2, 5], [1, 2]) == knnkm.EINVAL       # job with fewer than kappa+1 rows
     assert call([0, 64, 200], [65, 5], [1, 2]) == knnkm.EINVAL     # k > n
     assert call([0, 64, 200], [0, 5], [1, 2]) == knnkm.EINVAL      # k < 1
+
+
+def test_assign_shape_validation(dry):
+    h = dry.handle
+    for gs, pb in [(1, 64), (2, 128), (4, 64), (4, 128), (0, 0)]:
+        assert _call("knnkm_set_assign_shape", h, gs, pb) == knnkm.OK, (gs, pb)
+    for gs, pb in [(8, 64), (3, 64), (2, 96), (-1, 64)]:
+        assert _call("knnkm_set_assign_shape", h, gs, pb) == knnkm.EINVAL, (gs, pb)

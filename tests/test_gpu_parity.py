@@ -302,6 +302,38 @@ def test_assign_autotune_same_result(ctx):
         knnkm.knnkm_autotune(ctx, True)
 
 
+SHAPES = [(1, 64), (2, 64), (4, 64), (1, 128), (2, 128), (4, 128)]
+
+
+@pytest.mark.parametrize("n,d,k,kappa", [(3001, 3, 60, 5), (5000, 32, 150, 20), (4099, 128, 90, 20),
+                                         (2500, 512, 40, 50), (3000, 24, 50, 40), (2000, 16, 30, 30)])
+def test_assign_shapes_same_bits(ctx, n, d, k, kappa):
+    """Every launch shape (samples per row group and pass, samples per block)
+    gives the same labels, best distances and moved count."""
+    say("assign shapes", n, d, k, kappa)
+    X = dev(datagen.mixture(n, d, k, seed=n + d))
+    C = dev(datagen.mixture(k, d, k, seed=7 * k))
+    G = dev(rand_graph(n, kappa, 3)) if kappa < k else None
+    lab = dev(np.random.default_rng(1).integers(0, k, n).astype(np.int32))
+    ref = None
+    try:
+        for gs, pb in SHAPES:
+            knnkm.knnkm_set_assign_shape(ctx, gs, pb)
+            out = torch.empty(n, dtype=torch.int32, device=DEV)
+            best = torch.empty(n, dtype=torch.float32, device=DEV)
+            mv = torch.zeros(1, dtype=torch.int64, device=DEV)
+            knnkm.knn_assign(ctx, X, C, G, lab, out, best_d2=best, n_moved=mv, kappa=kappa)
+            got = (host(out), host(best).view(np.uint32), int(host(mv)[0]))
+            if ref is None:
+                ref = got
+            else:
+                assert np.array_equal(got[0], ref[0]), (gs, pb)
+                assert np.array_equal(got[1], ref[1]), (gs, pb)
+                assert got[2] == ref[2], (gs, pb)
+    finally:
+        knnkm.knnkm_set_assign_shape(ctx, 0)
+
+
 def test_fit_graph_equals_eager(ctx):
     """Sweeps 3..T replay a captured graph; every replay matches the eager
     launches (odd T leaves one eager sweep after the pairs), with eager work
