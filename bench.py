@@ -298,10 +298,13 @@ def bench_serving(seconds, seed, log, rate=None):
     }
 
 
-def assign_bytes(n, d, k, kappa):
-    # X rows, graph rows, neighbour labels, own label, output label, visiting
-    # order, centroids (each read once)
-    return n * (4 * d + 8 * kappa + 12) + 4 * k * d
+def assign_bytes(n, d, k, kappa, evaluated=None):
+    # graph rows, neighbour labels, own label, output label, visiting order
+    # for every sample; the rows of the samples whose distances are
+    # evaluated (all of them unless counted: a sample whose neighbours all
+    # share its cluster needs none); centroids (each read once)
+    ev = n if evaluated is None else evaluated
+    return n * (8 * kappa + 12) + ev * 4 * d + 4 * k * d
 
 
 def make_data(cfg, seed, device):
@@ -442,7 +445,8 @@ def main():
     kp = knnkm.knnkm_phase_times(ctx)
     knnkm.knnkm_enable_timing(ctx, 1)
     assign_ms = kp["assign_ms"] / max(1.0, kp["assign_launches"])
-    bytes_assign = assign_bytes(n, d, k, kappa)
+    evaluated = kp["assign_evaluated"] / max(1.0, kp["assign_launches"]) if kp["assign_evaluated"] >= 0 else None
+    bytes_assign = assign_bytes(n, d, k, kappa, evaluated)
     achieved = bytes_assign / (assign_ms / 1000.0) / 1e9
     out = {
         "metric": "samples assigned/s per iteration",
@@ -469,6 +473,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.config),
                      "algorithmic_bytes_per_launch": bytes_assign,
+                     "evaluated_samples_per_launch": evaluated,
                      "launches_timed": kp["assign_launches"]},
     }
     out["autotuned_shapes"] = [ln for ln in knnkm.knnkm_autotune_table().splitlines() if ln]

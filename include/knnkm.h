@@ -92,7 +92,9 @@ knnkm_status knnkm_workspace_bytes(const knnkm_ctx* ctx, int64_t* out);
  *  kappa >= k, Q_i = {0..k-1}.  labels_out[i] = the closest centroid in Q_i;
  *  the sample stays unless some candidate is strictly closer, and among equal
  *  minima the smallest id wins.  Decisions are exact up to float64 rounding
- *  (float32 evaluation, float64 re-evaluation of near ties).
+ *  (float32 evaluation, float64 re-evaluation of near ties).  When Q_i holds
+ *  only the sample's own cluster it stays without a distance being
+ *  evaluated, unless best_d2 is requested.
  *  C: k x d float32, row-major (leading dimension d).  G_ids: n x kappa int32
  *  with ids in [0,n).  labels_in must not alias labels_out.
  *  best_d2 (nullable): n floats, squared distance to the chosen centroid.
@@ -294,15 +296,17 @@ knnkm_status knnkm_enable_graphs(knnkm_ctx* ctx, int32_t on);
  * with at least 65,536 samples for a given group shape, size bin and call
  * site (a direct knn_assign call, a graph-construction round, the fit's first
  * sweep, later fit sweeps) times every candidate shape once (samples per row
- * group and pass, samples per block) on that call's own data, synchronising
- * the stream, and keeps the fastest for the process.  Every shape gives the
- * same results. */
+ * group and pass, samples per block, rows loaded first or lazily) on that
+ * call's own data, synchronising the stream, and keeps the fastest for the
+ * process.  Every shape gives the same results. */
 knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on);
 /* Fix the assignment's launch shape for this context (overrides the
- * autotuner): gs samples per row group and pass (1, 2 or 4), pb samples per
- * block (64 or 128); gs = 0 returns to the automatic choice.  Results do not
- * depend on the shape.  KNNKM_EINVAL for any other combination. */
-knnkm_status knnkm_set_assign_shape(knnkm_ctx* ctx, int32_t gs, int32_t pb);
+ * autotuner): gs samples per row group and pass, pb samples per block (64 or
+ * 128), lazy = 1 to load a sample's row only when a distance is needed (after
+ * its neighbour labels are known; gs 1 or 2) or 0 to load it first (gs 1, 2
+ * or 4).  gs = 0 returns to the automatic choice.  Results do not depend on
+ * the shape.  KNNKM_EINVAL for any other combination. */
+knnkm_status knnkm_set_assign_shape(knnkm_ctx* ctx, int32_t gs, int32_t pb, int32_t lazy);
 /* The process-wide table of tuned shapes as text (one line per entry) into
  * buf (len bytes, NUL-terminated, truncated); *needed gets the full size. */
 knnkm_status knnkm_autotune_table(char* buf, int64_t len, int64_t* needed);
@@ -318,7 +322,10 @@ knnkm_status knnkm_autotune_table(char* buf, int64_t len, int64_t* needed);
  *          working copy of the data in cluster order)
  *   out[2] last knn_kmeans_fit iterations (assign + update + distortion)
  *   out[3] sum of the timed assignment launches of those iterations (on = 2)
- *   out[4] iterations run (count), out[5] assignment launches timed (count) */
+ *   out[4] iterations run (count), out[5] assignment launches timed (count)
+ *   out[6] samples whose candidate distances those launches evaluated, summed
+ *          (count; a sample whose neighbours all share its cluster has its
+ *          own cluster as the only candidate and needs none) (on = 2) */
 knnkm_status knnkm_enable_timing(knnkm_ctx* ctx, int32_t on);
 knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t count);
 

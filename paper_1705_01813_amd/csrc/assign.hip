@@ -85,17 +85,27 @@ __device__ inline void for_each_cand(const int (&v)[SM], const bool (&valid)[SM]
 // rows; neighbour labels) are issued for all GS samples before any is used,
 // so a wavefront keeps several sample rows in flight.  SM candidate slots
 // per lane (SM * L >= kappa + 1).
-template <int L, int V, int GS, int SM>
+//
+// A sample whose neighbours all share its own cluster has that cluster as its
+// only candidate, so it stays without any distance being evaluated (unless
+// best distances are requested).  With LAZY the sample's row is loaded only
+// when a distance is needed, after its neighbour labels are known (fewer
+// bytes, one more dependent step); without it the row is loaded first.
+// eval_acc counts the samples whose distances were evaluated.
+template <int L, int V, int GS, int SM, int LAZY>
 __global__ __launch_bounds__(256) void k_assign(
     const float* __restrict__ X, int n, int d, int64_t ldx, const float* __restrict__ C, int k,
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
     float* __restrict__ best_out, unsigned long long* __restrict__ moved_acc,
-    const int* __restrict__ order, int dense, int nchunks, int pb, double rel, int vec_x, int vec_c,
-    const int* __restrict__ job_of, const int* __restrict__ kbase) {
+    unsigned long long* __restrict__ eval_acc, const int* __restrict__ order, int dense, int nchunks, int pb,
+    double rel, int vec_x, int vec_c, const int* __restrict__ job_of, const int* __restrict__ kbase) {
   constexpr int GW = 64 / L;           // samples per wavefront and pass
   constexpr int PASS = 4 * GW * GS;    // samples per block and pass
-  __shared__ unsigned int block_moved;
-  if (threadIdx.x == 0) block_moved = 0;
+  __shared__ unsigned int block_moved, block_eval;
+  if (threadIdx.x == 0) {
+    block_moved = 0;
+    block_eval = 0;
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane / L, j = lane % L;
@@ -103,7 +113,7 @@ __global__ __launch_bounds__(256) void k_assign(
   // XCD-aware chunk mapping: hardware places block b on XCD b % 8.
   const int per_xcd = gridDim.x / 8;
   const int chunk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  unsigned int my_moved = 0;
+  unsigned int my_moved = 0, my_eval = 0;
   if (chunk < nchunks) {
     const int64_t start = (int64_t)chunk * pb;
     const int64_t end = min((int64_t)n, start + pb);
@@ -122,7 +132,7 @@ __global__ __launch_bounds__(256) void k_assign(
 #pragma unroll
       for (int p = 0; p < GS; ++p) {
         const int64_t i = ii[p];
-        if (act[p]) {
+        if (act[p] && !LAZY) {
           load_row<V>(x[p], X + i * ldx, j, d, vec_x);
         } else {
 #pragma unroll
@@ -154,10 +164,29 @@ __global__ __launch_bounds__(256) void k_assign(
           valid[p][s] = act[p] && !dense_i[p] && e <= kappa;
           cv[p][s] = !valid[p][s] ? -1 : (e == 0 ? cur[p] : lab_in[nb[p][s]]);
         }
+      // the own cluster as the only candidate decides the sample
+      bool single[GS];
+#pragma unroll
+      for (int p = 0; p < GS; ++p) {
+        bool other = false;
+#pragma unroll
+        for (int s = 0; s < SM; ++s) other = other || (valid[p][s] && cv[p][s] != cur[p]);
+        single[p] = act[p] && !dense_i[p] && !best_out && cur[p] >= 0 && (__ballot(other) & gmask) == 0;
+      }
+      if (LAZY) {
+#pragma unroll
+        for (int p = 0; p < GS; ++p)
+          if (act[p] && !single[p]) load_row<V>(x[p], X + ii[p] * ldx, j, d, vec_x);
+      }
 
 #pragma unroll
       for (int p = 0; p < GS; ++p) {
         if (!act[p]) continue;  // group-uniform
+        if (single[p]) {        // group-uniform
+          if (j == 0) lab_out[ii[p]] = cur[p];
+          continue;
+        }
+        if (j == 0) my_eval++;
         // pass 1: float32 distances, best and second best
         float b1 = FLT_MAX, b2 = FLT_MAX;
         int q1 = -1;
@@ -215,10 +244,12 @@ __global__ __launch_bounds__(256) void k_assign(
       }
     }
   }
-  if (moved_acc) {
+  if (moved_acc || eval_acc) {
     if (my_moved) atomicAdd(&block_moved, my_moved);
+    if (my_eval) atomicAdd(&block_eval, my_eval);
     __syncthreads();
-    if (threadIdx.x == 0 && block_moved) atomicAdd(moved_acc, (unsigned long long)block_moved);
+    if (threadIdx.x == 0 && moved_acc && block_moved) atomicAdd(moved_acc, (unsigned long long)block_moved);
+    if (threadIdx.x == 0 && eval_acc && block_eval) atomicAdd(eval_acc, (unsigned long long)block_eval);
   }
 }
 
@@ -228,29 +259,36 @@ __global__ __launch_bounds__(256) void k_assign(
 // best at 1M x 128; the autotuner below times the candidates on the first
 // large call of each (group shape, size bin) and keeps the fastest.
 struct AssignCfg {
-  int gs = 2, pb = 64;
+  int gs = 2, pb = 64, lazy = 0;  // lazy: sample rows loaded only when a distance is needed
 };
-static const AssignCfg kAssignCandidates[] = {{1, 64}, {2, 64}, {4, 64}, {1, 128}, {2, 128}, {4, 128}};
+static const AssignCfg kAssignCandidates[] = {{1, 64, 0}, {2, 64, 0}, {4, 64, 0}, {1, 128, 0}, {2, 128, 0},
+                                              {4, 128, 0}, {1, 64, 1},  {2, 64, 1},  {1, 128, 1}, {2, 128, 1}};
 
 template <int L, int V, int SM>
 static void launch_assign(knnkm_ctx* ctx, AssignCfg cfg, const float* X, int64_t n, int32_t d, int64_t ldx,
                           const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                           const int32_t* labels_in, int32_t* labels_out, float* best_d2,
-                          unsigned long long* acc, const int32_t* order, bool dense, double rel, bool vec_x,
-                          bool vec_c, const int32_t* job_of, const int32_t* kbase) {
+                          unsigned long long* acc, unsigned long long* eacc, const int32_t* order, bool dense,
+                          double rel, bool vec_x, bool vec_c, const int32_t* job_of, const int32_t* kbase) {
   const int nchunks = (int)((n + cfg.pb - 1) / cfg.pb);
   const int grid = ((nchunks + 7) / 8) * 8;
-#define LG(GG)                                                                                              \
-  k_assign<L, V, GG, SM><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in,  \
-                                                        labels_out, best_d2, acc, order, dense ? 1 : 0,     \
-                                                        nchunks, cfg.pb, rel, vec_x ? 1 : 0, vec_c ? 1 : 0, \
-                                                        job_of, kbase)
-  if (cfg.gs == 1)
-    LG(1);
-  else if (cfg.gs == 4)
-    LG(4);
-  else
-    LG(2);
+#define LG(GG, LZ)                                                                                          \
+  k_assign<L, V, GG, SM, LZ><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in,  \
+                                                            labels_out, best_d2, acc, eacc, order, dense ? 1 : 0, \
+                                                            nchunks, cfg.pb, rel, vec_x ? 1 : 0, vec_c ? 1 : 0,   \
+                                                            job_of, kbase)
+  if (cfg.lazy) {
+    if (cfg.gs == 1)
+      LG(1, 1);
+    else
+      LG(2, 1);
+  } else if (cfg.gs == 1) {
+    LG(1, 0);
+  } else if (cfg.gs == 4) {
+    LG(4, 0);
+  } else {
+    LG(2, 0);
+  }
 #undef LG
 }
 
@@ -258,11 +296,11 @@ template <int L, int V>
 static void launch_assign_sm(knnkm_ctx* ctx, int S, AssignCfg cfg, const float* X, int64_t n, int32_t d,
                              int64_t ldx, const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                              const int32_t* labels_in, int32_t* labels_out, float* best_d2,
-                             unsigned long long* acc, const int32_t* order, bool dense, double rel, bool vec_x,
-                             bool vec_c, const int32_t* job_of, const int32_t* kbase) {
+                             unsigned long long* acc, unsigned long long* eacc, const int32_t* order, bool dense,
+                             double rel, bool vec_x, bool vec_c, const int32_t* job_of, const int32_t* kbase) {
 #define LS(SS)                                                                                            \
   launch_assign<L, V, SS>(ctx, cfg, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
-                          order, dense, rel, vec_x, vec_c, job_of, kbase)
+                          eacc, order, dense, rel, vec_x, vec_c, job_of, kbase)
   if (S <= 1)
     LS(1);
   else if (S <= 2)
@@ -299,10 +337,10 @@ extern "C" knnkm_status knnkm_autotune_table(char* buf, int64_t len, int64_t* ne
     char line[160];
     const uint64_t k = kv.first;
     snprintf(line, sizeof(line),
-             "knn_assign device=%d L=%d V=%d slots=%d dense=%d n_bin=2^%d use=%s gs=%d pb=%d us=%.1f\n",
+             "knn_assign device=%d L=%d V=%d slots=%d dense=%d n_bin=2^%d use=%s gs=%d pb=%d lazy=%d us=%.1f\n",
              (int)((k >> 40) & 0xFF), (int)((k >> 32) & 0xFF), (int)((k >> 24) & 0xFF), (int)((k >> 16) & 0xFF),
              (int)((k >> 8) & 0x1), (int)(k & 0xFF), kUseName[(k >> 9) & 0x3], kv.second.cfg.gs, kv.second.cfg.pb,
-             kv.second.us);
+             kv.second.cfg.lazy, kv.second.us);
     out += line;
   }
   if (buf && len > 0) {
@@ -320,12 +358,16 @@ extern "C" knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on) {
   return KNNKM_OK;
 }
 
-extern "C" knnkm_status knnkm_set_assign_shape(knnkm_ctx* ctx, int32_t gs, int32_t pb) {
+extern "C" knnkm_status knnkm_set_assign_shape(knnkm_ctx* ctx, int32_t gs, int32_t pb, int32_t lazy) {
   if (!ctx) return KNNKM_EINVAL;
-  const bool ok = gs == 0 || ((gs == 1 || gs == 2 || gs == 4) && (pb == 64 || pb == 128));
-  if (!ok) return knnkm_fail(ctx, KNNKM_EINVAL, "set_assign_shape: gs=%d pb=%d is not a launch shape", gs, pb);
+  const bool ok = gs == 0 || ((pb == 64 || pb == 128) && ((lazy == 0 && (gs == 1 || gs == 2 || gs == 4)) ||
+                                                          (lazy == 1 && (gs == 1 || gs == 2))));
+  if (!ok)
+    return knnkm_fail(ctx, KNNKM_EINVAL, "set_assign_shape: gs=%d pb=%d lazy=%d is not a launch shape", gs, pb,
+                      lazy);
   ctx->assign_gs = gs;
   ctx->assign_pb = pb;
+  ctx->assign_lazy = lazy;
   return KNNKM_OK;
 }
 
@@ -333,8 +375,9 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                        int64_t* n_moved, const int32_t* order, bool dense, const int32_t* job_of,
-                       const int32_t* kbase, int use) {
+                       const int32_t* kbase, int use, int64_t* n_eval) {
   if (n_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
+  if (n_eval) KNNKM_TRY(ks_fill_i64(ctx, n_eval, 1, 0));
   if (n == 0) return KNNKM_OK;
   const bool all_dense = dense;
   int L, V;
@@ -348,9 +391,10 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   const bool vec_x = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
   const bool vec_c = (d % 4 == 0) && ((uintptr_t)C % 16 == 0);
   unsigned long long* acc = (unsigned long long*)n_moved;
+  unsigned long long* eacc = (unsigned long long*)n_eval;
 #define LA(LL, VV)                                                                                         \
   launch_assign_sm<LL, VV>(ctx, S, cfg, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
-                           order, dense, rel, vec_x, vec_c, job_of, kbase)
+                           eacc, order, dense, rel, vec_x, vec_c, job_of, kbase)
   auto launch = [&](AssignCfg cfg) {
   if (V == 4) {
     switch (L) {
@@ -380,6 +424,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   if (ctx->assign_gs > 0) {
     cfg.gs = ctx->assign_gs;
     cfg.pb = ctx->assign_pb;
+    cfg.lazy = ctx->assign_lazy;
     found = true;
   } else {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -400,6 +445,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
       float best = 1e30f;
       for (const AssignCfg& c : kAssignCandidates) {
         if (n_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
+        if (n_eval) KNNKM_TRY(ks_fill_i64(ctx, n_eval, 1, 0));
         KNNKM_HIP(ctx, hipEventRecord(e0, ctx->stream));
         launch(c);
         KNNKM_HIP(ctx, hipEventRecord(e1, ctx->stream));
@@ -415,6 +461,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
       std::lock_guard<std::mutex> g(g_tune_mu);
       g_tuned[key] = AssignTuned{cfg, best * 1000.f};
       if (n_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
+      if (n_eval) KNNKM_TRY(ks_fill_i64(ctx, n_eval, 1, 0));
     }
   }
   launch(cfg);

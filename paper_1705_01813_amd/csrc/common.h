@@ -34,12 +34,13 @@ struct knnkm_ctx {
   int fit_ev = -1;             // fit start, init end, iterations end = +0, +1, +2
   int assign_ev0 = -1, assign_n = 0;  // pairs around the assignment launches of the fit
   int fit_iters = 0;                  // sweeps of the last fit
+  const int64_t* fit_evals = nullptr;  // per-sweep evaluated-sample counts of the last timed fit (device)
   // fit iterations replayed from a captured HIP graph (captured on a private
   // stream, launched on `stream`)
   bool graphs = true;
   // launch shapes of the assignment chosen by timing the candidates once
   bool autotune = true;
-  int assign_gs = 0, assign_pb = 64;  // forced assignment shape (gs = 0: automatic)
+  int assign_gs = 0, assign_pb = 64, assign_lazy = 0;  // forced assignment shape (gs = 0: automatic)
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   bool capturing = false;
   hipStream_t cap_stream = nullptr;
@@ -187,7 +188,8 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                        int64_t* n_moved, const int32_t* order, bool dense,
-                       const int32_t* job_of = nullptr, const int32_t* kbase = nullptr, int use = KS_USE_CALL);
+                       const int32_t* job_of = nullptr, const int32_t* kbase = nullptr, int use = KS_USE_CALL,
+                       int64_t* n_eval = nullptr);
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
                          int32_t* labels);

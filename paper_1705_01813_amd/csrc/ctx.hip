@@ -3,6 +3,8 @@
 #include <cstdarg>
 #include <cstring>
 
+#include <vector>
+
 #include "common.h"
 
 knnkm_status knnkm_fail(knnkm_ctx* ctx, knnkm_status st, const char* fmt, ...) {
@@ -48,6 +50,7 @@ knnkm_status knnkm_ws_release(knnkm_ctx* ctx) {
   for (auto& kv : ctx->ws)
     if (kv.second.ptr) (void)hipFreeAsync(kv.second.ptr, ctx->stream);
   ctx->ws.clear();
+  ctx->fit_evals = nullptr;
   tm_plan_free(ctx->tm_plan);  // its device tables were workspace
   ctx->tm_plan = nullptr;
   KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -196,7 +199,7 @@ static double ev_ms(knnkm_ctx* ctx, int a) {
 
 extern "C" knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t count) {
   if (!ctx || !out || count < 1) return KNNKM_EINVAL;
-  double v[6] = {-1.0, -1.0, -1.0, -1.0, 0.0, 0.0};
+  double v[7] = {-1.0, -1.0, -1.0, -1.0, 0.0, 0.0, -1.0};
   if (!ctx->dry) {
     (void)hipSetDevice(ctx->device);
     v[0] = ev_ms(ctx, ctx->build_ev);
@@ -209,9 +212,21 @@ extern "C" knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t c
     }
     v[4] = ctx->fit_ev >= 0 ? (double)ctx->fit_iters : 0.0;
     v[5] = (double)ctx->assign_n;
+    if (ctx->fit_evals && ctx->assign_n > 0 && count > 6) {
+      std::vector<int64_t> ev((size_t)ctx->assign_n);
+      if (hipMemcpyAsync(ev.data(), ctx->fit_evals + 1, sizeof(int64_t) * ev.size(), hipMemcpyDeviceToHost,
+                         ctx->stream) == hipSuccess &&
+          hipStreamSynchronize(ctx->stream) == hipSuccess) {
+        double s = 0.0;
+        for (int64_t e : ev) s += (double)e;
+        v[6] = s;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
   }
-  for (int i = 0; i < count && i < 6; ++i) out[i] = v[i];
-  for (int i = 6; i < count; ++i) out[i] = 0.0;
+  for (int i = 0; i < count && i < 7; ++i) out[i] = v[i];
+  for (int i = 7; i < count; ++i) out[i] = 0.0;
   return KNNKM_OK;
 }
 

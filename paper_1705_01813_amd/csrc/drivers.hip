@@ -388,9 +388,9 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   mark(3);
 
   // one sweep: assignment, update, distortion of every job
-  auto sweep = [&](const int32_t* cu, int32_t* nx, int64_t* mv, bool first) -> knnkm_status {
+  auto sweep = [&](const int32_t* cu, int32_t* nx, int64_t* mv, bool first, int64_t* ev) -> knnkm_status {
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
-                     J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT);
+                     J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT, ev);
   };
   // The first sweep moves a large share of the samples away from the
   // initial partition: its update rebuilds the sums from a label sort and
@@ -407,13 +407,21 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     k_range_trace<<<m, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, tr);
     return knnkm_check(ctx, "fit iteration");
   };
+  ctx->fit_evals = nullptr;
   const bool time_all = ctx->timing >= 2;
+  // with every assignment timed, also count the samples whose distances
+  // each one evaluated
+  int64_t* evals = nullptr;
+  if (time_all) {
+    evals = (int64_t*)knnkm_ws(ctx, "fit_evals", sizeof(int64_t) * (size_t)(T + 1));
+    if (!evals) return KNNKM_ENOMEM;
+  }
   int32_t* cur = labp;
   int32_t* nxt = lab2;
   int it = 0;
   auto eager = [&](int t) -> knnkm_status {
     if (time_all) mark(6 + 2 * (t - 1));
-    KNNKM_TRY(sweep(cur, nxt, moved + t, t == 1));
+    KNNKM_TRY(sweep(cur, nxt, moved + t, t == 1, evals ? evals + t : nullptr));
     if (time_all) {
       mark(7 + 2 * (t - 1));
       ctx->assign_n = t;
@@ -458,11 +466,11 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       ok = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
         ctx->capturing = true;
-        knnkm_status st = sweep(cur, nxt, mv_slot, false);
+        knnkm_status st = sweep(cur, nxt, mv_slot, false, nullptr);
         if (st == KNNKM_OK) st = update(cur, nxt, tr_slot, false);
         if (st == KNNKM_OK) {
           k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
-          st = sweep(nxt, cur, mv_slot, false);
+          st = sweep(nxt, cur, mv_slot, false, nullptr);
         }
         if (st == KNNKM_OK) st = update(nxt, cur, tr_slot, false);
         if (st == KNNKM_OK) k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
@@ -494,6 +502,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   KNNKM_TRY(knnkm_check(ctx, "fit labels"));
   *iters_run = it;
   ctx->fit_iters = it;
+  ctx->fit_evals = evals;
   return KNNKM_OK;
 }
 

@@ -137,7 +137,7 @@ def lib():
             "knnkm_enable_timing": [P, i32],
             "knnkm_enable_graphs": [P, i32],
             "knnkm_autotune": [P, i32],
-            "knnkm_set_assign_shape": [P, i32, i32],
+            "knnkm_set_assign_shape": [P, i32, i32, i32],
             "knnkm_autotune_table": [P, i64, ctypes.POINTER(i64)],
             "knnkm_phase_times": [P, P, i32],
             "knnkm_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)],
@@ -355,9 +355,9 @@ def knnkm_autotune(ctx, on=True):
     _chk(ctx.handle, lib().knnkm_autotune(ctx.handle, 1 if on else 0))
 
 
-def knnkm_set_assign_shape(ctx, gs=0, pb=64):
+def knnkm_set_assign_shape(ctx, gs=0, pb=64, lazy=0):
     """Fix the assignment's launch shape (gs = 0: automatic)."""
-    _chk(ctx.handle, lib().knnkm_set_assign_shape(ctx.handle, int(gs), int(pb)))
+    _chk(ctx.handle, lib().knnkm_set_assign_shape(ctx.handle, int(gs), int(pb), int(lazy)))
 
 
 def knnkm_autotune_table():
@@ -374,7 +374,7 @@ def knnkm_enable_timing(ctx, on=True):
     _chk(ctx.handle, lib().knnkm_enable_timing(ctx.handle, int(on)))
 
 
-PHASES = ("build_ms", "fit_init_ms", "fit_iters_ms", "assign_ms", "iters", "assign_launches")
+PHASES = ("build_ms", "fit_init_ms", "fit_iters_ms", "assign_ms", "iters", "assign_launches", "assign_evaluated")
 
 
 def knnkm_phase_times(ctx):

@@ -114,7 +114,7 @@ def test_batched_validation(dry):
 
 def test_assign_shape_validation(dry):
     h = dry.handle
-    for gs, pb in [(1, 64), (2, 128), (4, 64), (4, 128), (0, 0)]:
-        assert _call("knnkm_set_assign_shape", h, gs, pb) == knnkm.OK, (gs, pb)
-    for gs, pb in [(8, 64), (3, 64), (2, 96), (-1, 64)]:
-        assert _call("knnkm_set_assign_shape", h, gs, pb) == knnkm.EINVAL, (gs, pb)
+    for gs, pb, lazy in [(1, 64, 0), (2, 128, 0), (4, 64, 0), (4, 128, 0), (1, 64, 1), (2, 128, 1), (0, 0, 0)]:
+        assert _call("knnkm_set_assign_shape", h, gs, pb, lazy) == knnkm.OK, (gs, pb, lazy)
+    for gs, pb, lazy in [(8, 64, 0), (3, 64, 0), (2, 96, 0), (-1, 64, 0), (4, 64, 1), (1, 64, 2)]:
+        assert _call("knnkm_set_assign_shape", h, gs, pb, lazy) == knnkm.EINVAL, (gs, pb, lazy)

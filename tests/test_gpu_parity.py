@@ -302,34 +302,45 @@ def test_assign_autotune_same_result(ctx):
         knnkm.knnkm_autotune(ctx, True)
 
 
-SHAPES = [(1, 64), (2, 64), (4, 64), (1, 128), (2, 128), (4, 128)]
+SHAPES = [(1, 64, 0), (2, 64, 0), (4, 64, 0), (1, 128, 0), (2, 128, 0), (4, 128, 0), (1, 64, 1), (2, 128, 1)]
 
 
 @pytest.mark.parametrize("n,d,k,kappa", [(3001, 3, 60, 5), (5000, 32, 150, 20), (4099, 128, 90, 20),
                                          (2500, 512, 40, 50), (3000, 24, 50, 40), (2000, 16, 30, 30)])
 def test_assign_shapes_same_bits(ctx, n, d, k, kappa):
-    """Every launch shape (samples per row group and pass, samples per block)
-    gives the same labels, best distances and moved count."""
+    """Every launch shape (samples per row group and pass, samples per block,
+    rows loaded first or lazily) gives the same labels, best distances and
+    moved count, with and without best distances requested (without them,
+    single-candidate samples skip their distances)."""
     say("assign shapes", n, d, k, kappa)
     X = dev(datagen.mixture(n, d, k, seed=n + d))
     C = dev(datagen.mixture(k, d, k, seed=7 * k))
     G = dev(rand_graph(n, kappa, 3)) if kappa < k else None
-    lab = dev(np.random.default_rng(1).integers(0, k, n).astype(np.int32))
+    # every other sample hands its label to its neighbours, so that many
+    # samples have their own cluster as the only candidate
+    lab_np = np.random.default_rng(1).integers(0, k, n).astype(np.int32)
+    if G is not None:
+        Gh = host(G)
+        for i in range(0, n, 2):
+            lab_np[Gh[i]] = lab_np[i]
+    lab = dev(lab_np)
     ref = None
     try:
-        for gs, pb in SHAPES:
-            knnkm.knnkm_set_assign_shape(ctx, gs, pb)
-            out = torch.empty(n, dtype=torch.int32, device=DEV)
-            best = torch.empty(n, dtype=torch.float32, device=DEV)
-            mv = torch.zeros(1, dtype=torch.int64, device=DEV)
-            knnkm.knn_assign(ctx, X, C, G, lab, out, best_d2=best, n_moved=mv, kappa=kappa)
-            got = (host(out), host(best).view(np.uint32), int(host(mv)[0]))
-            if ref is None:
-                ref = got
-            else:
-                assert np.array_equal(got[0], ref[0]), (gs, pb)
-                assert np.array_equal(got[1], ref[1]), (gs, pb)
-                assert got[2] == ref[2], (gs, pb)
+        for gs, pb, lazy in SHAPES:
+            knnkm.knnkm_set_assign_shape(ctx, gs, pb, lazy)
+            for want_best in (True, False):
+                out = torch.empty(n, dtype=torch.int32, device=DEV)
+                best = torch.empty(n, dtype=torch.float32, device=DEV) if want_best else None
+                mv = torch.zeros(1, dtype=torch.int64, device=DEV)
+                knnkm.knn_assign(ctx, X, C, G, lab, out, best_d2=best, n_moved=mv, kappa=kappa)
+                got = (host(out), host(best).view(np.uint32) if want_best else None, int(host(mv)[0]))
+                if ref is None:
+                    ref = got
+                else:
+                    assert np.array_equal(got[0], ref[0]), (gs, pb, lazy, want_best)
+                    if want_best:
+                        assert np.array_equal(got[1], ref[1]), (gs, pb, lazy)
+                    assert got[2] == ref[2], (gs, pb, lazy, want_best)
     finally:
         knnkm.knnkm_set_assign_shape(ctx, 0)
 
