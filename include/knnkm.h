@@ -292,6 +292,15 @@ knnkm_status knnkm_server_destroy(knnkm_server* srv);
  * launches. */
 knnkm_status knnkm_enable_graphs(knnkm_ctx* ctx, int32_t on);
 
+/* Active sets in the fit sweeps (default on; graph fits with n * kappa below
+ * 2^31).  A sample whose own cluster was its only candidate stays so until
+ * its own label or a neighbour's label changes, so from the second sweep on
+ * knn_kmeans_fit and knnkm_fit_batched evaluate only the samples that had
+ * several candidates, moved, or have a neighbour that moved (found through
+ * reverse lists of the graph, built once per fit) and copy the other
+ * labels.  Results are the same bits with active sets on or off. */
+knnkm_status knnkm_enable_active_sets(knnkm_ctx* ctx, int32_t on);
+
 /* Autotuner of the assignment's launch shapes (default on): the first call
  * with at least 65,536 samples for a given group shape, size bin and call
  * site (a direct knn_assign call, a graph-construction round, the fit's first

@@ -92,13 +92,21 @@ __device__ inline void for_each_cand(const int (&v)[SM], const bool (&valid)[SM]
 // when a distance is needed, after its neighbour labels are known (fewer
 // bytes, one more dependent step); without it the row is loaded first.
 // eval_acc counts the samples whose distances were evaluated.
+//
+// Active sets (fit sweeps): act_in (nullable) marks the samples to look at;
+// any other sample is known to have its own cluster as the only candidate
+// and keeps its label.  act_out (nullable) receives 1 for every sample whose
+// distances were evaluated (it had several candidates, so it is looked at
+// again next sweep) and 0 otherwise; the update then marks the samples whose
+// own or neighbours' labels change.
 template <int L, int V, int GS, int SM, int LAZY>
 __global__ __launch_bounds__(256) void k_assign(
     const float* __restrict__ X, int n, int d, int64_t ldx, const float* __restrict__ C, int k,
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
     float* __restrict__ best_out, unsigned long long* __restrict__ moved_acc,
     unsigned long long* __restrict__ eval_acc, const int* __restrict__ order, int dense, int nchunks, int pb,
-    double rel, int vec_x, int vec_c, const int* __restrict__ job_of, const int* __restrict__ kbase) {
+    double rel, int vec_x, int vec_c, const int* __restrict__ job_of, const int* __restrict__ kbase,
+    const uint8_t* __restrict__ act_in, uint8_t* __restrict__ act_out) {
   constexpr int GW = 64 / L;           // samples per wavefront and pass
   constexpr int PASS = 4 * GW * GS;    // samples per block and pass
   __shared__ unsigned int block_moved, block_eval;
@@ -119,20 +127,22 @@ __global__ __launch_bounds__(256) void k_assign(
     const int64_t end = min((int64_t)n, start + pb);
     for (int64_t base = start; base < end; base += PASS) {
       int64_t ii[GS];
-      bool act[GS];
+      bool act[GS], live[GS];
 #pragma unroll
       for (int p = 0; p < GS; ++p) {
         const int64_t idx = base + w * GW + g + p * 4 * GW;
         act[p] = idx < end;
         ii[p] = act[p] ? (order ? (int64_t)order[idx] : idx) : 0;
       }
+#pragma unroll
+      for (int p = 0; p < GS; ++p) live[p] = act[p] && (!act_in || act_in[ii[p]] != 0);
       float x[GS][V];
       int cur[GS], kb[GS], kc[GS], nb[GS][SM];
       bool dense_i[GS];
 #pragma unroll
       for (int p = 0; p < GS; ++p) {
         const int64_t i = ii[p];
-        if (act[p] && !LAZY) {
+        if (live[p] && !LAZY) {
           load_row<V>(x[p], X + i * ldx, j, d, vec_x);
         } else {
 #pragma unroll
@@ -142,7 +152,7 @@ __global__ __launch_bounds__(256) void k_assign(
         kb[p] = 0;
         kc[p] = k;
         dense_i[p] = dense;
-        if (job_of && act[p]) {
+        if (job_of && live[p]) {
           const int q = job_of[i];
           kb[p] = kbase[q];
           kc[p] = kbase[q + 1] - kb[p];
@@ -151,7 +161,7 @@ __global__ __launch_bounds__(256) void k_assign(
 #pragma unroll
         for (int s = 0; s < SM; ++s) {
           const int e = j + L * s;
-          nb[p][s] = (act[p] && !dense_i[p] && e >= 1 && e <= kappa) ? G[i * kappa + (e - 1)] : -1;
+          nb[p][s] = (live[p] && !dense_i[p] && e >= 1 && e <= kappa) ? G[i * kappa + (e - 1)] : -1;
         }
       }
       int cv[GS][SM];
@@ -161,7 +171,7 @@ __global__ __launch_bounds__(256) void k_assign(
 #pragma unroll
         for (int s = 0; s < SM; ++s) {
           const int e = j + L * s;
-          valid[p][s] = act[p] && !dense_i[p] && e <= kappa;
+          valid[p][s] = live[p] && !dense_i[p] && e <= kappa;
           cv[p][s] = !valid[p][s] ? -1 : (e == 0 ? cur[p] : lab_in[nb[p][s]]);
         }
       // the own cluster as the only candidate decides the sample
@@ -171,19 +181,22 @@ __global__ __launch_bounds__(256) void k_assign(
         bool other = false;
 #pragma unroll
         for (int s = 0; s < SM; ++s) other = other || (valid[p][s] && cv[p][s] != cur[p]);
-        single[p] = act[p] && !dense_i[p] && !best_out && cur[p] >= 0 && (__ballot(other) & gmask) == 0;
+        single[p] = live[p] && !dense_i[p] && !best_out && cur[p] >= 0 && (__ballot(other) & gmask) == 0;
       }
       if (LAZY) {
 #pragma unroll
         for (int p = 0; p < GS; ++p)
-          if (act[p] && !single[p]) load_row<V>(x[p], X + ii[p] * ldx, j, d, vec_x);
+          if (live[p] && !single[p]) load_row<V>(x[p], X + ii[p] * ldx, j, d, vec_x);
       }
 
 #pragma unroll
       for (int p = 0; p < GS; ++p) {
-        if (!act[p]) continue;  // group-uniform
-        if (single[p]) {        // group-uniform
-          if (j == 0) lab_out[ii[p]] = cur[p];
+        if (!act[p]) continue;       // group-uniform
+        if (!live[p] || single[p]) {  // group-uniform
+          if (j == 0) {
+            lab_out[ii[p]] = cur[p];
+            if (act_out) act_out[ii[p]] = 0;
+          }
           continue;
         }
         if (j == 0) my_eval++;
@@ -239,11 +252,178 @@ __global__ __launch_bounds__(256) void k_assign(
         if (j == 0) {
           lab_out[ii[p]] = result;
           if (best_out) best_out[ii[p]] = bestv;
+          if (act_out) act_out[ii[p]] = 1;
           if (cur[p] >= 0 && result != cur[p]) my_moved++;
         }
       }
     }
   }
+  if (moved_acc || eval_acc) {
+    if (my_moved) atomicAdd(&block_moved, my_moved);
+    if (my_eval) atomicAdd(&block_eval, my_eval);
+    __syncthreads();
+    if (threadIdx.x == 0 && moved_acc && block_moved) atomicAdd(moved_acc, (unsigned long long)block_moved);
+    if (threadIdx.x == 0 && eval_acc && block_eval) atomicAdd(eval_acc, (unsigned long long)block_eval);
+  }
+}
+
+// Active-set sweeps.  k_act_compact lists the positions whose flag is set
+// and clears the flags it read, which makes that array the clean output of
+// the next sweep.  A block takes CPB = 4 x 16 x 64 consecutive positions and
+// reserves its share of the list with one atomic (blocks land in varying
+// order; decisions do not depend on the order of the list).
+__global__ __launch_bounds__(256) void k_act_compact(int64_t n, uint8_t* __restrict__ act, int32_t* __restrict__ list,
+                                                     int32_t* __restrict__ count) {
+  constexpr int RW = 16;  // rounds of 64 positions per wavefront
+  __shared__ int32_t wtot[4], wbase[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + w) * (RW * 64);
+  uint64_t m[RW];
+  int32_t tot = 0;
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const int64_t p = base + r * 64 + lane;
+    bool a = false;
+    if (p < n) {
+      a = act[p] != 0;
+      if (a) act[p] = 0;
+    }
+    m[r] = __ballot(a);
+    tot += (int32_t)__popcll(m[r]);
+  }
+  if (lane == 0) wtot[w] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int32_t all = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+    int32_t at = all ? atomicAdd(count, all) : 0;
+    for (int q = 0; q < 4; ++q) {
+      wbase[q] = at;
+      at += wtot[q];
+    }
+  }
+  __syncthreads();
+  int32_t at = wbase[w];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    if ((m[r] >> lane) & 1ull) list[at + __popcll(m[r] & lanes_below())] = (int32_t)(base + r * 64 + lane);
+    at += (int32_t)__popcll(m[r]);
+  }
+}
+
+// The listed samples, one per row group (grid-stride over the list), each
+// through the same candidate collection, float32 pass and float64 pass as
+// k_assign with one sample per group, so labels are the same bits.  Labels
+// of unlisted samples are not written: the update keeps both label arrays
+// equal outside the samples a sweep moves.  act_out as in k_assign.
+template <int L, int V, int SM>
+__global__ __launch_bounds__(256) void k_assign_list(
+    const float* __restrict__ X, int d, int64_t ldx, const float* __restrict__ C, int k,
+    const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
+    unsigned long long* __restrict__ moved_acc, unsigned long long* __restrict__ eval_acc,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ count, double rel, int vec_x, int vec_c,
+    const int* __restrict__ job_of, const int* __restrict__ kbase, uint8_t* __restrict__ act_out) {
+  constexpr int GW = 64 / L;
+  __shared__ unsigned int block_moved, block_eval;
+  if (threadIdx.x == 0) {
+    block_moved = 0;
+    block_eval = 0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane / L, j = lane % L;
+  const uint64_t gmask = group_mask<L>(g);
+  const int cnt = *count;
+  const int gid = (blockIdx.x * 4 + w) * GW + g;
+  const int ngroups = gridDim.x * 4 * GW;
+  unsigned int my_moved = 0, my_eval = 0;
+  // wave-uniform trip count: groups of a wavefront stay in step
+  const int first = (blockIdx.x * 4 + w) * GW;
+  for (int base = first; base < cnt; base += ngroups) {
+    const int li = base + g;
+    const bool live = li < cnt;  // group-uniform
+    const int64_t i = live ? (int64_t)list[li] : 0;
+    const int cur = live ? lab_in[i] : -1;
+    int kb = 0, kc = k;
+    bool dn = false;
+    if (job_of && live) {
+      const int q = job_of[i];
+      kb = kbase[q];
+      kc = kbase[q + 1] - kb;
+      dn = kappa >= kc;
+    }
+    int nb[SM], cv[SM];
+    bool valid[SM];
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      const int e = j + L * s;
+      nb[s] = (live && !dn && e >= 1 && e <= kappa) ? G[i * kappa + (e - 1)] : -1;
+    }
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      const int e = j + L * s;
+      valid[s] = live && !dn && e <= kappa;
+      cv[s] = !valid[s] ? -1 : (e == 0 ? cur : lab_in[nb[s]]);
+    }
+    bool other = false;
+#pragma unroll
+    for (int s = 0; s < SM; ++s) other = other || (valid[s] && cv[s] != cur);
+    const bool single = live && !dn && cur >= 0 && (__ballot(other) & gmask) == 0;
+    if (live && single) {  // group-uniform
+      if (j == 0) {
+        lab_out[i] = cur;
+        if (act_out) act_out[i] = 0;
+      }
+    } else if (live) {
+      float x[V];
+      load_row<V>(x, X + i * ldx, j, d, vec_x);
+      float b1 = FLT_MAX, b2 = FLT_MAX;
+      int q1 = -1;
+      auto pass1 = [&](int q) {
+        const float dq = group_sum<L>(part32<V>(x, C + (int64_t)q * d, j, d, vec_c));
+        if (dq < b1 || (dq == b1 && q < q1)) {
+          if (q1 >= 0) b2 = fminf(b2, b1);
+          b1 = dq;
+          q1 = q;
+        } else {
+          b2 = fminf(b2, dq);
+        }
+      };
+      if (dn)
+        for (int q = kb; q < kb + kc; ++q) pass1(q);
+      else
+        for_each_cand<L, SM>(cv, valid, gmask, pass1);
+      const double thr = (double)b1 * (1.0 + rel) / (1.0 - rel) + 1e-30;
+      int result = q1;
+      if ((double)b2 <= thr) {
+        double m64 = DBL_MAX, cur64 = -1.0;
+        int q64 = -1;
+        auto pass2 = [&](int q) {
+          const float* cr = C + (int64_t)q * d;
+          const float dq = group_sum<L>(part32<V>(x, cr, j, d, vec_c));
+          if ((double)dq <= thr) {
+            const double e = group_sum<L>(part64<V>(x, cr, j, d, vec_c));
+            if (q == cur) cur64 = e;
+            if (e < m64 || (e == m64 && q < q64)) {
+              m64 = e;
+              q64 = q;
+            }
+          }
+        };
+        if (dn)
+          for (int q = kb; q < kb + kc; ++q) pass2(q);
+        else
+          for_each_cand<L, SM>(cv, valid, gmask, pass2);
+        result = (cur >= 0 && cur64 >= 0.0 && cur64 == m64) ? cur : q64;
+      }
+      if (j == 0) {
+        lab_out[i] = result;
+        if (act_out) act_out[i] = 1;
+        my_eval++;
+        if (cur >= 0 && result != cur) my_moved++;
+      }
+    }
+  }
+  (void)gid;
   if (moved_acc || eval_acc) {
     if (my_moved) atomicAdd(&block_moved, my_moved);
     if (my_eval) atomicAdd(&block_eval, my_eval);
@@ -269,14 +449,15 @@ static void launch_assign(knnkm_ctx* ctx, AssignCfg cfg, const float* X, int64_t
                           const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                           const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                           unsigned long long* acc, unsigned long long* eacc, const int32_t* order, bool dense,
-                          double rel, bool vec_x, bool vec_c, const int32_t* job_of, const int32_t* kbase) {
+                          double rel, bool vec_x, bool vec_c, const int32_t* job_of, const int32_t* kbase,
+                          const uint8_t* act_in, uint8_t* act_out) {
   const int nchunks = (int)((n + cfg.pb - 1) / cfg.pb);
   const int grid = ((nchunks + 7) / 8) * 8;
 #define LG(GG, LZ)                                                                                          \
   k_assign<L, V, GG, SM, LZ><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in,  \
                                                             labels_out, best_d2, acc, eacc, order, dense ? 1 : 0, \
                                                             nchunks, cfg.pb, rel, vec_x ? 1 : 0, vec_c ? 1 : 0,   \
-                                                            job_of, kbase)
+                                                            job_of, kbase, act_in, act_out)
   if (cfg.lazy) {
     if (cfg.gs == 1)
       LG(1, 1);
@@ -297,10 +478,11 @@ static void launch_assign_sm(knnkm_ctx* ctx, int S, AssignCfg cfg, const float* 
                              int64_t ldx, const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                              const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                              unsigned long long* acc, unsigned long long* eacc, const int32_t* order, bool dense,
-                             double rel, bool vec_x, bool vec_c, const int32_t* job_of, const int32_t* kbase) {
+                             double rel, bool vec_x, bool vec_c, const int32_t* job_of, const int32_t* kbase,
+                             const uint8_t* act_in, uint8_t* act_out) {
 #define LS(SS)                                                                                            \
   launch_assign<L, V, SS>(ctx, cfg, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
-                          eacc, order, dense, rel, vec_x, vec_c, job_of, kbase)
+                          eacc, order, dense, rel, vec_x, vec_c, job_of, kbase, act_in, act_out)
   if (S <= 1)
     LS(1);
   else if (S <= 2)
@@ -375,7 +557,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                        int64_t* n_moved, const int32_t* order, bool dense, const int32_t* job_of,
-                       const int32_t* kbase, int use, int64_t* n_eval) {
+                       const int32_t* kbase, int use, int64_t* n_eval, const uint8_t* act_in, uint8_t* act_out) {
   if (n_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
   if (n_eval) KNNKM_TRY(ks_fill_i64(ctx, n_eval, 1, 0));
   if (n == 0) return KNNKM_OK;
@@ -394,7 +576,48 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   unsigned long long* eacc = (unsigned long long*)n_eval;
 #define LA(LL, VV)                                                                                         \
   launch_assign_sm<LL, VV>(ctx, S, cfg, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
-                           eacc, order, dense, rel, vec_x, vec_c, job_of, kbase)
+                           eacc, order, dense, rel, vec_x, vec_c, job_of, kbase, act_in, act_out)
+  if (act_in && !best_d2 && !order && !all_dense) {
+    // active-set sweep: list the flagged samples, then assign them
+    KNNKM_WS(ctx, list, int32_t, "as_act_list", n);
+    KNNKM_WS(ctx, cnt, int32_t, "as_act_count", 1);
+    KNNKM_TRY(ks_fill_i32(ctx, cnt, 1, 0));
+    k_act_compact<<<(unsigned)((n + 4095) / 4096), 256, 0, ctx->stream>>>(n, const_cast<uint8_t*>(act_in), list, cnt);
+    const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
+#define LP(LL, VV, SS)                                                                                        \
+  k_assign_list<LL, VV, SS><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
+                                                           acc, eacc, list, cnt, rel, vec_x ? 1 : 0,            \
+                                                           vec_c ? 1 : 0, job_of, kbase, act_out)
+#define LPS(LL, VV)     \
+  if (S <= 1)           \
+    LP(LL, VV, 1);      \
+  else if (S <= 2)      \
+    LP(LL, VV, 2);      \
+  else if (S <= 4)      \
+    LP(LL, VV, 4);      \
+  else                  \
+    LP(LL, VV, 8);
+    if (V == 4) {
+      switch (L) {
+        case 4: LPS(4, 4) break;
+        case 8: LPS(8, 4) break;
+        case 16: LPS(16, 4) break;
+        case 32: LPS(32, 4) break;
+        default: LPS(64, 4) break;
+      }
+    } else {
+      switch (L) {
+        case 4: LPS(4, 8) break;
+        case 8: LPS(8, 8) break;
+        case 16: LPS(16, 8) break;
+        case 32: LPS(32, 8) break;
+        default: LPS(64, 8) break;
+      }
+    }
+#undef LPS
+#undef LP
+    return knnkm_check(ctx, "knn_assign (active set)");
+  }
   auto launch = [&](AssignCfg cfg) {
   if (V == 4) {
     switch (L) {

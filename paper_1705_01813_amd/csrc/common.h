@@ -40,6 +40,7 @@ struct knnkm_ctx {
   bool graphs = true;
   // launch shapes of the assignment chosen by timing the candidates once
   bool autotune = true;
+  bool active_sets = true;  // fit sweeps look only at samples that can change
   int assign_gs = 0, assign_pb = 64, assign_lazy = 0;  // forced assignment shape (gs = 0: automatic)
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   bool capturing = false;
@@ -189,7 +190,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                        int64_t* n_moved, const int32_t* order, bool dense,
                        const int32_t* job_of = nullptr, const int32_t* kbase = nullptr, int use = KS_USE_CALL,
-                       int64_t* n_eval = nullptr);
+                       int64_t* n_eval = nullptr, const uint8_t* act_in = nullptr, uint8_t* act_out = nullptr);
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
                          int32_t* labels);
@@ -225,8 +226,16 @@ knnkm_status ks_fx_scales(knnkm_ctx* ctx, const uint32_t* jmax, int m, const int
                           int32_t* cs);
 knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32_t d, const int32_t* cs,
                             uint64_t* D);
-knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, const int32_t* cur,
+knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, int32_t* cur,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
-                          int32_t* dirty, float* C, double* Iterm);
+                          int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off = nullptr,
+                          const int32_t* rev_src = nullptr, uint8_t* act_out = nullptr);
+// Active-set marks of the samples moved between cur and nxt and of the rows
+// listing them (reverse lists of the graph); moved labels copied into cur.
+knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,
+                           const int32_t* rev_src, uint8_t* act_out);
+// Reverse lists of an n x kappa graph: rev_off (n + 1), rev_src (n * kappa).
+knnkm_status ks_reverse_graph(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, int32_t* rev_off,
+                              int32_t* rev_src);
 knnkm_status ks_fill_i64(knnkm_ctx* ctx, int64_t* p, int64_t count, int64_t v);
 knnkm_status ks_fill_i32(knnkm_ctx* ctx, int32_t* p, int64_t count, int32_t v);

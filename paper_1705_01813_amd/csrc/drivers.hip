@@ -385,24 +385,49 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     k_permute_graph<<<grid_for(n * kappa, 256, 16384), 256, 0, ctx->stream>>>(G_ids, kappa, perm, inv, n, Gp);
   k_gather_i32<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(labels, perm, n, labp);
   KNNKM_TRY(knnkm_check(ctx, "fit working copy"));
+  // Active sets: after the first sweep only the samples that had several
+  // candidates, moved, or have a neighbour that moved are looked at; every
+  // other sample still has its own cluster as the only candidate and keeps
+  // its label (same results).  One flag array per label buffer: the flags
+  // next to a label array mark the samples the sweep reading it evaluates.
+  const bool use_act = ctx->active_sets && use_graph && n * (int64_t)kappa < INT32_MAX;
+  int32_t *rev_off = nullptr, *rev_src = nullptr;
+  uint8_t *act_p = nullptr, *act_2 = nullptr;
+  if (use_act) {
+    rev_off = (int32_t*)knnkm_ws(ctx, "fit_rev_off", sizeof(int32_t) * (size_t)(n + 1));
+    rev_src = (int32_t*)knnkm_ws(ctx, "fit_rev_src", sizeof(int32_t) * (size_t)n * kappa);
+    act_p = (uint8_t*)knnkm_ws(ctx, "fit_act_p", (size_t)(n + 3) / 4 * 4);
+    act_2 = (uint8_t*)knnkm_ws(ctx, "fit_act_2", (size_t)n);
+    if (!rev_off || !rev_src || !act_p || !act_2) return KNNKM_ENOMEM;
+    KNNKM_TRY(ks_reverse_graph(ctx, Gp, n, kappa, rev_off, rev_src));
+    // the first sweep writes every flag next to its output; the other array
+    // starts clear
+    KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)act_p, (n + 3) / 4, 0));
+  }
+  auto act_for = [&](const int32_t* lab) -> uint8_t* {
+    return use_act ? (lab == labp ? act_p : act_2) : nullptr;
+  };
   mark(3);
 
   // one sweep: assignment, update, distortion of every job
   auto sweep = [&](const int32_t* cu, int32_t* nx, int64_t* mv, bool first, int64_t* ev) -> knnkm_status {
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
-                     J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT, ev);
+                     J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT, ev, first ? nullptr : act_for(cu),
+                     act_for(nx));
   };
   // The first sweep moves a large share of the samples away from the
   // initial partition: its update rebuilds the sums from a label sort and
   // the segmented float64 sums (as at initialisation) and converts them to
   // fixed point; later sweeps apply only their moves.
-  auto update = [&](const int32_t* cu, const int32_t* nx, double* tr, bool full) -> knnkm_status {
+  auto update = [&](int32_t* cu, const int32_t* nx, double* tr, bool full) -> knnkm_status {
     if (full) {
       KNNKM_TRY(ks_label_sort(ctx, nx, n, K, counts, off, mem));
       KNNKM_TRY(ks_segsum(ctx, Xp, n, d, d, K, counts, off, mem, C, sums0, Iterm));
       KNNKM_TRY(ks_fx_from_f64(ctx, sums0, K, d, cs, Dfx));
+      if (use_act) KNNKM_TRY(ks_mark_moved(ctx, n, cu, nx, rev_off, rev_src, act_for(nx)));
     } else {
-      KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty, C, Iterm));
+      KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty, C, Iterm, rev_off, rev_src,
+                             act_for(nx)));
     }
     k_range_trace<<<m, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, tr);
     return knnkm_check(ctx, "fit iteration");
@@ -503,6 +528,12 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   *iters_run = it;
   ctx->fit_iters = it;
   ctx->fit_evals = evals;
+  return KNNKM_OK;
+}
+
+extern "C" knnkm_status knnkm_enable_active_sets(knnkm_ctx* ctx, int32_t on) {
+  if (!ctx) return KNNKM_EINVAL;
+  ctx->active_sets = on != 0;
   return KNNKM_OK;
 }
 

@@ -93,13 +93,28 @@ __global__ void k_fx_from_f64(const double* __restrict__ sums, int64_t kd, int d
   }
 }
 
+// Active sets: a moved sample, and every sample that has it as a neighbour
+// (reverse lists rev_off/rev_src of the fixed graph), must be looked at in
+// the next sweep; act_out[.] = 1 for all of them (the same value from every
+// writer, so the order of the stores does not matter).
+__device__ inline void mark_moved(int64_t p, const int32_t* __restrict__ rev_off, const int32_t* __restrict__ rev_src,
+                                  uint8_t* __restrict__ act_out, int lane) {
+  if (lane == 0) act_out[p] = 1;
+  for (int32_t e = rev_off[p] + lane; e < rev_off[p + 1]; e += 64) act_out[rev_src[e]] = 1;
+}
+
 // Every moved sample: its row out of D[old], into D[new]; sizes and dirty
-// flags of both clusters.  A wavefront scans 64 positions and then applies
-// its moved samples one at a time, lanes over the dimensions.
+// flags of both clusters.  With act_out (active sets) also its marks, and
+// its new label written over the old one in cur, so that the two label
+// arrays agree outside the samples the next sweep writes.  A wavefront scans
+// 64 positions and then applies its moved samples one at a time, lanes over
+// the dimensions.
 __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, int64_t n, int d,
-                                                  const int32_t* __restrict__ cur, const int32_t* __restrict__ nxt,
+                                                  int32_t* __restrict__ cur, const int32_t* __restrict__ nxt,
                                                   const int32_t* __restrict__ cs, uint64_t* __restrict__ D,
-                                                  int32_t* __restrict__ counts, int32_t* __restrict__ dirty) {
+                                                  int32_t* __restrict__ counts, int32_t* __restrict__ dirty,
+                                                  const int32_t* __restrict__ rev_off,
+                                                  const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -116,10 +131,12 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
       atomicAdd(&counts[b], 1);
       atomicOr(&dirty[a], 1);
       atomicOr(&dirty[b], 1);
+      if (act_out) cur[p] = b;
     }
     for (uint64_t M = __ballot(moved); M; M &= M - 1) {
       const int q = (int)__builtin_ctzll(M);
       const int from = __shfl(a, q, 64), to = __shfl(b, q, 64);
+      if (act_out) mark_moved(base + q, rev_off, rev_src, act_out, lane);
       const int s = cs[to];  // both clusters belong to the sample's job
       const float* row = X + (base + q) * (int64_t)d;
       for (int t = lane; t < d; t += 64) {
@@ -130,6 +147,44 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
         fx_atomic_add(D + 2 * ((int64_t)from * d + t), hi, lo);
       }
     }
+  }
+}
+
+// Active-set marks of the moved samples alone (the sweep whose sums are
+// rebuilt rather than updated), with their labels synchronised as above.
+__global__ __launch_bounds__(256) void k_mark_moved(int64_t n, int32_t* __restrict__ cur,
+                                                    const int32_t* __restrict__ nxt,
+                                                    const int32_t* __restrict__ rev_off,
+                                                    const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+    const int64_t p = base + lane;
+    int b = 0;
+    const bool moved = p < n && cur[p] != (b = nxt[p]);
+    if (moved) cur[p] = b;
+    for (uint64_t M = __ballot(moved); M; M &= M - 1)
+      mark_moved(base + (int)__builtin_ctzll(M), rev_off, rev_src, act_out, lane);
+  }
+}
+
+// Reverse lists of a graph of n rows with kappa ids each: rev_src holds, for
+// every target p in rev_off[p] .. rev_off[p+1], the rows that list p (in no
+// particular order).  Ids outside [0, n) are left out.
+__global__ void k_rev_count(const int32_t* __restrict__ G, int64_t ne, int64_t n, int32_t* __restrict__ cnt) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t t = G[e];
+    if (t >= 0 && t < n) atomicAdd(&cnt[t], 1);
+  }
+}
+__global__ void k_rev_fill(const int32_t* __restrict__ G, int64_t ne, int64_t n, int kappa,
+                           const int32_t* __restrict__ off, int32_t* __restrict__ cursor, int32_t* __restrict__ src) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t t = G[e];
+    if (t < 0 || t >= n) continue;
+    const int32_t pos = atomicAdd(&cursor[t], 1);
+    src[off[t] + pos] = (int32_t)(e / kappa);
   }
 }
 
@@ -179,10 +234,31 @@ knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32
   return knnkm_check(ctx, "fixed-point sums");
 }
 
-knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, const int32_t* cur,
+knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, int32_t* cur,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
-                          int32_t* dirty, float* C, double* Iterm) {
-  k_fx_moves<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty);
+                          int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off, const int32_t* rev_src,
+                          uint8_t* act_out) {
+  k_fx_moves<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty, rev_off,
+                                                              rev_src, act_out);
   k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, dirty, C, Iterm);
   return knnkm_check(ctx, "incremental update");
+}
+
+knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,
+                           const int32_t* rev_src, uint8_t* act_out) {
+  k_mark_moved<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, cur, nxt, rev_off, rev_src, act_out);
+  return knnkm_check(ctx, "active-set marks");
+}
+
+knnkm_status ks_reverse_graph(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, int32_t* rev_off,
+                              int32_t* rev_src) {
+  KNNKM_WS(ctx, cursor, int32_t, "rev_cursor", n);
+  const int64_t ne = n * (int64_t)kappa;
+  KNNKM_TRY(ks_fill_i32(ctx, rev_off, n + 1, 0));
+  KNNKM_TRY(ks_fill_i32(ctx, cursor, n, 0));
+  k_rev_count<<<grid_for(ne, 256, 16384), 256, 0, ctx->stream>>>(G, ne, n, rev_off);
+  KNNKM_TRY(knnkm_check(ctx, "reverse graph counts"));
+  KNNKM_TRY(ks_scan_exclusive(ctx, rev_off, rev_off, n, true));
+  k_rev_fill<<<grid_for(ne, 256, 16384), 256, 0, ctx->stream>>>(G, ne, n, kappa, rev_off, cursor, rev_src);
+  return knnkm_check(ctx, "reverse graph");
 }

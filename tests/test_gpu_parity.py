@@ -422,6 +422,70 @@ def test_fit_update_exact_at_scale(ctx):
     assert np.array_equal(runs[0][2], runs[1][2])
 
 
+@pytest.mark.parametrize("n,d,k,kappa,T,early", [(20000, 32, 200, 10, 12, False), (200_000, 128, 2000, 20, 9, False),
+                                                 (30000, 16, 300, 8, 15, True), (5000, 512, 60, 20, 7, False)])
+def test_fit_active_sets_same_bits(ctx, n, d, k, kappa, T, early):
+    """From the second sweep on the fit looks only at samples that had several
+    candidates, moved, or have a neighbour that moved; with active sets off
+    every sample is looked at.  Labels, centroids, counts, trace and the
+    number of sweeps are the same bits, with graph replay and with early
+    stopping."""
+    say("fit active sets", n, d, k, kappa, T, early)
+    X = dev(datagen.mixture(n, d, k, seed=n + 3))
+    p = knnkm.default_params(kappa=kappa, max_iters=T, seed=9, early_stop=early)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    knnkm.knn_build(ctx, X, p, gi, gd)
+
+    def run(active):
+        knnkm.knnkm_enable_active_sets(ctx, active)
+        lab = torch.empty(n, dtype=torch.int32, device=DEV)
+        C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+        cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+        tr, it = knnkm.knn_kmeans_fit(ctx, X, k, gi, p, lab, C, cnt)
+        return host(lab), host(C), host(cnt), np.asarray(tr), it
+
+    try:
+        ref = run(False)
+        for rep in range(2):
+            got = run(True)
+            for a, b in zip(ref[:4], got[:4]):
+                assert np.array_equal(a, b), rep
+            assert got[4] == ref[4]
+    finally:
+        knnkm.knnkm_enable_active_sets(ctx, True)
+
+
+def test_batch_active_sets_same_bits(ctx):
+    """The same for a batched fit (jobs of different sizes, one of them with
+    kappa >= k, evaluated in full every sweep)."""
+    sizes = [3000, 700, 1500, 64, 2200]
+    Xs, n_off, ks, seeds = _batch(sizes, 24, seed=41)
+    ks[3] = 2  # kappa >= k: that job is exhaustive
+    X = dev(np.concatenate(Xs))
+    n, kappa, K = int(n_off[-1]), 10, sum(ks)
+    p = knnkm.default_params(kappa=kappa, max_iters=9, seed=4)
+    say("batch active sets", sizes, ks)
+
+    def run(active):
+        knnkm.knnkm_enable_active_sets(ctx, active)
+        gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+        gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+        lab = torch.empty(n, dtype=torch.int32, device=DEV)
+        C = torch.empty((K, 24), dtype=torch.float32, device=DEV)
+        cnt = torch.empty(K, dtype=torch.int32, device=DEV)
+        tr = knnkm.knnkm_fit_batched(ctx, X, n_off, ks, seeds, p, gi, gd, lab, C, cnt)
+        return host(gi), host(lab), host(C), host(cnt), np.asarray(tr)
+
+    try:
+        ref = run(False)
+        got = run(True)
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b)
+    finally:
+        knnkm.knnkm_enable_active_sets(ctx, True)
+
+
 # ----------------------------------------------------------------- batching --
 def _batch(sizes, d, seed):
     Xs = [datagen.mixture(nq, d, max(2, nq // 32), seed=seed + q) for q, nq in enumerate(sizes)]
