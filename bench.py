@@ -298,13 +298,14 @@ def bench_serving(seconds, seed, log, rate=None):
     }
 
 
-def assign_bytes(n, d, k, kappa, evaluated=None):
-    # graph rows, neighbour labels, own label, output label, visiting order
-    # for every sample; the rows of the samples whose distances are
-    # evaluated (all of them unless counted: a sample whose neighbours all
-    # share its cluster needs none); centroids (each read once)
+def assign_bytes(n, d, k, kappa, evaluated=None, listed=None):
+    # per sample looked at: graph row, neighbour labels, own and output label,
+    # visiting order; per sample whose distances are evaluated: its row (a
+    # sample whose neighbours all share its cluster needs none); centroids
+    # once; with active sets, one flag byte per sample for the list
     ev = n if evaluated is None else evaluated
-    return n * (8 * kappa + 12) + ev * 4 * d + 4 * k * d
+    ls = n if listed is None else listed
+    return ls * (8 * kappa + 12) + ev * 4 * d + 4 * k * d + (n if listed is not None else 0)
 
 
 def make_data(cfg, seed, device):
@@ -446,7 +447,8 @@ def main():
     knnkm.knnkm_enable_timing(ctx, 1)
     assign_ms = kp["assign_ms"] / max(1.0, kp["assign_launches"])
     evaluated = kp["assign_evaluated"] / max(1.0, kp["assign_launches"]) if kp["assign_evaluated"] >= 0 else None
-    bytes_assign = assign_bytes(n, d, k, kappa, evaluated)
+    listed = kp["assign_listed"] / max(1.0, kp["assign_launches"]) if kp["assign_listed"] >= 0 else None
+    bytes_assign = assign_bytes(n, d, k, kappa, evaluated, listed)
     achieved = bytes_assign / (assign_ms / 1000.0) / 1e9
     out = {
         "metric": "samples assigned/s per iteration",
@@ -474,6 +476,7 @@ def main():
                      "traffic": measured_traffic(args.config),
                      "algorithmic_bytes_per_launch": bytes_assign,
                      "evaluated_samples_per_launch": evaluated,
+                     "listed_samples_per_launch": listed,
                      "launches_timed": kp["assign_launches"]},
     }
     out["autotuned_shapes"] = [ln for ln in knnkm.knnkm_autotune_table().splitlines() if ln]

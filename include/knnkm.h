@@ -334,7 +334,9 @@ knnkm_status knnkm_autotune_table(char* buf, int64_t len, int64_t* needed);
  *   out[4] iterations run (count), out[5] assignment launches timed (count)
  *   out[6] samples whose candidate distances those launches evaluated, summed
  *          (count; a sample whose neighbours all share its cluster has its
- *          own cluster as the only candidate and needs none) (on = 2) */
+ *          own cluster as the only candidate and needs none) (on = 2)
+ *   out[7] samples those launches looked at, summed (count; all of them in
+ *          the first sweep, the active set after it) (on = 2) */
 knnkm_status knnkm_enable_timing(knnkm_ctx* ctx, int32_t on);
 knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t count);
 

@@ -273,10 +273,12 @@ __global__ __launch_bounds__(256) void k_assign(
 // reserves its share of the list with one atomic (blocks land in varying
 // order; decisions do not depend on the order of the list).
 __global__ __launch_bounds__(256) void k_act_compact(int64_t n, uint8_t* __restrict__ act, int32_t* __restrict__ list,
-                                                     int32_t* __restrict__ count) {
+                                                     int32_t* __restrict__ count, int32_t* __restrict__ clear_other) {
   constexpr int RW = 16;  // rounds of 64 positions per wavefront
   __shared__ int32_t wtot[4], wbase[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the other list's counter is free during this sweep: clear it for the next
+  if (clear_other && blockIdx.x == 0 && threadIdx.x == 0) *clear_other = 0;
   const int64_t base = ((int64_t)blockIdx.x * 4 + w) * (RW * 64);
   uint64_t m[RW];
   int32_t tot = 0;
@@ -321,7 +323,8 @@ __global__ __launch_bounds__(256) void k_assign_list(
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
     unsigned long long* __restrict__ moved_acc, unsigned long long* __restrict__ eval_acc,
     const int32_t* __restrict__ list, const int32_t* __restrict__ count, double rel, int vec_x, int vec_c,
-    const int* __restrict__ job_of, const int* __restrict__ kbase, uint8_t* __restrict__ act_out) {
+    const int* __restrict__ job_of, const int* __restrict__ kbase, uint8_t* __restrict__ act_out,
+    int64_t* __restrict__ n_listed) {
   constexpr int GW = 64 / L;
   __shared__ unsigned int block_moved, block_eval;
   if (threadIdx.x == 0) {
@@ -333,6 +336,7 @@ __global__ __launch_bounds__(256) void k_assign_list(
   const int g = lane / L, j = lane % L;
   const uint64_t gmask = group_mask<L>(g);
   const int cnt = *count;
+  if (n_listed && blockIdx.x == 0 && threadIdx.x == 0) *n_listed = cnt;
   const int gid = (blockIdx.x * 4 + w) * GW + g;
   const int ngroups = gridDim.x * 4 * GW;
   unsigned int my_moved = 0, my_eval = 0;
@@ -557,9 +561,11 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                        int64_t* n_moved, const int32_t* order, bool dense, const int32_t* job_of,
-                       const int32_t* kbase, int use, int64_t* n_eval, const uint8_t* act_in, uint8_t* act_out) {
-  if (n_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
+                       const int32_t* kbase, int use, int64_t* n_eval, const uint8_t* act_in, uint8_t* act_out,
+                       int64_t* n_active, int32_t* list_count, int32_t* list_count_other, bool zero_moved) {
+  if (n_moved && zero_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
   if (n_eval) KNNKM_TRY(ks_fill_i64(ctx, n_eval, 1, 0));
+  if (n_active && !(act_in && !best_d2 && !order && !dense)) KNNKM_TRY(ks_fill_i64(ctx, n_active, 1, n));
   if (n == 0) return KNNKM_OK;
   const bool all_dense = dense;
   int L, V;
@@ -580,14 +586,19 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   if (act_in && !best_d2 && !order && !all_dense) {
     // active-set sweep: list the flagged samples, then assign them
     KNNKM_WS(ctx, list, int32_t, "as_act_list", n);
-    KNNKM_WS(ctx, cnt, int32_t, "as_act_count", 1);
-    KNNKM_TRY(ks_fill_i32(ctx, cnt, 1, 0));
-    k_act_compact<<<(unsigned)((n + 4095) / 4096), 256, 0, ctx->stream>>>(n, const_cast<uint8_t*>(act_in), list, cnt);
+    int32_t* cnt = list_count;
+    if (!cnt) {
+      cnt = (int32_t*)knnkm_ws(ctx, "as_act_count", sizeof(int32_t));
+      if (!cnt) return KNNKM_ENOMEM;
+      KNNKM_TRY(ks_fill_i32(ctx, cnt, 1, 0));
+    }
+    k_act_compact<<<(unsigned)((n + 4095) / 4096), 256, 0, ctx->stream>>>(n, const_cast<uint8_t*>(act_in), list, cnt,
+                                                                          list_count_other);
     const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
 #define LP(LL, VV, SS)                                                                                        \
   k_assign_list<LL, VV, SS><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
                                                            acc, eacc, list, cnt, rel, vec_x ? 1 : 0,            \
-                                                           vec_c ? 1 : 0, job_of, kbase, act_out)
+                                                           vec_c ? 1 : 0, job_of, kbase, act_out, n_active)
 #define LPS(LL, VV)     \
   if (S <= 1)           \
     LP(LL, VV, 1);      \

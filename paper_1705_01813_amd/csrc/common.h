@@ -35,6 +35,7 @@ struct knnkm_ctx {
   int assign_ev0 = -1, assign_n = 0;  // pairs around the assignment launches of the fit
   int fit_iters = 0;                  // sweeps of the last fit
   const int64_t* fit_evals = nullptr;  // per-sweep evaluated-sample counts of the last timed fit (device)
+  const int64_t* fit_actives = nullptr;  // per-sweep listed-sample counts of the last timed fit (device)
   // fit iterations replayed from a captured HIP graph (captured on a private
   // stream, launched on `stream`)
   bool graphs = true;
@@ -190,7 +191,9 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                        int64_t* n_moved, const int32_t* order, bool dense,
                        const int32_t* job_of = nullptr, const int32_t* kbase = nullptr, int use = KS_USE_CALL,
-                       int64_t* n_eval = nullptr, const uint8_t* act_in = nullptr, uint8_t* act_out = nullptr);
+                       int64_t* n_eval = nullptr, const uint8_t* act_in = nullptr, uint8_t* act_out = nullptr,
+                       int64_t* n_active = nullptr, int32_t* list_count = nullptr,
+                       int32_t* list_count_other = nullptr, bool zero_moved = true);
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
                          int32_t* labels);

@@ -51,6 +51,7 @@ knnkm_status knnkm_ws_release(knnkm_ctx* ctx) {
     if (kv.second.ptr) (void)hipFreeAsync(kv.second.ptr, ctx->stream);
   ctx->ws.clear();
   ctx->fit_evals = nullptr;
+  ctx->fit_actives = nullptr;
   tm_plan_free(ctx->tm_plan);  // its device tables were workspace
   ctx->tm_plan = nullptr;
   KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -199,7 +200,7 @@ static double ev_ms(knnkm_ctx* ctx, int a) {
 
 extern "C" knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t count) {
   if (!ctx || !out || count < 1) return KNNKM_EINVAL;
-  double v[7] = {-1.0, -1.0, -1.0, -1.0, 0.0, 0.0, -1.0};
+  double v[8] = {-1.0, -1.0, -1.0, -1.0, 0.0, 0.0, -1.0, -1.0};
   if (!ctx->dry) {
     (void)hipSetDevice(ctx->device);
     v[0] = ev_ms(ctx, ctx->build_ev);
@@ -212,21 +213,23 @@ extern "C" knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t c
     }
     v[4] = ctx->fit_ev >= 0 ? (double)ctx->fit_iters : 0.0;
     v[5] = (double)ctx->assign_n;
-    if (ctx->fit_evals && ctx->assign_n > 0 && count > 6) {
+    const int64_t* per_sweep[2] = {ctx->fit_evals, ctx->fit_actives};
+    for (int c = 0; c < 2; ++c) {
+      if (!per_sweep[c] || ctx->assign_n <= 0 || count <= 6 + c) continue;
       std::vector<int64_t> ev((size_t)ctx->assign_n);
-      if (hipMemcpyAsync(ev.data(), ctx->fit_evals + 1, sizeof(int64_t) * ev.size(), hipMemcpyDeviceToHost,
+      if (hipMemcpyAsync(ev.data(), per_sweep[c] + 1, sizeof(int64_t) * ev.size(), hipMemcpyDeviceToHost,
                          ctx->stream) == hipSuccess &&
           hipStreamSynchronize(ctx->stream) == hipSuccess) {
         double s = 0.0;
         for (int64_t e : ev) s += (double)e;
-        v[6] = s;
+        v[6 + c] = s;
       } else {
         (void)hipGetLastError();
       }
     }
   }
-  for (int i = 0; i < count && i < 7; ++i) out[i] = v[i];
-  for (int i = 7; i < count; ++i) out[i] = 0.0;
+  for (int i = 0; i < count && i < 8; ++i) out[i] = v[i];
+  for (int i = 8; i < count; ++i) out[i] = 0.0;
   return KNNKM_OK;
 }
 

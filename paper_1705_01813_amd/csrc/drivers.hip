@@ -102,12 +102,15 @@ __global__ void k_scatter_i32(const int32_t* __restrict__ src, const int32_t* __
 
 // Per-iteration bookkeeping inside a captured fit: the moved count and the
 // distortions of iteration *it go to their slots, then *it advances.
-__global__ void k_fit_book(const int64_t* __restrict__ mv_slot, int64_t* __restrict__ moved,
+__global__ void k_fit_book(int64_t* __restrict__ mv_slot, int64_t* __restrict__ moved,
                            const double* __restrict__ tr_slot, double* __restrict__ trace, int m,
                            int32_t* __restrict__ it) {
   const int t = *it;
   for (int q = threadIdx.x; q < m; q += blockDim.x) trace[(int64_t)t * m + q] = tr_slot[q];
-  if (threadIdx.x == 0) moved[t] = *mv_slot;
+  if (threadIdx.x == 0) {
+    moved[t] = *mv_slot;
+    *mv_slot = 0;  // the next sweep accumulates from zero
+  }
   __syncthreads();
   if (threadIdx.x == 0) *it = t + 1;
 }
@@ -314,6 +317,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   KNNKM_WS(ctx, rowsq, double, "fit_rowsq", n);
   KNNKM_WS(ctx, sxx, double, "fit_sxx", m);
   KNNKM_WS(ctx, moved, int64_t, "fit_moved", (int64_t)T + 1);
+  KNNKM_TRY(ks_fill_i64(ctx, moved, (int64_t)T + 1, 0));
   // phase events: 2 fit start, 3 initialisation done, 4 iterations done,
   // 6+2j / 7+2j around the assignment of iteration j+1
   auto mark = [&](int e) {
@@ -393,7 +397,11 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   const bool use_act = ctx->active_sets && use_graph && n * (int64_t)kappa < INT32_MAX;
   int32_t *rev_off = nullptr, *rev_src = nullptr;
   uint8_t *act_p = nullptr, *act_2 = nullptr;
+  int32_t* lcnt = nullptr;  // list counters, one per flag array
   if (use_act) {
+    lcnt = (int32_t*)knnkm_ws(ctx, "fit_list_counts", 2 * sizeof(int32_t));
+    if (!lcnt) return KNNKM_ENOMEM;
+    KNNKM_TRY(ks_fill_i32(ctx, lcnt, 2, 0));
     rev_off = (int32_t*)knnkm_ws(ctx, "fit_rev_off", sizeof(int32_t) * (size_t)(n + 1));
     rev_src = (int32_t*)knnkm_ws(ctx, "fit_rev_src", sizeof(int32_t) * (size_t)n * kappa);
     act_p = (uint8_t*)knnkm_ws(ctx, "fit_act_p", (size_t)(n + 3) / 4 * 4);
@@ -407,13 +415,19 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   auto act_for = [&](const int32_t* lab) -> uint8_t* {
     return use_act ? (lab == labp ? act_p : act_2) : nullptr;
   };
+  auto cnt_for = [&](const int32_t* lab) -> int32_t* {
+    return use_act ? (lab == labp ? lcnt : lcnt + 1) : nullptr;
+  };
   mark(3);
 
   // one sweep: assignment, update, distortion of every job
-  auto sweep = [&](const int32_t* cu, int32_t* nx, int64_t* mv, bool first, int64_t* ev) -> knnkm_status {
+  auto sweep = [&](const int32_t* cu, int32_t* nx, int64_t* mv, bool first, int64_t* ev,
+                   int64_t* ac) -> knnkm_status {
+    // moved counters are cleared once per fit (eager sweeps: one slot each)
+    // or by the bookkeeping kernel (graph replays)
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
                      J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT, ev, first ? nullptr : act_for(cu),
-                     act_for(nx));
+                     act_for(nx), ac, cnt_for(cu), cnt_for(nx), false);
   };
   // The first sweep moves a large share of the samples away from the
   // initial partition: its update rebuilds the sums from a label sort and
@@ -433,20 +447,22 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     return knnkm_check(ctx, "fit iteration");
   };
   ctx->fit_evals = nullptr;
+  ctx->fit_actives = nullptr;
   const bool time_all = ctx->timing >= 2;
-  // with every assignment timed, also count the samples whose distances
-  // each one evaluated
-  int64_t* evals = nullptr;
+  // with every assignment timed, also count the samples each one looked at
+  // and the samples whose distances it evaluated
+  int64_t *evals = nullptr, *actives = nullptr;
   if (time_all) {
     evals = (int64_t*)knnkm_ws(ctx, "fit_evals", sizeof(int64_t) * (size_t)(T + 1));
-    if (!evals) return KNNKM_ENOMEM;
+    actives = (int64_t*)knnkm_ws(ctx, "fit_actives", sizeof(int64_t) * (size_t)(T + 1));
+    if (!evals || !actives) return KNNKM_ENOMEM;
   }
   int32_t* cur = labp;
   int32_t* nxt = lab2;
   int it = 0;
   auto eager = [&](int t) -> knnkm_status {
     if (time_all) mark(6 + 2 * (t - 1));
-    KNNKM_TRY(sweep(cur, nxt, moved + t, t == 1, evals ? evals + t : nullptr));
+    KNNKM_TRY(sweep(cur, nxt, moved + t, t == 1, evals ? evals + t : nullptr, actives ? actives + t : nullptr));
     if (time_all) {
       mark(7 + 2 * (t - 1));
       ctx->assign_n = t;
@@ -477,6 +493,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     KNNKM_WS(ctx, mv_slot, int64_t, "fit_mv_slot", 1);
     KNNKM_WS(ctx, tr_slot, double, "fit_tr_slot", m);
     KNNKM_TRY(ks_fill_i32(ctx, book_it, 1, t));
+    KNNKM_TRY(ks_fill_i64(ctx, mv_slot, 1, 0));
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool ok = true;
@@ -491,11 +508,11 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       ok = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
         ctx->capturing = true;
-        knnkm_status st = sweep(cur, nxt, mv_slot, false, nullptr);
+        knnkm_status st = sweep(cur, nxt, mv_slot, false, nullptr, nullptr);
         if (st == KNNKM_OK) st = update(cur, nxt, tr_slot, false);
         if (st == KNNKM_OK) {
           k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
-          st = sweep(nxt, cur, mv_slot, false, nullptr);
+          st = sweep(nxt, cur, mv_slot, false, nullptr, nullptr);
         }
         if (st == KNNKM_OK) st = update(nxt, cur, tr_slot, false);
         if (st == KNNKM_OK) k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
@@ -528,6 +545,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   *iters_run = it;
   ctx->fit_iters = it;
   ctx->fit_evals = evals;
+  ctx->fit_actives = actives;
   return KNNKM_OK;
 }
 

@@ -379,7 +379,8 @@ def knnkm_enable_timing(ctx, on=True):
     _chk(ctx.handle, lib().knnkm_enable_timing(ctx.handle, int(on)))
 
 
-PHASES = ("build_ms", "fit_init_ms", "fit_iters_ms", "assign_ms", "iters", "assign_launches", "assign_evaluated")
+PHASES = ("build_ms", "fit_init_ms", "fit_iters_ms", "assign_ms", "iters", "assign_launches", "assign_evaluated",
+          "assign_listed")
 
 
 def knnkm_phase_times(ctx):
