@@ -267,9 +267,11 @@ __global__ __launch_bounds__(256) void k_assign(
   }
 }
 
-// Active-set sweeps.  k_act_compact lists the positions whose flag is set
-// and clears the flags it read, which makes that array the clean output of
-// the next sweep.  A block takes CPB = 4 x 16 x 64 consecutive positions and
+// Active-set sweeps.  A sample's flag has bit 0 when it had several
+// candidates in the last sweep and bit 1 when its own or a neighbour's label
+// changed since.  k_act_compact lists the positions whose flag is set (bit 1
+// carried in the sign bit of the entry) and clears the flags it read, which
+// makes that array the clean output of the next sweep.  A block takes CPB = 4 x 16 x 64 consecutive positions and
 // reserves its share of the list with one atomic (blocks land in varying
 // order; decisions do not depend on the order of the list).
 __global__ __launch_bounds__(256) void k_act_compact(int64_t n, uint8_t* __restrict__ act, int32_t* __restrict__ list,
@@ -281,14 +283,17 @@ __global__ __launch_bounds__(256) void k_act_compact(int64_t n, uint8_t* __restr
   if (clear_other && blockIdx.x == 0 && threadIdx.x == 0) *clear_other = 0;
   const int64_t base = ((int64_t)blockIdx.x * 4 + w) * (RW * 64);
   uint64_t m[RW];
+  bool chg[RW];
   int32_t tot = 0;
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
     const int64_t p = base + r * 64 + lane;
     bool a = false;
     if (p < n) {
-      a = act[p] != 0;
+      const uint8_t f = act[p];
+      a = f != 0;
       if (a) act[p] = 0;
+      chg[r] = (f & 2) != 0;
     }
     m[r] = __ballot(a);
     tot += (int32_t)__popcll(m[r]);
@@ -307,7 +312,9 @@ __global__ __launch_bounds__(256) void k_act_compact(int64_t n, uint8_t* __restr
   int32_t at = wbase[w];
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
-    if ((m[r] >> lane) & 1ull) list[at + __popcll(m[r] & lanes_below())] = (int32_t)(base + r * 64 + lane);
+    if ((m[r] >> lane) & 1ull)
+      list[at + __popcll(m[r] & lanes_below())] =
+          (int32_t)((uint32_t)(base + r * 64 + lane) | (chg[r] ? 0x80000000u : 0u));
     at += (int32_t)__popcll(m[r]);
   }
 }
@@ -316,7 +323,11 @@ __global__ __launch_bounds__(256) void k_act_compact(int64_t n, uint8_t* __restr
 // through the same candidate collection, float32 pass and float64 pass as
 // k_assign with one sample per group, so labels are the same bits.  Labels
 // of unlisted samples are not written: the update keeps both label arrays
-// equal outside the samples a sweep moves.  act_out as in k_assign.
+// equal outside the samples a sweep moves.  act_out as in k_assign.  A
+// listed sample whose candidate set is unchanged (bit 1 clear) and none of
+// whose candidate centroids changed in the last update (cdirty, per cluster;
+// null: all changed) has all the inputs of its last decision, to stay, so
+// it stays without a distance being evaluated.
 template <int L, int V, int SM>
 __global__ __launch_bounds__(256) void k_assign_list(
     const float* __restrict__ X, int d, int64_t ldx, const float* __restrict__ C, int k,
@@ -324,7 +335,7 @@ __global__ __launch_bounds__(256) void k_assign_list(
     unsigned long long* __restrict__ moved_acc, unsigned long long* __restrict__ eval_acc,
     const int32_t* __restrict__ list, const int32_t* __restrict__ count, double rel, int vec_x, int vec_c,
     const int* __restrict__ job_of, const int* __restrict__ kbase, uint8_t* __restrict__ act_out,
-    int64_t* __restrict__ n_listed) {
+    int64_t* __restrict__ n_listed, const int32_t* __restrict__ cdirty) {
   constexpr int GW = 64 / L;
   __shared__ unsigned int block_moved, block_eval;
   if (threadIdx.x == 0) {
@@ -345,7 +356,9 @@ __global__ __launch_bounds__(256) void k_assign_list(
   for (int base = first; base < cnt; base += ngroups) {
     const int li = base + g;
     const bool live = li < cnt;  // group-uniform
-    const int64_t i = live ? (int64_t)list[li] : 0;
+    const uint32_t ent = live ? (uint32_t)list[li] : 0u;
+    const bool changed = (ent >> 31) != 0;
+    const int64_t i = (int64_t)(ent & 0x7FFFFFFFu);
     const int cur = live ? lab_in[i] : -1;
     int kb = 0, kc = k;
     bool dn = false;
@@ -372,10 +385,22 @@ __global__ __launch_bounds__(256) void k_assign_list(
 #pragma unroll
     for (int s = 0; s < SM; ++s) other = other || (valid[s] && cv[s] != cur);
     const bool single = live && !dn && cur >= 0 && (__ballot(other) & gmask) == 0;
+    bool cand_dirty = true;
+    if (!changed && !dn && cdirty) {
+      bool any = false;
+#pragma unroll
+      for (int s = 0; s < SM; ++s) any = any || (valid[s] && cdirty[cv[s]] != 0);
+      cand_dirty = (__ballot(any) & gmask) != 0;
+    }
     if (live && single) {  // group-uniform
       if (j == 0) {
         lab_out[i] = cur;
         if (act_out) act_out[i] = 0;
+      }
+    } else if (live && !cand_dirty) {  // same inputs as its last decision: stays
+      if (j == 0) {
+        lab_out[i] = cur;
+        if (act_out) act_out[i] = 1;
       }
     } else if (live) {
       float x[V];
@@ -562,7 +587,8 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,
                        int64_t* n_moved, const int32_t* order, bool dense, const int32_t* job_of,
                        const int32_t* kbase, int use, int64_t* n_eval, const uint8_t* act_in, uint8_t* act_out,
-                       int64_t* n_active, int32_t* list_count, int32_t* list_count_other, bool zero_moved) {
+                       int64_t* n_active, int32_t* list_count, int32_t* list_count_other, bool zero_moved,
+                       const int32_t* cdirty) {
   if (n_moved && zero_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
   if (n_eval) KNNKM_TRY(ks_fill_i64(ctx, n_eval, 1, 0));
   if (n_active && !(act_in && !best_d2 && !order && !dense)) KNNKM_TRY(ks_fill_i64(ctx, n_active, 1, n));
@@ -598,7 +624,8 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
 #define LP(LL, VV, SS)                                                                                        \
   k_assign_list<LL, VV, SS><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
                                                            acc, eacc, list, cnt, rel, vec_x ? 1 : 0,            \
-                                                           vec_c ? 1 : 0, job_of, kbase, act_out, n_active)
+                                                           vec_c ? 1 : 0, job_of, kbase, act_out, n_active,    \
+                                                           cdirty)
 #define LPS(LL, VV)     \
   if (S <= 1)           \
     LP(LL, VV, 1);      \

@@ -193,7 +193,8 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        const int32_t* job_of = nullptr, const int32_t* kbase = nullptr, int use = KS_USE_CALL,
                        int64_t* n_eval = nullptr, const uint8_t* act_in = nullptr, uint8_t* act_out = nullptr,
                        int64_t* n_active = nullptr, int32_t* list_count = nullptr,
-                       int32_t* list_count_other = nullptr, bool zero_moved = true);
+                       int32_t* list_count_other = nullptr, bool zero_moved = true,
+                       const int32_t* cdirty = nullptr);
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
                          int32_t* labels);
@@ -231,8 +232,8 @@ knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32
                             uint64_t* D);
 knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, int32_t* cur,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
-                          int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off = nullptr,
-                          const int32_t* rev_src = nullptr, uint8_t* act_out = nullptr);
+                          int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off,
+                          const int32_t* rev_src, uint8_t* act_out, int32_t* dirty_clear);
 // Active-set marks of the samples moved between cur and nxt and of the rows
 // listing them (reverse lists of the graph); moved labels copied into cur.
 knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,

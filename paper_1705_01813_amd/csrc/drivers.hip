@@ -361,9 +361,13 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   // fixed point, one scale exponent per job)
   KNNKM_WS(ctx, cs, int32_t, "fit_scale", K);
   KNNKM_WS(ctx, Dfx, uint64_t, "fit_dfx", (int64_t)K * d * 2);
+  // clusters whose members changed in a sweep's update, one array per label
+  // buffer (the output buffer of that sweep), read by the next sweep
   KNNKM_WS(ctx, dirty, int32_t, "fit_dirty", K);
+  KNNKM_WS(ctx, dirty2, int32_t, "fit_dirty2", K);
   KNNKM_TRY(ks_fx_scales(ctx, jmax, m, k32, K, cs));
   KNNKM_TRY(ks_fill_i32(ctx, dirty, K, 0));
+  KNNKM_TRY(ks_fill_i32(ctx, dirty2, K, 0));
 
   // The sweeps run on a working copy of X (and of the graph) in the cluster
   // order of the initial partition: rows are then read as streams, and the
@@ -418,6 +422,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   auto cnt_for = [&](const int32_t* lab) -> int32_t* {
     return use_act ? (lab == labp ? lcnt : lcnt + 1) : nullptr;
   };
+  auto dirty_for = [&](const int32_t* lab) -> int32_t* { return lab == labp ? dirty : dirty2; };
   mark(3);
 
   // one sweep: assignment, update, distortion of every job
@@ -427,7 +432,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     // or by the bookkeeping kernel (graph replays)
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
                      J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT, ev, first ? nullptr : act_for(cu),
-                     act_for(nx), ac, cnt_for(cu), cnt_for(nx), false);
+                     act_for(nx), ac, cnt_for(cu), cnt_for(nx), false, first ? nullptr : dirty_for(cu));
   };
   // The first sweep moves a large share of the samples away from the
   // initial partition: its update rebuilds the sums from a label sort and
@@ -439,9 +444,12 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       KNNKM_TRY(ks_segsum(ctx, Xp, n, d, d, K, counts, off, mem, C, sums0, Iterm));
       KNNKM_TRY(ks_fx_from_f64(ctx, sums0, K, d, cs, Dfx));
       if (use_act) KNNKM_TRY(ks_mark_moved(ctx, n, cu, nx, rev_off, rev_src, act_for(nx)));
+      // every centroid was recomputed
+      KNNKM_TRY(ks_fill_i32(ctx, dirty_for(nx), K, 1));
+      KNNKM_TRY(ks_fill_i32(ctx, dirty_for(cu), K, 0));
     } else {
-      KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty, C, Iterm, rev_off, rev_src,
-                             act_for(nx)));
+      KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty_for(nx), C, Iterm, rev_off, rev_src,
+                             act_for(nx), dirty_for(cu)));
     }
     k_range_trace<<<m, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, tr);
     return knnkm_check(ctx, "fit iteration");

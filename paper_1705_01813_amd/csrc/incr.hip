@@ -94,13 +94,15 @@ __global__ void k_fx_from_f64(const double* __restrict__ sums, int64_t kd, int d
 }
 
 // Active sets: a moved sample, and every sample that has it as a neighbour
-// (reverse lists rev_off/rev_src of the fixed graph), must be looked at in
-// the next sweep; act_out[.] = 1 for all of them (the same value from every
-// writer, so the order of the stores does not matter).
+// (reverse lists rev_off/rev_src of the fixed graph), have a new candidate
+// set for the next sweep; bit 1 of their flag says so.  Bit 0 was written
+// by this sweep's assignment, which has finished, so every writer here
+// stores the same value and the order of the stores does not matter.
+__device__ inline void mark_one(uint8_t* __restrict__ act_out, int64_t x) { act_out[x] = act_out[x] | 2; }
 __device__ inline void mark_moved(int64_t p, const int32_t* __restrict__ rev_off, const int32_t* __restrict__ rev_src,
                                   uint8_t* __restrict__ act_out, int lane) {
-  if (lane == 0) act_out[p] = 1;
-  for (int32_t e = rev_off[p] + lane; e < rev_off[p + 1]; e += 64) act_out[rev_src[e]] = 1;
+  if (lane == 0) mark_one(act_out, p);
+  for (int32_t e = rev_off[p] + lane; e < rev_off[p + 1]; e += 64) mark_one(act_out, rev_src[e]);
 }
 
 // Every moved sample: its row out of D[old], into D[new]; sizes and dirty
@@ -188,14 +190,19 @@ __global__ void k_rev_fill(const int32_t* __restrict__ G, int64_t ne, int64_t n,
   }
 }
 
-// Clusters whose members changed: centroid (unchanged when empty) and the
-// Eqn. 2 term; one wavefront per cluster.
+// Clusters whose members changed (dirty, set by this sweep's moves and kept
+// for the next sweep's assignment): centroid (unchanged when empty) and the
+// Eqn. 2 term; one wavefront per cluster.  dirty_clear, the previous
+// sweep's flags, is cleared on the way.
 __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict__ D, int32_t K, int d,
                                                      const int32_t* __restrict__ cs,
-                                                     const int32_t* __restrict__ counts, int32_t* __restrict__ dirty,
-                                                     float* __restrict__ C, double* __restrict__ Iterm) {
+                                                     const int32_t* __restrict__ counts,
+                                                     const int32_t* __restrict__ dirty,
+                                                     int32_t* __restrict__ dirty_clear, float* __restrict__ C,
+                                                     double* __restrict__ Iterm) {
   const int lane = threadIdx.x & 63;
   for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < K; r += (int64_t)gridDim.x * 4) {
+    if (lane == 0) dirty_clear[r] = 0;
     if (!dirty[r]) continue;  // wave-uniform
     const int cnt = counts[r];
     const int s = cs[r];
@@ -207,10 +214,7 @@ __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict_
       sq = fma(v, v, sq);
     }
     sq = wave_sum(sq);
-    if (lane == 0) {
-      Iterm[r] = cnt > 0 ? sq / (double)cnt : 0.0;
-      atomicExch(&dirty[r], 0);
-    }
+    if (lane == 0) Iterm[r] = cnt > 0 ? sq / (double)cnt : 0.0;
   }
 }
 
@@ -237,10 +241,10 @@ knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32
 knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, int32_t* cur,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off, const int32_t* rev_src,
-                          uint8_t* act_out) {
+                          uint8_t* act_out, int32_t* dirty_clear) {
   k_fx_moves<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty, rev_off,
                                                               rev_src, act_out);
-  k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, dirty, C, Iterm);
+  k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, dirty, dirty_clear, C, Iterm);
   return knnkm_check(ctx, "incremental update");
 }
 
