@@ -276,27 +276,34 @@ __global__ __launch_bounds__(256) void k_assign(
 // order; decisions do not depend on the order of the list).
 __global__ __launch_bounds__(256) void k_act_compact(int64_t n, uint8_t* __restrict__ act, int32_t* __restrict__ list,
                                                      int32_t* __restrict__ count, int32_t* __restrict__ clear_other) {
-  constexpr int RW = 16;  // rounds of 64 positions per wavefront
+  // a lane reads the flags of four consecutive positions as one word (the
+  // flag arrays are padded to a multiple of four bytes)
+  constexpr int RW = 4;  // rounds of 256 positions per wavefront
   __shared__ int32_t wtot[4], wbase[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   // the other list's counter is free during this sweep: clear it for the next
   if (clear_other && blockIdx.x == 0 && threadIdx.x == 0) *clear_other = 0;
-  const int64_t base = ((int64_t)blockIdx.x * 4 + w) * (RW * 64);
-  uint64_t m[RW];
-  bool chg[RW];
+  const int64_t base = ((int64_t)blockIdx.x * 4 + w) * (RW * 256);
+  const int64_t nw = (n + 3) / 4;
+  uint32_t* act4 = reinterpret_cast<uint32_t*>(act);
+  uint64_t m[RW][4], c[RW][4];
   int32_t tot = 0;
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
-    const int64_t p = base + r * 64 + lane;
-    bool a = false;
-    if (p < n) {
-      const uint8_t f = act[p];
-      a = f != 0;
-      if (a) act[p] = 0;
-      chg[r] = (f & 2) != 0;
+    const int64_t wi = base / 4 + r * 64 + lane;
+    uint32_t f = 0;
+    if (wi < nw) {
+      f = act4[wi];
+      if (f) act4[wi] = 0;
     }
-    m[r] = __ballot(a);
-    tot += (int32_t)__popcll(m[r]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const bool in = 4 * wi + b < n;  // padding bytes past the last position never count
+      const uint32_t fb = in ? (f >> (8 * b)) & 0xFFu : 0u;
+      m[r][b] = __ballot(fb != 0);
+      c[r][b] = __ballot((fb & 2u) != 0);
+      tot += (int32_t)__popcll(m[r][b]);
+    }
   }
   if (lane == 0) wtot[w] = tot;
   __syncthreads();
@@ -311,12 +318,16 @@ __global__ __launch_bounds__(256) void k_act_compact(int64_t n, uint8_t* __restr
   __syncthreads();
   int32_t at = wbase[w];
 #pragma unroll
-  for (int r = 0; r < RW; ++r) {
-    if ((m[r] >> lane) & 1ull)
-      list[at + __popcll(m[r] & lanes_below())] =
-          (int32_t)((uint32_t)(base + r * 64 + lane) | (chg[r] ? 0x80000000u : 0u));
-    at += (int32_t)__popcll(m[r]);
-  }
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if ((m[r][b] >> lane) & 1ull) {
+        const int64_t p = base + 4 * (r * 64 + lane) + b;
+        list[at + __popcll(m[r][b] & lanes_below())] =
+            (int32_t)((uint32_t)p | (((c[r][b] >> lane) & 1ull) ? 0x80000000u : 0u));
+      }
+      at += (int32_t)__popcll(m[r][b]);
+    }
 }
 
 // The listed samples, one per row group (grid-stride over the list), each

@@ -409,12 +409,13 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     rev_off = (int32_t*)knnkm_ws(ctx, "fit_rev_off", sizeof(int32_t) * (size_t)(n + 1));
     rev_src = (int32_t*)knnkm_ws(ctx, "fit_rev_src", sizeof(int32_t) * (size_t)n * kappa);
     act_p = (uint8_t*)knnkm_ws(ctx, "fit_act_p", (size_t)(n + 3) / 4 * 4);
-    act_2 = (uint8_t*)knnkm_ws(ctx, "fit_act_2", (size_t)n);
+    act_2 = (uint8_t*)knnkm_ws(ctx, "fit_act_2", (size_t)(n + 3) / 4 * 4);
     if (!rev_off || !rev_src || !act_p || !act_2) return KNNKM_ENOMEM;
     KNNKM_TRY(ks_reverse_graph(ctx, Gp, n, kappa, rev_off, rev_src));
-    // the first sweep writes every flag next to its output; the other array
-    // starts clear
+    // both flag arrays start clear (the first sweep writes every flag of
+    // its output array; the padding bytes stay zero)
     KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)act_p, (n + 3) / 4, 0));
+    KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)act_2, (n + 3) / 4, 0));
   }
   auto act_for = [&](const int32_t* lab) -> uint8_t* {
     return use_act ? (lab == labp ? act_p : act_2) : nullptr;

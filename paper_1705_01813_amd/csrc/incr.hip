@@ -105,12 +105,23 @@ __device__ inline void mark_moved(int64_t p, const int32_t* __restrict__ rev_off
   for (int32_t e = rev_off[p] + lane; e < rev_off[p + 1]; e += 64) mark_one(act_out, rev_src[e]);
 }
 
+// 128-bit two's-complement accumulation in registers
+__device__ inline void add128(uint64_t& h, uint64_t& l, uint64_t bh, uint64_t bl) {
+  const uint64_t nl = l + bl;
+  h += bh + (nl < l ? 1ull : 0ull);
+  l = nl;
+}
+
 // Every moved sample: its row out of D[old], into D[new]; sizes and dirty
 // flags of both clusters.  With act_out (active sets) also its marks, and
 // its new label written over the old one in cur, so that the two label
 // arrays agree outside the samples the next sweep writes.  A wavefront scans
-// 64 positions and then applies its moved samples one at a time, lanes over
-// the dimensions.
+// 64 positions and takes its moved samples in order, lanes over the
+// dimensions (DPL per lane); consecutive moved samples that leave the same
+// cluster (or join the same one), common in the cluster-ordered working
+// copy, are summed in registers first and reach D with one atomic per run
+// and dimension (integer sums: the same bits in any grouping).
+template <int DPL>
 __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, int64_t n, int d,
                                                   int32_t* __restrict__ cur, const int32_t* __restrict__ nxt,
                                                   const int32_t* __restrict__ cs, uint64_t* __restrict__ D,
@@ -135,20 +146,48 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
       atomicOr(&dirty[b], 1);
       if (act_out) cur[p] = b;
     }
-    for (uint64_t M = __ballot(moved); M; M &= M - 1) {
+    uint64_t M = __ballot(moved);
+    if (!M) continue;  // wave-uniform
+    int run_from = -1, run_to = -1;
+    uint64_t fh[DPL], fl[DPL], th[DPL], tl[DPL];
+#pragma unroll
+    for (int e = 0; e < DPL; ++e) fh[e] = fl[e] = th[e] = tl[e] = 0;
+    auto flush = [&](uint64_t (&h)[DPL], uint64_t (&l)[DPL], int r) {
+#pragma unroll
+      for (int e = 0; e < DPL; ++e) {
+        const int t = lane + 64 * e;
+        if (t < d) fx_atomic_add(D + 2 * ((int64_t)r * d + t), h[e], l[e]);
+        h[e] = l[e] = 0;
+      }
+    };
+    for (; M; M &= M - 1) {
       const int q = (int)__builtin_ctzll(M);
       const int from = __shfl(a, q, 64), to = __shfl(b, q, 64);
       if (act_out) mark_moved(base + q, rev_off, rev_src, act_out, lane);
+      if (from != run_from) {
+        if (run_from >= 0) flush(fh, fl, run_from);
+        run_from = from;
+      }
+      if (to != run_to) {
+        if (run_to >= 0) flush(th, tl, run_to);
+        run_to = to;
+      }
       const int s = cs[to];  // both clusters belong to the sample's job
       const float* row = X + (base + q) * (int64_t)d;
-      for (int t = lane; t < d; t += 64) {
-        uint64_t hi, lo;
-        fx_of_double((double)row[t], s, hi, lo);
-        fx_atomic_add(D + 2 * ((int64_t)to * d + t), hi, lo);
-        fx_neg(hi, lo);
-        fx_atomic_add(D + 2 * ((int64_t)from * d + t), hi, lo);
+#pragma unroll
+      for (int e = 0; e < DPL; ++e) {
+        const int t = lane + 64 * e;
+        if (t < d) {
+          uint64_t hi, lo;
+          fx_of_double((double)row[t], s, hi, lo);
+          add128(th[e], tl[e], hi, lo);
+          fx_neg(hi, lo);
+          add128(fh[e], fl[e], hi, lo);
+        }
       }
     }
+    flush(fh, fl, run_from);
+    flush(th, tl, run_to);
   }
 }
 
@@ -242,8 +281,18 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off, const int32_t* rev_src,
                           uint8_t* act_out, int32_t* dirty_clear) {
-  k_fx_moves<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty, rev_off,
-                                                              rev_src, act_out);
+#define MV(DD)                                                                                           \
+  k_fx_moves<DD><<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty, \
+                                                                  rev_off, rev_src, act_out)
+  if (d <= 64)
+    MV(1);
+  else if (d <= 128)
+    MV(2);
+  else if (d <= 256)
+    MV(4);
+  else
+    MV(8);
+#undef MV
   k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, dirty, dirty_clear, C, Iterm);
   return knnkm_check(ctx, "incremental update");
 }
