@@ -208,73 +208,6 @@ __global__ __launch_bounds__(256) void k_seg_partial(const float* __restrict__ X
   }
 }
 
-// Chunk sums with float4 row loads: LR lanes per row, RPW = 64/LR rows per
-// pass, Q float4 per lane and row; 8 passes of rows are requested before any
-// is added.
-template <int LR, int Q>
-__global__ __launch_bounds__(256) void k_seg_partial4(const float* __restrict__ X, int d, int64_t ldx,
-                                                      int32_t k, const int32_t* __restrict__ offsets,
-                                                      const int32_t* __restrict__ members,
-                                                      const int32_t* __restrict__ chunk_off,
-                                                      int64_t max_chunks, double* __restrict__ partial) {
-  constexpr int RPW = 64 / LR, B = 8;
-  const int lane = threadIdx.x & 63;
-  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= max_chunks || c >= chunk_off[k]) return;
-  int lo = 0, hi = k;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (chunk_off[mid] <= c) lo = mid; else hi = mid;
-  }
-  const int r = lo;
-  const int64_t p0 = offsets[r] + (c - chunk_off[r]) * SEG_CHUNK;
-  const int64_t p1 = min((int64_t)offsets[r + 1], p0 + SEG_CHUNK);
-  const int sl = lane / LR, j = lane % LR;
-  double acc[Q][4];
-#pragma unroll
-  for (int q = 0; q < Q; ++q)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) acc[q][e] = 0.0;
-  for (int64_t pb = p0; pb < p1; pb += RPW * B) {
-    float4 v[B][Q];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const int64_t row = pb + sl + RPW * b;
-      const float* xr = row < p1 ? X + (int64_t)members[row] * ldx : nullptr;
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int f = 4 * (j + LR * q);
-        v[b][q] = (xr && f < d) ? *reinterpret_cast<const float4*>(xr + f) : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < B; ++b)
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        acc[q][0] += (double)v[b][q].x;
-        acc[q][1] += (double)v[b][q].y;
-        acc[q][2] += (double)v[b][q].z;
-        acc[q][3] += (double)v[b][q].w;
-      }
-  }
-#pragma unroll
-  for (int o = LR; o < 64; o <<= 1)
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[q][e] += __shfl_xor(acc[q][e], o, 64);
-  if (sl == 0) {
-    double* out = partial + c * d;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int f = 4 * (j + LR * q);
-      if (f < d)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) out[f + e] = acc[q][e];
-    }
-  }
-}
-
 template <int T>
 __global__ __launch_bounds__(256) void k_seg_final(int d, int32_t k, const int32_t* __restrict__ counts,
                                                    const int32_t* __restrict__ chunk_off,
@@ -321,30 +254,9 @@ knnkm_status ks_segsum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   KNNKM_WS(ctx, partial, double, "seg_partial", max_chunks * d);
   const int T = (d + 63) / 64;
   const unsigned gp = (unsigned)((max_chunks + 3) / 4), gf = (unsigned)((k + 3) / 4);
-  const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
-  if (vec) {
-    const int ql = d / 4;
-    int lr = 1;
-    while (lr < ql && lr < 64) lr <<= 1;
-#define SP4(LRR, QQ) \
-  k_seg_partial4<LRR, QQ><<<gp, 256, 0, ctx->stream>>>(X, d, ldx, k, offsets, members, cc, max_chunks, partial)
-    switch (lr) {
-      case 1: SP4(1, 1); break;
-      case 2: SP4(2, 1); break;
-      case 4: SP4(4, 1); break;
-      case 8: SP4(8, 1); break;
-      case 16: SP4(16, 1); break;
-      case 32: SP4(32, 1); break;
-      default:
-        if (ql <= 64) SP4(64, 1); else SP4(64, 2);
-        break;
-    }
-#undef SP4
-  }
 #define SEG(TT)                                                                                        \
-  if (!vec)                                                                                            \
-    k_seg_partial<TT><<<gp, 256, 0, ctx->stream>>>(X, d, ldx, k, offsets, members, cc, max_chunks,    \
-                                                   partial);                                           \
+  k_seg_partial<TT><<<gp, 256, 0, ctx->stream>>>(X, d, ldx, k, offsets, members, cc, max_chunks,      \
+                                                 partial);                                             \
   k_seg_final<TT><<<gf, 256, 0, ctx->stream>>>(d, k, counts, cc, partial, C, sums, Iterm)
   switch (T) {
     case 1: SEG(1); break;
