@@ -422,8 +422,9 @@ def test_fit_update_exact_at_scale(ctx):
     assert np.array_equal(runs[0][2], runs[1][2])
 
 
-@pytest.mark.parametrize("n,d,k,kappa,T,early", [(20000, 32, 200, 10, 12, False), (200_000, 128, 2000, 20, 9, False),
-                                                 (30000, 16, 300, 8, 15, True), (5000, 512, 60, 20, 7, False)])
+@pytest.mark.parametrize("n,d,k,kappa,T,early", [(20000, 32, 200, 10, 12, False), (200_003, 128, 2000, 20, 9, False),
+                                                 (30002, 16, 300, 8, 15, True), (5001, 512, 60, 20, 7, False),
+                                                 (777, 3, 25, 6, 10, False)])
 def test_fit_active_sets_same_bits(ctx, n, d, k, kappa, T, early):
     """From the second sweep on the fit looks only at samples that had several
     candidates, moved, or have a neighbour that moved; with active sets off
@@ -459,7 +460,7 @@ def test_fit_active_sets_same_bits(ctx, n, d, k, kappa, T, early):
 def test_batch_active_sets_same_bits(ctx):
     """The same for a batched fit (jobs of different sizes, one of them with
     kappa >= k, evaluated in full every sweep)."""
-    sizes = [3000, 700, 1500, 64, 2200]
+    sizes = [3000, 701, 1500, 64, 2201]  # 7466 rows: the last flag word is partly padding
     Xs, n_off, ks, seeds = _batch(sizes, 24, seed=41)
     ks[3] = 2  # kappa >= k: that job is exhaustive
     X = dev(np.concatenate(Xs))
