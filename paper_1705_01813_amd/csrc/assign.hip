@@ -359,12 +359,10 @@ __global__ __launch_bounds__(256) void k_assign_list(
   const uint64_t gmask = group_mask<L>(g);
   const int cnt = *count;
   if (n_listed && blockIdx.x == 0 && threadIdx.x == 0) *n_listed = cnt;
-  const int gid = (blockIdx.x * 4 + w) * GW + g;
   const int ngroups = gridDim.x * 4 * GW;
   unsigned int my_moved = 0, my_eval = 0;
   // wave-uniform trip count: groups of a wavefront stay in step
-  const int first = (blockIdx.x * 4 + w) * GW;
-  for (int base = first; base < cnt; base += ngroups) {
+  for (int base = (blockIdx.x * 4 + w) * GW; base < cnt; base += ngroups) {
     const int li = base + g;
     const bool live = li < cnt;  // group-uniform
     const uint32_t ent = live ? (uint32_t)list[li] : 0u;
@@ -463,7 +461,6 @@ __global__ __launch_bounds__(256) void k_assign_list(
       }
     }
   }
-  (void)gid;
   if (moved_acc || eval_acc) {
     if (my_moved) atomicAdd(&block_moved, my_moved);
     if (my_eval) atomicAdd(&block_eval, my_eval);

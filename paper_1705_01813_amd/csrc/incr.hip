@@ -13,8 +13,8 @@
 // bits).  Only the moved samples are touched each sweep; a cluster whose
 // members changed gets C_r = float32(D_r / n_r) (rounded to float64 first)
 // and the Eqn. 2 term ||D_r||^2 / n_r.
-#include "common.h"
 #include "fixed128.h"
+#include "rowgroup.h"
 
 // Multi-word atomic add: the carry out of the low word is known from the
 // value the low-word atomic returns.
@@ -29,40 +29,72 @@ __device__ inline void fx_atomic_add(uint64_t* p, uint64_t hi, uint64_t lo) {
 // Per-row statistics in one pass over X: ||x_i||^2 in float64 (the Eqn. 2
 // identity of the distortion) and the largest |x| of every job, as the bits
 // of a non-negative float (ordered like the floats, so an atomic max of the
-// bits is exact in any order).  A wavefront takes a contiguous run of rows,
-// so the job changes rarely within it.
+// bits is exact in any order).  Row groups of L lanes (V dimensions each)
+// take a contiguous run of rows per wavefront; each lane keeps a running
+// maximum that is reduced and published when its row's job changes (rare)
+// and at the end, where a block combines its groups first, so one atomic
+// per block and job reaches memory (many atomics on one job's word would
+// serialise).
+template <int L, int V>
 __global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
-                                                   const int32_t* __restrict__ job_of, double* __restrict__ rowsq,
-                                                   uint32_t* __restrict__ jmax) {
-  const int lane = threadIdx.x & 63;
+                                                   int vec, const int32_t* __restrict__ job_of,
+                                                   double* __restrict__ rowsq, uint32_t* __restrict__ jmax) {
+  constexpr int GW = 64 / L;
+  __shared__ int32_t sjob[4 * GW];
+  __shared__ float smax[4 * GW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane / L, j = lane % L;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const int64_t per = (n + nwaves - 1) / nwaves;
+  const int64_t per = ((n + nwaves - 1) / nwaves + GW - 1) / GW * GW;
   const int64_t i0 = wave * per, i1 = min(n, i0 + per);
   float mx = 0.f;
   int job = -1;
-  for (int64_t i = i0; i < i1; ++i) {
+  for (int64_t r0 = i0; r0 < i1; r0 += GW) {
+    const int64_t i = r0 + g;
+    const bool act = i < i1;  // group-uniform
+    if (!act) continue;
     const int q = job_of ? job_of[i] : 0;
-    if (q != job) {
+    if (q != job) {  // group-uniform
       if (job >= 0) {
-        const float w = wave_max(mx);
-        if (lane == 0) atomicMax(&jmax[job], __float_as_uint(w));
+        const float wm = group_max<L>(mx);
+        if (j == 0) atomicMax(&jmax[job], __float_as_uint(wm));
       }
       job = q;
       mx = 0.f;
     }
+    float x[V];
+    load_row<V>(x, X + i * ldx, j, d, vec != 0);
     double a = 0.0;
-    for (int t = lane; t < d; t += 64) {
-      const float x = X[i * ldx + t];
-      mx = fmaxf(mx, fabsf(x));
-      a = fma((double)x, (double)x, a);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      mx = fmaxf(mx, fabsf(x[e]));
+      a = fma((double)x[e], (double)x[e], a);
     }
-    a = wave_sum(a);
-    if (lane == 0) rowsq[i] = a;
+    a = group_sum<L>(a);
+    if (j == 0) rowsq[i] = a;
   }
-  if (job >= 0) {
-    const float w = wave_max(mx);
-    if (lane == 0) atomicMax(&jmax[job], __float_as_uint(w));
+  float gm = 0.f;
+  if (job >= 0) gm = group_max<L>(mx);  // group-uniform
+  if (j == 0) {
+    sjob[w * GW + g] = job;
+    smax[w * GW + g] = gm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int cj = -1;
+    float cm = 0.f;
+    for (int t = 0; t < 4 * GW; ++t) {
+      const int q = sjob[t];
+      if (q < 0) continue;
+      if (q != cj) {
+        if (cj >= 0) atomicMax(&jmax[cj], __float_as_uint(cm));
+        cj = q;
+        cm = 0.f;
+      }
+      cm = fmaxf(cm, smax[t]);
+    }
+    if (cj >= 0) atomicMax(&jmax[cj], __float_as_uint(cm));
   }
 }
 
@@ -260,7 +292,29 @@ __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict_
 knnkm_status ks_row_stats(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int m,
                           const int32_t* job_of, double* rowsq, uint32_t* jmax) {
   KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)jmax, m, 0));
-  k_row_stats<<<grid_for(n, 64, 16384), 256, 0, ctx->stream>>>(X, n, d, ldx, job_of, rowsq, jmax);
+  int L, V;
+  pick_group(d, 1, &L, &V);
+  const int vec = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+  const unsigned grid = grid_for(n, 1024, 1024);
+#define RS(LL, VV) k_row_stats<LL, VV><<<grid, 256, 0, ctx->stream>>>(X, n, d, ldx, vec, job_of, rowsq, jmax)
+  if (V == 4) {
+    switch (L) {
+      case 4: RS(4, 4); break;
+      case 8: RS(8, 4); break;
+      case 16: RS(16, 4); break;
+      case 32: RS(32, 4); break;
+      default: RS(64, 4); break;
+    }
+  } else {
+    switch (L) {
+      case 4: RS(4, 8); break;
+      case 8: RS(8, 8); break;
+      case 16: RS(16, 8); break;
+      case 32: RS(32, 8); break;
+      default: RS(64, 8); break;
+    }
+  }
+#undef RS
   return knnkm_check(ctx, "row statistics");
 }
 

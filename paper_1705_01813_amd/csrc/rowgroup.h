@@ -58,6 +58,17 @@ __device__ inline double group_sum(double v) {
 }
 
 template <int L>
+__device__ inline float group_max(float v) {
+  if (L >= 2) v = fmaxf(v, dpp_f32<DPP_QUAD_XOR1>(v));
+  if (L >= 4) v = fmaxf(v, dpp_f32<DPP_QUAD_XOR2>(v));
+  if (L >= 8) v = fmaxf(v, dpp_f32<DPP_ROW_HALF_MIRROR>(v));
+  if (L >= 16) v = fmaxf(v, dpp_f32<DPP_ROW_MIRROR>(v));
+  if (L >= 32) v = fmaxf(v, swz16_f32(v));
+  if (L >= 64) v = fmaxf(v, __shfl_xor(v, 32, 64));
+  return v;
+}
+
+template <int L>
 __device__ inline uint64_t group_mask(int g) {
   return L == 64 ? ~0ull : (((1ull << L) - 1ull) << (g * L));
 }
