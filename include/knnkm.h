@@ -301,6 +301,15 @@ knnkm_status knnkm_enable_graphs(knnkm_ctx* ctx, int32_t on);
  * labels.  Results are the same bits with active sets on or off. */
 knnkm_status knnkm_enable_active_sets(knnkm_ctx* ctx, int32_t on);
 
+/* Subtree finishing in the two-means tree of Alg. 1 (default on).  Once a
+ * node to split has at most 1,024 members, one block performs every later
+ * split of its subtree (seeds, the Lloyd 2-means steps, the ordering by
+ * delta and the balanced split) with the member ids held on chip, instead of
+ * one launch per step per depth.  Every step keeps the same arithmetic and
+ * order, so labels from knnkm_twomeans, knn_build and knn_kmeans_fit are the
+ * same bits with it on or off.  Returns KNNKM_EINVAL for a null context. */
+knnkm_status knnkm_enable_subtree_finish(knnkm_ctx* ctx, int32_t on);
+
 /* Autotuner of the assignment's launch shapes (default on): the first call
  * with at least 65,536 samples for a given group shape, size bin and call
  * site (a direct knn_assign call, a graph-construction round, the fit's first

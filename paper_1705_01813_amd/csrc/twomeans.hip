@@ -28,6 +28,7 @@
 #define TM_TILE 1024    // positions per tile of the per-member passes
 #define TM_SMALL 2048   // nodes up to this size split inside one block
 #define TM_CHUNK 16     // tiles per chunk of the two-stage node reduction
+#define TM_SEL_PASSES 12  // 8-bit digits of the 96-bit (delta key, id)
 
 struct TMLevel {
   int depth;
@@ -40,6 +41,14 @@ struct TMLevel {
   int ncopy, copy_base;    // unsplit nodes (copied unchanged)
   int nchunks, chunk_base; // groups of up to TM_CHUNK tiles of one node
   int max_node_tiles;      // largest number of tiles of one split node
+  int nfin, fin_base;      // subtrees finished by one block, rooted at this depth
+};
+
+// One split of a subtree that a single block finishes (k_tm_finish): the node
+// at `off` (relative to the subtree's first position) of `size` members.
+struct TMFinOp {
+  int64_t heap;   // heap index of the node inside its job's tree (seed stream)
+  int32_t off, size, job, depth;
 };
 
 struct TMPlan {
@@ -61,6 +70,8 @@ struct TMPlan {
   std::vector<int32_t> big_btb, big_bte;                  // per big node: range in the bigtile list
   std::vector<int32_t> split_cb, split_ce;                // per split node: range of its chunks
   std::vector<int32_t> chunk_tb, chunk_te;                // per chunk: range of its tiles
+  std::vector<int32_t> fin_off, fin_size, fin_ob, fin_oe;  // per finished subtree: rows, op range
+  std::vector<TMFinOp> fin_ops;                           // splits of the subtrees, depth order each
   int max_split = 0, max_tiles = 0, max_big = 0, max_chunks = 0;
   // device copies
   void* dev = nullptr;
@@ -68,8 +79,9 @@ struct TMPlan {
   const int32_t *d_split_off, *d_split_size, *d_split_tile_begin, *d_split_tile_end, *d_tile_split,
       *d_tile_start, *d_tile_len, *d_big_split, *d_bigtile, *d_bigtile_big, *d_small_split,
       *d_copy_off, *d_copy_size, *d_leaf_off, *d_big_btb, *d_big_bte, *d_split_cb, *d_split_ce,
-      *d_chunk_tb, *d_chunk_te, *d_split_job;
+      *d_chunk_tb, *d_chunk_te, *d_split_job, *d_fin_off, *d_fin_size, *d_fin_ob, *d_fin_oe;
   const int64_t* d_split_heap;
+  const TMFinOp* d_fin_ops;
 };
 
 // The device tables live in the context workspace ("tm_plan").
@@ -78,7 +90,11 @@ void tm_plan_free(TMPlan* p) { delete p; }
 // Tree shapes of several independent jobs (job j: rows [off_j, off_j + n_j),
 // k_j leaves), merged depth by depth so one launch per step covers every job
 // that still splits; a job whose tree is complete is carried over as a copy.
-static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vector<int32_t>& jk) {
+// With `finish`, a split node of at most TM_TILE members becomes the root of
+// a subtree that one block finishes: its splits at this and every later depth
+// leave the per-depth lists and become that subtree's ops.
+static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vector<int32_t>& jk,
+                       bool finish) {
   P = TMPlan();
   const int nj = (int)jn.size();
   P.key.clear();
@@ -88,13 +104,17 @@ static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vec
     P.key.push_back(jk[q]);
     total += jn[q];
   }
+  P.key.push_back(finish ? 1 : 0);
   P.n = total;
   std::vector<std::vector<int64_t>> joff(nj), jsize(nj);
+  std::vector<std::vector<int32_t>> jroot(nj);  // per node: finished subtree holding it, or -1
+  std::vector<std::vector<TMFinOp>> rops;       // per finished subtree: its splits
   {
     int64_t at = 0;
     for (int q = 0; q < nj; ++q) {
       joff[q] = {at};
       jsize[q] = {jn[q]};
+      jroot[q] = {-1};
       at += jn[q];
     }
   }
@@ -114,10 +134,12 @@ static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vec
     L.small_base = (int)P.small_split.size();
     L.copy_base = (int)P.copy_off.size();
     L.chunk_base = (int)P.chunk_tb.size();
+    L.fin_base = (int)P.fin_off.size();
     L.max_node_tiles = 0;
     for (int q = 0; q < nj; ++q) {
     std::vector<int64_t>& off = joff[q];
     std::vector<int64_t>& size = jsize[q];
+    std::vector<int32_t>& root = jroot[q];
     const int m = (int)off.size();
     const int32_t k = jk[q];
     if ((int64_t)m >= k) {  // this job's tree is complete: carry its rows over
@@ -136,7 +158,38 @@ static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vec
       for (int j = 0; j < k - m; ++j) split[ord[j]] = 1;
     }
     std::vector<int64_t> noff, nsize;
+    std::vector<int32_t> nroot;
     for (int i = 0; i < m; ++i) {
+      int32_t rt = root[i];
+      if (rt < 0 && finish && split[i] && size[i] <= TM_TILE) {
+        rt = (int32_t)P.fin_off.size();
+        P.fin_off.push_back((int32_t)off[i]);
+        P.fin_size.push_back((int32_t)size[i]);
+        rops.emplace_back();
+      }
+      if (rt >= 0) {
+        if (split[i]) {
+          TMFinOp op;
+          op.heap = ((int64_t)1 << depth) + i;
+          op.off = (int32_t)(off[i] - P.fin_off[rt]);
+          op.size = (int32_t)size[i];
+          op.job = q;
+          op.depth = depth;
+          rops[rt].push_back(op);
+          const int64_t h = (size[i] + 1) / 2;
+          noff.push_back(off[i]);
+          nsize.push_back(h);
+          noff.push_back(off[i] + h);
+          nsize.push_back(size[i] - h);
+          nroot.push_back(rt);
+          nroot.push_back(rt);
+        } else {
+          noff.push_back(off[i]);
+          nsize.push_back(size[i]);
+          nroot.push_back(rt);
+        }
+        continue;
+      }
       if (split[i]) {
         const int local = (int)P.split_off.size() - L.split_base;
         P.split_off.push_back((int32_t)off[i]);
@@ -179,16 +232,21 @@ static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vec
         nsize.push_back(h);
         noff.push_back(off[i] + h);
         nsize.push_back(size[i] - h);
+        nroot.push_back(-1);
+        nroot.push_back(-1);
       } else {
         P.copy_off.push_back((int32_t)off[i]);
         P.copy_size.push_back((int32_t)size[i]);
         noff.push_back(off[i]);
         nsize.push_back(size[i]);
+        nroot.push_back(-1);
       }
     }
     off.swap(noff);
     size.swap(nsize);
+    root.swap(nroot);
     }
+    L.nfin = (int)P.fin_off.size() - L.fin_base;
     L.nsplit = (int)P.split_off.size() - L.split_base;
     L.ntiles = (int)P.tile_split.size() - L.tile_base;
     L.nbig = (int)P.big_split.size() - L.big_base;
@@ -202,6 +260,11 @@ static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vec
     P.max_big = std::max(P.max_big, L.nbig);
     P.levels.push_back(L);
     ++depth;
+  }
+  for (const auto& ops : rops) {
+    P.fin_ob.push_back((int32_t)P.fin_ops.size());
+    P.fin_ops.insert(P.fin_ops.end(), ops.begin(), ops.end());
+    P.fin_oe.push_back((int32_t)P.fin_ops.size());
   }
   // leaves of all jobs, left to right, job after job
   P.leaf_off.clear();
@@ -225,7 +288,10 @@ static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P) {
       {P.big_btb.data(), P.big_btb.size() * 4},       {P.big_bte.data(), P.big_bte.size() * 4},
       {P.split_cb.data(), P.split_cb.size() * 4},     {P.split_ce.data(), P.split_ce.size() * 4},
       {P.chunk_tb.data(), P.chunk_tb.size() * 4},     {P.chunk_te.data(), P.chunk_te.size() * 4},
-      {P.split_job.data(), P.split_job.size() * 4}};
+      {P.split_job.data(), P.split_job.size() * 4},
+      {P.fin_off.data(), P.fin_off.size() * 4},       {P.fin_size.data(), P.fin_size.size() * 4},
+      {P.fin_ob.data(), P.fin_ob.size() * 4},         {P.fin_oe.data(), P.fin_oe.size() * 4},
+      {P.fin_ops.data(), P.fin_ops.size() * sizeof(TMFinOp)}};
   size_t total = 0;
   std::vector<size_t> at;
   for (auto& p : parts) {
@@ -266,6 +332,11 @@ static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P) {
   P.d_chunk_tb = (const int32_t*)(b + at[19]);
   P.d_chunk_te = (const int32_t*)(b + at[20]);
   P.d_split_job = (const int32_t*)(b + at[21]);
+  P.d_fin_off = (const int32_t*)(b + at[22]);
+  P.d_fin_size = (const int32_t*)(b + at[23]);
+  P.d_fin_ob = (const int32_t*)(b + at[24]);
+  P.d_fin_oe = (const int32_t*)(b + at[25]);
+  P.d_fin_ops = (const TMFinOp*)(b + at[26]);
   return KNNKM_OK;
 }
 
@@ -326,6 +397,29 @@ __device__ inline void tm_node_consts(const float* __restrict__ cu, const float*
   }
 }
 
+// Rows at positions p, p + step, ..., p + (U-1) step of a node (those below
+// len), all loaded before any is used so that U row loads are in flight per
+// group; ids[q] is the sample at node position q.
+template <int V, int U>
+__device__ inline void tm_load_rows(float (&x)[U][V], const float* __restrict__ X, int64_t ldx,
+                                    const int32_t* ids, int p, int step, int len, int j, int d,
+                                    bool vec) {
+  int32_t id[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) id[u] = p + u * step < len ? ids[p + u * step] : -1;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (id[u] >= 0) {
+      load_row<V>(x[u], X + (int64_t)id[u] * ldx, j, d, vec);
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; ++e) x[u][e] = 0.f;
+    }
+  }
+}
+
+#define TM_UNROLL 4
+
 // One block per tile: side of each member, float64 sums per side.  Group gid
 // of the block takes tile positions gid, gid + NG, ...; the NG group sums are
 // then added in group order.
@@ -353,18 +447,23 @@ __global__ __launch_bounds__(256) void k_tm_accum(const float* __restrict__ X, i
 #pragma unroll
   for (int e = 0; e < V; ++e) au[e] = av[e] = 0.0;
   int cnu = 0, cnv = 0;
-  for (int p = gid; p < len; p += NG) {
-    float x[V];
-    load_row<V>(x, X + (int64_t)perm[start + p] * ldx, j, d, vec);
-    const double delta = group_sum<L>(tm_part<V>(x, wv, sv));
-    if (delta <= 0.0) {
-      ++cnu;
+  for (int p = gid; p < len; p += TM_UNROLL * NG) {
+    float x[TM_UNROLL][V];
+    tm_load_rows<V, TM_UNROLL>(x, X, ldx, perm + start, p, NG, len, j, d, vec);
 #pragma unroll
-      for (int e = 0; e < V; ++e) au[e] += (double)x[e];
-    } else {
-      ++cnv;
+    for (int u = 0; u < TM_UNROLL; ++u) {
+      if (p + u * NG < len) {  // members in position order, as one row at a time
+        const double delta = group_sum<L>(tm_part<V>(x[u], wv, sv));
+        if (delta <= 0.0) {
+          ++cnu;
 #pragma unroll
-      for (int e = 0; e < V; ++e) av[e] += (double)x[e];
+          for (int e = 0; e < V; ++e) au[e] += (double)x[u][e];
+        } else {
+          ++cnv;
+#pragma unroll
+          for (int e = 0; e < V; ++e) av[e] += (double)x[u][e];
+        }
+      }
     }
   }
 #pragma unroll
@@ -468,11 +567,16 @@ __global__ __launch_bounds__(256) void k_tm_delta(const float* __restrict__ X, i
   const float* cu = cent + (int64_t)js * 2 * d;
   double wv[V], sv[V];
   tm_node_consts<V>(cu, cu + d, j, d, wv, sv);
-  for (int p = gid; p < len; p += NG) {
-    float x[V];
-    load_row<V>(x, X + (int64_t)perm[start + p] * ldx, j, d, vec);
-    const double delta = group_sum<L>(tm_part<V>(x, wv, sv));
-    if (j == 0) keys[start + p] = dkey(delta);
+  for (int p = gid; p < len; p += TM_UNROLL * NG) {
+    float x[TM_UNROLL][V];
+    tm_load_rows<V, TM_UNROLL>(x, X, ldx, perm + start, p, NG, len, j, d, vec);
+#pragma unroll
+    for (int u = 0; u < TM_UNROLL; ++u) {
+      if (p + u * NG < len) {
+        const double delta = group_sum<L>(tm_part<V>(x[u], wv, sv));
+        if (j == 0) keys[start + p + u * NG] = dkey(delta);
+      }
+    }
   }
 }
 
@@ -588,6 +692,10 @@ __device__ inline bool sel_match(uint64_t key, int32_t id, int pass, const SelSt
   return ((uint32_t)id >> sh) == (st.pi >> sh);
 }
 
+// Selection state and histograms are kept per pass: st[p * nbig + b] is the
+// prefix decided before pass p of big node b, hist[(p * nbig + b) * 256 + .]
+// the digit counts of pass p.  Each pass's blocks derive their own state from
+// the previous pass's finished histogram, so no block waits for another.
 __global__ __launch_bounds__(256) void k_tm_sel_init(int nbig, const int32_t* __restrict__ big_split,
                                                      const int32_t* __restrict__ s_size,
                                                      SelState* st, int32_t* hist) {
@@ -596,45 +704,19 @@ __global__ __launch_bounds__(256) void k_tm_sel_init(int nbig, const int32_t* __
     st[b].pi = 0;
     st[b].h = (s_size[big_split[b]] + 1) / 2;
   }
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nbig * 256; e += gridDim.x * blockDim.x)
+  for (int64_t e = blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)nbig * 256 * TM_SEL_PASSES;
+       e += gridDim.x * blockDim.x)
     hist[e] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_tm_sel_hist(const int32_t* __restrict__ perm,
-                                                     const uint64_t* __restrict__ keys,
-                                                     const int32_t* __restrict__ bigtile,
-                                                     const int32_t* __restrict__ bigtile_big,
-                                                     const int32_t* __restrict__ t_start,
-                                                     const int32_t* __restrict__ t_len, int pass,
-                                                     const SelState* __restrict__ st,
-                                                     int32_t* __restrict__ hist) {
-  __shared__ int32_t h[256];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int tile = bigtile[blockIdx.x];
-  const int b = bigtile_big[blockIdx.x];
-  const SelState s = st[b];
-  const int start = t_start[tile], len = t_len[tile];
-  for (int p = threadIdx.x; p < len; p += 256) {
-    const uint64_t key = keys[start + p];
-    const int32_t id = perm[start + p];
-    if (sel_match(key, id, pass, s)) atomicAdd(&h[sel_digit(key, id, pass)], 1);
-  }
-  __syncthreads();
-  const int c = h[threadIdx.x];
-  if (c) atomicAdd(&hist[b * 256 + threadIdx.x], c);
-}
-
-// One 256-thread block per big node: the bucket holding the rank-h element is
-// the digit whose exclusive prefix count is < h <= inclusive count.
-__global__ __launch_bounds__(256) void k_tm_sel_pick(int pass, SelState* st, int32_t* hist) {
-  __shared__ int32_t sh[8];
-  const int b = blockIdx.x;
-  int32_t* hh = hist + b * 256;
+// Whole block: the state after `pass` from the state before it and that
+// pass's histogram: the bucket holding the rank-h member is the digit whose
+// exclusive prefix count is < h <= inclusive count.
+__device__ inline SelState sel_next(const SelState& s, const int32_t* __restrict__ hh, int pass,
+                                    int32_t* sh8, SelState* shs) {
   const int32_t c = hh[threadIdx.x];
-  const SelState s = st[b];
   int32_t tot;
-  const int32_t ex = block_scan_excl_256(c, sh, &tot);
+  const int32_t ex = block_scan_excl_256(c, sh8, &tot);
   if (c > 0 && ex < s.h && s.h <= ex + c) {
     SelState t = s;
     t.h -= ex;
@@ -643,24 +725,70 @@ __global__ __launch_bounds__(256) void k_tm_sel_pick(int pass, SelState* st, int
       t.pk |= (uint64_t)dg << (56 - 8 * pass);
     else
       t.pi |= (uint32_t)dg << (24 - 8 * (pass - 8));
-    st[b] = t;
+    *shs = t;
   }
-  hh[threadIdx.x] = 0;
+  __syncthreads();
+  const SelState r = *shs;
+  __syncthreads();
+  return r;
+}
+
+// One block per tile of a big node: state for this pass (the first tile's
+// block stores it), then the histogram of the current digit over the members
+// that match the decided prefix, added into the node's histogram of the pass.
+__global__ __launch_bounds__(256) void k_tm_sel_pass(const int32_t* __restrict__ perm,
+                                                     const uint64_t* __restrict__ keys,
+                                                     const int32_t* __restrict__ bigtile,
+                                                     const int32_t* __restrict__ bigtile_big,
+                                                     const int32_t* __restrict__ big_btb,
+                                                     const int32_t* __restrict__ t_start,
+                                                     const int32_t* __restrict__ t_len, int pass, int nbig,
+                                                     SelState* __restrict__ st, int32_t* __restrict__ hist) {
+  __shared__ int32_t h[256];
+  __shared__ int32_t sh8[8];
+  __shared__ SelState shs;
+  h[threadIdx.x] = 0;
+  const int tile = bigtile[blockIdx.x];
+  const int b = bigtile_big[blockIdx.x];
+  SelState s;
+  if (pass == 0) {
+    s = st[b];
+  } else {
+    s = sel_next(st[(int64_t)(pass - 1) * nbig + b], hist + ((int64_t)(pass - 1) * nbig + b) * 256, pass - 1,
+                 sh8, &shs);
+    if (blockIdx.x == big_btb[b] && threadIdx.x == 0) st[(int64_t)pass * nbig + b] = s;
+  }
+  __syncthreads();
+  const int start = t_start[tile], len = t_len[tile];
+  for (int p = threadIdx.x; p < len; p += 256) {
+    const uint64_t key = keys[start + p];
+    const int32_t id = perm[start + p];
+    if (sel_match(key, id, pass, s)) atomicAdd(&h[sel_digit(key, id, pass)], 1);
+  }
+  __syncthreads();
+  const int c = h[threadIdx.x];
+  if (c) atomicAdd(&hist[((int64_t)pass * nbig + b) * 256 + threadIdx.x], c);
 }
 
 __global__ __launch_bounds__(256) void k_tm_part_count(const int32_t* __restrict__ perm,
                                                        const uint64_t* __restrict__ keys,
                                                        const int32_t* __restrict__ bigtile,
                                                        const int32_t* __restrict__ bigtile_big,
+                                                       const int32_t* __restrict__ big_btb,
                                                        const int32_t* __restrict__ t_start,
-                                                       const int32_t* __restrict__ t_len,
-                                                       const SelState* __restrict__ st,
+                                                       const int32_t* __restrict__ t_len, int nbig,
+                                                       SelState* __restrict__ st, const int32_t* __restrict__ hist,
                                                        int32_t* __restrict__ tile_left) {
   __shared__ int32_t c;
+  __shared__ int32_t sh8[8];
+  __shared__ SelState shs;
   if (threadIdx.x == 0) c = 0;
-  __syncthreads();
   const int tile = bigtile[blockIdx.x];
-  const SelState s = st[bigtile_big[blockIdx.x]];
+  const int b = bigtile_big[blockIdx.x];
+  constexpr int LAST = TM_SEL_PASSES - 1;
+  const SelState s = sel_next(st[(int64_t)LAST * nbig + b], hist + ((int64_t)LAST * nbig + b) * 256, LAST,
+                              sh8, &shs);
+  if (blockIdx.x == big_btb[b] && threadIdx.x == 0) st[(int64_t)TM_SEL_PASSES * nbig + b] = s;
   const int start = t_start[tile], len = t_len[tile];
   int mine = 0;
   for (int p = threadIdx.x; p < len; p += 256)
@@ -749,6 +877,179 @@ __global__ void k_tm_labels(const int32_t* __restrict__ perm, const int32_t* __r
     for (int p = leaf_off[r] + threadIdx.x; p < leaf_off[r + 1]; p += blockDim.x) labels[perm[p]] = r;
 }
 
+// One block per subtree of at most TM_TILE members: every remaining split of
+// the subtree, depth after depth, with the member ids held in LDS.  Each step
+// does the same arithmetic in the same order as the per-depth kernels above
+// (group gid of the block sums positions gid, gid + NG, ... of the node; the
+// group sums are added in group order; a one-tile node's mean passes through
+// the same additions of zero as the per-node reduction), so the tree is
+// bitwise the one the per-depth path builds.  The final ids go to both
+// permutation buffers, so the ping-pong copies of later depths see them.
+template <int L, int V>
+__global__ __launch_bounds__(256) void k_tm_finish(const float* __restrict__ X, int d, int64_t ldx,
+                                                   int32_t* __restrict__ perm_a, int32_t* __restrict__ perm_b,
+                                                   const int32_t* __restrict__ f_off,
+                                                   const int32_t* __restrict__ f_size,
+                                                   const int32_t* __restrict__ f_ob,
+                                                   const int32_t* __restrict__ f_oe,
+                                                   const TMFinOp* __restrict__ ops,
+                                                   const uint64_t* __restrict__ seeds, uint64_t seed1,
+                                                   int round_tag, int iters, int vec) {
+  constexpr int NG = 4 * (64 / L);
+  constexpr int W = L * V;
+  constexpr int ACC_BYTES = NG * 2 * W * 8;
+  constexpr int SORT_BYTES = TM_TILE * 12;
+  __shared__ int32_t sid[TM_TILE], sid2[TM_TILE];
+  __shared__ uint64_t skey[TM_TILE];
+  __shared__ float scent[2 * KNNKM_MAX_D];
+  __shared__ __align__(16) char sraw[ACC_BYTES > SORT_BYTES ? ACC_BYTES : SORT_BYTES];
+  __shared__ int32_t shc[NG][2];
+  __shared__ int32_t sscan[8];
+  double(*acc)[2][W] = reinterpret_cast<double(*)[2][W]>(sraw);
+  uint64_t* sk = reinterpret_cast<uint64_t*>(sraw);
+  int32_t* si = reinterpret_cast<int32_t*>(sraw + TM_TILE * 8);
+
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = lane % L, gid = w * (64 / L) + lane / L;
+  const int R0 = f_off[blockIdx.x], S = f_size[blockIdx.x];
+  for (int p = threadIdx.x; p < S; p += 256) sid[p] = perm_a[R0 + p];
+  __syncthreads();
+  for (int o = f_ob[blockIdx.x]; o < f_oe[blockIdx.x]; ++o) {
+    const TMFinOp op = ops[o];
+    const int off = op.off, s = op.size;
+    {  // seeds: two distinct members
+      const uint64_t seed = seeds ? seeds[op.job] : seed1;
+      const uint64_t key = sm_key(seed, sm_stream(RNG_TWOMEANS, (uint64_t)round_tag, (uint64_t)op.heap));
+      const uint32_t r0 = sm_below(sm_draw(key, 0), (uint32_t)s);
+      uint32_t r1 = sm_below(sm_draw(key, 1), (uint32_t)s - 1);
+      if (r1 >= r0) r1 += 1;
+      const float* xu = X + (int64_t)sid[off + r0] * ldx;
+      const float* xv = X + (int64_t)sid[off + r1] * ldx;
+      for (int dim = threadIdx.x; dim < d; dim += 256) {
+        scent[dim] = xu[dim];
+        scent[d + dim] = xv[dim];
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+      double wv[V], sv[V];
+      tm_node_consts<V>(scent, scent + d, j, d, wv, sv);
+      double au[V], av[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) au[e] = av[e] = 0.0;
+      int cnu = 0, cnv = 0;
+      for (int p = gid; p < s; p += TM_UNROLL * NG) {
+        float x[TM_UNROLL][V];
+        tm_load_rows<V, TM_UNROLL>(x, X, ldx, sid + off, p, NG, s, j, d, vec);
+#pragma unroll
+        for (int u = 0; u < TM_UNROLL; ++u) {
+          if (p + u * NG < s) {
+            const double delta = group_sum<L>(tm_part<V>(x[u], wv, sv));
+            if (delta <= 0.0) {
+              ++cnu;
+#pragma unroll
+              for (int e = 0; e < V; ++e) au[e] += (double)x[u][e];
+            } else {
+              ++cnv;
+#pragma unroll
+              for (int e = 0; e < V; ++e) av[e] += (double)x[u][e];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        acc[gid][0][j * V + e] = au[e];
+        acc[gid][1][j * V + e] = av[e];
+      }
+      if (j == 0) {
+        shc[gid][0] = cnu;
+        shc[gid][1] = cnv;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < 2 * d; e += 256) {
+        const int side = e / d, dim = e % d;
+        double t = 0.0;
+        for (int q = 0; q < NG; ++q) t += acc[q][side][dim];
+        const double sum = (((0.0 + t) + 0.0) + 0.0) + 0.0;
+        int cnt = 0;
+        for (int q = 0; q < NG; ++q) cnt += shc[q][side];
+        if (cnt > 0) scent[e] = (float)(sum / (double)cnt);
+      }
+      __syncthreads();
+    }
+    {  // delta keys with the final centroids
+      double wv[V], sv[V];
+      tm_node_consts<V>(scent, scent + d, j, d, wv, sv);
+      for (int p = gid; p < s; p += TM_UNROLL * NG) {
+        float x[TM_UNROLL][V];
+        tm_load_rows<V, TM_UNROLL>(x, X, ldx, sid + off, p, NG, s, j, d, vec);
+#pragma unroll
+        for (int u = 0; u < TM_UNROLL; ++u) {
+          if (p + u * NG < s) {
+            const double delta = group_sum<L>(tm_part<V>(x[u], wv, sv));
+            if (j == 0) skey[off + p + u * NG] = dkey(delta);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // threshold: the ceil(s/2)-th smallest (key, id), by a bitonic sort
+    int P2 = 1;
+    while (P2 < s) P2 <<= 1;
+    for (int e = threadIdx.x; e < P2; e += 256) {
+      sk[e] = e < s ? skey[off + e] : ~0ull;
+      si[e] = e < s ? sid[off + e] : INT32_MAX;
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= P2; kk <<= 1) {
+      for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+        for (int e = threadIdx.x; e < P2; e += 256) {
+          const int x = e ^ jj;
+          if (x > e) {
+            const bool up = (e & kk) == 0;
+            const bool gt = !kv_le(sk[e], si[e], sk[x], si[x]);
+            if (gt == up) {
+              const uint64_t tk = sk[e];
+              sk[e] = sk[x];
+              sk[x] = tk;
+              const int32_t ti = si[e];
+              si[e] = si[x];
+              si[x] = ti;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    const int h = (s + 1) / 2;
+    const uint64_t tk = sk[h - 1];
+    const int32_t ti = si[h - 1];
+    // stable partition of the node's positions: (key, id) <= threshold first
+    const int per = (s + 255) / 256;
+    const int p0 = threadIdx.x * per, p1 = min(s, p0 + per);
+    int cnt = 0;
+    for (int p = p0; p < p1; ++p) cnt += kv_le(skey[off + p], sid[off + p], tk, ti) ? 1 : 0;
+    int32_t tot;
+    const int32_t before = block_scan_excl_256(cnt, sscan, &tot);
+    int lpos = off + before, rpos = off + h + (min(p0, s) - before);
+    for (int p = p0; p < p1; ++p) {
+      const int32_t id = sid[off + p];
+      if (kv_le(skey[off + p], id, tk, ti))
+        sid2[lpos++] = id;
+      else
+        sid2[rpos++] = id;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < s; p += 256) sid[off + p] = sid2[off + p];
+    __syncthreads();
+  }
+  for (int p = threadIdx.x; p < S; p += 256) {
+    perm_a[R0 + p] = sid[p];
+    perm_b[R0 + p] = sid[p];
+  }
+}
+
 // ------------------------------------------------------------------ driver --
 template <int L, int V>
 static void launch_accum(knnkm_ctx* ctx, const TMPlan& P, const TMLevel& Lv, const float* X, int d,
@@ -766,6 +1067,16 @@ static void launch_delta(knnkm_ctx* ctx, const TMPlan& P, const TMLevel& Lv, con
                                                        P.d_tile_start + Lv.tile_base,
                                                        P.d_tile_len + Lv.tile_base, cent, keys,
                                                        vec ? 1 : 0);
+}
+
+template <int L, int V>
+static void launch_finish(knnkm_ctx* ctx, const TMPlan& P, const TMLevel& Lv, const float* X, int d,
+                          int64_t ldx, int32_t* perm, int32_t* perm_next, const uint64_t* seeds,
+                          uint64_t seed1, int round_tag, int iters, bool vec) {
+  k_tm_finish<L, V><<<Lv.nfin, 256, 0, ctx->stream>>>(
+      X, d, ldx, perm, perm_next, P.d_fin_off + Lv.fin_base, P.d_fin_size + Lv.fin_base,
+      P.d_fin_ob + Lv.fin_base, P.d_fin_oe + Lv.fin_base, P.d_fin_ops, seeds, seed1, round_tag, iters,
+      vec ? 1 : 0);
 }
 
 // Dispatch on the row-group shape chosen for d.
@@ -801,11 +1112,12 @@ knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_
     key.push_back(jk[q]);
     n += jn[q];
   }
+  key.push_back(ctx->tm_finish ? 1 : 0);
   if (!ctx->tm_plan || ctx->tm_plan->key != key) {
     KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     tm_plan_free(ctx->tm_plan);
     ctx->tm_plan = new TMPlan();
-    build_plan(*ctx->tm_plan, jn, jk);
+    build_plan(*ctx->tm_plan, jn, jk, ctx->tm_finish);
     KNNKM_TRY(upload_plan(ctx, *ctx->tm_plan));
   }
   const TMPlan& P = *ctx->tm_plan;
@@ -816,11 +1128,11 @@ knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_
   const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
   KNNKM_WS(ctx, permbuf, int32_t, "tm_perm", 2 * n);
   KNNKM_WS(ctx, keys, uint64_t, "tm_keys", n);
-  KNNKM_WS(ctx, cent, float, "tm_cent", (int64_t)P.max_split * 2 * d);
-  KNNKM_WS(ctx, partial, double, "tm_partial", (int64_t)P.max_tiles * 2 * d);
-  KNNKM_WS(ctx, pcnt, int32_t, "tm_pcnt", (int64_t)P.max_tiles * 2);
-  KNNKM_WS(ctx, sel, SelState, "tm_sel", std::max(1, P.max_big));
-  KNNKM_WS(ctx, hist, int32_t, "tm_hist", (int64_t)std::max(1, P.max_big) * 256);
+  KNNKM_WS(ctx, cent, float, "tm_cent", (int64_t)std::max(1, P.max_split) * 2 * d);
+  KNNKM_WS(ctx, partial, double, "tm_partial", (int64_t)std::max(1, P.max_tiles) * 2 * d);
+  KNNKM_WS(ctx, pcnt, int32_t, "tm_pcnt", (int64_t)std::max(1, P.max_tiles) * 2);
+  KNNKM_WS(ctx, sel, SelState, "tm_sel", (int64_t)std::max(1, P.max_big) * (TM_SEL_PASSES + 1));
+  KNNKM_WS(ctx, hist, int32_t, "tm_hist", (int64_t)std::max(1, P.max_big) * 256 * TM_SEL_PASSES);
   KNNKM_WS(ctx, tleft, int32_t, "tm_tleft", std::max(1, P.max_tiles));
   KNNKM_WS(ctx, cpart, double, "tm_cpart", (int64_t)std::max(1, P.max_chunks) * 2 * d);
   KNNKM_WS(ctx, ccnt, int32_t, "tm_ccnt", (int64_t)std::max(1, P.max_chunks) * 2);
@@ -832,11 +1144,14 @@ knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_
     const int32_t* s_off = P.d_split_off + L.split_base;
     const int32_t* s_size = P.d_split_size + L.split_base;
     const unsigned gw = (unsigned)((L.nsplit + 3) / 4);
+    if (L.nfin)
+      TM_DISPATCH(launch_finish, ctx, P, L, X, d, ldx, perm, perm_next, seeds_dev, seed1, round_tag, iters,
+                  vec);
     if (L.nsplit)
       k_tm_seed<<<gw, 256, 0, ctx->stream>>>(X, d, ldx, perm, L.nsplit, s_off, s_size,
                                              P.d_split_heap + L.split_base, P.d_split_job + L.split_base,
                                              seeds_dev, seed1, round_tag, cent);
-    for (int it = 0; it < iters; ++it) {
+    for (int it = 0; it < iters && L.nsplit; ++it) {
       TM_DISPATCH(launch_accum, ctx, P, L, X, d, ldx, perm, cent, partial, pcnt, vec);
       if (L.max_node_tiles > TM_CHUNK) {
         // nodes with many tiles: tiles -> chunks -> node, each stage in fixed order
@@ -851,7 +1166,7 @@ knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_
                                                       cent);
       }
     }
-    TM_DISPATCH(launch_delta, ctx, P, L, X, d, ldx, perm, cent, keys, vec);
+    if (L.nsplit) TM_DISPATCH(launch_delta, ctx, P, L, X, d, ldx, perm, cent, keys, vec);
     KNNKM_TRY(knnkm_check(ctx, "twomeans level"));
     if (L.nsmall)
       k_tm_split_small<<<L.nsmall, 256, 0, ctx->stream>>>(perm, keys, P.d_small_split + L.small_base,
@@ -862,17 +1177,18 @@ knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_
       const int32_t* bs = P.d_big_split + L.big_base;
       const int32_t* ts = P.d_tile_start + L.tile_base;
       const int32_t* tl = P.d_tile_len + L.tile_base;
-      k_tm_sel_init<<<grid_for((int64_t)L.nbig * 256, 256, 1024), 256, 0, ctx->stream>>>(L.nbig, bs, s_size,
-                                                                                    sel, hist);
-      for (int pass = 0; pass < 12; ++pass) {
-        k_tm_sel_hist<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, ts, tl, pass, sel, hist);
-        k_tm_sel_pick<<<L.nbig, 256, 0, ctx->stream>>>(pass, sel, hist);
-      }
-      k_tm_part_count<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, ts, tl, sel, tleft);
+      k_tm_sel_init<<<grid_for((int64_t)L.nbig * 256 * TM_SEL_PASSES, 256, 4096), 256, 0, ctx->stream>>>(
+          L.nbig, bs, s_size, sel, hist);
+      for (int pass = 0; pass < TM_SEL_PASSES; ++pass)
+        k_tm_sel_pass<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, P.d_big_btb + L.big_base, ts, tl,
+                                                            pass, L.nbig, sel, hist);
+      k_tm_part_count<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, P.d_big_btb + L.big_base, ts, tl,
+                                                            L.nbig, sel, hist, tleft);
       k_tm_part_scan<<<L.nbig, 256, 0, ctx->stream>>>(P.d_big_btb + L.big_base, P.d_big_bte + L.big_base,
                                                       tleft);
       k_tm_part_write<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, bs, s_off, s_size, ts, tl,
-                                                            sel, tleft, perm_next);
+                                                            sel + (int64_t)TM_SEL_PASSES * L.nbig, tleft,
+                                                            perm_next);
     }
     if (L.ncopy)
       k_tm_copy<<<L.ncopy, 256, 0, ctx->stream>>>(perm, P.d_copy_off + L.copy_base,
@@ -906,4 +1222,10 @@ extern "C" knnkm_status knnkm_twomeans(knnkm_ctx* ctx, const float* X, int64_t n
   if (ctx->dry) return KNNKM_OK;
   KNNKM_HIP(ctx, hipSetDevice(ctx->device));
   return ks_twomeans(ctx, X, n, d, ldx, k, seed, round_tag, bisect_iters, labels);
+}
+
+extern "C" knnkm_status knnkm_enable_subtree_finish(knnkm_ctx* ctx, int32_t on) {
+  if (!ctx) return KNNKM_EINVAL;
+  ctx->tm_finish = on != 0;
+  return KNNKM_OK;
 }

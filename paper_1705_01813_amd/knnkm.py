@@ -24,7 +24,8 @@ EXPORTS = [
     "knnkm_default_params", "knnkm_workspace_bytes", "knn_assign", "centroid_update",
     "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
     "knn_kmeans_fit", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times",
-    "knnkm_fit_batched", "knnkm_enable_graphs", "knnkm_enable_active_sets", "knnkm_autotune", "knnkm_autotune_table", "knnkm_set_assign_shape",
+    "knnkm_fit_batched", "knnkm_enable_graphs", "knnkm_enable_active_sets", "knnkm_enable_subtree_finish",
+    "knnkm_autotune", "knnkm_autotune_table", "knnkm_set_assign_shape",
     "knnkm_server_create", "knnkm_server_submit", "knnkm_server_wait",
     "knnkm_server_stats_get", "knnkm_server_last_error", "knnkm_server_destroy",
 ]
@@ -137,6 +138,7 @@ def lib():
             "knnkm_enable_timing": [P, i32],
             "knnkm_enable_graphs": [P, i32],
             "knnkm_enable_active_sets": [P, i32],
+            "knnkm_enable_subtree_finish": [P, i32],
             "knnkm_autotune": [P, i32],
             "knnkm_set_assign_shape": [P, i32, i32, i32],
             "knnkm_autotune_table": [P, i64, ctypes.POINTER(i64)],
@@ -354,6 +356,10 @@ def knnkm_enable_graphs(ctx, on=True):
 
 def knnkm_enable_active_sets(ctx, on=True):
     _chk(ctx.handle, lib().knnkm_enable_active_sets(ctx.handle, 1 if on else 0))
+
+
+def knnkm_enable_subtree_finish(ctx, on=True):
+    _chk(ctx.handle, lib().knnkm_enable_subtree_finish(ctx.handle, 1 if on else 0))
 
 
 def knnkm_autotune(ctx, on=True):

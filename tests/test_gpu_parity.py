@@ -183,6 +183,60 @@ def test_twomeans_parity(ctx, n, d, k):
     assert np.array_equal(got, want), f"agreement {np.mean(got == want):.6f}"
 
 
+@pytest.mark.parametrize("n,d,k,iters", [(200_003, 128, 2000, 2), (50_000, 3, 20_000, 2), (30_000, 512, 300, 1),
+                                         (4097, 64, 4097, 2), (100_000, 24, 97, 3), (1024, 7, 1000, 0)])
+def test_twomeans_subtree_finish_same_bits(ctx, n, d, k, iters):
+    """Subtrees of at most 1,024 members finished by one block each give the
+    labels of the per-depth kernels, bit for bit (leaves of one member, a
+    partial last depth, no Lloyd step, d = 512)."""
+    say("twomeans subtree finish", n, d, k, iters)
+    X = dev(datagen.mixture(n, d, 50, seed=n + 5))
+
+    def run(on):
+        knnkm.knnkm_enable_subtree_finish(ctx, on)
+        lab = torch.empty(n, dtype=torch.int32, device=DEV)
+        knnkm.knnkm_twomeans(ctx, X, k, 7, 3, iters, lab)
+        return host(lab)
+
+    try:
+        ref = run(False)
+        got = run(True)
+        assert np.array_equal(ref, got), f"agreement {np.mean(ref == got):.6f}"
+        assert np.array_equal(np.bincount(got, minlength=k), np.bincount(ref, minlength=k))
+    finally:
+        knnkm.knnkm_enable_subtree_finish(ctx, True)
+
+
+def test_batch_subtree_finish_same_bits(ctx):
+    """Many jobs in one tree launch (graph rounds and the fit's initial
+    clusters): jobs whose nodes reach 1,024 members at different depths, one
+    job small enough to be finished from the root."""
+    sizes = [3000, 701, 1500, 64, 9000, 2201]
+    Xs, n_off, ks, seeds = _batch(sizes, 40, seed=77)
+    X = dev(np.concatenate(Xs))
+    n, kappa, K = int(n_off[-1]), 8, sum(ks)
+    p = knnkm.default_params(kappa=kappa, max_iters=6, seed=5)
+    say("batch subtree finish", sizes, ks)
+
+    def run(on):
+        knnkm.knnkm_enable_subtree_finish(ctx, on)
+        gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+        gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+        lab = torch.empty(n, dtype=torch.int32, device=DEV)
+        C = torch.empty((K, 40), dtype=torch.float32, device=DEV)
+        cnt = torch.empty(K, dtype=torch.int32, device=DEV)
+        tr = knnkm.knnkm_fit_batched(ctx, X, n_off, ks, seeds, p, gi, gd, lab, C, cnt)
+        return host(gi), host(gd), host(lab), host(C), host(cnt), np.asarray(tr)
+
+    try:
+        ref = run(False)
+        got = run(True)
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b)
+    finally:
+        knnkm.knnkm_enable_subtree_finish(ctx, True)
+
+
 # ------------------------------------------------------------------- graph --
 @pytest.mark.parametrize("n,d,kappa", [(50, 4, 49), (1000, 32, 10), (3001, 128, 50), (500, 512, 20),
                                        (300, 16, 128)])
