@@ -302,12 +302,14 @@ knnkm_status knnkm_enable_graphs(knnkm_ctx* ctx, int32_t on);
 knnkm_status knnkm_enable_active_sets(knnkm_ctx* ctx, int32_t on);
 
 /* Subtree finishing in the two-means tree of Alg. 1 (default on).  Once a
- * node to split has at most 1,024 members, one block performs every later
- * split of its subtree (seeds, the Lloyd 2-means steps, the ordering by
- * delta and the balanced split) with the member ids held on chip, instead of
- * one launch per step per depth.  Every step keeps the same arithmetic and
- * order, so labels from knnkm_twomeans, knn_build and knn_kmeans_fit are the
- * same bits with it on or off.  Returns KNNKM_EINVAL for a null context. */
+ * node to split has at most R members, one block performs every later split
+ * of its subtree (seeds, the Lloyd 2-means steps, the ordering by delta and
+ * the balanced split) with the member ids held on chip, instead of one launch
+ * per step per depth.  Every step keeps the same arithmetic and order, so
+ * labels from knnkm_twomeans, knn_build and knn_kmeans_fit are the same bits
+ * with it on or off and for every R.  on: 0 off, 1 on with R = 1,024, or R
+ * itself (2..1,024).  Returns KNNKM_EINVAL for a null context or another
+ * value. */
 knnkm_status knnkm_enable_subtree_finish(knnkm_ctx* ctx, int32_t on);
 
 /* Autotuner of the assignment's launch shapes (default on): the first call

@@ -42,7 +42,7 @@ struct knnkm_ctx {
   // launch shapes of the assignment chosen by timing the candidates once
   bool autotune = true;
   bool active_sets = true;  // fit sweeps look only at samples that can change
-  bool tm_finish = true;    // two-means subtrees of <= TM_TILE members finished by one block
+  int tm_finish_max = 1024;  // two-means subtrees up to this size finished by one block (0: off)
   int assign_gs = 0, assign_pb = 64, assign_lazy = 0;  // forced assignment shape (gs = 0: automatic)
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   bool capturing = false;

@@ -667,44 +667,62 @@ __global__ __launch_bounds__(256) void k_refine_merge(const float* __restrict__ 
       }
       uint64_t M = __ballot(valid);
       if (!M) continue;
-      // exact float64 distances: group g takes the g-th pending candidate;
-      // lane j of the group reads float4 chunks j, j + L, ... of both rows
+      // exact float64 distances: group g takes the g-th and the (G+g)-th
+      // pending candidates (both rows in flight); lane j of the group reads
+      // float4 chunks j, j + L, ... of the rows, summed in that order
       for (uint64_t rest = M; rest;) {
-        int q = -1;
+        int q0 = -1, q1 = -1;
 #pragma unroll
-        for (int gg = 0; gg < G; ++gg) {
+        for (int gg = 0; gg < 2 * G; ++gg) {
           if (rest) {
             const int b = (int)__builtin_ctzll(rest);
             rest &= rest - 1;
-            if (gg == g) q = b;
+            if (gg == g) q0 = b;
+            if (gg == G + g) q1 = b;
           }
         }
-        double a = 0.0;
-        const int jd = __shfl(cid, q < 0 ? 0 : q, 64);  // all lanes take part
-        if (q >= 0) {
-          const float* xc = X + (int64_t)jd * ldx;
+        double a0 = 0.0, a1 = 0.0;
+        const int jd0 = __shfl(cid, q0 < 0 ? 0 : q0, 64);  // all lanes take part
+        const int jd1 = __shfl(cid, q1 < 0 ? 0 : q1, 64);
+        const float* xc0 = X + (int64_t)(q0 >= 0 ? jd0 : (int)i) * ldx;
+        const float* xc1 = X + (int64_t)(q1 >= 0 ? jd1 : (int)i) * ldx;
+        if (q0 >= 0) {
           if (vec) {
             for (int c4 = 4 * j; c4 < d; c4 += 4 * L) {
               const float4 p4 = *reinterpret_cast<const float4*>(xr + c4);
-              const float4 q4 = *reinterpret_cast<const float4*>(xc + c4);
-              double df = (double)p4.x - (double)q4.x;
-              a = fma(df, df, a);
-              df = (double)p4.y - (double)q4.y;
-              a = fma(df, df, a);
-              df = (double)p4.z - (double)q4.z;
-              a = fma(df, df, a);
-              df = (double)p4.w - (double)q4.w;
-              a = fma(df, df, a);
+              const float4 u4 = *reinterpret_cast<const float4*>(xc0 + c4);
+              const float4 v4 = *reinterpret_cast<const float4*>(xc1 + c4);
+              double df = (double)p4.x - (double)u4.x;
+              a0 = fma(df, df, a0);
+              df = (double)p4.y - (double)u4.y;
+              a0 = fma(df, df, a0);
+              df = (double)p4.z - (double)u4.z;
+              a0 = fma(df, df, a0);
+              df = (double)p4.w - (double)u4.w;
+              a0 = fma(df, df, a0);
+              df = (double)p4.x - (double)v4.x;
+              a1 = fma(df, df, a1);
+              df = (double)p4.y - (double)v4.y;
+              a1 = fma(df, df, a1);
+              df = (double)p4.z - (double)v4.z;
+              a1 = fma(df, df, a1);
+              df = (double)p4.w - (double)v4.w;
+              a1 = fma(df, df, a1);
             }
           } else {
             for (int t = j; t < d; t += L) {
-              const double df = (double)xr[t] - (double)xc[t];
-              a = fma(df, df, a);
+              const double p = (double)xr[t];
+              double df = p - (double)xc0[t];
+              a0 = fma(df, df, a0);
+              df = p - (double)xc1[t];
+              a1 = fma(df, df, a1);
             }
           }
         }
-        a = group_sum<L>(a);
-        if (q >= 0 && j == 0) keys[q] = (float)a;
+        a0 = group_sum<L>(a0);
+        a1 = group_sum<L>(a1);
+        if (q0 >= 0 && j == 0) keys[q0] = (float)a0;
+        if (q1 >= 0 && j == 0) keys[q1] = (float)a1;
       }
       __builtin_amdgcn_wave_barrier();
       const float ck = valid ? keys[lane] : FLT_MAX;

@@ -29,6 +29,7 @@
 #define TM_SMALL 2048   // nodes up to this size split inside one block
 #define TM_CHUNK 16     // tiles per chunk of the two-stage node reduction
 #define TM_SEL_PASSES 12  // 8-bit digits of the 96-bit (delta key, id)
+#define TM_FINISH_DEFAULT TM_TILE  // largest subtree root that one block finishes
 
 struct TMLevel {
   int depth;
@@ -90,11 +91,12 @@ void tm_plan_free(TMPlan* p) { delete p; }
 // Tree shapes of several independent jobs (job j: rows [off_j, off_j + n_j),
 // k_j leaves), merged depth by depth so one launch per step covers every job
 // that still splits; a job whose tree is complete is carried over as a copy.
-// With `finish`, a split node of at most TM_TILE members becomes the root of
-// a subtree that one block finishes: its splits at this and every later depth
-// leave the per-depth lists and become that subtree's ops.
+// With finish_max > 0, a split node of at most finish_max (<= TM_TILE)
+// members becomes the root of a subtree that one block finishes: its splits
+// at this and every later depth leave the per-depth lists and become that
+// subtree's ops.
 static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vector<int32_t>& jk,
-                       bool finish) {
+                       int finish_max) {
   P = TMPlan();
   const int nj = (int)jn.size();
   P.key.clear();
@@ -104,7 +106,7 @@ static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vec
     P.key.push_back(jk[q]);
     total += jn[q];
   }
-  P.key.push_back(finish ? 1 : 0);
+  P.key.push_back(finish_max);
   P.n = total;
   std::vector<std::vector<int64_t>> joff(nj), jsize(nj);
   std::vector<std::vector<int32_t>> jroot(nj);  // per node: finished subtree holding it, or -1
@@ -161,7 +163,7 @@ static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vec
     std::vector<int32_t> nroot;
     for (int i = 0; i < m; ++i) {
       int32_t rt = root[i];
-      if (rt < 0 && finish && split[i] && size[i] <= TM_TILE) {
+      if (rt < 0 && split[i] && size[i] <= finish_max) {
         rt = (int32_t)P.fin_off.size();
         P.fin_off.push_back((int32_t)off[i]);
         P.fin_size.push_back((int32_t)size[i]);
@@ -419,6 +421,7 @@ __device__ inline void tm_load_rows(float (&x)[U][V], const float* __restrict__ 
 }
 
 #define TM_UNROLL 4
+#define TM_FIN_UNROLL 3  // fewer in flight per group in the finisher: four blocks per CU fit
 
 // One block per tile: side of each member, float64 sums per side.  Group gid
 // of the block takes tile positions gid, gid + NG, ...; the NG group sums are
@@ -886,7 +889,7 @@ __global__ void k_tm_labels(const int32_t* __restrict__ perm, const int32_t* __r
 // bitwise the one the per-depth path builds.  The final ids go to both
 // permutation buffers, so the ping-pong copies of later depths see them.
 template <int L, int V>
-__global__ __launch_bounds__(256) void k_tm_finish(const float* __restrict__ X, int d, int64_t ldx,
+__global__ __launch_bounds__(256, 4) void k_tm_finish(const float* __restrict__ X, int d, int64_t ldx,
                                                    int32_t* __restrict__ perm_a, int32_t* __restrict__ perm_b,
                                                    const int32_t* __restrict__ f_off,
                                                    const int32_t* __restrict__ f_size,
@@ -897,17 +900,19 @@ __global__ __launch_bounds__(256) void k_tm_finish(const float* __restrict__ X, 
                                                    int round_tag, int iters, int vec) {
   constexpr int NG = 4 * (64 / L);
   constexpr int W = L * V;
-  constexpr int ACC_BYTES = NG * 2 * W * 8;
+  constexpr int ACC_BYTES = NG * W * 8;  // one side's group sums at a time
   constexpr int SORT_BYTES = TM_TILE * 12;
-  __shared__ int32_t sid[TM_TILE], sid2[TM_TILE];
+  __shared__ int32_t sid[TM_TILE];
   __shared__ uint64_t skey[TM_TILE];
   __shared__ float scent[2 * KNNKM_MAX_D];
+  // group sums, or the sort buffers, or the partition's output
   __shared__ __align__(16) char sraw[ACC_BYTES > SORT_BYTES ? ACC_BYTES : SORT_BYTES];
   __shared__ int32_t shc[NG][2];
   __shared__ int32_t sscan[8];
-  double(*acc)[2][W] = reinterpret_cast<double(*)[2][W]>(sraw);
+  double(*acc)[W] = reinterpret_cast<double(*)[W]>(sraw);
   uint64_t* sk = reinterpret_cast<uint64_t*>(sraw);
   int32_t* si = reinterpret_cast<int32_t*>(sraw + TM_TILE * 8);
+  int32_t* sid2 = reinterpret_cast<int32_t*>(sraw);
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = lane % L, gid = w * (64 / L) + lane / L;
@@ -938,11 +943,11 @@ __global__ __launch_bounds__(256) void k_tm_finish(const float* __restrict__ X, 
 #pragma unroll
       for (int e = 0; e < V; ++e) au[e] = av[e] = 0.0;
       int cnu = 0, cnv = 0;
-      for (int p = gid; p < s; p += TM_UNROLL * NG) {
-        float x[TM_UNROLL][V];
-        tm_load_rows<V, TM_UNROLL>(x, X, ldx, sid + off, p, NG, s, j, d, vec);
+      for (int p = gid; p < s; p += TM_FIN_UNROLL * NG) {
+        float x[TM_FIN_UNROLL][V];
+        tm_load_rows<V, TM_FIN_UNROLL>(x, X, ldx, sid + off, p, NG, s, j, d, vec);
 #pragma unroll
-        for (int u = 0; u < TM_UNROLL; ++u) {
+        for (int u = 0; u < TM_FIN_UNROLL; ++u) {
           if (p + u * NG < s) {
             const double delta = group_sum<L>(tm_part<V>(x[u], wv, sv));
             if (delta <= 0.0) {
@@ -957,35 +962,33 @@ __global__ __launch_bounds__(256) void k_tm_finish(const float* __restrict__ X, 
           }
         }
       }
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        acc[gid][0][j * V + e] = au[e];
-        acc[gid][1][j * V + e] = av[e];
-      }
       if (j == 0) {
         shc[gid][0] = cnu;
         shc[gid][1] = cnv;
       }
-      __syncthreads();
-      for (int e = threadIdx.x; e < 2 * d; e += 256) {
-        const int side = e / d, dim = e % d;
-        double t = 0.0;
-        for (int q = 0; q < NG; ++q) t += acc[q][side][dim];
-        const double sum = (((0.0 + t) + 0.0) + 0.0) + 0.0;
-        int cnt = 0;
-        for (int q = 0; q < NG; ++q) cnt += shc[q][side];
-        if (cnt > 0) scent[e] = (float)(sum / (double)cnt);
+      for (int side = 0; side < 2; ++side) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[gid][j * V + e] = side ? av[e] : au[e];
+        __syncthreads();
+        for (int dim = threadIdx.x; dim < d; dim += 256) {
+          double t = 0.0;
+          for (int q = 0; q < NG; ++q) t += acc[q][dim];
+          const double sum = (((0.0 + t) + 0.0) + 0.0) + 0.0;
+          int cnt = 0;
+          for (int q = 0; q < NG; ++q) cnt += shc[q][side];
+          if (cnt > 0) scent[side * d + dim] = (float)(sum / (double)cnt);
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
     {  // delta keys with the final centroids
       double wv[V], sv[V];
       tm_node_consts<V>(scent, scent + d, j, d, wv, sv);
-      for (int p = gid; p < s; p += TM_UNROLL * NG) {
-        float x[TM_UNROLL][V];
-        tm_load_rows<V, TM_UNROLL>(x, X, ldx, sid + off, p, NG, s, j, d, vec);
+      for (int p = gid; p < s; p += TM_FIN_UNROLL * NG) {
+        float x[TM_FIN_UNROLL][V];
+        tm_load_rows<V, TM_FIN_UNROLL>(x, X, ldx, sid + off, p, NG, s, j, d, vec);
 #pragma unroll
-        for (int u = 0; u < TM_UNROLL; ++u) {
+        for (int u = 0; u < TM_FIN_UNROLL; ++u) {
           if (p + u * NG < s) {
             const double delta = group_sum<L>(tm_part<V>(x[u], wv, sv));
             if (j == 0) skey[off + p + u * NG] = dkey(delta);
@@ -1112,12 +1115,12 @@ knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_
     key.push_back(jk[q]);
     n += jn[q];
   }
-  key.push_back(ctx->tm_finish ? 1 : 0);
+  key.push_back(ctx->tm_finish_max);
   if (!ctx->tm_plan || ctx->tm_plan->key != key) {
     KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     tm_plan_free(ctx->tm_plan);
     ctx->tm_plan = new TMPlan();
-    build_plan(*ctx->tm_plan, jn, jk, ctx->tm_finish);
+    build_plan(*ctx->tm_plan, jn, jk, ctx->tm_finish_max);
     KNNKM_TRY(upload_plan(ctx, *ctx->tm_plan));
   }
   const TMPlan& P = *ctx->tm_plan;
@@ -1226,6 +1229,8 @@ extern "C" knnkm_status knnkm_twomeans(knnkm_ctx* ctx, const float* X, int64_t n
 
 extern "C" knnkm_status knnkm_enable_subtree_finish(knnkm_ctx* ctx, int32_t on) {
   if (!ctx) return KNNKM_EINVAL;
-  ctx->tm_finish = on != 0;
+  if (on < 0 || on > TM_TILE)
+    return knnkm_fail(ctx, KNNKM_EINVAL, "subtree finish: %d is not 0, 1 or a root size 2..%d", on, TM_TILE);
+  ctx->tm_finish_max = on == 1 ? TM_FINISH_DEFAULT : on;
   return KNNKM_OK;
 }

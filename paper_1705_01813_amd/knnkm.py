@@ -359,7 +359,8 @@ def knnkm_enable_active_sets(ctx, on=True):
 
 
 def knnkm_enable_subtree_finish(ctx, on=True):
-    _chk(ctx.handle, lib().knnkm_enable_subtree_finish(ctx.handle, 1 if on else 0))
+    """on: False/0 off, True/1 on (subtree roots up to 1,024 members), or the root size limit."""
+    _chk(ctx.handle, lib().knnkm_enable_subtree_finish(ctx.handle, int(on)))
 
 
 def knnkm_autotune(ctx, on=True):

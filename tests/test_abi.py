@@ -118,3 +118,12 @@ def test_assign_shape_validation(dry):
         assert _call("knnkm_set_assign_shape", h, gs, pb, lazy) == knnkm.OK, (gs, pb, lazy)
     for gs, pb, lazy in [(8, 64, 0), (3, 64, 0), (2, 96, 0), (-1, 64, 0), (4, 64, 1), (1, 64, 2)]:
         assert _call("knnkm_set_assign_shape", h, gs, pb, lazy) == knnkm.EINVAL, (gs, pb, lazy)
+
+
+def test_subtree_finish_validation(dry):
+    h = dry.handle
+    for on in (0, 1, 2, 256, 1024):
+        assert _call("knnkm_enable_subtree_finish", h, on) == knnkm.OK, on
+    for on in (-1, 1025, 4096):
+        assert _call("knnkm_enable_subtree_finish", h, on) == knnkm.EINVAL, on
+    assert _call("knnkm_enable_subtree_finish", h, 1) == knnkm.OK

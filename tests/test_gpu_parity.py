@@ -186,9 +186,9 @@ def test_twomeans_parity(ctx, n, d, k):
 @pytest.mark.parametrize("n,d,k,iters", [(200_003, 128, 2000, 2), (50_000, 3, 20_000, 2), (30_000, 512, 300, 1),
                                          (4097, 64, 4097, 2), (100_000, 24, 97, 3), (1024, 7, 1000, 0)])
 def test_twomeans_subtree_finish_same_bits(ctx, n, d, k, iters):
-    """Subtrees of at most 1,024 members finished by one block each give the
-    labels of the per-depth kernels, bit for bit (leaves of one member, a
-    partial last depth, no Lloyd step, d = 512)."""
+    """Subtrees of at most 1,024 (or 300) members finished by one block each
+    give the labels of the per-depth kernels, bit for bit (leaves of one
+    member, a partial last depth, no Lloyd step, d = 512)."""
     say("twomeans subtree finish", n, d, k, iters)
     X = dev(datagen.mixture(n, d, 50, seed=n + 5))
 
@@ -199,10 +199,10 @@ def test_twomeans_subtree_finish_same_bits(ctx, n, d, k, iters):
         return host(lab)
 
     try:
-        ref = run(False)
-        got = run(True)
-        assert np.array_equal(ref, got), f"agreement {np.mean(ref == got):.6f}"
-        assert np.array_equal(np.bincount(got, minlength=k), np.bincount(ref, minlength=k))
+        ref = run(0)
+        for lim in (1, 300):  # roots up to 1,024 members, up to 300
+            got = run(lim)
+            assert np.array_equal(ref, got), (lim, f"agreement {np.mean(ref == got):.6f}")
     finally:
         knnkm.knnkm_enable_subtree_finish(ctx, True)
 
