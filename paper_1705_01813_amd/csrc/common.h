@@ -238,7 +238,7 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
 // Active-set marks of the samples moved between cur and nxt and of the rows
 // listing them (reverse lists of the graph); moved labels copied into cur.
 knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,
-                           const int32_t* rev_src, uint8_t* act_out);
+                           const int32_t* rev_src, uint8_t* act_out, const int64_t* moved, int64_t all_at);
 // Reverse lists of an n x kappa graph: rev_off (n + 1), rev_src (n * kappa).
 knnkm_status ks_reverse_graph(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, int32_t* rev_off,
                               int32_t* rev_src);

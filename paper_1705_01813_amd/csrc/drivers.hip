@@ -439,12 +439,15 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   // initial partition: its update rebuilds the sums from a label sort and
   // the segmented float64 sums (as at initialisation) and converts them to
   // fixed point; later sweeps apply only their moves.
-  auto update = [&](int32_t* cu, const int32_t* nx, double* tr, bool full) -> knnkm_status {
+  auto update = [&](int32_t* cu, const int32_t* nx, double* tr, bool full, const int64_t* mv) -> knnkm_status {
     if (full) {
       KNNKM_TRY(ks_label_sort(ctx, nx, n, K, counts, off, mem));
       KNNKM_TRY(ks_segsum(ctx, Xp, n, d, d, K, counts, off, mem, C, sums0, Iterm));
       KNNKM_TRY(ks_fx_from_f64(ctx, sums0, K, d, cs, Dfx));
-      if (use_act) KNNKM_TRY(ks_mark_moved(ctx, n, cu, nx, rev_off, rev_src, act_for(nx)));
+      // the moves' marks, or every row once the moved samples' reverse
+      // lists (kappa entries each on average) would cover n
+      if (use_act)
+        KNNKM_TRY(ks_mark_moved(ctx, n, cu, nx, rev_off, rev_src, act_for(nx), mv, (n + kappa) / (kappa + 1)));
       // every centroid was recomputed
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(nx), K, 1));
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(cu), K, 0));
@@ -476,7 +479,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       mark(7 + 2 * (t - 1));
       ctx->assign_n = t;
     }
-    KNNKM_TRY(update(cur, nxt, trace_dev + (int64_t)t * m, t == 1));
+    KNNKM_TRY(update(cur, nxt, trace_dev + (int64_t)t * m, t == 1, moved + t));
     std::swap(cur, nxt);
     it = t;
     return KNNKM_OK;
@@ -518,12 +521,12 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       if (ok) {
         ctx->capturing = true;
         knnkm_status st = sweep(cur, nxt, mv_slot, false, nullptr, nullptr);
-        if (st == KNNKM_OK) st = update(cur, nxt, tr_slot, false);
+        if (st == KNNKM_OK) st = update(cur, nxt, tr_slot, false, nullptr);
         if (st == KNNKM_OK) {
           k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
           st = sweep(nxt, cur, mv_slot, false, nullptr, nullptr);
         }
-        if (st == KNNKM_OK) st = update(nxt, cur, tr_slot, false);
+        if (st == KNNKM_OK) st = update(nxt, cur, tr_slot, false, nullptr);
         if (st == KNNKM_OK) k_fit_book<<<1, 256, 0, ctx->stream>>>(mv_slot, moved, tr_slot, trace_dev, m, book_it);
         ctx->capturing = false;
         ok = hipStreamEndCapture(ctx->stream, &graph) == hipSuccess && st == KNNKM_OK && graph;

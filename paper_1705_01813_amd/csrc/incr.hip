@@ -225,20 +225,30 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
 
 // Active-set marks of the moved samples alone (the sweep whose sums are
 // rebuilt rather than updated), with their labels synchronised as above.
+// When the sweep moved at least all_at samples (their reverse lists then
+// cover most rows), every row is marked instead of the moved samples and the
+// rows listing them: a superset of the marks, so the next sweep's results are
+// the same, for one streaming pass instead of scattered marks.
 __global__ __launch_bounds__(256) void k_mark_moved(int64_t n, int32_t* __restrict__ cur,
                                                     const int32_t* __restrict__ nxt,
                                                     const int32_t* __restrict__ rev_off,
-                                                    const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out) {
+                                                    const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out,
+                                                    const int64_t* __restrict__ moved, int64_t all_at) {
   const int lane = threadIdx.x & 63;
+  const bool all = *moved >= all_at;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
     const int64_t p = base + lane;
     int b = 0;
-    const bool moved = p < n && cur[p] != (b = nxt[p]);
-    if (moved) cur[p] = b;
-    for (uint64_t M = __ballot(moved); M; M &= M - 1)
-      mark_moved(base + (int)__builtin_ctzll(M), rev_off, rev_src, act_out, lane);
+    const bool mv = p < n && cur[p] != (b = nxt[p]);
+    if (mv) cur[p] = b;
+    if (all) {
+      if (p < n) mark_one(act_out, p);
+    } else {
+      for (uint64_t M = __ballot(mv); M; M &= M - 1)
+        mark_moved(base + (int)__builtin_ctzll(M), rev_off, rev_src, act_out, lane);
+    }
   }
 }
 
@@ -352,8 +362,9 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
 }
 
 knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,
-                           const int32_t* rev_src, uint8_t* act_out) {
-  k_mark_moved<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, cur, nxt, rev_off, rev_src, act_out);
+                           const int32_t* rev_src, uint8_t* act_out, const int64_t* moved, int64_t all_at) {
+  k_mark_moved<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, cur, nxt, rev_off, rev_src, act_out, moved,
+                                                                all_at);
   return knnkm_check(ctx, "active-set marks");
 }
 
