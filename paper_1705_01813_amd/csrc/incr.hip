@@ -131,10 +131,37 @@ __global__ void k_fx_from_f64(const double* __restrict__ sums, int64_t kd, int d
 // by this sweep's assignment, which has finished, so every writer here
 // stores the same value and the order of the stores does not matter.
 __device__ inline void mark_one(uint8_t* __restrict__ act_out, int64_t x) { act_out[x] = act_out[x] | 2; }
-__device__ inline void mark_moved(int64_t p, const int32_t* __restrict__ rev_off, const int32_t* __restrict__ rev_src,
-                                  uint8_t* __restrict__ act_out, int lane) {
-  if (lane == 0) mark_one(act_out, p);
-  for (int32_t e = rev_off[p] + lane; e < rev_off[p + 1]; e += 64) mark_one(act_out, rev_src[e]);
+// Whole wave: the marks of every moved sample of the wave (lane q holds
+// position p and `moved`), the wave's marks laid end to end over the lanes
+// (sample q owns entries [ex_q, ex_q + 1 + its reverse-list length); its
+// first entry is the sample itself), so all of them are in flight at once.
+__device__ inline void mark_moved_wave(bool moved, int64_t p, const int32_t* __restrict__ rev_off,
+                                       const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out,
+                                       int lane) {
+  int32_t r0 = 0, c = 0;
+  if (moved) {
+    r0 = rev_off[p];
+    c = 1 + rev_off[p + 1] - r0;
+  }
+  int32_t inc = c;  // inclusive scan of the entry counts over the lanes
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  const int32_t total = __shfl(inc, 63, 64);
+  for (int32_t e0 = 0; e0 < total; e0 += 64) {  // wave-uniform: every lane takes part in the shuffles
+    const int32_t e = e0 + lane;
+    int q = 0;  // owner: the first lane whose inclusive count exceeds e
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+      if (__shfl(inc, q + step - 1, 64) <= e) q += step;
+    q = min(q, 63);
+    const int32_t local = e - (__shfl(inc, q, 64) - __shfl(c, q, 64));
+    const int32_t rq = __shfl(r0, q, 64);
+    const int64_t pq = __shfl(p, q, 64);
+    if (e < total) mark_one(act_out, local == 0 ? pq : (int64_t)rev_src[rq + local - 1]);
+  }
 }
 
 // 128-bit two's-complement accumulation in registers
@@ -180,6 +207,7 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
     }
     uint64_t M = __ballot(moved);
     if (!M) continue;  // wave-uniform
+    if (act_out) mark_moved_wave(moved, p, rev_off, rev_src, act_out, lane);
     int run_from = -1, run_to = -1;
     uint64_t fh[DPL], fl[DPL], th[DPL], tl[DPL];
 #pragma unroll
@@ -192,10 +220,21 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
         h[e] = l[e] = 0;
       }
     };
+    // the next moved sample's row is loaded while this one is converted
+    float xn[DPL];
+    auto load = [&](int q) {
+      const float* row = X + (base + q) * (int64_t)d;
+#pragma unroll
+      for (int e = 0; e < DPL; ++e) xn[e] = lane + 64 * e < d ? row[lane + 64 * e] : 0.f;
+    };
+    load((int)__builtin_ctzll(M));
     for (; M; M &= M - 1) {
       const int q = (int)__builtin_ctzll(M);
+      float xr[DPL];
+#pragma unroll
+      for (int e = 0; e < DPL; ++e) xr[e] = xn[e];
+      if (M & (M - 1)) load((int)__builtin_ctzll(M & (M - 1)));
       const int from = __shfl(a, q, 64), to = __shfl(b, q, 64);
-      if (act_out) mark_moved(base + q, rev_off, rev_src, act_out, lane);
       if (from != run_from) {
         if (run_from >= 0) flush(fh, fl, run_from);
         run_from = from;
@@ -205,13 +244,12 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
         run_to = to;
       }
       const int s = cs[to];  // both clusters belong to the sample's job
-      const float* row = X + (base + q) * (int64_t)d;
 #pragma unroll
       for (int e = 0; e < DPL; ++e) {
         const int t = lane + 64 * e;
         if (t < d) {
           uint64_t hi, lo;
-          fx_of_double((double)row[t], s, hi, lo);
+          fx_of_double((double)xr[e], s, hi, lo);
           add128(th[e], tl[e], hi, lo);
           fx_neg(hi, lo);
           add128(fh[e], fl[e], hi, lo);
@@ -245,9 +283,8 @@ __global__ __launch_bounds__(256) void k_mark_moved(int64_t n, int32_t* __restri
     if (mv) cur[p] = b;
     if (all) {
       if (p < n) mark_one(act_out, p);
-    } else {
-      for (uint64_t M = __ballot(mv); M; M &= M - 1)
-        mark_moved(base + (int)__builtin_ctzll(M), rev_off, rev_src, act_out, lane);
+    } else if (__ballot(mv)) {
+      mark_moved_wave(mv, p, rev_off, rev_src, act_out, lane);
     }
   }
 }
