@@ -265,7 +265,7 @@ __global__ __launch_bounds__(512) void k_refine_tile(const float* __restrict__ X
                                                      int kappa, int32_t k, const int32_t* __restrict__ offsets,
                                                      const int32_t* __restrict__ members,
                                                      const int32_t* __restrict__ wb_off, int64_t max_items,
-                                                     float err_c, int vec, int32_t* __restrict__ G_ids,
+                                                     int smin, float err_c, int vec, int32_t* __restrict__ G_ids,
                                                      float* __restrict__ G_d2) {
   extern __shared__ __align__(16) char smem[];
   const TileLayout lay(RB, dpad, SINGLE, kappa);
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(512) void k_refine_tile(const float* __restrict__ X
     cl = blockIdx.x;
     i0 = 0;
     s = offsets[cl + 1] - offsets[cl];
-    if (s < 2 || s > RB) return;
+    if (s < 2 || s <= smin || s > RB) return;  // another launch takes clusters of <= smin
   } else {
     const int64_t item = blockIdx.x;
     if (item >= max_items || item >= wb_off[k]) return;
@@ -792,12 +792,12 @@ __global__ void k_row_blocks(const int32_t* __restrict__ counts, int32_t k, int 
 template <bool BF16, int L, int V, int RB, bool SINGLE>
 static void launch_tile(knnkm_ctx* ctx, unsigned grid, const float* X, int d, int64_t ldx, int dpad,
                         int kappa, int32_t k, const int32_t* off, const int32_t* mem, const int32_t* wb,
-                        int64_t max_items, float err_c, bool vec, int32_t* G_ids, float* G_d2) {
+                        int64_t max_items, int smin, float err_c, bool vec, int32_t* G_ids, float* G_d2) {
   const size_t lds = refine_tile_lds(d, RB, SINGLE, kappa);
   hipFuncSetAttribute((const void*)k_refine_tile<BF16, L, V, RB, SINGLE>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   k_refine_tile<BF16, L, V, RB, SINGLE><<<grid, 512, lds, ctx->stream>>>(
-      X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, err_c, vec ? 1 : 0, G_ids, G_d2);
+      X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, smin, err_c, vec ? 1 : 0, G_ids, G_d2);
 }
 
 template <bool BF16, int L, int V>
@@ -805,11 +805,16 @@ static knnkm_status launch_refine(knnkm_ctx* ctx, const float* X, int64_t n, int
                                   int kappa, int32_t k, const int32_t* off, const int32_t* mem,
                                   const int32_t* wb, int rb1, int rb2, float err_c, bool vec,
                                   int32_t* G_ids, float* G_d2) {
-  // one tile per cluster of at most rb1 members
+  // one tile per cluster of at most rb1 members; with 64-row tiles, the
+  // clusters of at most 32 members take the 32-row kernel (less LDS, more
+  // blocks per CU; the lists do not depend on the tile size)
   switch (rb1) {
-    case 64: launch_tile<BF16, L, V, 64, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, err_c, vec, G_ids, G_d2); break;
-    case 32: launch_tile<BF16, L, V, 32, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, err_c, vec, G_ids, G_d2); break;
-    default: launch_tile<BF16, L, V, 16, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, err_c, vec, G_ids, G_d2); break;
+    case 64:
+      launch_tile<BF16, L, V, 32, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, 0, err_c, vec, G_ids, G_d2);
+      launch_tile<BF16, L, V, 64, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, 32, err_c, vec, G_ids, G_d2);
+      break;
+    case 32: launch_tile<BF16, L, V, 32, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, 0, err_c, vec, G_ids, G_d2); break;
+    default: launch_tile<BF16, L, V, 16, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, 0, err_c, vec, G_ids, G_d2); break;
   }
   KNNKM_TRY(knnkm_check(ctx, "graph refine (one-tile clusters)"));
   // larger clusters: blocks of rb2 rows walking blocks of rb2 columns; the
@@ -817,9 +822,9 @@ static knnkm_status launch_refine(knnkm_ctx* ctx, const float* X, int64_t n, int
   const int64_t max_items = n / rb2 + k + 1;
   const unsigned g = (unsigned)max_items;
   switch (rb2) {
-    case 64: launch_tile<BF16, L, V, 64, false>(ctx, g, X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, err_c, vec, G_ids, G_d2); break;
-    case 32: launch_tile<BF16, L, V, 32, false>(ctx, g, X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, err_c, vec, G_ids, G_d2); break;
-    default: launch_tile<BF16, L, V, 16, false>(ctx, g, X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, err_c, vec, G_ids, G_d2); break;
+    case 64: launch_tile<BF16, L, V, 64, false>(ctx, g, X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, 0, err_c, vec, G_ids, G_d2); break;
+    case 32: launch_tile<BF16, L, V, 32, false>(ctx, g, X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, 0, err_c, vec, G_ids, G_d2); break;
+    default: launch_tile<BF16, L, V, 16, false>(ctx, g, X, d, ldx, dpad, kappa, k, off, mem, wb, max_items, 0, err_c, vec, G_ids, G_d2); break;
   }
   return knnkm_check(ctx, "graph refine (multi-tile clusters)");
 }
