@@ -16,8 +16,9 @@
 //   delta     the same delta with the final centroids, stored as an ordered key
 //   split     the first ceil(s/2) members in (delta, id) order go left:
 //             nodes of <= TM_SMALL members sort (delta, id) in LDS; larger nodes
-//             find the threshold by a 12-digit radix select over the 96-bit
-//             (delta key, id) and partition tile by tile
+//             find the threshold key by an 8-digit radix select and partition
+//             tile by tile, members equal to it going left in position
+//             (= id) order up to the remaining rank
 // Leaves are numbered left to right.
 #include <algorithm>
 #include <cstring>
@@ -28,7 +29,7 @@
 #define TM_TILE 1024    // positions per tile of the per-member passes
 #define TM_SMALL 2048   // nodes up to this size split inside one block
 #define TM_CHUNK 16     // tiles per chunk of the two-stage node reduction
-#define TM_SEL_PASSES 12  // 8-bit digits of the 96-bit (delta key, id)
+#define TM_SEL_PASSES 8  // 8-bit digits of the 64-bit delta key
 #define TM_FINISH_DEFAULT TM_TILE  // largest subtree root that one block finishes
 
 struct TMLevel {
@@ -673,26 +674,22 @@ __global__ __launch_bounds__(256) void k_tm_split_small(const int32_t* __restric
   tm_partition_block(perm, keys, off, s, h, tk, ti, perm_out, sh_scan);
 }
 
-// Radix select over 96-bit (key, id) for nodes larger than one tile.
+// Nodes larger than one tile: radix select of the ceil(s/2)-th smallest
+// delta key, 8 bits per pass.  The members whose key equals it are ordered
+// by id, and a node holds its members in ascending id order (every split is
+// a stable partition of an ascending sequence), so the ones that go left are
+// the first h' of them in position order, h' being the rank left inside the
+// last bucket: the partition counts them instead of selecting on the id.
 struct SelState {
   uint64_t pk;  // decided high bits of the key
-  uint32_t pi;  // decided high bits of the id
   int32_t h;    // rank still to find inside the current bucket (1-based)
 };
 
-__device__ inline int sel_digit(uint64_t key, int32_t id, int pass) {
-  if (pass < 8) return (int)((key >> (56 - 8 * pass)) & 255);
-  return (int)(((uint32_t)id >> (24 - 8 * (pass - 8))) & 255);
-}
-__device__ inline bool sel_match(uint64_t key, int32_t id, int pass, const SelState& st) {
+__device__ inline int sel_digit(uint64_t key, int pass) { return (int)((key >> (56 - 8 * pass)) & 255); }
+__device__ inline bool sel_match(uint64_t key, int pass, const SelState& st) {
   if (pass == 0) return true;
-  if (pass <= 8) {
-    const int sh = 64 - 8 * pass;
-    return (key >> sh) == (st.pk >> sh);
-  }
-  if (key != st.pk) return false;
-  const int sh = 32 - 8 * (pass - 8);
-  return ((uint32_t)id >> sh) == (st.pi >> sh);
+  const int sh = 64 - 8 * pass;
+  return (key >> sh) == (st.pk >> sh);
 }
 
 // Selection state and histograms are kept per pass: st[p * nbig + b] is the
@@ -704,7 +701,6 @@ __global__ __launch_bounds__(256) void k_tm_sel_init(int nbig, const int32_t* __
                                                      SelState* st, int32_t* hist) {
   for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nbig; b += gridDim.x * blockDim.x) {
     st[b].pk = 0;
-    st[b].pi = 0;
     st[b].h = (s_size[big_split[b]] + 1) / 2;
   }
   for (int64_t e = blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)nbig * 256 * TM_SEL_PASSES;
@@ -723,11 +719,7 @@ __device__ inline SelState sel_next(const SelState& s, const int32_t* __restrict
   if (c > 0 && ex < s.h && s.h <= ex + c) {
     SelState t = s;
     t.h -= ex;
-    const int dg = threadIdx.x;
-    if (pass < 8)
-      t.pk |= (uint64_t)dg << (56 - 8 * pass);
-    else
-      t.pi |= (uint32_t)dg << (24 - 8 * (pass - 8));
+    t.pk |= (uint64_t)threadIdx.x << (56 - 8 * pass);
     *shs = t;
   }
   __syncthreads();
@@ -765,27 +757,28 @@ __global__ __launch_bounds__(256) void k_tm_sel_pass(const int32_t* __restrict__
   const int start = t_start[tile], len = t_len[tile];
   for (int p = threadIdx.x; p < len; p += 256) {
     const uint64_t key = keys[start + p];
-    const int32_t id = perm[start + p];
-    if (sel_match(key, id, pass, s)) atomicAdd(&h[sel_digit(key, id, pass)], 1);
+    if (sel_match(key, pass, s)) atomicAdd(&h[sel_digit(key, pass)], 1);
   }
   __syncthreads();
   const int c = h[threadIdx.x];
   if (c) atomicAdd(&hist[((int64_t)pass * nbig + b) * 256 + threadIdx.x], c);
 }
 
-__global__ __launch_bounds__(256) void k_tm_part_count(const int32_t* __restrict__ perm,
-                                                       const uint64_t* __restrict__ keys,
+// One block per tile of a big node: the node's threshold key (the state
+// after the last pass; the first tile's block stores it) and the tile's
+// numbers of members below it and equal to it.
+__global__ __launch_bounds__(256) void k_tm_part_count(const uint64_t* __restrict__ keys,
                                                        const int32_t* __restrict__ bigtile,
                                                        const int32_t* __restrict__ bigtile_big,
                                                        const int32_t* __restrict__ big_btb,
                                                        const int32_t* __restrict__ t_start,
                                                        const int32_t* __restrict__ t_len, int nbig,
                                                        SelState* __restrict__ st, const int32_t* __restrict__ hist,
-                                                       int32_t* __restrict__ tile_left) {
-  __shared__ int32_t c;
+                                                       int32_t* __restrict__ tile_less, int32_t* __restrict__ tile_tie) {
+  __shared__ int32_t cl, ct;
   __shared__ int32_t sh8[8];
   __shared__ SelState shs;
-  if (threadIdx.x == 0) c = 0;
+  if (threadIdx.x == 0) cl = ct = 0;
   const int tile = bigtile[blockIdx.x];
   const int b = bigtile_big[blockIdx.x];
   constexpr int LAST = TM_SEL_PASSES - 1;
@@ -793,33 +786,46 @@ __global__ __launch_bounds__(256) void k_tm_part_count(const int32_t* __restrict
                               sh8, &shs);
   if (blockIdx.x == big_btb[b] && threadIdx.x == 0) st[(int64_t)TM_SEL_PASSES * nbig + b] = s;
   const int start = t_start[tile], len = t_len[tile];
-  int mine = 0;
-  for (int p = threadIdx.x; p < len; p += 256)
-    mine += kv_le(keys[start + p], perm[start + p], s.pk, (int32_t)s.pi) ? 1 : 0;
-  atomicAdd(&c, mine);
+  int less = 0, tie = 0;
+  for (int p = threadIdx.x; p < len; p += 256) {
+    const uint64_t key = keys[start + p];
+    less += key < s.pk ? 1 : 0;
+    tie += key == s.pk ? 1 : 0;
+  }
+  atomicAdd(&cl, less);
+  atomicAdd(&ct, tie);
   __syncthreads();
-  if (threadIdx.x == 0) tile_left[blockIdx.x] = c;
-}
-
-// Exclusive scan of the left counts over the tiles of each big node.
-// One block per big node: exclusive scan of the left counts of its tiles.
-__global__ __launch_bounds__(256) void k_tm_part_scan(const int32_t* __restrict__ big_btb,
-                                                      const int32_t* __restrict__ big_bte,
-                                                      int32_t* __restrict__ tile_left) {
-  __shared__ int32_t sh[8];
-  const int b = blockIdx.x;
-  const int tb = big_btb[b], te = big_bte[b];
-  int32_t carry = 0;
-  for (int base = tb; base < te; base += 256) {
-    const int t = base + threadIdx.x;
-    const int32_t c = t < te ? tile_left[t] : 0;
-    int32_t tot;
-    const int32_t ex = block_scan_excl_256(c, sh, &tot);
-    if (t < te) tile_left[t] = carry + ex;
-    carry += tot;
+  if (threadIdx.x == 0) {
+    tile_less[blockIdx.x] = cl;
+    tile_tie[blockIdx.x] = ct;
   }
 }
 
+// One block per big node: exclusive scans of both counts over its tiles.
+__global__ __launch_bounds__(256) void k_tm_part_scan(const int32_t* __restrict__ big_btb,
+                                                      const int32_t* __restrict__ big_bte,
+                                                      int32_t* __restrict__ tile_less,
+                                                      int32_t* __restrict__ tile_tie) {
+  __shared__ int32_t sh[8];
+  const int b = blockIdx.x;
+  const int tb = big_btb[b], te = big_bte[b];
+  int32_t carry_l = 0, carry_t = 0;
+  for (int base = tb; base < te; base += 256) {
+    const int t = base + threadIdx.x;
+    int32_t tot;
+    const int32_t ex_l = block_scan_excl_256(t < te ? tile_less[t] : 0, sh, &tot);
+    if (t < te) tile_less[t] = carry_l + ex_l;
+    carry_l += tot;
+    const int32_t ex_t = block_scan_excl_256(t < te ? tile_tie[t] : 0, sh, &tot);
+    if (t < te) tile_tie[t] = carry_t + ex_t;
+    carry_t += tot;
+  }
+}
+
+// Stable partition of a big node, tile by tile: a member goes left when its
+// key is below the threshold, or equal to it and among the first h' such
+// members of the node in position order.  Each thread takes a contiguous
+// chunk of the tile; lefts_before = less_before + min(ties_before, h').
 __global__ __launch_bounds__(256) void k_tm_part_write(const int32_t* __restrict__ perm,
                                                        const uint64_t* __restrict__ keys,
                                                        const int32_t* __restrict__ bigtile,
@@ -830,40 +836,41 @@ __global__ __launch_bounds__(256) void k_tm_part_write(const int32_t* __restrict
                                                        const int32_t* __restrict__ t_start,
                                                        const int32_t* __restrict__ t_len,
                                                        const SelState* __restrict__ st,
-                                                       const int32_t* __restrict__ tile_left_base,
+                                                       const int32_t* __restrict__ less_base,
+                                                       const int32_t* __restrict__ tie_base,
                                                        int32_t* __restrict__ perm_out) {
-  __shared__ int32_t sh_scan[256];
+  __shared__ int32_t sh8[8];
   const int tile = bigtile[blockIdx.x];
   const int b = bigtile_big[blockIdx.x];
   const SelState s = st[b];
+  const uint64_t tk = s.pk;
+  const int hp = s.h;
   const int j = big_split[b];
   const int off = s_off[j], h = (s_size[j] + 1) / 2;
   const int start = t_start[tile], len = t_len[tile];
   const int per = (len + 255) / 256;
   const int p0 = start + threadIdx.x * per;
   const int p1 = min(start + len, p0 + per);
-  int cnt = 0;
-  for (int p = p0; p < p1; ++p) cnt += kv_le(keys[p], perm[p], s.pk, (int32_t)s.pi) ? 1 : 0;
-  sh_scan[threadIdx.x] = cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int e = 0; e < 256; ++e) {
-      int c = sh_scan[e];
-      sh_scan[e] = run;
-      run += c;
-    }
+  int cl = 0, ct = 0;
+  for (int p = p0; p < p1; ++p) {
+    const uint64_t key = keys[p];
+    cl += key < tk ? 1 : 0;
+    ct += key == tk ? 1 : 0;
   }
-  __syncthreads();
-  const int lefts_before = tile_left_base[blockIdx.x] + sh_scan[threadIdx.x];
-  int lpos = off + lefts_before;
-  int rpos = off + h + ((p0 - off) - lefts_before);
+  int32_t tot;
+  int lb = less_base[blockIdx.x] + block_scan_excl_256(cl, sh8, &tot);
+  int tb = tie_base[blockIdx.x] + block_scan_excl_256(ct, sh8, &tot);
   for (int p = p0; p < p1; ++p) {
     const int32_t id = perm[p];
-    if (kv_le(keys[p], id, s.pk, (int32_t)s.pi))
-      perm_out[lpos++] = id;
+    const uint64_t key = keys[p];
+    const int lefts_before = lb + min(tb, hp);
+    const bool left = key < tk || (key == tk && tb < hp);
+    if (left)
+      perm_out[off + lefts_before] = id;
     else
-      perm_out[rpos++] = id;
+      perm_out[off + h + (p - off) - lefts_before] = id;
+    lb += key < tk ? 1 : 0;
+    tb += key == tk ? 1 : 0;
   }
 }
 
@@ -1136,7 +1143,8 @@ knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_
   KNNKM_WS(ctx, pcnt, int32_t, "tm_pcnt", (int64_t)std::max(1, P.max_tiles) * 2);
   KNNKM_WS(ctx, sel, SelState, "tm_sel", (int64_t)std::max(1, P.max_big) * (TM_SEL_PASSES + 1));
   KNNKM_WS(ctx, hist, int32_t, "tm_hist", (int64_t)std::max(1, P.max_big) * 256 * TM_SEL_PASSES);
-  KNNKM_WS(ctx, tleft, int32_t, "tm_tleft", std::max(1, P.max_tiles));
+  KNNKM_WS(ctx, tless, int32_t, "tm_tless", std::max(1, P.max_tiles));
+  KNNKM_WS(ctx, ttie, int32_t, "tm_ttie", std::max(1, P.max_tiles));
   KNNKM_WS(ctx, cpart, double, "tm_cpart", (int64_t)std::max(1, P.max_chunks) * 2 * d);
   KNNKM_WS(ctx, ccnt, int32_t, "tm_ccnt", (int64_t)std::max(1, P.max_chunks) * 2);
   int32_t* perm = permbuf;
@@ -1185,12 +1193,12 @@ knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_
       for (int pass = 0; pass < TM_SEL_PASSES; ++pass)
         k_tm_sel_pass<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, P.d_big_btb + L.big_base, ts, tl,
                                                             pass, L.nbig, sel, hist);
-      k_tm_part_count<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, P.d_big_btb + L.big_base, ts, tl,
-                                                            L.nbig, sel, hist, tleft);
+      k_tm_part_count<<<L.nbigtiles, 256, 0, ctx->stream>>>(keys, bt, btb, P.d_big_btb + L.big_base, ts, tl,
+                                                            L.nbig, sel, hist, tless, ttie);
       k_tm_part_scan<<<L.nbig, 256, 0, ctx->stream>>>(P.d_big_btb + L.big_base, P.d_big_bte + L.big_base,
-                                                      tleft);
+                                                      tless, ttie);
       k_tm_part_write<<<L.nbigtiles, 256, 0, ctx->stream>>>(perm, keys, bt, btb, bs, s_off, s_size, ts, tl,
-                                                            sel + (int64_t)TM_SEL_PASSES * L.nbig, tleft,
+                                                            sel + (int64_t)TM_SEL_PASSES * L.nbig, tless, ttie,
                                                             perm_next);
     }
     if (L.ncopy)

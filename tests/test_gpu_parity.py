@@ -183,6 +183,21 @@ def test_twomeans_parity(ctx, n, d, k):
     assert np.array_equal(got, want), f"agreement {np.mean(got == want):.6f}"
 
 
+@pytest.mark.parametrize("n,d,k,distinct", [(12000, 8, 37, 40), (9000, 16, 100, 3), (30000, 4, 9, 7)])
+def test_twomeans_parity_duplicate_rows(ctx, n, d, k, distinct):
+    """Rows drawn from a few distinct rows: many members share a delta (and
+    both seeds can be the same row, making every delta zero), so inside nodes
+    larger than one tile the ids decide which members go left."""
+    say("twomeans duplicate rows", n, d, k, distinct)
+    base = datagen.mixture(distinct, d, 3, seed=n + distinct)
+    X = np.ascontiguousarray(base[np.random.default_rng(n).integers(0, distinct, n)])
+    want = twomeans.twomeans(X, k, seed=7, rnd=3)
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    knnkm.knnkm_twomeans(ctx, dev(X), k, 7, 3, 2, lab)
+    got = host(lab)
+    assert np.array_equal(got, want), f"agreement {np.mean(got == want):.6f}"
+
+
 @pytest.mark.parametrize("n,d,k,iters", [(200_003, 128, 2000, 2), (50_000, 3, 20_000, 2), (30_000, 512, 300, 1),
                                          (4097, 64, 4097, 2), (100_000, 24, 97, 3), (1024, 7, 1000, 0)])
 def test_twomeans_subtree_finish_same_bits(ctx, n, d, k, iters):
