@@ -526,6 +526,49 @@ def test_fit_active_sets_same_bits(ctx, n, d, k, kappa, T, early):
         knnkm.knnkm_enable_active_sets(ctx, True)
 
 
+@pytest.mark.parametrize("n,d,k,kappa,sigma,few", [(32768, 16, 64, 12, 0.1, True), (16384, 8, 16, 8, 0.02, True),
+                                                   (20000, 32, 200, 10, 1.0, False)])
+def test_fit_first_sweep_marks_same_bits(ctx, n, d, k, kappa, sigma, few):
+    """After the first sweep the fit marks the moved samples and the rows
+    listing them, or every row once the moved samples number at least
+    n/(kappa+1).  The first sweep is replayed through the public calls
+    (TwoMeans init with the fit's seed and round tag, its means, one
+    knn_assign) to check which rule these data take; either way the fit with
+    active sets equals the fit without, bit for bit."""
+    say("fit first-sweep marks", n, d, k, kappa, sigma, few)
+    X = dev(datagen.mixture(n, d, k, seed=n + 3, sigma=sigma))
+    p = knnkm.default_params(kappa=kappa, max_iters=8, seed=9)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    knnkm.knn_build(ctx, X, p, gi, gd)
+    init = torch.empty(n, dtype=torch.int32, device=DEV)
+    knnkm.knnkm_twomeans(ctx, X, k, 9, knnkm.ROUND_FIT, p.bisect_iters, init)
+    C0 = torch.zeros((k, d), dtype=torch.float32, device=DEV)
+    c0 = torch.empty(k, dtype=torch.int32, device=DEV)
+    knnkm.centroid_update(ctx, X, init, C0, c0)
+    lab1 = torch.empty(n, dtype=torch.int32, device=DEV)
+    knnkm.knn_assign(ctx, X, C0, gi, init, lab1)
+    moved = int((lab1 != init).sum())
+    assert (moved < (n + kappa) // (kappa + 1)) == few, moved
+
+    def run(active):
+        knnkm.knnkm_enable_active_sets(ctx, active)
+        lab = torch.empty(n, dtype=torch.int32, device=DEV)
+        C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+        cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+        tr, it = knnkm.knn_kmeans_fit(ctx, X, k, gi, p, lab, C, cnt)
+        return host(lab), host(C), host(cnt), np.asarray(tr), it
+
+    try:
+        ref = run(False)
+        got = run(True)
+        for a, b in zip(ref[:4], got[:4]):
+            assert np.array_equal(a, b)
+        assert got[4] == ref[4]
+    finally:
+        knnkm.knnkm_enable_active_sets(ctx, True)
+
+
 def test_batch_active_sets_same_bits(ctx):
     """The same for a batched fit (jobs of different sizes, one of them with
     kappa >= k, evaluated in full every sweep)."""
