@@ -30,9 +30,7 @@
 #define MAX_SLOTS 8
 
 template <int V>
-__device__ inline float part32(const float (&x)[V], const float* __restrict__ cr, int j, int d, bool vec) {
-  float c[V];
-  load_row<V>(c, cr, j, d, vec);
+__device__ inline float dist32(const float (&x)[V], const float (&c)[V]) {
   float acc = 0.f;
 #pragma unroll
   for (int e = 0; e < V; ++e) {
@@ -40,6 +38,12 @@ __device__ inline float part32(const float (&x)[V], const float* __restrict__ cr
     acc = fmaf(df, df, acc);
   }
   return acc;
+}
+template <int V>
+__device__ inline float part32(const float (&x)[V], const float* __restrict__ cr, int j, int d, bool vec) {
+  float c[V];
+  load_row<V>(c, cr, j, d, vec);
+  return dist32<V>(x, c);
 }
 
 template <int V>
@@ -77,6 +81,47 @@ __device__ inline void for_each_cand(const int (&v)[SM], const bool (&valid)[SM]
     for (int s = 0; s < SM; ++s)
       if (pend[s] && v[s] == q) pend[s] = false;
     f(q);
+  }
+}
+
+// The same visit, with the centroid row slice of the next candidate loaded
+// while the current one is used: f(q, c) gets candidate q and its dims
+// [j*V, j*V + V) of C.
+template <int L, int V, int SM, typename F>
+__device__ inline void for_each_cand_row(const int (&v)[SM], const bool (&valid)[SM], uint64_t gmask,
+                                         const float* __restrict__ C, int d, int j, bool vec, F&& f) {
+  bool pend[SM];
+#pragma unroll
+  for (int s = 0; s < SM; ++s) pend[s] = valid[s];
+  auto next = [&]() -> int {
+    int q = -1;
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      if (q < 0) {
+        const uint64_t m = __ballot(pend[s]) & gmask;
+        if (m) q = __shfl(v[s], (int)__builtin_ctzll(m), 64);
+      }
+    }
+    if (q >= 0) {
+#pragma unroll
+      for (int s = 0; s < SM; ++s)
+        if (pend[s] && v[s] == q) pend[s] = false;
+    }
+    return q;
+  };
+  int q = next();
+  if (q < 0) return;
+  float c[V];
+  load_row<V>(c, C + (int64_t)q * d, j, d, vec);
+  while (true) {
+    const int qn = next();
+    float cn[V];
+    if (qn >= 0) load_row<V>(cn, C + (int64_t)qn * d, j, d, vec);
+    f(q, c);
+    if (qn < 0) break;
+    q = qn;
+#pragma unroll
+    for (int e = 0; e < V; ++e) c[e] = cn[e];
   }
 }
 
@@ -203,8 +248,7 @@ __global__ __launch_bounds__(256) void k_assign(
         // pass 1: float32 distances, best and second best
         float b1 = FLT_MAX, b2 = FLT_MAX;
         int q1 = -1;
-        auto pass1 = [&](int q) {
-          const float dq = group_sum<L>(part32<V>(x[p], C + (int64_t)q * d, j, d, vec_c));
+        auto pass1 = [&](int q, float dq) {
           if (dq < b1 || (dq == b1 && q < q1)) {
             if (q1 >= 0) b2 = fminf(b2, b1);
             b1 = dq;
@@ -214,9 +258,11 @@ __global__ __launch_bounds__(256) void k_assign(
           }
         };
         if (dense_i[p])
-          for (int q = kb[p]; q < kb[p] + kc[p]; ++q) pass1(q);
+          for (int q = kb[p]; q < kb[p] + kc[p]; ++q)
+            pass1(q, group_sum<L>(part32<V>(x[p], C + (int64_t)q * d, j, d, vec_c)));
         else
-          for_each_cand<L, SM>(cv[p], valid[p], gmask, pass1);
+          for_each_cand_row<L, V, SM>(cv[p], valid[p], gmask, C, d, j, vec_c,
+                                      [&](int q, const float (&c)[V]) { pass1(q, group_sum<L>(dist32<V>(x[p], c))); });
 
         const double thr = (double)b1 * (1.0 + rel) / (1.0 - rel) + 1e-30;
         int result = q1;
@@ -416,8 +462,7 @@ __global__ __launch_bounds__(256) void k_assign_list(
       load_row<V>(x, X + i * ldx, j, d, vec_x);
       float b1 = FLT_MAX, b2 = FLT_MAX;
       int q1 = -1;
-      auto pass1 = [&](int q) {
-        const float dq = group_sum<L>(part32<V>(x, C + (int64_t)q * d, j, d, vec_c));
+      auto pass1 = [&](int q, float dq) {
         if (dq < b1 || (dq == b1 && q < q1)) {
           if (q1 >= 0) b2 = fminf(b2, b1);
           b1 = dq;
@@ -427,9 +472,10 @@ __global__ __launch_bounds__(256) void k_assign_list(
         }
       };
       if (dn)
-        for (int q = kb; q < kb + kc; ++q) pass1(q);
+        for (int q = kb; q < kb + kc; ++q) pass1(q, group_sum<L>(part32<V>(x, C + (int64_t)q * d, j, d, vec_c)));
       else
-        for_each_cand<L, SM>(cv, valid, gmask, pass1);
+        for_each_cand_row<L, V, SM>(cv, valid, gmask, C, d, j, vec_c,
+                                    [&](int q, const float (&c)[V]) { pass1(q, group_sum<L>(dist32<V>(x, c))); });
       const double thr = (double)b1 * (1.0 + rel) / (1.0 - rel) + 1e-30;
       int result = q1;
       if ((double)b2 <= thr) {
