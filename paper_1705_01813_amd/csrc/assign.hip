@@ -125,6 +125,68 @@ __device__ inline void for_each_cand_row(const int (&v)[SM], const bool (&valid)
   }
 }
 
+// The candidate visits of GS samples of a group advanced together: each step
+// takes the next candidate of every sample still visiting (use[p]) and loads
+// its centroid slice while the previous ones are used.  Every sample sees
+// its own candidates in its own order.  f(p, q, c).
+template <int L, int V, int SM, int GS, typename F>
+__device__ inline void for_each_cand_rows(const int (&v)[GS][SM], const bool (&valid)[GS][SM],
+                                          const bool (&use)[GS], uint64_t gmask, const float* __restrict__ C,
+                                          int d, int j, bool vec, F&& f) {
+  bool pend[GS][SM];
+#pragma unroll
+  for (int p = 0; p < GS; ++p)
+#pragma unroll
+    for (int s = 0; s < SM; ++s) pend[p][s] = use[p] && valid[p][s];
+  auto next = [&](int p) -> int {
+    int q = -1;
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      if (q < 0) {
+        const uint64_t m = __ballot(pend[p][s]) & gmask;
+        if (m) q = __shfl(v[p][s], (int)__builtin_ctzll(m), 64);
+      }
+    }
+    if (q >= 0) {
+#pragma unroll
+      for (int s = 0; s < SM; ++s)
+        if (pend[p][s] && v[p][s] == q) pend[p][s] = false;
+    }
+    return q;
+  };
+  int q[GS];
+  float c[GS][V];
+  bool any = false;
+#pragma unroll
+  for (int p = 0; p < GS; ++p) {
+    q[p] = next(p);
+    if (q[p] >= 0) {
+      load_row<V>(c[p], C + (int64_t)q[p] * d, j, d, vec);
+      any = true;
+    }
+  }
+  while (any) {  // group-uniform
+    int qn[GS];
+    float cn[GS][V];
+#pragma unroll
+    for (int p = 0; p < GS; ++p) {
+      qn[p] = q[p] >= 0 ? next(p) : -1;
+      if (qn[p] >= 0) load_row<V>(cn[p], C + (int64_t)qn[p] * d, j, d, vec);
+    }
+    any = false;
+#pragma unroll
+    for (int p = 0; p < GS; ++p) {
+      if (q[p] >= 0) f(p, q[p], c[p]);
+      q[p] = qn[p];
+      if (q[p] >= 0) {
+        any = true;
+#pragma unroll
+        for (int e = 0; e < V; ++e) c[p][e] = cn[p][e];
+      }
+    }
+  }
+}
+
 // One row group (L lanes) per sample, GS samples per group at a time: the
 // loads of each dependency level (sample ids; rows, own labels and graph
 // rows; neighbour labels) are issued for all GS samples before any is used,
@@ -376,16 +438,21 @@ __global__ __launch_bounds__(256) void k_act_compact(int64_t n, uint8_t* __restr
     }
 }
 
-// The listed samples, one per row group (grid-stride over the list), each
+// The listed samples, GS per row group (grid-stride over the list), each
 // through the same candidate collection, float32 pass and float64 pass as
-// k_assign with one sample per group, so labels are the same bits.  Labels
+// k_assign with one sample per group, so labels are the same bits.  The
+// candidate loops of a group's samples advance together (the next centroid
+// row of every sample is loaded while the current ones reduce), so a group
+// keeps GS dependent load chains in flight (GS = 2 where a row group is a
+// whole wavefront, d > 256: one sample per wavefront leaves its loads too
+// serial; smaller groups keep GS = 1 and their higher occupancy).  Labels
 // of unlisted samples are not written: the update keeps both label arrays
 // equal outside the samples a sweep moves.  act_out as in k_assign.  A
 // listed sample whose candidate set is unchanged (bit 1 clear) and none of
-// whose candidate centroids changed in the last update (cdirty, per cluster;
-// null: all changed) has all the inputs of its last decision, to stay, so
-// it stays without a distance being evaluated.
-template <int L, int V, int SM>
+// whose candidate centroids changed in the last update (cdirty, per
+// cluster; null: all changed) has all the inputs of its last decision, to
+// stay, so it stays without a distance being evaluated.
+template <int L, int V, int SM, int GS>
 __global__ __launch_bounds__(256) void k_assign_list(
     const float* __restrict__ X, int d, int64_t ldx, const float* __restrict__ C, int k,
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
@@ -408,102 +475,143 @@ __global__ __launch_bounds__(256) void k_assign_list(
   const int ngroups = gridDim.x * 4 * GW;
   unsigned int my_moved = 0, my_eval = 0;
   // wave-uniform trip count: groups of a wavefront stay in step
-  for (int base = (blockIdx.x * 4 + w) * GW; base < cnt; base += ngroups) {
-    const int li = base + g;
-    const bool live = li < cnt;  // group-uniform
-    const uint32_t ent = live ? (uint32_t)list[li] : 0u;
-    const bool changed = (ent >> 31) != 0;
-    const int64_t i = (int64_t)(ent & 0x7FFFFFFFu);
-    const int cur = live ? lab_in[i] : -1;
-    int kb = 0, kc = k;
-    bool dn = false;
-    if (job_of && live) {
-      const int q = job_of[i];
-      kb = kbase[q];
-      kc = kbase[q + 1] - kb;
-      dn = kappa >= kc;
-    }
-    int nb[SM], cv[SM];
-    bool valid[SM];
+  for (int base = (blockIdx.x * 4 + w) * GW * GS; base < cnt; base += ngroups * GS) {
+    bool live[GS], changed[GS], dn[GS], eval[GS];
+    int64_t i[GS];
+    int cur[GS], kb[GS], kc[GS];
+    int cv[GS][SM];
+    bool valid[GS][SM];
 #pragma unroll
-    for (int s = 0; s < SM; ++s) {
-      const int e = j + L * s;
-      nb[s] = (live && !dn && e >= 1 && e <= kappa) ? G[i * kappa + (e - 1)] : -1;
+    for (int p = 0; p < GS; ++p) {
+      const int li = base + p * GW + g;
+      live[p] = li < cnt;  // group-uniform
+      const uint32_t ent = live[p] ? (uint32_t)list[li] : 0u;
+      changed[p] = (ent >> 31) != 0;
+      i[p] = (int64_t)(ent & 0x7FFFFFFFu);
     }
 #pragma unroll
-    for (int s = 0; s < SM; ++s) {
-      const int e = j + L * s;
-      valid[s] = live && !dn && e <= kappa;
-      cv[s] = !valid[s] ? -1 : (e == 0 ? cur : lab_in[nb[s]]);
-    }
-    bool other = false;
-#pragma unroll
-    for (int s = 0; s < SM; ++s) other = other || (valid[s] && cv[s] != cur);
-    const bool single = live && !dn && cur >= 0 && (__ballot(other) & gmask) == 0;
-    bool cand_dirty = true;
-    if (!changed && !dn && cdirty) {
-      bool any = false;
-#pragma unroll
-      for (int s = 0; s < SM; ++s) any = any || (valid[s] && cdirty[cv[s]] != 0);
-      cand_dirty = (__ballot(any) & gmask) != 0;
-    }
-    if (live && single) {  // group-uniform
-      if (j == 0) {
-        lab_out[i] = cur;
-        if (act_out) act_out[i] = 0;
+    for (int p = 0; p < GS; ++p) {
+      cur[p] = live[p] ? lab_in[i[p]] : -1;
+      kb[p] = 0;
+      kc[p] = k;
+      dn[p] = false;
+      if (job_of && live[p]) {
+        const int q = job_of[i[p]];
+        kb[p] = kbase[q];
+        kc[p] = kbase[q + 1] - kb[p];
+        dn[p] = kappa >= kc[p];
       }
-    } else if (live && !cand_dirty) {  // same inputs as its last decision: stays
-      if (j == 0) {
-        lab_out[i] = cur;
-        if (act_out) act_out[i] = 1;
+    }
+    int nb[GS][SM];
+#pragma unroll
+    for (int p = 0; p < GS; ++p)
+#pragma unroll
+      for (int s = 0; s < SM; ++s) {
+        const int e = j + L * s;
+        nb[p][s] = (live[p] && !dn[p] && e >= 1 && e <= kappa) ? G[i[p] * kappa + (e - 1)] : -1;
       }
-    } else if (live) {
-      float x[V];
-      load_row<V>(x, X + i * ldx, j, d, vec_x);
-      float b1 = FLT_MAX, b2 = FLT_MAX;
-      int q1 = -1;
-      auto pass1 = [&](int q, float dq) {
-        if (dq < b1 || (dq == b1 && q < q1)) {
-          if (q1 >= 0) b2 = fminf(b2, b1);
-          b1 = dq;
-          q1 = q;
-        } else {
-          b2 = fminf(b2, dq);
+#pragma unroll
+    for (int p = 0; p < GS; ++p)
+#pragma unroll
+      for (int s = 0; s < SM; ++s) {
+        const int e = j + L * s;
+        valid[p][s] = live[p] && !dn[p] && e <= kappa;
+        cv[p][s] = !valid[p][s] ? -1 : (e == 0 ? cur[p] : lab_in[nb[p][s]]);
+      }
+#pragma unroll
+    for (int p = 0; p < GS; ++p) {
+      bool other = false;
+#pragma unroll
+      for (int s = 0; s < SM; ++s) other = other || (valid[p][s] && cv[p][s] != cur[p]);
+      const bool single = live[p] && !dn[p] && cur[p] >= 0 && (__ballot(other) & gmask) == 0;
+      bool cand_dirty = true;
+      if (!changed[p] && !dn[p] && cdirty) {
+        bool any = false;
+#pragma unroll
+        for (int s = 0; s < SM; ++s) any = any || (valid[p][s] && cdirty[cv[p][s]] != 0);
+        cand_dirty = (__ballot(any) & gmask) != 0;
+      }
+      eval[p] = false;
+      if (live[p] && single) {  // group-uniform
+        if (j == 0) {
+          lab_out[i[p]] = cur[p];
+          if (act_out) act_out[i[p]] = 0;
         }
-      };
-      if (dn)
-        for (int q = kb; q < kb + kc; ++q) pass1(q, group_sum<L>(part32<V>(x, C + (int64_t)q * d, j, d, vec_c)));
-      else
-        for_each_cand_row<L, V, SM>(cv, valid, gmask, C, d, j, vec_c,
-                                    [&](int q, const float (&c)[V]) { pass1(q, group_sum<L>(dist32<V>(x, c))); });
-      const double thr = (double)b1 * (1.0 + rel) / (1.0 - rel) + 1e-30;
-      int result = q1;
-      if ((double)b2 <= thr) {
+      } else if (live[p] && !cand_dirty) {  // same inputs as its last decision: stays
+        if (j == 0) {
+          lab_out[i[p]] = cur[p];
+          if (act_out) act_out[i[p]] = 1;
+        }
+      } else if (live[p]) {
+        eval[p] = true;
+      }
+    }
+    float x[GS][V];
+#pragma unroll
+    for (int p = 0; p < GS; ++p)
+      if (eval[p]) load_row<V>(x[p], X + i[p] * ldx, j, d, vec_x);
+    // pass 1: float32 distances, best and second best of every sample
+    float b1[GS], b2[GS];
+    int q1[GS];
+#pragma unroll
+    for (int p = 0; p < GS; ++p) {
+      b1[p] = b2[p] = FLT_MAX;
+      q1[p] = -1;
+    }
+    auto pass1 = [&](int p, int q, float dq) {
+      if (dq < b1[p] || (dq == b1[p] && q < q1[p])) {
+        if (q1[p] >= 0) b2[p] = fminf(b2[p], b1[p]);
+        b1[p] = dq;
+        q1[p] = q;
+      } else {
+        b2[p] = fminf(b2[p], dq);
+      }
+    };
+    {
+      bool sparse[GS];
+#pragma unroll
+      for (int p = 0; p < GS; ++p) {
+        sparse[p] = eval[p] && !dn[p];
+        if (eval[p] && dn[p])
+          for (int q = kb[p]; q < kb[p] + kc[p]; ++q)
+            pass1(p, q, group_sum<L>(part32<V>(x[p], C + (int64_t)q * d, j, d, vec_c)));
+      }
+      for_each_cand_rows<L, V, SM, GS>(cv, valid, sparse, gmask, C, d, j, vec_c,
+                                       [&](int p, int q, const float (&c)[V]) {
+                                         pass1(p, q, group_sum<L>(dist32<V>(x[p], c)));
+                                       });
+    }
+#pragma unroll
+    for (int p = 0; p < GS; ++p) {
+      if (!eval[p]) continue;  // group-uniform
+      const double thr = (double)b1[p] * (1.0 + rel) / (1.0 - rel) + 1e-30;
+      int result = q1[p];
+      if ((double)b2[p] <= thr) {
         double m64 = DBL_MAX, cur64 = -1.0;
         int q64 = -1;
         auto pass2 = [&](int q) {
           const float* cr = C + (int64_t)q * d;
-          const float dq = group_sum<L>(part32<V>(x, cr, j, d, vec_c));
+          const float dq = group_sum<L>(part32<V>(x[p], cr, j, d, vec_c));
           if ((double)dq <= thr) {
-            const double e = group_sum<L>(part64<V>(x, cr, j, d, vec_c));
-            if (q == cur) cur64 = e;
+            const double e = group_sum<L>(part64<V>(x[p], cr, j, d, vec_c));
+            if (q == cur[p]) cur64 = e;
             if (e < m64 || (e == m64 && q < q64)) {
               m64 = e;
               q64 = q;
             }
           }
         };
-        if (dn)
-          for (int q = kb; q < kb + kc; ++q) pass2(q);
+        if (dn[p])
+          for (int q = kb[p]; q < kb[p] + kc[p]; ++q) pass2(q);
         else
-          for_each_cand<L, SM>(cv, valid, gmask, pass2);
-        result = (cur >= 0 && cur64 >= 0.0 && cur64 == m64) ? cur : q64;
+          for_each_cand<L, SM>(cv[p], valid[p], gmask, pass2);
+        result = (cur[p] >= 0 && cur64 >= 0.0 && cur64 == m64) ? cur[p] : q64;
       }
       if (j == 0) {
-        lab_out[i] = result;
-        if (act_out) act_out[i] = 1;
+        lab_out[i[p]] = result;
+        if (act_out) act_out[i[p]] = 1;
         my_eval++;
-        if (cur >= 0 && result != cur) my_moved++;
+        if (cur[p] >= 0 && result != cur[p]) my_moved++;
       }
     }
   }
@@ -676,7 +784,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                                                                           list_count_other);
     const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
 #define LP(LL, VV, SS)                                                                                        \
-  k_assign_list<LL, VV, SS><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
+  k_assign_list<LL, VV, SS, ((LL) >= 64 ? 2 : 1)><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
                                                            acc, eacc, list, cnt, rel, vec_x ? 1 : 0,            \
                                                            vec_c ? 1 : 0, job_of, kbase, act_out, n_active,    \
                                                            cdirty)
