@@ -19,6 +19,9 @@
 //             find the threshold key by an 8-digit radix select and partition
 //             tile by tile, members equal to it going left in position
 //             (= id) order up to the remaining rank
+// A node to split of at most the finish limit (1,024 members by default) is
+// the root of a subtree that one block finishes with the ids in LDS
+// (k_tm_finish): the same steps, arithmetic and order for every later depth.
 // Leaves are numbered left to right.
 #include <algorithm>
 #include <cstring>
