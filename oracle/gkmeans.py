@@ -18,7 +18,7 @@ collected clusters" (Sec. 4.2).  Readings (design notes):
   rounded to float32 (the storage format of C); a cluster with no members keeps
   its previous centroid.  Composite vectors D_r (Eqn. 2) are the float64 sums.
 
-Pins (tests/test_oracle_gkmeans.py): kappa >= k equals scipy's cdist argmin; the
+Pins (tests/test_oracle_pins.py): kappa >= k equals scipy's cdist argmin; the
 complete graph (kappa = n-1) equals an exhaustive argmin over non-empty
 clusters; hand-worked 1-D fixtures in tests/golden/; the update equals a pandas
 group-by mean (and, for integer data, group-by sums bit for bit); the direct
@@ -46,36 +46,51 @@ def candidates(cur, labels_all, G_rows):
     return np.concatenate([cur[:, None], labels_all[G_rows]], axis=1)
 
 
+def _decide(Xb, C64, cur, cand):
+    """The decision of a block of rows Xb (float64) with current labels cur and
+    candidate lists cand: stay unless a candidate is strictly closer; among
+    the closest candidates the smallest id.  Returns (labels, best_d2)."""
+    d = _dist_to(Xb, C64, cand)
+    dcur = np.einsum("ij,ij->i", Xb - C64[cur], Xb - C64[cur])
+    m = d.min(axis=1)
+    big = np.iinfo(np.int64).max
+    newlab = np.where(d == m[:, None], cand, big).min(axis=1)
+    stay = dcur <= m
+    return np.where(stay, cur, newlab), np.where(stay, dcur, m)
+
+
 def gk_assign(X, C, labels_in, G_ids):
     """One Jacobi sweep of the graph-restricted assignment.
 
     Returns (labels_out int32, best_d2 float64, n_moved)."""
-    X64 = np.asarray(X, np.float32).astype(np.float64)
+    n = np.asarray(X).shape[0]
+    out, best = gk_assign_rows(X, C, labels_in, G_ids, np.arange(n))
+    moved = int((out != np.asarray(labels_in)).sum())
+    return out, best, moved
+
+
+def gk_assign_rows(X, C, labels_in, G_ids, rows):
+    """The same sweep for the given rows only (every row's label still enters
+    the candidate lists): (labels_out int32, best_d2 float64) of those rows.
+    Used to check sampled outputs of problems too large to sweep in full."""
+    rows = np.asarray(rows, np.int64)
     C64 = np.asarray(C, np.float32).astype(np.float64)
     labels_in = np.asarray(labels_in, np.int64)
-    G_ids = np.asarray(G_ids, np.int64)
-    n = X64.shape[0]
     k = C64.shape[0]
-    kappa = G_ids.shape[1]
-    out = np.empty(n, np.int32)
-    best = np.empty(n, np.float64)
-    for s in range(0, n, CHUNK):
-        e = min(n, s + CHUNK)
+    kappa = np.asarray(G_ids).shape[1]
+    out = np.empty(rows.size, np.int32)
+    best = np.empty(rows.size, np.float64)
+    for s in range(0, rows.size, CHUNK):
+        e = min(rows.size, s + CHUNK)
+        r = rows[s:e]
+        Xb = np.asarray(X[r], np.float32).astype(np.float64)
+        cur = labels_in[r]
         if kappa >= k:
             cand = np.broadcast_to(np.arange(k), (e - s, k))
         else:
-            cand = candidates(labels_in[s:e], labels_in, G_ids[s:e])
-        d = _dist_to(X64[s:e], C64, cand)
-        cur = labels_in[s:e]
-        dcur = np.einsum("ij,ij->i", X64[s:e] - C64[cur], X64[s:e] - C64[cur])
-        m = d.min(axis=1)
-        big = np.iinfo(np.int64).max
-        newlab = np.where(d == m[:, None], cand, big).min(axis=1)
-        stay = dcur <= m
-        out[s:e] = np.where(stay, cur, newlab)
-        best[s:e] = np.where(stay, dcur, m)
-    moved = int((out != labels_in).sum())
-    return out, best, moved
+            cand = candidates(cur, labels_in, np.asarray(G_ids[r], np.int64))
+        out[s:e], best[s:e] = _decide(Xb, C64, cur, cand)
+    return out, best
 
 
 def dense_assign(X, C):

@@ -115,6 +115,31 @@ def test_assign_ties_and_duplicates(ctx):
     assert int(host(mv)[0]) == moved
 
 
+def test_assign_full_size_sampled(ctx):
+    """knn_assign at the full 1M x 128 workload size (the integer mixture,
+    k = 10,000, kappa = 20; random input labels, so rows have many
+    candidates): 4,000 sampled rows plus the first and the last against the
+    oracle row by row, and the moved count against the whole output."""
+    n, d, k, kappa = 1_000_000, 128, 10_000, 20
+    say("assign full size", n, d, k, kappa)
+    X = datagen.config_data("c2", seed=77)
+    rs = np.random.default_rng(5)
+    C = (X[rs.choice(n, k, replace=False)] + rs.normal(0, 4.0, size=(k, d))).astype(np.float32)
+    lab_in = rs.integers(0, k, n).astype(np.int32)
+    c = rs.integers(0, n - 1, size=(n, kappa))
+    G = (c + (c >= np.arange(n)[:, None])).astype(np.int32)
+    out = torch.empty(n, dtype=torch.int32, device=DEV)
+    bd = torch.empty(n, dtype=torch.float32, device=DEV)
+    mv = torch.zeros(1, dtype=torch.int64, device=DEV)
+    knnkm.knn_assign(ctx, dev(X), dev(C), dev(G), dev(lab_in), out, bd, mv)
+    got, got_bd = host(out), host(bd)
+    assert int(host(mv)[0]) == int((got != lab_in).sum())
+    rows = np.concatenate([rs.choice(n, 4000, replace=False), [0, n - 1]])
+    want, want_bd = gkmeans.gk_assign_rows(X, C, lab_in, G, rows)
+    assert np.array_equal(got[rows], want)
+    np.testing.assert_allclose(got_bd[rows], want_bd, rtol=2e-6, atol=1e-6)
+
+
 def test_assign_kappa_ge_k_is_exact_lloyd(ctx):
     say("assign dense")
     from scipy.spatial.distance import cdist
@@ -449,6 +474,52 @@ def test_fit_graph_equals_eager(ctx):
             assert np.array_equal(host(t1), host(t2))
     finally:
         knnkm.knnkm_enable_graphs(ctx, True)
+
+
+def test_fit_full_size_fixed_point(ctx):
+    """The 1M x 128 workload as the benchmark runs it (knn_build, then
+    knn_kmeans_fit with T = 30, captured-graph sweeps and active sets).  It
+    converges within the 30 sweeps, so its labels are a fixed point of the
+    assignment with the returned centroids: no sample moves on the GPU, and
+    sampled rows get the oracle's own decision.  The centroids of sampled
+    clusters are the float32 means of their members (integer data: the
+    float64 sums are exact), the counts are the label histogram and the traced
+    distortion is Eqn. 4 of the returned partition."""
+    n, d, k, kappa, T = 1_000_000, 128, 10_000, 20, 30
+    say("fit full size", n, d, k, kappa, T)
+    X = datagen.config_data("c2", seed=1234)
+    Xd = dev(X)
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=10, max_iters=T, seed=1234)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    knnkm.knn_build(ctx, Xd, p, gi, gd)
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+    cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+    tr, it = knnkm.knn_kmeans_fit(ctx, Xd, k, gi, p, lab, C, cnt)
+    assert it == T
+    out = torch.empty(n, dtype=torch.int32, device=DEV)
+    mv = torch.zeros(1, dtype=torch.int64, device=DEV)
+    knnkm.knn_assign(ctx, Xd, C, gi, lab, out, None, mv)
+    labs, Ch, cnth, G = host(lab), host(C), host(cnt), host(gi)
+    assert int(host(mv)[0]) == 0 and np.array_equal(host(out), labs)
+    rs = np.random.default_rng(9)
+    rows = np.concatenate([rs.choice(n, 4000, replace=False), [0, n - 1]])
+    want, _ = gkmeans.gk_assign_rows(X, Ch, labs, G, rows)
+    assert np.array_equal(want, labs[rows])
+    counts = np.bincount(labs, minlength=k)
+    assert np.array_equal(cnth, counts)
+    order = np.argsort(labs, kind="stable")
+    start = np.concatenate([[0], np.cumsum(counts)])
+    for r in rs.choice(np.nonzero(counts)[0], 200, replace=False):
+        m = X[order[start[r]:start[r + 1]]].astype(np.float64)
+        assert np.array_equal(Ch[r], (m.sum(0) / len(m)).astype(np.float32)), r
+    E = 0.0
+    for s0 in range(0, n, 100_000):
+        diff = X[s0:s0 + 100_000].astype(np.float64) - Ch[labs[s0:s0 + 100_000]].astype(np.float64)
+        E += float(np.einsum("ij,ij->", diff, diff))
+    E /= n
+    assert abs(tr[-1] - E) <= 1e-9 * E, (tr[-1], E)
 
 
 def test_fit_update_exact_at_scale(ctx):

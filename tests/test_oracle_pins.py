@@ -137,6 +137,29 @@ def test_assign_enumeration_beyond_one_block():
     assert moved == int((lab != lab_in).sum())
 
 
+def test_assign_rows_restricted():
+    """gk_assign_rows on sampled rows (any order, a row repeated) returns each
+    row's label and best distance as written out by hand from the whole label
+    array, and the same rows of the full sweep; kappa >= k included."""
+    rs = np.random.default_rng(21)
+    for n, d, k, kappa in [(9000, 4, 300, 6), (500, 3, 4, 6)]:
+        X = rs.normal(size=(n, d)).astype(np.float32)
+        C = rs.normal(size=(k, d)).astype(np.float32)
+        lab_in = rs.integers(0, k, n)
+        G = rs.integers(0, n, size=(n, kappa))
+        rows = np.concatenate([rs.choice(n, 300, replace=False), [0, n - 1, 0]])
+        lab, best = gkmeans.gk_assign_rows(X, C, lab_in, G, rows)
+        full, full_best, _ = gkmeans.gk_assign(X, C, lab_in, G)
+        assert np.array_equal(lab, full[rows]) and np.array_equal(best, full_best[rows])
+        for t, i in enumerate(rows):
+            Q = set(range(k)) if kappa >= k else {int(lab_in[i])} | {int(lab_in[j]) for j in G[i]}
+            dist = {q: float(sum((float(X[i, u]) - float(C[q, u])) ** 2 for u in range(d))) for q in Q}
+            m = min(dist.values())
+            want = int(lab_in[i]) if dist[int(lab_in[i])] == m else min(q for q in Q if dist[q] == m)
+            assert lab[t] == want
+            assert abs(best[t] - dist[want]) <= 1e-12 * max(1.0, dist[want])
+
+
 # ----------------------------------------------------------- update ----
 
 def test_update_hand_worked_and_identity():
