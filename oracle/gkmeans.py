@@ -72,12 +72,13 @@ def gk_assign(X, C, labels_in, G_ids):
 def gk_assign_rows(X, C, labels_in, G_ids, rows):
     """The same sweep for the given rows only (every row's label still enters
     the candidate lists): (labels_out int32, best_d2 float64) of those rows.
-    Used to check sampled outputs of problems too large to sweep in full."""
+    Used to check sampled outputs of problems too large to sweep in full: X
+    and G_ids need only support shape and row indexing by the rows asked for."""
     rows = np.asarray(rows, np.int64)
     C64 = np.asarray(C, np.float32).astype(np.float64)
     labels_in = np.asarray(labels_in, np.int64)
     k = C64.shape[0]
-    kappa = np.asarray(G_ids).shape[1]
+    kappa = G_ids.shape[1]
     out = np.empty(rows.size, np.int32)
     best = np.empty(rows.size, np.float64)
     for s in range(0, rows.size, CHUNK):

@@ -140,6 +140,51 @@ def test_assign_full_size_sampled(ctx):
     np.testing.assert_allclose(got_bd[rows], want_bd, rtol=2e-6, atol=1e-6)
 
 
+class _HostRows:
+    """The rows of a device matrix at the given ids, copied to the host and
+    indexable by those ids (the oracle's row-restricted sweep reads no other)."""
+
+    def __init__(self, mat, ids):
+        ids = np.asarray(ids, np.int64)
+        self.shape = tuple(int(v) for v in mat.shape)
+        self.data = mat[torch.from_numpy(ids).to(mat.device)].cpu().numpy()
+        self.pos = {int(v): t for t, v in enumerate(ids)}
+
+    def __getitem__(self, r):
+        return self.data[[self.pos[int(v)] for v in np.atleast_1d(r)]]
+
+
+def test_assign_full_size_c3_sampled(ctx):
+    """knn_assign at the full 10M x 512 size of the precision-form workload
+    (its mixture recipe, k = 1,000,000, kappa = 50; row offsets beyond 2^31
+    elements): 2,000 sampled rows plus the first and the last against the
+    oracle, and the moved count against the whole output."""
+    c = datagen.CONFIGS["c3"]
+    n, d, k, kappa = 10_000_000, 512, 1_000_000, 50
+    say("assign full size c3", n, d, k, kappa)
+    Xd = datagen.mixture_device(n, d, c["comps"], 31, c["centre"], c["lo"], c["hi"], c["sigma"], c["clip"],
+                                c["integer"], device=DEV)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(3)
+    Cd = (Xd[torch.randint(0, n, (k,), generator=g, device=DEV)]
+          + 0.1 * torch.randn((k, d), generator=g, device=DEV)).contiguous()
+    labd = torch.randint(0, k, (n,), generator=g, device=DEV).to(torch.int32)
+    nb = torch.randint(0, n - 1, (n, kappa), generator=g, device=DEV)
+    Gd = (nb + (nb >= torch.arange(n, device=DEV)[:, None])).to(torch.int32)
+    del nb
+    out = torch.empty(n, dtype=torch.int32, device=DEV)
+    bd = torch.empty(n, dtype=torch.float32, device=DEV)
+    mv = torch.zeros(1, dtype=torch.int64, device=DEV)
+    knnkm.knn_assign(ctx, Xd, Cd, Gd, labd, out, bd, mv)
+    got, got_bd, lab = host(out), host(bd), host(labd)
+    assert int(host(mv)[0]) == int((got != lab).sum())
+    rs = np.random.default_rng(6)
+    rows = np.concatenate([rs.choice(n, 2000, replace=False), [0, n - 1]])
+    want, want_bd = gkmeans.gk_assign_rows(_HostRows(Xd, rows), host(Cd), lab, _HostRows(Gd, rows), rows)
+    assert np.array_equal(got[rows], want)
+    np.testing.assert_allclose(got_bd[rows], want_bd, rtol=2e-6, atol=1e-6)
+
+
 def test_assign_kappa_ge_k_is_exact_lloyd(ctx):
     say("assign dense")
     from scipy.spatial.distance import cdist
