@@ -567,6 +567,31 @@ def test_fit_full_size_fixed_point(ctx):
     assert abs(tr[-1] - E) <= 1e-9 * E, (tr[-1], E)
 
 
+def test_knn_build_full_size_properties(ctx):
+    """knn_build at the full 1M x 128 size as the benchmark runs it: every row
+    holds kappa distinct ids other than its own, sorted by (d2, id), and on
+    4,000 sampled rows every d2 is the float32 of the exact squared distance
+    (integer data: the float64 sum is exact)."""
+    n, d, kappa = 1_000_000, 128, 20
+    say("knn_build full size", n, d, kappa)
+    X = datagen.config_data("c2", seed=1234)
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=10, max_iters=30, seed=1234)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    knnkm.knn_build(ctx, dev(X), p, gi, gd)
+    G, D = host(gi), host(gd)
+    assert G.min() >= 0 and G.max() < n
+    assert not (G == np.arange(n)[:, None]).any()
+    Gs = np.sort(G, axis=1)
+    assert (np.diff(Gs, axis=1) != 0).all()
+    ok = (D[:, 1:] > D[:, :-1]) | ((D[:, 1:] == D[:, :-1]) & (G[:, 1:] > G[:, :-1]))
+    assert ok.all()
+    rows = np.random.default_rng(4).choice(n, 4000, replace=False)
+    diff = X[rows][:, None, :].astype(np.float64) - X[G[rows]].astype(np.float64)
+    exact = np.einsum("ijk,ijk->ij", diff, diff).astype(np.float32)
+    assert np.array_equal(D[rows], exact)
+
+
 def test_fit_update_exact_at_scale(ctx):
     """The incremental update at a size whose composite vectors (Eqn. 2,
     k x d x 16 bytes of fixed point) far exceed the caches: every centroid is
