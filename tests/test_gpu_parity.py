@@ -292,6 +292,48 @@ def test_twomeans_subtree_finish_same_bits(ctx, n, d, k, iters):
         knnkm.knnkm_enable_subtree_finish(ctx, True)
 
 
+def _leaf_sizes(n, k):
+    """Leaf sizes, left to right, of the oracle's tree shape."""
+    shape = twomeans.tree_shape(n, k)
+    if not shape:
+        return [n]
+    sizes, flags = shape[-1]
+    out = []
+    for sz, f in zip(sizes, flags):
+        out += [(sz + 1) // 2, sz // 2] if f else [sz]
+    return out
+
+
+def test_twomeans_full_size_shape(ctx):
+    """TwoMeans at the full sizes of the fits it initialises: the 1M x 128
+    workload (k = 10,000), whose leaves hold exactly the oracle's tree-shape
+    sizes in leaf order and equal the per-depth kernels' leaves bit for bit,
+    and the 10M x 512 workload (k = 1,000,000), whose leaves hold the tree-shape
+    sizes."""
+    say("twomeans full size")
+    n, k = 1_000_000, 10_000
+    X = dev(datagen.config_data("c2", seed=1234))
+    labs = []
+    try:
+        for on in (True, False):
+            knnkm.knnkm_enable_subtree_finish(ctx, on)
+            lab = torch.empty(n, dtype=torch.int32, device=DEV)
+            knnkm.knnkm_twomeans(ctx, X, k, 1234, knnkm.ROUND_FIT, 2, lab)
+            labs.append(host(lab))
+    finally:
+        knnkm.knnkm_enable_subtree_finish(ctx, True)
+    assert np.array_equal(labs[0], labs[1])
+    assert np.array_equal(np.bincount(labs[0], minlength=k), _leaf_sizes(n, k))
+    del X
+    c = datagen.CONFIGS["c3"]
+    n, k = 10_000_000, 1_000_000
+    X = datagen.mixture_device(n, 512, c["comps"], 31, c["centre"], c["lo"], c["hi"], c["sigma"], c["clip"],
+                               c["integer"], device=DEV)
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    knnkm.knnkm_twomeans(ctx, X, k, 5, knnkm.ROUND_FIT, 2, lab)
+    assert np.array_equal(np.bincount(host(lab), minlength=k), _leaf_sizes(n, k))
+
+
 def test_batch_subtree_finish_same_bits(ctx):
     """Many jobs in one tree launch (graph rounds and the fit's initial
     clusters): jobs whose nodes reach 1,024 members at different depths, one
