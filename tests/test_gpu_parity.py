@@ -833,6 +833,40 @@ def test_batch_equals_alone(ctx, init):
         assert np.array_equal(tr[q], a_tr), q
 
 
+def test_batch_full_size_equals_alone(ctx):
+    """The batching form at its full size (4,096 jobs, n ~ U[64, 4096],
+    d = 128, k = ceil(n/32), kappa = 8, T = 20, per-job seeds): eight jobs
+    spread over the batch, the last one included, give the same graph, labels,
+    centroids, counts and trace bits alone as inside the batch."""
+    m, d, kappa, T = 4096, 128, 8, 20
+    say("batch full size", m)
+    sizes = datagen.instance_sizes(m, 2024).astype(np.int64)
+    ks = [int(-(-n // 32)) for n in sizes]
+    n_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    k_off = np.concatenate([[0], np.cumsum(ks)]).astype(np.int64)
+    seeds = [2024 * 7919 + q for q in range(m)]
+    X = datagen.batch_mixture_device(sizes, d, ks, 2024, device=DEV)
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=10, max_iters=T)
+
+    def outs(n, k):
+        return (torch.empty((n, kappa), dtype=torch.int32, device=DEV),
+                torch.empty((n, kappa), dtype=torch.float32, device=DEV),
+                torch.empty(n, dtype=torch.int32, device=DEV),
+                torch.empty((k, d), dtype=torch.float32, device=DEV),
+                torch.empty(k, dtype=torch.int32, device=DEV))
+
+    gi, gd, lab, C, cnt = outs(int(n_off[-1]), int(k_off[-1]))
+    tr = knnkm.knnkm_fit_batched(ctx, X, n_off, ks, seeds, p, gi, gd, lab, C, cnt)
+    jobs = sorted(np.random.default_rng(8).choice(m - 1, 7, replace=False).tolist()) + [m - 1]
+    for j in jobs:
+        r0, r1, c0, c1 = int(n_off[j]), int(n_off[j + 1]), int(k_off[j]), int(k_off[j + 1])
+        o = outs(r1 - r0, c1 - c0)
+        t1 = knnkm.knnkm_fit_batched(ctx, X[r0:r1], [0, r1 - r0], [ks[j]], [seeds[j]], p, *o)
+        assert torch.equal(o[0] + r0, gi[r0:r1]) and torch.equal(o[1], gd[r0:r1]), j
+        assert torch.equal(o[2], lab[r0:r1]) and torch.equal(o[3], C[c0:c1]) and torch.equal(o[4], cnt[c0:c1]), j
+        assert np.array_equal(t1[0], tr[j]), j
+
+
 def test_batch_graph_equals_eager(ctx):
     sizes = [80, 400, 1200, 90]
     d, kappa, T = 16, 8, 8
