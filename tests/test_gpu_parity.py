@@ -227,6 +227,37 @@ def test_update_parity(ctx, n, d, k):
     assert abs(float(host(E)[0]) - e_want) <= 1e-12 * e_want
 
 
+def test_update_and_distortion_full_size(ctx):
+    """centroid_update and distortion at the full 1M x 128 size (the integer
+    mixture, k = 10,000, random labels with one empty cluster): counts,
+    float64 sums and float32 centroids bit for bit against the oracle on every
+    cluster (integer data: exact sums), the distortion within 1e-12."""
+    n, d, k = 1_000_000, 128, 10_000
+    say("update full size", n, d, k)
+    X = datagen.config_data("c2", seed=55)
+    rs = np.random.default_rng(55)
+    lab = rs.integers(0, k, n).astype(np.int32)
+    lab[lab == 7] = 8  # cluster 7 is empty: keeps its previous centroid
+    Cprev = rs.normal(size=(k, d)).astype(np.float32)
+    C_want, cnt_want, sums_want = gkmeans.centroid_update(X, lab, k, Cprev)
+    Xd, labd = dev(X), dev(lab)
+    C = dev(Cprev)
+    cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+    sums = torch.empty((k, d), dtype=torch.float64, device=DEV)
+    knnkm.centroid_update(ctx, Xd, labd, C, cnt, sums)
+    assert np.array_equal(host(cnt), cnt_want)
+    assert np.array_equal(host(sums), sums_want)
+    assert np.array_equal(host(C), C_want)
+    E = torch.zeros(1, dtype=torch.float64, device=DEV)
+    knnkm.distortion(ctx, Xd, C, labd, E)
+    e_want = 0.0
+    for s0 in range(0, n, 100_000):
+        diff = X[s0:s0 + 100_000].astype(np.float64) - C_want[lab[s0:s0 + 100_000]].astype(np.float64)
+        e_want += float(np.einsum("ij,ij->", diff, diff))
+    e_want /= n
+    assert abs(float(host(E)[0]) - e_want) <= 1e-12 * e_want
+
+
 def test_update_integer_data_bit_exact(ctx):
     say("update integer")
     X = datagen.integer_grid(30000, 128, seed=3)
