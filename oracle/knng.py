@@ -14,7 +14,7 @@
   G[j].  A pair is "visited" for row i when j is already in G[i]; the row keeps
   the kappa smallest (value, id) entries of its old list and the new pairs.
 
-Pins (tests/test_oracle_knng.py): one round with k0 = 1 is an exact brute-force
+Pins (tests/test_oracle_pins.py): one round with k0 = 1 is an exact brute-force
 KNN graph (checked against scipy's cKDTree); rows sorted, self-free and
 duplicate-free with stored values equal to the recomputed distances; the
 kappa-th value of every row never increases from one round to the next; tau = 0

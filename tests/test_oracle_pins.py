@@ -259,6 +259,112 @@ def _check_tree(X, k, seed):
     return lab, nodes, shape
 
 
+def _sides(A, cu, cv):
+    """Rows joining u and v, written out with Python floats (u on a tie)."""
+    u, v = [], []
+    for r, x in enumerate(A.tolist()):
+        du = sum((a - b) ** 2 for a, b in zip(x, cu))
+        dv = sum((a - b) ** 2 for a, b in zip(x, cv))
+        (u if du <= dv else v).append(r)
+    return u, v
+
+
+@pytest.mark.parametrize("case", [0, 1, 2])
+def test_bisect_hand_worked(case):
+    """Hand-worked two-step bisections (tests/golden/bisect_2d.json): the
+    centroids after each Lloyd step, and the children.  The cases hold a
+    distance tie that must go to u, an empty side that keeps its centroid, and
+    a delta tie that exists only for the float32-rounded mean."""
+    c = _gold("bisect_2d.json")["cases"][case]
+    A = np.array(c["A"], np.float32).astype(np.float64)
+    members = np.array(c["members"])
+    prev = (c["A"][c["r0"]], c["A"][c["r1"]])
+    for it, st in enumerate(c["after_step"], 1):
+        # the fixture's sides follow from the previous centroids
+        assert _sides(A, *prev) == (st["u"], st["v"])
+        cu, cv = twomeans.lloyd_steps(A, A[c["r0"]], A[c["r1"]], it)
+        assert cu.tolist() == st["c_u"] and cv.tolist() == st["c_v"]
+        prev = (st["c_u"], st["c_v"])
+    L, R, cu, cv = twomeans.split_node(A, members, c["r0"], c["r1"], 2)
+    assert L.tolist() == c["left"] and R.tolist() == c["right"]
+    assert cu.tolist() == c["after_step"][-1]["c_u"] and cv.tolist() == c["after_step"][-1]["c_v"]
+
+
+def test_bisect_matches_scipy_kmeans2():
+    """The bisection's final centroids equal scipy's kmeans2 run for the same
+    two Lloyd steps from the same seed rows (tie-free data; kmeans2 keeps
+    float64 means, so they agree within float32 rounding).  One or three steps
+    of kmeans2 land far away on this data, so the step count is pinned."""
+    from scipy.cluster.vq import kmeans2
+
+    for s in range(6):
+        X = datagen.mixture(400, 4, 3, seed=100 + s, sigma=4.0)
+        A = X.astype(np.float64)
+        r0, r1 = twomeans.seed_pair(7, 0, 3, s, 400)
+        _, _, cu, cv = twomeans.bisect(A, np.arange(400), 7, 0, 3, s, 2)
+        got = np.stack([cu, cv]).astype(np.float64)
+        scale = np.abs(A).max()
+        for it in (1, 2, 3):
+            cb, _ = kmeans2(A, A[[r0, r1]].copy(), iter=it, minit="matrix", missing="warn")
+            err = np.abs(cb - got).max()
+            if it == 2:
+                assert err <= 4 * np.finfo(np.float32).eps * scale, err
+            elif s != 5:  # seed pair 5 has converged by the second step
+                assert err > 1e-3 * scale
+
+
+def test_seed_pair_distinct_and_uniform():
+    """Seed positions are two distinct members; over many nodes every ordered
+    pair of positions is about equally likely (chi-square, s = 6)."""
+    cnt = np.zeros((6, 6))
+    for node in range(30000):
+        r0, r1 = twomeans.seed_pair(3, 1, 15, node, 6)
+        assert 0 <= r0 < 6 and 0 <= r1 < 6 and r0 != r1
+        cnt[r0, r1] += 1
+    exp = 30000 / 30.0
+    off = ~np.eye(6, dtype=bool)
+    assert (((cnt[off] - exp) ** 2) / exp).sum() < 70  # 29 dof, p ~ 1e-4
+
+
+def _pq_leaves(n, k):
+    """Alg. 1 as a literal priority queue: pop the largest cluster, split it
+    into ceil(s/2) and floor(s/2), push both, until k clusters exist.  Ties in
+    size go to the shallower cluster, then the leftmost (the paper leaves ties
+    open).  Returns the leaf sizes from left to right."""
+    import heapq
+
+    heap = [(-n, 0, ())]  # (-size, depth, path from the root: 0 left, 1 right)
+    while len(heap) < k:
+        neg, depth, path = heapq.heappop(heap)
+        s = -neg
+        heapq.heappush(heap, (-((s + 1) // 2), depth + 1, path + (0,)))
+        heapq.heappush(heap, (-(s // 2), depth + 1, path + (1,)))
+    return [-neg for neg, _, _ in sorted(heap, key=lambda t: t[2])]
+
+
+def _shape_leaves(n, k):
+    shape = twomeans.tree_shape(n, k)
+    if not shape:
+        return [n]
+    sizes, flags = shape[-1]
+    return [c for s, f in zip(sizes, flags) for c in (((s + 1) // 2, s // 2) if f else (s,))]
+
+
+@pytest.mark.parametrize("n", [1000, 2047, 10007])
+def test_level_synchronous_schedule_is_pop_the_largest(n):
+    """Splitting depth by depth (the last depth: the largest nodes, leftmost
+    first) gives the same leaves, in order, as the literal pop-the-largest
+    queue of Alg. 1, and the oracle's tree puts exactly those sizes in its
+    leaves 0..k-1."""
+    for k in (1, 2, 7, 100, 299, 777, n // 3, n - 1, n):
+        want = _pq_leaves(n, k)
+        assert _shape_leaves(n, k) == want, (n, k)
+        if n == 1000 and k in (7, 100, 299, 777):
+            X = datagen.mixture(n, 3, 9, seed=k)
+            lab = twomeans.twomeans(X, k, seed=2, rnd=0)
+            assert np.bincount(lab, minlength=k).tolist() == want
+
+
 @pytest.mark.parametrize("n,k", [(1000, 7), (1000, 16), (777, 100), (64, 64), (50, 1), (300, 299)])
 def test_twomeans_balanced(n, k):
     X = datagen.mixture(n, 5, 9, seed=n + k)
@@ -369,6 +475,21 @@ def test_exact_refs_match_scipy():
     assert np.array_equal(ids, ii[:, 1:])
     C = X[:9] + 0.5
     assert (exact.lloyd_assign(X, C) == cdist(X.astype(np.float64), C.astype(np.float64), "sqeuclidean").argmin(1)).all()
+
+
+def test_metrics_hand_worked():
+    """recall@kappa, top-1 recall and label agreement on lists written out by
+    hand."""
+    G = np.array([[1, 2, 3], [0, 2, 4], [5, 6, 7]])
+    exact_ids = np.array([[3, 1, 9], [4, 2, 0], [1, 2, 3]])
+    # row 0 finds {1, 3} of {3, 1, 9}, row 1 all three, row 2 none: 5 of 9
+    assert metrics.recall_at_kappa(G, exact_ids) == 5 / 9
+    # first entries 1.0, 2.5, 0.5 against exact 1-NN distances 1.0, 2.0, 0.5:
+    # rows 0 and 2 sit at the exact distance (a tie counts), row 1 does not
+    G_d2 = np.array([[1.0, 2.0], [2.5, 3.0], [0.5, 0.5]], np.float32)
+    assert metrics.recall_top1(G_d2, np.array([1.0, 2.0, 0.5], np.float32)) == 2 / 3
+    assert metrics.agreement([1, 2, 3, 4], [1, 0, 3, 4]) == 0.75
+    assert metrics.agreement([], []) == 1.0
 
 
 def test_gap_mask_flags_near_ties():
