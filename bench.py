@@ -7,20 +7,25 @@ sweep + intra-cluster comparison) followed by knn_kmeans_fit (Alg. 2 in its
 Lloyd form: TwoMeans initialisation, then T sweeps of assignment, centroid
 update and distortion).
 
-Printed value: samples assigned per second per iteration, n / (time of one fit
-iteration), from HIP events the library records on its stream inside the timed
-steps.  The end-to-end fit time (build + fit) is ms_per_step.  The roofline
-entry is the assignment kernel (knn_assign), whose algorithmic bytes per launch
-are n*(4d + 8*kappa + 12) + 4*k*d.
+The default workload is the precision form at 10M x 512 into k = 1M clusters
+(the synthetic stand-in for the paper's Table 2 task).  Printed value: samples
+assigned per second per iteration, n / (time of one fit iteration), from HIP
+events the library records on its stream inside the timed steps.  The
+end-to-end fit time (build + fit) is ms_per_step.  The roofline entries are
+the assignment kernel (knn_assign): averaged over the fit's sweeps, and for the
+first sweep alone (every sample looked at); each names the bytes it counts.
 
-Beside it the line carries the two added forms, measured in the same run:
-"batching" (many independent small jobs, shaped like the 4,096-job workload,
-in one batched call against the same jobs run one at a time) and "serving"
-(a Poisson stream of jobs through the request loop with continuous batching
-against the same stream served one job at a time; p50/p99 latency and jobs/s).
---config c4 / c5 run those two at full size and print their own line.
+Beside it the line carries the per-sweep record of one fit, the precision
+report (graph recall and distortion error against float64 references), the two
+added forms measured in the same run ("batching": many independent small jobs
+in one batched call against the same jobs one at a time; "serving": a Poisson
+stream through the request loop with continuous batching against the same
+stream served one job at a time), and the FP64 oracle timed on the host on
+slices of the same state.  --config c4 / c5 run those forms at full size and
+print their own line; --candidate-sharing measures how many candidate clusters
+consecutive samples share.
 
-Usage: python bench.py [--config c2] [--steps K] [--warmup W] [--gpus 1]
+Usage: python bench.py [--config c3] [--steps K] [--warmup W] [--gpus 1]
 """
 import argparse
 import json
@@ -119,7 +124,7 @@ def precision_report(ctx, X, p, G_ids, G_d2, labels, C, trace, samples, seed, lo
                          "distortion of the returned labels)"}
 
 
-def measured_traffic(config):
+def measured_traffic(config, key="traffic_bytes_per_launch"):
     """HBM bytes per fit assignment launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a plain copy
     of known size), or None when that summary is missing, is for another
@@ -136,9 +141,9 @@ def measured_traffic(config):
             a, b = line.split("=", 1)
             kv[a.strip()] = b.strip()
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if kv.get("assign_source_sha256") != sha or "traffic_bytes_per_launch" not in kv:
+    if kv.get("assign_source_sha256") != sha or key not in kv:
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return float(kv[key])
 
 
 def _pct(v, q):
@@ -321,34 +326,130 @@ def make_data(cfg, seed, device):
     return torch.from_numpy(X).to(device)
 
 
-def cpu_baseline(cfg, seed, budget_s):
-    """The FP64 oracle's fit iterations on a bounded slice of the same recipe."""
-    from oracle import gkmeans, knng
-    from paper_1705_01813_amd import datagen
+class _Rows:
+    """Rows of a device matrix at given ids, copied to the host and indexable
+    by those ids (the oracle's row-restricted sweep reads no other rows)."""
 
-    m = min(cfg["n"], 20_000 if cfg["d"] <= 128 else 5_000)
-    k = max(2, (cfg["k"] * m) // cfg["n"])
-    X = datagen.config_data(cfg["data"], seed=seed, n=m)
-    G, _ = knng.knn_build(X, cfg["kappa"], xi=cfg["xi"], tau=2, seed=seed)
-    labels = np.random.default_rng(seed).integers(0, k, m).astype(np.int32)
-    C, _, _ = gkmeans.centroid_update(X, labels, k, np.zeros((k, X.shape[1]), np.float32))
-    iters, t_total = 0, 0.0
-    while t_total < budget_s or iters == 0:
-        t0 = time.perf_counter()
-        labels, _, _ = gkmeans.gk_assign(X, C, labels, G)
-        C, _, _ = gkmeans.centroid_update(X, labels, k, C)
-        gkmeans.distortion(X, C, labels)
-        t_total += time.perf_counter() - t0
-        iters += 1
+    def __init__(self, mat, ids):
+        import torch
+
+        ids = np.asarray(ids, np.int64)
+        self.shape = tuple(int(v) for v in mat.shape)
+        self.data = mat[torch.from_numpy(ids).to(mat.device)].cpu().numpy()
+        self.pos = np.full(int(ids.max()) + 1, -1, np.int64)
+        self.pos[ids] = np.arange(ids.size)
+
+    def __getitem__(self, r):
+        return self.data[self.pos[np.asarray(r, np.int64)]]
+
+
+def _host_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS",
+                                          "BLIS_NUM_THREADS") if os.environ.get(k) is not None}
+    return model, len(os.sched_getaffinity(0)), env
+
+
+def cpu_baseline(ctx, X, G_ids, cfg, seed, budget_s, log):
+    """The FP64 oracle's iteration (graph-restricted assignment, centroid
+    update, distortion) on slices of the GPU's own state -- the fit's initial
+    partition (TwoMeans labels and their means) and the graph the GPU built --
+    timed on the host.  Slices of growing size (up to 100k rows) run until the
+    time budget is spent; the per-iteration time for all n rows is extrapolated
+    linearly in the slice size (least squares over the slices)."""
+    import torch
+
+    from oracle import gkmeans
+    from paper_1705_01813_amd import knnkm
+
+    n, d = X.shape
+    k = cfg["k"]
+    lab0 = torch.empty(n, dtype=torch.int32, device=X.device)
+    knnkm.knnkm_twomeans(ctx, X, k, seed, 0xFFFF, 2, lab0)
+    C0 = torch.zeros((k, d), dtype=torch.float32, device=X.device)
+    cnt = torch.empty(k, dtype=torch.int32, device=X.device)
+    knnkm.centroid_update(ctx, X, lab0, C0, cnt)
+    torch.cuda.synchronize()
+    labels = lab0.cpu().numpy()
+    C = C0.cpu().numpy()
+    del C0, cnt, lab0
+    rs = np.random.default_rng(seed)
+    sizes, times = [], []
+    m, spent, cpu_spent = 12_500, 0.0, 0.0
+    while m <= min(n, 100_000) and (len(sizes) < 2 or spent < budget_s):
+        start = int(rs.integers(0, n - m + 1))
+        rows = np.arange(start, start + m)
+        Xr, Gr = _Rows(X, rows), _Rows(G_ids, rows)
+        w0, c0 = time.perf_counter(), time.process_time()
+        out, _ = gkmeans.gk_assign_rows(Xr, C, labels, Gr, rows)
+        Cn, _, _ = gkmeans.centroid_update(Xr.data, out, k, C)
+        gkmeans.distortion(Xr.data, Cn, out)
+        dt = time.perf_counter() - w0
+        cpu_spent += time.process_time() - c0
+        spent += dt
+        sizes.append(m)
+        times.append(dt)
+        log(f"oracle iteration on a {m}-row slice: {dt:.2f} s")
+        m *= 2
+    b, a = np.polyfit(np.asarray(sizes, np.float64), np.asarray(times, np.float64), 1) if len(sizes) > 1 \
+        else (times[0] / sizes[0], 0.0)
+    t_full = a + b * n
+    model, affinity, env = _host_info()
+    used = cpu_spent / spent if spent > 0 else 1.0
     return {
-        "value": m * iters / t_total,
+        "value": n / t_full,
         "unit": "samples assigned/s per iteration",
-        "cores": 1,
+        "cores": max(1, int(round(used))),
         "kind": "oracle",
-        "sample": f"first {m} rows of the same recipe, k={k}, kappa={cfg['kappa']}, graph from the oracle's "
-                  f"own knn_build (tau=2); {iters} oracle iterations (assign + update + distortion) "
-                  f"in {t_total:.1f} s; numpy float64, single thread",
+        "sample": f"one oracle iteration (assign + update + distortion, numpy float64) on row slices of "
+                  f"{sizes} of the GPU's state for this workload (TwoMeans partition with its means, the GPU's "
+                  f"graph, all k={k} centroids); per-iteration time for n={n} extrapolated linearly in the "
+                  f"slice size: {t_full:.1f} s = {a:.2f} s + {b * 1e3:.4f} ms/row",
+        "extrapolated": True,
+        "slice_seconds": dict(zip([str(v) for v in sizes], times)),
+        "cpu_over_wall": used,
+        "host": {"cpu_model": model, "affinity_cores": affinity, "blas_env": env},
     }
+
+
+def candidate_sharing(ctx, X, G_ids, k, seed, log):
+    """How many distinct candidate clusters T consecutive samples of the fit's
+    working order (the cluster order of the initial partition) have together,
+    against the sum of their own counts: the reuse a tile of T samples could
+    get from staging candidate centroid rows once."""
+    import torch
+
+    from paper_1705_01813_amd import knnkm
+
+    n = X.shape[0]
+    lab = torch.empty(n, dtype=torch.int32, device=X.device)
+    knnkm.knnkm_twomeans(ctx, X, k, seed, 0xFFFF, 2, lab)
+    order = torch.argsort(lab.long(), stable=True)
+    cand = torch.cat([lab[:, None], lab[G_ids.long()]], 1)[order]
+    srt = torch.sort(cand, 1)[0]
+    per = (1 + (srt[:, 1:] != srt[:, :-1]).sum(1)).double()
+    total = float(per.sum())
+    out = {"candidates_per_sample": total / n}
+    w = cand.shape[1]
+    for T in (4, 16, 64, 256, 1024, 8192):
+        m = n // T
+        union = 0
+        rows_per = max(1, (1 << 27) // (T * w))
+        for r0 in range(0, m, rows_per):
+            blk = cand[r0 * T:min(m, r0 + rows_per) * T].reshape(-1, T * w)
+            sb = torch.sort(blk, 1)[0]
+            union += int((1 + (sb[:, 1:] != sb[:, :-1]).sum(1)).sum())
+        own = float(per[:m * T].sum())
+        out[f"tile_{T}"] = {"distinct_per_tile": union / m, "sum_per_tile": own / m, "reuse": own / union}
+        log(f"tile {T}: {out[f'tile_{T}']}")
+    return out
 
 
 def main():
@@ -356,18 +457,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS) + ["c4", "c5"])
+    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS) + ["c4", "c5"])
     ap.add_argument("--no-forms", action="store_true", help="skip the batching and serving measurements")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision report")
     ap.add_argument("--counters", action="store_true",
                     help="for counter runs: sweeps as separate dispatches (no graph), no forms or oracle, "
                          "then a 1 GiB elementwise copy that calibrates the memory counters")
+    ap.add_argument("--candidate-sharing", action="store_true",
+                    help="after one build, measure the candidate clusters shared by consecutive samples")
     ap.add_argument("--forms-jobs", type=int, default=4096, help="jobs of the batching measurement")
     ap.add_argument("--forms-sample", type=int, default=64, help="jobs timed one at a time")
     ap.add_argument("--serve-seconds", type=float, default=None,
                     help="arrival window of the serving run (default 2 s beside the main line, 60 s for c5)")
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: --gpus N with N > 1 is not supported "
@@ -400,7 +504,7 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     n, d, k, kappa, T = cfg["n"], cfg["d"], cfg["k"], cfg["kappa"], cfg["T"]
-    print(f"[bench] config {args.config}: {cfg['desc']}", file=sys.stderr, flush=True)
+    log(f"config {args.config}: {cfg['desc']}")
     X = make_data(cfg, args.seed, dev)
     G_ids = torch.empty((n, kappa), dtype=torch.int32, device=dev)
     G_d2 = torch.empty((n, kappa), dtype=torch.float32, device=dev)
@@ -413,9 +517,17 @@ def main():
     knnkm.knnkm_enable_timing(ctx, True)
     if args.counters:
         knnkm.knnkm_enable_graphs(ctx, False)
-        args.no_forms = args.no_cpu_baseline = True
+        args.no_forms = args.no_cpu_baseline = args.no_precision = True
     p = knnkm.default_params(kappa=kappa, xi=cfg["xi"], tau=cfg["tau"], max_iters=T, seed=args.seed,
                              init=cfg["init"], precision=cfg["precision"])
+
+    if args.candidate_sharing:
+        knnkm.knn_build(ctx, X, p, G_ids, G_d2)
+        res = candidate_sharing(ctx, X, G_ids, k, args.seed, log)
+        print(json.dumps({"candidate_sharing": res, "config": {"workload": f"{args.config}: {cfg['desc']}"}}),
+              flush=True)
+        ctx.close()
+        return 0
 
     def step():
         knnkm.knn_build(ctx, X, p, G_ids, G_d2)
@@ -423,15 +535,14 @@ def main():
 
     for w in range(args.warmup):
         step()
-        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        log(f"warmup {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     phases = []
     t0 = time.perf_counter()
     for s in range(args.steps):
         trace, iters = step()
         phases.append(knnkm.knnkm_phase_times(ctx))
-        print(f"[bench] step {s + 1}/{args.steps}: E_0={trace[0]:.6g} E_T={trace[-1]:.6g} "
-              f"phases={phases[-1]}", file=sys.stderr, flush=True)
+        log(f"step {s + 1}/{args.steps}: E_0={trace[0]:.6g} E_T={trace[-1]:.6g} phases={phases[-1]}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
@@ -444,12 +555,22 @@ def main():
     knnkm.knnkm_enable_timing(ctx, 2)
     knnkm.knn_kmeans_fit(ctx, X, k, G_ids, p, labels, C, counts)
     kp = knnkm.knnkm_phase_times(ctx)
+    sw = knnkm.knnkm_sweep_stats(ctx)
     knnkm.knnkm_enable_timing(ctx, 1)
-    assign_ms = kp["assign_ms"] / max(1.0, kp["assign_launches"])
-    evaluated = kp["assign_evaluated"] / max(1.0, kp["assign_launches"]) if kp["assign_evaluated"] >= 0 else None
-    listed = kp["assign_listed"] / max(1.0, kp["assign_launches"]) if kp["assign_listed"] >= 0 else None
+    log(f"sweeps: {sw}")
+    launches = max(1.0, kp["assign_launches"])
+    assign_ms = kp["assign_ms"] / launches
+    evaluated = kp["assign_evaluated"] / launches if kp["assign_evaluated"] >= 0 else None
+    listed = kp["assign_listed"] / launches if kp["assign_listed"] >= 0 else None
     bytes_assign = assign_bytes(n, d, k, kappa, evaluated, listed)
     achieved = bytes_assign / (assign_ms / 1000.0) / 1e9
+    first_ms = sw["assign_ms"][0]
+    bytes_first = assign_bytes(n, d, k, kappa)
+    achieved_first = bytes_first / (first_ms / 1000.0) / 1e9
+    counted = ("per launch: for every sample looked at its graph row and neighbour labels (8 kappa B) and "
+               "its own label, output label and visiting order (12 B); for every sample whose distances are "
+               "evaluated its row (4d B); the centroids once (4kd B); with active sets one flag byte per "
+               "sample")
     out = {
         "metric": "samples assigned/s per iteration",
         "value": value,
@@ -469,21 +590,35 @@ def main():
         "end_to_end_fit_s": ms_per_step / 1000.0,
         "phases_ms": {"knn_build": mean["build_ms"], "fit_init": mean["fit_init_ms"],
                       "fit_iterations": mean["fit_iters_ms"], "per_iteration": iter_ms,
-                      "knn_assign_per_launch": assign_ms},
+                      "knn_assign_per_launch": assign_ms, "knn_assign_first_sweep": first_ms},
         "final_distortion": float(trace[-1]),
-        "roofline": {"kernel": "knn_assign", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "roofline": {"kernel": "knn_assign (fit sweeps, average per launch)", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.config),
-                     "algorithmic_bytes_per_launch": bytes_assign,
-                     "evaluated_samples_per_launch": evaluated,
-                     "listed_samples_per_launch": listed,
-                     "launches_timed": kp["assign_launches"]},
+                     "algorithmic_bytes_per_launch": bytes_assign, "bytes_counted": counted,
+                     "evaluated_samples_per_launch": evaluated, "listed_samples_per_launch": listed,
+                     "launches_timed": kp["assign_launches"], "avg_launch_ms": assign_ms},
+        "roofline_first_sweep": {"kernel": "knn_assign (first fit sweep: every sample looked at and evaluated)",
+                                 "bound": "hbm", "achieved": achieved_first, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": achieved_first / HBM_PEAK_GBS,
+                                 "traffic": measured_traffic(args.config, "first_traffic_bytes"),
+                                 "algorithmic_bytes_per_launch": bytes_first,
+                                 "bytes_counted": "n (8 kappa + 12) + n 4d + 4kd: every graph row, neighbour "
+                                                  "label, own and output label and sample row, and the "
+                                                  "centroids once",
+                                 "launch_ms": first_ms},
+        "sweeps": sw,
     }
     out["autotuned_shapes"] = [ln for ln in knnkm.knnkm_autotune_table().splitlines() if ln]
-    if cfg["precision"] and not args.counters:
+    if cfg["precision"] and not args.no_precision:
         out["precision"] = precision_report(ctx, X, p, G_ids, G_d2, labels, C, trace, 64, args.seed, log)
+    del labels, C, counts
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(ctx, X, G_ids, cfg, args.seed, args.cpu_seconds, log)
     ctx.close()
-    del X, G_ids, G_d2, labels, C, counts
+    del X, G_ids, G_d2
     torch.cuda.empty_cache()
     if args.counters:
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB read, 1 GiB written
@@ -494,9 +629,6 @@ def main():
     if not args.no_forms:
         out["batching"] = bench_batching(args.forms_jobs, args.forms_sample, args.seed, log)
         out["serving"] = bench_serving(args.serve_seconds or 2.0, args.seed, log)
-    if not args.no_cpu_baseline:
-        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, args.seed, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -320,6 +320,16 @@ knnkm_status knnkm_enable_subtree_finish(knnkm_ctx* ctx, int32_t on);
  * call's own data, synchronising the stream, and keeps the fastest for the
  * process.  Every shape gives the same results. */
 knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on);
+/* Early-abandoned partial distances in the assignment for wide rows
+ * (256 < d <= 512, kappa <= 63; default on).  Each sample is handled by one
+ * wavefront: its distinct candidates are listed, the distance to its own
+ * centroid is computed in full, and every other candidate is summed 64
+ * dimensions at a time and dropped once a rigorous lower bound of the partial
+ * sum exceeds a rigorous upper bound of the best full distance so far.
+ * Decisions (labels, moved counts, active-set flags) are the same with it on
+ * or off; calls that request best_d2 use the full-distance kernels. */
+knnkm_status knnkm_enable_partial_distances(knnkm_ctx* ctx, int32_t on);
+
 /* Fix the assignment's launch shape for this context (overrides the
  * autotuner): gs samples per row group and pass, pb samples per block (64 or
  * 128), lazy = 1 to load a sample's row only when a distance is needed (after
@@ -350,6 +360,17 @@ knnkm_status knnkm_autotune_table(char* buf, int64_t len, int64_t* needed);
  *          the first sweep, the active set after it) (on = 2) */
 knnkm_status knnkm_enable_timing(knnkm_ctx* ctx, int32_t on);
 knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t count);
+
+/* Per-sweep record of the last knn_kmeans_fit on ctx (count >= 0 entries per
+ * array, host memory, each array may be null; *n_out = the sweeps written,
+ * min(count, sweeps run)).  Entry j is sweep j+1:
+ *   assign_ms  duration of its assignment launches (timing level 2, else -1)
+ *   listed     samples the assignment looked at (timing level 2, else -1)
+ *   evaluated  samples whose candidate distances it evaluated (level 2, else -1)
+ *   moved      samples whose label changed (every fit of one job)
+ * Waits for the context stream. */
+knnkm_status knnkm_sweep_stats(knnkm_ctx* ctx, double* assign_ms, int64_t* listed, int64_t* evaluated,
+                               int64_t* moved, int32_t count, int32_t* n_out);
 
 /* Counter-based generator used for every random draw of the method
  * (SplitMix64 output function applied to key + (ctr+1)*0x9E3779B97F4A7C15,

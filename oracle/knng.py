@@ -71,23 +71,33 @@ def merge_row(ids, d2, new_ids, new_d2, kappa):
     return all_i[o], all_d[o]
 
 
+def refine_cluster(A64, mem, G_rows, D_rows):
+    """Alg. 3 inner loops for one cluster S_m: every pair <i, j> of its members
+    (global ids ``mem``, rows A64 in float64 in the same order) updates G[i]
+    and G[j].  G_rows / D_rows are the members' current lists; returns the
+    updated lists (the other rows of the graph are not touched)."""
+    kappa = G_rows.shape[1]
+    out_i = np.array(G_rows, dtype=np.int64, copy=True)
+    out_d = np.array(D_rows, dtype=np.float32, copy=True)
+    if len(mem) < 2:
+        return out_i, out_d
+    diff = A64[:, None, :] - A64[None, :, :]
+    D = np.einsum("ijk,ijk->ij", diff, diff).astype(np.float32)
+    for a in range(len(mem)):
+        others = np.concatenate([np.arange(a), np.arange(a + 1, len(mem))])
+        out_i[a], out_d[a] = merge_row(out_i[a], out_d[a], np.asarray(mem)[others], D[a, others], kappa)
+    return out_i, out_d
+
+
 def refine(X, G_ids, G_d2, labels):
     """Exhaustive comparison inside every cluster of ``labels`` and list update."""
     X64 = np.asarray(X, np.float32).astype(np.float64)
     G_ids = np.array(G_ids, dtype=np.int64, copy=True)
     G_d2 = np.array(G_d2, dtype=np.float32, copy=True)
-    kappa = G_ids.shape[1]
     order = np.argsort(labels, kind="stable")
     bounds = np.flatnonzero(np.diff(np.asarray(labels)[order])) + 1
     for mem in np.split(order, bounds):
-        if len(mem) < 2:
-            continue
-        A = X64[mem]
-        diff = A[:, None, :] - A[None, :, :]
-        D = np.einsum("ijk,ijk->ij", diff, diff).astype(np.float32)
-        for a, i in enumerate(mem):
-            others = np.concatenate([np.arange(a), np.arange(a + 1, len(mem))])
-            G_ids[i], G_d2[i] = merge_row(G_ids[i], G_d2[i], mem[others], D[a, others], kappa)
+        G_ids[mem], G_d2[mem] = refine_cluster(X64[mem], mem, G_ids[mem], G_d2[mem])
     return G_ids.astype(np.int32), G_d2
 
 

@@ -731,6 +731,12 @@ extern "C" knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on) {
   return KNNKM_OK;
 }
 
+extern "C" knnkm_status knnkm_enable_partial_distances(knnkm_ctx* ctx, int32_t on) {
+  if (!ctx) return KNNKM_EINVAL;
+  ctx->wide_pd = on != 0;
+  return KNNKM_OK;
+}
+
 extern "C" knnkm_status knnkm_set_assign_shape(knnkm_ctx* ctx, int32_t gs, int32_t pb, int32_t lazy) {
   if (!ctx) return KNNKM_EINVAL;
   const bool ok = gs == 0 || ((pb == 64 || pb == 128) && ((lazy == 0 && (gs == 1 || gs == 2 || gs == 4)) ||
@@ -771,6 +777,9 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
 #define LA(LL, VV)                                                                                         \
   launch_assign_sm<LL, VV>(ctx, S, cfg, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, best_d2, acc, \
                            eacc, order, dense, rel, vec_x, vec_c, job_of, kbase, act_in, act_out)
+  // wide rows: one wavefront per sample with early-abandoned partial
+  // distances (same decisions; best distances come from the kernels below)
+  const bool wide = ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense && labels_in && !best_d2;
   if (act_in && !best_d2 && !order && !all_dense) {
     // active-set sweep: list the flagged samples, then assign them
     KNNKM_WS(ctx, list, int32_t, "as_act_list", n);
@@ -782,6 +791,9 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
     }
     k_act_compact<<<(unsigned)((n + 4095) / 4096), 256, 0, ctx->stream>>>(n, const_cast<uint8_t*>(act_in), list, cnt,
                                                                           list_count_other);
+    if (wide)
+      return ks_assign_pd(ctx, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc, eacc, nullptr, job_of,
+                          kbase, nullptr, act_out, list, cnt, n_active, cdirty, 0);
     const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
 #define LP(LL, VV, SS)                                                                                        \
   k_assign_list<LL, VV, SS, ((LL) >= 64 ? 2 : 1)><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
@@ -838,6 +850,9 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   }
   };
 #undef LA
+  if (wide)
+    return ks_assign_pd(ctx, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc, eacc, order, job_of,
+                        kbase, act_in, act_out, nullptr, nullptr, nullptr, nullptr, 64);
   // shape: tuned entry, else (large call, tuning allowed, not inside a
   // graph capture) time every candidate once, else the default
   const int Sb = S <= 1 ? 1 : (S <= 2 ? 2 : (S <= 4 ? 4 : 8));

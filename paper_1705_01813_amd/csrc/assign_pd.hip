@@ -1,0 +1,370 @@
+// Graph-restricted assignment for wide rows (256 < d <= 512): one wavefront
+// per sample, candidate distances by partial sums with early abandoning.
+//
+// The decision is the one of Alg. 2's Lloyd form (Sec. 4.2): the sample moves
+// to the closest centroid among the clusters of its kappa neighbours and its
+// own, staying unless a candidate is strictly closer, smallest id among equal
+// minima.  At this width the candidates of one sample are nearly all distinct
+// and hardly shared with the samples next to it, so every candidate costs one
+// gathered centroid row; most candidates are far from the sample, and a sum
+// of squares over the first dimensions already exceeds the distance to the
+// sample's own centroid.  So:
+//  * the candidates are deduplicated in LDS (first occurrence order, own
+//    cluster first) and the own centroid's full float32 distance is computed;
+//  * the other candidates go in batches of 64/GL, GL lanes per candidate:
+//    64 dimensions at a time are added to a running float32 partial sum, and
+//    a candidate is dropped as soon as a rigorous lower bound of its partial
+//    sum exceeds a rigorous upper bound of the best full distance found so far
+//    (the candidate then cannot be the closest nor tie with it); a candidate
+//    that survives every chunk has its full distance;
+//  * best and second best over the full distances, and when they are within
+//    the rigorous float32 error margin, float64 re-evaluation of every
+//    survivor inside it with the tie rule, as in the narrow kernels.
+// Decisions therefore equal those of a float64 evaluation of every candidate;
+// no centroid row is read past the chunk that rules it out.
+#include <cfloat>
+
+#include "rowgroup.h"
+
+namespace {
+
+constexpr int PD_CHUNK = 64;  // dimensions per early-abandon step
+
+struct alignas(16) PDWave {
+  float x[512];      // the sample's row
+  int32_t raw[64];   // candidate labels by graph entry (0 = own)
+  int32_t cand[64];  // distinct candidates, own first
+  float full[64];    // float32 full distance of candidate slot (FLT_MAX: dropped)
+};
+
+// Orders this wavefront's LDS writes before its later LDS reads by other
+// lanes (a wavefront's LDS operations execute in order; this keeps the
+// compiler from moving them across).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Sum over aligned groups of GL lanes (GL in {4, 8}); every lane of a group
+// ends with the same bits.
+template <int GL>
+__device__ inline float gl_sum(float v) {
+  v += dpp_f32<DPP_QUAD_XOR1>(v);
+  v += dpp_f32<DPP_QUAD_XOR2>(v);
+  if (GL >= 8) v += dpp_f32<DPP_ROW_HALF_MIRROR>(v);
+  return v;
+}
+
+// The decision of one sample, by the whole wavefront (every argument
+// wave-uniform except lane-held ones).  cv: the candidate label held by lane
+// e (entry e: 0 own, 1..kappa neighbours; -1 unused).  Returns the label.
+template <int GL>
+__device__ inline int pd_decide(PDWave& sh, const float* __restrict__ xrow, int d, bool vec_x,
+                                const float* __restrict__ C, bool vec_c, int cur, int cv, double rel,
+                                bool dense) {
+  const int lane = threadIdx.x & 63;
+  // the row into LDS (lane j: dims [8j, 8j+8)) and the standard layout
+  float x[8];
+  load_row<8>(x, xrow, lane, d, vec_x);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) sh.x[lane * 8 + e] = x[e];
+  // distinct candidates in first-occurrence order
+  sh.raw[lane] = cv;
+  wave_lds_sync();
+  bool first = cv >= 0;
+  if (!dense) {
+#pragma unroll 8
+    for (int e = 0; e < 64; ++e) first = first && !(e < lane && sh.raw[e] == cv);
+  }
+  const uint64_t fm = __ballot(first);
+  const int u = __popcll(fm);
+  if (first) sh.cand[__popcll(fm & lanes_below())] = cv;
+  // own centroid: full float32 distance, 64-lane layout
+  float b1, b2 = FLT_MAX;
+  int q1 = cur;
+  {
+    float c[8];
+    load_row<8>(c, C + (int64_t)cur * d, lane, d, vec_c);
+    float acc = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float df = x[e] - c[e];
+      acc = fmaf(df, df, acc);
+    }
+    b1 = group_sum<64>(acc);
+  }
+  sh.full[lane] = FLT_MAX;
+  wave_lds_sync();
+  if (lane == 0) sh.full[0] = b1;
+  wave_lds_sync();
+  constexpr int NG = 64 / GL;      // candidates per batch
+  constexpr int PL = PD_CHUNK / GL;  // dimensions per lane and chunk
+  const int g = lane / GL, jj = lane % GL;
+  const int nch = (d + PD_CHUNK - 1) / PD_CHUNK;
+  for (int s0 = 1; s0 < u; s0 += NG) {
+    const int slot = s0 + g;
+    bool alive = slot < u;
+    const int q = alive ? sh.cand[slot] : 0;
+    const float* cr = C + (int64_t)q * d;
+    const double ub = (double)b1 * (1.0 + rel) + 1e-30;
+    float P = 0.f;
+    for (int ch = 0; ch < nch; ++ch) {
+      if (__ballot(alive) == 0) break;
+      const int base = ch * PD_CHUNK + jj * PL;
+      float acc = 0.f;
+      if (alive) {
+#pragma unroll
+        for (int e = 0; e < PL; e += 4) {
+          float4 cq;
+          if (vec_c && base + e < d) {
+            cq = *reinterpret_cast<const float4*>(cr + base + e);
+          } else {
+            cq.x = base + e < d ? cr[base + e] : 0.f;
+            cq.y = base + e + 1 < d ? cr[base + e + 1] : 0.f;
+            cq.z = base + e + 2 < d ? cr[base + e + 2] : 0.f;
+            cq.w = base + e + 3 < d ? cr[base + e + 3] : 0.f;
+          }
+          const float4 xq = *reinterpret_cast<const float4*>(&sh.x[base + e]);
+          float df = xq.x - cq.x;
+          acc = fmaf(df, df, acc);
+          df = xq.y - cq.y;
+          acc = fmaf(df, df, acc);
+          df = xq.z - cq.z;
+          acc = fmaf(df, df, acc);
+          df = xq.w - cq.w;
+          acc = fmaf(df, df, acc);
+        }
+      }
+      P += gl_sum<GL>(acc);
+      if (alive && (double)P * (1.0 - rel) > ub) alive = false;
+    }
+    if (alive && jj == 0) sh.full[slot] = P;
+    wave_lds_sync();
+    // fold the batch's survivors into best / second best, in slot order
+    const int hi = min(u, s0 + NG);
+    for (int t = s0; t < hi; ++t) {
+      const float dq = sh.full[t];
+      if (dq == FLT_MAX) continue;
+      const int qq = sh.cand[t];
+      if (dq < b1 || (dq == b1 && qq < q1)) {
+        b2 = fminf(b2, b1);
+        b1 = dq;
+        q1 = qq;
+      } else {
+        b2 = fminf(b2, dq);
+      }
+    }
+  }
+  const double thr = (double)b1 * (1.0 + rel) / (1.0 - rel) + 1e-30;
+  if ((double)b2 > thr) return q1;
+  // float64 re-evaluation of every survivor inside the margin
+  double m64 = DBL_MAX, cur64 = -1.0;
+  int q64 = -1;
+  for (int t = 0; t < u; ++t) {
+    const float dq = sh.full[t];
+    if (dq == FLT_MAX || (double)dq > thr) continue;
+    const int qq = sh.cand[t];
+    float c[8];
+    load_row<8>(c, C + (int64_t)qq * d, lane, d, vec_c);
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const double df = (double)x[e] - (double)c[e];
+      acc = fma(df, df, acc);
+    }
+    const double e64 = group_sum<64>(acc);
+    if (qq == cur) cur64 = e64;
+    if (e64 < m64 || (e64 == m64 && qq < q64)) {
+      m64 = e64;
+      q64 = qq;
+    }
+  }
+  return (cur64 >= 0.0 && cur64 == m64) ? cur : q64;
+}
+
+// Candidate label of lane e for sample i (entry 0: own label; 1..kappa:
+// neighbour labels; for a sample whose job has no more clusters than kappa,
+// every cluster of its job, own first).
+__device__ inline int pd_candidate(int lane, int64_t i, int cur, const int* __restrict__ G, int kappa,
+                                   const int* __restrict__ lab_in, bool dense, int kb, int kc) {
+  if (lane == 0) return cur;
+  if (dense) {
+    if (lane >= kc) return -1;
+    const int v = kb + lane - 1;
+    return v < cur ? v : v + 1;
+  }
+  return lane <= kappa ? lab_in[G[i * kappa + (lane - 1)]] : -1;
+}
+
+// Full sweep: block b takes pb consecutive positions of `order` (or of the
+// identity), wave w of it the positions w, w+4, ...  Same arguments and
+// outputs as k_assign without best distances.
+template <int GL>
+__global__ __launch_bounds__(256) void k_assign_pd(
+    const float* __restrict__ X, int n, int d, int64_t ldx, const float* __restrict__ C, int k,
+    const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
+    unsigned long long* __restrict__ moved_acc, unsigned long long* __restrict__ eval_acc,
+    const int* __restrict__ order, int nchunks, int pb, double rel, int vec_x, int vec_c,
+    const int* __restrict__ job_of, const int* __restrict__ kbase, const uint8_t* __restrict__ act_in,
+    uint8_t* __restrict__ act_out) {
+  __shared__ PDWave sh[4];
+  __shared__ unsigned int block_moved, block_eval;
+  if (threadIdx.x == 0) {
+    block_moved = 0;
+    block_eval = 0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int per_xcd = gridDim.x / 8;
+  const int chunk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  unsigned int my_moved = 0, my_eval = 0;
+  if (chunk < nchunks) {
+    const int64_t start = (int64_t)chunk * pb;
+    const int64_t end = min((int64_t)n, start + pb);
+    for (int64_t idx = start + w; idx < end; idx += 4) {
+      const int64_t i = order ? (int64_t)order[idx] : idx;
+      const int cur = lab_in[i];
+      if (act_in && act_in[i] == 0) {
+        if (lane == 0) {
+          lab_out[i] = cur;
+          if (act_out) act_out[i] = 0;
+        }
+        continue;
+      }
+      int kb = 0, kc = k;
+      if (job_of) {
+        const int q = job_of[i];
+        kb = kbase[q];
+        kc = kbase[q + 1] - kb;
+      }
+      const bool dense = kappa >= kc;
+      const int cv = pd_candidate(lane, i, cur, G, kappa, lab_in, dense, kb, kc);
+      const bool other = cv >= 0 && cv != cur;
+      if (!dense && __ballot(other) == 0) {  // the own cluster is the only candidate
+        if (lane == 0) {
+          lab_out[i] = cur;
+          if (act_out) act_out[i] = 0;
+        }
+        continue;
+      }
+      const int res = pd_decide<GL>(sh[w], X + i * ldx, d, vec_x, C, vec_c, cur, cv, rel, dense);
+      if (lane == 0) {
+        lab_out[i] = res;
+        if (act_out) act_out[i] = 1;
+        ++my_eval;
+        if (res != cur) ++my_moved;
+      }
+    }
+  }
+  if (moved_acc || eval_acc) {
+    if (my_moved) atomicAdd(&block_moved, my_moved);
+    if (my_eval) atomicAdd(&block_eval, my_eval);
+    __syncthreads();
+    if (threadIdx.x == 0 && moved_acc && block_moved) atomicAdd(moved_acc, (unsigned long long)block_moved);
+    if (threadIdx.x == 0 && eval_acc && block_eval) atomicAdd(eval_acc, (unsigned long long)block_eval);
+  }
+}
+
+// Active-set sweep over the listed positions (entries as k_act_compact writes
+// them: position, bit 31 = own or a neighbour's label changed), one listed
+// sample per wavefront, grid-stride.  Same outputs as k_assign_list.
+template <int GL>
+__global__ __launch_bounds__(256) void k_assign_list_pd(
+    const float* __restrict__ X, int d, int64_t ldx, const float* __restrict__ C, int k,
+    const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
+    unsigned long long* __restrict__ moved_acc, unsigned long long* __restrict__ eval_acc,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ count, double rel, int vec_x, int vec_c,
+    const int* __restrict__ job_of, const int* __restrict__ kbase, uint8_t* __restrict__ act_out,
+    int64_t* __restrict__ n_listed, const int32_t* __restrict__ cdirty) {
+  __shared__ PDWave sh[4];
+  __shared__ unsigned int block_moved, block_eval;
+  if (threadIdx.x == 0) {
+    block_moved = 0;
+    block_eval = 0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cnt = *count;
+  if (n_listed && blockIdx.x == 0 && threadIdx.x == 0) *n_listed = cnt;
+  unsigned int my_moved = 0, my_eval = 0;
+  for (int li = blockIdx.x * 4 + w; li < cnt; li += gridDim.x * 4) {
+    const uint32_t ent = (uint32_t)list[li];
+    const bool changed = (ent >> 31) != 0;
+    const int64_t i = (int64_t)(ent & 0x7FFFFFFFu);
+    const int cur = lab_in[i];
+    int kb = 0, kc = k;
+    if (job_of) {
+      const int q = job_of[i];
+      kb = kbase[q];
+      kc = kbase[q + 1] - kb;
+    }
+    const bool dense = kappa >= kc;
+    const int cv = pd_candidate(lane, i, cur, G, kappa, lab_in, dense, kb, kc);
+    const bool other = cv >= 0 && cv != cur;
+    if (!dense && __ballot(other) == 0) {
+      if (lane == 0) {
+        lab_out[i] = cur;
+        if (act_out) act_out[i] = 0;
+      }
+      continue;
+    }
+    if (!changed && !dense && cdirty) {
+      // the same candidates as in the last sweep and none of their
+      // centroids changed: the last decision, to stay, stands
+      if (__ballot(cv >= 0 && cdirty[cv] != 0) == 0) {
+        if (lane == 0) {
+          lab_out[i] = cur;
+          if (act_out) act_out[i] = 1;
+        }
+        continue;
+      }
+    }
+    const int res = pd_decide<GL>(sh[w], X + i * ldx, d, vec_x, C, vec_c, cur, cv, rel, dense);
+    if (lane == 0) {
+      lab_out[i] = res;
+      if (act_out) act_out[i] = 1;
+      ++my_eval;
+      if (res != cur) ++my_moved;
+    }
+  }
+  if (moved_acc || eval_acc) {
+    if (my_moved) atomicAdd(&block_moved, my_moved);
+    if (my_eval) atomicAdd(&block_eval, my_eval);
+    __syncthreads();
+    if (threadIdx.x == 0 && moved_acc && block_moved) atomicAdd(moved_acc, (unsigned long long)block_moved);
+    if (threadIdx.x == 0 && eval_acc && block_eval) atomicAdd(eval_acc, (unsigned long long)block_eval);
+  }
+}
+
+}  // namespace
+
+// Relative error bound used by the wide kernel: 8 products per lane, six
+// levels of lane reduction for the own distance, or three levels per chunk
+// plus up to eight chunk additions; twice the worst case.
+static double pd_rel() { return (8.0 + 8.0 + 6.0 + 3.0) * 0x1p-23; }
+
+bool ks_assign_pd_ok(int32_t d, int32_t kappa) { return d > 256 && d <= 512 && kappa <= 63; }
+
+knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, const float* C,
+                          int32_t k, const int32_t* G_ids, int32_t kappa, const int32_t* labels_in,
+                          int32_t* labels_out, unsigned long long* acc, unsigned long long* eacc,
+                          const int32_t* order, const int32_t* job_of, const int32_t* kbase,
+                          const uint8_t* act_in, uint8_t* act_out, const int32_t* list, const int32_t* list_count,
+                          int64_t* n_listed, const int32_t* cdirty, int pb) {
+  const bool vec_x = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0) && (d % 4 == 0);
+  const bool vec_c = (d % 4 == 0) && ((uintptr_t)C % 16 == 0);
+  const double rel = pd_rel();
+  if (list) {
+    const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
+    k_assign_list_pd<8><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc,
+                                                       eacc, list, list_count, rel, vec_x ? 1 : 0, vec_c ? 1 : 0,
+                                                       job_of, kbase, act_out, n_listed, cdirty);
+    return knnkm_check(ctx, "knn_assign (wide rows, active set)");
+  }
+  const int nchunks = (int)((n + pb - 1) / pb);
+  const int grid = ((nchunks + 7) / 8) * 8;
+  k_assign_pd<8><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc,
+                                                eacc, order, nchunks, pb, rel, vec_x ? 1 : 0, vec_c ? 1 : 0, job_of,
+                                                kbase, act_in, act_out);
+  return knnkm_check(ctx, "knn_assign (wide rows)");
+}

@@ -36,12 +36,14 @@ struct knnkm_ctx {
   int fit_iters = 0;                  // sweeps of the last fit
   const int64_t* fit_evals = nullptr;  // per-sweep evaluated-sample counts of the last timed fit (device)
   const int64_t* fit_actives = nullptr;  // per-sweep listed-sample counts of the last timed fit (device)
+  const int64_t* fit_moved = nullptr;    // per-sweep moved-sample counts of the last fit (device)
   // fit iterations replayed from a captured HIP graph (captured on a private
   // stream, launched on `stream`)
   bool graphs = true;
   // launch shapes of the assignment chosen by timing the candidates once
   bool autotune = true;
   bool active_sets = true;  // fit sweeps look only at samples that can change
+  bool wide_pd = true;      // wide rows: early-abandoned partial distances in the assignment
   int tm_finish_max = 1024;  // two-means subtrees up to this size finished by one block (0: off)
   int assign_gs = 0, assign_pb = 64, assign_lazy = 0;  // forced assignment shape (gs = 0: automatic)
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
@@ -196,6 +198,17 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        int64_t* n_active = nullptr, int32_t* list_count = nullptr,
                        int32_t* list_count_other = nullptr, bool zero_moved = true,
                        const int32_t* cdirty = nullptr);
+// Wide rows (256 < d <= 512, kappa <= 63): one wavefront per sample with
+// early-abandoned partial distances.  list != null: the active-set sweep over
+// the listed positions (list_count entries); else a full sweep in `order`
+// (pb positions per block).  Same decisions and flags as the narrow kernels.
+bool ks_assign_pd_ok(int32_t d, int32_t kappa);
+knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, const float* C,
+                          int32_t k, const int32_t* G_ids, int32_t kappa, const int32_t* labels_in,
+                          int32_t* labels_out, unsigned long long* acc, unsigned long long* eacc,
+                          const int32_t* order, const int32_t* job_of, const int32_t* kbase,
+                          const uint8_t* act_in, uint8_t* act_out, const int32_t* list, const int32_t* list_count,
+                          int64_t* n_listed, const int32_t* cdirty, int pb);
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
                          int32_t* labels);

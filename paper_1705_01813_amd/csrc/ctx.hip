@@ -52,6 +52,7 @@ knnkm_status knnkm_ws_release(knnkm_ctx* ctx) {
   ctx->ws.clear();
   ctx->fit_evals = nullptr;
   ctx->fit_actives = nullptr;
+  ctx->fit_moved = nullptr;
   tm_plan_free(ctx->tm_plan);  // its device tables were workspace
   ctx->tm_plan = nullptr;
   KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -230,6 +231,34 @@ extern "C" knnkm_status knnkm_phase_times(knnkm_ctx* ctx, double* out, int32_t c
   }
   for (int i = 0; i < count && i < 8; ++i) out[i] = v[i];
   for (int i = 8; i < count; ++i) out[i] = 0.0;
+  return KNNKM_OK;
+}
+
+extern "C" knnkm_status knnkm_sweep_stats(knnkm_ctx* ctx, double* assign_ms, int64_t* listed, int64_t* evaluated,
+                                         int64_t* moved, int32_t count, int32_t* n_out) {
+  if (!ctx || count < 0 || !n_out) return KNNKM_EINVAL;
+  *n_out = 0;
+  if (ctx->dry) return KNNKM_OK;
+  (void)hipSetDevice(ctx->device);
+  const int ns = std::min(count, ctx->fit_iters);
+  if (ns <= 0) return KNNKM_OK;
+  for (int j = 0; j < ns; ++j) {
+    if (assign_ms) assign_ms[j] = (ctx->assign_ev0 >= 0 && j < ctx->assign_n) ? ev_ms(ctx, ctx->assign_ev0 + 2 * j) : -1.0;
+  }
+  const int64_t* src[3] = {ctx->fit_actives, ctx->fit_evals, ctx->fit_moved};
+  int64_t* dst[3] = {listed, evaluated, moved};
+  for (int c = 0; c < 3; ++c) {
+    if (!dst[c]) continue;
+    for (int j = 0; j < ns; ++j) dst[c][j] = -1;
+    if (!src[c]) continue;
+    if (hipMemcpyAsync(dst[c], src[c] + 1, sizeof(int64_t) * (size_t)ns, hipMemcpyDeviceToHost, ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return knnkm_fail(ctx, KNNKM_EDEVICE, "sweep_stats: copy failed");
+    }
+  }
+  *n_out = ns;
   return KNNKM_OK;
 }
 

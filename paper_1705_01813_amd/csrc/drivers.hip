@@ -28,7 +28,12 @@ __global__ void k_job_of(const int64_t* __restrict__ n_off, int m, int64_t n, in
 }
 
 // k_q distinct rows of every job by Floyd's algorithm (one thread per job;
-// bitmap membership over the job's rows).  ids are global row ids.
+// bitmap membership over the job's rows).  ids are global row ids.  Job q owns
+// the bitmap words [r0/32 + q, r0/32 + q + ceil(n_q/32)) with its rows'
+// bits counted from r0: the slices of different jobs never share a word
+// (floor(a) + ceil(b) <= floor(a + b) + 1), so the thread of a job is the
+// only one that reads or writes its words.  The bitmap holds
+// ceil(n/32) + m words.
 __global__ void k_random_init_ids(const int64_t* __restrict__ n_off, const int32_t* __restrict__ k_off, int m,
                                   const uint64_t* __restrict__ seeds, uint32_t* __restrict__ bitmap,
                                   int32_t* __restrict__ ids) {
@@ -36,15 +41,15 @@ __global__ void k_random_init_ids(const int64_t* __restrict__ n_off, const int32
   if (q >= m) return;
   const int64_t r0 = n_off[q], nq = n_off[q + 1] - r0;
   const int32_t k0 = k_off[q], kq = k_off[q + 1] - k0;
+  uint32_t* bits = bitmap + (r0 >> 5) + q;
   const uint64_t key = sm_key(seeds[q], sm_stream(RNG_RANDOM_INIT, 0, 0));
   const int64_t base = nq - kq;
   for (int64_t j = base; j < nq; ++j) {
     const int64_t t = sm_below(sm_draw(key, (uint64_t)(j - base)), (uint32_t)(j + 1));
-    const int64_t gt = r0 + t;
-    const bool seen = (bitmap[gt >> 5] >> (gt & 31)) & 1u;
-    const int64_t v = r0 + (seen ? j : t);
-    bitmap[v >> 5] |= 1u << (v & 31);
-    ids[k0 + (j - base)] = (int32_t)v;
+    const bool seen = (bits[t >> 5] >> (t & 31)) & 1u;
+    const int64_t v = seen ? j : t;
+    bits[v >> 5] |= 1u << (v & 31);
+    ids[k0 + (j - base)] = (int32_t)(r0 + v);
   }
 }
 
@@ -335,9 +340,10 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
 
   // initial partition
   if (p->init == KNNKM_INIT_RANDOM) {
-    KNNKM_WS(ctx, bitmap, uint32_t, "fit_bitmap", (n + 31) / 32);
+    const int64_t bm_words = (n + 31) / 32 + m;
+    KNNKM_WS(ctx, bitmap, uint32_t, "fit_bitmap", bm_words);
     KNNKM_WS(ctx, ids, int32_t, "fit_init_ids", K);
-    KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)bitmap, (n + 31) / 32, 0));
+    KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)bitmap, bm_words, 0));
     k_random_init_ids<<<(m + 63) / 64, 64, 0, ctx->stream>>>(J.n_off, k32, m, J.seeds, bitmap, ids);
     k_gather_rows<<<grid_for((int64_t)K * d, 256, 4096), 256, 0, ctx->stream>>>(X, d, ldx, ids, K, C);
     KNNKM_TRY(knnkm_check(ctx, "random init"));
@@ -460,6 +466,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   };
   ctx->fit_evals = nullptr;
   ctx->fit_actives = nullptr;
+  ctx->fit_moved = nullptr;
   const bool time_all = ctx->timing >= 2;
   // with every assignment timed, also count the samples each one looked at
   // and the samples whose distances it evaluated
@@ -558,6 +565,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   ctx->fit_iters = it;
   ctx->fit_evals = evals;
   ctx->fit_actives = actives;
+  ctx->fit_moved = m == 1 ? moved : nullptr;
   return KNNKM_OK;
 }
 

@@ -23,9 +23,9 @@ EXPORTS = [
     "knnkm_create", "knnkm_destroy", "knnkm_set_stream", "knnkm_last_error",
     "knnkm_default_params", "knnkm_workspace_bytes", "knn_assign", "centroid_update",
     "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
-    "knn_kmeans_fit", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times",
+    "knn_kmeans_fit", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times", "knnkm_sweep_stats",
     "knnkm_fit_batched", "knnkm_enable_graphs", "knnkm_enable_active_sets", "knnkm_enable_subtree_finish",
-    "knnkm_autotune", "knnkm_autotune_table", "knnkm_set_assign_shape",
+    "knnkm_autotune", "knnkm_autotune_table", "knnkm_set_assign_shape", "knnkm_enable_partial_distances",
     "knnkm_server_create", "knnkm_server_submit", "knnkm_server_wait",
     "knnkm_server_stats_get", "knnkm_server_last_error", "knnkm_server_destroy",
 ]
@@ -140,9 +140,11 @@ def lib():
             "knnkm_enable_active_sets": [P, i32],
             "knnkm_enable_subtree_finish": [P, i32],
             "knnkm_autotune": [P, i32],
+            "knnkm_enable_partial_distances": [P, i32],
             "knnkm_set_assign_shape": [P, i32, i32, i32],
             "knnkm_autotune_table": [P, i64, ctypes.POINTER(i64)],
             "knnkm_phase_times": [P, P, i32],
+            "knnkm_sweep_stats": [P, P, P, P, P, i32, P],
             "knnkm_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)],
             "knnkm_server_submit": [P, ctypes.POINTER(Job), ctypes.POINTER(u64)],
             "knnkm_server_wait": [P, u64, i64, ctypes.POINTER(JobInfo)],
@@ -363,6 +365,10 @@ def knnkm_enable_subtree_finish(ctx, on=True):
     _chk(ctx.handle, lib().knnkm_enable_subtree_finish(ctx.handle, int(on)))
 
 
+def knnkm_enable_partial_distances(ctx, on=True):
+    _chk(ctx.handle, lib().knnkm_enable_partial_distances(ctx.handle, 1 if on else 0))
+
+
 def knnkm_autotune(ctx, on=True):
     _chk(ctx.handle, lib().knnkm_autotune(ctx.handle, 1 if on else 0))
 
@@ -394,6 +400,21 @@ def knnkm_phase_times(ctx):
     out = np.zeros(len(PHASES), np.float64)
     _chk(ctx.handle, lib().knnkm_phase_times(ctx.handle, out.ctypes.data_as(ctypes.c_void_p), len(PHASES)))
     return dict(zip(PHASES, out.tolist()))
+
+
+def knnkm_sweep_stats(ctx, max_sweeps=1024):
+    """Per-sweep record of the last fit: assignment ms, listed, evaluated and
+    moved samples (lists; -1 where not recorded)."""
+    ms = np.zeros(max_sweeps, np.float64)
+    cnt = [np.zeros(max_sweeps, np.int64) for _ in range(3)]
+    n_out = ctypes.c_int32(0)
+    st = lib().knnkm_sweep_stats(ctx.handle, ms.ctypes.data_as(ctypes.c_void_p),
+                                 *[c.ctypes.data_as(ctypes.c_void_p) for c in cnt], max_sweeps,
+                                 ctypes.byref(n_out))
+    _chk(ctx.handle, st)
+    k = n_out.value
+    return {"assign_ms": ms[:k].tolist(), "listed": cnt[0][:k].tolist(), "evaluated": cnt[1][:k].tolist(),
+            "moved": cnt[2][:k].tolist()}
 
 
 def knnkm_rng_draw(ctx, seed, stream, ctr0, out):

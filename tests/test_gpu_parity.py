@@ -947,3 +947,266 @@ def test_batch_matches_oracle(ctx):
         w_lab, _, _, w_tr, _, _ = gkmeans.fit(Xq, ks[q], w_i, T, seed=seeds[q])
         assert np.array_equal(lab[r0:r1], w_lab), q
         np.testing.assert_allclose(tr[q], w_tr, rtol=1e-9)
+
+
+def test_batch_random_init_many_small_jobs(ctx):
+    """Random initialisation in a batch of many small jobs whose row ranges
+    share 32-bit words of the seed bitmap, with k_q at or near n_q (nearly
+    every row is a seed, so a lost bitmap bit would duplicate a seed): each
+    job's labels and trace equal the oracle's fit of that job alone."""
+    rs = np.random.default_rng(606)
+    m, d, kappa, T = 192, 4, 8, 2
+    sizes = rs.integers(9, 41, m).astype(np.int64)
+    ks = [int(nq - (q % 3)) for q, nq in enumerate(sizes)]
+    seeds = [31 * q + 5 for q in range(m)]
+    say("batch random init, many small jobs", m)
+    Xs = [rs.normal(size=(int(nq), d)).astype(np.float32) for nq in sizes]
+    X = np.concatenate(Xs)
+    n_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n, K = X.shape[0], sum(ks)
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=1, max_iters=T, init=knnkm.INIT_RANDOM)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    C = torch.empty((K, d), dtype=torch.float32, device=DEV)
+    cnt = torch.empty(K, dtype=torch.int32, device=DEV)
+    tr = knnkm.knnkm_fit_batched(ctx, dev(X), n_off, ks, seeds, p, gi, gd, lab, C, cnt)
+    gi, lab = host(gi), host(lab)
+    for q, Xq in enumerate(Xs):
+        r0, r1 = n_off[q], n_off[q + 1]
+        w_i, _ = knng.knn_build(Xq, kappa, xi=50, tau=1, seed=seeds[q])
+        assert np.array_equal(gi[r0:r1] - r0, w_i), q
+        w_lab, _, _, w_tr, _, _ = gkmeans.fit(Xq, ks[q], w_i, T, seed=seeds[q], init=gkmeans.INIT_RANDOM)
+        assert np.array_equal(lab[r0:r1], w_lab), q
+        # with k_q = n_q the distortion is 0; the GPU evaluates it through the
+        # Eqn. 2 identity, whose float64 cancellation error scales with the
+        # mean squared norm of the rows
+        scale = float((Xq.astype(np.float64) ** 2).sum(1).mean())
+        np.testing.assert_allclose(tr[q], w_tr, rtol=1e-9, atol=1e-12 * scale)
+
+
+def test_c1_end_to_end(ctx):
+    """The plain-method workload at its full size (10,000 x 32 from a
+    100-component mixture; knn_build with kappa = 10, xi = 50, tau = 10; fit
+    with k = 100, T = 20 from the seed-fixed random initialisation) through
+    the C ABI against the oracle's knn_build + fit: graph ids and distances,
+    labels and counts bit for bit, the distortion trace within 1e-9, and a
+    trace that never increases."""
+    from oracle import metrics
+
+    c = datagen.CONFIGS["c1"]
+    n, d, k, kappa, T, seed = c["n"], c["d"], 100, 10, 20, 1234
+    say("c1 end to end", n, d, k, kappa, T)
+    X = datagen.config_data("c1", seed=seed)
+    Xd = dev(X)
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=10, max_iters=T, seed=seed, init=knnkm.INIT_RANDOM)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    knnkm.knn_build(ctx, Xd, p, gi, gd)
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+    cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+    tr, it = knnkm.knn_kmeans_fit(ctx, Xd, k, gi, p, lab, C, cnt)
+    w_i, w_d = knng.knn_build(X, kappa, xi=50, tau=10, seed=seed)
+    assert np.array_equal(host(gi), w_i)
+    assert np.array_equal(host(gd), w_d)
+    w_lab, w_C, w_cnt, w_tr, w_it, _ = gkmeans.fit(X, k, w_i, T, seed=seed, init=gkmeans.INIT_RANDOM)
+    got = host(lab)
+    assert metrics.agreement(got, w_lab) >= 0.999
+    assert it == w_it and np.array_equal(got, w_lab)
+    assert np.array_equal(host(cnt), w_cnt)
+    np.testing.assert_allclose(host(C), w_C, rtol=2 ** -23, atol=0)
+    np.testing.assert_allclose(tr, w_tr, rtol=1e-9)
+    assert (np.diff(tr) <= 1e-12 * tr[0]).all()
+
+
+def _refine_round_sampled(ctx, Xd, G0i, G0d, k0, seed, t, precision, clusters, rs):
+    """One round of graph construction replayed through the public calls
+    (two-means tree with round tag t, its means, one graph-restricted sweep,
+    the intra-cluster refinement), then the refined rows of `clusters` sampled
+    clusters against the oracle's refinement of exactly those clusters (their
+    members' rows and old lists copied to the host)."""
+    n, d = Xd.shape
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    knnkm.knnkm_twomeans(ctx, Xd, k0, seed, t, 2, lab)
+    C = torch.zeros((k0, d), dtype=torch.float32, device=DEV)
+    cnt = torch.empty(k0, dtype=torch.int32, device=DEV)
+    knnkm.centroid_update(ctx, Xd, lab, C, cnt)
+    lab2 = torch.empty_like(lab)
+    knnkm.knn_assign(ctx, Xd, C, G0i, lab, lab2)
+    gi, gd = G0i.clone(), G0d.clone()
+    knnkm.knnkm_graph_refine(ctx, Xd, lab2, k0, precision, gi, gd)
+    torch.cuda.synchronize()
+    labels = lab2.long()
+    sizes = torch.bincount(labels, minlength=k0)
+    nonempty = torch.nonzero(sizes >= 2).flatten().cpu().numpy()
+    pick = rs.choice(nonempty, clusters, replace=False)
+    order = torch.argsort(labels, stable=True)
+    starts = torch.cumsum(sizes, 0) - sizes
+    checked = 0
+    for c in pick:
+        mem_d = order[int(starts[c]):int(starts[c]) + int(sizes[c])]
+        mem = mem_d.cpu().numpy()
+        A64 = Xd[mem_d].cpu().numpy().astype(np.float64)
+        w_i, w_d = knng.refine_cluster(A64, mem, G0i[mem_d].cpu().numpy(), G0d[mem_d].cpu().numpy())
+        assert np.array_equal(gi[mem_d].cpu().numpy(), w_i), int(c)
+        assert np.array_equal(gd[mem_d].cpu().numpy(), w_d), int(c)
+        checked += len(mem)
+    return checked
+
+
+def test_refine_full_size_c2_sampled_clusters(ctx):
+    """A graph-construction round at the 1M x 128 workload size (k0 = 20,000
+    clusters, kappa = 20, float32 screen), replayed step by step through the
+    public calls from the random initial lists: every member row of 200
+    sampled clusters equals the oracle's refinement of those clusters."""
+    n, d, kappa, seed = 1_000_000, 128, 20, 11
+    say("refine full size c2", n, d, kappa)
+    X = datagen.config_data("c2", seed=seed)
+    Xd = dev(X)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    knnkm.knnkm_graph_init(ctx, Xd, kappa, seed, gi, gd)
+    rows = _refine_round_sampled(ctx, Xd, gi, gd, n // 50, seed, 0, knnkm.FP32, 200, np.random.default_rng(1))
+    say("rows checked", rows)
+    assert rows >= 200 * 2
+
+
+def test_refine_full_size_c3_sampled_clusters_bf16(ctx):
+    """The same at the 10M x 512 size of the precision form (k0 = 200,000,
+    kappa = 50, bfloat16 screen with float32/float64 re-rank), from the
+    graph after one earlier round: 200 sampled clusters bit for bit."""
+    c = datagen.CONFIGS["c3"]
+    n, d, kappa, seed = 10_000_000, 512, 50, 12
+    say("refine full size c3 bf16", n, d, kappa)
+    Xd = datagen.mixture_device(n, d, c["comps"], seed, c["centre"], c["lo"], c["hi"], c["sigma"], c["clip"],
+                                c["integer"], device=DEV)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=1, seed=seed, precision=knnkm.BF16_RERANK)
+    knnkm.knn_build(ctx, Xd, p, gi, gd)
+    rows = _refine_round_sampled(ctx, Xd, gi, gd, n // 50, seed, 1, knnkm.BF16_RERANK, 200,
+                                 np.random.default_rng(2))
+    say("rows checked", rows)
+    assert rows >= 200 * 2
+
+
+@pytest.mark.parametrize("n,d,k,kappa", [(6000, 512, 300, 50), (5000, 300, 200, 63), (4099, 264, 500, 10),
+                                         (3000, 384, 40, 20)])
+def test_assign_wide_partial_distances(ctx, n, d, k, kappa):
+    """Wide rows: the early-abandoned partial distances give the oracle's
+    labels and moved count, and the same labels as the full-distance kernel,
+    from random input labels (many candidates per sample and many moves) and
+    from the labels one sweep later (fewer moves)."""
+    say("assign wide", n, d, k, kappa)
+    X = datagen.mixture(n, d, max(2, k // 2), seed=d + k, sigma=0.5, centre="normal")
+    rs = np.random.default_rng(d)
+    C = (X[rs.choice(n, k, replace=False)] + rs.normal(0, 0.1, size=(k, d))).astype(np.float32)
+    G = rand_graph(n, kappa, seed=k)
+    lab_rand = rs.integers(0, k, n).astype(np.int32)
+    lab_near, _, _ = gkmeans.gk_assign(X, C, lab_rand, G)
+    Xd, Cd, Gd = dev(X), dev(C), dev(G)
+    for lab_in in (lab_rand, lab_near.astype(np.int32)):
+        want, _, want_mv = gkmeans.gk_assign(X, C, lab_in, G)
+        got = {}
+        for pd in (True, False):
+            knnkm.knnkm_enable_partial_distances(ctx, pd)
+            out = torch.empty(n, dtype=torch.int32, device=DEV)
+            mv = torch.zeros(1, dtype=torch.int64, device=DEV)
+            knnkm.knn_assign(ctx, Xd, Cd, Gd, dev(lab_in), out, None, mv)
+            got[pd] = (host(out), int(host(mv)[0]))
+        knnkm.knnkm_enable_partial_distances(ctx, True)
+        assert np.array_equal(got[True][0], want)
+        assert got[True][1] == want_mv
+        assert np.array_equal(got[True][0], got[False][0]) and got[True][1] == got[False][1]
+
+
+def test_assign_wide_near_ties(ctx):
+    """Wide rows whose candidates sit at equal or nearly equal distances
+    (duplicated centroids, a centroid copied with one coordinate nudged by one
+    ulp): the float64 pass and the tie rule decide as in the oracle."""
+    n, d, k, kappa = 2000, 512, 64, 30
+    say("assign wide ties")
+    X = datagen.mixture(n, d, 16, seed=5, sigma=0.5, centre="normal")
+    rs = np.random.default_rng(3)
+    base = X[rs.choice(n, k // 2, replace=False)].copy()
+    C = np.concatenate([base, base]).astype(np.float32)  # every centroid twice
+    C[k // 2 + 1, 7] = np.nextafter(C[k // 2 + 1, 7], np.float32(np.inf))
+    G = rand_graph(n, kappa, seed=8)
+    lab_in = rs.integers(0, k, n).astype(np.int32)
+    want, _, want_mv = gkmeans.gk_assign(X, C, lab_in, G)
+    out = torch.empty(n, dtype=torch.int32, device=DEV)
+    mv = torch.zeros(1, dtype=torch.int64, device=DEV)
+    knnkm.knn_assign(ctx, dev(X), dev(C), dev(G), dev(lab_in), out, None, mv)
+    assert np.array_equal(host(out), want)
+    assert int(host(mv)[0]) == want_mv
+
+
+@pytest.mark.parametrize("d", [512, 320])
+def test_fit_wide_partial_distances_same_bits(ctx, d):
+    """A fit on wide rows (the library's graph, active sets on) gives the same
+    labels, centroids, counts and trace with the partial-distance kernels on
+    and off, and the oracle's labels and trace."""
+    n, k, kappa, T = 6000, 300, 50, 8
+    say("fit wide", d)
+    X = datagen.mixture(n, d, 500, seed=d, sigma=0.5, centre="normal")
+    Xd = dev(X)
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=2, max_iters=T, seed=4)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    knnkm.knn_build(ctx, Xd, p, gi, gd)
+    res = {}
+    for pd in (True, False):
+        knnkm.knnkm_enable_partial_distances(ctx, pd)
+        lab = torch.empty(n, dtype=torch.int32, device=DEV)
+        C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+        cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+        tr, it = knnkm.knn_kmeans_fit(ctx, Xd, k, gi, p, lab, C, cnt)
+        res[pd] = (host(lab), host(C), host(cnt), tr)
+    knnkm.knnkm_enable_partial_distances(ctx, True)
+    for a, b in zip(res[True], res[False]):
+        assert np.array_equal(a, b)
+    w_lab, _, _, w_tr, _, _ = gkmeans.fit(X, k, host(gi), T, seed=4)
+    assert np.array_equal(res[True][0], w_lab)
+    np.testing.assert_allclose(res[True][3], w_tr, rtol=1e-9)
+
+
+def test_batch_wide_rows_with_small_jobs(ctx):
+    """A batch of wide-row jobs, some with fewer clusters than kappa (every
+    cluster of the job is a candidate): batched equals alone and equals the
+    partial-distance kernels switched off."""
+    sizes = [120, 900, 64, 1500]
+    d, kappa, T = 300, 16, 5
+    say("batch wide rows", sizes)
+    Xs = [datagen.mixture(nq, d, max(2, nq // 40), seed=90 + q, sigma=0.5, centre="normal")
+          for q, nq in enumerate(sizes)]
+    n_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    ks = [3, 60, 12, 200]  # jobs 0 and 2: k_q <= kappa
+    seeds = [70 + q for q in range(len(sizes))]
+    X = dev(np.concatenate(Xs))
+    n, K = int(n_off[-1]), sum(ks)
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=2, max_iters=T)
+
+    def run(pd):
+        knnkm.knnkm_enable_partial_distances(ctx, pd)
+        out = [torch.empty((n, kappa), dtype=torch.int32, device=DEV),
+               torch.empty((n, kappa), dtype=torch.float32, device=DEV),
+               torch.empty(n, dtype=torch.int32, device=DEV),
+               torch.empty((K, d), dtype=torch.float32, device=DEV),
+               torch.empty(K, dtype=torch.int32, device=DEV)]
+        tr = knnkm.knnkm_fit_batched(ctx, X, n_off, ks, seeds, p, *out)
+        return [host(t) for t in out] + [tr]
+
+    try:
+        a, b = run(True), run(False)
+    finally:
+        knnkm.knnkm_enable_partial_distances(ctx, True)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    k_off = np.concatenate([[0], np.cumsum(ks)])
+    for q, Xq in enumerate(Xs):
+        w_i, _ = knng.knn_build(Xq, kappa, xi=50, tau=2, seed=seeds[q])
+        assert np.array_equal(a[0][n_off[q]:n_off[q + 1]] - n_off[q], w_i), q
+        w_lab, _, _, w_tr, _, _ = gkmeans.fit(Xq, ks[q], w_i, T, seed=seeds[q])
+        assert np.array_equal(a[2][n_off[q]:n_off[q + 1]], w_lab), q
+        np.testing.assert_allclose(a[5][q], w_tr, rtol=1e-9)

@@ -1,6 +1,8 @@
 """Serving form on the GPU: jobs submitted to the request loop while others run
 return exactly what the same job returns alone (graph, labels, centroids,
-counts, distortion trace), and the HBM budget bounds what is admitted."""
+counts, distortion trace), served jobs of both dimensionalities equal the
+FP64 oracle's build and fit of that job, and the HBM budget bounds what is
+admitted."""
 import threading
 import time
 
@@ -9,6 +11,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import gkmeans, knng  # noqa: E402
 from paper_1705_01813_amd import datagen, knnkm  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -70,6 +73,22 @@ def _check_same(ctx, jobs, results):
         assert np.array_equal(res["trace"], tr), j
 
 
+def _check_oracle(jobs, results, picks):
+    """Served jobs against the oracle's knn_build + fit of the same job: graph
+    ids, labels and counts bit for bit, centroids within one float32 ulp, the
+    trace within 1e-9."""
+    for j in picks:
+        (X, k, p), res = jobs[j], results[j]
+        X = np.ascontiguousarray(X)
+        w_i, _ = knng.knn_build(X, p.kappa, xi=p.xi, tau=p.tau, seed=p.seed)
+        assert np.array_equal(res["G_ids"], w_i), j
+        w_lab, w_C, w_cnt, w_tr, _, _ = gkmeans.fit(X, k, w_i, p.max_iters, seed=p.seed, init=p.init)
+        assert np.array_equal(res["labels"], w_lab), j
+        assert np.array_equal(res["counts"], w_cnt), j
+        np.testing.assert_allclose(res["C"], w_C, rtol=2 ** -23, atol=0)
+        np.testing.assert_allclose(res["trace"], w_tr, rtol=1e-9)
+
+
 def test_server_alone_equals_mix(ctx):
     jobs = _jobs(24, seed=3)
     say("server mix", [(X.shape, k) for X, k, _ in jobs])
@@ -93,6 +112,12 @@ def test_server_alone_equals_mix(ctx):
     assert st["ws_overruns"] == 0
     assert len({r["info"]["batch"] for r in results}) < len(jobs)
     _check_same(ctx, jobs, results)
+    # two served jobs of each dimensionality against the oracle
+    picks = [j for j, (X, _, _) in enumerate(jobs) if X.shape[1] == 16][:2] + \
+            [j for j, (X, _, _) in enumerate(jobs) if X.shape[1] == 32][:2]
+    say("oracle check of served jobs", picks)
+    assert len(picks) == 4
+    _check_oracle(jobs, results, picks)
 
 
 def test_server_tight_budget(ctx):
