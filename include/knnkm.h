@@ -120,6 +120,18 @@ knnkm_status centroid_update(knnkm_ctx* ctx, const float* X, int64_t n, int32_t 
 knnkm_status distortion(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                         const float* C, int32_t k, const int32_t* labels, double* E);
 
+/* distortion without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and bits as distortion(); its
+ * partial sums live in a fixed 4 MiB device array of the library (one copy
+ * per device, held until the process ends, its address resolved once per
+ * device by knnkm_create) instead of the context workspace, and it calls no
+ * allocating routine.  Requires n <= 134,201,344 (KNNKM_EUNSUPPORTED beyond,
+ * before any launch).  Calls that overlap on one device share that array and
+ * race: serialise them (one stream, or events between streams). */
+knnkm_status distortion_noalloc(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                                const float* C, int32_t k, const int32_t* labels, double* E);
+
 /* Two-means tree, Alg. 1: labels in [0,k) from a level-synchronous balanced
  * bisection.  Every split seeds two centroids from two distinct members
  * (counter-based draws keyed by seed, round_tag and the node), runs

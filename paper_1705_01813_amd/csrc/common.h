@@ -186,6 +186,12 @@ knnkm_status ks_segsum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        const int32_t* members, float* C, double* sums, double* Iterm);
 // Deterministic float64 sum of count values into *out (device).
 knnkm_status ks_sum_f64(knnkm_ctx* ctx, const double* in, int64_t count, double* out);
+// The same with the tile partials (ceil(count/8192) doubles when count >
+// 65536) in a buffer the caller provides.
+knnkm_status ks_sum_f64_with(knnkm_ctx* ctx, const double* in, int64_t count, double* part, double* out);
+// Resolves, once per device (that device current), the device address of the
+// fixed scratch array of the allocation-free calls.
+knnkm_status ks_noalloc_setup(knnkm_ctx* ctx);
 // Assignment kernel launcher (order: optional visiting order of samples;
 // use: where the call comes from, a key of the tuned launch shapes).
 enum { KS_USE_CALL = 0, KS_USE_BUILD = 1, KS_USE_FIT_FIRST = 2, KS_USE_FIT = 3 };

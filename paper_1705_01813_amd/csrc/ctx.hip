@@ -102,6 +102,12 @@ extern "C" knnkm_status knnkm_create(int device, void* hip_stream, knnkm_ctx** o
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
+    // device address of the fixed scratch used by the allocation-free calls
+    if (ks_noalloc_setup(ctx) != KNNKM_OK) {
+      g_create_err = ctx->err;
+      delete ctx;
+      return KNNKM_EDEVICE;
+    }
   }
   *out = ctx;
   return KNNKM_OK;
@@ -388,10 +394,9 @@ __global__ __launch_bounds__(256) void k_sum_f64_tiles(const double* in, int64_t
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
-knnkm_status ks_sum_f64(knnkm_ctx* ctx, const double* in, int64_t count, double* out) {
+knnkm_status ks_sum_f64_with(knnkm_ctx* ctx, const double* in, int64_t count, double* part, double* out) {
   if (count > 65536) {
-    int64_t tiles = (count + 8191) / 8192;
-    KNNKM_WS(ctx, part, double, "sum_f64_part", tiles);
+    const int64_t tiles = (count + 8191) / 8192;
     k_sum_f64_tiles<<<(unsigned)tiles, 256, 0, ctx->stream>>>(in, count, part);
     KNNKM_TRY(knnkm_check(ctx, "sum_f64 tiles"));
     k_sum_f64<<<1, 256, 0, ctx->stream>>>(part, tiles, out);
@@ -399,6 +404,15 @@ knnkm_status ks_sum_f64(knnkm_ctx* ctx, const double* in, int64_t count, double*
   }
   k_sum_f64<<<1, 256, 0, ctx->stream>>>(in, count, out);
   return knnkm_check(ctx, "sum_f64");
+}
+
+knnkm_status ks_sum_f64(knnkm_ctx* ctx, const double* in, int64_t count, double* out) {
+  double* part = nullptr;
+  if (count > 65536) {
+    KNNKM_WS(ctx, p, double, "sum_f64_part", (count + 8191) / 8192);
+    part = p;
+  }
+  return ks_sum_f64_with(ctx, in, count, part, out);
 }
 
 // --------------------------------------------------- generator exposure --

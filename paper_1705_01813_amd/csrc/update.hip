@@ -11,6 +11,8 @@
 //    the chunk partials of a cluster in chunk order, so the result is
 //    identical on every run.
 //  * distortion: float64 per sample, fixed per-block order, fixed final sum.
+#include <mutex>
+
 #include "common.h"
 
 #define RS_TILE 1024
@@ -370,4 +372,69 @@ extern "C" knnkm_status distortion(knnkm_ctx* ctx, const float* X, int64_t n, in
   if (ctx->dry) return KNNKM_OK;
   KNNKM_HIP(ctx, hipSetDevice(ctx->device));
   return ks_sqdist_sum(ctx, X, n, d, ldx, C, labels, E, 1.0 / (double)n);
+}
+
+// ------------------------------------------------ allocation-free distortion --
+// distortion_noalloc keeps its per-block partial sums (and, past 65,536
+// blocks, the partials of their sum) in this fixed array instead of the
+// context workspace.  Each device holds its own copy until the process ends;
+// host code uses only the device address resolved below, never the array's
+// name.  Every call overwrites what it reads, so nothing needs clearing; calls
+// that overlap on one device race on it.
+#define NOALLOC_SCRATCH_DOUBLES (1 << 19) /* 4 MiB */
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[64] = {};  // per device, resolved once
+
+knnkm_status ks_noalloc_setup(knnkm_ctx* ctx) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (ctx->device < 0 || ctx->device >= 64)
+    return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "device %d: the fixed scratch supports devices 0..63", ctx->device);
+  if (g_scratch_dev[ctx->device]) return KNNKM_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return knnkm_fail(ctx, KNNKM_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+  }
+  g_scratch_dev[ctx->device] = (double*)ptr;
+  return KNNKM_OK;
+}
+
+extern "C" knnkm_status distortion_noalloc(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                                           const float* C, int32_t k, const int32_t* labels, double* E) {
+  KNNKM_TRY(check_common(ctx, "distortion_noalloc", X, n, d, ldx, k));
+  if (!labels || !C || !E) return knnkm_fail(ctx, KNNKM_EINVAL, "distortion_noalloc: null pointer");
+  const int64_t blocks = (n + 255) / 256;
+  const int64_t tiles = blocks > 65536 ? (blocks + 8191) / 8192 : 0;
+  if (blocks + tiles > NOALLOC_SCRATCH_DOUBLES)
+    return knnkm_fail(ctx, KNNKM_EUNSUPPORTED,
+                      "distortion_noalloc: n=%lld needs %lld scratch doubles, the fixed scratch holds %d "
+                      "(n <= 134,201,344)",
+                      (long long)n, (long long)(blocks + tiles), NOALLOC_SCRATCH_DOUBLES);
+  if (ctx->dry) return KNNKM_OK;
+  KNNKM_HIP(ctx, hipSetDevice(ctx->device));
+  double* part = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    part = g_scratch_dev[ctx->device];
+  }
+  if (!part) return knnkm_fail(ctx, KNNKM_EDEVICE, "distortion_noalloc: scratch not resolved for this device");
+  const int T = (d + 63) / 64;
+#define DL(TT) k_sqdist_blocks<TT><<<(unsigned)blocks, 256, 0, ctx->stream>>>(X, n, d, ldx, C, labels, part)
+  switch (T) {
+    case 1: DL(1); break;
+    case 2: DL(2); break;
+    case 3: DL(3); break;
+    case 4: DL(4); break;
+    case 5: DL(5); break;
+    case 6: DL(6); break;
+    case 7: DL(7); break;
+    default: DL(8); break;
+  }
+#undef DL
+  KNNKM_TRY(knnkm_check(ctx, "distortion_noalloc blocks"));
+  KNNKM_TRY(ks_sum_f64_with(ctx, part, blocks, part + blocks, E));
+  k_scale_f64<<<1, 64, 0, ctx->stream>>>(E, 1.0 / (double)n);
+  return knnkm_check(ctx, "distortion_noalloc scale");
 }

@@ -23,7 +23,7 @@ EXPORTS = [
     "knnkm_create", "knnkm_destroy", "knnkm_set_stream", "knnkm_last_error",
     "knnkm_default_params", "knnkm_workspace_bytes", "knn_assign", "centroid_update",
     "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
-    "knn_kmeans_fit", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times", "knnkm_sweep_stats",
+    "knn_kmeans_fit", "distortion_noalloc", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times", "knnkm_sweep_stats",
     "knnkm_fit_batched", "knnkm_enable_graphs", "knnkm_enable_active_sets", "knnkm_enable_subtree_finish",
     "knnkm_autotune", "knnkm_autotune_table", "knnkm_set_assign_shape", "knnkm_enable_partial_distances",
     "knnkm_server_create", "knnkm_server_submit", "knnkm_server_wait",
@@ -128,6 +128,7 @@ def lib():
             "knn_assign": [P, P, i64, i32, i64, P, i32, P, i32, P, P, P, P],
             "centroid_update": [P, P, i64, i32, i64, P, i32, P, P, P],
             "distortion": [P, P, i64, i32, i64, P, i32, P, P],
+            "distortion_noalloc": [P, P, i64, i32, i64, P, i32, P, P],
             "knnkm_twomeans": [P, P, i64, i32, i64, i32, u64, i32, i32, P],
             "knnkm_graph_init": [P, P, i64, i32, i64, i32, u64, P, P],
             "knnkm_graph_refine": [P, P, i64, i32, i64, P, i32, i32, P, P, i32],
@@ -272,6 +273,16 @@ def distortion(ctx, X, C, labels, E):
     n, d, ldx = _rows(X)
     st = lib().distortion(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx, _ptr(C, torch.float32, "C"),
                           C.shape[0], _ptr(labels, torch.int32, "labels"), _ptr(E, torch.float64, "E"))
+    _chk(ctx.handle, st)
+
+
+def distortion_noalloc(ctx, X, C, labels, E):
+    """Allocation-free variant of distortion (fixed library scratch)."""
+    import torch
+
+    n, d, ldx = _rows(X)
+    st = lib().distortion_noalloc(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx, _ptr(C, torch.float32, "C"),
+                                  C.shape[0], _ptr(labels, torch.int32, "labels"), _ptr(E, torch.float64, "E"))
     _chk(ctx.handle, st)
 
 
