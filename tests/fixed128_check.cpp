@@ -2,7 +2,11 @@
 // centroid update, against the compiler's own 128-bit integer arithmetic:
 // long double scaling (64-bit significand, exact for a double times 2^s)
 // truncated to __int128, and the correctly rounded __int128 -> double
-// conversion.  Prints the number of mismatches; exit status 1 on any.
+// conversion.  Also checks, on the same cases, an earlier form of the
+// fixed-point -> double conversion written with 64-bit variable shifts
+// (fx_to_double_shift64 below), which the library no longer uses.  Prints the
+// number of mismatches; exit status 1 on any.  Built both plainly and with
+// the address and undefined-behaviour sanitizers by the test that runs it.
 #include <cstdio>
 #include <random>
 
@@ -14,12 +18,35 @@ static __int128 want_of_double(double v, int s) {
   return v < 0 ? -(__int128)mag : (__int128)mag;
 }
 
+// The earlier conversion: the 64 bits below the leading one taken with 64-bit
+// shifts of the two words, a sticky bit for the rest, one rounding through
+// (double) of a 64-bit integer, then two exact power-of-two scalings.
+static double fx_to_double_shift64(uint64_t hi, uint64_t lo, int s) {
+  const bool neg = (int64_t)hi < 0;
+  if (neg) fx_neg(hi, lo);
+  double m;
+  if (hi == 0) {
+    m = (double)lo;
+  } else {
+    const int lz = __builtin_clzll(hi);
+    const int sh = 64 - lz;
+    uint64_t top = lz ? ((hi << lz) | (lo >> (64 - lz))) : hi;
+    const uint64_t rest = sh >= 64 ? lo : (lo & ((1ull << sh) - 1));
+    if (rest) top |= 1;
+    m = std::ldexp((double)top, sh);
+  }
+  return std::ldexp(neg ? -m : m, -s);
+}
+
 static __int128 join(uint64_t hi, uint64_t lo) { return (__int128)(((unsigned __int128)hi << 64) | lo); }
+
+static long bad_shift64 = 0;
 
 static long check_to(__int128 x, int s) {
   const double want = std::ldexp((double)x, -s);
-  const double got = fx_to_double((uint64_t)((unsigned __int128)x >> 64), (uint64_t)x, s);
-  return want != got;
+  const uint64_t hi = (uint64_t)((unsigned __int128)x >> 64), lo = (uint64_t)x;
+  bad_shift64 += fx_to_double_shift64(hi, lo, s) != want;
+  return fx_to_double(hi, lo, s) != want;
 }
 
 int main(int argc, char** argv) {
@@ -44,7 +71,9 @@ int main(int argc, char** argv) {
     }
     // exact ties at the 53-bit boundary, with and without a sticky bit below
     if (b >= 60) {
-      const unsigned __int128 base = ((unsigned __int128)g() | ((unsigned __int128)1 << 63)) << (b - 63);
+      // a random (b+1)-bit value with its top bit set (b = 60..62 shift right)
+      const unsigned __int128 top = (unsigned __int128)g() | ((unsigned __int128)1 << 63);
+      const unsigned __int128 base = b >= 63 ? top << (b - 63) : top >> (63 - b);
       const unsigned __int128 half = (unsigned __int128)1 << (b - 53);
       bad_to += check_to((__int128)(base | half), 7) + check_to((__int128)((base | half) + 1), 7);
     }
@@ -66,6 +95,7 @@ int main(int argc, char** argv) {
     const __int128 x = (g() & 1) ? -(__int128)m : (__int128)m;
     bad_to += check_to(x, (int)(g() % 121));
   }
-  std::printf("fx_of_double mismatches %ld, fx_to_double mismatches %ld\n", bad_of, bad_to);
-  return (bad_of || bad_to) ? 1 : 0;
+  std::printf("fx_of_double mismatches %ld, fx_to_double mismatches %ld, shift64 form mismatches %ld\n", bad_of,
+              bad_to, bad_shift64);
+  return (bad_of || bad_to || bad_shift64) ? 1 : 0;
 }
