@@ -35,6 +35,17 @@ struct alignas(16) PDWave {
   int32_t raw[64];   // candidate labels by graph entry (0 = own)
   int32_t cand[64];  // distinct candidates, own first
   float full[64];    // float32 full distance of candidate slot (FLT_MAX: dropped)
+  float lb[64];      // lower bound of the squared distance of candidate slot
+};
+
+// Result of one decision: the label; u, an upper bound of the distance (not
+// squared) to the chosen centroid; and, per lane e, a lower bound of the
+// distance to the cluster of graph entry e (0 where that cluster is the
+// chosen one or the entry is unused).
+struct PDResult {
+  int label;
+  float u;
+  float lb;  // lane-held
 };
 
 // Orders this wavefront's LDS writes before its later LDS reads by other
@@ -57,28 +68,36 @@ __device__ inline float gl_sum(float v) {
 
 // The decision of one sample, by the whole wavefront (every argument
 // wave-uniform except lane-held ones).  cv: the candidate label held by lane
-// e (entry e: 0 own, 1..kappa neighbours; -1 unused).  Returns the label.
+// e (entry e: 0 own, 1..kappa neighbours; -1 unused).  skip (lane-held): the
+// entry's cluster is already known to be strictly farther than the own
+// centroid, so it takes no part (its lane's lb is left to the caller).
+// Returns the label and the bounds of PDResult: every candidate's squared
+// distance is bracketed by rigorous float32 bounds (a dropped one from below
+// by its partial sum), so they hold for the exact distances.
 template <int GL>
-__device__ inline int pd_decide(PDWave& sh, const float* __restrict__ xrow, int d, bool vec_x,
-                                const float* __restrict__ C, bool vec_c, int cur, int cv, double rel,
-                                bool dense) {
+__device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow, int d, bool vec_x,
+                                     const float* __restrict__ C, bool vec_c, int cur, int cv, double rel,
+                                     bool dense, bool skip) {
   const int lane = threadIdx.x & 63;
   // the row into LDS (lane j: dims [8j, 8j+8)) and the standard layout
   float x[8];
   load_row<8>(x, xrow, lane, d, vec_x);
 #pragma unroll
   for (int e = 0; e < 8; ++e) sh.x[lane * 8 + e] = x[e];
-  // distinct candidates in first-occurrence order
-  sh.raw[lane] = cv;
+  // distinct candidates in first-occurrence order (own first); fe: the first
+  // entry holding the lane's cluster
+  const int mine = (cv >= 0 && !(skip && lane > 0)) ? cv : -1;
+  sh.raw[lane] = mine;
   wave_lds_sync();
-  bool first = cv >= 0;
-  if (!dense) {
-#pragma unroll 8
-    for (int e = 0; e < 64; ++e) first = first && !(e < lane && sh.raw[e] == cv);
+  int fe = mine >= 0 ? lane : -1;
+  if (!dense && mine >= 0) {
+    for (int e = lane - 1; e >= 0; --e)
+      if (sh.raw[e] == mine) fe = e;
   }
-  const uint64_t fm = __ballot(first);
+  const uint64_t fm = __ballot(fe == lane);
   const int u = __popcll(fm);
-  if (first) sh.cand[__popcll(fm & lanes_below())] = cv;
+  if (fe == lane) sh.cand[__popcll(fm & lanes_below())] = mine;
+  const int myslot = fe >= 0 ? __popcll(fm & ((1ull << fe) - 1ull)) : -1;
   // own centroid: full float32 distance, 64-lane layout
   float b1, b2 = FLT_MAX;
   int q1 = cur;
@@ -94,8 +113,12 @@ __device__ inline int pd_decide(PDWave& sh, const float* __restrict__ xrow, int 
     b1 = group_sum<64>(acc);
   }
   sh.full[lane] = FLT_MAX;
+  sh.lb[lane] = FLT_MAX;
   wave_lds_sync();
-  if (lane == 0) sh.full[0] = b1;
+  if (lane == 0) {
+    sh.full[0] = b1;
+    sh.lb[0] = f32_round_down((double)b1 * (1.0 - rel));
+  }
   wave_lds_sync();
   constexpr int NG = 64 / GL;      // candidates per batch
   constexpr int PL = PD_CHUNK / GL;  // dimensions per lane and chunk
@@ -136,9 +159,15 @@ __device__ inline int pd_decide(PDWave& sh, const float* __restrict__ xrow, int 
         }
       }
       P += gl_sum<GL>(acc);
-      if (alive && (double)P * (1.0 - rel) > ub) alive = false;
+      if (alive && (double)P * (1.0 - rel) > ub) {
+        alive = false;
+        if (jj == 0) sh.lb[slot] = f32_round_down((double)P * (1.0 - rel));
+      }
     }
-    if (alive && jj == 0) sh.full[slot] = P;
+    if (alive && jj == 0) {
+      sh.full[slot] = P;
+      sh.lb[slot] = f32_round_down((double)P * (1.0 - rel));
+    }
     wave_lds_sync();
     // fold the batch's survivors into best / second best, in slot order
     const int hi = min(u, s0 + NG);
@@ -156,30 +185,43 @@ __device__ inline int pd_decide(PDWave& sh, const float* __restrict__ xrow, int 
     }
   }
   const double thr = (double)b1 * (1.0 + rel) / (1.0 - rel) + 1e-30;
-  if ((double)b2 > thr) return q1;
-  // float64 re-evaluation of every survivor inside the margin
-  double m64 = DBL_MAX, cur64 = -1.0;
-  int q64 = -1;
-  for (int t = 0; t < u; ++t) {
-    const float dq = sh.full[t];
-    if (dq == FLT_MAX || (double)dq > thr) continue;
-    const int qq = sh.cand[t];
-    float c[8];
-    load_row<8>(c, C + (int64_t)qq * d, lane, d, vec_c);
-    double acc = 0.0;
+  int res = q1;
+  double dres = (double)b1 * (1.0 + rel) + 1e-30;  // upper bound of the chosen squared distance
+  if ((double)b2 <= thr) {
+    // float64 re-evaluation of every survivor inside the margin
+    double m64 = DBL_MAX, cur64 = -1.0;
+    int q64 = -1;
+    for (int t = 0; t < u; ++t) {
+      const float dq = sh.full[t];
+      if (dq == FLT_MAX || (double)dq > thr) continue;
+      const int qq = sh.cand[t];
+      float c[8];
+      load_row<8>(c, C + (int64_t)qq * d, lane, d, vec_c);
+      double acc = 0.0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const double df = (double)x[e] - (double)c[e];
-      acc = fma(df, df, acc);
+      for (int e = 0; e < 8; ++e) {
+        const double df = (double)x[e] - (double)c[e];
+        acc = fma(df, df, acc);
+      }
+      const double e64 = group_sum<64>(acc);
+      if (qq == cur) cur64 = e64;
+      if (e64 < m64 || (e64 == m64 && qq < q64)) {
+        m64 = e64;
+        q64 = qq;
+      }
     }
-    const double e64 = group_sum<64>(acc);
-    if (qq == cur) cur64 = e64;
-    if (e64 < m64 || (e64 == m64 && qq < q64)) {
-      m64 = e64;
-      q64 = qq;
-    }
+    res = (cur64 >= 0.0 && cur64 == m64) ? cur : q64;
+    dres = m64 * (1.0 + 0x1p-40) + 1e-300;
   }
-  return (cur64 >= 0.0 && cur64 == m64) ? cur : q64;
+  PDResult r;
+  r.label = res;
+  r.u = f32_round_up(sqrt(dres) * (1.0 + 0x1p-50));
+  r.lb = 0.f;
+  if (myslot >= 0 && mine != res) {
+    const float lq = sh.lb[myslot];
+    r.lb = lq == FLT_MAX ? 0.f : f32_round_down(sqrt((double)lq) * (1.0 - 0x1p-50));
+  }
+  return r;
 }
 
 // Candidate label of lane e for sample i (entry 0: own label; 1..kappa:
@@ -206,7 +248,7 @@ __global__ __launch_bounds__(256) void k_assign_pd(
     unsigned long long* __restrict__ moved_acc, unsigned long long* __restrict__ eval_acc,
     const int* __restrict__ order, int nchunks, int pb, double rel, int vec_x, int vec_c,
     const int* __restrict__ job_of, const int* __restrict__ kbase, const uint8_t* __restrict__ act_in,
-    uint8_t* __restrict__ act_out) {
+    uint8_t* __restrict__ act_out, float* __restrict__ bnd_u, float* __restrict__ bnd_lb) {
   __shared__ PDWave sh[4];
   __shared__ unsigned int block_moved, block_eval;
   if (threadIdx.x == 0) {
@@ -247,12 +289,14 @@ __global__ __launch_bounds__(256) void k_assign_pd(
         }
         continue;
       }
-      const int res = pd_decide<GL>(sh[w], X + i * ldx, d, vec_x, C, vec_c, cur, cv, rel, dense);
+      const PDResult r = pd_decide<GL>(sh[w], X + i * ldx, d, vec_x, C, vec_c, cur, cv, rel, dense, false);
+      if (bnd_u && lane <= kappa) bnd_lb[i * (kappa + 1) + lane] = r.lb;
       if (lane == 0) {
-        lab_out[i] = res;
+        lab_out[i] = r.label;
         if (act_out) act_out[i] = 1;
+        if (bnd_u) bnd_u[i] = r.u;
         ++my_eval;
-        if (res != cur) ++my_moved;
+        if (r.label != cur) ++my_moved;
       }
     }
   }
@@ -275,7 +319,8 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
     unsigned long long* __restrict__ moved_acc, unsigned long long* __restrict__ eval_acc,
     const int32_t* __restrict__ list, const int32_t* __restrict__ count, double rel, int vec_x, int vec_c,
     const int* __restrict__ job_of, const int* __restrict__ kbase, uint8_t* __restrict__ act_out,
-    int64_t* __restrict__ n_listed, const int32_t* __restrict__ cdirty) {
+    int64_t* __restrict__ n_listed, const int32_t* __restrict__ cdirty, float* __restrict__ bnd_u,
+    float* __restrict__ bnd_lb, const float* __restrict__ delta) {
   __shared__ PDWave sh[4];
   __shared__ unsigned int block_moved, block_eval;
   if (threadIdx.x == 0) {
@@ -308,23 +353,55 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
       }
       continue;
     }
+    bool skip = false;
+    float lb_drift = 0.f, U_own = 0.f;
     if (!changed && !dense && cdirty) {
       // the same candidates as in the last sweep and none of their
       // centroids changed: the last decision, to stay, stands
-      if (__ballot(cv >= 0 && cdirty[cv] != 0) == 0) {
+      const bool dq = cv >= 0 && cdirty[cv] != 0;
+      if (__ballot(dq) == 0) {
         if (lane == 0) {
           lab_out[i] = cur;
           if (act_out) act_out[i] = 1;
         }
         continue;
       }
+      if (bnd_u) {
+        // drift bounds (triangle inequality): the own centroid moved by at
+        // most delta[cur], the centroid of entry e by at most its delta; an
+        // entry whose lower bound, less its movement, still exceeds the own
+        // centroid's upper bound, plus its movement, is strictly farther
+        const float dv = dq ? delta[cv] : 0.f;
+        const double U = ((double)bnd_u[i] + (double)__shfl(dv, 0, 64)) * (1.0 + 0x1p-50);
+        const double Le = lane <= kappa ? ((double)bnd_lb[i * (kappa + 1) + lane] - (double)dv) * (1.0 - 0x1p-50)
+                                        : 0.0;
+        skip = cv < 0 || cv == cur || Le > U;
+        lb_drift = f32_round_down(Le);
+        U_own = f32_round_up(U);
+        if (__ballot(!skip) == 0) {  // every other cluster is strictly farther: stays
+          if (lane <= kappa) bnd_lb[i * (kappa + 1) + lane] = cv == cur ? 0.f : lb_drift;
+          if (lane == 0) {
+            lab_out[i] = cur;
+            if (act_out) act_out[i] = 1;
+            bnd_u[i] = U_own;
+          }
+          continue;
+        }
+      }
     }
-    const int res = pd_decide<GL>(sh[w], X + i * ldx, d, vec_x, C, vec_c, cur, cv, rel, dense);
+    const PDResult r = pd_decide<GL>(sh[w], X + i * ldx, d, vec_x, C, vec_c, cur, cv, rel, dense, skip);
+    if (bnd_u && lane <= kappa) {
+      // skipped entries keep their drifted bounds (the chosen cluster is at
+      // least as close as the own one, so they remain valid lower bounds)
+      const bool keep = skip && lane > 0 && cv >= 0 && cv != cur && cv != r.label;
+      bnd_lb[i * (kappa + 1) + lane] = keep ? lb_drift : r.lb;
+    }
     if (lane == 0) {
-      lab_out[i] = res;
+      lab_out[i] = r.label;
       if (act_out) act_out[i] = 1;
+      if (bnd_u) bnd_u[i] = r.u;
       ++my_eval;
-      if (res != cur) ++my_moved;
+      if (r.label != cur) ++my_moved;
     }
   }
   if (moved_acc || eval_acc) {
@@ -350,7 +427,10 @@ knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, 
                           int32_t* labels_out, unsigned long long* acc, unsigned long long* eacc,
                           const int32_t* order, const int32_t* job_of, const int32_t* kbase,
                           const uint8_t* act_in, uint8_t* act_out, const int32_t* list, const int32_t* list_count,
-                          int64_t* n_listed, const int32_t* cdirty, int pb) {
+                          int64_t* n_listed, const int32_t* cdirty, int pb, float* bnd_u, float* bnd_lb,
+                          const float* delta) {
+  if ((bnd_u != nullptr) != (bnd_lb != nullptr) || (list && bnd_u && cdirty && !delta))
+    return knnkm_fail(ctx, KNNKM_EINVAL, "knn_assign (wide rows): incomplete drift bounds");
   const bool vec_x = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0) && (d % 4 == 0);
   const bool vec_c = (d % 4 == 0) && ((uintptr_t)C % 16 == 0);
   const double rel = pd_rel();
@@ -358,13 +438,14 @@ knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, 
     const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
     k_assign_list_pd<8><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc,
                                                        eacc, list, list_count, rel, vec_x ? 1 : 0, vec_c ? 1 : 0,
-                                                       job_of, kbase, act_out, n_listed, cdirty);
+                                                       job_of, kbase, act_out, n_listed, cdirty, bnd_u, bnd_lb,
+                                                       delta);
     return knnkm_check(ctx, "knn_assign (wide rows, active set)");
   }
   const int nchunks = (int)((n + pb - 1) / pb);
   const int grid = ((nchunks + 7) / 8) * 8;
   k_assign_pd<8><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc,
                                                 eacc, order, nchunks, pb, rel, vec_x ? 1 : 0, vec_c ? 1 : 0, job_of,
-                                                kbase, act_in, act_out);
+                                                kbase, act_in, act_out, bnd_u, bnd_lb);
   return knnkm_check(ctx, "knn_assign (wide rows)");
 }

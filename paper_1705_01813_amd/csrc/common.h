@@ -127,6 +127,20 @@ __device__ inline float wave_max(float v) {
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
   return v;
 }
+// float32 not below a non-negative double (an upper bound kept in float32):
+// the next float32 up is the next bit pattern for non-negative values
+__device__ inline float f32_round_up(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);
+  return f;
+}
+// float32 not above a non-negative double (0 for v <= 0)
+__device__ inline float f32_round_down(double v) {
+  if (v <= 0.0) return 0.f;
+  float f = (float)v;
+  if ((double)f > v) f = __uint_as_float(__float_as_uint(f) - 1u);
+  return f;
+}
 __device__ inline int lane_id() { return threadIdx.x & (WAVE - 1); }
 __device__ inline uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
 
@@ -183,7 +197,8 @@ knnkm_status ks_label_sort(knnkm_ctx* ctx, const int32_t* labels, int64_t n, int
 // where empty); Iterm[r] = ||D_r||^2 / n_r (0 where empty).
 knnkm_status ks_segsum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        int32_t k, const int32_t* counts, const int32_t* offsets,
-                       const int32_t* members, float* C, double* sums, double* Iterm);
+                       const int32_t* members, float* C, double* sums, double* Iterm,
+                       float* delta = nullptr);
 // Deterministic float64 sum of count values into *out (device).
 knnkm_status ks_sum_f64(knnkm_ctx* ctx, const double* in, int64_t count, double* out);
 // The same with the tile partials (ceil(count/8192) doubles when count >
@@ -203,7 +218,8 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        int64_t* n_eval = nullptr, const uint8_t* act_in = nullptr, uint8_t* act_out = nullptr,
                        int64_t* n_active = nullptr, int32_t* list_count = nullptr,
                        int32_t* list_count_other = nullptr, bool zero_moved = true,
-                       const int32_t* cdirty = nullptr);
+                       const int32_t* cdirty = nullptr, float* bnd_u = nullptr, float* bnd_lb = nullptr,
+                       const float* cdelta = nullptr);
 // Wide rows (256 < d <= 512, kappa <= 63): one wavefront per sample with
 // early-abandoned partial distances.  list != null: the active-set sweep over
 // the listed positions (list_count entries); else a full sweep in `order`
@@ -214,7 +230,8 @@ knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, 
                           int32_t* labels_out, unsigned long long* acc, unsigned long long* eacc,
                           const int32_t* order, const int32_t* job_of, const int32_t* kbase,
                           const uint8_t* act_in, uint8_t* act_out, const int32_t* list, const int32_t* list_count,
-                          int64_t* n_listed, const int32_t* cdirty, int pb);
+                          int64_t* n_listed, const int32_t* cdirty, int pb, float* bnd_u, float* bnd_lb,
+                          const float* delta);
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
                          int32_t* labels);
@@ -253,7 +270,8 @@ knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32
 knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, int32_t* cur,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off,
-                          const int32_t* rev_src, uint8_t* act_out, int32_t* dirty_clear);
+                          const int32_t* rev_src, uint8_t* act_out, int32_t* dirty_clear,
+                          float* delta);
 // Active-set marks of the samples moved between cur and nxt and of the rows
 // listing them (reverse lists of the graph); moved labels copied into cur.
 knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,

@@ -430,6 +430,18 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     return use_act ? (lab == labp ? lcnt : lcnt + 1) : nullptr;
   };
   auto dirty_for = [&](const int32_t* lab) -> int32_t* { return lab == labp ? dirty : dirty2; };
+  // Wide rows: every evaluated sample leaves bounds of its distances (an
+  // upper bound to its centroid, a lower bound to the cluster of each graph
+  // entry) and every update the movement of each changed centroid, so the
+  // clusters that the triangle inequality still rules out need no distance.
+  const bool drift = use_act && ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense;
+  float *bnd_u = nullptr, *bnd_lb = nullptr, *cdelta = nullptr;
+  if (drift) {
+    bnd_u = (float*)knnkm_ws(ctx, "fit_bnd_u", sizeof(float) * (size_t)n);
+    bnd_lb = (float*)knnkm_ws(ctx, "fit_bnd_lb", sizeof(float) * (size_t)n * (kappa + 1));
+    cdelta = (float*)knnkm_ws(ctx, "fit_delta", sizeof(float) * (size_t)K);
+    if (!bnd_u || !bnd_lb || !cdelta) return KNNKM_ENOMEM;
+  }
   mark(3);
 
   // one sweep: assignment, update, distortion of every job
@@ -439,7 +451,8 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     // or by the bookkeeping kernel (graph replays)
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
                      J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT, ev, first ? nullptr : act_for(cu),
-                     act_for(nx), ac, cnt_for(cu), cnt_for(nx), false, first ? nullptr : dirty_for(cu));
+                     act_for(nx), ac, cnt_for(cu), cnt_for(nx), false, first ? nullptr : dirty_for(cu), bnd_u,
+                     bnd_lb, first ? nullptr : cdelta);
   };
   // The first sweep moves a large share of the samples away from the
   // initial partition: its update rebuilds the sums from a label sort and
@@ -448,7 +461,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   auto update = [&](int32_t* cu, const int32_t* nx, double* tr, bool full, const int64_t* mv) -> knnkm_status {
     if (full) {
       KNNKM_TRY(ks_label_sort(ctx, nx, n, K, counts, off, mem));
-      KNNKM_TRY(ks_segsum(ctx, Xp, n, d, d, K, counts, off, mem, C, sums0, Iterm));
+      KNNKM_TRY(ks_segsum(ctx, Xp, n, d, d, K, counts, off, mem, C, sums0, Iterm, cdelta));
       KNNKM_TRY(ks_fx_from_f64(ctx, sums0, K, d, cs, Dfx));
       // the moves' marks, or every row once the moved samples' reverse
       // lists (kappa entries each on average) would cover n
@@ -459,7 +472,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(cu), K, 0));
     } else {
       KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty_for(nx), C, Iterm, rev_off, rev_src,
-                             act_for(nx), dirty_for(cu)));
+                             act_for(nx), dirty_for(cu), cdelta));
     }
     k_range_trace<<<m, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, tr);
     return knnkm_check(ctx, "fit iteration");

@@ -317,22 +317,33 @@ __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict_
                                                      const int32_t* __restrict__ counts,
                                                      const int32_t* __restrict__ dirty,
                                                      int32_t* __restrict__ dirty_clear, float* __restrict__ C,
-                                                     double* __restrict__ Iterm) {
+                                                     double* __restrict__ Iterm, float* __restrict__ delta) {
   const int lane = threadIdx.x & 63;
   for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < K; r += (int64_t)gridDim.x * 4) {
     if (lane == 0) dirty_clear[r] = 0;
     if (!dirty[r]) continue;  // wave-uniform
     const int cnt = counts[r];
     const int s = cs[r];
-    double sq = 0.0;
+    double sq = 0.0, mv = 0.0;
     for (int t = lane; t < d; t += 64) {
       const int64_t e = r * d + t;
       const double v = fx_to_double(D[2 * e + 1], D[2 * e], s);
-      if (cnt > 0) C[e] = (float)(v / (double)cnt);
+      if (cnt > 0) {
+        const float c = (float)(v / (double)cnt);
+        if (delta) {
+          const double df = (double)c - (double)C[e];  // exact: two float32 values
+          mv = fma(df, df, mv);
+        }
+        C[e] = c;
+      }
       sq = fma(v, v, sq);
     }
     sq = wave_sum(sq);
     if (lane == 0) Iterm[r] = cnt > 0 ? sq / (double)cnt : 0.0;
+    if (delta) {
+      mv = wave_sum(mv);
+      if (lane == 0) delta[r] = f32_round_up(sqrt(mv) * (1.0 + 0x1p-40));
+    }
   }
 }
 
@@ -381,7 +392,7 @@ knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32
 knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, int32_t* cur,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off, const int32_t* rev_src,
-                          uint8_t* act_out, int32_t* dirty_clear) {
+                          uint8_t* act_out, int32_t* dirty_clear, float* delta) {
 #define MV(DD)                                                                                           \
   k_fx_moves<DD><<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty, \
                                                                   rev_off, rev_src, act_out)
@@ -394,7 +405,8 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
   else
     MV(8);
 #undef MV
-  k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, dirty, dirty_clear, C, Iterm);
+  k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, dirty, dirty_clear, C, Iterm,
+                                                                delta);
   return knnkm_check(ctx, "incremental update");
 }
 

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_seg_final(int d, int32_t k, const int32
                                                    const int32_t* __restrict__ chunk_off,
                                                    const double* __restrict__ partial,
                                                    float* __restrict__ C, double* __restrict__ sums,
-                                                   double* __restrict__ Iterm) {
+                                                   double* __restrict__ Iterm, float* __restrict__ delta) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= k) return;
@@ -231,23 +231,36 @@ __global__ __launch_bounds__(256) void k_seg_final(int d, int32_t k, const int32
       if (dim < d) s[t] += pr[dim];
     }
   }
-  double sq = 0.0;
+  double sq = 0.0, mv = 0.0;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     int dim = lane + 64 * t;
     if (dim < d) {
       if (sums) sums[r * d + dim] = s[t];
-      if (cnt > 0) C[r * d + dim] = (float)(s[t] / (double)cnt);
+      if (cnt > 0) {
+        const float c = (float)(s[t] / (double)cnt);
+        if (delta) {
+          const double df = (double)c - (double)C[r * d + dim];  // exact: two float32 values
+          mv = fma(df, df, mv);
+        }
+        C[r * d + dim] = c;
+      }
       sq = fma(s[t], s[t], sq);
     }
   }
   sq = wave_sum(sq);
   if (lane == 0 && Iterm) Iterm[r] = cnt > 0 ? sq / (double)cnt : 0.0;
+  // movement of the centroid (upper bound, float32), for the drift bounds
+  // of the assignment
+  if (delta) {
+    mv = wave_sum(mv);
+    if (lane == 0) delta[r] = f32_round_up(sqrt(mv) * (1.0 + 0x1p-40));
+  }
 }
 
 knnkm_status ks_segsum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        int32_t k, const int32_t* counts, const int32_t* offsets,
-                       const int32_t* members, float* C, double* sums, double* Iterm) {
+                       const int32_t* members, float* C, double* sums, double* Iterm, float* delta) {
   KNNKM_WS(ctx, cc, int32_t, "seg_chunk_off", (int64_t)k + 1);
   k_chunk_counts<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, cc);
   KNNKM_TRY(knnkm_check(ctx, "chunk counts"));
@@ -259,7 +272,7 @@ knnkm_status ks_segsum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
 #define SEG(TT)                                                                                        \
   k_seg_partial<TT><<<gp, 256, 0, ctx->stream>>>(X, d, ldx, k, offsets, members, cc, max_chunks,      \
                                                  partial);                                             \
-  k_seg_final<TT><<<gf, 256, 0, ctx->stream>>>(d, k, counts, cc, partial, C, sums, Iterm)
+  k_seg_final<TT><<<gf, 256, 0, ctx->stream>>>(d, k, counts, cc, partial, C, sums, Iterm, delta)
   switch (T) {
     case 1: SEG(1); break;
     case 2: SEG(2); break;
