@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libknnkm.so")
 OBJ = os.path.join(PKG, "_build")
-SOURCES = ["ctx.hip", "assign.hip", "assign_pd.hip", "update.hip", "twomeans.hip", "graph.hip", "drivers.hip",
+SOURCES = ["ctx.hip", "assign.hip", "assign_pd.hip", "refine_exact.hip", "update.hip", "twomeans.hip", "graph.hip", "drivers.hip",
            "server.hip", "incr.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

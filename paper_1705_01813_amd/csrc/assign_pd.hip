@@ -79,11 +79,14 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
                                      const float* __restrict__ C, bool vec_c, int cur, int cv, double rel,
                                      bool dense, bool skip) {
   const int lane = threadIdx.x & 63;
-  // the row into LDS (lane j: dims [8j, 8j+8)) and the standard layout
-  float x[8];
-  load_row<8>(x, xrow, lane, d, vec_x);
+  // the row into LDS (lane j: dims [8j, 8j+8), read back by the same lane
+  // where the 64-lane layout is used)
+  {
+    float x[8];
+    load_row<8>(x, xrow, lane, d, vec_x);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) sh.x[lane * 8 + e] = x[e];
+    for (int e = 0; e < 8; ++e) sh.x[lane * 8 + e] = x[e];
+  }
   // distinct candidates in first-occurrence order (own first); fe: the first
   // entry holding the lane's cluster
   const int mine = (cv >= 0 && !(skip && lane > 0)) ? cv : -1;
@@ -107,7 +110,7 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
     float acc = 0.f;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const float df = x[e] - c[e];
+      const float df = sh.x[lane * 8 + e] - c[e];
       acc = fmaf(df, df, acc);
     }
     b1 = group_sum<64>(acc);
@@ -200,7 +203,7 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
       double acc = 0.0;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const double df = (double)x[e] - (double)c[e];
+        const double df = (double)sh.x[lane * 8 + e] - (double)c[e];
         acc = fma(df, df, acc);
       }
       const double e64 = group_sum<64>(acc);
@@ -310,9 +313,13 @@ __global__ __launch_bounds__(256) void k_assign_pd(
 }
 
 // Active-set sweep over the listed positions (entries as k_act_compact writes
-// them: position, bit 31 = own or a neighbour's label changed), one listed
-// sample per wavefront, grid-stride.  Same outputs as k_assign_list.
-template <int GL>
+// them: position, bit 31 = own or a neighbour's label changed), grid-stride,
+// NS listed samples per wavefront and step: the loads of each dependent level
+// (list entries; own labels and graph rows; neighbour labels; changed flags
+// of the candidate clusters) are issued for all NS samples before any is
+// used, then the samples are decided one after the other.  Same outputs as
+// k_assign_list.
+template <int GL, int NS>
 __global__ __launch_bounds__(256) void k_assign_list_pd(
     const float* __restrict__ X, int d, int64_t ldx, const float* __restrict__ C, int k,
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
@@ -332,76 +339,125 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
   const int cnt = *count;
   if (n_listed && blockIdx.x == 0 && threadIdx.x == 0) *n_listed = cnt;
   unsigned int my_moved = 0, my_eval = 0;
-  for (int li = blockIdx.x * 4 + w; li < cnt; li += gridDim.x * 4) {
-    const uint32_t ent = (uint32_t)list[li];
-    const bool changed = (ent >> 31) != 0;
-    const int64_t i = (int64_t)(ent & 0x7FFFFFFFu);
-    const int cur = lab_in[i];
-    int kb = 0, kc = k;
-    if (job_of) {
-      const int q = job_of[i];
-      kb = kbase[q];
-      kc = kbase[q + 1] - kb;
+  const int stride = gridDim.x * 4 * NS;
+  for (int li0 = (blockIdx.x * 4 + w) * NS; li0 < cnt; li0 += stride) {
+    bool live[NS], changed[NS], dense[NS];
+    int64_t ii[NS];
+    int cur[NS], kb[NS], kc[NS], nb[NS], cv[NS];
+    bool dq[NS];
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      live[p] = li0 + p < cnt;  // wave-uniform
+      const uint32_t ent = live[p] ? (uint32_t)list[li0 + p] : 0u;
+      changed[p] = (ent >> 31) != 0;
+      ii[p] = (int64_t)(ent & 0x7FFFFFFFu);
     }
-    const bool dense = kappa >= kc;
-    const int cv = pd_candidate(lane, i, cur, G, kappa, lab_in, dense, kb, kc);
-    const bool other = cv >= 0 && cv != cur;
-    if (!dense && __ballot(other) == 0) {
-      if (lane == 0) {
-        lab_out[i] = cur;
-        if (act_out) act_out[i] = 0;
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      const int64_t i = ii[p];
+      cur[p] = live[p] ? lab_in[i] : 0;
+      kb[p] = 0;
+      kc[p] = k;
+      if (job_of && live[p]) {
+        const int q = job_of[i];
+        kb[p] = kbase[q];
+        kc[p] = kbase[q + 1] - kb[p];
       }
-      continue;
+      nb[p] = (live[p] && lane >= 1 && lane <= kappa) ? G[i * kappa + (lane - 1)] : -1;
     }
-    bool skip = false;
-    float lb_drift = 0.f, U_own = 0.f;
-    if (!changed && !dense && cdirty) {
-      // the same candidates as in the last sweep and none of their
-      // centroids changed: the last decision, to stay, stands
-      const bool dq = cv >= 0 && cdirty[cv] != 0;
-      if (__ballot(dq) == 0) {
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      dense[p] = kappa >= kc[p];
+      if (!live[p]) {
+        cv[p] = -1;
+      } else if (lane == 0) {
+        cv[p] = cur[p];
+      } else if (dense[p]) {
+        const int v = kb[p] + lane - 1;
+        cv[p] = lane >= kc[p] ? -1 : (v < cur[p] ? v : v + 1);
+      } else {
+        cv[p] = nb[p] >= 0 ? lab_in[nb[p]] : -1;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      const bool look = live[p] && !changed[p] && !dense[p] && cdirty && cv[p] >= 0;
+      dq[p] = look && cdirty[cv[p]] != 0;
+    }
+    // the decisions, one sample after the other (one copy of the decision
+    // code: the sample's values are selected, not indexed)
+    auto pick = [&](const auto(&a)[NS], int p) {
+      auto v = a[0];
+#pragma unroll
+      for (int q = 1; q < NS; ++q)
+        if (p == q) v = a[q];
+      return v;
+    };
+#pragma unroll 1
+    for (int p = 0; p < NS; ++p) {
+      if (!pick(live, p)) continue;  // wave-uniform
+      const int64_t i = pick(ii, p);
+      const int c = pick(cv, p), own = pick(cur, p);
+      const bool chg = pick(changed, p), dn = pick(dense, p), dirt = pick(dq, p);
+      const bool other = c >= 0 && c != own;
+      if (!dn && __ballot(other) == 0) {
         if (lane == 0) {
-          lab_out[i] = cur;
-          if (act_out) act_out[i] = 1;
+          lab_out[i] = own;
+          if (act_out) act_out[i] = 0;
         }
         continue;
       }
-      if (bnd_u) {
-        // drift bounds (triangle inequality): the own centroid moved by at
-        // most delta[cur], the centroid of entry e by at most its delta; an
-        // entry whose lower bound, less its movement, still exceeds the own
-        // centroid's upper bound, plus its movement, is strictly farther
-        const float dv = dq ? delta[cv] : 0.f;
-        const double U = ((double)bnd_u[i] + (double)__shfl(dv, 0, 64)) * (1.0 + 0x1p-50);
-        const double Le = lane <= kappa ? ((double)bnd_lb[i * (kappa + 1) + lane] - (double)dv) * (1.0 - 0x1p-50)
-                                        : 0.0;
-        skip = cv < 0 || cv == cur || Le > U;
-        lb_drift = f32_round_down(Le);
-        U_own = f32_round_up(U);
-        if (__ballot(!skip) == 0) {  // every other cluster is strictly farther: stays
-          if (lane <= kappa) bnd_lb[i * (kappa + 1) + lane] = cv == cur ? 0.f : lb_drift;
+      bool skip = false;
+      float lb_drift = 0.f;
+      if (!chg && !dn && cdirty) {
+        // the same candidates as in the last sweep and none of their
+        // centroids changed: the last decision, to stay, stands
+        if (__ballot(dirt) == 0) {
           if (lane == 0) {
-            lab_out[i] = cur;
+            lab_out[i] = own;
             if (act_out) act_out[i] = 1;
-            bnd_u[i] = U_own;
           }
           continue;
         }
+        if (bnd_u) {
+          // drift bounds (triangle inequality): the own centroid moved by at
+          // most delta[own], the centroid of entry e by at most its delta; an
+          // entry whose lower bound, less its movement, still exceeds the own
+          // centroid's upper bound, plus its movement, is strictly farther
+          // (movements are read for the changed clusters only: most of a late
+          // sweep's candidates are unchanged, and each read is a scattered line)
+          const float de = dirt ? delta[c] : 0.f;
+          const float u_p = bnd_u[i];
+          const float lb_p = lane <= kappa ? bnd_lb[i * (kappa + 1) + lane] : 0.f;
+          const double U = ((double)u_p + (double)__shfl(de, 0, 64)) * (1.0 + 0x1p-50);
+          const double Le = lane <= kappa ? ((double)lb_p - (double)de) * (1.0 - 0x1p-50) : 0.0;
+          skip = c < 0 || c == own || Le > U;
+          lb_drift = f32_round_down(Le);
+          if (__ballot(!skip) == 0) {  // every other cluster is strictly farther: stays
+            if (lane <= kappa) bnd_lb[i * (kappa + 1) + lane] = c == own ? 0.f : lb_drift;
+            if (lane == 0) {
+              lab_out[i] = own;
+              if (act_out) act_out[i] = 1;
+              bnd_u[i] = f32_round_up(U);
+            }
+            continue;
+          }
+        }
       }
-    }
-    const PDResult r = pd_decide<GL>(sh[w], X + i * ldx, d, vec_x, C, vec_c, cur, cv, rel, dense, skip);
-    if (bnd_u && lane <= kappa) {
-      // skipped entries keep their drifted bounds (the chosen cluster is at
-      // least as close as the own one, so they remain valid lower bounds)
-      const bool keep = skip && lane > 0 && cv >= 0 && cv != cur && cv != r.label;
-      bnd_lb[i * (kappa + 1) + lane] = keep ? lb_drift : r.lb;
-    }
-    if (lane == 0) {
-      lab_out[i] = r.label;
-      if (act_out) act_out[i] = 1;
-      if (bnd_u) bnd_u[i] = r.u;
-      ++my_eval;
-      if (r.label != cur) ++my_moved;
+      const PDResult r = pd_decide<GL>(sh[w], X + i * ldx, d, vec_x, C, vec_c, own, c, rel, dn, skip);
+      if (bnd_u && lane <= kappa) {
+        // skipped entries keep their drifted bounds (the chosen cluster is at
+        // least as close as the own one, so they remain valid lower bounds)
+        const bool keep = skip && lane > 0 && c >= 0 && c != own && c != r.label;
+        bnd_lb[i * (kappa + 1) + lane] = keep ? lb_drift : r.lb;
+      }
+      if (lane == 0) {
+        lab_out[i] = r.label;
+        if (act_out) act_out[i] = 1;
+        if (bnd_u) bnd_u[i] = r.u;
+        ++my_eval;
+        if (r.label != own) ++my_moved;
+      }
     }
   }
   if (moved_acc || eval_acc) {
@@ -436,10 +492,18 @@ knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, 
   const double rel = pd_rel();
   if (list) {
     const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
-    k_assign_list_pd<8><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc,
-                                                       eacc, list, list_count, rel, vec_x ? 1 : 0, vec_c ? 1 : 0,
-                                                       job_of, kbase, act_out, n_listed, cdirty, bnd_u, bnd_lb,
-                                                       delta);
+    // listed samples interleaved per wavefront: 2 unless the context fixes
+    // the assignment shape to one sample per group
+#define LPD(NS)                                                                                               \
+  k_assign_list_pd<8, NS><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
+                                                        acc, eacc, list, list_count, rel, vec_x ? 1 : 0,      \
+                                                        vec_c ? 1 : 0, job_of, kbase, act_out, n_listed,      \
+                                                        cdirty, bnd_u, bnd_lb, delta)
+    if (ctx->assign_gs == 1)
+      LPD(1);
+    else
+      LPD(2);
+#undef LPD
     return knnkm_check(ctx, "knn_assign (wide rows, active set)");
   }
   const int nchunks = (int)((n + pb - 1) / pb);

@@ -224,6 +224,11 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
 // early-abandoned partial distances.  list != null: the active-set sweep over
 // the listed positions (list_count entries); else a full sweep in `order`
 // (pb positions per block).  Same decisions and flags as the narrow kernels.
+// Exact all-pairs refinement of the clusters with smin < s <= smax members
+// (smax <= 128; one block per cluster, rows of the graph updated in place).
+knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, int32_t kappa, int32_t k,
+                             const int32_t* offsets, const int32_t* members, int32_t smin, int32_t smax,
+                             bool vec, int32_t* G_ids, float* G_d2);
 bool ks_assign_pd_ok(int32_t d, int32_t kappa);
 knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, const float* C,
                           int32_t k, const int32_t* G_ids, int32_t kappa, const int32_t* labels_in,

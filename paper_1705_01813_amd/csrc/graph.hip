@@ -19,9 +19,11 @@
 //        LDS by row groups, rounded to float32);
 //     5. each row (one wave) drops survivors already in its list (visited
 //        pairs) and merges the rest by per-lane ranks, writing the graph row.
-//   Larger clusters go through a screen over 64 x 64 member blocks and a
-//   per-row merge (below); clusters too large for that item count fall back
-//   to row blocks walking the cluster's column blocks.  Every row belongs to
+//   Clusters larger than a tile and of at most 128 members get the exact
+//   distances of all their pairs (refine_exact.hip); larger ones go through a
+//   screen over 64 x 64 member blocks and a per-row merge (below); clusters
+//   too large for that item count fall back to row blocks walking the
+//   cluster's column blocks.  Every row belongs to
 //   exactly one cluster, so rows are updated without atomics.  Both precisions
 //   produce the same graph: the screen only removes pairs that provably cannot
 //   enter, and a row's result is the kappa smallest (d2, id) of its old list
@@ -773,6 +775,8 @@ static size_t refine_tile_lds(int d, int RB, bool single, int kappa) {
 }
 
 #define LDS_BUDGET (160 * 1024)
+// clusters larger than one tile and at most this size: exact all-pairs kernel
+#define RX_MAX 128
 
 // Largest tile edge in {64, 32, 16} whose layout fits in LDS (0: none).
 static int pick_rb(int d, bool single, int kappa) {
@@ -856,7 +860,9 @@ knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   const int64_t denom = n / SC_RB + k + 1;
   const int64_t t_max = std::max<int64_t>(1, std::min<int64_t>(46340, INT32_MAX / denom));
   const int hi = (int)std::min<int64_t>(t_max * SC_RB, INT32_MAX);
-  k_screen_items<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, rb1, hi, items);
+  // clusters of rb1 < s <= RX_MAX: exact all-pairs kernel (below)
+  const int lo_screen = std::max(rb1, RX_MAX);
+  k_screen_items<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, lo_screen, hi, items);
   k_row_blocks<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, hi, rb2, wb);
   KNNKM_TRY(knnkm_check(ctx, "refine blocks"));
   KNNKM_TRY(ks_scan_exclusive(ctx, items, items, k, true));
@@ -901,6 +907,8 @@ knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
 #undef RM
   }
   KNNKM_TRY(knnkm_check(ctx, "graph refine merge"));
+  if (rb1 < RX_MAX)
+    KNNKM_TRY(ks_refine_exact(ctx, X, d, ldx, kappa, k, off, mem, rb1, RX_MAX, vec, G_ids, G_d2));
 #define RF(BF, LL, VV)                                                                                    \
   return launch_refine<BF, LL, VV>(ctx, X, n, d, ldx, dpad, kappa, k, off, mem, wb, rb1, rb2, err_c, vec, \
                                    G_ids, G_d2)

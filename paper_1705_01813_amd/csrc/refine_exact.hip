@@ -1,0 +1,250 @@
+// Exhaustive comparison inside mid-sized clusters (Alg. 3 inner loops) with
+// exact keys for every pair: one block of 256 threads per cluster of
+// smin < s <= SMAX members (SMAX = 64 or 128).
+//
+// At the cluster sizes graph construction produces (about xi = 50 members)
+// a screen of the Gram block leaves too many survivors for a separate exact
+// re-rank to pay off, so every pair gets its key here:
+//  1. the members' rows stream through LDS in slices (float32, transposed,
+//     double-buffered: the next slice is in registers while the current one
+//     is used), and the float64 Gram block G = X_S X_S^T of the cluster is
+//     accumulated on MFMA (v_mfma_f64_16x16x4, the 16 x 16 tiles of the
+//     upper triangle spread over the four wavefronts);
+//  2. d2 = G_ii + G_jj - 2 G_ij in float64, with a rigorous bound of its
+//     error; its float32 rounding is kept when the whole error interval
+//     rounds to the same float32 value -- that value is then the float32
+//     rounding of the exact squared distance, which the direct float64
+//     difference also gives -- and otherwise (near ties with a rounding
+//     boundary, near-duplicate rows, where G_ii + G_jj cancels) the pair is
+//     recomputed by a float64 direct difference over its two rows;
+//  3. one wavefront per member merges the cluster's other members that are
+//     not yet in its list, keeping the kappa smallest (d2, id) -- the same
+//     list as any other order of comparison (merge.h).
+#include <cfloat>
+#include <cmath>
+
+#include "common.h"
+#include "merge.h"
+
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// float32 neighbours of a finite positive float32 value
+__device__ inline float f32_next(float f) { return __uint_as_float(__float_as_uint(f) + 1u); }
+__device__ inline float f32_prev(float f) { return __uint_as_float(__float_as_uint(f) - 1u); }
+
+constexpr int RX_UNC_CAP = 256;  // uncertified pairs listed per cluster
+
+template <int SMAX, int SL>
+__global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X, int d, int64_t ldx, int kappa,
+                                                     int32_t k, const int32_t* __restrict__ offsets,
+                                                     const int32_t* __restrict__ members, int smin, int vec,
+                                                     int32_t* __restrict__ G_ids, float* __restrict__ G_d2) {
+  constexpr int TG = SMAX / 16;              // tile rows of the Gram block
+  constexpr int MAXT = TG * (TG + 1) / 2;    // tiles of its upper triangle
+  constexpr int TPW = (MAXT + 3) / 4;        // tiles per wavefront
+  constexpr int NC = SMAX / 64;              // candidates per lane in the merge
+  constexpr int NF4 = SMAX * (SL / 4);       // float4 per slice
+  constexpr int PER = (NF4 + 255) / 256;     // per thread
+  // slice row stride: the four k rows an MFMA operand read touches start 16
+  // banks apart
+  constexpr int XS = SMAX + 16;
+  static_assert(2 * SL * XS >= 8 * KNNKM_MAX_KAPPA, "merge scratch reuses the slice buffers");
+  __shared__ __align__(16) float xs[2 * SL * XS];  // two slices, dimension-major
+  __shared__ float km[SMAX * SMAX];                  // keys
+  __shared__ double nrm[SMAX];                       // diagonal of the Gram block
+  __shared__ int32_t ids[SMAX];
+  __shared__ int nunc;                 // uncertified pairs
+  __shared__ int16_t unc[RX_UNC_CAP];  // the first of them, r * SMAX + c
+  const int cl = blockIdx.x;
+  if (cl >= k) return;
+  const int c0 = offsets[cl];
+  const int s = offsets[cl + 1] - c0;
+  if (s <= smin || s > SMAX || s < 2) return;  // block-uniform
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid < SMAX) ids[tid] = tid < s ? members[c0 + tid] : -1;
+  if (tid == 0) nunc = 0;
+  // this wavefront's tiles: the active ones (I <= J < ceil(s/16)) in
+  // row-major order, every fourth
+  const int ta = (s + 15) / 16;
+  const int nta = ta * (ta + 1) / 2;
+  int ti[TPW], tj[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    int t = w + 4 * q, a = 0;
+    if (t >= nta) t = -1;
+    while (t >= 0 && t >= ta - a) {
+      t -= ta - a;
+      ++a;
+    }
+    ti[q] = t < 0 ? -1 : a;
+    tj[q] = t < 0 ? -1 : a + t;
+  }
+  d4_t acc[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+  __syncthreads();
+  float4 nxt[PER];
+  auto fetch = [&](int t0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e % SMAX, t = t0 + 4 * (e / SMAX);
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < NF4 && r < s && t < d) {
+        const float* row = X + (int64_t)ids[r] * ldx;
+        if (vec) {
+          v = *reinterpret_cast<const float4*>(row + t);
+        } else {
+          v.x = row[t];
+          v.y = t + 1 < d ? row[t + 1] : 0.f;
+          v.z = t + 2 < d ? row[t + 2] : 0.f;
+          v.w = t + 3 < d ? row[t + 3] : 0.f;
+        }
+      }
+      nxt[u] = v;
+    }
+  };
+  auto store = [&](float* buf) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      if (e >= NF4) continue;
+      const int r = e % SMAX, q4 = e / SMAX;
+      buf[(4 * q4) * XS + r] = nxt[u].x;
+      buf[(4 * q4 + 1) * XS + r] = nxt[u].y;
+      buf[(4 * q4 + 2) * XS + r] = nxt[u].z;
+      buf[(4 * q4 + 3) * XS + r] = nxt[u].w;
+    }
+  };
+  fetch(0);
+  store(xs);
+  __syncthreads();
+  int cur = 0;
+  const int kr = lane >> 4, rc = lane & 15;  // MFMA operands: k row, tile row or column
+  for (int t0 = 0; t0 < d; t0 += SL) {
+    const bool more = t0 + SL < d;
+    if (more) fetch(t0 + SL);
+    const float* buf = xs + cur * (SL * XS);
+#pragma unroll
+    for (int kk = 0; kk < SL; kk += 4) {
+      const float* kb = buf + (kk + kr) * XS + rc;
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        if (ti[q] < 0) continue;  // wave-uniform
+        const double a = (double)kb[16 * ti[q]];
+        const double b = (double)kb[16 * tj[q]];
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+      }
+    }
+    if (more) store(xs + (cur ^ 1) * (SL * XS));
+    __syncthreads();
+    cur ^= 1;
+  }
+  // the output of a tile: lane l holds rows (l >> 4) + 4v, column l & 15
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    if (ti[q] < 0 || ti[q] != tj[q]) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (kr + 4 * v == rc) nrm[16 * ti[q] + rc] = acc[q][v];
+  }
+  __syncthreads();
+  // keys; an uncertified one is marked and recomputed below.  Error of d2
+  // (float64 Gram expansion over K summed products): at most
+  // (2K + 16) 2^-53 (G_ii + G_jj).
+  const double gam = (2.0 * (double)((d + SL - 1) / SL * SL) + 16.0) * 0x1p-53;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    if (ti[q] < 0) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * ti[q] + kr + 4 * v, c = 16 * tj[q] + rc;
+      if (r < c && c < s) {
+        const double nn = nrm[r] + nrm[c];
+        const double D = nn - 2.0 * acc[q][v];
+        const double E = gam * nn + 1e-300;
+        const float f = (float)D;
+        bool ok = D - E > 0.0 && f > 0.f && f < FLT_MAX;
+        if (ok) {
+          const double lo = 0.5 * ((double)f32_prev(f) + (double)f);
+          const double hi = 0.5 * ((double)f + (double)f32_next(f));
+          ok = D - E > lo && D + E < hi;
+        }
+        km[r * SMAX + c] = f;
+        km[c * SMAX + r] = f;
+        if (!ok) {
+          const int u = atomicAdd(&nunc, 1);
+          if (u < RX_UNC_CAP) unc[u] = (int16_t)(r * SMAX + c);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // uncertified pairs: float64 direct difference of the two rows, one
+  // wavefront per pair (lane j: dimensions j, j + 64, ...; fixed order).
+  // Past the list's capacity every pair of the cluster is recomputed.
+  const int nu = nunc;  // block-uniform
+  if (nu > 0) {
+    const int np = nu <= RX_UNC_CAP ? nu : s * s;
+    for (int p = w; p < np; p += 4) {
+      int pr, pc;
+      if (nu <= RX_UNC_CAP) {
+        pr = unc[p] / SMAX;
+        pc = unc[p] % SMAX;
+      } else {
+        pr = p / s;
+        pc = p % s;
+        if (pr >= pc) continue;  // wave-uniform
+      }
+      const float* xa = X + (int64_t)ids[pr] * ldx;
+      const float* xb = X + (int64_t)ids[pc] * ldx;
+      double a = 0.0;
+      for (int t = lane; t < d; t += 64) {
+        const double df = (double)xa[t] - (double)xb[t];
+        a = fma(df, df, a);
+      }
+      a = wave_sum(a);
+      if (lane == 0) {
+        km[pr * SMAX + pc] = (float)a;
+        km[pc * SMAX + pr] = (float)a;
+      }
+    }
+    __syncthreads();
+  }
+  // merge: one wavefront per member; lane l holds candidates l, l + 64, ...
+  for (int r = w; r < s; r += 4) {
+    float ck[NC];
+    int cid[NC];
+    bool valid[NC];
+#pragma unroll
+    for (int h = 0; h < NC; ++h) {
+      const int c = lane + 64 * h;
+      valid[h] = c < s && c != r;
+      ck[h] = valid[h] ? km[r * SMAX + c] : FLT_MAX;
+      cid[h] = valid[h] ? ids[c] : -1;
+    }
+    const int64_t row = (int64_t)ids[r] * kappa;
+    // merge scratch: this wavefront's part of the slice buffers, free now
+    float* mk = xs + 2 * KNNKM_MAX_KAPPA * w;
+    merge_row<NC>(G_d2 + row, G_ids + row, kappa, ck, cid, valid, mk,
+                  reinterpret_cast<int32_t*>(mk + KNNKM_MAX_KAPPA));
+  }
+}
+
+}  // namespace
+
+knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, int32_t kappa, int32_t k,
+                             const int32_t* offsets, const int32_t* members, int32_t smin, int32_t smax,
+                             bool vec, int32_t* G_ids, float* G_d2) {
+  if (smax > 128) return knnkm_fail(ctx, KNNKM_EINVAL, "refine_exact: clusters of at most 128 members");
+  if (k <= 0 || smin >= smax) return KNNKM_OK;
+  if (smin < 64)
+    k_refine_gram<64, 32><<<(unsigned)k, 256, 0, ctx->stream>>>(X, d, ldx, kappa, k, offsets, members, smin,
+                                                             vec ? 1 : 0, G_ids, G_d2);
+  if (smax > 64)
+    k_refine_gram<128, 8><<<(unsigned)k, 256, 0, ctx->stream>>>(X, d, ldx, kappa, k, offsets, members,
+                                                              std::max(smin, 64), vec ? 1 : 0, G_ids, G_d2);
+  return knnkm_check(ctx, "graph refine (exact, mid-sized clusters)");
+}

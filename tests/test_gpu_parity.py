@@ -435,6 +435,11 @@ def test_refine_parity(ctx, precision, n, d, kappa, k):
     got_i, got_d = host(gi), host(gd)
     msg = _graph_diff(got_i, got_d, want_i, want_d, lab)
     assert not msg, msg
+    # the same clusters once more: every pair is now visited or too far, so
+    # no row changes (the visited test of the list update, Alg. 3)
+    knnkm.knnkm_graph_refine(ctx, dev(X), dev(lab), k, precision, gi, gd)
+    msg = _graph_diff(host(gi), host(gd), want_i, want_d, lab)
+    assert not msg, "second pass changed rows: " + msg
 
 
 @pytest.mark.parametrize("precision", [knnkm.FP32, knnkm.BF16_RERANK])
