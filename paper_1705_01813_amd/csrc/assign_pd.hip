@@ -9,14 +9,21 @@
 // gathered centroid row; most candidates are far from the sample, and a sum
 // of squares over the first dimensions already exceeds the distance to the
 // sample's own centroid.  So:
-//  * the candidates are deduplicated in LDS (first occurrence order, own
-//    cluster first) and the own centroid's full float32 distance is computed;
-//  * the other candidates go in batches of 64/GL, GL lanes per candidate:
-//    64 dimensions at a time are added to a running float32 partial sum, and
-//    a candidate is dropped as soon as a rigorous lower bound of its partial
-//    sum exceeds a rigorous upper bound of the best full distance found so far
-//    (the candidate then cannot be the closest nor tie with it); a candidate
-//    that survives every chunk has its full distance;
+//  * every graph entry holding another cluster is a candidate slot (a
+//    cluster held by several entries is evaluated once per entry, with the
+//    same bits each time; at this width that is a few percent of the
+//    entries, less than sorting them out would cost);
+//  * the full float32 distances of the own centroid and of the first slot
+//    (the cluster of the nearest graph entry holding another cluster, the
+//    likeliest to be the closest) are computed first, their loads in flight
+//    together;
+//  * the other candidates advance breadth first, 64 dimensions (a chunk) at a
+//    time, GL lanes per candidate and up to 32 candidates' loads in flight
+//    per wavefront: each chunk adds to a running float32 partial sum, and a
+//    candidate is dropped as soon as a rigorous lower bound of its partial
+//    sum exceeds a rigorous upper bound of the best of those distances (the
+//    candidate then cannot be the closest nor tie with it); one that survives
+//    every chunk has its full distance;
 //  * best and second best over the full distances, and when they are within
 //    the rigorous float32 error margin, float64 re-evaluation of every
 //    survivor inside it with the tie rule, as in the narrow kernels.
@@ -29,13 +36,16 @@
 namespace {
 
 constexpr int PD_CHUNK = 64;  // dimensions per early-abandon step
+constexpr int PD_SB = 4;      // candidate batches whose loads are in flight together
+constexpr int PD_PILOT = 1;   // candidates whose full distance is taken with the own one
 
 struct alignas(16) PDWave {
-  float x[512];      // the sample's row
-  int32_t raw[64];   // candidate labels by graph entry (0 = own)
-  int32_t cand[64];  // distinct candidates, own first
-  float full[64];    // float32 full distance of candidate slot (FLT_MAX: dropped)
-  float lb[64];      // lower bound of the squared distance of candidate slot
+  float x[512];       // the sample's row
+  int32_t cand[64];   // cluster of slot s (slot 0: the own one)
+  float full[64];     // float32 full distance of slot (FLT_MAX: dropped)
+  float lb[64];       // lower bound of the squared distance of slot
+  float part[64];     // running partial sum of slot
+  int32_t al[2][64];  // slots alive at this chunk and at the next
 };
 
 // Result of one decision: the label; u, an upper bound of the distance (not
@@ -78,6 +88,7 @@ template <int GL>
 __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow, int d, bool vec_x,
                                      const float* __restrict__ C, bool vec_c, int cur, int cv, double rel,
                                      bool dense, bool skip) {
+  (void)dense;
   const int lane = threadIdx.x & 63;
   // the row into LDS (lane j: dims [8j, 8j+8), read back by the same lane
   // where the 64-lane layout is used)
@@ -87,104 +98,181 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
 #pragma unroll
     for (int e = 0; e < 8; ++e) sh.x[lane * 8 + e] = x[e];
   }
-  // distinct candidates in first-occurrence order (own first); fe: the first
-  // entry holding the lane's cluster
+  // slots: 0 the own cluster, then the entries holding another one in entry
+  // order; an entry holding the own cluster maps to slot 0
   const int mine = (cv >= 0 && !(skip && lane > 0)) ? cv : -1;
-  sh.raw[lane] = mine;
-  wave_lds_sync();
-  int fe = mine >= 0 ? lane : -1;
-  if (!dense && mine >= 0) {
-    for (int e = lane - 1; e >= 0; --e)
-      if (sh.raw[e] == mine) fe = e;
-  }
-  const uint64_t fm = __ballot(fe == lane);
-  const int u = __popcll(fm);
-  if (fe == lane) sh.cand[__popcll(fm & lanes_below())] = mine;
-  const int myslot = fe >= 0 ? __popcll(fm & ((1ull << fe) - 1ull)) : -1;
-  // own centroid: full float32 distance, 64-lane layout
-  float b1, b2 = FLT_MAX;
-  int q1 = cur;
-  {
-    float c[8];
-    load_row<8>(c, C + (int64_t)cur * d, lane, d, vec_c);
-    float acc = 0.f;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float df = sh.x[lane * 8 + e] - c[e];
-      acc = fmaf(df, df, acc);
-    }
-    b1 = group_sum<64>(acc);
-  }
+  const bool isc = lane > 0 && mine >= 0 && mine != cur;
+  const uint64_t cm = __ballot(isc);
+  const int A0 = __popcll(cm);
+  const int myslot = mine < 0 ? -1 : (isc ? 1 + __popcll(cm & lanes_below()) : 0);
   sh.full[lane] = FLT_MAX;
   sh.lb[lane] = FLT_MAX;
-  wave_lds_sync();
-  if (lane == 0) {
-    sh.full[0] = b1;
-    sh.lb[0] = f32_round_down((double)b1 * (1.0 - rel));
+  sh.part[lane] = 0.f;
+  if (isc) {
+    sh.cand[myslot] = mine;
+    sh.al[0][myslot - 1] = myslot;
   }
-  wave_lds_sync();
-  constexpr int NG = 64 / GL;      // candidates per batch
-  constexpr int PL = PD_CHUNK / GL;  // dimensions per lane and chunk
-  const int g = lane / GL, jj = lane % GL;
-  const int nch = (d + PD_CHUNK - 1) / PD_CHUNK;
-  for (int s0 = 1; s0 < u; s0 += NG) {
-    const int slot = s0 + g;
-    bool alive = slot < u;
-    const int q = alive ? sh.cand[slot] : 0;
-    const float* cr = C + (int64_t)q * d;
-    const double ub = (double)b1 * (1.0 + rel) + 1e-30;
-    float P = 0.f;
-    for (int ch = 0; ch < nch; ++ch) {
-      if (__ballot(alive) == 0) break;
-      const int base = ch * PD_CHUNK + jj * PL;
-      float acc = 0.f;
-      if (alive) {
+  // full float32 distances (64-lane layout, loads in flight together) of
+  // the own centroid and of the first PD_PILOT candidate slots, the clusters
+  // of the nearest graph entries and the likeliest to be the closest: the
+  // bound the other candidates are dropped against is then tight from the
+  // start
+  const int np = min(A0, PD_PILOT);
+  int qp[1 + PD_PILOT];
+  qp[0] = cur;
+  {
+    uint64_t M = cm;
 #pragma unroll
-        for (int e = 0; e < PL; e += 4) {
-          float4 cq;
-          if (vec_c && base + e < d) {
-            cq = *reinterpret_cast<const float4*>(cr + base + e);
-          } else {
-            cq.x = base + e < d ? cr[base + e] : 0.f;
-            cq.y = base + e + 1 < d ? cr[base + e + 1] : 0.f;
-            cq.z = base + e + 2 < d ? cr[base + e + 2] : 0.f;
-            cq.w = base + e + 3 < d ? cr[base + e + 3] : 0.f;
-          }
-          const float4 xq = *reinterpret_cast<const float4*>(&sh.x[base + e]);
-          float df = xq.x - cq.x;
-          acc = fmaf(df, df, acc);
-          df = xq.y - cq.y;
-          acc = fmaf(df, df, acc);
-          df = xq.z - cq.z;
-          acc = fmaf(df, df, acc);
-          df = xq.w - cq.w;
+    for (int p = 1; p <= PD_PILOT; ++p) {
+      qp[p] = p <= np ? __builtin_amdgcn_readlane(mine, (int)__builtin_ctzll(M)) : cur;
+      M &= M - 1;
+    }
+  }
+  float dp[1 + PD_PILOT];
+  {
+    float c[1 + PD_PILOT][8];
+#pragma unroll
+    for (int p = 0; p <= PD_PILOT; ++p)
+      if (p <= np) load_row<8>(c[p], C + (int64_t)qp[p] * d, lane, d, vec_c);
+#pragma unroll
+    for (int p = 0; p <= PD_PILOT; ++p) {
+      float acc = 0.f;
+      if (p <= np) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float df = sh.x[lane * 8 + e] - c[p][e];
           acc = fmaf(df, df, acc);
         }
       }
-      P += gl_sum<GL>(acc);
-      if (alive && (double)P * (1.0 - rel) > ub) {
-        alive = false;
-        if (jj == 0) sh.lb[slot] = f32_round_down((double)P * (1.0 - rel));
-      }
+      dp[p] = group_sum<64>(acc);
     }
-    if (alive && jj == 0) {
-      sh.full[slot] = P;
-      sh.lb[slot] = f32_round_down((double)P * (1.0 - rel));
+  }
+  float b1 = dp[0], b2 = FLT_MAX;
+  int q1 = cur;
+  wave_lds_sync();
+  if (lane <= np) {
+    float v = dp[0];
+#pragma unroll
+    for (int p = 1; p <= PD_PILOT; ++p)
+      if (lane == p) v = dp[p];
+    if (lane == 0) sh.cand[0] = cur;
+    sh.full[lane] = v;
+    sh.lb[lane] = f32_round_down((double)v * (1.0 - rel));
+  }
+#pragma unroll
+  for (int p = 1; p <= PD_PILOT; ++p) {
+    if (p > np) break;
+    const float dq = dp[p];
+    const int qq = qp[p];
+    if (qq == q1) continue;  // a cluster held by several entries
+    if (dq < b1 || (dq == b1 && qq < q1)) {
+      b2 = fminf(b2, b1);
+      b1 = dq;
+      q1 = qq;
+    } else {
+      b2 = fminf(b2, dq);
+    }
+  }
+  wave_lds_sync();
+  constexpr int NG = 64 / GL;        // candidates per batch
+  constexpr int PL = PD_CHUNK / GL;  // dimensions per lane and chunk
+  const int g = lane / GL, jj = lane % GL;
+  const int nch = (d + PD_CHUNK - 1) / PD_CHUNK;
+  const double ub = (double)b1 * (1.0 + rel) + 1e-30;
+  // the other slots, breadth first (al[0] lists slots 1..A0; the pilots
+  // are skipped)
+  int A = A0 - np, buf = 0;
+  for (int ch = 0; ch < nch && A > 0; ++ch) {
+    const bool last = ch == nch - 1;
+    const int base = ch * PD_CHUNK + jj * PL;
+    int nA = 0;
+    for (int s0 = 0; s0 < A; s0 += NG * PD_SB) {
+      int slot[PD_SB];
+      float4 cq[PD_SB][PL / 4];
+#pragma unroll
+      for (int u = 0; u < PD_SB; ++u) {
+        const int idx = s0 + u * NG + g;
+        slot[u] = idx < A ? sh.al[buf][ch == 0 ? idx + np : idx] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < PD_SB; ++u) {
+        const float* cr = C + (int64_t)(slot[u] >= 0 ? sh.cand[slot[u]] : 0) * d;
+#pragma unroll
+        for (int e = 0; e < PL; e += 4) {
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (slot[u] >= 0) {
+            if (vec_c && base + e < d) {
+              v = *reinterpret_cast<const float4*>(cr + base + e);
+            } else {
+              v.x = base + e < d ? cr[base + e] : 0.f;
+              v.y = base + e + 1 < d ? cr[base + e + 1] : 0.f;
+              v.z = base + e + 2 < d ? cr[base + e + 2] : 0.f;
+              v.w = base + e + 3 < d ? cr[base + e + 3] : 0.f;
+            }
+          }
+          cq[u][e / 4] = v;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PD_SB; ++u) {
+        if (s0 + u * NG >= A) break;  // wave-uniform: no candidate left in this batch
+        float acc = 0.f;
+        if (slot[u] >= 0) {
+#pragma unroll
+          for (int e = 0; e < PL; e += 4) {
+            const float4 xq = *reinterpret_cast<const float4*>(&sh.x[base + e]);
+            const float4 c4 = cq[u][e / 4];
+            float df = xq.x - c4.x;
+            acc = fmaf(df, df, acc);
+            df = xq.y - c4.y;
+            acc = fmaf(df, df, acc);
+            df = xq.z - c4.z;
+            acc = fmaf(df, df, acc);
+            df = xq.w - c4.w;
+            acc = fmaf(df, df, acc);
+          }
+        }
+        const float sum = gl_sum<GL>(acc);
+        bool keep = false;
+        if (slot[u] >= 0) {
+          const float P = sh.part[slot[u]] + sum;
+          const float lbp = f32_round_down((double)P * (1.0 - rel));
+          if ((double)P * (1.0 - rel) > ub) {
+            if (jj == 0) sh.lb[slot[u]] = lbp;
+          } else if (last) {
+            if (jj == 0) {
+              sh.full[slot[u]] = P;
+              sh.lb[slot[u]] = lbp;
+            }
+          } else {
+            keep = true;
+            if (jj == 0) sh.part[slot[u]] = P;
+          }
+        }
+        const uint64_t km = __ballot(keep && jj == 0);
+        if (keep && jj == 0) sh.al[buf ^ 1][nA + __popcll(km & lanes_below())] = slot[u];
+        nA += __popcll(km);
+      }
     }
     wave_lds_sync();
-    // fold the batch's survivors into best / second best, in slot order
-    const int hi = min(u, s0 + NG);
-    for (int t = s0; t < hi; ++t) {
-      const float dq = sh.full[t];
-      if (dq == FLT_MAX) continue;
-      const int qq = sh.cand[t];
-      if (dq < b1 || (dq == b1 && qq < q1)) {
-        b2 = fminf(b2, b1);
-        b1 = dq;
-        q1 = qq;
-      } else {
-        b2 = fminf(b2, dq);
-      }
+    A = nA;
+    buf ^= 1;
+  }
+  // best and second best over the full distances (lane t reads slot t; the
+  // tie rule makes the result independent of the order of the fold)
+  const float fl = lane <= A0 ? sh.full[lane] : FLT_MAX;
+  const int ql = lane <= A0 ? sh.cand[lane] : -1;
+  for (uint64_t F = __ballot(lane > np && fl != FLT_MAX); F; F &= F - 1) {
+    const int t = (int)__builtin_ctzll(F);
+    const float dq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fl), t));
+    const int qq = __builtin_amdgcn_readlane(ql, t);
+    if (qq == q1) continue;  // a cluster held by several entries
+    if (dq < b1 || (dq == b1 && qq < q1)) {
+      b2 = fminf(b2, b1);
+      b1 = dq;
+      q1 = qq;
+    } else {
+      b2 = fminf(b2, dq);
     }
   }
   const double thr = (double)b1 * (1.0 + rel) / (1.0 - rel) + 1e-30;
@@ -194,10 +282,9 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
     // float64 re-evaluation of every survivor inside the margin
     double m64 = DBL_MAX, cur64 = -1.0;
     int q64 = -1;
-    for (int t = 0; t < u; ++t) {
-      const float dq = sh.full[t];
-      if (dq == FLT_MAX || (double)dq > thr) continue;
-      const int qq = sh.cand[t];
+    for (uint64_t F = __ballot(fl != FLT_MAX && (double)fl <= thr); F; F &= F - 1) {
+      const int t = (int)__builtin_ctzll(F);
+      const int qq = __builtin_amdgcn_readlane(ql, t);
       float c[8];
       load_row<8>(c, C + (int64_t)qq * d, lane, d, vec_c);
       double acc = 0.0;
@@ -224,6 +311,7 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
     const float lq = sh.lb[myslot];
     r.lb = lq == FLT_MAX ? 0.f : f32_round_down(sqrt((double)lq) * (1.0 - 0x1p-50));
   }
+  wave_lds_sync();  // every lane has read the slots before the next sample writes them
   return r;
 }
 

@@ -276,11 +276,17 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off,
                           const int32_t* rev_src, uint8_t* act_out, int32_t* dirty_clear,
-                          float* delta);
+                          float* delta, int64_t* mass = nullptr);
 // Active-set marks of the samples moved between cur and nxt and of the rows
 // listing them (reverse lists of the graph); moved labels copied into cur.
 knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,
                            const int32_t* rev_src, uint8_t* act_out, const int64_t* moved, int64_t all_at);
+// Active-set marks (bit 0) of the samples with a dirty cluster among their
+// candidates and of the samples of jobs with at most kappa clusters; every
+// sample when mass is null or *mass >= all_at.
+knnkm_status ks_mark_dirty(knnkm_ctx* ctx, int64_t n, const int32_t* lab, const int32_t* dirty,
+                           const int32_t* rev_off, const int32_t* rev_src, uint8_t* act_out, const int64_t* mass,
+                           int64_t all_at, const int32_t* job_of, const int32_t* kbase, int32_t kappa);
 // Reverse lists of an n x kappa graph: rev_off (n + 1), rev_src (n * kappa).
 knnkm_status ks_reverse_graph(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, int32_t* rev_off,
                               int32_t* rev_src);

@@ -399,18 +399,22 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     k_permute_graph<<<grid_for(n * kappa, 256, 16384), 256, 0, ctx->stream>>>(G_ids, kappa, perm, inv, n, Gp);
   k_gather_i32<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(labels, perm, n, labp);
   KNNKM_TRY(knnkm_check(ctx, "fit working copy"));
-  // Active sets: after the first sweep only the samples that had several
-  // candidates, moved, or have a neighbour that moved are looked at; every
-  // other sample still has its own cluster as the only candidate and keeps
-  // its label (same results).  One flag array per label buffer: the flags
-  // next to a label array mark the samples the sweep reading it evaluates.
+  // Active sets: after the first sweep only the samples whose candidate set
+  // changed (they or a neighbour moved) or one of whose candidate centroids
+  // changed (a member of a dirty cluster, or a sample listing one in its
+  // graph row) are looked at; every other sample has the inputs of its last
+  // decision and keeps its label (same results).  One flag array per label
+  // buffer: the flags next to a label array mark the samples the sweep
+  // reading it looks at.
   const bool use_act = ctx->active_sets && use_graph && n * (int64_t)kappa < INT32_MAX;
   int32_t *rev_off = nullptr, *rev_src = nullptr;
   uint8_t *act_p = nullptr, *act_2 = nullptr;
   int32_t* lcnt = nullptr;  // list counters, one per flag array
+  int64_t* dmass = nullptr;  // members of the clusters an update made dirty
   if (use_act) {
     lcnt = (int32_t*)knnkm_ws(ctx, "fit_list_counts", 2 * sizeof(int32_t));
-    if (!lcnt) return KNNKM_ENOMEM;
+    dmass = (int64_t*)knnkm_ws(ctx, "fit_dirty_mass", sizeof(int64_t));
+    if (!lcnt || !dmass) return KNNKM_ENOMEM;
     KNNKM_TRY(ks_fill_i32(ctx, lcnt, 2, 0));
     rev_off = (int32_t*)knnkm_ws(ctx, "fit_rev_off", sizeof(int32_t) * (size_t)(n + 1));
     rev_src = (int32_t*)knnkm_ws(ctx, "fit_rev_src", sizeof(int32_t) * (size_t)n * kappa);
@@ -449,9 +453,10 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
                    int64_t* ac) -> knnkm_status {
     // moved counters are cleared once per fit (eager sweeps: one slot each)
     // or by the bookkeeping kernel (graph replays)
+    // (the flags of the next sweep come from the update's marks alone)
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
                      J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT, ev, first ? nullptr : act_for(cu),
-                     act_for(nx), ac, cnt_for(cu), cnt_for(nx), false, first ? nullptr : dirty_for(cu), bnd_u,
+                     nullptr, ac, cnt_for(cu), cnt_for(nx), false, first ? nullptr : dirty_for(cu), bnd_u,
                      bnd_lb, first ? nullptr : cdelta);
   };
   // The first sweep moves a large share of the samples away from the
@@ -470,9 +475,17 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       // every centroid was recomputed
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(nx), K, 1));
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(cu), K, 0));
+      if (use_act)
+        KNNKM_TRY(ks_mark_dirty(ctx, n, nx, dirty_for(nx), rev_off, rev_src, act_for(nx), nullptr, 0, J.job_of, k32,
+                                kappa));
     } else {
       KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty_for(nx), C, Iterm, rev_off, rev_src,
-                             act_for(nx), dirty_for(cu), cdelta));
+                             act_for(nx), dirty_for(cu), cdelta, dmass));
+      // scattered marks while the dirty clusters' members and the rows
+      // listing them stay below about 2n; every sample beyond that
+      if (use_act)
+        KNNKM_TRY(ks_mark_dirty(ctx, n, nx, dirty_for(nx), rev_off, rev_src, act_for(nx), dmass,
+                                2 * n / (kappa + 1), J.job_of, k32, kappa));
     }
     k_range_trace<<<m, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, tr);
     return knnkm_check(ctx, "fit iteration");

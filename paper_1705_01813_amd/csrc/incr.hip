@@ -127,14 +127,18 @@ __global__ void k_fx_from_f64(const double* __restrict__ sums, int64_t kd, int d
 
 // Active sets: a moved sample, and every sample that has it as a neighbour
 // (reverse lists rev_off/rev_src of the fixed graph), have a new candidate
-// set for the next sweep; bit 1 of their flag says so.  Bit 0 was written
-// by this sweep's assignment, which has finished, so every writer here
-// stores the same value and the order of the stores does not matter.
-__device__ inline void mark_one(uint8_t* __restrict__ act_out, int64_t x) { act_out[x] = act_out[x] | 2; }
-// Whole wave: the marks of every moved sample of the wave (lane q holds
+// set for the next sweep; bit 1 of their flag says so.  Bit 0 says that a
+// candidate centroid of the sample changed (k_mark_dirty).  Within one
+// kernel every writer of a flag sets the same bit of a value no other
+// kernel is writing at the time, so all of them store the same byte and the
+// order of the stores does not matter.
+template <int BIT>
+__device__ inline void mark_one(uint8_t* __restrict__ act_out, int64_t x) { act_out[x] = act_out[x] | BIT; }
+// Whole wave: the marks of every selected sample of the wave (lane q holds
 // position p and `moved`), the wave's marks laid end to end over the lanes
 // (sample q owns entries [ex_q, ex_q + 1 + its reverse-list length); its
 // first entry is the sample itself), so all of them are in flight at once.
+template <int BIT = 2>
 __device__ inline void mark_moved_wave(bool moved, int64_t p, const int32_t* __restrict__ rev_off,
                                        const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out,
                                        int lane) {
@@ -160,7 +164,7 @@ __device__ inline void mark_moved_wave(bool moved, int64_t p, const int32_t* __r
     const int32_t local = e - (__shfl(inc, q, 64) - __shfl(c, q, 64));
     const int32_t rq = __shfl(r0, q, 64);
     const int64_t pq = __shfl(p, q, 64);
-    if (e < total) mark_one(act_out, local == 0 ? pq : (int64_t)rev_src[rq + local - 1]);
+    if (e < total) mark_one<BIT>(act_out, local == 0 ? pq : (int64_t)rev_src[rq + local - 1]);
   }
 }
 
@@ -282,10 +286,46 @@ __global__ __launch_bounds__(256) void k_mark_moved(int64_t n, int32_t* __restri
     const bool mv = p < n && cur[p] != (b = nxt[p]);
     if (mv) cur[p] = b;
     if (all) {
-      if (p < n) mark_one(act_out, p);
+      if (p < n) mark_one<2>(act_out, p);
     } else if (__ballot(mv)) {
       mark_moved_wave(mv, p, rev_off, rev_src, act_out, lane);
     }
+  }
+}
+
+// Active-set marks of changed centroids: every sample in a dirty cluster
+// (labels lab, after the update) and every sample that lists it in its graph
+// row has that cluster among its candidates, so bit 0 of their flags is set;
+// a sample none of whose candidate centroids changed and whose candidate set
+// is the same (bit 1 clear) has every input of its last decision and is not
+// looked at.  A sample of a job with no more clusters than kappa has all of
+// them as candidates and is always marked (job_of/kbase: jobs of a batch,
+// null for one job).  With mass (the members of all dirty clusters) null or
+// at least all_at, every sample is marked instead: one streaming pass in
+// place of scattered marks that would cover most rows.
+__global__ __launch_bounds__(256) void k_mark_dirty(int64_t n, const int32_t* __restrict__ lab,
+                                                    const int32_t* __restrict__ dirty,
+                                                    const int32_t* __restrict__ rev_off,
+                                                    const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out,
+                                                    const int64_t* __restrict__ mass, int64_t all_at,
+                                                    const int32_t* __restrict__ job_of,
+                                                    const int32_t* __restrict__ kbase, int kappa) {
+  const int lane = threadIdx.x & 63;
+  const bool all = !mass || *mass >= all_at;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+    const int64_t p = base + lane;
+    if (all) {
+      if (p < n) mark_one<1>(act_out, p);
+      continue;
+    }
+    bool sel = p < n && dirty[lab[p]] != 0;
+    if (p < n && !sel && job_of) {
+      const int q = job_of[p];
+      sel = kappa >= kbase[q + 1] - kbase[q];
+    }
+    if (__ballot(sel)) mark_moved_wave<1>(sel, p, rev_off, rev_src, act_out, lane);
   }
 }
 
@@ -311,18 +351,21 @@ __global__ void k_rev_fill(const int32_t* __restrict__ G, int64_t ne, int64_t n,
 // Clusters whose members changed (dirty, set by this sweep's moves and kept
 // for the next sweep's assignment): centroid (unchanged when empty) and the
 // Eqn. 2 term; one wavefront per cluster.  dirty_clear, the previous
-// sweep's flags, is cleared on the way.
+// sweep's flags, is cleared on the way; mass (nullable, cleared before)
+// receives the number of members of all dirty clusters.
 __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict__ D, int32_t K, int d,
                                                      const int32_t* __restrict__ cs,
                                                      const int32_t* __restrict__ counts,
                                                      const int32_t* __restrict__ dirty,
                                                      int32_t* __restrict__ dirty_clear, float* __restrict__ C,
-                                                     double* __restrict__ Iterm, float* __restrict__ delta) {
+                                                     double* __restrict__ Iterm, float* __restrict__ delta,
+                                                     unsigned long long* __restrict__ mass) {
   const int lane = threadIdx.x & 63;
   for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < K; r += (int64_t)gridDim.x * 4) {
     if (lane == 0) dirty_clear[r] = 0;
     if (!dirty[r]) continue;  // wave-uniform
     const int cnt = counts[r];
+    if (mass && lane == 0 && cnt > 0) atomicAdd(mass, (unsigned long long)cnt);
     const int s = cs[r];
     double sq = 0.0, mv = 0.0;
     for (int t = lane; t < d; t += 64) {
@@ -392,7 +435,8 @@ knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32
 knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, int32_t* cur,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off, const int32_t* rev_src,
-                          uint8_t* act_out, int32_t* dirty_clear, float* delta) {
+                          uint8_t* act_out, int32_t* dirty_clear, float* delta, int64_t* mass) {
+  if (mass) KNNKM_TRY(ks_fill_i64(ctx, mass, 1, 0));
 #define MV(DD)                                                                                           \
   k_fx_moves<DD><<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty, \
                                                                   rev_off, rev_src, act_out)
@@ -406,7 +450,7 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
     MV(8);
 #undef MV
   k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, dirty, dirty_clear, C, Iterm,
-                                                                delta);
+                                                                delta, (unsigned long long*)mass);
   return knnkm_check(ctx, "incremental update");
 }
 
@@ -415,6 +459,14 @@ knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_
   k_mark_moved<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, cur, nxt, rev_off, rev_src, act_out, moved,
                                                                 all_at);
   return knnkm_check(ctx, "active-set marks");
+}
+
+knnkm_status ks_mark_dirty(knnkm_ctx* ctx, int64_t n, const int32_t* lab, const int32_t* dirty,
+                           const int32_t* rev_off, const int32_t* rev_src, uint8_t* act_out, const int64_t* mass,
+                           int64_t all_at, const int32_t* job_of, const int32_t* kbase, int32_t kappa) {
+  k_mark_dirty<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, lab, dirty, rev_off, rev_src, act_out, mass,
+                                                                all_at, job_of, kbase, kappa);
+  return knnkm_check(ctx, "active-set marks of changed centroids");
 }
 
 knnkm_status ks_reverse_graph(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, int32_t* rev_off,
