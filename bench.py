@@ -124,15 +124,24 @@ def precision_report(ctx, X, p, G_ids, G_d2, labels, C, trace, samples, seed, lo
                          "distortion of the returned labels)"}
 
 
+ASSIGN_SOURCES = ("assign.hip", "assign_pd.hip")  # the fit assignment kernels
+
+
+def assign_source_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ASSIGN_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1705_01813_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(config, key="traffic_bytes_per_launch"):
     """HBM bytes per fit assignment launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a plain copy
     of known size), or None when that summary is missing, is for another
-    workload, or predates the current source of the assignment kernel."""
-    import hashlib
-
+    workload, or predates the current source of the assignment kernels."""
     path = os.path.join(ROOT, "profiles", f"knn_assign_{config}_traffic.txt")
-    src = os.path.join(ROOT, "paper_1705_01813_amd", "csrc", "assign.hip")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -140,10 +149,92 @@ def measured_traffic(config, key="traffic_bytes_per_launch"):
         if "=" in line and not line.startswith("#"):
             a, b = line.split("=", 1)
             kv[a.strip()] = b.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if kv.get("assign_source_sha256") != sha or key not in kv:
+    if kv.get("assign_source_sha256") != assign_source_sha256() or key not in kv:
         return None
     return float(kv[key])
+
+
+def traffic_summary(config, fetch_csv, write_csv, bench_json):
+    """Writes profiles/knn_assign_<config>_traffic.txt from two rocprofv3
+    counter runs of `bench.py --config <config> --steps 1 --warmup 0
+    --counters` (FETCH_SIZE, then WRITE_SIZE) and that run's JSON line: the
+    fit assignment launches of the kernel pass (the last fit of the run) with
+    their list compactions, each counter scaled by its value on the 1 GiB copy
+    at the end of the run.  Host only."""
+    import csv
+
+    def per_dispatch(path, counter):
+        rows = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            key = int(r["Dispatch_Id"])
+            nm = r["Kernel_Name"]
+            v = float(r["Counter_Value"])
+            if key in rows:
+                rows[key] = (nm, rows[key][1] + v, int(r["Grid_Size"]))
+            else:
+                rows[key] = (nm, v, int(r["Grid_Size"]))
+        return [(k,) + rows[k] for k in sorted(rows)]
+
+    line = [ln for ln in open(bench_json) if ln.startswith("{")][-1]
+    b = json.loads(line)
+    sw = b["sweeps"]
+    launches = len(sw["assign_ms"])
+    out = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        ds = per_dispatch(path, counter)
+        # the copy: the last elementwise dispatch of the run (torch.mul over
+        # 2^28 floats; the fill before it writes and reads next to nothing)
+        copy = [x for x in ds if "elementwise" in x[1]][-1]
+        scale = float(1 << 20) / copy[2]  # KiB of the 1 GiB stream
+        assign = [i for i, x in enumerate(ds) if "k_assign" in x[1]]
+        last = assign[-launches:]
+        total = sum(ds[i][2] for i in last)
+        compact = sum(x[2] for x in ds[last[0]:last[-1] + 1] if "k_act_compact" in x[1])
+        out[counter] = {"scale": scale, "copy_kib": copy[2], "raw_kib_per_launch": (total + compact) / launches,
+                        "first_kib": ds[last[0]][2], "first_kernel": ds[last[0]][1].split("(")[0]}
+    f, w = out["FETCH_SIZE"], out["WRITE_SIZE"]
+    fetch_b = f["raw_kib_per_launch"] * 1024 * f["scale"]
+    write_b = w["raw_kib_per_launch"] * 1024 * w["scale"]
+    first_b = (f["first_kib"] * f["scale"] + w["first_kib"] * w["scale"]) * 1024
+    cfg = CONFIGS[config]
+    n, d, k, kappa = cfg["n"], cfg["d"], cfg["k"], cfg["kappa"]
+    ev = sum(sw["evaluated"][1:]) + n
+    ls = sum(sw["listed"][1:]) + n
+    alg = (sum(assign_bytes(n, d, k, kappa, e, l) for e, l in zip(sw["evaluated"][1:], sw["listed"][1:]))
+           + assign_bytes(n, d, k, kappa)) / launches
+    path = os.path.join(ROOT, "profiles", f"knn_assign_{config}_traffic.txt")
+    with open(path, "w") as fh:
+        fh.write(f"# knn_assign on the {cfg['desc']} workload: HBM traffic per fit assignment launch\n")
+        fh.write("# Commands (one MI355X; R = the repository root; one counter per run):\n")
+        for c, o in (("FETCH_SIZE", "out_fetch"), ("WRITE_SIZE", "out_write")):
+            fh.write(f"#   cd /tmp && timeout -s KILL 600 rocprofv3 --pmc {c} --kernel-include-regex "
+                     f"\"k_assign|k_act_compact|elementwise\" -d {o} -o run --output-format csv -- python3 "
+                     f"$R/bench.py --config {config} --steps 1 --warmup 0 --counters > {o}.json\n")
+        fh.write(f"#   python3 $R/bench.py --config {config} --traffic-summary out_fetch/run_counter_collection.csv "
+                 f"out_write/run_counter_collection.csv out_fetch.json\n")
+        fh.write("# bench.py --counters runs the workload with every sweep as its own dispatch, then a 1 GiB "
+                 "elementwise copy.\n")
+        fh.write(f"# FETCH_SIZE of the 1 GiB copy read {f['copy_kib']:.0f} KiB (scale {f['scale']:.4f}); "
+                 f"WRITE_SIZE {w['copy_kib']:.0f} KiB (scale {w['scale']:.4f}).\n")
+        fh.write(f"# The last fit's {launches} assignment launches (the kernel pass of the run) and the list "
+                 "compactions between them; totals per launch:\n")
+        fh.write(f"fetch_kib_per_launch_raw = {f['raw_kib_per_launch']:.1f}\n")
+        fh.write(f"write_kib_per_launch_raw = {w['raw_kib_per_launch']:.1f}\n")
+        fh.write(f"fetch_bytes_per_launch = {fetch_b:.0f}\n")
+        fh.write(f"write_bytes_per_launch = {write_b:.0f}\n")
+        fh.write(f"traffic_bytes_per_launch = {fetch_b + write_b:.0f}\n")
+        fh.write(f"algorithmic_bytes_per_launch = {alg:.0f}\n")
+        fh.write(f"# (per launch: graph rows, neighbour, own and output labels of the {ls / launches:.0f} samples "
+                 f"listed on average; rows of the {ev / launches:.0f} samples evaluated; centroids once; a flag "
+                 "byte per sample; listed and evaluated counts from the same run's JSON line)\n")
+        fh.write(f"traffic_over_algorithmic = {(fetch_b + write_b) / alg:.3f}\n")
+        fh.write(f"# first launch ({f['first_kernel']}: every sample looked at and evaluated)\n")
+        fh.write(f"first_traffic_bytes = {first_b:.0f}\n")
+        fh.write(f"first_algorithmic_bytes = {assign_bytes(n, d, k, kappa):.0f}\n")
+        fh.write(f"assign_source_sha256 = {assign_source_sha256()}\n")
+    return path
 
 
 def _pct(v, q):
@@ -463,6 +554,8 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="for counter runs: sweeps as separate dispatches (no graph), no forms or oracle, "
                          "then a 1 GiB elementwise copy that calibrates the memory counters")
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
+                    help="host only: write the committed traffic summary of --config from two counter runs")
     ap.add_argument("--candidate-sharing", action="store_true",
                     help="after one build, measure the candidate clusters shared by consecutive samples")
     ap.add_argument("--forms-jobs", type=int, default=4096, help="jobs of the batching measurement")
@@ -473,6 +566,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
+    if args.traffic_summary:
+        print(traffic_summary(args.config, *args.traffic_summary))
+        return 0
     if args.gpus != 1:
         print("bench.py runs on one GPU only: --gpus N with N > 1 is not supported "
               "(there is no multi-GPU path)", file=sys.stderr)

@@ -333,13 +333,19 @@ knnkm_status knnkm_enable_subtree_finish(knnkm_ctx* ctx, int32_t on);
  * process.  Every shape gives the same results. */
 knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on);
 /* Early-abandoned partial distances in the assignment for wide rows
- * (256 < d <= 512, kappa <= 63; default on).  Each sample is handled by one
- * wavefront: its distinct candidates are listed, the distance to its own
- * centroid is computed in full, and every other candidate is summed 64
- * dimensions at a time and dropped once a rigorous lower bound of the partial
- * sum exceeds a rigorous upper bound of the best full distance so far.
- * Decisions (labels, moved counts, active-set flags) are the same with it on
- * or off; calls that request best_d2 use the full-distance kernels. */
+ * (256 < d <= 512, kappa <= 63).  Each sample is handled by one wavefront:
+ * an upper bound of the distance to its closest candidate comes first (full
+ * distances of the own centroid and of the nearest entry's cluster, or in
+ * the fit's sweeps on active sets the drift bound of the own centroid), and
+ * every candidate is summed 64 dimensions at a time and dropped once a
+ * rigorous lower bound of its distance over those dimensions exceeds it; the
+ * survivors get full float32 distances (float64 near ties).  on: 0 off, 1 on
+ * (default), the graph build's and the fit's sweeps reading a bfloat16
+ * shadow of the centroids for the partial sums (half the bytes; the bound
+ * accounts for each shadow row's distance to its float32 row), 2 on with the
+ * float32 centroids only.  Decisions (labels, moved counts, active-set
+ * flags) are the same in every mode; calls that request best_d2 use the
+ * full-distance kernels.  Other values: KNNKM_EINVAL. */
 knnkm_status knnkm_enable_partial_distances(knnkm_ctx* ctx, int32_t on);
 
 /* Fix the assignment's launch shape for this context (overrides the

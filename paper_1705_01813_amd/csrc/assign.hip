@@ -733,7 +733,9 @@ extern "C" knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on) {
 
 extern "C" knnkm_status knnkm_enable_partial_distances(knnkm_ctx* ctx, int32_t on) {
   if (!ctx) return KNNKM_EINVAL;
+  if (on < 0 || on > 2) return knnkm_fail(ctx, KNNKM_EINVAL, "partial distances: %d is not 0, 1 or 2", on);
   ctx->wide_pd = on != 0;
+  ctx->pd_shadow = on == 1;
   return KNNKM_OK;
 }
 
@@ -756,7 +758,8 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        int64_t* n_moved, const int32_t* order, bool dense, const int32_t* job_of,
                        const int32_t* kbase, int use, int64_t* n_eval, const uint8_t* act_in, uint8_t* act_out,
                        int64_t* n_active, int32_t* list_count, int32_t* list_count_other, bool zero_moved,
-                       const int32_t* cdirty, float* bnd_u, float* bnd_lb, const float* cdelta) {
+                       const int32_t* cdirty, float* bnd_u, float* bnd_lb, const float* cdelta,
+                       const uint16_t* Cb, const float* ceps) {
   if (n_moved && zero_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
   if (n_eval) KNNKM_TRY(ks_fill_i64(ctx, n_eval, 1, 0));
   if (n_active && !(act_in && !best_d2 && !order && !dense)) KNNKM_TRY(ks_fill_i64(ctx, n_active, 1, n));
@@ -793,7 +796,8 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                                                                           list_count_other);
     if (wide)
       return ks_assign_pd(ctx, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc, eacc, nullptr, job_of,
-                          kbase, nullptr, act_out, list, cnt, n_active, cdirty, 0, bnd_u, bnd_lb, cdelta);
+                          kbase, nullptr, act_out, list, cnt, n_active, cdirty, 0, bnd_u, bnd_lb, cdelta, Cb,
+                          ceps);
     const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
 #define LP(LL, VV, SS)                                                                                        \
   k_assign_list<LL, VV, SS, ((LL) >= 64 ? 2 : 1)><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
@@ -852,7 +856,8 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
 #undef LA
   if (wide)
     return ks_assign_pd(ctx, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc, eacc, order, job_of,
-                        kbase, act_in, act_out, nullptr, nullptr, nullptr, nullptr, 64, bnd_u, bnd_lb, nullptr);
+                        kbase, act_in, act_out, nullptr, nullptr, nullptr, nullptr, 64, bnd_u, bnd_lb, nullptr, Cb,
+                        ceps);
   // shape: tuned entry, else (large call, tuning allowed, not inside a
   // graph capture) time every candidate once, else the default
   const int Sb = S <= 1 ? 1 : (S <= 2 ? 2 : (S <= 4 ? 4 : 8));

@@ -6,24 +6,32 @@
 // own, staying unless a candidate is strictly closer, smallest id among equal
 // minima.  At this width the candidates of one sample are nearly all distinct
 // and hardly shared with the samples next to it, so every candidate costs one
-// gathered centroid row; most candidates are far from the sample, and a sum
-// of squares over the first dimensions already exceeds the distance to the
-// sample's own centroid.  So:
+// gathered centroid row and the sweep is bound by those gathers; most
+// candidates are far from the sample, and a sum of squares over the first
+// dimensions already exceeds the distance to the closest centroid.  So:
 //  * every graph entry holding another cluster is a candidate slot (a
 //    cluster held by several entries is evaluated once per entry, with the
 //    same bits each time; at this width that is a few percent of the
 //    entries, less than sorting them out would cost);
-//  * the full float32 distances of the own centroid and of the first slot
-//    (the cluster of the nearest graph entry holding another cluster, the
-//    likeliest to be the closest) are computed first, their loads in flight
-//    together;
-//  * the other candidates advance breadth first, 64 dimensions (a chunk) at a
+//  * an upper bound ub of the squared distance to the closest centroid comes
+//    first, from the full float32 distance of the own centroid and, in a
+//    full sweep, of the first slot (the cluster of the nearest entry holding
+//    another one, the likeliest to be the closest; in the sweeps on active
+//    sets a sample mostly stays), their loads in flight together;
+//  * the candidates advance breadth first, 64 dimensions (a chunk) at a
 //    time, GL lanes per candidate and up to 32 candidates' loads in flight
-//    per wavefront: each chunk adds to a running float32 partial sum, and a
-//    candidate is dropped as soon as a rigorous lower bound of its partial
-//    sum exceeds a rigorous upper bound of the best of those distances (the
-//    candidate then cannot be the closest nor tie with it); one that survives
-//    every chunk has its full distance;
+//    per wavefront, reading the bfloat16 shadow of the centroids when there
+//    is one (half the bytes; eps bounds each shadow row's distance to the
+//    float32 row) and the float32 rows otherwise: each chunk adds to a
+//    running float32 partial sum P, and a candidate is dropped as soon as a
+//    rigorous lower bound of its squared distance over the dimensions so far,
+//    (sqrt(P (1 - rel)) - eps)^2 by the triangle inequality, exceeds ub (the
+//    candidate then cannot be the closest nor tie with it);
+//  * with the shadow, a survivor of every chunk has its distance bracketed
+//    by (sqrt(P (1 -+ rel)) -+ eps)^2, and only those whose lower end is
+//    within the smallest upper end (and ub) remain;
+//  * the remaining candidates get full float32 distances from the float32
+//    rows;
 //  * best and second best over the full distances, and when they are within
 //    the rigorous float32 error margin, float64 re-evaluation of every
 //    survivor inside it with the tie rule, as in the narrow kernels.
@@ -35,14 +43,19 @@
 
 namespace {
 
-constexpr int PD_CHUNK = 64;  // dimensions per early-abandon step
+// dimensions per early-abandon step: 64 of float32, 128 of bfloat16 (the same
+// 32 bytes per lane and candidate; at most eight chunk additions, 16 products
+// per lane, either way within the error bound pd_rel)
+template <bool SH>
+constexpr int pd_chunk() { return SH ? 128 : 64; }
+
 constexpr int PD_SB = 4;      // candidate batches whose loads are in flight together
-constexpr int PD_PILOT = 1;   // candidates whose full distance is taken with the own one
+constexpr int PD_EX = 4;      // full float32 rows in flight together
 
 struct alignas(16) PDWave {
   float x[512];       // the sample's row
   int32_t cand[64];   // cluster of slot s (slot 0: the own one)
-  float full[64];     // float32 full distance of slot (FLT_MAX: dropped)
+  float full[64];     // float32 full distance of slot (FLT_MAX: not taken)
   float lb[64];       // lower bound of the squared distance of slot
   float part[64];     // running partial sum of slot
   int32_t al[2][64];  // slots alive at this chunk and at the next
@@ -76,19 +89,73 @@ __device__ inline float gl_sum(float v) {
   return v;
 }
 
+// bfloat16 (bit pattern) to float32, exact
+__device__ inline float bf16_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Rigorous lower bound of a squared distance from a float32 partial sum P
+// (relative error at most rel) of the squared differences to a row within
+// eps (Euclidean) of the true row: (sqrt(P (1 - rel)) - eps)^2, rounded down.
+__device__ inline double pd_lower(float P, double rel, float eps) {
+  const double t = sqrt((double)P * (1.0 - rel)) * (1.0 - 0x1p-50) - (double)eps;
+  return t > 0.0 ? t * t * (1.0 - 0x1p-50) : 0.0;
+}
+
+// Rigorous upper bound of the squared distance from the float32 sum P of the
+// squared differences to a row within eps of the true row over every
+// dimension: (sqrt(P (1 + rel)) + eps)^2, rounded up.
+__device__ inline double pd_upper(float P, double rel, float eps) {
+  const double t = sqrt((double)P * (1.0 + rel)) * (1.0 + 0x1p-50) + (double)eps;
+  return t * t * (1.0 + 0x1p-50);
+}
+
+// Full float32 distances (64-lane layout) of the row in LDS to the float32
+// centroids of up to PD_EX slots taken from `pick` (index -> slot, -1 none),
+// their loads in flight together; lane 0 stores full and lb of each slot.
+template <typename Pick>
+__device__ __attribute__((always_inline)) inline void pd_exact(PDWave& sh, int ne, Pick pick, const float* __restrict__ C, int d, bool vec_c,
+                                double rel) {
+  const int lane = threadIdx.x & 63;
+  for (int e0 = 0; e0 < ne; e0 += PD_EX) {
+    int sl[PD_EX];
+    float c[PD_EX][8];
+#pragma unroll
+    for (int u = 0; u < PD_EX; ++u) {
+      sl[u] = e0 + u < ne ? pick(e0 + u) : -1;
+      if (sl[u] >= 0) load_row<8>(c[u], C + (int64_t)sh.cand[sl[u]] * d, lane, d, vec_c);
+    }
+#pragma unroll
+    for (int u = 0; u < PD_EX; ++u) {
+      if (sl[u] < 0) break;  // wave-uniform
+      float acc = 0.f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float df = sh.x[lane * 8 + e] - c[u][e];
+        acc = fmaf(df, df, acc);
+      }
+      const float v = group_sum<64>(acc);
+      if (lane == 0) {
+        sh.full[sl[u]] = v;
+        sh.lb[sl[u]] = f32_round_down((double)v * (1.0 - rel));
+      }
+    }
+  }
+}
+
 // The decision of one sample, by the whole wavefront (every argument
 // wave-uniform except lane-held ones).  cv: the candidate label held by lane
 // e (entry e: 0 own, 1..kappa neighbours; -1 unused).  skip (lane-held): the
 // entry's cluster is already known to be strictly farther than the own
 // centroid, so it takes no part (its lane's lb is left to the caller).
-// Returns the label and the bounds of PDResult: every candidate's squared
-// distance is bracketed by rigorous float32 bounds (a dropped one from below
-// by its partial sum), so they hold for the exact distances.
-template <int GL>
-__device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow, int d, bool vec_x,
-                                     const float* __restrict__ C, bool vec_c, int cur, int cv, double rel,
-                                     bool dense, bool skip) {
-  (void)dense;
+// Cb/eps: the bfloat16 shadow of C (null: the float32 rows are read).
+// pilot: the first slot's full distance is taken with the own one.  Returns
+// the label and the bounds of PDResult: every candidate's squared distance
+// is bracketed by rigorous bounds (a dropped one from below by its partial
+// sum), so they hold for the exact distances.
+template <int GL, bool SH>
+__device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow, int d, bool vec_x,
+                                     const float* __restrict__ C, bool vec_c, const uint16_t* __restrict__ Cb,
+                                     const float* __restrict__ eps, bool vec_b, int cur, int cv, double rel,
+                                     bool skip, bool pilot) {
   const int lane = threadIdx.x & 63;
   // the row into LDS (lane j: dims [8j, 8j+8), read back by the same lane
   // where the 64-lane layout is used)
@@ -112,83 +179,33 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
     sh.cand[myslot] = mine;
     sh.al[0][myslot - 1] = myslot;
   }
-  // full float32 distances (64-lane layout, loads in flight together) of
-  // the own centroid and of the first PD_PILOT candidate slots, the clusters
-  // of the nearest graph entries and the likeliest to be the closest: the
-  // bound the other candidates are dropped against is then tight from the
-  // start
-  const int np = min(A0, PD_PILOT);
-  int qp[1 + PD_PILOT];
-  qp[0] = cur;
-  {
-    uint64_t M = cm;
-#pragma unroll
-    for (int p = 1; p <= PD_PILOT; ++p) {
-      qp[p] = p <= np ? __builtin_amdgcn_readlane(mine, (int)__builtin_ctzll(M)) : cur;
-      M &= M - 1;
-    }
-  }
-  float dp[1 + PD_PILOT];
-  {
-    float c[1 + PD_PILOT][8];
-#pragma unroll
-    for (int p = 0; p <= PD_PILOT; ++p)
-      if (p <= np) load_row<8>(c[p], C + (int64_t)qp[p] * d, lane, d, vec_c);
-#pragma unroll
-    for (int p = 0; p <= PD_PILOT; ++p) {
-      float acc = 0.f;
-      if (p <= np) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float df = sh.x[lane * 8 + e] - c[p][e];
-          acc = fmaf(df, df, acc);
-        }
-      }
-      dp[p] = group_sum<64>(acc);
-    }
-  }
-  float b1 = dp[0], b2 = FLT_MAX;
-  int q1 = cur;
+  if (lane == 0) sh.cand[0] = cur;
   wave_lds_sync();
-  if (lane <= np) {
-    float v = dp[0];
-#pragma unroll
-    for (int p = 1; p <= PD_PILOT; ++p)
-      if (lane == p) v = dp[p];
-    if (lane == 0) sh.cand[0] = cur;
-    sh.full[lane] = v;
-    sh.lb[lane] = f32_round_down((double)v * (1.0 - rel));
-  }
-#pragma unroll
-  for (int p = 1; p <= PD_PILOT; ++p) {
-    if (p > np) break;
-    const float dq = dp[p];
-    const int qq = qp[p];
-    if (qq == q1) continue;  // a cluster held by several entries
-    if (dq < b1 || (dq == b1 && qq < q1)) {
-      b2 = fminf(b2, b1);
-      b1 = dq;
-      q1 = qq;
-    } else {
-      b2 = fminf(b2, dq);
-    }
-  }
+  // the own centroid in full, and the first slot with it with a pilot
+  const int np = pilot ? min(A0, 1) : 0;
+  pd_exact(sh, 1 + np, [](int e) { return e; }, C, d, vec_c, rel);
   wave_lds_sync();
+  const double ub = (double)fminf(sh.full[0], np ? sh.full[1] : FLT_MAX) * (1.0 + rel) + 1e-30;
   constexpr int NG = 64 / GL;        // candidates per batch
-  constexpr int PL = PD_CHUNK / GL;  // dimensions per lane and chunk
+  constexpr int CHK = pd_chunk<SH>();
+  constexpr int PL = CHK / GL;  // dimensions per lane and chunk
+  static_assert(PL == 8 || (SH && PL == 16), "32 bytes per lane and chunk");
   const int g = lane / GL, jj = lane % GL;
-  const int nch = (d + PD_CHUNK - 1) / PD_CHUNK;
-  const double ub = (double)b1 * (1.0 + rel) + 1e-30;
-  // the other slots, breadth first (al[0] lists slots 1..A0; the pilots
-  // are skipped)
+  const int nch = (d + CHK - 1) / CHK;
+  // the other slots, breadth first (al[0] lists slots 1..A0; the first np
+  // are done).  With the shadow, the survivors of the last chunk go to the
+  // next list for their float32 distances; without it they have them.
   int A = A0 - np, buf = 0;
   for (int ch = 0; ch < nch && A > 0; ++ch) {
     const bool last = ch == nch - 1;
-    const int base = ch * PD_CHUNK + jj * PL;
+    const int base = ch * CHK + jj * PL;
     int nA = 0;
     for (int s0 = 0; s0 < A; s0 += NG * PD_SB) {
       int slot[PD_SB];
-      float4 cq[PD_SB][PL / 4];
+      // the chunk of each batch's candidate: 8 bfloat16 (packed in four
+      // words) or 8 float32 values per lane
+      constexpr int NW = SH ? PL / 2 : PL;
+      uint32_t cq[PD_SB][NW];
 #pragma unroll
       for (int u = 0; u < PD_SB; ++u) {
         const int idx = s0 + u * NG + g;
@@ -196,11 +213,34 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
       }
 #pragma unroll
       for (int u = 0; u < PD_SB; ++u) {
-        const float* cr = C + (int64_t)(slot[u] >= 0 ? sh.cand[slot[u]] : 0) * d;
 #pragma unroll
-        for (int e = 0; e < PL; e += 4) {
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (slot[u] >= 0) {
+        for (int e = 0; e < NW; ++e) cq[u][e] = 0u;
+        if (slot[u] < 0) continue;
+        const int64_t q = sh.cand[slot[u]];
+        if constexpr (SH) {
+          const uint16_t* br = Cb + q * d;
+          if (vec_b && base + PL <= d) {
+#pragma unroll
+            for (int h = 0; h < PL / 8; ++h) {
+              const uint4 v = *reinterpret_cast<const uint4*>(br + base + 8 * h);
+              cq[u][4 * h] = v.x;
+              cq[u][4 * h + 1] = v.y;
+              cq[u][4 * h + 2] = v.z;
+              cq[u][4 * h + 3] = v.w;
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < PL; e += 2) {
+              const uint32_t lo = base + e < d ? br[base + e] : 0u;
+              const uint32_t hi = base + e + 1 < d ? br[base + e + 1] : 0u;
+              cq[u][e / 2] = lo | (hi << 16);
+            }
+          }
+        } else {
+          const float* cr = C + q * d;
+#pragma unroll
+          for (int e = 0; e < PL; e += 4) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             if (vec_c && base + e < d) {
               v = *reinterpret_cast<const float4*>(cr + base + e);
             } else {
@@ -209,8 +249,11 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
               v.z = base + e + 2 < d ? cr[base + e + 2] : 0.f;
               v.w = base + e + 3 < d ? cr[base + e + 3] : 0.f;
             }
+            cq[u][e] = __float_as_uint(v.x);
+            cq[u][e + 1] = __float_as_uint(v.y);
+            cq[u][e + 2] = __float_as_uint(v.z);
+            cq[u][e + 3] = __float_as_uint(v.w);
           }
-          cq[u][e / 4] = v;
         }
       }
 #pragma unroll
@@ -221,14 +264,25 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
 #pragma unroll
           for (int e = 0; e < PL; e += 4) {
             const float4 xq = *reinterpret_cast<const float4*>(&sh.x[base + e]);
-            const float4 c4 = cq[u][e / 4];
-            float df = xq.x - c4.x;
+            float c0, c1, c2, c3;
+            if constexpr (SH) {
+              c0 = bf16_f32(cq[u][e / 2] & 0xFFFFu);
+              c1 = bf16_f32(cq[u][e / 2] >> 16);
+              c2 = bf16_f32(cq[u][e / 2 + 1] & 0xFFFFu);
+              c3 = bf16_f32(cq[u][e / 2 + 1] >> 16);
+            } else {
+              c0 = __uint_as_float(cq[u][e]);
+              c1 = __uint_as_float(cq[u][e + 1]);
+              c2 = __uint_as_float(cq[u][e + 2]);
+              c3 = __uint_as_float(cq[u][e + 3]);
+            }
+            float df = xq.x - c0;
             acc = fmaf(df, df, acc);
-            df = xq.y - c4.y;
+            df = xq.y - c1;
             acc = fmaf(df, df, acc);
-            df = xq.z - c4.z;
+            df = xq.z - c2;
             acc = fmaf(df, df, acc);
-            df = xq.w - c4.w;
+            df = xq.w - c3;
             acc = fmaf(df, df, acc);
           }
         }
@@ -236,17 +290,20 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
         bool keep = false;
         if (slot[u] >= 0) {
           const float P = sh.part[slot[u]] + sum;
-          const float lbp = f32_round_down((double)P * (1.0 - rel));
-          if ((double)P * (1.0 - rel) > ub) {
-            if (jj == 0) sh.lb[slot[u]] = lbp;
-          } else if (last) {
+          const double lo = SH ? pd_lower(P, rel, eps[sh.cand[slot[u]]]) : (double)P * (1.0 - rel);
+          if (lo > ub) {
+            if (jj == 0) sh.lb[slot[u]] = f32_round_down(lo);
+          } else if (last && !SH) {
             if (jj == 0) {
               sh.full[slot[u]] = P;
-              sh.lb[slot[u]] = lbp;
+              sh.lb[slot[u]] = f32_round_down(lo);
             }
           } else {
             keep = true;
-            if (jj == 0) sh.part[slot[u]] = P;
+            if (jj == 0) {
+              sh.part[slot[u]] = P;
+              if (last) sh.lb[slot[u]] = f32_round_down(lo);
+            }
           }
         }
         const uint64_t km = __ballot(keep && jj == 0);
@@ -258,56 +315,88 @@ __device__ inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
     A = nA;
     buf ^= 1;
   }
-  // best and second best over the full distances (lane t reads slot t; the
-  // tie rule makes the result independent of the order of the fold)
-  const float fl = lane <= A0 ? sh.full[lane] : FLT_MAX;
-  const int ql = lane <= A0 ? sh.cand[lane] : -1;
-  for (uint64_t F = __ballot(lane > np && fl != FLT_MAX); F; F &= F - 1) {
-    const int t = (int)__builtin_ctzll(F);
-    const float dq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fl), t));
-    const int qq = __builtin_amdgcn_readlane(ql, t);
-    if (qq == q1) continue;  // a cluster held by several entries
-    if (dq < b1 || (dq == b1 && qq < q1)) {
-      b2 = fminf(b2, b1);
-      b1 = dq;
-      q1 = qq;
-    } else {
-      b2 = fminf(b2, dq);
+  if (SH && A > 0) {
+    // the survivors' shadow distances bracket their distances: only those
+    // whose lower bound is within the smallest upper bound (and ub) can be
+    // the closest or tie with it
+    const int sl = lane < A ? sh.al[buf][lane] : -1;
+    double lo = DBL_MAX, hi = DBL_MAX;
+    if (sl >= 0) {
+      const float P = sh.part[sl];
+      const float e = eps[sh.cand[sl]];
+      lo = pd_lower(P, rel, e);
+      hi = pd_upper(P, rel, e);
     }
-  }
-  const double thr = (double)b1 * (1.0 + rel) / (1.0 - rel) + 1e-30;
-  int res = q1;
-  double dres = (double)b1 * (1.0 + rel) + 1e-30;  // upper bound of the chosen squared distance
-  if ((double)b2 <= thr) {
-    // float64 re-evaluation of every survivor inside the margin
-    double m64 = DBL_MAX, cur64 = -1.0;
-    int q64 = -1;
-    for (uint64_t F = __ballot(fl != FLT_MAX && (double)fl <= thr); F; F &= F - 1) {
-      const int t = (int)__builtin_ctzll(F);
-      const int qq = __builtin_amdgcn_readlane(ql, t);
-      float c[8];
-      load_row<8>(c, C + (int64_t)qq * d, lane, d, vec_c);
-      double acc = 0.0;
+    double m = hi;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const double df = (double)sh.x[lane * 8 + e] - (double)c[e];
-        acc = fma(df, df, acc);
-      }
-      const double e64 = group_sum<64>(acc);
-      if (qq == cur) cur64 = e64;
-      if (e64 < m64 || (e64 == m64 && qq < q64)) {
-        m64 = e64;
-        q64 = qq;
-      }
-    }
-    res = (cur64 >= 0.0 && cur64 == m64) ? cur : q64;
-    dres = m64 * (1.0 + 0x1p-40) + 1e-300;
+    for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+    m = fmin(m, ub);
+    const bool stay = sl >= 0 && lo <= m;
+    const uint64_t M = __ballot(stay);
+    if (stay) sh.al[buf ^ 1][__popcll(M & lanes_below())] = sl;
+    A = __popcll(M);
+    buf ^= 1;
+    wave_lds_sync();
+  }
+  // the remaining survivors' float32 distances
+  if (A > 0) {
+    pd_exact(sh, A, [&](int e) { return sh.al[buf][e]; }, C, d, vec_c, rel);
+    wave_lds_sync();
   }
   PDResult r;
-  r.label = res;
-  r.u = f32_round_up(sqrt(dres) * (1.0 + 0x1p-50));
   r.lb = 0.f;
-  if (myslot >= 0 && mine != res) {
+  {
+    // best and second best over the full distances (lane t reads slot t; the
+    // tie rule makes the result independent of the order of the fold)
+    const float fl = lane <= A0 ? sh.full[lane] : FLT_MAX;
+    const int ql = lane <= A0 ? sh.cand[lane] : -1;
+    float b1 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(fl))), b2 = FLT_MAX;
+    int q1 = cur;
+    for (uint64_t F = __ballot(lane >= 1 && fl != FLT_MAX); F; F &= F - 1) {
+      const int t = (int)__builtin_ctzll(F);
+      const float dq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fl), t));
+      const int qq = __builtin_amdgcn_readlane(ql, t);
+      if (qq == q1) continue;  // a cluster held by several entries
+      if (dq < b1 || (dq == b1 && qq < q1)) {
+        b2 = fminf(b2, b1);
+        b1 = dq;
+        q1 = qq;
+      } else {
+        b2 = fminf(b2, dq);
+      }
+    }
+    const double thr = (double)b1 * (1.0 + rel) / (1.0 - rel) + 1e-30;
+    int res = q1;
+    double dres = (double)b1 * (1.0 + rel) + 1e-30;  // upper bound of the chosen squared distance
+    if ((double)b2 <= thr) {
+      // float64 re-evaluation of every survivor inside the margin
+      double m64 = DBL_MAX, cur64 = -1.0;
+      int q64 = -1;
+      for (uint64_t F = __ballot(fl != FLT_MAX && (double)fl <= thr); F; F &= F - 1) {
+        const int t = (int)__builtin_ctzll(F);
+        const int qq = __builtin_amdgcn_readlane(ql, t);
+        float c[8];
+        load_row<8>(c, C + (int64_t)qq * d, lane, d, vec_c);
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const double df = (double)sh.x[lane * 8 + e] - (double)c[e];
+          acc = fma(df, df, acc);
+        }
+        const double e64 = group_sum<64>(acc);
+        if (qq == cur) cur64 = e64;
+        if (e64 < m64 || (e64 == m64 && qq < q64)) {
+          m64 = e64;
+          q64 = qq;
+        }
+      }
+      res = (cur64 >= 0.0 && cur64 == m64) ? cur : q64;
+      dres = m64 * (1.0 + 0x1p-40) + 1e-300;
+    }
+    r.label = res;
+    r.u = f32_round_up(sqrt(dres) * (1.0 + 0x1p-50));
+  }
+  if (myslot >= 0 && mine != r.label) {
     const float lq = sh.lb[myslot];
     r.lb = lq == FLT_MAX ? 0.f : f32_round_down(sqrt((double)lq) * (1.0 - 0x1p-50));
   }
@@ -332,14 +421,15 @@ __device__ inline int pd_candidate(int lane, int64_t i, int cur, const int* __re
 // Full sweep: block b takes pb consecutive positions of `order` (or of the
 // identity), wave w of it the positions w, w+4, ...  Same arguments and
 // outputs as k_assign without best distances.
-template <int GL>
+template <int GL, bool SH>
 __global__ __launch_bounds__(256) void k_assign_pd(
     const float* __restrict__ X, int n, int d, int64_t ldx, const float* __restrict__ C, int k,
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
     unsigned long long* __restrict__ moved_acc, unsigned long long* __restrict__ eval_acc,
     const int* __restrict__ order, int nchunks, int pb, double rel, int vec_x, int vec_c,
     const int* __restrict__ job_of, const int* __restrict__ kbase, const uint8_t* __restrict__ act_in,
-    uint8_t* __restrict__ act_out, float* __restrict__ bnd_u, float* __restrict__ bnd_lb) {
+    uint8_t* __restrict__ act_out, float* __restrict__ bnd_u, float* __restrict__ bnd_lb,
+    const uint16_t* __restrict__ Cb, const float* __restrict__ ceps, int vec_b) {
   __shared__ PDWave sh[4];
   __shared__ unsigned int block_moved, block_eval;
   if (threadIdx.x == 0) {
@@ -380,7 +470,8 @@ __global__ __launch_bounds__(256) void k_assign_pd(
         }
         continue;
       }
-      const PDResult r = pd_decide<GL>(sh[w], X + i * ldx, d, vec_x, C, vec_c, cur, cv, rel, dense, false);
+      const PDResult r = pd_decide<GL, SH>(sh[w], X + i * ldx, d, vec_x, C, vec_c, Cb, ceps, vec_b, cur, cv, rel, false,
+                                           true);
       if (bnd_u && lane <= kappa) bnd_lb[i * (kappa + 1) + lane] = r.lb;
       if (lane == 0) {
         lab_out[i] = r.label;
@@ -407,7 +498,7 @@ __global__ __launch_bounds__(256) void k_assign_pd(
 // of the candidate clusters) are issued for all NS samples before any is
 // used, then the samples are decided one after the other.  Same outputs as
 // k_assign_list.
-template <int GL, int NS>
+template <int GL, int NS, bool SH>
 __global__ __launch_bounds__(256) void k_assign_list_pd(
     const float* __restrict__ X, int d, int64_t ldx, const float* __restrict__ C, int k,
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
@@ -415,7 +506,8 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
     const int32_t* __restrict__ list, const int32_t* __restrict__ count, double rel, int vec_x, int vec_c,
     const int* __restrict__ job_of, const int* __restrict__ kbase, uint8_t* __restrict__ act_out,
     int64_t* __restrict__ n_listed, const int32_t* __restrict__ cdirty, float* __restrict__ bnd_u,
-    float* __restrict__ bnd_lb, const float* __restrict__ delta) {
+    float* __restrict__ bnd_lb, const float* __restrict__ delta, const uint16_t* __restrict__ Cb,
+    const float* __restrict__ ceps, int vec_b) {
   __shared__ PDWave sh[4];
   __shared__ unsigned int block_moved, block_eval;
   if (threadIdx.x == 0) {
@@ -532,7 +624,9 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
           }
         }
       }
-      const PDResult r = pd_decide<GL>(sh[w], X + i * ldx, d, vec_x, C, vec_c, own, c, rel, dn, skip);
+      // (a listed sample mostly stays: no pilot)
+      const PDResult r = pd_decide<GL, SH>(sh[w], X + i * ldx, d, vec_x, C, vec_c, Cb, ceps, vec_b, own, c, rel, skip,
+                                           false);
       if (bnd_u && lane <= kappa) {
         // skipped entries keep their drifted bounds (the chosen cluster is at
         // least as close as the own one, so they remain valid lower bounds)
@@ -559,12 +653,43 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
 
 }  // namespace
 
-// Relative error bound used by the wide kernel: 8 products per lane, six
-// levels of lane reduction for the own distance, or three levels per chunk
-// plus up to eight chunk additions; twice the worst case.
+// Relative error bound used by the wide kernel, in units of 2^-24 to first
+// order: a rounded difference squared (2) plus the products summed per lane
+// and the reduction levels; full distances 8 + 6, float32 chunks 8 + 3 plus up
+// to eight chunk additions, bfloat16 chunks 16 + 3 plus up to four: at most
+// 25, and the bound is twice that.
 static double pd_rel() { return (8.0 + 8.0 + 6.0 + 3.0) * 0x1p-23; }
 
 bool ks_assign_pd_ok(int32_t d, int32_t kappa) { return d > 256 && d <= 512 && kappa <= 63; }
+
+// bfloat16 shadow of centroid rows (all, or those with dirty[r] set): one
+// wavefront per row; eps[r] = ||c_r - bf16(c_r)|| rounded up (every
+// difference is exact in float32, its square in float64).
+__global__ __launch_bounds__(256) void k_c_shadow(const float* __restrict__ C, int32_t K, int d,
+                                                  const int32_t* __restrict__ dirty, uint16_t* __restrict__ Cb,
+                                                  float* __restrict__ eps) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < K; r += (int64_t)gridDim.x * 4) {
+    if (dirty && !dirty[r]) continue;  // wave-uniform
+    double e2 = 0.0;
+    for (int t = lane; t < d; t += 64) {
+      const float c = C[r * d + t];
+      const uint16_t h = bf16_rne(c);
+      Cb[r * d + t] = h;
+      const double df = (double)(c - __uint_as_float((uint32_t)h << 16));
+      e2 = fma(df, df, e2);
+    }
+    e2 = wave_sum(e2);
+    if (lane == 0) eps[r] = f32_round_up(sqrt(e2) * (1.0 + 0x1p-40));
+  }
+}
+
+knnkm_status ks_c_shadow(knnkm_ctx* ctx, const float* C, int32_t K, int32_t d, const int32_t* dirty, uint16_t* Cb,
+                         float* eps) {
+  if (K <= 0) return KNNKM_OK;
+  k_c_shadow<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(C, K, d, dirty, Cb, eps);
+  return knnkm_check(ctx, "bfloat16 centroid shadow");
+}
 
 knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, const float* C,
                           int32_t k, const int32_t* G_ids, int32_t kappa, const int32_t* labels_in,
@@ -572,32 +697,47 @@ knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, 
                           const int32_t* order, const int32_t* job_of, const int32_t* kbase,
                           const uint8_t* act_in, uint8_t* act_out, const int32_t* list, const int32_t* list_count,
                           int64_t* n_listed, const int32_t* cdirty, int pb, float* bnd_u, float* bnd_lb,
-                          const float* delta) {
+                          const float* delta, const uint16_t* Cb, const float* ceps) {
   if ((bnd_u != nullptr) != (bnd_lb != nullptr) || (list && bnd_u && cdirty && !delta))
     return knnkm_fail(ctx, KNNKM_EINVAL, "knn_assign (wide rows): incomplete drift bounds");
+  if ((Cb != nullptr) != (ceps != nullptr))
+    return knnkm_fail(ctx, KNNKM_EINVAL, "knn_assign (wide rows): bfloat16 shadow without its bounds");
   const bool vec_x = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0) && (d % 4 == 0);
   const bool vec_c = (d % 4 == 0) && ((uintptr_t)C % 16 == 0);
+  const bool vec_b = (d % 8 == 0) && ((uintptr_t)Cb % 16 == 0);
   const double rel = pd_rel();
   if (list) {
     const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
     // listed samples interleaved per wavefront: 2 unless the context fixes
     // the assignment shape to one sample per group
-#define LPD(NS)                                                                                               \
-  k_assign_list_pd<8, NS><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
+#define LPD(NS, SH)                                                                                           \
+  k_assign_list_pd<8, NS, SH><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
                                                         acc, eacc, list, list_count, rel, vec_x ? 1 : 0,      \
                                                         vec_c ? 1 : 0, job_of, kbase, act_out, n_listed,      \
-                                                        cdirty, bnd_u, bnd_lb, delta)
-    if (ctx->assign_gs == 1)
-      LPD(1);
-    else
-      LPD(2);
+                                                        cdirty, bnd_u, bnd_lb, delta, Cb, ceps, vec_b ? 1 : 0)
+    if (ctx->assign_gs == 1) {
+      if (Cb)
+        LPD(1, true);
+      else
+        LPD(1, false);
+    } else {
+      if (Cb)
+        LPD(2, true);
+      else
+        LPD(2, false);
+    }
 #undef LPD
     return knnkm_check(ctx, "knn_assign (wide rows, active set)");
   }
   const int nchunks = (int)((n + pb - 1) / pb);
   const int grid = ((nchunks + 7) / 8) * 8;
-  k_assign_pd<8><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc,
+if (Cb)
+      k_assign_pd<8, true><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc,
                                                 eacc, order, nchunks, pb, rel, vec_x ? 1 : 0, vec_c ? 1 : 0, job_of,
-                                                kbase, act_in, act_out, bnd_u, bnd_lb);
+                                                kbase, act_in, act_out, bnd_u, bnd_lb, Cb, ceps, vec_b ? 1 : 0);
+  else
+      k_assign_pd<8, false><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc,
+                                                eacc, order, nchunks, pb, rel, vec_x ? 1 : 0, vec_c ? 1 : 0, job_of,
+                                                kbase, act_in, act_out, bnd_u, bnd_lb, Cb, ceps, vec_b ? 1 : 0);
   return knnkm_check(ctx, "knn_assign (wide rows)");
 }

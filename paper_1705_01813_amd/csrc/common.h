@@ -44,6 +44,7 @@ struct knnkm_ctx {
   bool autotune = true;
   bool active_sets = true;  // fit sweeps look only at samples that can change
   bool wide_pd = true;      // wide rows: early-abandoned partial distances in the assignment
+  bool pd_shadow = true;    // ... reading a bfloat16 shadow of the centroids in the build and fit sweeps
   int tm_finish_max = 1024;  // two-means subtrees up to this size finished by one block (0: off)
   int assign_gs = 0, assign_pb = 64, assign_lazy = 0;  // forced assignment shape (gs = 0: automatic)
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
@@ -135,6 +136,11 @@ __device__ inline float f32_round_up(double v) {
   return f;
 }
 // float32 not above a non-negative double (0 for v <= 0)
+// float32 -> bfloat16 bit pattern, round to nearest even (finite values)
+__device__ inline uint16_t bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
 __device__ inline float f32_round_down(double v) {
   if (v <= 0.0) return 0.f;
   float f = (float)v;
@@ -219,24 +225,30 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        int64_t* n_active = nullptr, int32_t* list_count = nullptr,
                        int32_t* list_count_other = nullptr, bool zero_moved = true,
                        const int32_t* cdirty = nullptr, float* bnd_u = nullptr, float* bnd_lb = nullptr,
-                       const float* cdelta = nullptr);
-// Wide rows (256 < d <= 512, kappa <= 63): one wavefront per sample with
-// early-abandoned partial distances.  list != null: the active-set sweep over
-// the listed positions (list_count entries); else a full sweep in `order`
-// (pb positions per block).  Same decisions and flags as the narrow kernels.
+                       const float* cdelta = nullptr, const uint16_t* Cb = nullptr, const float* ceps = nullptr);
 // Exact all-pairs refinement of the clusters with smin < s <= smax members
 // (smax <= 128; one block per cluster, rows of the graph updated in place).
 knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, int32_t kappa, int32_t k,
                              const int32_t* offsets, const int32_t* members, int32_t smin, int32_t smax,
                              bool vec, int32_t* G_ids, float* G_d2);
+// Wide rows (256 < d <= 512, kappa <= 63): one wavefront per sample with
+// early-abandoned partial distances.  list != null: the active-set sweep over
+// the listed positions (list_count entries); else a full sweep in `order`
+// (pb positions per block).  Same decisions and flags as the narrow kernels.
+// Cb/ceps (nullable together): bfloat16 shadow of C and its row bounds
+// (ks_c_shadow), read for the early-abandon steps.
 bool ks_assign_pd_ok(int32_t d, int32_t kappa);
+// bfloat16 shadow Cb (K x d) of the centroid rows of C, all or those with
+// dirty[r] set, and eps[r] >= ||c_r - bf16(c_r)||.
+knnkm_status ks_c_shadow(knnkm_ctx* ctx, const float* C, int32_t K, int32_t d, const int32_t* dirty, uint16_t* Cb,
+                         float* eps);
 knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, const float* C,
                           int32_t k, const int32_t* G_ids, int32_t kappa, const int32_t* labels_in,
                           int32_t* labels_out, unsigned long long* acc, unsigned long long* eacc,
                           const int32_t* order, const int32_t* job_of, const int32_t* kbase,
                           const uint8_t* act_in, uint8_t* act_out, const int32_t* list, const int32_t* list_count,
                           int64_t* n_listed, const int32_t* cdirty, int pb, float* bnd_u, float* bnd_lb,
-                          const float* delta);
+                          const float* delta, const uint16_t* Cb = nullptr, const float* ceps = nullptr);
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
                          int32_t* labels);
@@ -276,7 +288,8 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off,
                           const int32_t* rev_src, uint8_t* act_out, int32_t* dirty_clear,
-                          float* delta, int64_t* mass = nullptr);
+                          float* delta, int64_t* mass = nullptr, uint16_t* Cb = nullptr,
+                          float* ceps = nullptr);
 // Active-set marks of the samples moved between cur and nxt and of the rows
 // listing them (reverse lists of the graph); moved labels copied into cur.
 knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,

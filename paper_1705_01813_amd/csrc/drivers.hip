@@ -286,14 +286,24 @@ static knnkm_status build_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
     KNNKM_WS(ctx, mem, int32_t, "kb_members", n);
     KNNKM_WS(ctx, C, float, "kb_centroids", (int64_t)K0 * d);
     KNNKM_WS(ctx, nrm, float, "kb_norms", n);
+    // wide rows: the bfloat16 shadow the assignment's early-abandon steps read
+    uint16_t* Cb = nullptr;
+    float* ceps = nullptr;
+    if (ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense && ctx->pd_shadow) {
+      Cb = (uint16_t*)knnkm_ws(ctx, "kb_cshadow", sizeof(uint16_t) * (size_t)K0 * d);
+      ceps = (float*)knnkm_ws(ctx, "kb_ceps", sizeof(float) * (size_t)K0);
+      if (!Cb || !ceps) return KNNKM_ENOMEM;
+    }
     KNNKM_TRY(ks_row_norms(ctx, X, n, d, ldx, nrm));
     for (int t = 0; t < p->tau; ++t) {
       KNNKM_TRY(ks_twomeans_multi(ctx, X, d, ldx, J.n_host, k0, J.m > 1 ? J.seeds : nullptr, J.seed_host[0], t,
                                   p->bisect_iters, lab));
       KNNKM_TRY(ks_label_sort(ctx, lab, n, K0, counts, off, mem));
       KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K0, counts, off, mem, C, nullptr, nullptr));
+      if (Cb) KNNKM_TRY(ks_c_shadow(ctx, C, K0, d, nullptr, Cb, ceps));
       KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, K0, G_ids, kappa, lab, lab2, nullptr, nullptr, mem,
-                          J.m == 1 && all_dense, J.job_of, k0_32, KS_USE_BUILD));
+                          J.m == 1 && all_dense, J.job_of, k0_32, KS_USE_BUILD, nullptr, nullptr, nullptr, nullptr,
+                          nullptr, nullptr, true, nullptr, nullptr, nullptr, nullptr, Cb, ceps));
       KNNKM_TRY(ks_refine(ctx, X, n, d, ldx, lab2, K0, p->precision, G_ids, G_d2, kappa, nrm));
     }
   }
@@ -440,6 +450,15 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   // clusters that the triangle inequality still rules out need no distance.
   const bool drift = use_act && ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense;
   float *bnd_u = nullptr, *bnd_lb = nullptr, *cdelta = nullptr;
+  // and the bfloat16 shadow of the centroids read by the early-abandon steps
+  uint16_t* Cb = nullptr;
+  float* ceps = nullptr;
+  if (ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense && ctx->pd_shadow) {
+    Cb = (uint16_t*)knnkm_ws(ctx, "fit_cshadow", sizeof(uint16_t) * (size_t)K * d);
+    ceps = (float*)knnkm_ws(ctx, "fit_ceps", sizeof(float) * (size_t)K);
+    if (!Cb || !ceps) return KNNKM_ENOMEM;
+    KNNKM_TRY(ks_c_shadow(ctx, C, K, d, nullptr, Cb, ceps));
+  }
   if (drift) {
     bnd_u = (float*)knnkm_ws(ctx, "fit_bnd_u", sizeof(float) * (size_t)n);
     bnd_lb = (float*)knnkm_ws(ctx, "fit_bnd_lb", sizeof(float) * (size_t)n * (kappa + 1));
@@ -457,7 +476,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
                      J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT, ev, first ? nullptr : act_for(cu),
                      nullptr, ac, cnt_for(cu), cnt_for(nx), false, first ? nullptr : dirty_for(cu), bnd_u,
-                     bnd_lb, first ? nullptr : cdelta);
+                     bnd_lb, first ? nullptr : cdelta, Cb, ceps);
   };
   // The first sweep moves a large share of the samples away from the
   // initial partition: its update rebuilds the sums from a label sort and
@@ -475,12 +494,13 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       // every centroid was recomputed
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(nx), K, 1));
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(cu), K, 0));
+      if (Cb) KNNKM_TRY(ks_c_shadow(ctx, C, K, d, nullptr, Cb, ceps));
       if (use_act)
         KNNKM_TRY(ks_mark_dirty(ctx, n, nx, dirty_for(nx), rev_off, rev_src, act_for(nx), nullptr, 0, J.job_of, k32,
                                 kappa));
     } else {
       KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty_for(nx), C, Iterm, rev_off, rev_src,
-                             act_for(nx), dirty_for(cu), cdelta, dmass));
+                             act_for(nx), dirty_for(cu), cdelta, dmass, Cb, ceps));
       // scattered marks while the dirty clusters' members and the rows
       // listing them stay below about 2n; every sample beyond that
       if (use_act)

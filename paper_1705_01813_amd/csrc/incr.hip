@@ -352,14 +352,16 @@ __global__ void k_rev_fill(const int32_t* __restrict__ G, int64_t ne, int64_t n,
 // for the next sweep's assignment): centroid (unchanged when empty) and the
 // Eqn. 2 term; one wavefront per cluster.  dirty_clear, the previous
 // sweep's flags, is cleared on the way; mass (nullable, cleared before)
-// receives the number of members of all dirty clusters.
+// receives the number of members of all dirty clusters; Cb/ceps (nullable)
+// the bfloat16 shadow of each new centroid and its bound.
 __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict__ D, int32_t K, int d,
                                                      const int32_t* __restrict__ cs,
                                                      const int32_t* __restrict__ counts,
                                                      const int32_t* __restrict__ dirty,
                                                      int32_t* __restrict__ dirty_clear, float* __restrict__ C,
                                                      double* __restrict__ Iterm, float* __restrict__ delta,
-                                                     unsigned long long* __restrict__ mass) {
+                                                     unsigned long long* __restrict__ mass, uint16_t* __restrict__ Cb,
+                                                     float* __restrict__ ceps) {
   const int lane = threadIdx.x & 63;
   for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < K; r += (int64_t)gridDim.x * 4) {
     if (lane == 0) dirty_clear[r] = 0;
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict_
     const int cnt = counts[r];
     if (mass && lane == 0 && cnt > 0) atomicAdd(mass, (unsigned long long)cnt);
     const int s = cs[r];
-    double sq = 0.0, mv = 0.0;
+    double sq = 0.0, mv = 0.0, e2 = 0.0;
     for (int t = lane; t < d; t += 64) {
       const int64_t e = r * d + t;
       const double v = fx_to_double(D[2 * e + 1], D[2 * e], s);
@@ -378,10 +380,20 @@ __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict_
           mv = fma(df, df, mv);
         }
         C[e] = c;
+        if (Cb) {
+          const uint16_t h = bf16_rne(c);
+          Cb[e] = h;
+          const double dq = (double)(c - __uint_as_float((uint32_t)h << 16));  // exact
+          e2 = fma(dq, dq, e2);
+        }
       }
       sq = fma(v, v, sq);
     }
     sq = wave_sum(sq);
+    if (Cb && cnt > 0) {
+      e2 = wave_sum(e2);
+      if (lane == 0) ceps[r] = f32_round_up(sqrt(e2) * (1.0 + 0x1p-40));
+    }
     if (lane == 0) Iterm[r] = cnt > 0 ? sq / (double)cnt : 0.0;
     if (delta) {
       mv = wave_sum(mv);
@@ -435,7 +447,8 @@ knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32
 knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, int32_t* cur,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off, const int32_t* rev_src,
-                          uint8_t* act_out, int32_t* dirty_clear, float* delta, int64_t* mass) {
+                          uint8_t* act_out, int32_t* dirty_clear, float* delta, int64_t* mass, uint16_t* Cb,
+                          float* ceps) {
   if (mass) KNNKM_TRY(ks_fill_i64(ctx, mass, 1, 0));
 #define MV(DD)                                                                                           \
   k_fx_moves<DD><<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty, \
@@ -450,7 +463,7 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
     MV(8);
 #undef MV
   k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, dirty, dirty_clear, C, Iterm,
-                                                                delta, (unsigned long long*)mass);
+                                                                delta, (unsigned long long*)mass, Cb, ceps);
   return knnkm_check(ctx, "incremental update");
 }
 

@@ -377,7 +377,9 @@ def knnkm_enable_subtree_finish(ctx, on=True):
 
 
 def knnkm_enable_partial_distances(ctx, on=True):
-    _chk(ctx.handle, lib().knnkm_enable_partial_distances(ctx.handle, 1 if on else 0))
+    """on: False/0 off, True/1 on (bfloat16 centroid shadow in the build and
+    fit sweeps), 2 on with float32 centroids only."""
+    _chk(ctx.handle, lib().knnkm_enable_partial_distances(ctx.handle, int(on)))
 
 
 def knnkm_autotune(ctx, on=True):

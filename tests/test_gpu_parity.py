@@ -1151,7 +1151,8 @@ def test_assign_wide_near_ties(ctx):
 def test_fit_wide_partial_distances_same_bits(ctx, d):
     """A fit on wide rows (the library's graph, active sets on) gives the same
     labels, centroids, counts and trace with the partial-distance kernels on
-    and off, and the oracle's labels and trace."""
+    (reading the bfloat16 centroid shadow, or float32 centroids only) and
+    off, and the oracle's labels and trace."""
     n, k, kappa, T = 6000, 300, 50, 8
     say("fit wide", d)
     X = datagen.mixture(n, d, 500, seed=d, sigma=0.5, centre="normal")
@@ -1161,25 +1162,29 @@ def test_fit_wide_partial_distances_same_bits(ctx, d):
     gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
     knnkm.knn_build(ctx, Xd, p, gi, gd)
     res = {}
-    for pd in (True, False):
-        knnkm.knnkm_enable_partial_distances(ctx, pd)
-        lab = torch.empty(n, dtype=torch.int32, device=DEV)
-        C = torch.empty((k, d), dtype=torch.float32, device=DEV)
-        cnt = torch.empty(k, dtype=torch.int32, device=DEV)
-        tr, it = knnkm.knn_kmeans_fit(ctx, Xd, k, gi, p, lab, C, cnt)
-        res[pd] = (host(lab), host(C), host(cnt), tr)
-    knnkm.knnkm_enable_partial_distances(ctx, True)
-    for a, b in zip(res[True], res[False]):
-        assert np.array_equal(a, b)
+    try:
+        for pd in (1, 2, 0):
+            knnkm.knnkm_enable_partial_distances(ctx, pd)
+            lab = torch.empty(n, dtype=torch.int32, device=DEV)
+            C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+            cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+            tr, it = knnkm.knn_kmeans_fit(ctx, Xd, k, gi, p, lab, C, cnt)
+            res[pd] = (host(lab), host(C), host(cnt), tr)
+    finally:
+        knnkm.knnkm_enable_partial_distances(ctx, True)
+    for mode in (2, 0):
+        for a, b in zip(res[1], res[mode]):
+            assert np.array_equal(a, b), mode
     w_lab, _, _, w_tr, _, _ = gkmeans.fit(X, k, host(gi), T, seed=4)
-    assert np.array_equal(res[True][0], w_lab)
-    np.testing.assert_allclose(res[True][3], w_tr, rtol=1e-9)
+    assert np.array_equal(res[1][0], w_lab)
+    np.testing.assert_allclose(res[1][3], w_tr, rtol=1e-9)
 
 
 def test_batch_wide_rows_with_small_jobs(ctx):
     """A batch of wide-row jobs, some with fewer clusters than kappa (every
-    cluster of the job is a candidate): batched equals alone and equals the
-    partial-distance kernels switched off."""
+    cluster of the job is a candidate): graph and fit equal those with the
+    partial-distance kernels reading float32 centroids only or switched off,
+    and the oracle's."""
     sizes = [120, 900, 64, 1500]
     d, kappa, T = 300, 16, 5
     say("batch wide rows", sizes)
@@ -1203,11 +1208,11 @@ def test_batch_wide_rows_with_small_jobs(ctx):
         return [host(t) for t in out] + [tr]
 
     try:
-        a, b = run(True), run(False)
+        a, b, c = run(1), run(0), run(2)
     finally:
         knnkm.knnkm_enable_partial_distances(ctx, True)
-    for u, v in zip(a, b):
-        assert np.array_equal(u, v)
+    for u, v, w in zip(a, b, c):
+        assert np.array_equal(u, v) and np.array_equal(u, w)
     k_off = np.concatenate([[0], np.cumsum(ks)])
     for q, Xq in enumerate(Xs):
         w_i, _ = knng.knn_build(Xq, kappa, xi=50, tau=2, seed=seeds[q])
