@@ -51,7 +51,7 @@ typedef enum {
 } knnkm_status;
 
 enum { KNNKM_FP32 = 0, KNNKM_BF16_RERANK = 1 };
-enum { KNNKM_INIT_TWOMEANS = 0, KNNKM_INIT_RANDOM = 1 };
+enum { KNNKM_INIT_TWOMEANS = 0, KNNKM_INIT_RANDOM = 1, KNNKM_INIT_LABELS = 2 };
 
 /* Limits of this implementation (KNNKM_EUNSUPPORTED beyond them). */
 #define KNNKM_MAX_D 512     /* dimensions per sample */
@@ -64,7 +64,8 @@ typedef struct {
   int32_t tau;          /* graph construction rounds (Alg. 3); default 10 */
   int32_t bisect_iters; /* Lloyd 2-means steps per bisection of Alg. 1; default 2 */
   int32_t precision;    /* KNNKM_FP32 or KNNKM_BF16_RERANK (pair filter of knn_build) */
-  int32_t init;         /* KNNKM_INIT_TWOMEANS (Alg. 2 start) or KNNKM_INIT_RANDOM */
+  int32_t init;         /* KNNKM_INIT_TWOMEANS (Alg. 2 start), KNNKM_INIT_RANDOM, or
+                           KNNKM_INIT_LABELS (knn_kmeans_fit only: resume) */
   int32_t max_iters;    /* fit iterations T; the paper runs 30 (Sec. 5.4) */
   int32_t early_stop;   /* 1: stop after an iteration that moved no sample (Sec. 1 convergence) */
   uint64_t seed;        /* keys every random draw (graph init, bisection seeds, random init) */
@@ -85,6 +86,13 @@ const char* knnkm_last_error(const knnkm_ctx* ctx);
 knnkm_status knnkm_default_params(knnkm_params* p);
 /* Device bytes currently held by the context workspace. */
 knnkm_status knnkm_workspace_bytes(const knnkm_ctx* ctx, int64_t* out);
+/* Planning estimate (host only, no context): an upper estimate of the
+ * workspace that knn_build followed by knn_kmeans_fit of one job of n rows
+ * of d dimensions into k clusters with params grows a fresh context to
+ * (the serving form charges its batches with the same formula).  Inputs and
+ * outputs (X, graph, labels, centroids, counts) are the caller's and not
+ * included.  KNNKM_EINVAL on out-of-range arguments. */
+knnkm_status knnkm_workspace_estimate(int64_t n, int32_t d, int32_t k, const knnkm_params* params, int64_t* out);
 
 /* Graph-restricted assignment, one Jacobi sweep (Alg. 2 candidate collection,
  * Lloyd form of Sec. 4.2 "GK-means^-").
@@ -174,7 +182,14 @@ knnkm_status knn_build(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
  * assignment), C_0 = their means; then for t = 1..max_iters: knn_assign with
  * G_ids, centroid update, distortion.  trace_host (max_iters+1 doubles, host)
  * receives E_0..E_T (Eqn. 4); iters_run_host the number of sweeps done.
- * Outputs labels (n), C (k x d), counts (k) on the device.  Synchronous. */
+ * Outputs labels (n), C (k x d), counts (k) on the device.  Synchronous.
+ * Resume: with init = KNNKM_INIT_LABELS the fit starts from the partition
+ * held in labels (input and output; every entry in [0, k), else
+ * KNNKM_EINVAL) and keeps the centroids in C of the clusters that partition
+ * leaves empty; C_0 is the means of the others.  A fit of T1 sweeps followed
+ * by one of T2 sweeps from its labels and C continues it: the same labels,
+ * centroids and counts as one fit of T1 + T2 sweeps (its trace continues
+ * from E_T1), up to the float64 summation order of the rebuilt sums. */
 knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                             int32_t k, const int32_t* G_ids, const knnkm_params* params,
                             int32_t* labels, float* C, int32_t* counts, double* trace_host,
@@ -191,7 +206,8 @@ knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d
  *  k_q), job q's clusters after those of jobs 0..q-1; trace_host (host,
  *  m x (max_iters+1)): E_0..E_T of job q at row q.  early_stop is ignored.
  *  Each job's results are bit-identical to running it alone through
- *  knn_build + knn_kmeans_fit with its seed.  Synchronous. */
+ *  knn_build + knn_kmeans_fit with its seed.  init = KNNKM_INIT_LABELS is
+ *  not accepted (KNNKM_EINVAL).  Synchronous. */
 knnkm_status knnkm_fit_batched(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, int32_t m,
                                const int64_t* n_off_host, const int32_t* k_host,
                                const uint64_t* seeds_host, const knnkm_params* params, int32_t* G_ids,

@@ -164,13 +164,19 @@ def init_labels(X, k, seed, init, iters=2):
     return labels, np.zeros((k, X.shape[1]), np.float32)
 
 
-def fit(X, k, G_ids, T, seed, init=INIT_TWOMEANS, bisect_iters=2, early_stop=False):
+def fit(X, k, G_ids, T, seed, init=INIT_TWOMEANS, bisect_iters=2, early_stop=False, labels0=None, C0=None):
     """GK-means^- fit.  labels_0 from the initialisation (Alg. 2 starts from
-    Alg. 1; the random form picks k distinct rows as seeds); C_0 = means of
+    Alg. 1; the random form picks k distinct rows as seeds), or given
+    (labels0, with C0 holding the centroids of the clusters it leaves empty:
+    the iterations of Alg. 2 continued from a partition); C_0 = means of
     labels_0.  For t = 1..T: assign with the graph, update, distortion.
     Returns (labels, C, counts, trace[E_0..E_T'], iters_run, moved list)."""
     X = np.asarray(X, np.float32)
-    labels, Cseed = init_labels(X, k, seed, init, bisect_iters)
+    if labels0 is not None:
+        labels = np.asarray(labels0, np.int64).copy()
+        Cseed = np.asarray(C0, np.float32).copy() if C0 is not None else np.zeros((k, X.shape[1]), np.float32)
+    else:
+        labels, Cseed = init_labels(X, k, seed, init, bisect_iters)
     C, counts, _ = centroid_update(X, labels, k, Cseed)
     trace = [distortion(X, C, labels)]
     moved_hist = []

@@ -180,7 +180,7 @@ static knnkm_status check_params(knnkm_ctx* ctx, const knnkm_params* p, const ch
   if (p->max_iters < 0) return knnkm_fail(ctx, KNNKM_EINVAL, "%s: max_iters must be >= 0", who);
   if (p->precision != KNNKM_FP32 && p->precision != KNNKM_BF16_RERANK)
     return knnkm_fail(ctx, KNNKM_EINVAL, "%s: unknown precision %d", who, p->precision);
-  if (p->init != KNNKM_INIT_TWOMEANS && p->init != KNNKM_INIT_RANDOM)
+  if (p->init != KNNKM_INIT_TWOMEANS && p->init != KNNKM_INIT_RANDOM && p->init != KNNKM_INIT_LABELS)
     return knnkm_fail(ctx, KNNKM_EINVAL, "%s: unknown init %d", who, p->init);
   return KNNKM_OK;
 }
@@ -360,11 +360,13 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     // exhaustive assignment to the seeds of the sample's own job
     KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, K, nullptr, K, nullptr, labels, nullptr, nullptr, nullptr, true,
                         J.job_of, k32));
-  } else {
+  } else if (p->init == KNNKM_INIT_TWOMEANS) {
     KNNKM_TRY(ks_twomeans_multi(ctx, X, d, ldx, J.n_host, kq, m > 1 ? J.seeds : nullptr, J.seed_host[0],
                                 KNNKM_ROUND_FIT, p->bisect_iters, labels));
     KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)C, (int64_t)K * d, 0));
   }
+  // KNNKM_INIT_LABELS: labels and the centroids of empty clusters are the
+  // caller's (checked by the entry point)
   KNNKM_WS(ctx, jmax, uint32_t, "fit_jmax", m);
   KNNKM_TRY(ks_row_stats(ctx, X, n, d, ldx, m, J.job_of, rowsq, jmax));
   k_range_sum<<<m, 1024, 0, ctx->stream>>>(rowsq, J.n_off, sxx);
@@ -615,6 +617,15 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   return KNNKM_OK;
 }
 
+// Resume: counts the labels outside [0, k).
+__global__ void k_check_labels(const int32_t* __restrict__ lab, int64_t n, int32_t k,
+                               unsigned long long* __restrict__ bad) {
+  unsigned long long c = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += (lab[i] < 0 || lab[i] >= k) ? 1ull : 0ull;
+  if (c) atomicAdd(bad, c);
+}
+
 extern "C" knnkm_status knnkm_enable_active_sets(knnkm_ctx* ctx, int32_t on) {
   if (!ctx) return KNNKM_EINVAL;
   ctx->active_sets = on != 0;
@@ -647,6 +658,16 @@ extern "C" knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n
   J.n_off_host = {0, n};
   J.seed_host = {p->seed};
   KNNKM_TRY(upload_jobs(ctx, J, "one"));
+  if (p->init == KNNKM_INIT_LABELS) {
+    KNNKM_WS(ctx, bad, int64_t, "fit_bad_labels", 1);
+    KNNKM_TRY(ks_fill_i64(ctx, bad, 1, 0));
+    k_check_labels<<<grid_for(n, 256, 4096), 256, 0, ctx->stream>>>(labels, n, k, (unsigned long long*)bad);
+    int64_t nbad = 0;
+    KNNKM_HIP(ctx, hipMemcpyAsync(&nbad, bad, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (nbad) return knnkm_fail(ctx, KNNKM_EINVAL, "knn_kmeans_fit: %lld input labels outside [0, %d)",
+                                (long long)nbad, k);
+  }
   KNNKM_WS(ctx, trace, double, "fit_trace", (int64_t)p->max_iters + 1);
   int it = 0;
   KNNKM_TRY(fit_impl(ctx, X, d, ldx, J, std::vector<int32_t>{k}, G_ids, p, labels, C, counts, trace, &it));
@@ -691,6 +712,8 @@ extern "C" knnkm_status knnkm_fit_batched(knnkm_ctx* ctx, const float* X, int32_
   if (m < 1 || !n_off_host || !k_host || !seeds_host)
     return knnkm_fail(ctx, KNNKM_EINVAL, "knnkm_fit_batched: need m >= 1 and job tables");
   KNNKM_TRY(check_params(ctx, p, "knnkm_fit_batched"));
+  if (p->init == KNNKM_INIT_LABELS)
+    return knnkm_fail(ctx, KNNKM_EINVAL, "knnkm_fit_batched: init from labels is knn_kmeans_fit only");
   const int kappa = p->kappa;
   if (kappa < 1 || kappa > KNNKM_MAX_KAPPA)
     return knnkm_fail(ctx, kappa < 1 ? KNNKM_EINVAL : KNNKM_EUNSUPPORTED, "knnkm_fit_batched: kappa=%d", kappa);

@@ -57,9 +57,20 @@ int64_t ws_estimate(int64_t n, int64_t d, int64_t k, int64_t k0, int64_t kappa, 
   b += 16 * d * (n / (1024 * 16) + kx + 2);  // two-means chunk partials
   b += 200 * (k + k0);                       // per-cluster tables and the tree plan
   b += 24 * d * k + 4 * n;                   // fit: float64 sums and fixed-point composite vectors
+  b += 4 * (kappa + 1) * n + 4 * n + 8 * n;  // fit: reverse graph lists, active list, flag arrays
+  b += 4 * (kappa + 2) * n + 4 * k;          // fit: drift bounds (wide rows)
+  b += 2 * d * (k + k0) + 4 * (k + k0);      // bfloat16 centroid shadows (wide rows)
   b += 64 * m + 16 * (T + 1) * m;            // job tables and traces
   b += 1 << 20;                              // scans, partial sums, small tables
   return b + b / 8 + (32 << 20);
+}
+
+extern "C" knnkm_status knnkm_workspace_estimate(int64_t n, int32_t d, int32_t k, const knnkm_params* p,
+                                                 int64_t* out) {
+  if (!p || !out || n < 1 || d < 1 || k < 1 || k > n || p->xi < 2 || p->kappa < 1) return KNNKM_EINVAL;
+  const int64_t k0 = p->tau > 0 ? std::max<int64_t>(1, n / p->xi) : 0;
+  *out = ws_estimate(n, d, k, k0, p->kappa, 1, std::max(0, p->max_iters));
+  return KNNKM_OK;
 }
 
 struct SJob {

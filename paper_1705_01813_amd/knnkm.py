@@ -14,14 +14,14 @@ LIB_PATH = os.path.join(_HERE, "libknnkm.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EAGAIN = 0, 1, 2, 3, 4, 5
 FP32, BF16_RERANK = 0, 1
-INIT_TWOMEANS, INIT_RANDOM = 0, 1
+INIT_TWOMEANS, INIT_RANDOM, INIT_LABELS = 0, 1, 2
 ROUND_FIT = 0xFFFF
 MAX_D, MAX_KAPPA = 512, 128
 
 # Entry points declared in include/knnkm.h (checked against the header by the tests).
 EXPORTS = [
     "knnkm_create", "knnkm_destroy", "knnkm_set_stream", "knnkm_last_error",
-    "knnkm_default_params", "knnkm_workspace_bytes", "knn_assign", "centroid_update",
+    "knnkm_default_params", "knnkm_workspace_bytes", "knnkm_workspace_estimate", "knn_assign", "centroid_update",
     "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
     "knn_kmeans_fit", "distortion_noalloc", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times", "knnkm_sweep_stats",
     "knnkm_fit_batched", "knnkm_enable_graphs", "knnkm_enable_active_sets", "knnkm_enable_subtree_finish",
@@ -125,6 +125,7 @@ def lib():
             "knnkm_set_stream": [P, P],
             "knnkm_default_params": [ctypes.POINTER(Params)],
             "knnkm_workspace_bytes": [P, ctypes.POINTER(i64)],
+            "knnkm_workspace_estimate": [i64, i32, i32, ctypes.POINTER(Params), ctypes.POINTER(i64)],
             "knn_assign": [P, P, i64, i32, i64, P, i32, P, i32, P, P, P, P],
             "centroid_update": [P, P, i64, i32, i64, P, i32, P, P, P],
             "distortion": [P, P, i64, i32, i64, P, i32, P, P],
@@ -322,6 +323,15 @@ def knn_build(ctx, X, params, G_ids, G_d2):
     st = lib().knn_build(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx, ctypes.byref(params),
                          _ptr(G_ids, torch.int32, "G_ids"), _ptr(G_d2, torch.float32, "G_d2"))
     _chk(ctx.handle, st)
+
+
+def knnkm_workspace_estimate(n, d, k, params):
+    """Planning estimate of the workspace of knn_build + knn_kmeans_fit (bytes)."""
+    v = ctypes.c_int64()
+    st = lib().knnkm_workspace_estimate(n, d, k, ctypes.byref(params), ctypes.byref(v))
+    if st != OK:
+        raise KnnkmError(st, "knnkm_workspace_estimate: invalid arguments")
+    return v.value
 
 
 def knn_kmeans_fit(ctx, X, k, G_ids, params, labels, C, counts):

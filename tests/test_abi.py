@@ -110,6 +110,11 @@ def test_batched_validation(dry):
     assert call([0, 5, 200], [2, 5], [1, 2]) == knnkm.EINVAL       # job with fewer than kappa+1 rows
     assert call([0, 64, 200], [65, 5], [1, 2]) == knnkm.EINVAL     # k > n
     assert call([0, 64, 200], [0, 5], [1, 2]) == knnkm.EINVAL      # k < 1
+    p.init = knnkm.INIT_LABELS                                      # resume is knn_kmeans_fit only
+    assert call([0, 64, 200], [2, 5], [1, 2]) == knnkm.EINVAL
+    assert "knn_kmeans_fit only" in knnkm.lib().knnkm_last_error(h).decode()
+    p.init = 3
+    assert call([0, 64, 200], [2, 5], [1, 2]) == knnkm.EINVAL
 
 
 def test_assign_shape_validation(dry):
@@ -127,3 +132,15 @@ def test_subtree_finish_validation(dry):
     for on in (-1, 1025, 4096):
         assert _call("knnkm_enable_subtree_finish", h, on) == knnkm.EINVAL, on
     assert _call("knnkm_enable_subtree_finish", h, 1) == knnkm.OK
+
+
+def test_workspace_estimate_validation():
+    p = knnkm.default_params(kappa=10)
+    a = knnkm.knnkm_workspace_estimate(10_000, 32, 100, p)
+    b = knnkm.knnkm_workspace_estimate(1_000_000, 32, 100, p)
+    c = knnkm.knnkm_workspace_estimate(1_000_000, 512, 100, p)
+    assert 0 < a < b < c
+    for n, d, k in [(0, 32, 1), (100, 0, 1), (100, 32, 0), (100, 32, 101)]:
+        with pytest.raises(knnkm.KnnkmError) as e:
+            knnkm.knnkm_workspace_estimate(n, d, k, p)
+        assert e.value.status == knnkm.EINVAL

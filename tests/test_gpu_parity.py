@@ -488,6 +488,71 @@ def test_fit_parity(ctx, init):
     assert (np.diff(tr) <= 1e-12 * tr[0]).all()
 
 
+def test_fit_resume_continues_the_fit(ctx):
+    """Resume (init from labels): T1 sweeps, then T2 sweeps from the labels
+    and centroids they end with, equal one fit of T1 + T2 sweeps (integer
+    data: every sum is exact, so the rebuilt float64 sums equal the
+    fixed-point ones) and the oracle's fit resumed the same way; labels
+    outside [0, k) are rejected."""
+    n, d, k, kappa, T1, T2 = 6000, 32, 80, 10, 4, 5
+    say("fit resume", n, d, k, kappa, T1, T2)
+    X = datagen.mixture(n, d, 60, seed=41, lo=0.0, hi=255.0, sigma=20.0, clip=(0.0, 255.0), integer=True)
+    G, _ = knng.knn_build(X, kappa, xi=50, tau=2, seed=4)
+    Xd, Gd = dev(X), dev(G)
+
+    def run(T, init, lab=None, C=None):
+        p = knnkm.default_params(kappa=kappa, max_iters=T, seed=6, init=init)
+        lab = torch.empty(n, dtype=torch.int32, device=DEV) if lab is None else lab
+        C = torch.empty((k, d), dtype=torch.float32, device=DEV) if C is None else C
+        cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+        tr, it = knnkm.knn_kmeans_fit(ctx, Xd, k, Gd, p, lab, C, cnt)
+        return lab, C, cnt, tr
+
+    lab, C, cnt, tr = run(T1 + T2, knnkm.INIT_TWOMEANS)
+    l1, C1, _, t1 = run(T1, knnkm.INIT_TWOMEANS)
+    l1h, C1h = host(l1), host(C1)
+    l2, C2, c2, t2 = run(T2, knnkm.INIT_LABELS, l1, C1)
+    assert np.array_equal(host(l2), host(lab))
+    assert np.array_equal(host(C2), host(C))
+    assert np.array_equal(host(c2), host(cnt))
+    np.testing.assert_allclose(t2[0], t1[-1], rtol=1e-12)
+    np.testing.assert_allclose(t2[1:], tr[T1 + 1:], rtol=1e-12)
+    w_lab, w_C, w_cnt, w_tr, _, _ = gkmeans.fit(X, k, G, T2, seed=0, labels0=l1h, C0=C1h)
+    assert np.array_equal(host(l2), w_lab)
+    assert np.array_equal(host(c2), w_cnt)
+    assert np.array_equal(host(C2), w_C)
+    np.testing.assert_allclose(t2, w_tr, rtol=1e-9)
+    bad = torch.from_numpy(l1h.copy()).to(DEV)
+    bad[17] = k
+    with pytest.raises(knnkm.KnnkmError) as e:
+        run(2, knnkm.INIT_LABELS, bad, C1)
+    assert e.value.status == knnkm.EINVAL and "outside" in str(e.value)
+
+
+@pytest.mark.parametrize("n,d,k,kappa", [(6000, 32, 60, 10), (3000, 512, 100, 50), (2500, 300, 40, 20)])
+def test_workspace_estimate_bounds_a_build_and_fit(n, d, k, kappa):
+    """The planning estimate bounds the workspace a fresh context grows to in
+    knn_build + knn_kmeans_fit (narrow and wide rows)."""
+    say("workspace estimate", n, d, k, kappa)
+    X = dev(datagen.mixture(n, d, 40, seed=n + d, sigma=0.5, centre="normal"))
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=2, max_iters=5, seed=3)
+    c = knnkm.Context(0)
+    try:
+        gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+        gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+        knnkm.knn_build(c, X, p, gi, gd)
+        lab = torch.empty(n, dtype=torch.int32, device=DEV)
+        C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+        cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+        knnkm.knn_kmeans_fit(c, X, k, gi, p, lab, C, cnt)
+        held = c.workspace_bytes()
+    finally:
+        c.close()
+    est = knnkm.knnkm_workspace_estimate(n, d, k, p)
+    say("held", held, "estimate", est)
+    assert 0 < held <= est
+
+
 def test_assign_autotune_same_result(ctx):
     """The autotuner times every launch shape on the call's own data; the
     results do not depend on the shape it keeps."""

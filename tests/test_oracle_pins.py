@@ -236,6 +236,22 @@ def test_fit_distortion_never_increases():
             assert m2 == 0 and (l2 == lab).all()
 
 
+def test_fit_resumed_from_its_labels_continues_it():
+    """Alg. 2's iterations continued from a partition: T1 sweeps, then T2
+    sweeps from the labels and centroids they end with, are the T1 + T2
+    sweeps of one fit (an empty cluster keeps the centroid it had)."""
+    X = datagen.mixture(1500, 5, 30, seed=12)
+    G, _ = exact.brute_knn(X, 6)
+    k = 40  # more clusters than components: some empty out along the way
+    for init in (gkmeans.INIT_RANDOM, gkmeans.INIT_TWOMEANS):
+        lab, C, cnt, tr, _, mv = gkmeans.fit(X, k, G, 7, seed=5, init=init)
+        l1, C1, _, t1, _, _ = gkmeans.fit(X, k, G, 3, seed=5, init=init)
+        l2, C2, c2, t2, _, mv2 = gkmeans.fit(X, k, G, 4, seed=0, labels0=l1, C0=C1)
+        assert np.array_equal(l2, lab) and np.array_equal(C2, C) and np.array_equal(c2, cnt)
+        assert mv2 == mv[3:]
+        assert t2[0] == t1[-1] and np.array_equal(t2[1:], tr[4:])
+
+
 def test_random_init_labels_are_exhaustive_argmin():
     X = datagen.mixture(500, 4, 10, seed=11)
     lab0, C0 = gkmeans.init_labels(X, 10, 5, gkmeans.INIT_RANDOM)
