@@ -307,7 +307,7 @@ def bench_batching(m, sample, seed, log):
     }
 
 
-def bench_serving(seconds, seed, log, rate=None):
+def bench_serving(seconds, seed, log, rate=None, single_seconds=10.0):
     """The serving stream through the request loop (continuous batching, 4
     slots) and through the same loop restricted to one job at a time."""
     import threading
@@ -376,15 +376,25 @@ def bench_serving(seconds, seed, log, rate=None):
             "max_queued": st["max_queued"],
             "hbm_peak_charged_gb": st["bytes_peak"] / 1e9,
             "ws_overruns": st["ws_overruns"],
-            "keeps_up": span <= seconds * 1.05,
+            "keeps_up": span <= window[0] * 1.05,
         }
 
     rows = sum(int(X.shape[0]) for _, X, _, _ in jobs)
     log(f"serving: {len(jobs)} jobs ({rows} rows) over {seconds} s")
+    window = [seconds]  # arrival window of the jobs run() serves
     cont = run(4, 4096)
+    # one job at a time: the whole stream for short windows; for longer ones
+    # the jobs arriving in the first single_seconds (its throughput does not
+    # depend on the window; its queueing latency grows with it)
+    all_jobs = jobs
+    if single_seconds and single_seconds < seconds:
+        jobs = [j for j in all_jobs if j[0] < single_seconds]
+        window[0] = single_seconds
     single = run(1, 1)
+    single["sampled"] = (f"jobs arriving in the first {single_seconds:g} s ({len(jobs)} of {len(all_jobs)})"
+                         if len(jobs) < len(all_jobs) else "every job")
     return {
-        "workload": f"Poisson arrivals at {rate:g} jobs/s for {seconds:g} s ({len(jobs)} jobs, {rows} rows): "
+        "workload": f"Poisson arrivals at {rate:g} jobs/s for {seconds:g} s ({len(all_jobs)} jobs, {rows} rows): "
                     f"n = round(10^U[3,6]), d in {{64,128,256}}, k = n/100, kappa={C5['kappa']}, "
                     f"T={C5['T']}, tau={C5['tau']}, xi={C5['xi']}; rows are random slices of a per-d "
                     f"mixture pool in pinned host memory; HBM budget {C5['budget'] / 1e9:g} GB",
@@ -510,6 +520,58 @@ def cpu_baseline(ctx, X, G_ids, cfg, seed, budget_s, log):
     }
 
 
+def xi_sweep(n, seed, log, xis=(50, 100, 256, 512), kappa=50):
+    """One graph-refinement round (Alg. 3 inner loops) at d = 512 on n rows of
+    the 10M x 512 recipe, for cluster sizes xi: the clusters are a TwoMeans
+    partition into n / xi leaves, the graph the random initial lists.  Per xi
+    and screen precision: the round's time, the dense Gram flops of the
+    clusters (2 xi d per member), the rate against the MFMA peaks, and the
+    ceiling the round's bytes put on it (member rows and graph rows read once:
+    4d + 8 kappa per member)."""
+    import torch
+
+    from paper_1705_01813_amd import datagen, knnkm
+
+    dev = "cuda:0"
+    c = datagen.CONFIGS["c3"]
+    d = c["d"]
+    X = datagen.mixture_device(n, d, max(1, n // 10), seed, c["centre"], c["lo"], c["hi"], c["sigma"], c["clip"],
+                               c["integer"], device=dev)
+    ctx = knnkm.Context(0)
+    gi0 = torch.empty((n, kappa), dtype=torch.int32, device=dev)
+    gd0 = torch.empty((n, kappa), dtype=torch.float32, device=dev)
+    knnkm.knnkm_graph_init(ctx, X, kappa, seed, gi0, gd0)
+    lab = torch.empty(n, dtype=torch.int32, device=dev)
+    out = []
+    peaks = {"fp32": 157.3, "bf16": 2500.0}
+    for xi in xis:
+        k0 = max(1, n // xi)
+        knnkm.knnkm_twomeans(ctx, X, k0, seed, 0, 2, lab)
+        flops = 2.0 * d * float((torch.bincount(lab.long(), minlength=k0).double() ** 2).sum())
+        bytes_ = n * (4 * d + 8 * kappa)
+        row = {"xi": xi, "k0": k0, "gram_flops": flops, "bytes": bytes_, "flop_per_byte": flops / bytes_}
+        for name, prec in (("fp32", knnkm.FP32), ("bf16", knnkm.BF16_RERANK)):
+            gi, gd = gi0.clone(), gd0.clone()
+            knnkm.knnkm_graph_refine(ctx, X, lab, k0, prec, gi, gd)  # warm-up (same inputs)
+            gi.copy_(gi0)
+            gd.copy_(gd0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            knnkm.knnkm_graph_refine(ctx, X, lab, k0, prec, gi, gd)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            tf = flops / (ms * 1e-3) / 1e12
+            cap = min(1.0, (flops / bytes_) * HBM_PEAK_GBS / 1e3 / peaks[name])
+            row[name] = {"refine_ms": ms, "gram_tflops": tf, "frac_of_mfma_peak": tf / peaks[name],
+                         "hbm_ceiling_frac_of_mfma_peak": cap}
+            log(f"xi {xi}: k0 {k0}, {name} screen: {ms:.2f} ms, {tf:.2f} TFLOP/s")
+        out.append(row)
+    ctx.close()
+    return {"workload": f"one refinement round, n={n} rows of the 10M x 512 recipe, d={d}, kappa={kappa}, "
+                        "TwoMeans clusters of xi members, random initial lists",
+            "peaks_tflops": peaks, "sweep": out}
+
+
 def candidate_sharing(ctx, X, G_ids, k, seed, log):
     """How many distinct candidate clusters T consecutive samples of the fit's
     working order (the cluster order of the initial partition) have together,
@@ -556,6 +618,8 @@ def main():
                          "then a 1 GiB elementwise copy that calibrates the memory counters")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
                     help="host only: write the committed traffic summary of --config from two counter runs")
+    ap.add_argument("--xi-sweep", type=int, default=0, metavar="N",
+                    help="time one refinement round at d=512 on N rows for xi in 50, 100, 256, 512")
     ap.add_argument("--candidate-sharing", action="store_true",
                     help="after one build, measure the candidate clusters shared by consecutive samples")
     ap.add_argument("--forms-jobs", type=int, default=4096, help="jobs of the batching measurement")
@@ -581,6 +645,9 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    if args.xi_sweep:
+        print(json.dumps({"xi_sweep": xi_sweep(args.xi_sweep, args.seed, log)}), flush=True)
+        return 0
     if args.config == "c4":
         b = bench_batching(C4["m"], args.forms_sample, args.seed, log)
         print(json.dumps({"metric": "jobs/s", "value": b["batched_jobs_per_s"], "unit": "jobs/s", "n_gpus": 1,

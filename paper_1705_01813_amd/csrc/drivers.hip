@@ -411,13 +411,17 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     k_permute_graph<<<grid_for(n * kappa, 256, 16384), 256, 0, ctx->stream>>>(G_ids, kappa, perm, inv, n, Gp);
   k_gather_i32<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(labels, perm, n, labp);
   KNNKM_TRY(knnkm_check(ctx, "fit working copy"));
-  // Active sets: after the first sweep only the samples whose candidate set
-  // changed (they or a neighbour moved) or one of whose candidate centroids
-  // changed (a member of a dirty cluster, or a sample listing one in its
-  // graph row) are looked at; every other sample has the inputs of its last
-  // decision and keeps its label (same results).  One flag array per label
-  // buffer: the flags next to a label array mark the samples the sweep
-  // reading it looks at.
+  // Active sets: after the first sweep a sample is looked at only when its
+  // candidate set changed (it or a neighbour moved: bit 1 of its flag) or it
+  // may have to move for another reason: narrow rows list the samples that
+  // had several candidates (bit 0 from the sweep) and skip those none of
+  // whose candidate centroids changed; wide rows, where nearly every sample
+  // has several candidates, list only the samples with a changed candidate
+  // centroid (bit 0 from the update: a member of a dirty cluster, or a
+  // sample listing one in its graph row).  Every other sample has the inputs
+  // of its last decision and keeps its label (same results).  One flag array
+  // per label buffer: the flags next to a label array mark the samples the
+  // sweep reading it looks at.
   const bool use_act = ctx->active_sets && use_graph && n * (int64_t)kappa < INT32_MAX;
   int32_t *rev_off = nullptr, *rev_src = nullptr;
   uint8_t *act_p = nullptr, *act_2 = nullptr;
@@ -474,10 +478,11 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
                    int64_t* ac) -> knnkm_status {
     // moved counters are cleared once per fit (eager sweeps: one slot each)
     // or by the bookkeeping kernel (graph replays)
-    // (the flags of the next sweep come from the update's marks alone)
+    // (with drift bounds the flags of the next sweep come from the update's
+    // marks alone)
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
                      J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT, ev, first ? nullptr : act_for(cu),
-                     nullptr, ac, cnt_for(cu), cnt_for(nx), false, first ? nullptr : dirty_for(cu), bnd_u,
+                     drift ? nullptr : act_for(nx), ac, cnt_for(cu), cnt_for(nx), false, first ? nullptr : dirty_for(cu), bnd_u,
                      bnd_lb, first ? nullptr : cdelta, Cb, ceps);
   };
   // The first sweep moves a large share of the samples away from the
@@ -497,15 +502,15 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(nx), K, 1));
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(cu), K, 0));
       if (Cb) KNNKM_TRY(ks_c_shadow(ctx, C, K, d, nullptr, Cb, ceps));
-      if (use_act)
+      if (drift)
         KNNKM_TRY(ks_mark_dirty(ctx, n, nx, dirty_for(nx), rev_off, rev_src, act_for(nx), nullptr, 0, J.job_of, k32,
                                 kappa));
     } else {
       KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty_for(nx), C, Iterm, rev_off, rev_src,
-                             act_for(nx), dirty_for(cu), cdelta, dmass, Cb, ceps));
+                             act_for(nx), dirty_for(cu), cdelta, drift ? dmass : nullptr, Cb, ceps));
       // scattered marks while the dirty clusters' members and the rows
       // listing them stay below about 2n; every sample beyond that
-      if (use_act)
+      if (drift)
         KNNKM_TRY(ks_mark_dirty(ctx, n, nx, dirty_for(nx), rev_off, rev_src, act_for(nx), dmass,
                                 2 * n / (kappa + 1), J.job_of, k32, kappa));
     }
