@@ -516,3 +516,129 @@ def test_gap_mask_flags_near_ties():
     assert dec.tolist() == [True, True]
     dec, _ = metrics.assign_gap_mask(X, C, np.array([0, 1]), np.array([[1], [0]]))
     assert dec.tolist() == [False, True]  # x=0 is equidistant from -1 and 1
+
+
+# ---------------------------------------------------------------- boost form --
+from oracle import boost  # noqa: E402
+
+
+def _objective_direct(X, labels, k):
+    """I = sum_r ||sum of members||^2 / n_r computed from the partition alone."""
+    X64 = np.asarray(X, np.float64)
+    tot = 0.0
+    for r in range(k):
+        m = X64[np.asarray(labels) == r]
+        if len(m):
+            s = m.sum(0)
+            tot += float(s @ s) / len(m)
+    return tot
+
+
+def test_boost_eqn3_equals_weighted_form_and_objective_change():
+    rs = np.random.default_rng(5)
+    X = datagen.mixture(300, 7, 6, seed=13)
+    k = 9
+    labels = rs.integers(0, k, 300)
+    D, n_r = boost.composite(X, labels, k)
+    I0 = boost.objective(D, n_r)
+    assert abs(I0 - _objective_direct(X, labels, k)) <= 1e-10 * I0
+    for _ in range(200):
+        i = int(rs.integers(0, 300))
+        u = int(labels[i])
+        v = int(rs.integers(0, k))
+        if v == u:
+            continue
+        x = X[i].astype(np.float64)
+        lit = boost.delta_I(x, D[u], n_r[u], D[v], n_r[v])
+        cu, cv = D[u] / n_r[u], (D[v] / n_r[v] if n_r[v] else np.zeros(7))
+        wu = boost.weights(n_r[u], True) * float(((x - cu) ** 2).sum())
+        wv = boost.weights(n_r[v], False) * float(((x - cv) ** 2).sum())
+        assert abs(lit - (wu - wv)) <= 1e-9 * I0
+        moved = labels.copy()
+        moved[i] = v
+        assert abs(lit - (_objective_direct(X, moved, k) - I0)) <= 1e-9 * I0
+
+
+def test_boost_hand_worked_move_the_lloyd_rule_keeps():
+    g = json.load(open(os.path.join(GOLD, "boost_1d.json")))
+    X = np.array(g["X"], np.float32)[:, None]
+    G = np.array(g["graph"])
+    lab0 = np.array(g["labels0"])
+    D, n_r = boost.composite(X, lab0, 2)
+    assert boost.objective(D, n_r) == g["I0"]
+    assert boost.delta_I(X[1].astype(np.float64), D[0], n_r[0], D[1], n_r[1]) == g["gain_sample1"]
+    assert boost.best_move(X[1], 0, [1], D, n_r) == (1, g["gain_sample1"])
+    # the Lloyd rule keeps sample 1 where it is
+    lloyd, _, _ = gkmeans.gk_assign(X, (D / n_r[:, None]).astype(np.float32), lab0, G)
+    assert lloyd[1] == 0
+    lab1, applied, nprop = boost.boost_round(X, lab0, G, D, n_r, seed=1, rnd=1)
+    assert list(lab1) == g["labels1"] and nprop == 1 and applied[0][:3] == (1, 0, 1)
+    D1, n1 = boost.composite(X, lab1, 2)
+    assert boost.objective(D1, n1) == g["I1"]
+
+
+def test_boost_conflicting_proposals_apply_the_larger_key():
+    # samples 1 and 2 both propose into cluster 1 (and leave cluster 0): one
+    # move per cluster, the larger priority key wins
+    X = np.array([[0.0], [2.0], [2.1], [0.1], [3.5]], np.float32)
+    lab0 = np.array([0, 0, 0, 0, 1])
+    G = np.array([[3], [4], [4], [0], [1]])
+    D, n_r = boost.composite(X, lab0, 2)
+    assert boost.best_move(X[1], 0, [1], D, n_r)[0] == 1
+    assert boost.best_move(X[2], 0, [1], D, n_r)[0] == 1
+    for rnd in range(1, 6):
+        lab1, applied, nprop = boost.boost_round(X, lab0, G, D, n_r, seed=3, rnd=rnd)
+        assert nprop == 2 and len(applied) == 1
+        win = max((1, 2), key=lambda i: boost.priority(3, rnd, i))
+        assert applied[0][0] == win and lab1[win] == 1 and lab1[3 - win] == 0
+
+
+def test_boost_round_gain_is_the_sum_of_independent_moves():
+    X = datagen.mixture(400, 5, 8, seed=21)
+    k = 12
+    G, _ = exact.brute_knn(X, 6)
+    labels = np.random.default_rng(2).integers(0, k, 400)
+    D, n_r = boost.composite(X, labels, k)
+    I0 = boost.objective(D, n_r)
+    lab1, applied, nprop = boost.boost_round(X, labels, G, D, n_r, seed=7, rnd=1)
+    assert 1 <= len(applied) <= nprop
+    used = [r for _, u, v, _ in applied for r in (u, v)]
+    assert len(used) == len(set(used))  # no cluster in two applied moves
+    D1, n1 = boost.composite(X, lab1, k)
+    gain = sum(g for *_, g in applied)
+    assert abs(boost.objective(D1, n1) - I0 - gain) <= 1e-9 * I0
+    # the same moves one after the other (Eqn. 3 on the running state), in
+    # reverse order: each gain is the one the round computed
+    Dq, nq = D.copy(), n_r.copy()
+    for i, u, v, g in reversed(applied):
+        x = X[i].astype(np.float64)
+        assert abs(boost.delta_I(x, Dq[u], nq[u], Dq[v], nq[v]) - g) <= 1e-9 * I0
+        Dq[u] -= x
+        Dq[v] += x
+        nq[u] -= 1
+        nq[v] += 1
+
+
+def test_boost_rounds_monotone_and_stop_at_a_fixed_point():
+    X = datagen.mixture(600, 4, 10, seed=22)
+    k = 15
+    G, _ = exact.brute_knn(X, 8)
+    lab0 = gkmeans.init_labels(X, k, 9, gkmeans.INIT_TWOMEANS)[0]
+    lab, C, cnt, tr, t, moves = boost.boost_rounds(X, k, G, lab0, 200, seed=9)
+    assert (np.diff(tr) <= 1e-12 * tr[0]).all()
+    assert moves[-1] == 0 and t < 200  # converged: the last round proposed nothing
+    assert cnt.sum() == 600 and np.array_equal(cnt, np.bincount(lab, minlength=k))
+    # no positive move is left for the printed sequential form either
+    lab2, Is, mv = boost.boost_sequential(X, k, G, lab, 1)
+    assert mv == [0] and np.array_equal(lab2, lab)
+
+
+def test_boost_sequential_never_decreases_the_objective():
+    X = datagen.mixture(500, 3, 7, seed=23)
+    k = 10
+    G, _ = exact.brute_knn(X, 5)
+    lab0 = np.random.default_rng(4).integers(0, k, 500)
+    D, n_r = boost.composite(X, lab0, k)
+    lab, Is, mv = boost.boost_sequential(X, k, G, lab0, 6)
+    assert Is[0] >= boost.objective(D, n_r) and all(b >= a - 1e-9 * a for a, b in zip(Is, Is[1:]))
+    assert mv[0] > 0
