@@ -195,6 +195,32 @@ knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d
                             int32_t* labels, float* C, int32_t* counts, double* trace_host,
                             int32_t* iters_run_host);
 
+/* Boost form of the fit (Alg. 2 as printed, Sec. 3.1 / Eqn. 3), in
+ * data-parallel rounds.  Alg. 2 moves a sample from its cluster u to the
+ * cluster v of its kappa neighbours that maximises the gain of
+ * I = sum_r D_r'D_r / n_r (Eqn. 2) when that gain is positive; here that
+ * gain is n_u/(n_u-1)|x - c_u|^2 - n_v/(n_v+1)|x - c_v|^2 (Eqn. 3 rewritten;
+ * 0 for the first term when the move empties u), c_r the float64 mean of the
+ * exact sum D_r.  A round: every sample finds its best move against the same
+ * state (the smallest weighted distance n_v/(n_v+1)|x - c_v|^2 over the
+ * clusters of its graph row other than u, smallest id among equal ones;
+ * proposed when the own weighted distance is strictly larger); each cluster
+ * keeps, among the proposals touching it, the one with the largest priority
+ * (a counter-based draw of (params->seed, round, sample) in the high 32 bits,
+ * the sample id in the low 32); the proposals that keep both their clusters
+ * move.  No two moves of a round share a cluster, so I rises by exactly the
+ * sum of their gains (the round equals the same moves made one by one).
+ * Rounds stop after one with no proposal or after params->max_iters rounds
+ * (at most 65535).  Initial partition as knn_kmeans_fit (params->init,
+ * including KNNKM_INIT_LABELS).  Outputs labels (n), C (k x d, the float32
+ * means; clusters left empty keep the initial centroid), counts (k);
+ * trace_host (max_iters + 1 doubles) receives E_0..E_t (Eqn. 4);
+ * rounds_run_host the rounds done.  G_ids: n x kappa, required.
+ * Synchronous (one host read per round). */
+knnkm_status knn_boost_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int32_t k,
+                           const int32_t* G_ids, const knnkm_params* params, int32_t* labels, float* C,
+                           int32_t* counts, double* trace_host, int32_t* rounds_run_host);
+
 /* Batching form: m independent jobs (graph build and fit, Alg. 3 then Alg. 2)
  * in one call, every phase one launch over all jobs.
  *  X: the jobs' rows concatenated; job q owns rows [n_off_host[q],

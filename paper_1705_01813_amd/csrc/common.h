@@ -289,7 +289,21 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off,
                           const int32_t* rev_src, uint8_t* act_out, int32_t* dirty_clear,
                           float* delta, int64_t* mass = nullptr, uint16_t* Cb = nullptr,
-                          float* ceps = nullptr);
+                          float* ceps = nullptr, double* C64 = nullptr);
+// Exact fixed-point D of every cluster from its members (CSR), and the
+// centroids, float64 means and Eqn. 2 terms of every cluster from D.
+knnkm_status ks_fx_exact_sums(knnkm_ctx* ctx, const float* X, int64_t ldx, int32_t d, int32_t K, const int32_t* off,
+                              const int32_t* mem, const int32_t* cs, uint64_t* D);
+knnkm_status ks_fx_finalize_all(knnkm_ctx* ctx, const uint64_t* D, int32_t K, int32_t d, const int32_t* cs,
+                                const int32_t* counts, float* C, double* Iterm, double* C64);
+// Boost form (boost.hip): every sample's best positive move (Eqn. 3) against
+// the same state -> prop (target cluster or -1), *nprop += proposals; then
+// the conflict-free selection of a round and the next labels.
+knnkm_status ks_boost_propose(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, const int32_t* G,
+                              int32_t kappa, const int32_t* labels, const int32_t* counts, const double* C64,
+                              int32_t* prop, int64_t* nprop);
+knnkm_status ks_boost_select(knnkm_ctx* ctx, int64_t n, const int32_t* labels, const int32_t* prop, int32_t K,
+                             uint64_t seed, int32_t round, uint64_t* win, int32_t* next);
 // Active-set marks of the samples moved between cur and nxt and of the rows
 // listing them (reverse lists of the graph); moved labels copied into cur.
 knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,

@@ -311,6 +311,34 @@ static knnkm_status build_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
   return KNNKM_OK;
 }
 
+// The initial partition of a fit (Alg. 2 starts from Alg. 1; or k distinct
+// rows as seeds and an exhaustive assignment to them; or the caller's
+// labels), and the centroids that clusters left empty keep: zero after
+// Alg. 1, the seed rows after the random start, the caller's with labels.
+static knnkm_status init_partition(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, Jobs& J,
+                                   const std::vector<int32_t>& kq, const knnkm_params* p, int32_t K,
+                                   const int32_t* k32, int32_t* labels, float* C) {
+  const int64_t n = J.n;
+  const int m = J.m;
+  if (p->init == KNNKM_INIT_RANDOM) {
+    const int64_t bm_words = (n + 31) / 32 + m;
+    KNNKM_WS(ctx, bitmap, uint32_t, "fit_bitmap", bm_words);
+    KNNKM_WS(ctx, ids, int32_t, "fit_init_ids", K);
+    KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)bitmap, bm_words, 0));
+    k_random_init_ids<<<(m + 63) / 64, 64, 0, ctx->stream>>>(J.n_off, k32, m, J.seeds, bitmap, ids);
+    k_gather_rows<<<grid_for((int64_t)K * d, 256, 4096), 256, 0, ctx->stream>>>(X, d, ldx, ids, K, C);
+    KNNKM_TRY(knnkm_check(ctx, "random init"));
+    // exhaustive assignment to the seeds of the sample's own job
+    KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, K, nullptr, K, nullptr, labels, nullptr, nullptr, nullptr, true,
+                        J.job_of, k32));
+  } else if (p->init == KNNKM_INIT_TWOMEANS) {
+    KNNKM_TRY(ks_twomeans_multi(ctx, X, d, ldx, J.n_host, kq, m > 1 ? J.seeds : nullptr, J.seed_host[0],
+                                KNNKM_ROUND_FIT, p->bisect_iters, labels));
+    KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)C, (int64_t)K * d, 0));
+  }
+  return KNNKM_OK;
+}
+
 // Alg. 2 (Lloyd form) for every job of J.  labels are global cluster ids;
 // trace_dev receives E_t of job q at [t * m + q]; *iters_run the sweeps done.
 static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, Jobs& J,
@@ -348,25 +376,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   }
   mark(2);
 
-  // initial partition
-  if (p->init == KNNKM_INIT_RANDOM) {
-    const int64_t bm_words = (n + 31) / 32 + m;
-    KNNKM_WS(ctx, bitmap, uint32_t, "fit_bitmap", bm_words);
-    KNNKM_WS(ctx, ids, int32_t, "fit_init_ids", K);
-    KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)bitmap, bm_words, 0));
-    k_random_init_ids<<<(m + 63) / 64, 64, 0, ctx->stream>>>(J.n_off, k32, m, J.seeds, bitmap, ids);
-    k_gather_rows<<<grid_for((int64_t)K * d, 256, 4096), 256, 0, ctx->stream>>>(X, d, ldx, ids, K, C);
-    KNNKM_TRY(knnkm_check(ctx, "random init"));
-    // exhaustive assignment to the seeds of the sample's own job
-    KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, K, nullptr, K, nullptr, labels, nullptr, nullptr, nullptr, true,
-                        J.job_of, k32));
-  } else if (p->init == KNNKM_INIT_TWOMEANS) {
-    KNNKM_TRY(ks_twomeans_multi(ctx, X, d, ldx, J.n_host, kq, m > 1 ? J.seeds : nullptr, J.seed_host[0],
-                                KNNKM_ROUND_FIT, p->bisect_iters, labels));
-    KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)C, (int64_t)K * d, 0));
-  }
-  // KNNKM_INIT_LABELS: labels and the centroids of empty clusters are the
-  // caller's (checked by the entry point)
+  KNNKM_TRY(init_partition(ctx, X, d, ldx, J, kq, p, K, k32, labels, C));
   KNNKM_WS(ctx, jmax, uint32_t, "fit_jmax", m);
   KNNKM_TRY(ks_row_stats(ctx, X, n, d, ldx, m, J.job_of, rowsq, jmax));
   k_range_sum<<<m, 1024, 0, ctx->stream>>>(rowsq, J.n_off, sxx);
@@ -773,4 +783,116 @@ extern "C" knnkm_status knnkm_fit_batched(knnkm_ctx* ctx, const float* X, int32_
   }
   KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return knnkm_check(ctx, "knnkm_fit_batched");
+}
+
+// Alg. 2 as printed (boost form), data-parallel rounds (boost.hip): one job.
+// trace_dev receives E_0..E_t (Eqn. 4 through Eqn. 2); *rounds_run the
+// rounds done (the last one proposed nothing, or t = max_iters).
+static knnkm_status boost_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, Jobs& J, int32_t k,
+                               const int32_t* G_ids, const knnkm_params* p, int32_t* labels, float* C,
+                               int32_t* counts, double* trace_dev, int* rounds_run) {
+  const int kappa = p->kappa;
+  const int T = p->max_iters;
+  const int64_t n = J.n;
+  int32_t *k32, K;
+  int64_t* k64;
+  KNNKM_TRY(upload_koff(ctx, std::vector<int32_t>{k}, "boost", &k32, &k64, &K));
+  KNNKM_TRY(init_partition(ctx, X, d, ldx, J, std::vector<int32_t>{k}, p, K, k32, labels, C));
+  KNNKM_WS(ctx, rowsq, double, "fit_rowsq", n);
+  KNNKM_WS(ctx, sxx, double, "fit_sxx", 1);
+  KNNKM_WS(ctx, jmax, uint32_t, "fit_jmax", 1);
+  KNNKM_TRY(ks_row_stats(ctx, X, n, d, ldx, 1, nullptr, rowsq, jmax));
+  k_range_sum<<<1, 1024, 0, ctx->stream>>>(rowsq, J.n_off, sxx);
+  KNNKM_WS(ctx, cs, int32_t, "fit_scale", K);
+  KNNKM_TRY(ks_fx_scales(ctx, jmax, 1, k32, K, cs));
+  KNNKM_WS(ctx, off, int32_t, "fit_offsets", (int64_t)K + 1);
+  KNNKM_WS(ctx, mem, int32_t, "fit_members", n);
+  KNNKM_TRY(ks_label_sort(ctx, labels, n, K, counts, off, mem));
+  KNNKM_WS(ctx, Dfx, uint64_t, "fit_dfx", (int64_t)K * d * 2);
+  KNNKM_WS(ctx, C64, double, "boost_c64", (int64_t)K * d);
+  KNNKM_WS(ctx, Iterm, double, "fit_iterm", K);
+  KNNKM_TRY(ks_fx_exact_sums(ctx, X, ldx, d, K, off, mem, cs, Dfx));
+  KNNKM_TRY(ks_fx_finalize_all(ctx, Dfx, K, d, cs, counts, C, Iterm, C64));
+  k_range_trace<<<1, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, trace_dev);
+  KNNKM_TRY(knnkm_check(ctx, "boost initialisation"));
+  // the moves read rows by position with stride d: a contiguous copy when
+  // the caller's rows are strided
+  const float* Xc = X;
+  if (ldx != d) {
+    KNNKM_WS(ctx, xc, float, "boost_rows", n * (int64_t)d);
+    KNNKM_HIP(ctx, hipMemcpy2DAsync(xc, sizeof(float) * d, X, sizeof(float) * ldx, sizeof(float) * d, n,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    Xc = xc;
+  }
+  KNNKM_WS(ctx, nxt, int32_t, "fit_labels2", n);
+  KNNKM_WS(ctx, prop, int32_t, "boost_prop", n);
+  KNNKM_WS(ctx, win, uint64_t, "boost_win", K);
+  KNNKM_WS(ctx, dirty, int32_t, "fit_dirty", K);
+  KNNKM_WS(ctx, dirty2, int32_t, "fit_dirty2", K);
+  KNNKM_WS(ctx, nprop, int64_t, "boost_nprop", (int64_t)T + 1);
+  KNNKM_TRY(ks_fill_i32(ctx, dirty, K, 0));
+  KNNKM_TRY(ks_fill_i32(ctx, dirty2, K, 0));
+  KNNKM_TRY(ks_fill_i64(ctx, nprop, (int64_t)T + 1, 0));
+  int32_t *dset = dirty, *dclear = dirty2;
+  int t = 0;
+  for (t = 1; t <= T; ++t) {
+    KNNKM_TRY(ks_boost_propose(ctx, X, n, d, ldx, G_ids, kappa, labels, counts, C64, prop, nprop + t));
+    KNNKM_TRY(ks_boost_select(ctx, n, labels, prop, K, p->seed, t, win, nxt));
+    // the applied moves into D (exact), sizes, centroids, means, Eqn. 2 terms
+    KNNKM_TRY(ks_fx_update(ctx, Xc, n, d, labels, nxt, cs, Dfx, K, counts, dset, C, Iterm, nullptr, nullptr,
+                           nullptr, dclear, nullptr, nullptr, nullptr, nullptr, C64));
+    std::swap(dset, dclear);
+    KNNKM_HIP(ctx, hipMemcpyAsync(labels, nxt, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
+    k_range_trace<<<1, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, trace_dev + t);
+    int64_t np = 0;
+    KNNKM_HIP(ctx, hipMemcpyAsync(&np, nprop + t, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (np == 0) break;
+  }
+  *rounds_run = std::min(t, T);
+  return knnkm_check(ctx, "boost rounds");
+}
+
+extern "C" knnkm_status knn_boost_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int32_t k,
+                                      const int32_t* G_ids, const knnkm_params* p, int32_t* labels, float* C,
+                                      int32_t* counts, double* trace_host, int32_t* rounds_run_host) {
+  if (!ctx) return KNNKM_EINVAL;
+  if (ctx->sticky) return KNNKM_EDEVICE;
+  KNNKM_TRY(check_data(ctx, X, n, d, ldx, "knn_boost_fit"));
+  KNNKM_TRY(check_params(ctx, p, "knn_boost_fit"));
+  if (k < 1 || k > n) return knnkm_fail(ctx, KNNKM_EINVAL, "knn_boost_fit: need 1 <= k <= n");
+  const int kappa = p->kappa;
+  if (kappa < 1 || kappa > n - 1) return knnkm_fail(ctx, KNNKM_EINVAL, "knn_boost_fit: need 1 <= kappa <= n-1");
+  if (kappa > KNNKM_MAX_KAPPA)
+    return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "knn_boost_fit: kappa=%d > %d", kappa, KNNKM_MAX_KAPPA);
+  if (p->max_iters > 0xFFFF) return knnkm_fail(ctx, KNNKM_EINVAL, "knn_boost_fit: max_iters > 65535");
+  if (!labels || !C || !counts || !G_ids) return knnkm_fail(ctx, KNNKM_EINVAL, "knn_boost_fit: null pointer");
+  if (ctx->dry) return KNNKM_OK;
+  KNNKM_HIP(ctx, hipSetDevice(ctx->device));
+  Jobs J;
+  J.m = 1;
+  J.n = n;
+  J.n_host = {n};
+  J.n_off_host = {0, n};
+  J.seed_host = {p->seed};
+  KNNKM_TRY(upload_jobs(ctx, J, "one"));
+  if (p->init == KNNKM_INIT_LABELS) {
+    KNNKM_WS(ctx, bad, int64_t, "fit_bad_labels", 1);
+    KNNKM_TRY(ks_fill_i64(ctx, bad, 1, 0));
+    k_check_labels<<<grid_for(n, 256, 4096), 256, 0, ctx->stream>>>(labels, n, k, (unsigned long long*)bad);
+    int64_t nbad = 0;
+    KNNKM_HIP(ctx, hipMemcpyAsync(&nbad, bad, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (nbad) return knnkm_fail(ctx, KNNKM_EINVAL, "knn_boost_fit: %lld input labels outside [0, %d)",
+                                (long long)nbad, k);
+  }
+  KNNKM_WS(ctx, trace, double, "fit_trace", (int64_t)p->max_iters + 1);
+  int t = 0;
+  KNNKM_TRY(boost_impl(ctx, X, d, ldx, J, k, G_ids, p, labels, C, counts, trace, &t));
+  if (trace_host)
+    KNNKM_HIP(ctx, hipMemcpyAsync(trace_host, trace, sizeof(double) * (size_t)(t + 1), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+  KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (rounds_run_host) *rounds_run_host = t;
+  return knnkm_check(ctx, "knn_boost_fit");
 }

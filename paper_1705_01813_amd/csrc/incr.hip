@@ -353,7 +353,8 @@ __global__ void k_rev_fill(const int32_t* __restrict__ G, int64_t ne, int64_t n,
 // Eqn. 2 term; one wavefront per cluster.  dirty_clear, the previous
 // sweep's flags, is cleared on the way; mass (nullable, cleared before)
 // receives the number of members of all dirty clusters; Cb/ceps (nullable)
-// the bfloat16 shadow of each new centroid and its bound.
+// the bfloat16 shadow of each new centroid and its bound; C64 (nullable) the
+// float64 mean D_r / n_r.  dirty null: every cluster.
 __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict__ D, int32_t K, int d,
                                                      const int32_t* __restrict__ cs,
                                                      const int32_t* __restrict__ counts,
@@ -361,11 +362,11 @@ __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict_
                                                      int32_t* __restrict__ dirty_clear, float* __restrict__ C,
                                                      double* __restrict__ Iterm, float* __restrict__ delta,
                                                      unsigned long long* __restrict__ mass, uint16_t* __restrict__ Cb,
-                                                     float* __restrict__ ceps) {
+                                                     float* __restrict__ ceps, double* __restrict__ C64) {
   const int lane = threadIdx.x & 63;
   for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < K; r += (int64_t)gridDim.x * 4) {
-    if (lane == 0) dirty_clear[r] = 0;
-    if (!dirty[r]) continue;  // wave-uniform
+    if (dirty_clear && lane == 0) dirty_clear[r] = 0;
+    if (dirty && !dirty[r]) continue;  // wave-uniform
     const int cnt = counts[r];
     if (mass && lane == 0 && cnt > 0) atomicAdd(mass, (unsigned long long)cnt);
     const int s = cs[r];
@@ -380,6 +381,7 @@ __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict_
           mv = fma(df, df, mv);
         }
         C[e] = c;
+        if (C64) C64[e] = v / (double)cnt;
         if (Cb) {
           const uint16_t h = bf16_rne(c);
           Cb[e] = h;
@@ -448,7 +450,7 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off, const int32_t* rev_src,
                           uint8_t* act_out, int32_t* dirty_clear, float* delta, int64_t* mass, uint16_t* Cb,
-                          float* ceps) {
+                          float* ceps, double* C64) {
   if (mass) KNNKM_TRY(ks_fill_i64(ctx, mass, 1, 0));
 #define MV(DD)                                                                                           \
   k_fx_moves<DD><<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty, \
@@ -463,7 +465,7 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
     MV(8);
 #undef MV
   k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, dirty, dirty_clear, C, Iterm,
-                                                                delta, (unsigned long long*)mass, Cb, ceps);
+                                                                delta, (unsigned long long*)mass, Cb, ceps, C64);
   return knnkm_check(ctx, "incremental update");
 }
 
@@ -472,6 +474,42 @@ knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_
   k_mark_moved<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, cur, nxt, rev_off, rev_src, act_out, moved,
                                                                 all_at);
   return knnkm_check(ctx, "active-set marks");
+}
+
+// D_r of every cluster from its members (CSR off/mem), exactly: each row's
+// value converted to the cluster's fixed point and added as a 128-bit
+// integer; one wavefront per cluster, lanes over the dimensions.
+__global__ __launch_bounds__(256) void k_fx_exact_sums(const float* __restrict__ X, int64_t ldx, int d, int32_t K,
+                                                       const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ mem,
+                                                       const int32_t* __restrict__ cs, uint64_t* __restrict__ D) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < K; r += (int64_t)gridDim.x * 4) {
+    const int s = cs[r];
+    for (int t = lane; t < d; t += 64) {
+      uint64_t h = 0, l = 0;
+      for (int q = off[r]; q < off[r + 1]; ++q) {
+        uint64_t bh, bl;
+        fx_of_double((double)X[(int64_t)mem[q] * ldx + t], s, bh, bl);
+        add128(h, l, bh, bl);
+      }
+      D[2 * (r * d + t)] = l;
+      D[2 * (r * d + t) + 1] = h;
+    }
+  }
+}
+
+knnkm_status ks_fx_exact_sums(knnkm_ctx* ctx, const float* X, int64_t ldx, int32_t d, int32_t K, const int32_t* off,
+                              const int32_t* mem, const int32_t* cs, uint64_t* D) {
+  k_fx_exact_sums<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(X, ldx, d, K, off, mem, cs, D);
+  return knnkm_check(ctx, "exact fixed-point sums");
+}
+
+knnkm_status ks_fx_finalize_all(knnkm_ctx* ctx, const uint64_t* D, int32_t K, int32_t d, const int32_t* cs,
+                                const int32_t* counts, float* C, double* Iterm, double* C64) {
+  k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, nullptr, nullptr, C, Iterm,
+                                                                nullptr, nullptr, nullptr, nullptr, C64);
+  return knnkm_check(ctx, "centroids from fixed-point sums");
 }
 
 knnkm_status ks_mark_dirty(knnkm_ctx* ctx, int64_t n, const int32_t* lab, const int32_t* dirty,

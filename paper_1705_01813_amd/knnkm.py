@@ -23,7 +23,7 @@ EXPORTS = [
     "knnkm_create", "knnkm_destroy", "knnkm_set_stream", "knnkm_last_error",
     "knnkm_default_params", "knnkm_workspace_bytes", "knnkm_workspace_estimate", "knn_assign", "centroid_update",
     "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
-    "knn_kmeans_fit", "distortion_noalloc", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times", "knnkm_sweep_stats",
+    "knn_kmeans_fit", "knn_boost_fit", "distortion_noalloc", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times", "knnkm_sweep_stats",
     "knnkm_fit_batched", "knnkm_enable_graphs", "knnkm_enable_active_sets", "knnkm_enable_subtree_finish",
     "knnkm_autotune", "knnkm_autotune_table", "knnkm_set_assign_shape", "knnkm_enable_partial_distances",
     "knnkm_server_create", "knnkm_server_submit", "knnkm_server_wait",
@@ -135,6 +135,7 @@ def lib():
             "knnkm_graph_refine": [P, P, i64, i32, i64, P, i32, i32, P, P, i32],
             "knn_build": [P, P, i64, i32, i64, ctypes.POINTER(Params), P, P],
             "knn_kmeans_fit": [P, P, i64, i32, i64, i32, P, ctypes.POINTER(Params), P, P, P, P, P],
+            "knn_boost_fit": [P, P, i64, i32, i64, i32, P, ctypes.POINTER(Params), P, P, P, P, P],
             "knnkm_rng_draw": [P, u64, u64, u64, i64, P],
             "knnkm_fit_batched": [P, P, i32, i64, i32, P, P, P, ctypes.POINTER(Params), P, P, P, P, P, P],
             "knnkm_enable_timing": [P, i32],
@@ -346,6 +347,22 @@ def knn_kmeans_fit(ctx, X, k, G_ids, params, labels, C, counts):
                               _ptr(labels, torch.int32, "labels"), _ptr(C, torch.float32, "C"),
                               _ptr(counts, torch.int32, "counts"),
                               trace.ctypes.data_as(ctypes.c_void_p), ctypes.byref(it))
+    _chk(ctx.handle, st)
+    return trace[: it.value + 1], it.value
+
+
+def knn_boost_fit(ctx, X, k, G_ids, params, labels, C, counts):
+    """Boost form.  Returns (trace of E_0..E_t as numpy, rounds run)."""
+    import torch
+
+    n, d, ldx = _rows(X)
+    trace = np.zeros(params.max_iters + 1, np.float64)
+    it = ctypes.c_int32()
+    st = lib().knn_boost_fit(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx, k,
+                             _ptr(G_ids, torch.int32, "G_ids"), ctypes.byref(params),
+                             _ptr(labels, torch.int32, "labels"), _ptr(C, torch.float32, "C"),
+                             _ptr(counts, torch.int32, "counts"),
+                             trace.ctypes.data_as(ctypes.c_void_p), ctypes.byref(it))
     _chk(ctx.handle, st)
     return trace[: it.value + 1], it.value
 

@@ -13,7 +13,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import exact, gkmeans, knng, rng, twomeans  # noqa: E402
+from oracle import boost, exact, gkmeans, knng, rng, twomeans  # noqa: E402
 from paper_1705_01813_amd import datagen, knnkm  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -551,6 +551,54 @@ def test_workspace_estimate_bounds_a_build_and_fit(n, d, k, kappa):
     est = knnkm.knnkm_workspace_estimate(n, d, k, p)
     say("held", held, "estimate", est)
     assert 0 < held <= est
+
+
+@pytest.mark.parametrize("init,n,d,k,kappa,T", [(knnkm.INIT_TWOMEANS, 1500, 8, 30, 8, 40),
+                                                 (knnkm.INIT_RANDOM, 1200, 5, 20, 10, 60),
+                                                 (knnkm.INIT_TWOMEANS, 700, 33, 12, 70, 30)])
+def test_boost_fit_parity(ctx, init, n, d, k, kappa, T):
+    """The boost form (Alg. 2 as printed, Eqn. 3) in data-parallel rounds:
+    labels, counts, centroids and the rounds run equal the oracle's rounds
+    bit for bit, the trace within 1e-9, and I never decreases (the applied
+    moves of a round share no cluster)."""
+    say("boost fit", init, n, d, k, kappa, T)
+    X = datagen.mixture(n, d, max(2, k // 2), seed=d + k)
+    G, _ = knng.knn_build(X, kappa, xi=50, tau=2, seed=4)
+    lab0, C0 = gkmeans.init_labels(X, k, 6, init)
+    w_lab, w_C, w_cnt, w_tr, w_t, w_mv = boost.boost_rounds(X, k, G, lab0, T, seed=6, C0=C0)
+    p = knnkm.default_params(kappa=kappa, max_iters=T, seed=6, init=init)
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+    cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+    tr, t = knnkm.knn_boost_fit(ctx, dev(X), k, dev(G), p, lab, C, cnt)
+    say("rounds", t, "moves", w_mv[:8])
+    assert t == w_t
+    assert np.array_equal(host(lab), w_lab)
+    assert np.array_equal(host(cnt), w_cnt)
+    assert np.array_equal(host(C), w_C)
+    np.testing.assert_allclose(tr, w_tr, rtol=1e-9)
+    assert (np.diff(tr) <= 1e-12 * tr[0]).all()
+
+
+def test_boost_fit_converges_to_a_fixed_point_of_alg2(ctx):
+    """Rounds until no sample proposes: the printed sequential Alg. 2 makes no
+    move from the returned state, and the labels equal the oracle's."""
+    n, d, k, kappa = 900, 4, 15, 8
+    say("boost fixed point", n, d, k, kappa)
+    X = datagen.mixture(n, d, 10, seed=22)
+    G, _ = exact.brute_knn(X, kappa)
+    p = knnkm.default_params(kappa=kappa, max_iters=500, seed=9)
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    C = torch.empty((k, d), dtype=torch.float32, device=DEV)
+    cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+    tr, t = knnkm.knn_boost_fit(ctx, dev(X), k, dev(G), p, lab, C, cnt)
+    assert t < 500
+    got = host(lab)
+    lab2, _, mv = boost.boost_sequential(X, k, G, got, 1)
+    assert mv == [0]
+    lab0 = gkmeans.init_labels(X, k, 9, gkmeans.INIT_TWOMEANS)[0]
+    w_lab = boost.boost_rounds(X, k, G, lab0, 500, seed=9)[0]
+    assert np.array_equal(got, w_lab)
 
 
 def test_assign_autotune_same_result(ctx):
