@@ -752,6 +752,12 @@ extern "C" knnkm_status knnkm_set_assign_shape(knnkm_ctx* ctx, int32_t gs, int32
   return KNNKM_OK;
 }
 
+knnkm_status ks_act_compact(knnkm_ctx* ctx, int64_t n, uint8_t* act, int32_t* list, int32_t* count) {
+  KNNKM_TRY(ks_fill_i32(ctx, count, 1, 0));
+  k_act_compact<<<(unsigned)((n + 4095) / 4096), 256, 0, ctx->stream>>>(n, act, list, count, nullptr);
+  return knnkm_check(ctx, "active list");
+}
+
 knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        const float* C, int32_t k, const int32_t* G_ids, int32_t kappa,
                        const int32_t* labels_in, int32_t* labels_out, float* best_d2,

@@ -7,7 +7,8 @@
 // (the first term 0 when the move empties u), with c_r = D_r / n_r.
 //
 // A round: every sample computes its best move against the same state
-// (k_boost_propose); each cluster keeps, among the proposals touching it as
+// (k_boost_propose; a sample none of whose clusters -- its own, those of its
+// neighbours -- changed since its last proposal keeps it); each cluster keeps, among the proposals touching it as
 // source or target, the one with the largest priority key (k_boost_bid); a
 // proposal that keeps both of its clusters is applied (k_boost_apply).  No
 // two applied moves share a cluster, so each one's gain is unchanged by the
@@ -52,14 +53,13 @@ __global__ __launch_bounds__(256) void k_boost_propose(const float* __restrict__
                                                        const int32_t* __restrict__ lab,
                                                        const int32_t* __restrict__ cnt,
                                                        const double* __restrict__ C64, int32_t* __restrict__ prop,
-                                                       unsigned long long* __restrict__ nprop) {
+                                                       const int32_t* __restrict__ list,
+                                                       const int32_t* __restrict__ count) {
   __shared__ float xs[4][KNNKM_MAX_D];
-  __shared__ unsigned int block_prop;
-  if (threadIdx.x == 0) block_prop = 0;
-  __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  unsigned int my = 0;
-  for (int64_t i = blockIdx.x * 4 + w; i < n; i += (int64_t)gridDim.x * 4) {
+  const int64_t m = list ? (int64_t)*count : n;
+  for (int64_t li = blockIdx.x * 4 + w; li < m; li += (int64_t)gridDim.x * 4) {
+    const int64_t i = list ? (int64_t)(list[li] & 0x7FFFFFFF) : li;
     for (int j = lane; j < d; j += 64) xs[w][j] = X[i * ldx + j];
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -91,18 +91,11 @@ __global__ __launch_bounds__(256) void k_boost_propose(const float* __restrict__
         br = orr;
       }
     }
-    if (lane == 0) {
-      const int pv = (br != INT_MAX && wu > bw) ? br : -1;
-      prop[i] = pv;
-      my += pv >= 0 ? 1u : 0u;
-    }
+    if (lane == 0) prop[i] = (br != INT_MAX && wu > bw) ? br : -1;
     // every lane has read the row before the next sample overwrites it
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
-  if (my) atomicAdd(&block_prop, my);
-  __syncthreads();
-  if (threadIdx.x == 0 && block_prop) atomicAdd(nprop, (unsigned long long)block_prop);
 }
 
 __device__ inline uint64_t boost_key(uint64_t seed, int32_t round, int64_t i) {
@@ -110,15 +103,26 @@ __device__ inline uint64_t boost_key(uint64_t seed, int32_t round, int64_t i) {
   return ((h >> 32) << 32) | (uint64_t)(uint32_t)i;
 }
 
-__global__ void k_boost_bid(int64_t n, const int32_t* __restrict__ lab, const int32_t* __restrict__ prop,
-                            uint64_t seed, int32_t round, unsigned long long* __restrict__ win) {
+// Bids of every proposal on its two clusters; *nprop += proposals.
+__global__ __launch_bounds__(256) void k_boost_bid(int64_t n, const int32_t* __restrict__ lab,
+                                                   const int32_t* __restrict__ prop, uint64_t seed, int32_t round,
+                                                   unsigned long long* __restrict__ win,
+                                                   unsigned long long* __restrict__ nprop) {
+  __shared__ unsigned int block_prop;
+  if (threadIdx.x == 0) block_prop = 0;
+  __syncthreads();
+  unsigned int my = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int v = prop[i];
     if (v < 0) continue;
+    ++my;
     const unsigned long long key = boost_key(seed, round, i);
     atomicMax(&win[lab[i]], key);
     atomicMax(&win[v], key);
   }
+  if (my) atomicAdd(&block_prop, my);
+  __syncthreads();
+  if (threadIdx.x == 0 && block_prop) atomicAdd(nprop, (unsigned long long)block_prop);
 }
 
 __global__ void k_boost_apply(int64_t n, const int32_t* __restrict__ lab, const int32_t* __restrict__ prop,
@@ -139,18 +143,18 @@ __global__ void k_boost_apply(int64_t n, const int32_t* __restrict__ lab, const 
 
 knnkm_status ks_boost_propose(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, const int32_t* G,
                               int32_t kappa, const int32_t* labels, const int32_t* counts, const double* C64,
-                              int32_t* prop, int64_t* nprop) {
+                              int32_t* prop, const int32_t* list, const int32_t* count) {
   if (n <= 0) return KNNKM_OK;
   k_boost_propose<<<grid_for(n, 4, 65536), 256, 0, ctx->stream>>>(X, n, d, ldx, G, kappa, labels, counts, C64, prop,
-                                                                  (unsigned long long*)nprop);
+                                                                  list, count);
   return knnkm_check(ctx, "boost proposals");
 }
 
 knnkm_status ks_boost_select(knnkm_ctx* ctx, int64_t n, const int32_t* labels, const int32_t* prop, int32_t K,
-                             uint64_t seed, int32_t round, uint64_t* win, int32_t* next) {
+                             uint64_t seed, int32_t round, uint64_t* win, int32_t* next, int64_t* nprop) {
   KNNKM_TRY(ks_fill_i64(ctx, (int64_t*)win, K, 0));
   k_boost_bid<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, labels, prop, seed, round,
-                                                               (unsigned long long*)win);
+                                                               (unsigned long long*)win, (unsigned long long*)nprop);
   k_boost_apply<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, labels, prop, seed, round,
                                                                  (const unsigned long long*)win, next);
   return knnkm_check(ctx, "boost selection");

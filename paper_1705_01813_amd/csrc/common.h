@@ -299,11 +299,15 @@ knnkm_status ks_fx_finalize_all(knnkm_ctx* ctx, const uint64_t* D, int32_t K, in
 // Boost form (boost.hip): every sample's best positive move (Eqn. 3) against
 // the same state -> prop (target cluster or -1), *nprop += proposals; then
 // the conflict-free selection of a round and the next labels.
+// Only the listed samples (list/count as ks_act_compact writes them; list
+// null: every sample) are evaluated; the others keep their proposal.
 knnkm_status ks_boost_propose(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, const int32_t* G,
                               int32_t kappa, const int32_t* labels, const int32_t* counts, const double* C64,
-                              int32_t* prop, int64_t* nprop);
+                              int32_t* prop, const int32_t* list, const int32_t* count);
 knnkm_status ks_boost_select(knnkm_ctx* ctx, int64_t n, const int32_t* labels, const int32_t* prop, int32_t K,
-                             uint64_t seed, int32_t round, uint64_t* win, int32_t* next);
+                             uint64_t seed, int32_t round, uint64_t* win, int32_t* next, int64_t* nprop);
+// Lists the positions whose active-set flag is set (and clears the flags).
+knnkm_status ks_act_compact(knnkm_ctx* ctx, int64_t n, uint8_t* act, int32_t* list, int32_t* count);
 // Active-set marks of the samples moved between cur and nxt and of the rows
 // listing them (reverse lists of the graph); moved labels copied into cur.
 knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,

@@ -826,6 +826,17 @@ static knnkm_status boost_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
   }
   KNNKM_WS(ctx, nxt, int32_t, "fit_labels2", n);
   KNNKM_WS(ctx, prop, int32_t, "boost_prop", n);
+  // active lists: after a round only the samples with a changed cluster
+  // among their own and their neighbours' (members of a dirty cluster and
+  // the samples listing one in their graph rows) propose again
+  KNNKM_WS(ctx, rev_off, int32_t, "fit_rev_off", n + 1);
+  KNNKM_WS(ctx, rev_src, int32_t, "fit_rev_src", n * (int64_t)kappa);
+  KNNKM_WS(ctx, act, uint8_t, "fit_act_p", (n + 3) / 4 * 4);
+  KNNKM_WS(ctx, list, int32_t, "as_act_list", n);
+  KNNKM_WS(ctx, lcount, int32_t, "fit_list_counts", 1);
+  KNNKM_WS(ctx, dmass, int64_t, "fit_dirty_mass", 1);
+  KNNKM_TRY(ks_reverse_graph(ctx, G_ids, n, kappa, rev_off, rev_src));
+  KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)act, (n + 3) / 4, 0));
   KNNKM_WS(ctx, win, uint64_t, "boost_win", K);
   KNNKM_WS(ctx, dirty, int32_t, "fit_dirty", K);
   KNNKM_WS(ctx, dirty2, int32_t, "fit_dirty2", K);
@@ -836,13 +847,17 @@ static knnkm_status boost_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
   int32_t *dset = dirty, *dclear = dirty2;
   int t = 0;
   for (t = 1; t <= T; ++t) {
-    KNNKM_TRY(ks_boost_propose(ctx, X, n, d, ldx, G_ids, kappa, labels, counts, C64, prop, nprop + t));
-    KNNKM_TRY(ks_boost_select(ctx, n, labels, prop, K, p->seed, t, win, nxt));
+    KNNKM_TRY(ks_boost_propose(ctx, X, n, d, ldx, G_ids, kappa, labels, counts, C64, prop, t > 1 ? list : nullptr,
+                               lcount));
+    KNNKM_TRY(ks_boost_select(ctx, n, labels, prop, K, p->seed, t, win, nxt, nprop + t));
     // the applied moves into D (exact), sizes, centroids, means, Eqn. 2 terms
     KNNKM_TRY(ks_fx_update(ctx, Xc, n, d, labels, nxt, cs, Dfx, K, counts, dset, C, Iterm, nullptr, nullptr,
-                           nullptr, dclear, nullptr, nullptr, nullptr, nullptr, C64));
-    std::swap(dset, dclear);
+                           nullptr, dclear, nullptr, dmass, nullptr, nullptr, C64));
     KNNKM_HIP(ctx, hipMemcpyAsync(labels, nxt, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
+    KNNKM_TRY(ks_mark_dirty(ctx, n, labels, dset, rev_off, rev_src, act, dmass, 2 * n / (kappa + 1), nullptr, nullptr,
+                            kappa));
+    KNNKM_TRY(ks_act_compact(ctx, n, act, list, lcount));
+    std::swap(dset, dclear);
     k_range_trace<<<1, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, trace_dev + t);
     int64_t np = 0;
     KNNKM_HIP(ctx, hipMemcpyAsync(&np, nprop + t, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
