@@ -781,7 +781,8 @@ def main():
         pb.max_iters = args.boost
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        tb, rb = knnkm.knn_boost_fit(ctx, X, k, G_ids, pb, labels, C, counts)
+        lab_b, C_b, cnt_b = torch.empty_like(labels), torch.empty_like(C), torch.empty_like(counts)
+        tb, rb = knnkm.knn_boost_fit(ctx, X, k, G_ids, pb, lab_b, C_b, cnt_b)
         torch.cuda.synchronize()
         tbs = time.perf_counter() - t0
         out["boost_form"] = {"rounds": rb, "converged": rb < args.boost, "seconds": tbs,
@@ -791,6 +792,7 @@ def main():
                              "note": "Alg. 2 as printed (Eqn. 3 moves) in conflict-free data-parallel rounds, from "
                                      "the same graph and initial partition as the Lloyd form's fit"}
         log(f"boost form: {rb} rounds in {tbs:.2f} s, E {tb[-1]:.6g} (Lloyd form {trace[-1]:.6g})")
+        del lab_b, C_b, cnt_b
     if cfg["precision"] and not args.no_precision:
         out["precision"] = precision_report(ctx, X, p, G_ids, G_d2, labels, C, trace, 64, args.seed, log)
     del labels, C, counts
