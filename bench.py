@@ -61,21 +61,12 @@ C5 = dict(rate=200.0, seconds=60.0, dims=(64, 128, 256), kappa=16, T=20, xi=50, 
           pool_rows=1_000_000)
 
 
-def precision_report(ctx, X, p, G_ids, G_d2, labels, C, trace, samples, seed, log):
-    """Quality of a precision-form result, against references computed with
-    plain PyTorch in float64 on the GPU (independent of the library's kernels):
-    recall@kappa of the graph on sampled rows against exact neighbours, the
-    relative error of the reported final distortion against the float64
-    distortion of the returned labels, and whether the FP32-screened build gives
-    the same graph as the BF16-screened one."""
+def exact_neighbours(X, rows, kappa):
+    """Ids of the kappa nearest other rows of X[rows] (plain PyTorch float64
+    on the GPU, blockwise over X)."""
     import torch
 
-    from paper_1705_01813_amd import knnkm
-
-    n, d = X.shape
-    kappa = G_ids.shape[1]
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    rows = torch.randint(0, n, (samples,), generator=g).to(X.device)
+    n = X.shape[0]
     q = X[rows].double()
     qn = (q * q).sum(1, keepdim=True)
     best_d, best_i = None, None
@@ -91,6 +82,121 @@ def precision_report(ctx, X, p, G_ids, G_d2, labels, C, trace, samples, seed, lo
             cd, ci = torch.cat([best_d, dd], 1), torch.cat([best_i, ids[None, :].expand_as(dd)], 1)
         best_d, pos = torch.topk(cd, kappa, dim=1, largest=False)
         best_i = torch.gather(ci, 1, pos)
+    return best_i
+
+
+def tau_study(n, seed, log, taus=(0, 1, 2, 3, 4, 5, 6, 8, 10, 14), kappa=20, samples=1000, T=30):
+    """Graph quality and clustering distortion as functions of the number of
+    construction rounds tau (Sec. 4.3): on n rows of the 1M x 128 recipe,
+    knn_build with tau rounds, the top-1 recall and recall@kappa of the graph
+    on sampled rows (exact float64 neighbours), and the distortion of a
+    30-iteration GK-means fit (Lloyd form) into n/100 clusters with that graph."""
+    import torch
+
+    from paper_1705_01813_amd import datagen, knnkm
+
+    dev = "cuda:0"
+    X = torch.from_numpy(datagen.config_data("c2", seed=seed, n=n)).to(dev)
+    d = X.shape[1]
+    k = max(1, n // 100)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    rows = torch.randint(0, n, (samples,), generator=g).to(dev)
+    ex = exact_neighbours(X, rows, kappa)
+    ctx = knnkm.Context(0)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=dev)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=dev)
+    lab = torch.empty(n, dtype=torch.int32, device=dev)
+    C = torch.empty((k, d), dtype=torch.float32, device=dev)
+    cnt = torch.empty(k, dtype=torch.int32, device=dev)
+    out = []
+    for tau in taus:
+        p = knnkm.default_params(kappa=kappa, xi=50, tau=tau, max_iters=T, seed=seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        knnkm.knn_build(ctx, X, p, gi, gd)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        got = gi[rows].long()
+        top1 = float((got[:, 0] == ex[:, 0]).double().mean())
+        hits = sum(len(set(a.tolist()) & set(b.tolist())) for a, b in zip(got, ex))
+        tr, _ = knnkm.knn_kmeans_fit(ctx, X, k, gi, p, lab, C, cnt)
+        out.append({"tau": tau, "build_s": tb, "recall_top1": top1, "recall_at_kappa": hits / float(samples * kappa),
+                    "fit_E_T": float(tr[-1])})
+        log(f"tau {tau}: build {tb:.3f} s, top-1 recall {top1:.3f}, E_T {tr[-1]:.6g}")
+    ctx.close()
+    return {"workload": f"n={n} rows of the 1M x 128 recipe, d={d}, kappa={kappa}, xi=50; fit k={k}, T={T}; "
+                        f"recall on {samples} sampled rows against exact float64 neighbours", "sweep": out}
+
+
+def scaling_sweeps(seed, log, ns=(10_000, 100_000, 1_000_000, 10_000_000), ks=(1024, 2048, 4096, 8192), T=30):
+    """Sec. 5.4's scalability tests on the 10M x 512 recipe (d = 512, ten rows
+    per mixture component): n varied at k = 1,024, and k varied at n = 10^6;
+    each point is knn_build (tau = 10, xi = 50, bfloat16 screen) plus a
+    30-iteration fit."""
+    import torch
+
+    from paper_1705_01813_amd import datagen, knnkm
+
+    dev = "cuda:0"
+    c = datagen.CONFIGS["c3"]
+    kappa = 50
+    ctx = knnkm.Context(0)
+
+    def point(X, k):
+        n, d = X.shape
+        p = knnkm.default_params(kappa=kappa, xi=50, tau=10, max_iters=T, seed=seed, precision=knnkm.BF16_RERANK)
+        gi = torch.empty((n, kappa), dtype=torch.int32, device=dev)
+        gd = torch.empty((n, kappa), dtype=torch.float32, device=dev)
+        lab = torch.empty(n, dtype=torch.int32, device=dev)
+        C = torch.empty((k, d), dtype=torch.float32, device=dev)
+        cnt = torch.empty(k, dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        knnkm.knn_build(ctx, X, p, gi, gd)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tr, _ = knnkm.knn_kmeans_fit(ctx, X, k, gi, p, lab, C, cnt)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return {"n": n, "k": k, "build_s": t1 - t0, "fit_s": t2 - t1, "total_s": t2 - t0, "E_T": float(tr[-1])}
+
+    def data(n):
+        return datagen.mixture_device(n, c["d"], max(1, n // 10), seed, c["centre"], c["lo"], c["hi"], c["sigma"],
+                                      c["clip"], c["integer"], device=dev)
+
+    by_n, by_k = [], []
+    for n in ns:
+        X = data(n)
+        by_n.append(point(X, 1024))
+        log(f"scaling n={n}, k=1024: {by_n[-1]}")
+        del X
+    X = data(1_000_000)
+    for k in ks:
+        by_k.append(point(X, k))
+        log(f"scaling n=1M, k={k}: {by_k[-1]}")
+    del X
+    ctx.close()
+    return {"workload": "10M x 512 recipe (d=512, ten rows per component, sigma 0.5), kappa=50, tau=10, xi=50, "
+                        "bfloat16 screen, T=30", "k1024_varying_n": by_n, "n1M_varying_k": by_k}
+
+
+def precision_report(ctx, X, p, G_ids, G_d2, labels, C, trace, samples, seed, log):
+    """Quality of a precision-form result, against references computed with
+    plain PyTorch in float64 on the GPU (independent of the library's kernels):
+    recall@kappa of the graph on sampled rows against exact neighbours, the
+    relative error of the reported final distortion against the float64
+    distortion of the returned labels, and whether the FP32-screened build gives
+    the same graph as the BF16-screened one."""
+    import torch
+
+    from paper_1705_01813_amd import knnkm
+
+    n, d = X.shape
+    kappa = G_ids.shape[1]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    rows = torch.randint(0, n, (samples,), generator=g).to(X.device)
+    best_i = exact_neighbours(X, rows, kappa)
+    step = 1 << 20
     got = G_ids[rows].long()
     hits = sum(len(set(a.tolist()) & set(b.tolist())) for a, b in zip(got, best_i))
     recall = hits / float(samples * kappa)
@@ -621,6 +727,10 @@ def main():
     ap.add_argument("--boost", type=int, default=0, metavar="R",
                     help="after the timed steps, run the boost form (knn_boost_fit) for up to R rounds from the same "
                          "graph and initialisation and report its rounds, time and distortion beside the Lloyd form's")
+    ap.add_argument("--tau-study", type=int, default=0, metavar="N",
+                    help="graph recall and fit distortion against the number of construction rounds on N rows")
+    ap.add_argument("--scaling", action="store_true",
+                    help="the scalability sweeps at d=512: n from 10k to 10M at k=1024, k from 1024 to 8192 at n=1M")
     ap.add_argument("--xi-sweep", type=int, default=0, metavar="N",
                     help="time one refinement round at d=512 on N rows for xi in 50, 100, 256, 512")
     ap.add_argument("--candidate-sharing", action="store_true",
@@ -648,6 +758,12 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    if args.tau_study:
+        print(json.dumps({"tau_study": tau_study(args.tau_study, args.seed, log)}), flush=True)
+        return 0
+    if args.scaling:
+        print(json.dumps({"scaling": scaling_sweeps(args.seed, log)}), flush=True)
+        return 0
     if args.xi_sweep:
         print(json.dumps({"xi_sweep": xi_sweep(args.xi_sweep, args.seed, log)}), flush=True)
         return 0
