@@ -642,3 +642,61 @@ def test_boost_sequential_never_decreases_the_objective():
     lab, Is, mv = boost.boost_sequential(X, k, G, lab0, 6)
     assert Is[0] >= boost.objective(D, n_r) and all(b >= a - 1e-9 * a for a, b in zip(Is, Is[1:]))
     assert mv[0] > 0
+
+
+# ----------------------------------------------------------- graph search --
+from oracle import anns  # noqa: E402
+
+
+def _connected_graph(X, kappa, seed):
+    """Exact (kappa-1)-NN lists plus the next row id (a ring), checked connected."""
+    G, _ = exact.brute_knn(X, kappa - 1)
+    r = ((np.arange(X.shape[0]) + 1) % X.shape[0])[:, None]
+    G = np.concatenate([G, r], 1)
+    seen, stack = {0}, [0]
+    while stack:
+        for b in G[stack.pop()]:
+            if int(b) not in seen:
+                seen.add(int(b))
+                stack.append(int(b))
+    assert len(seen) == X.shape[0]
+    return G
+
+
+def test_search_with_full_budget_is_exact():
+    A = datagen.mixture(640, 6, 12, seed=31)
+    X, Q = A[:600], A[600:]
+    G = _connected_graph(X, 8, 1)
+    ids, d2 = anns.search_all(X, G, Q, ef=600, top_k=10, max_visits=10**6, n_entry=1, seed=3, form="classic")
+    for i in range(Q.shape[0]):
+        dd = ((X.astype(np.float64) - Q[i].astype(np.float64)) ** 2).sum(1)
+        order = np.lexsort((np.arange(600), dd.astype(np.float32)))
+        assert list(ids[i]) == list(order[:10])
+        np.testing.assert_array_equal(d2[i], dd.astype(np.float32)[order[:10]].astype(np.float64))
+
+
+def test_search_list_form_equals_classic_form():
+    rs = np.random.default_rng(9)
+    A = datagen.mixture(1560, 5, 30, seed=33)
+    X, Q = A[:1500], A[1500:]
+    for kappa, ef, visits, n_entry in [(6, 8, 10**6, 1), (10, 32, 10**6, 3), (10, 64, 60, 1), (4, 16, 200, 2)]:
+        G = rs.integers(0, 1500, (1500, kappa)) if kappa == 4 else exact.brute_knn(X, kappa)[0]
+        a = anns.search_all(X, G, Q, ef, 5, visits, n_entry, seed=kappa, form="list")
+        b = anns.search_all(X, G, Q, ef, 5, visits, n_entry, seed=kappa, form="classic")
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (kappa, ef, visits)
+
+
+def test_search_keys_and_recall_trend():
+    A = datagen.mixture(3080, 8, 40, seed=35)
+    X, Q = A[:3000], A[3000:]
+    G = _connected_graph(X, 10, 2)
+    # the keys are the float32 of the float64 squared distance
+    k = anns.sq_keys(Q[0], X[:50])
+    np.testing.assert_array_equal(k, np.array([anns.sq_key(Q[0], x) for x in X[:50]]))
+    assert np.abs(k - ((X[:50].astype(np.float64) - Q[0]) ** 2).sum(1)).max() <= 1e-6 * k.max()
+    truth = np.array([np.argsort(((X.astype(np.float64) - q) ** 2).sum(1), kind="stable")[:10] for q in Q])
+    rec = []
+    for ef in (10, 20, 40, 80):
+        ids, _ = anns.search_all(X, G, Q, ef, 10, 10**6, 1, seed=5)
+        rec.append(np.mean([len(set(a) & set(b)) / 10.0 for a, b in zip(ids, truth)]))
+    assert all(b >= a - 0.02 for a, b in zip(rec, rec[1:])) and rec[-1] > rec[0] + 0.4 and rec[-1] > 0.8
