@@ -221,6 +221,29 @@ knnkm_status knn_boost_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d,
                            const int32_t* G_ids, const knnkm_params* params, int32_t* labels, float* C,
                            int32_t* counts, double* trace_host, int32_t* rounds_run_host);
 
+/* Approximate nearest neighbours of query rows by best-first search over a
+ * KNN graph (Sec. 4.3: the graph of Alg. 3 also serves this search; the paper
+ * gives no algorithm, this is the usual beam search).  Per query: a sorted
+ * list of at most ef entries (d2, id), seeded with n_entry distinct entry
+ * points (Floyd's sampling keyed by seed and the query index); the first
+ * entry not yet expanded is expanded -- its graph neighbours not seen before
+ * get their distances and are merged in, the list keeping its ef smallest --
+ * until every entry is expanded or max_visits points have been looked at
+ * (an expansion in progress completes).  Points are ordered by (d2, id); d2
+ * is the float32 rounding of the float64 squared distance summed over the
+ * dimensions in order.  Outputs (device): out_ids / out_d2, m x top_k
+ * (-1 / +inf past the end of a short list).  X: n x d (leading dimension
+ * ldx), G_ids: n x kappa, Q: m x d (leading dimension ldq), all device.
+ * Limits: ef <= KNNKM_SEARCH_MAX_EF, max_visits <= KNNKM_SEARCH_MAX_VISITS,
+ * n_entry <= KNNKM_SEARCH_MAX_ENTRY (KNNKM_EINVAL beyond).  Asynchronous. */
+#define KNNKM_SEARCH_MAX_EF 128
+#define KNNKM_SEARCH_MAX_VISITS 1920
+#define KNNKM_SEARCH_MAX_ENTRY 16
+knnkm_status knn_graph_search(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                              const int32_t* G_ids, int32_t kappa, const float* Q, int64_t m, int64_t ldq,
+                              int32_t ef, int32_t top_k, int32_t max_visits, int32_t n_entry, uint64_t seed,
+                              int32_t* out_ids, float* out_d2);
+
 /* Batching form: m independent jobs (graph build and fit, Alg. 3 then Alg. 2)
  * in one call, every phase one launch over all jobs.
  *  X: the jobs' rows concatenated; job q owns rows [n_off_host[q],

@@ -124,14 +124,15 @@ def search_list(X, G, q, entries, ef, top_k, max_visits):
             break
         L[nxt][2] = True
         c = L[nxt][1]
-        new = []
+        fresh = []
         for b in G[c]:
             b = int(b)
-            if b in visited:
-                continue
-            visited.add(b)
-            new.append([sq_key(q, X[b]), b, False])
-        L = sorted(L + new)[:ef]
+            if b not in visited:
+                visited.add(b)
+                fresh.append(b)
+        if fresh:
+            keys = sq_keys(q, X[fresh])
+            L = sorted(L + [[float(k), b, False] for k, b in zip(keys, fresh)])[:ef]
     return [e[1] for e in L[:top_k]], [e[0] for e in L[:top_k]]
 
 

@@ -12,7 +12,7 @@ SRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libknnkm.so")
 OBJ = os.path.join(PKG, "_build")
 SOURCES = ["ctx.hip", "assign.hip", "assign_pd.hip", "refine_exact.hip", "update.hip", "twomeans.hip", "graph.hip", "drivers.hip",
-           "server.hip", "incr.hip", "boost.hip"]
+           "server.hip", "incr.hip", "boost.hip", "search.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # packed FP32 instructions stay off (see the design notes)

@@ -5,8 +5,9 @@
 //
 // Lane l holds candidate slots l, l + 64, ... (NC of them).  Only candidates
 // that come before the row's kappa-th entry can enter, so a row none of whose
-// candidates does is left as it is after one comparison per slot.  Otherwise
-// the old row is staged in LDS; each entering candidate finds its position
+// candidates does is left as it is after one comparison per slot (the
+// kappa-th entry read from the lane holding it).  Otherwise the old row is
+// staged in LDS; each entering candidate finds its position
 // among the old entries by binary search and looks for its id among all of
 // them (a row passed in by the caller may hold any keys, so the search does
 // not rely on where its key would put the id); the entering candidates are
@@ -18,17 +19,47 @@
 
 __device__ inline bool mg_lt(float ka, int ia, float kb, int ib) { return ka < kb || (ka == kb && ia < ib); }
 
+// The old entries of a row as the lanes hold them: lane l has entries l and
+// l + 64 (FLT_MAX / INT32_MAX past kappa).  Loaded by the caller, so that the
+// next row's loads can be in flight while one row is merged.
+struct MergeRow {
+  float e0k, e1k;
+  int e0i, e1i;
+};
+
+__device__ inline MergeRow merge_load(const float* __restrict__ rowk, const int32_t* __restrict__ rowi, int kappa) {
+  const int lane = threadIdx.x & 63;
+  MergeRow m;
+  m.e0k = lane < kappa ? rowk[lane] : FLT_MAX;
+  m.e0i = lane < kappa ? rowi[lane] : INT32_MAX;
+  m.e1k = lane + 64 < kappa ? rowk[lane + 64] : FLT_MAX;
+  m.e1i = lane + 64 < kappa ? rowi[lane + 64] : INT32_MAX;
+  return m;
+}
+
 // rowk/rowi: the row (global memory), read and written by this wavefront
-// only.  sk/si: LDS scratch of kappa floats and ints for this wavefront.
+// only; old: its entries (merge_load).  sk/si: LDS scratch of kappa floats
+// and ints for this wavefront.
 template <int NC>
-__device__ inline void merge_row(float* __restrict__ rowk, int32_t* __restrict__ rowi, int kappa,
+__device__ inline void merge_row(float* __restrict__ rowk, int32_t* __restrict__ rowi, int kappa, const MergeRow& old,
                                  const float (&ck)[NC], const int (&cid)[NC], const bool (&valid)[NC],
                                  float* __restrict__ sk, int32_t* __restrict__ si) {
   const int lane = threadIdx.x & 63;
-  const float e0k = lane < kappa ? rowk[lane] : FLT_MAX;
-  const int e0i = lane < kappa ? rowi[lane] : INT32_MAX;
-  const float e1k = lane + 64 < kappa ? rowk[lane + 64] : FLT_MAX;
-  const int e1i = lane + 64 < kappa ? rowi[lane + 64] : INT32_MAX;
+  const float e0k = old.e0k, e1k = old.e1k;
+  const int e0i = old.e0i, e1i = old.e1i;
+  // the kappa-th entry, from the lane that holds it
+  const int tl = (kappa - 1) & 63;
+  const bool hi_half = kappa > 64;
+  const float tk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hi_half ? e1k : e0k), tl));
+  const int tid_ = __builtin_amdgcn_readlane(hi_half ? e1i : e0i, tl);
+  bool enter[NC];
+  bool any = false;
+#pragma unroll
+  for (int h = 0; h < NC; ++h) {
+    enter[h] = valid[h] && mg_lt(ck[h], cid[h], tk, tid_);
+    any = any || enter[h];
+  }
+  if (__ballot(any) == 0) return;  // nothing can enter: the row stays
   if (lane < kappa) {
     sk[lane] = e0k;
     si[lane] = e0i;
@@ -39,16 +70,6 @@ __device__ inline void merge_row(float* __restrict__ rowk, int32_t* __restrict__
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  const float tk = sk[kappa - 1];
-  const int tid_ = si[kappa - 1];
-  bool enter[NC];
-  bool any = false;
-#pragma unroll
-  for (int h = 0; h < NC; ++h) {
-    enter[h] = valid[h] && mg_lt(ck[h], cid[h], tk, tid_);
-    any = any || enter[h];
-  }
-  if (__ballot(any) == 0) return;  // nothing can enter: the row stays
   int pos[NC];
 #pragma unroll
   for (int h = 0; h < NC; ++h) {

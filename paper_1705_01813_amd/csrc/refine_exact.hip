@@ -214,7 +214,13 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
     __syncthreads();
   }
   // merge: one wavefront per member; lane l holds candidates l, l + 64, ...
+  // (the next member's row is loaded while one is merged)
+  MergeRow cur_row = {FLT_MAX, FLT_MAX, INT32_MAX, INT32_MAX};
+  if (w < s) cur_row = merge_load(G_d2 + (int64_t)ids[w] * kappa, G_ids + (int64_t)ids[w] * kappa, kappa);
   for (int r = w; r < s; r += 4) {
+    MergeRow nxt_row = cur_row;
+    if (r + 4 < s)
+      nxt_row = merge_load(G_d2 + (int64_t)ids[r + 4] * kappa, G_ids + (int64_t)ids[r + 4] * kappa, kappa);
     float ck[NC];
     int cid[NC];
     bool valid[NC];
@@ -228,8 +234,9 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
     const int64_t row = (int64_t)ids[r] * kappa;
     // merge scratch: this wavefront's part of the slice buffers, free now
     float* mk = xs + 2 * KNNKM_MAX_KAPPA * w;
-    merge_row<NC>(G_d2 + row, G_ids + row, kappa, ck, cid, valid, mk,
+    merge_row<NC>(G_d2 + row, G_ids + row, kappa, cur_row, ck, cid, valid, mk,
                   reinterpret_cast<int32_t*>(mk + KNNKM_MAX_KAPPA));
+    cur_row = nxt_row;
   }
 }
 

@@ -23,7 +23,7 @@ EXPORTS = [
     "knnkm_create", "knnkm_destroy", "knnkm_set_stream", "knnkm_last_error",
     "knnkm_default_params", "knnkm_workspace_bytes", "knnkm_workspace_estimate", "knn_assign", "centroid_update",
     "distortion", "knnkm_twomeans", "knnkm_graph_init", "knnkm_graph_refine", "knn_build",
-    "knn_kmeans_fit", "knn_boost_fit", "distortion_noalloc", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times", "knnkm_sweep_stats",
+    "knn_kmeans_fit", "knn_boost_fit", "knn_graph_search", "distortion_noalloc", "knnkm_rng_draw", "knnkm_enable_timing", "knnkm_phase_times", "knnkm_sweep_stats",
     "knnkm_fit_batched", "knnkm_enable_graphs", "knnkm_enable_active_sets", "knnkm_enable_subtree_finish",
     "knnkm_autotune", "knnkm_autotune_table", "knnkm_set_assign_shape", "knnkm_enable_partial_distances",
     "knnkm_server_create", "knnkm_server_submit", "knnkm_server_wait",
@@ -136,6 +136,7 @@ def lib():
             "knn_build": [P, P, i64, i32, i64, ctypes.POINTER(Params), P, P],
             "knn_kmeans_fit": [P, P, i64, i32, i64, i32, P, ctypes.POINTER(Params), P, P, P, P, P],
             "knn_boost_fit": [P, P, i64, i32, i64, i32, P, ctypes.POINTER(Params), P, P, P, P, P],
+            "knn_graph_search": [P, P, i64, i32, i64, P, i32, P, i64, i64, i32, i32, i32, i32, u64, P, P],
             "knnkm_rng_draw": [P, u64, u64, u64, i64, P],
             "knnkm_fit_batched": [P, P, i32, i64, i32, P, P, P, ctypes.POINTER(Params), P, P, P, P, P, P],
             "knnkm_enable_timing": [P, i32],
@@ -365,6 +366,21 @@ def knn_boost_fit(ctx, X, k, G_ids, params, labels, C, counts):
                              trace.ctypes.data_as(ctypes.c_void_p), ctypes.byref(it))
     _chk(ctx.handle, st)
     return trace[: it.value + 1], it.value
+
+
+def knn_graph_search(ctx, X, G_ids, Q, ef, top_k, out_ids, out_d2, max_visits=1920, n_entry=1, seed=0):
+    """Best-first search over the graph for the rows of Q (device tensors)."""
+    import torch
+
+    n, d, ldx = _rows(X)
+    m, dq, ldq = _rows(Q)
+    if dq != d:
+        raise ValueError("knn_graph_search: Q and X differ in d")
+    st = lib().knn_graph_search(ctx.handle, _ptr(X, torch.float32, "X"), n, d, ldx, _ptr(G_ids, torch.int32, "G_ids"),
+                                int(G_ids.shape[1]), _ptr(Q, torch.float32, "Q"), m, ldq, ef, top_k, max_visits,
+                                n_entry, ctypes.c_uint64(seed), _ptr(out_ids, torch.int32, "out_ids"),
+                                _ptr(out_d2, torch.float32, "out_d2"))
+    _chk(ctx.handle, st)
 
 
 def knnkm_fit_batched(ctx, X, n_off, ks, seeds, params, G_ids, G_d2, labels, C, counts):

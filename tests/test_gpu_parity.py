@@ -13,7 +13,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import boost, exact, gkmeans, knng, rng, twomeans  # noqa: E402
+from oracle import anns, boost, exact, gkmeans, knng, rng, twomeans  # noqa: E402
 from paper_1705_01813_amd import datagen, knnkm  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -599,6 +599,31 @@ def test_boost_fit_converges_to_a_fixed_point_of_alg2(ctx):
     lab0 = gkmeans.init_labels(X, k, 9, gkmeans.INIT_TWOMEANS)[0]
     w_lab = boost.boost_rounds(X, k, G, lab0, 500, seed=9)[0]
     assert np.array_equal(got, w_lab)
+
+
+@pytest.mark.parametrize("n,d,kappa,ef,top_k,visits,n_entry", [(3000, 8, 10, 16, 10, 1920, 1),
+                                                                (2500, 33, 20, 64, 20, 1920, 4),
+                                                                (4000, 5, 70, 128, 128, 1920, 16),
+                                                                (3000, 12, 10, 32, 8, 60, 2)])
+def test_graph_search_parity(ctx, n, d, kappa, ef, top_k, visits, n_entry):
+    """Best-first search over a built graph: ids and keys of every query
+    equal the oracle's search bit for bit (full and cut-off searches, several
+    entry points, kappa above one wavefront)."""
+    say("graph search", n, d, kappa, ef, top_k, visits, n_entry)
+    A = datagen.mixture(n + 200, d, 25, seed=d + kappa)
+    X, Q = A[:n], A[n:]
+    p = knnkm.default_params(kappa=kappa, xi=50, tau=3, seed=5)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    Xd = dev(X)
+    knnkm.knn_build(ctx, Xd, p, gi, gd)
+    G = host(gi)
+    ids = torch.empty((Q.shape[0], top_k), dtype=torch.int32, device=DEV)
+    d2 = torch.empty((Q.shape[0], top_k), dtype=torch.float32, device=DEV)
+    knnkm.knn_graph_search(ctx, Xd, gi, dev(Q), ef, top_k, ids, d2, max_visits=visits, n_entry=n_entry, seed=11)
+    w_i, w_d = anns.search_all(X, G, Q, ef, top_k, visits, n_entry, seed=11)
+    assert np.array_equal(host(ids), w_i)
+    assert np.array_equal(host(d2).astype(np.float64), w_d)
 
 
 def test_assign_autotune_same_result(ctx):
