@@ -109,7 +109,9 @@ def tau_study(n, seed, log, taus=(0, 1, 2, 3, 4, 5, 6, 8, 10, 14), kappa=20, sam
     C = torch.empty((k, d), dtype=torch.float32, device=dev)
     cnt = torch.empty(k, dtype=torch.int32, device=dev)
     out = []
-    for tau in taus:
+    for kappa, tau in graphs:
+        gi = torch.empty((n, kappa), dtype=torch.int32, device=dev)
+        gd = torch.empty((n, kappa), dtype=torch.float32, device=dev)
         p = knnkm.default_params(kappa=kappa, xi=50, tau=tau, max_iters=T, seed=seed)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -126,6 +128,85 @@ def tau_study(n, seed, log, taus=(0, 1, 2, 3, 4, 5, 6, 8, 10, 14), kappa=20, sam
     ctx.close()
     return {"workload": f"n={n} rows of the 1M x 128 recipe, d={d}, kappa={kappa}, xi=50; fit k={k}, T={T}; "
                         f"recall on {samples} sampled rows against exact float64 neighbours", "sweep": out}
+
+
+SEARCH = dict(n=1_000_000, d=128, xi=50, r=16)
+
+
+def search_bench(nq, seed, log, recipe="lowrank", efs=(10, 16, 32, 64, 128), entries=(1, 16), visits=(1920, 7680),
+                 graphs=((20, 10), (50, 10), (50, 32)), top_k=10, samples=1000):
+    """Nearest-neighbour search over the built graph (knn_graph_search).
+    n + nq rows of one recipe (the low-intrinsic-dimension ``lowrank`` recipe,
+    or the clustering mixture of the 1M x 128 workload), the last nq held out
+    as queries; the graph of knn_build over the rest for each (kappa, tau); the top-1
+    recall of the graph on sampled rows; recall@top_k of the search against
+    exact float64 neighbours and queries per second for several list sizes ef
+    and entry counts."""
+    import torch
+
+    from paper_1705_01813_amd import datagen, knnkm
+
+    dev = "cuda:0"
+    n, d = SEARCH["n"], SEARCH["d"]
+    if recipe == "lowrank":
+        A = torch.from_numpy(datagen.lowrank(n + nq, d, seed, r=SEARCH["r"])).to(dev)
+    else:
+        A = torch.from_numpy(datagen.config_data("c2", seed=seed, n=n + nq)).to(dev)
+    X, Q = A[:n], A[n:].contiguous()
+    # exact neighbours of the queries (plain PyTorch float64), blockwise
+    truth = []
+    for q0 in range(0, nq, 1024):
+        q = Q[q0:q0 + 1024].double()
+        best_d, best_i = None, None
+        for s0 in range(0, n, 1 << 18):
+            xb = X[s0:s0 + (1 << 18)].double()
+            dd = (q * q).sum(1, keepdim=True) + (xb * xb).sum(1)[None, :] - 2.0 * (q @ xb.T)
+            ids = torch.arange(s0, s0 + xb.shape[0], device=dev)[None, :].expand_as(dd)
+            if best_d is not None:
+                dd, ids = torch.cat([best_d, dd], 1), torch.cat([best_i, ids], 1)
+            best_d, pos = torch.topk(dd, top_k, dim=1, largest=False)
+            best_i = torch.gather(ids, 1, pos)
+        truth.append(best_i)
+    truth = torch.cat(truth).cpu().numpy()
+    rows_s = np.random.Generator(np.random.PCG64(seed + 7)).choice(n, samples, replace=False)
+    nn1 = exact_neighbours(X, torch.from_numpy(rows_s).to(dev), 1)[:, 0].cpu().numpy()
+    ctx = knnkm.Context(0)
+    out_i = torch.empty((nq, top_k), dtype=torch.int32, device=dev)
+    out_d = torch.empty((nq, top_k), dtype=torch.float32, device=dev)
+    rows = []
+    for kappa, tau in graphs:
+        gi = torch.empty((n, kappa), dtype=torch.int32, device=dev)
+        gd = torch.empty((n, kappa), dtype=torch.float32, device=dev)
+        p = knnkm.default_params(kappa=kappa, xi=SEARCH["xi"], tau=tau, seed=seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        knnkm.knn_build(ctx, X, p, gi, gd)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        g = gi.cpu().numpy()
+        r1 = float(np.mean(g[rows_s, 0] == nn1))
+        log(f"search graph kappa={kappa} tau={tau}: built in {tb:.2f} s, top-1 recall {r1:.4f}")
+        for mv, ne, ef in [(mv, ne, ef) for mv in visits for ne in entries for ef in efs]:
+            args = dict(max_visits=mv, n_entry=ne, seed=seed)
+            knnkm.knn_graph_search(ctx, X, gi, Q, ef, top_k, out_i, out_d, **args)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            knnkm.knn_graph_search(ctx, X, gi, Q, ef, top_k, out_i, out_d, **args)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            got = out_i.cpu().numpy().astype(np.int64)
+            rec = float(np.mean([len(set(a.tolist()) & set(b.tolist())) / float(top_k) for a, b in zip(got, truth)]))
+            rows.append({"kappa": kappa, "tau": tau, "graph_top1_recall": r1, "build_s": tb, "max_visits": mv,
+                         "entries": ne, "ef": ef, f"recall_at_{top_k}": rec, "queries_per_s": nq / dt,
+                         "ms": dt * 1e3})
+            log(f"search kappa={kappa} tau={tau} visits<={mv} entries={ne} ef={ef}: recall@{top_k} {rec:.4f}, "
+                f"{nq / dt:.0f} queries/s")
+    ctx.close()
+    what = (f"lowrank recipe (intrinsic dimension {SEARCH['r']}, SIFT-like integers)" if recipe == "lowrank"
+            else "the 1M x 128 clustering mixture")
+    return {"workload": f"n={n:,} d={d} {what}; {nq} held-out rows of the same draw as queries; graph of "
+                        f"knn_build (xi={SEARCH['xi']}); recall@{top_k} against exact float64 "
+                        "neighbours; one launch over all queries", "sweep": rows}
 
 
 def scaling_sweeps(seed, log, ns=(10_000, 100_000, 1_000_000, 10_000_000), ks=(1024, 2048, 4096, 8192), T=30):
@@ -729,6 +810,10 @@ def main():
                          "graph and initialisation and report its rounds, time and distortion beside the Lloyd form's")
     ap.add_argument("--tau-study", type=int, default=0, metavar="N",
                     help="graph recall and fit distortion against the number of construction rounds on N rows")
+    ap.add_argument("--search", type=int, default=0, metavar="Q",
+                    help="graph search: Q held-out queries against a 1M x 128 graph, recall@10 and queries/s")
+    ap.add_argument("--search-recipe", default="lowrank", choices=["lowrank", "mixture"],
+                    help="input recipe of --search")
     ap.add_argument("--scaling", action="store_true",
                     help="the scalability sweeps at d=512: n from 10k to 10M at k=1024, k from 1024 to 8192 at n=1M")
     ap.add_argument("--xi-sweep", type=int, default=0, metavar="N",
@@ -760,6 +845,10 @@ def main():
 
     if args.tau_study:
         print(json.dumps({"tau_study": tau_study(args.tau_study, args.seed, log)}), flush=True)
+        return 0
+    if args.search:
+        print(json.dumps({"search": search_bench(args.search, args.seed, log, recipe=args.search_recipe)}),
+              flush=True)
         return 0
     if args.scaling:
         print(json.dumps({"scaling": scaling_sweeps(args.seed, log)}), flush=True)

@@ -235,9 +235,12 @@ knnkm_status knn_boost_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d,
  * (-1 / +inf past the end of a short list).  X: n x d (leading dimension
  * ldx), G_ids: n x kappa, Q: m x d (leading dimension ldq), all device.
  * Limits: ef <= KNNKM_SEARCH_MAX_EF, max_visits <= KNNKM_SEARCH_MAX_VISITS,
- * n_entry <= KNNKM_SEARCH_MAX_ENTRY (KNNKM_EINVAL beyond).  Asynchronous. */
+ * n_entry <= KNNKM_SEARCH_MAX_ENTRY (KNNKM_EINVAL beyond).  Up to 1,920
+ * visits four queries share a workgroup; above that each query holds a
+ * larger table of visited points and fewer queries run at once.
+ * Asynchronous. */
 #define KNNKM_SEARCH_MAX_EF 128
-#define KNNKM_SEARCH_MAX_VISITS 1920
+#define KNNKM_SEARCH_MAX_VISITS 7680
 #define KNNKM_SEARCH_MAX_ENTRY 16
 knnkm_status knn_graph_search(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                               const int32_t* G_ids, int32_t kappa, const float* Q, int64_t m, int64_t ldq,

@@ -15,8 +15,10 @@
 // Points are compared by (d2, id), d2 the squared distance summed over the
 // dimensions in order in float64 with one rounding per operation, rounded
 // once to float32 (the keys of the graph) -- each distance by one lane.
-// Points seen are kept in an open-addressing hash in LDS (4,096 slots,
-// filled to at most about half by the visit limit).
+// Points seen are kept in an open-addressing hash in LDS, filled to at most
+// about half by the visit limit: 4,096 slots (four queries per workgroup)
+// for up to 1,920 visits, else 16,384 slots (one query per workgroup, two
+// workgroups per compute unit).
 #include <cfloat>
 #include <climits>
 
@@ -24,12 +26,13 @@
 
 namespace {
 
-constexpr int SR_HASH = 4096;
 constexpr uint64_t SR_PURPOSE = 5;  // random-number stream of the entry points
+constexpr int SR_SMALL_VISITS = 1920;  // visit limit of the 4,096-slot hash
 
+template <int HB>  // log2 of the hash slots
 struct SRWave {
   float q[KNNKM_MAX_D];
-  int32_t hash[SR_HASH];
+  int32_t hash[1 << HB];
   float lk[KNNKM_SEARCH_MAX_EF];
   int32_t li[KNNKM_SEARCH_MAX_EF];
   int32_t lx[KNNKM_SEARCH_MAX_EF];
@@ -44,13 +47,14 @@ __device__ inline void sr_sync() {
 }
 
 // Inserts id; true if it was not there yet.
+template <int HB>
 __device__ inline bool sr_insert(int32_t* hash, int32_t id) {
-  uint32_t h = ((uint32_t)id * 2654435761u) >> (32 - 12);  // 12 = log2(SR_HASH)
+  uint32_t h = ((uint32_t)id * 2654435761u) >> (32 - HB);
   while (true) {
     const int32_t prev = atomicCAS(&hash[h], -1, id);
     if (prev == -1) return true;
     if (prev == id) return false;
-    h = (h + 1) & (SR_HASH - 1);
+    h = (h + 1) & ((1u << HB) - 1);
   }
 }
 
@@ -68,7 +72,8 @@ __device__ inline float sr_key(const float* __restrict__ q, const float* __restr
 // Merges the candidates held by the lanes with `in` set (key ck, id ci) into
 // the sorted list (slots l and l + 64 held by lane l: k0/i0/x0, k1/i1/x1;
 // cnt entries), keeping the ef smallest; new entries are unexpanded.
-__device__ inline void sr_merge(SRWave& sh, bool in, float ck, int ci, int ef, int& cnt, float& k0, int& i0,
+template <class W>
+__device__ inline void sr_merge(W& sh, bool in, float ck, int ci, int ef, int& cnt, float& k0, int& i0,
                                 int& x0, float& k1, int& i1, int& x1) {
   const int lane = threadIdx.x & 63;
   uint64_t M = __ballot(in);
@@ -120,17 +125,19 @@ __device__ inline void sr_merge(SRWave& sh, bool in, float ck, int ci, int ef, i
   x1 = lane + 64 < cnt ? sh.lx[lane + 64] : 1;
 }
 
-__global__ __launch_bounds__(256) void k_graph_search(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
-                                                      const int32_t* __restrict__ G, int kappa,
-                                                      const float* __restrict__ Q, int64_t m, int64_t ldq, int ef,
-                                                      int top_k, int max_visits, int n_entry, uint64_t seed,
-                                                      int32_t* __restrict__ out_ids, float* __restrict__ out_d2) {
-  __shared__ SRWave shw[4];
+template <int HB, int WPB>  // hash bits, queries (wavefronts) per workgroup
+__global__ __launch_bounds__(64 * WPB) void k_graph_search(const float* __restrict__ X, int64_t n, int d,
+                                                           int64_t ldx, const int32_t* __restrict__ G, int kappa,
+                                                           const float* __restrict__ Q, int64_t m, int64_t ldq,
+                                                           int ef, int top_k, int max_visits, int n_entry,
+                                                           uint64_t seed, int32_t* __restrict__ out_ids,
+                                                           float* __restrict__ out_d2) {
+  __shared__ SRWave<HB> shw[WPB];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  SRWave& sh = shw[w];
-  for (int64_t qi = blockIdx.x * 4 + w; qi < m; qi += (int64_t)gridDim.x * 4) {
+  SRWave<HB>& sh = shw[w];
+  for (int64_t qi = (int64_t)blockIdx.x * WPB + w; qi < m; qi += (int64_t)gridDim.x * WPB) {
     for (int j = lane; j < d; j += 64) sh.q[j] = Q[qi * ldq + j];
-    for (int j = lane; j < SR_HASH; j += 64) sh.hash[j] = -1;
+    for (int j = lane; j < (1 << HB); j += 64) sh.hash[j] = -1;
     // entry points (Floyd's sampling, one draw per step)
     const int ne = (int)min<int64_t>(n_entry, n);
     if (lane == 0) {
@@ -154,7 +161,7 @@ __global__ __launch_bounds__(256) void k_graph_search(const float* __restrict__ 
       float key = FLT_MAX;
       if (in) {
         id = sh.ent[lane];
-        sr_insert(sh.hash, id);
+        sr_insert<HB>(sh.hash, id);
         key = sr_key(sh.q, X + (int64_t)id * ldx, d);
       }
       sr_merge(sh, in, key, id, ef, cnt, k0, i0, x0, k1, i1, x1);
@@ -183,7 +190,7 @@ __global__ __launch_bounds__(256) void k_graph_search(const float* __restrict__ 
       for (int e0 = 0; e0 < kappa; e0 += 64) {
         const int e = e0 + lane;
         const int b = e < kappa ? G[(int64_t)c * kappa + e] : -1;
-        const bool fresh = b >= 0 && b < n && sr_insert(sh.hash, b);
+        const bool fresh = b >= 0 && b < n && sr_insert<HB>(sh.hash, b);
         visited += __popcll(__ballot(fresh));
         float key = FLT_MAX;
         if (fresh) key = sr_key(sh.q, X + (int64_t)b * ldx, d);
@@ -226,7 +233,11 @@ extern "C" knnkm_status knn_graph_search(knnkm_ctx* ctx, const float* X, int64_t
     return knnkm_fail(ctx, KNNKM_EINVAL, "knn_graph_search: n_entry not in [1, %d]", KNNKM_SEARCH_MAX_ENTRY);
   if (ctx->dry || m == 0) return KNNKM_OK;
   KNNKM_HIP(ctx, hipSetDevice(ctx->device));
-  k_graph_search<<<grid_for(m, 4, 65536), 256, 0, ctx->stream>>>(X, n, d, ldx, G_ids, kappa, Q, m, ldq, ef, top_k,
-                                                                 max_visits, n_entry, seed, out_ids, out_d2);
+  if (max_visits <= SR_SMALL_VISITS)
+    k_graph_search<12, 4><<<grid_for(m, 4, 65536), 256, 0, ctx->stream>>>(
+        X, n, d, ldx, G_ids, kappa, Q, m, ldq, ef, top_k, max_visits, n_entry, seed, out_ids, out_d2);
+  else
+    k_graph_search<14, 1><<<grid_for(m, 1, 65536), 64, 0, ctx->stream>>>(
+        X, n, d, ldx, G_ids, kappa, Q, m, ldq, ef, top_k, max_visits, n_entry, seed, out_ids, out_d2);
   return knnkm_check(ctx, "knn_graph_search");
 }

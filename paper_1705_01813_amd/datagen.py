@@ -11,6 +11,13 @@ returns.  Recipes (stand-ins for the paper's datasets, Table 1):
   shape of SIFT1M (1M x 128 non-negative integer features); with centres
   N(0,1)^512 and sigma 0.5 it has the shape of VLAD10M (10M x 512).
 * ``integer_grid``: integers in [0, 255] (exact in float32 and bfloat16).
+* ``lowrank``: features of low intrinsic dimension, for nearest-neighbour
+  search.  A latent z in R^r is an overlapping Gaussian mixture (component
+  means N(0, spread^2 I), unit covariance); the feature is an offset plus a
+  random linear map of z (entries N(0, 1/r), scaled) plus isotropic noise,
+  clipped and rounded like SIFT.  Unlike the well-separated mixtures above,
+  whose KNN graphs fall apart into one piece per component, it has the
+  continuous local structure that a search over a KNN graph walks through.
 
 Host generation uses numpy's PCG64; ``mixture_device`` draws the same recipe
 with torch on a GPU (different bits, same distribution) for sizes where host
@@ -82,6 +89,26 @@ def mixture_device(n, d, comps, seed, centre="uniform", lo=-10.0, hi=10.0, sigma
         if integer:
             blk = torch.round(blk)
         X[s:e] = blk
+    return X
+
+
+def lowrank(n, d, seed, r=16, comps=100, spread=2.0, scale=20.0, offset=100.0, noise=4.0,
+            clip=(0.0, 255.0), integer=True):
+    rs = np.random.Generator(np.random.PCG64(seed))
+    W = rs.standard_normal(size=(r, d)) * (scale / np.sqrt(r))
+    means = spread * rs.standard_normal(size=(comps, r))
+    comp = rs.integers(0, comps, size=n)
+    X = np.empty((n, d), np.float32)
+    step = 1 << 16
+    for s in range(0, n, step):
+        e = min(n, s + step)
+        z = means[comp[s:e]] + rs.standard_normal(size=(e - s, r))
+        blk = offset + z @ W + noise * rs.standard_normal(size=(e - s, d))
+        if clip is not None:
+            np.clip(blk, clip[0], clip[1], out=blk)
+        if integer:
+            blk = np.rint(blk)
+        X[s:e] = blk.astype(np.float32)
     return X
 
 

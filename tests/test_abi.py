@@ -144,3 +144,22 @@ def test_workspace_estimate_validation():
         with pytest.raises(knnkm.KnnkmError) as e:
             knnkm.knnkm_workspace_estimate(n, d, k, p)
         assert e.value.status == knnkm.EINVAL
+
+
+def test_graph_search_validation(dry):
+    h = dry.handle
+    X = ctypes.c_void_p(0x1000)
+    P = ctypes.c_void_p(0x2000)
+    O = ctypes.c_void_p(0x3000)
+
+    def call(n=100, d=8, kappa=10, m=5, ef=16, top_k=10, visits=1920, n_entry=1, ldx=None):
+        return knnkm.lib().knn_graph_search(h, X, n, d, d if ldx is None else ldx, P, kappa, X, m, d, ef, top_k,
+                                            visits, n_entry, ctypes.c_uint64(0), O, O)
+
+    assert call() == knnkm.OK
+    assert call(m=0) == knnkm.OK
+    assert call(visits=7680, ef=128, top_k=128, n_entry=16) == knnkm.OK
+    for kw in [dict(visits=7681), dict(visits=0), dict(ef=129), dict(top_k=17), dict(top_k=0), dict(n_entry=17),
+               dict(n_entry=0), dict(kappa=0), dict(ldx=7), dict(n=0), dict(m=-1)]:
+        assert call(**kw) == knnkm.EINVAL, kw
+    assert call(d=513) == knnkm.EUNSUPPORTED

@@ -601,16 +601,18 @@ def test_boost_fit_converges_to_a_fixed_point_of_alg2(ctx):
     assert np.array_equal(got, w_lab)
 
 
-@pytest.mark.parametrize("n,d,kappa,ef,top_k,visits,n_entry", [(3000, 8, 10, 16, 10, 1920, 1),
-                                                                (2500, 33, 20, 64, 20, 1920, 4),
-                                                                (4000, 5, 70, 128, 128, 1920, 16),
-                                                                (3000, 12, 10, 32, 8, 60, 2)])
-def test_graph_search_parity(ctx, n, d, kappa, ef, top_k, visits, n_entry):
+@pytest.mark.parametrize("n,d,kappa,ef,top_k,visits,n_entry,comps", [(3000, 8, 10, 16, 10, 1920, 1, 25),
+                                                                      (2500, 33, 20, 64, 20, 1920, 4, 25),
+                                                                      (4000, 5, 70, 128, 128, 1920, 16, 25),
+                                                                      (3000, 12, 10, 32, 8, 60, 2, 25),
+                                                                      (8000, 24, 100, 128, 128, 5000, 8, 1)])
+def test_graph_search_parity(ctx, n, d, kappa, ef, top_k, visits, n_entry, comps):
     """Best-first search over a built graph: ids and keys of every query
     equal the oracle's search bit for bit (full and cut-off searches, several
-    entry points, kappa above one wavefront)."""
-    say("graph search", n, d, kappa, ef, top_k, visits, n_entry)
-    A = datagen.mixture(n + 200, d, 25, seed=d + kappa)
+    entry points, kappa above one wavefront, a visit limit above 1,920 that
+    takes the larger table of visited points and binds on some queries)."""
+    say("graph search", n, d, kappa, ef, top_k, visits, n_entry, comps)
+    A = datagen.mixture(n + 200, d, comps, seed=d + kappa)
     X, Q = A[:n], A[n:]
     p = knnkm.default_params(kappa=kappa, xi=50, tau=3, seed=5)
     gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
