@@ -380,7 +380,9 @@ def traffic_summary(config, fetch_csv, write_csv, bench_json):
         total = sum(ds[i][2] for i in last)
         compact = sum(x[2] for x in ds[last[0]:last[-1] + 1] if "k_act_compact" in x[1])
         out[counter] = {"scale": scale, "copy_kib": copy[2], "raw_kib_per_launch": (total + compact) / launches,
-                        "first_kib": ds[last[0]][2], "first_kernel": ds[last[0]][1].split("(")[0]}
+                        "first_kib": ds[last[0]][2],
+                        "first_kernel": ds[last[0]][1].replace("(anonymous namespace)::", "").replace("void ", "",
+                                                                                                      1).split("(")[0]}
     f, w = out["FETCH_SIZE"], out["WRITE_SIZE"]
     fetch_b = f["raw_kib_per_launch"] * 1024 * f["scale"]
     write_b = w["raw_kib_per_launch"] * 1024 * w["scale"]
@@ -825,6 +827,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=None,
                     help="arrival window of the serving run (default 2 s beside the main line, 60 s for c5)")
     ap.add_argument("--seed", type=int, default=1234)
+    ap.add_argument("--pd-mode", type=int, default=None, choices=[0, 1, 2, 3],
+                    help="wide-row partial distances: 0 off, 1 8-bit shadow (the library's default), 2 float32 "
+                         "only, 3 bfloat16 shadow")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -886,6 +891,8 @@ def main():
 
     ctx = knnkm.Context(0)
     knnkm.knnkm_enable_timing(ctx, True)
+    if args.pd_mode is not None:
+        knnkm.knnkm_enable_partial_distances(ctx, args.pd_mode)
     if args.counters:
         knnkm.knnkm_enable_graphs(ctx, False)
         args.no_forms = args.no_cpu_baseline = args.no_precision = True

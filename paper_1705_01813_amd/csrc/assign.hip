@@ -438,6 +438,19 @@ __global__ __launch_bounds__(256) void k_act_compact(int64_t n, uint8_t* __restr
     }
 }
 
+// bits[r / 32] bit r % 32 = (flags[r] != 0), for r < K (the last word's
+// bits past K are 0)
+__global__ __launch_bounds__(256) void k_pack_flags(const int32_t* __restrict__ flags, int32_t K,
+                                                    uint32_t* __restrict__ bits) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t b = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); b < K; b += (int64_t)gridDim.x * 256) {
+    const int64_t r = b + lane;
+    const uint64_t m = __ballot(r < K && flags[r] != 0);
+    if (lane == 0) bits[b >> 5] = (uint32_t)m;
+    if (lane == 32) bits[(b >> 5) + 1] = (uint32_t)(m >> 32);
+  }
+}
+
 // The listed samples, GS per row group (grid-stride over the list), each
 // through the same candidate collection, float32 pass and float64 pass as
 // k_assign with one sample per group, so labels are the same bits.  The
@@ -449,7 +462,7 @@ __global__ __launch_bounds__(256) void k_act_compact(int64_t n, uint8_t* __restr
 // of unlisted samples are not written: the update keeps both label arrays
 // equal outside the samples a sweep moves.  act_out as in k_assign.  A
 // listed sample whose candidate set is unchanged (bit 1 clear) and none of
-// whose candidate centroids changed in the last update (cdirty, per
+// whose candidate centroids changed in the last update (cbits, one bit per
 // cluster; null: all changed) has all the inputs of its last decision, to
 // stay, so it stays without a distance being evaluated.
 template <int L, int V, int SM, int GS>
@@ -459,7 +472,7 @@ __global__ __launch_bounds__(256) void k_assign_list(
     unsigned long long* __restrict__ moved_acc, unsigned long long* __restrict__ eval_acc,
     const int32_t* __restrict__ list, const int32_t* __restrict__ count, double rel, int vec_x, int vec_c,
     const int* __restrict__ job_of, const int* __restrict__ kbase, uint8_t* __restrict__ act_out,
-    int64_t* __restrict__ n_listed, const int32_t* __restrict__ cdirty) {
+    int64_t* __restrict__ n_listed, const uint32_t* __restrict__ cbits) {
   constexpr int GW = 64 / L;
   __shared__ unsigned int block_moved, block_eval;
   if (threadIdx.x == 0) {
@@ -525,10 +538,10 @@ __global__ __launch_bounds__(256) void k_assign_list(
       for (int s = 0; s < SM; ++s) other = other || (valid[p][s] && cv[p][s] != cur[p]);
       const bool single = live[p] && !dn[p] && cur[p] >= 0 && (__ballot(other) & gmask) == 0;
       bool cand_dirty = true;
-      if (!changed[p] && !dn[p] && cdirty) {
+      if (!changed[p] && !dn[p] && cbits) {
         bool any = false;
 #pragma unroll
-        for (int s = 0; s < SM; ++s) any = any || (valid[p][s] && cdirty[cv[p][s]] != 0);
+        for (int s = 0; s < SM; ++s) any = any || (valid[p][s] && bit_of(cbits, cv[p][s]));
         cand_dirty = (__ballot(any) & gmask) != 0;
       }
       eval[p] = false;
@@ -733,9 +746,9 @@ extern "C" knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on) {
 
 extern "C" knnkm_status knnkm_enable_partial_distances(knnkm_ctx* ctx, int32_t on) {
   if (!ctx) return KNNKM_EINVAL;
-  if (on < 0 || on > 2) return knnkm_fail(ctx, KNNKM_EINVAL, "partial distances: %d is not 0, 1 or 2", on);
+  if (on < 0 || on > 3) return knnkm_fail(ctx, KNNKM_EINVAL, "partial distances: %d is not 0, 1, 2 or 3", on);
   ctx->wide_pd = on != 0;
-  ctx->pd_shadow = on == 1;
+  ctx->pd_shadow = on == 1 ? 2 : (on == 3 ? 1 : 0);
   return KNNKM_OK;
 }
 
@@ -764,8 +777,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        int64_t* n_moved, const int32_t* order, bool dense, const int32_t* job_of,
                        const int32_t* kbase, int use, int64_t* n_eval, const uint8_t* act_in, uint8_t* act_out,
                        int64_t* n_active, int32_t* list_count, int32_t* list_count_other, bool zero_moved,
-                       const int32_t* cdirty, float* bnd_u, float* bnd_lb, const float* cdelta,
-                       const uint16_t* Cb, const float* ceps) {
+                       const int32_t* cdirty, float* bnd_u, float* bnd_lb, const float* cdelta, CShadow sw) {
   if (n_moved && zero_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
   if (n_eval) KNNKM_TRY(ks_fill_i64(ctx, n_eval, 1, 0));
   if (n_active && !(act_in && !best_d2 && !order && !dense)) KNNKM_TRY(ks_fill_i64(ctx, n_active, 1, n));
@@ -800,16 +812,24 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
     }
     k_act_compact<<<(unsigned)((n + 4095) / 4096), 256, 0, ctx->stream>>>(n, const_cast<uint8_t*>(act_in), list, cnt,
                                                                           list_count_other);
+    // the changed-centroid flags as one bit per cluster: the listed samples
+    // look them up for every candidate, and a bit array small enough to stay
+    // in the caches turns those scattered reads into cache hits
+    uint32_t* cbits = nullptr;
+    if (cdirty) {
+      cbits = (uint32_t*)knnkm_ws(ctx, "as_cbits", sizeof(uint32_t) * (((size_t)k + 63) / 64) * 2);
+      if (!cbits) return KNNKM_ENOMEM;
+      k_pack_flags<<<grid_for(k, 256, 65535), 256, 0, ctx->stream>>>(cdirty, k, cbits);
+    }
     if (wide)
       return ks_assign_pd(ctx, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc, eacc, nullptr, job_of,
-                          kbase, nullptr, act_out, list, cnt, n_active, cdirty, 0, bnd_u, bnd_lb, cdelta, Cb,
-                          ceps);
+                          kbase, nullptr, act_out, list, cnt, n_active, cbits, 0, bnd_u, bnd_lb, cdelta, sw);
     const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
 #define LP(LL, VV, SS)                                                                                        \
   k_assign_list<LL, VV, SS, ((LL) >= 64 ? 2 : 1)><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
                                                            acc, eacc, list, cnt, rel, vec_x ? 1 : 0,            \
                                                            vec_c ? 1 : 0, job_of, kbase, act_out, n_active,    \
-                                                           cdirty)
+                                                           cbits)
 #define LPS(LL, VV)     \
   if (S <= 1)           \
     LP(LL, VV, 1);      \
@@ -862,8 +882,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
 #undef LA
   if (wide)
     return ks_assign_pd(ctx, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc, eacc, order, job_of,
-                        kbase, act_in, act_out, nullptr, nullptr, nullptr, nullptr, 64, bnd_u, bnd_lb, nullptr, Cb,
-                        ceps);
+                        kbase, act_in, act_out, nullptr, nullptr, nullptr, nullptr, 64, bnd_u, bnd_lb, nullptr, sw);
   // shape: tuned entry, else (large call, tuning allowed, not inside a
   // graph capture) time every candidate once, else the default
   const int Sb = S <= 1 ? 1 : (S <= 2 ? 2 : (S <= 4 ? 4 : 8));

@@ -43,11 +43,15 @@
 
 namespace {
 
-// dimensions per early-abandon step: 64 of float32, 128 of bfloat16 (the same
-// 32 bytes per lane and candidate; at most eight chunk additions, 16 products
-// per lane, either way within the error bound pd_rel)
-template <bool SH>
-constexpr int pd_chunk() { return SH ? 128 : 64; }
+// dimensions per early-abandon step (within the error bound pd_rel of the
+// shadow kind): 64 of float32, 128 of bfloat16 (32 bytes per lane and
+// candidate); of 8-bit codes 256 in full sweeps (32 bytes per lane: fewer
+// dependent steps for the many candidates alive there) and 128 on active
+// sets (16 bytes per lane: finer abandoning for the few)
+template <int SK>
+constexpr int pd_chunk_full() { return SK == 2 ? 256 : (SK ? 128 : 64); }
+template <int SK>
+constexpr int pd_chunk_list() { return SK ? 128 : 64; }
 
 constexpr int PD_SB = 4;      // candidate batches whose loads are in flight together
 constexpr int PD_EX = 4;      // full float32 rows in flight together
@@ -146,16 +150,18 @@ __device__ __attribute__((always_inline)) inline void pd_exact(PDWave& sh, int n
 // e (entry e: 0 own, 1..kappa neighbours; -1 unused).  skip (lane-held): the
 // entry's cluster is already known to be strictly farther than the own
 // centroid, so it takes no part (its lane's lb is left to the caller).
-// Cb/eps: the bfloat16 shadow of C (null: the float32 rows are read).
+// sw: the shadow of C read in the chunk steps (SK = sw.kind; 0: the float32
+// rows).
 // pilot: the first slot's full distance is taken with the own one.  Returns
 // the label and the bounds of PDResult: every candidate's squared distance
 // is bracketed by rigorous bounds (a dropped one from below by its partial
 // sum), so they hold for the exact distances.
-template <int GL, bool SH>
-__device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow, int d, bool vec_x,
-                                     const float* __restrict__ C, bool vec_c, const uint16_t* __restrict__ Cb,
-                                     const float* __restrict__ eps, bool vec_b, int cur, int cv, double rel,
-                                     bool skip, bool pilot) {
+template <int GL, int SK, int CHK>
+__device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
+                                                                    int d, bool vec_x, const float* __restrict__ C,
+                                                                    bool vec_c, CShadow sw, bool vec_b, int cur,
+                                                                    int cv, double rel, bool skip, bool pilot) {
+  const float* __restrict__ eps = sw.eps;
   const int lane = threadIdx.x & 63;
   // the row into LDS (lane j: dims [8j, 8j+8), read back by the same lane
   // where the 64-lane layout is used)
@@ -187,9 +193,9 @@ __device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, 
   wave_lds_sync();
   const double ub = (double)fminf(sh.full[0], np ? sh.full[1] : FLT_MAX) * (1.0 + rel) + 1e-30;
   constexpr int NG = 64 / GL;        // candidates per batch
-  constexpr int CHK = pd_chunk<SH>();
   constexpr int PL = CHK / GL;  // dimensions per lane and chunk
-  static_assert(PL == 8 || (SH && PL == 16), "32 bytes per lane and chunk");
+  static_assert(PL * (SK == 2 ? 1 : (SK == 1 ? 2 : 4)) == 32 || (SK == 2 && PL == 16),
+                "32 bytes per lane and chunk (16 of 8-bit codes on active sets)");
   const int g = lane / GL, jj = lane % GL;
   const int nch = (d + CHK - 1) / CHK;
   // the other slots, breadth first (al[0] lists slots 1..A0; the first np
@@ -202,10 +208,12 @@ __device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, 
     int nA = 0;
     for (int s0 = 0; s0 < A; s0 += NG * PD_SB) {
       int slot[PD_SB];
-      // the chunk of each batch's candidate: 8 bfloat16 (packed in four
-      // words) or 8 float32 values per lane
-      constexpr int NW = SH ? PL / 2 : PL;
+      // the chunk of each batch's candidate per lane: 8 float32 values, 16
+      // bfloat16 (two per word) or 16 or 32 codes (four per word), and the
+      // code step of the candidate
+      constexpr int NW = SK == 2 ? PL / 4 : (SK == 1 ? PL / 2 : PL);
       uint32_t cq[PD_SB][NW];
+      float sc[PD_SB];
 #pragma unroll
       for (int u = 0; u < PD_SB; ++u) {
         const int idx = s0 + u * NG + g;
@@ -214,11 +222,31 @@ __device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, 
 #pragma unroll
       for (int u = 0; u < PD_SB; ++u) {
 #pragma unroll
-        for (int e = 0; e < NW; ++e) cq[u][e] = 0u;
+        for (int e = 0; e < NW; ++e) cq[u][e] = SK == 2 ? 0x80808080u : 0u;
+        sc[u] = 0.f;
         if (slot[u] < 0) continue;
         const int64_t q = sh.cand[slot[u]];
-        if constexpr (SH) {
-          const uint16_t* br = Cb + q * d;
+        if constexpr (SK == 2) {
+          const uint8_t* br = (const uint8_t*)sw.rows + q * d;
+          sc[u] = sw.scale[q];
+          if (vec_b && base + PL <= d) {
+#pragma unroll
+            for (int h = 0; h < PL / 16; ++h) {
+              const uint4 v = *reinterpret_cast<const uint4*>(br + base + 16 * h);
+              cq[u][4 * h] = v.x;
+              cq[u][4 * h + 1] = v.y;
+              cq[u][4 * h + 2] = v.z;
+              cq[u][4 * h + 3] = v.w;
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < PL; ++e) {
+              const uint32_t b = base + e < d ? br[base + e] : 128u;  // code 128: the value 0
+              cq[u][e / 4] = (cq[u][e / 4] & ~(0xFFu << (8 * (e % 4)))) | (b << (8 * (e % 4)));
+            }
+          }
+        } else if constexpr (SK == 1) {
+          const uint16_t* br = (const uint16_t*)sw.rows + q * d;
           if (vec_b && base + PL <= d) {
 #pragma unroll
             for (int h = 0; h < PL / 8; ++h) {
@@ -264,36 +292,41 @@ __device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, 
 #pragma unroll
           for (int e = 0; e < PL; e += 4) {
             const float4 xq = *reinterpret_cast<const float4*>(&sh.x[base + e]);
-            float c0, c1, c2, c3;
-            if constexpr (SH) {
-              c0 = bf16_f32(cq[u][e / 2] & 0xFFFFu);
-              c1 = bf16_f32(cq[u][e / 2] >> 16);
-              c2 = bf16_f32(cq[u][e / 2 + 1] & 0xFFFFu);
-              c3 = bf16_f32(cq[u][e / 2 + 1] >> 16);
+            float df0, df1, df2, df3;
+            if constexpr (SK == 2) {
+              // x - s (u - 128) with one rounding (the shadow value is the
+              // exact product)
+              const uint32_t w4 = cq[u][e / 4];
+              const float ns = -sc[u];
+              df0 = fmaf(ns, (float)(w4 & 0xFFu) - 128.f, xq.x);
+              df1 = fmaf(ns, (float)((w4 >> 8) & 0xFFu) - 128.f, xq.y);
+              df2 = fmaf(ns, (float)((w4 >> 16) & 0xFFu) - 128.f, xq.z);
+              df3 = fmaf(ns, (float)(w4 >> 24) - 128.f, xq.w);
+            } else if constexpr (SK == 1) {
+              df0 = xq.x - bf16_f32(cq[u][e / 2] & 0xFFFFu);
+              df1 = xq.y - bf16_f32(cq[u][e / 2] >> 16);
+              df2 = xq.z - bf16_f32(cq[u][e / 2 + 1] & 0xFFFFu);
+              df3 = xq.w - bf16_f32(cq[u][e / 2 + 1] >> 16);
             } else {
-              c0 = __uint_as_float(cq[u][e]);
-              c1 = __uint_as_float(cq[u][e + 1]);
-              c2 = __uint_as_float(cq[u][e + 2]);
-              c3 = __uint_as_float(cq[u][e + 3]);
+              df0 = xq.x - __uint_as_float(cq[u][e]);
+              df1 = xq.y - __uint_as_float(cq[u][e + 1]);
+              df2 = xq.z - __uint_as_float(cq[u][e + 2]);
+              df3 = xq.w - __uint_as_float(cq[u][e + 3]);
             }
-            float df = xq.x - c0;
-            acc = fmaf(df, df, acc);
-            df = xq.y - c1;
-            acc = fmaf(df, df, acc);
-            df = xq.z - c2;
-            acc = fmaf(df, df, acc);
-            df = xq.w - c3;
-            acc = fmaf(df, df, acc);
+            acc = fmaf(df0, df0, acc);
+            acc = fmaf(df1, df1, acc);
+            acc = fmaf(df2, df2, acc);
+            acc = fmaf(df3, df3, acc);
           }
         }
         const float sum = gl_sum<GL>(acc);
         bool keep = false;
         if (slot[u] >= 0) {
           const float P = sh.part[slot[u]] + sum;
-          const double lo = SH ? pd_lower(P, rel, eps[sh.cand[slot[u]]]) : (double)P * (1.0 - rel);
+          const double lo = SK ? pd_lower(P, rel, eps[sh.cand[slot[u]]]) : (double)P * (1.0 - rel);
           if (lo > ub) {
             if (jj == 0) sh.lb[slot[u]] = f32_round_down(lo);
-          } else if (last && !SH) {
+          } else if (last && !SK) {
             if (jj == 0) {
               sh.full[slot[u]] = P;
               sh.lb[slot[u]] = f32_round_down(lo);
@@ -315,7 +348,7 @@ __device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, 
     A = nA;
     buf ^= 1;
   }
-  if (SH && A > 0) {
+  if (SK && A > 0) {
     // the survivors' shadow distances bracket their distances: only those
     // whose lower bound is within the smallest upper bound (and ub) can be
     // the closest or tie with it
@@ -421,15 +454,14 @@ __device__ inline int pd_candidate(int lane, int64_t i, int cur, const int* __re
 // Full sweep: block b takes pb consecutive positions of `order` (or of the
 // identity), wave w of it the positions w, w+4, ...  Same arguments and
 // outputs as k_assign without best distances.
-template <int GL, bool SH>
+template <int GL, int SK>
 __global__ __launch_bounds__(256) void k_assign_pd(
     const float* __restrict__ X, int n, int d, int64_t ldx, const float* __restrict__ C, int k,
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
     unsigned long long* __restrict__ moved_acc, unsigned long long* __restrict__ eval_acc,
     const int* __restrict__ order, int nchunks, int pb, double rel, int vec_x, int vec_c,
     const int* __restrict__ job_of, const int* __restrict__ kbase, const uint8_t* __restrict__ act_in,
-    uint8_t* __restrict__ act_out, float* __restrict__ bnd_u, float* __restrict__ bnd_lb,
-    const uint16_t* __restrict__ Cb, const float* __restrict__ ceps, int vec_b) {
+    uint8_t* __restrict__ act_out, float* __restrict__ bnd_u, float* __restrict__ bnd_lb, CShadow sw, int vec_b) {
   __shared__ PDWave sh[4];
   __shared__ unsigned int block_moved, block_eval;
   if (threadIdx.x == 0) {
@@ -470,7 +502,8 @@ __global__ __launch_bounds__(256) void k_assign_pd(
         }
         continue;
       }
-      const PDResult r = pd_decide<GL, SH>(sh[w], X + i * ldx, d, vec_x, C, vec_c, Cb, ceps, vec_b, cur, cv, rel, false,
+      const PDResult r = pd_decide<GL, SK, pd_chunk_full<SK>()>(sh[w], X + i * ldx, d, vec_x, C, vec_c, sw, vec_b,
+                                                                 cur, cv, rel, false,
                                            true);
       if (bnd_u && lane <= kappa) bnd_lb[i * (kappa + 1) + lane] = r.lb;
       if (lane == 0) {
@@ -498,16 +531,15 @@ __global__ __launch_bounds__(256) void k_assign_pd(
 // of the candidate clusters) are issued for all NS samples before any is
 // used, then the samples are decided one after the other.  Same outputs as
 // k_assign_list.
-template <int GL, int NS, bool SH>
+template <int GL, int NS, int SK>
 __global__ __launch_bounds__(256) void k_assign_list_pd(
     const float* __restrict__ X, int d, int64_t ldx, const float* __restrict__ C, int k,
     const int* __restrict__ G, int kappa, const int* __restrict__ lab_in, int* __restrict__ lab_out,
     unsigned long long* __restrict__ moved_acc, unsigned long long* __restrict__ eval_acc,
     const int32_t* __restrict__ list, const int32_t* __restrict__ count, double rel, int vec_x, int vec_c,
     const int* __restrict__ job_of, const int* __restrict__ kbase, uint8_t* __restrict__ act_out,
-    int64_t* __restrict__ n_listed, const int32_t* __restrict__ cdirty, float* __restrict__ bnd_u,
-    float* __restrict__ bnd_lb, const float* __restrict__ delta, const uint16_t* __restrict__ Cb,
-    const float* __restrict__ ceps, int vec_b) {
+    int64_t* __restrict__ n_listed, const uint32_t* __restrict__ cbits, float* __restrict__ bnd_u,
+    float* __restrict__ bnd_lb, const float* __restrict__ delta, CShadow sw, int vec_b) {
   __shared__ PDWave sh[4];
   __shared__ unsigned int block_moved, block_eval;
   if (threadIdx.x == 0) {
@@ -561,8 +593,8 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
     }
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
-      const bool look = live[p] && !changed[p] && !dense[p] && cdirty && cv[p] >= 0;
-      dq[p] = look && cdirty[cv[p]] != 0;
+      const bool look = live[p] && !changed[p] && !dense[p] && cbits && cv[p] >= 0;
+      dq[p] = look && bit_of(cbits, cv[p]);
     }
     // the decisions, one sample after the other (one copy of the decision
     // code: the sample's values are selected, not indexed)
@@ -589,7 +621,7 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
       }
       bool skip = false;
       float lb_drift = 0.f;
-      if (!chg && !dn && cdirty) {
+      if (!chg && !dn && cbits) {
         // the same candidates as in the last sweep and none of their
         // centroids changed: the last decision, to stay, stands
         if (__ballot(dirt) == 0) {
@@ -625,7 +657,8 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
         }
       }
       // (a listed sample mostly stays: no pilot)
-      const PDResult r = pd_decide<GL, SH>(sh[w], X + i * ldx, d, vec_x, C, vec_c, Cb, ceps, vec_b, own, c, rel, skip,
+      const PDResult r = pd_decide<GL, SK, pd_chunk_list<SK>()>(sh[w], X + i * ldx, d, vec_x, C, vec_c, sw, vec_b,
+                                                                 own, c, rel, skip,
                                            false);
       if (bnd_u && lane <= kappa) {
         // skipped entries keep their drifted bounds (the chosen cluster is at
@@ -657,20 +690,26 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
 // order: a rounded difference squared (2) plus the products summed per lane
 // and the reduction levels; full distances 8 + 6, float32 chunks 8 + 3 plus up
 // to eight chunk additions, bfloat16 chunks 16 + 3 plus up to four: at most
-// 25, and the bound is twice that.
-static double pd_rel() { return (8.0 + 8.0 + 6.0 + 3.0) * 0x1p-23; }
+// 25; chunks of 8-bit codes 32 + 3 plus up to two (or 16 + 3 plus up to
+// four): 39.  The bound is twice that.
+static double pd_rel(int kind) { return (kind == 2 ? 39.0 : 25.0) * 0x1p-23; }
 
 bool ks_assign_pd_ok(int32_t d, int32_t kappa) { return d > 256 && d <= 512 && kappa <= 63; }
 
-// bfloat16 shadow of centroid rows (all, or those with dirty[r] set): one
-// wavefront per row; eps[r] = ||c_r - bf16(c_r)|| rounded up (every
-// difference is exact in float32, its square in float64).
+// Shadow of centroid rows (all, or those with dirty[r] set): one wavefront
+// per row.  bfloat16: eps[r] = ||c_r - bf16(c_r)|| rounded up (every
+// difference is exact in float32, its square in float64); 8-bit codes:
+// i8_shadow_row.
 __global__ __launch_bounds__(256) void k_c_shadow(const float* __restrict__ C, int32_t K, int d,
-                                                  const int32_t* __restrict__ dirty, uint16_t* __restrict__ Cb,
-                                                  float* __restrict__ eps) {
+                                                  const int32_t* __restrict__ dirty, CShadow sw) {
   const int lane = threadIdx.x & 63;
   for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < K; r += (int64_t)gridDim.x * 4) {
     if (dirty && !dirty[r]) continue;  // wave-uniform
+    if (sw.kind == 2) {
+      i8_shadow_row(C + r * d, d, (uint8_t*)sw.rows + r * d, &sw.scale[r], &sw.eps[r]);
+      continue;
+    }
+    uint16_t* Cb = (uint16_t*)sw.rows;
     double e2 = 0.0;
     for (int t = lane; t < d; t += 64) {
       const float c = C[r * d + t];
@@ -680,15 +719,14 @@ __global__ __launch_bounds__(256) void k_c_shadow(const float* __restrict__ C, i
       e2 = fma(df, df, e2);
     }
     e2 = wave_sum(e2);
-    if (lane == 0) eps[r] = f32_round_up(sqrt(e2) * (1.0 + 0x1p-40));
+    if (lane == 0) sw.eps[r] = f32_round_up(sqrt(e2) * (1.0 + 0x1p-40));
   }
 }
 
-knnkm_status ks_c_shadow(knnkm_ctx* ctx, const float* C, int32_t K, int32_t d, const int32_t* dirty, uint16_t* Cb,
-                         float* eps) {
-  if (K <= 0) return KNNKM_OK;
-  k_c_shadow<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(C, K, d, dirty, Cb, eps);
-  return knnkm_check(ctx, "bfloat16 centroid shadow");
+knnkm_status ks_c_shadow(knnkm_ctx* ctx, const float* C, int32_t K, int32_t d, const int32_t* dirty, CShadow sw) {
+  if (K <= 0 || sw.kind == 0) return KNNKM_OK;
+  k_c_shadow<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(C, K, d, dirty, sw);
+  return knnkm_check(ctx, "centroid shadow");
 }
 
 knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, const float* C,
@@ -696,48 +734,53 @@ knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, 
                           int32_t* labels_out, unsigned long long* acc, unsigned long long* eacc,
                           const int32_t* order, const int32_t* job_of, const int32_t* kbase,
                           const uint8_t* act_in, uint8_t* act_out, const int32_t* list, const int32_t* list_count,
-                          int64_t* n_listed, const int32_t* cdirty, int pb, float* bnd_u, float* bnd_lb,
-                          const float* delta, const uint16_t* Cb, const float* ceps) {
-  if ((bnd_u != nullptr) != (bnd_lb != nullptr) || (list && bnd_u && cdirty && !delta))
+                          int64_t* n_listed, const uint32_t* cbits, int pb, float* bnd_u, float* bnd_lb,
+                          const float* delta, CShadow sw) {
+  if ((bnd_u != nullptr) != (bnd_lb != nullptr) || (list && bnd_u && cbits && !delta))
     return knnkm_fail(ctx, KNNKM_EINVAL, "knn_assign (wide rows): incomplete drift bounds");
-  if ((Cb != nullptr) != (ceps != nullptr))
-    return knnkm_fail(ctx, KNNKM_EINVAL, "knn_assign (wide rows): bfloat16 shadow without its bounds");
+  if (sw.kind < 0 || sw.kind > 2 || (sw.kind && (!sw.rows || !sw.eps || (sw.kind == 2 && !sw.scale))))
+    return knnkm_fail(ctx, KNNKM_EINVAL, "knn_assign (wide rows): incomplete centroid shadow");
   const bool vec_x = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0) && (d % 4 == 0);
   const bool vec_c = (d % 4 == 0) && ((uintptr_t)C % 16 == 0);
-  const bool vec_b = (d % 8 == 0) && ((uintptr_t)Cb % 16 == 0);
-  const double rel = pd_rel();
+  // 16-byte shadow loads: rows of whole 16-byte units from an aligned base
+  const bool vec_b = (d % (sw.kind == 2 ? 16 : 8) == 0) && ((uintptr_t)sw.rows % 16 == 0);
+  const double rel = pd_rel(sw.kind);
   if (list) {
     const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
     // listed samples interleaved per wavefront: 2 unless the context fixes
     // the assignment shape to one sample per group
-#define LPD(NS, SH)                                                                                           \
-  k_assign_list_pd<8, NS, SH><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
+#define LPD(NS, SK)                                                                                           \
+  k_assign_list_pd<8, NS, SK><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
                                                         acc, eacc, list, list_count, rel, vec_x ? 1 : 0,      \
                                                         vec_c ? 1 : 0, job_of, kbase, act_out, n_listed,      \
-                                                        cdirty, bnd_u, bnd_lb, delta, Cb, ceps, vec_b ? 1 : 0)
+                                                        cbits, bnd_u, bnd_lb, delta, sw, vec_b ? 1 : 0)
+#define LPD_K(NS)            \
+  switch (sw.kind) {         \
+    case 1: LPD(NS, 1); break; \
+    case 2: LPD(NS, 2); break; \
+    default: LPD(NS, 0); break; \
+  }
     if (ctx->assign_gs == 1) {
-      if (Cb)
-        LPD(1, true);
-      else
-        LPD(1, false);
+      LPD_K(1);
     } else {
-      if (Cb)
-        LPD(2, true);
-      else
-        LPD(2, false);
+      LPD_K(2);
     }
+#undef LPD_K
 #undef LPD
     return knnkm_check(ctx, "knn_assign (wide rows, active set)");
   }
   const int nchunks = (int)((n + pb - 1) / pb);
   const int grid = ((nchunks + 7) / 8) * 8;
-if (Cb)
-      k_assign_pd<8, true><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc,
-                                                eacc, order, nchunks, pb, rel, vec_x ? 1 : 0, vec_c ? 1 : 0, job_of,
-                                                kbase, act_in, act_out, bnd_u, bnd_lb, Cb, ceps, vec_b ? 1 : 0);
-  else
-      k_assign_pd<8, false><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc,
-                                                eacc, order, nchunks, pb, rel, vec_x ? 1 : 0, vec_c ? 1 : 0, job_of,
-                                                kbase, act_in, act_out, bnd_u, bnd_lb, Cb, ceps, vec_b ? 1 : 0);
+#define FPD(SK)                                                                                                    \
+  k_assign_pd<8, SK><<<grid, 256, 0, ctx->stream>>>(X, (int)n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
+                                                    acc, eacc, order, nchunks, pb, rel, vec_x ? 1 : 0,           \
+                                                    vec_c ? 1 : 0, job_of, kbase, act_in, act_out, bnd_u, bnd_lb, \
+                                                    sw, vec_b ? 1 : 0)
+  switch (sw.kind) {
+    case 1: FPD(1); break;
+    case 2: FPD(2); break;
+    default: FPD(0); break;
+  }
+#undef FPD
   return knnkm_check(ctx, "knn_assign (wide rows)");
 }

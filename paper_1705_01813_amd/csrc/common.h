@@ -44,7 +44,9 @@ struct knnkm_ctx {
   bool autotune = true;
   bool active_sets = true;  // fit sweeps look only at samples that can change
   bool wide_pd = true;      // wide rows: early-abandoned partial distances in the assignment
-  bool pd_shadow = true;    // ... reading a bfloat16 shadow of the centroids in the build and fit sweeps
+  // ... reading a shadow of the centroids in the build and fit sweeps (the
+  // CShadow kinds: 0 none, the float32 rows; 1 bfloat16; 2 8-bit codes)
+  int pd_shadow = 2;
   int tm_finish_max = 1024;  // two-means subtrees up to this size finished by one block (0: off)
   int assign_gs = 0, assign_pb = 64, assign_lazy = 0;  // forced assignment shape (gs = 0: automatic)
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
@@ -135,12 +137,12 @@ __device__ inline float f32_round_up(double v) {
   if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);
   return f;
 }
-// float32 not above a non-negative double (0 for v <= 0)
 // float32 -> bfloat16 bit pattern, round to nearest even (finite values)
 __device__ inline uint16_t bf16_rne(float f) {
   const uint32_t u = __float_as_uint(f);
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
+// float32 not above a non-negative double (0 for v <= 0)
 __device__ inline float f32_round_down(double v) {
   if (v <= 0.0) return 0.f;
   float f = (float)v;
@@ -148,6 +150,8 @@ __device__ inline float f32_round_down(double v) {
   return f;
 }
 __device__ inline int lane_id() { return threadIdx.x & (WAVE - 1); }
+// flag r of a bit array (one bit per cluster)
+__device__ inline bool bit_of(const uint32_t* __restrict__ bits, int r) { return (bits[r >> 5] >> (r & 31)) & 1u; }
 __device__ inline uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
 
 // Order-preserving map of a double to uint64 (+0 and -0 map to the same key).
@@ -188,6 +192,43 @@ inline int grid_for(int64_t work, int per_block, int cap) {
   return (int)g;
 }
 
+// Low-precision copy of the centroid rows read by the early-abandon steps of
+// the wide-row assignment; row r decodes to within eps[r] (Euclidean) of the
+// float32 centroid.  kind 1: bfloat16 values (2 bytes per element); kind 2:
+// 8-bit codes u standing for scale[r] * (u - 128) (1 byte per element).
+struct CShadow {
+  void* rows = nullptr;
+  float* eps = nullptr;
+  float* scale = nullptr;  // kind 2
+  int kind = 0;            // 0: none
+};
+
+// 8-bit shadow of one centroid row by a whole wavefront: step s = (largest
+// magnitude) / 127, codes u = 128 + clamp(rint(c / s), -127, 127) (128 for a
+// zero row), and eps >= ||c - s (u - 128)|| (the products s (u - 128) are
+// exact in float64).
+__device__ inline void i8_shadow_row(const float* __restrict__ crow, int d, uint8_t* __restrict__ out,
+                                     float* __restrict__ step, float* __restrict__ eps) {
+  const int lane = threadIdx.x & 63;
+  float amax = 0.f;
+  for (int t = lane; t < d; t += 64) amax = fmaxf(amax, fabsf(crow[t]));
+  amax = wave_max(amax);
+  const float s = amax / 127.f;
+  double e2 = 0.0;
+  for (int t = lane; t < d; t += 64) {
+    const float c = crow[t];
+    const int q = s > 0.f ? (int)fminf(127.f, fmaxf(-127.f, rintf(c / s))) : 0;
+    out[t] = (uint8_t)(q + 128);
+    const double dq = (double)c - (double)s * (double)q;
+    e2 = fma(dq, dq, e2);
+  }
+  e2 = wave_sum(e2);
+  if (lane == 0) {
+    *step = s;
+    *eps = f32_round_up(sqrt(e2) * (1.0 + 0x1p-40));
+  }
+}
+
 // ------------------------------------------------- internal building blocks --
 // (defined in the .hip files; all enqueue on ctx->stream)
 
@@ -225,7 +266,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        int64_t* n_active = nullptr, int32_t* list_count = nullptr,
                        int32_t* list_count_other = nullptr, bool zero_moved = true,
                        const int32_t* cdirty = nullptr, float* bnd_u = nullptr, float* bnd_lb = nullptr,
-                       const float* cdelta = nullptr, const uint16_t* Cb = nullptr, const float* ceps = nullptr);
+                       const float* cdelta = nullptr, CShadow sw = {});
 // Exact all-pairs refinement of the clusters with smin < s <= smax members
 // (smax <= 128; one block per cluster, rows of the graph updated in place).
 knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, int32_t kappa, int32_t k,
@@ -235,20 +276,19 @@ knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
 // early-abandoned partial distances.  list != null: the active-set sweep over
 // the listed positions (list_count entries); else a full sweep in `order`
 // (pb positions per block).  Same decisions and flags as the narrow kernels.
-// Cb/ceps (nullable together): bfloat16 shadow of C and its row bounds
-// (ks_c_shadow), read for the early-abandon steps.
+// sw: the shadow of C (ks_c_shadow) read for the early-abandon steps, or
+// kind 0 (the float32 rows).
 bool ks_assign_pd_ok(int32_t d, int32_t kappa);
-// bfloat16 shadow Cb (K x d) of the centroid rows of C, all or those with
-// dirty[r] set, and eps[r] >= ||c_r - bf16(c_r)||.
-knnkm_status ks_c_shadow(knnkm_ctx* ctx, const float* C, int32_t K, int32_t d, const int32_t* dirty, uint16_t* Cb,
-                         float* eps);
+// Shadow (kind 1 or 2) of the centroid rows of C, all or those with dirty[r]
+// set, with its row bounds.
+knnkm_status ks_c_shadow(knnkm_ctx* ctx, const float* C, int32_t K, int32_t d, const int32_t* dirty, CShadow sw);
 knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, const float* C,
                           int32_t k, const int32_t* G_ids, int32_t kappa, const int32_t* labels_in,
                           int32_t* labels_out, unsigned long long* acc, unsigned long long* eacc,
                           const int32_t* order, const int32_t* job_of, const int32_t* kbase,
                           const uint8_t* act_in, uint8_t* act_out, const int32_t* list, const int32_t* list_count,
-                          int64_t* n_listed, const int32_t* cdirty, int pb, float* bnd_u, float* bnd_lb,
-                          const float* delta, const uint16_t* Cb = nullptr, const float* ceps = nullptr);
+                          int64_t* n_listed, const uint32_t* cbits, int pb, float* bnd_u, float* bnd_lb,
+                          const float* delta, CShadow sw = {});
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
                          int32_t* labels);
@@ -288,8 +328,7 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off,
                           const int32_t* rev_src, uint8_t* act_out, int32_t* dirty_clear,
-                          float* delta, int64_t* mass = nullptr, uint16_t* Cb = nullptr,
-                          float* ceps = nullptr, double* C64 = nullptr);
+                          float* delta, int64_t* mass = nullptr, CShadow sw = {}, double* C64 = nullptr);
 // Exact fixed-point D of every cluster from its members (CSR), and the
 // centroids, float64 means and Eqn. 2 terms of every cluster from D.
 knnkm_status ks_fx_exact_sums(knnkm_ctx* ctx, const float* X, int64_t ldx, int32_t d, int32_t K, const int32_t* off,

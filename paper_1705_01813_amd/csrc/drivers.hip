@@ -254,6 +254,30 @@ static knnkm_status upload_koff(knnkm_ctx* ctx, const std::vector<int32_t>& kq, 
   return KNNKM_OK;
 }
 
+// The centroid shadow of the context's kind (none: kind 0) for K rows of d
+// dimensions, in the workspace under names starting with `tag`.
+static knnkm_status shadow_alloc(knnkm_ctx* ctx, const char* tag, int32_t K, int32_t d, CShadow* sw) {
+  *sw = CShadow{};
+  if (ctx->pd_shadow == 0) return KNNKM_OK;
+  const size_t per = ctx->pd_shadow == 2 ? 1 : 2;  // bytes per element
+  char name[40];
+  snprintf(name, sizeof(name), "%s_cshadow", tag);
+  void* rows = knnkm_ws(ctx, name, per * (size_t)K * d);
+  snprintf(name, sizeof(name), "%s_ceps", tag);
+  float* eps = (float*)knnkm_ws(ctx, name, sizeof(float) * (size_t)K);
+  float* scale = nullptr;
+  if (ctx->pd_shadow == 2) {
+    snprintf(name, sizeof(name), "%s_cscale", tag);
+    scale = (float*)knnkm_ws(ctx, name, sizeof(float) * (size_t)K);
+  }
+  if (!rows || !eps || (ctx->pd_shadow == 2 && !scale)) return KNNKM_ENOMEM;
+  sw->rows = rows;
+  sw->eps = eps;
+  sw->scale = scale;
+  sw->kind = ctx->pd_shadow;
+  return KNNKM_OK;
+}
+
 // Alg. 3 for every job of J.
 static knnkm_status build_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, Jobs& J,
                                const knnkm_params* p, int32_t* G_ids, float* G_d2) {
@@ -286,24 +310,20 @@ static knnkm_status build_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
     KNNKM_WS(ctx, mem, int32_t, "kb_members", n);
     KNNKM_WS(ctx, C, float, "kb_centroids", (int64_t)K0 * d);
     KNNKM_WS(ctx, nrm, float, "kb_norms", n);
-    // wide rows: the bfloat16 shadow the assignment's early-abandon steps read
-    uint16_t* Cb = nullptr;
-    float* ceps = nullptr;
-    if (ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense && ctx->pd_shadow) {
-      Cb = (uint16_t*)knnkm_ws(ctx, "kb_cshadow", sizeof(uint16_t) * (size_t)K0 * d);
-      ceps = (float*)knnkm_ws(ctx, "kb_ceps", sizeof(float) * (size_t)K0);
-      if (!Cb || !ceps) return KNNKM_ENOMEM;
-    }
+    // wide rows: the centroid shadow the assignment's early-abandon steps read
+    CShadow sw;
+    if (ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense)
+      KNNKM_TRY(shadow_alloc(ctx, "kb", K0, d, &sw));
     KNNKM_TRY(ks_row_norms(ctx, X, n, d, ldx, nrm));
     for (int t = 0; t < p->tau; ++t) {
       KNNKM_TRY(ks_twomeans_multi(ctx, X, d, ldx, J.n_host, k0, J.m > 1 ? J.seeds : nullptr, J.seed_host[0], t,
                                   p->bisect_iters, lab));
       KNNKM_TRY(ks_label_sort(ctx, lab, n, K0, counts, off, mem));
       KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K0, counts, off, mem, C, nullptr, nullptr));
-      if (Cb) KNNKM_TRY(ks_c_shadow(ctx, C, K0, d, nullptr, Cb, ceps));
+      KNNKM_TRY(ks_c_shadow(ctx, C, K0, d, nullptr, sw));
       KNNKM_TRY(ks_assign(ctx, X, n, d, ldx, C, K0, G_ids, kappa, lab, lab2, nullptr, nullptr, mem,
                           J.m == 1 && all_dense, J.job_of, k0_32, KS_USE_BUILD, nullptr, nullptr, nullptr, nullptr,
-                          nullptr, nullptr, true, nullptr, nullptr, nullptr, nullptr, Cb, ceps));
+                          nullptr, nullptr, true, nullptr, nullptr, nullptr, nullptr, sw));
       KNNKM_TRY(ks_refine(ctx, X, n, d, ldx, lab2, K0, p->precision, G_ids, G_d2, kappa, nrm));
     }
   }
@@ -466,14 +486,11 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   // clusters that the triangle inequality still rules out need no distance.
   const bool drift = use_act && ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense;
   float *bnd_u = nullptr, *bnd_lb = nullptr, *cdelta = nullptr;
-  // and the bfloat16 shadow of the centroids read by the early-abandon steps
-  uint16_t* Cb = nullptr;
-  float* ceps = nullptr;
-  if (ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense && ctx->pd_shadow) {
-    Cb = (uint16_t*)knnkm_ws(ctx, "fit_cshadow", sizeof(uint16_t) * (size_t)K * d);
-    ceps = (float*)knnkm_ws(ctx, "fit_ceps", sizeof(float) * (size_t)K);
-    if (!Cb || !ceps) return KNNKM_ENOMEM;
-    KNNKM_TRY(ks_c_shadow(ctx, C, K, d, nullptr, Cb, ceps));
+  // and the shadow of the centroids read by the early-abandon steps
+  CShadow sw;
+  if (ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense) {
+    KNNKM_TRY(shadow_alloc(ctx, "fit", K, d, &sw));
+    KNNKM_TRY(ks_c_shadow(ctx, C, K, d, nullptr, sw));
   }
   if (drift) {
     bnd_u = (float*)knnkm_ws(ctx, "fit_bnd_u", sizeof(float) * (size_t)n);
@@ -493,7 +510,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
                      J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT, ev, first ? nullptr : act_for(cu),
                      drift ? nullptr : act_for(nx), ac, cnt_for(cu), cnt_for(nx), false, first ? nullptr : dirty_for(cu), bnd_u,
-                     bnd_lb, first ? nullptr : cdelta, Cb, ceps);
+                     bnd_lb, first ? nullptr : cdelta, sw);
   };
   // The first sweep moves a large share of the samples away from the
   // initial partition: its update rebuilds the sums from a label sort and
@@ -511,13 +528,13 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       // every centroid was recomputed
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(nx), K, 1));
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(cu), K, 0));
-      if (Cb) KNNKM_TRY(ks_c_shadow(ctx, C, K, d, nullptr, Cb, ceps));
+      KNNKM_TRY(ks_c_shadow(ctx, C, K, d, nullptr, sw));
       if (drift)
         KNNKM_TRY(ks_mark_dirty(ctx, n, nx, dirty_for(nx), rev_off, rev_src, act_for(nx), nullptr, 0, J.job_of, k32,
                                 kappa));
     } else {
       KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty_for(nx), C, Iterm, rev_off, rev_src,
-                             act_for(nx), dirty_for(cu), cdelta, drift ? dmass : nullptr, Cb, ceps));
+                             act_for(nx), dirty_for(cu), cdelta, drift ? dmass : nullptr, sw));
       // scattered marks while the dirty clusters' members and the rows
       // listing them stay below about 2n; every sample beyond that
       if (drift)
@@ -852,7 +869,7 @@ static knnkm_status boost_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
     KNNKM_TRY(ks_boost_select(ctx, n, labels, prop, K, p->seed, t, win, nxt, nprop + t));
     // the applied moves into D (exact), sizes, centroids, means, Eqn. 2 terms
     KNNKM_TRY(ks_fx_update(ctx, Xc, n, d, labels, nxt, cs, Dfx, K, counts, dset, C, Iterm, nullptr, nullptr,
-                           nullptr, dclear, nullptr, dmass, nullptr, nullptr, C64));
+                           nullptr, dclear, nullptr, dmass, CShadow{}, C64));
     KNNKM_HIP(ctx, hipMemcpyAsync(labels, nxt, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
     KNNKM_TRY(ks_mark_dirty(ctx, n, labels, dset, rev_off, rev_src, act, dmass, 2 * n / (kappa + 1), nullptr, nullptr,
                             kappa));

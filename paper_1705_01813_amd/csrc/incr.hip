@@ -352,17 +352,18 @@ __global__ void k_rev_fill(const int32_t* __restrict__ G, int64_t ne, int64_t n,
 // for the next sweep's assignment): centroid (unchanged when empty) and the
 // Eqn. 2 term; one wavefront per cluster.  dirty_clear, the previous
 // sweep's flags, is cleared on the way; mass (nullable, cleared before)
-// receives the number of members of all dirty clusters; Cb/ceps (nullable)
-// the bfloat16 shadow of each new centroid and its bound; C64 (nullable) the
-// float64 mean D_r / n_r.  dirty null: every cluster.
+// receives the number of members of all dirty clusters; sw (kind 0: none)
+// the shadow of each new centroid and its bound; C64 (nullable) the float64
+// mean D_r / n_r.  dirty null: every cluster.
 __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict__ D, int32_t K, int d,
                                                      const int32_t* __restrict__ cs,
                                                      const int32_t* __restrict__ counts,
                                                      const int32_t* __restrict__ dirty,
                                                      int32_t* __restrict__ dirty_clear, float* __restrict__ C,
                                                      double* __restrict__ Iterm, float* __restrict__ delta,
-                                                     unsigned long long* __restrict__ mass, uint16_t* __restrict__ Cb,
-                                                     float* __restrict__ ceps, double* __restrict__ C64) {
+                                                     unsigned long long* __restrict__ mass, CShadow sw,
+                                                     double* __restrict__ C64) {
+  uint16_t* __restrict__ Cb = sw.kind == 1 ? (uint16_t*)sw.rows : nullptr;
   const int lane = threadIdx.x & 63;
   for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < K; r += (int64_t)gridDim.x * 4) {
     if (dirty_clear && lane == 0) dirty_clear[r] = 0;
@@ -394,8 +395,10 @@ __global__ __launch_bounds__(256) void k_fx_finalize(const uint64_t* __restrict_
     sq = wave_sum(sq);
     if (Cb && cnt > 0) {
       e2 = wave_sum(e2);
-      if (lane == 0) ceps[r] = f32_round_up(sqrt(e2) * (1.0 + 0x1p-40));
+      if (lane == 0) sw.eps[r] = f32_round_up(sqrt(e2) * (1.0 + 0x1p-40));
     }
+    // (the lanes read back the elements of the row they wrote)
+    if (sw.kind == 2 && cnt > 0) i8_shadow_row(C + r * d, d, (uint8_t*)sw.rows + r * d, &sw.scale[r], &sw.eps[r]);
     if (lane == 0) Iterm[r] = cnt > 0 ? sq / (double)cnt : 0.0;
     if (delta) {
       mv = wave_sum(mv);
@@ -449,8 +452,8 @@ knnkm_status ks_fx_from_f64(knnkm_ctx* ctx, const double* sums, int32_t K, int32
 knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d, int32_t* cur,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off, const int32_t* rev_src,
-                          uint8_t* act_out, int32_t* dirty_clear, float* delta, int64_t* mass, uint16_t* Cb,
-                          float* ceps, double* C64) {
+                          uint8_t* act_out, int32_t* dirty_clear, float* delta, int64_t* mass, CShadow sw,
+                          double* C64) {
   if (mass) KNNKM_TRY(ks_fill_i64(ctx, mass, 1, 0));
 #define MV(DD)                                                                                           \
   k_fx_moves<DD><<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty, \
@@ -465,7 +468,7 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
     MV(8);
 #undef MV
   k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, dirty, dirty_clear, C, Iterm,
-                                                                delta, (unsigned long long*)mass, Cb, ceps, C64);
+                                                                delta, (unsigned long long*)mass, sw, C64);
   return knnkm_check(ctx, "incremental update");
 }
 
@@ -508,7 +511,7 @@ knnkm_status ks_fx_exact_sums(knnkm_ctx* ctx, const float* X, int64_t ldx, int32
 knnkm_status ks_fx_finalize_all(knnkm_ctx* ctx, const uint64_t* D, int32_t K, int32_t d, const int32_t* cs,
                                 const int32_t* counts, float* C, double* Iterm, double* C64) {
   k_fx_finalize<<<grid_for(K, 4, 16384), 256, 0, ctx->stream>>>(D, K, d, cs, counts, nullptr, nullptr, C, Iterm,
-                                                                nullptr, nullptr, nullptr, nullptr, C64);
+                                                                nullptr, nullptr, CShadow{}, C64);
   return knnkm_check(ctx, "centroids from fixed-point sums");
 }
 

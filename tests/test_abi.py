@@ -163,3 +163,11 @@ def test_graph_search_validation(dry):
                dict(n_entry=0), dict(kappa=0), dict(ldx=7), dict(n=0), dict(m=-1)]:
         assert call(**kw) == knnkm.EINVAL, kw
     assert call(d=513) == knnkm.EUNSUPPORTED
+
+
+def test_partial_distances_modes(dry):
+    for on in (0, 1, 2, 3):
+        assert _call("knnkm_enable_partial_distances", dry.handle, on) == knnkm.OK, on
+    for on in (-1, 4):
+        assert _call("knnkm_enable_partial_distances", dry.handle, on) == knnkm.EINVAL, on
+    assert _call("knnkm_enable_partial_distances", dry.handle, 1) == knnkm.OK

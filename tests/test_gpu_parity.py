@@ -1291,8 +1291,8 @@ def test_assign_wide_near_ties(ctx):
 def test_fit_wide_partial_distances_same_bits(ctx, d):
     """A fit on wide rows (the library's graph, active sets on) gives the same
     labels, centroids, counts and trace with the partial-distance kernels on
-    (reading the bfloat16 centroid shadow, or float32 centroids only) and
-    off, and the oracle's labels and trace."""
+    (reading the 8-bit or the bfloat16 centroid shadow, or float32 centroids
+    only) and off, and the oracle's labels and trace."""
     n, k, kappa, T = 6000, 300, 50, 8
     say("fit wide", d)
     X = datagen.mixture(n, d, 500, seed=d, sigma=0.5, centre="normal")
@@ -1303,7 +1303,7 @@ def test_fit_wide_partial_distances_same_bits(ctx, d):
     knnkm.knn_build(ctx, Xd, p, gi, gd)
     res = {}
     try:
-        for pd in (1, 2, 0):
+        for pd in (1, 3, 2, 0):
             knnkm.knnkm_enable_partial_distances(ctx, pd)
             lab = torch.empty(n, dtype=torch.int32, device=DEV)
             C = torch.empty((k, d), dtype=torch.float32, device=DEV)
@@ -1312,7 +1312,7 @@ def test_fit_wide_partial_distances_same_bits(ctx, d):
             res[pd] = (host(lab), host(C), host(cnt), tr)
     finally:
         knnkm.knnkm_enable_partial_distances(ctx, True)
-    for mode in (2, 0):
+    for mode in (3, 2, 0):
         for a, b in zip(res[1], res[mode]):
             assert np.array_equal(a, b), mode
     w_lab, _, _, w_tr, _, _ = gkmeans.fit(X, k, host(gi), T, seed=4)
@@ -1323,8 +1323,9 @@ def test_fit_wide_partial_distances_same_bits(ctx, d):
 def test_batch_wide_rows_with_small_jobs(ctx):
     """A batch of wide-row jobs, some with fewer clusters than kappa (every
     cluster of the job is a candidate): graph and fit equal those with the
-    partial-distance kernels reading float32 centroids only or switched off,
-    and the oracle's."""
+    partial-distance kernels reading the 8-bit shadow (d = 300: partial
+    16-byte units and a partial last chunk), the bfloat16 one or float32
+    centroids only, or switched off, and the oracle's."""
     sizes = [120, 900, 64, 1500]
     d, kappa, T = 300, 16, 5
     say("batch wide rows", sizes)
@@ -1348,11 +1349,11 @@ def test_batch_wide_rows_with_small_jobs(ctx):
         return [host(t) for t in out] + [tr]
 
     try:
-        a, b, c = run(1), run(0), run(2)
+        a, b, c, e = run(1), run(0), run(2), run(3)
     finally:
         knnkm.knnkm_enable_partial_distances(ctx, True)
-    for u, v, w in zip(a, b, c):
-        assert np.array_equal(u, v) and np.array_equal(u, w)
+    for u, v, w, z in zip(a, b, c, e):
+        assert np.array_equal(u, v) and np.array_equal(u, w) and np.array_equal(u, z)
     k_off = np.concatenate([[0], np.cumsum(ks)])
     for q, Xq in enumerate(Xs):
         w_i, _ = knng.knn_build(Xq, kappa, xi=50, tau=2, seed=seeds[q])
