@@ -777,7 +777,8 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        int64_t* n_moved, const int32_t* order, bool dense, const int32_t* job_of,
                        const int32_t* kbase, int use, int64_t* n_eval, const uint8_t* act_in, uint8_t* act_out,
                        int64_t* n_active, int32_t* list_count, int32_t* list_count_other, bool zero_moved,
-                       const int32_t* cdirty, float* bnd_u, float* bnd_lb, const float* cdelta, CShadow sw) {
+                       const int32_t* cdirty, float* bnd_u, float* bnd_lb, const float* cdelta, CShadow sw,
+                       const int32_t* nlab) {
   if (n_moved && zero_moved) KNNKM_TRY(ks_fill_i64(ctx, n_moved, 1, 0));
   if (n_eval) KNNKM_TRY(ks_fill_i64(ctx, n_eval, 1, 0));
   if (n_active && !(act_in && !best_d2 && !order && !dense)) KNNKM_TRY(ks_fill_i64(ctx, n_active, 1, n));
@@ -823,7 +824,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
     }
     if (wide)
       return ks_assign_pd(ctx, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc, eacc, nullptr, job_of,
-                          kbase, nullptr, act_out, list, cnt, n_active, cbits, 0, bnd_u, bnd_lb, cdelta, sw);
+                          kbase, nullptr, act_out, list, cnt, n_active, cbits, 0, bnd_u, bnd_lb, cdelta, sw, nlab);
     const unsigned grid = (unsigned)std::max(1, ctx->num_cus * 8);
 #define LP(LL, VV, SS)                                                                                        \
   k_assign_list<LL, VV, SS, ((LL) >= 64 ? 2 : 1)><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \

@@ -53,7 +53,10 @@ constexpr int pd_chunk_full() { return SK == 2 ? 256 : (SK ? 128 : 64); }
 template <int SK>
 constexpr int pd_chunk_list() { return SK ? 128 : 64; }
 
-constexpr int PD_SB = 4;      // candidate batches whose loads are in flight together
+// candidate batches whose loads are in flight together: full sweeps 4 (more
+// would cost a wavefront per SIMD), active-set sweeps 6
+constexpr int PD_SB_FULL = 4;
+constexpr int PD_SB_LIST = 6;
 constexpr int PD_EX = 4;      // full float32 rows in flight together
 
 struct alignas(16) PDWave {
@@ -156,7 +159,7 @@ __device__ __attribute__((always_inline)) inline void pd_exact(PDWave& sh, int n
 // the label and the bounds of PDResult: every candidate's squared distance
 // is bracketed by rigorous bounds (a dropped one from below by its partial
 // sum), so they hold for the exact distances.
-template <int GL, int SK, int CHK>
+template <int GL, int SK, int CHK, int PD_SB>
 __device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, const float* __restrict__ xrow,
                                                                     int d, bool vec_x, const float* __restrict__ C,
                                                                     bool vec_c, CShadow sw, bool vec_b, int cur,
@@ -502,9 +505,8 @@ __global__ __launch_bounds__(256) void k_assign_pd(
         }
         continue;
       }
-      const PDResult r = pd_decide<GL, SK, pd_chunk_full<SK>()>(sh[w], X + i * ldx, d, vec_x, C, vec_c, sw, vec_b,
-                                                                 cur, cv, rel, false,
-                                           true);
+      const PDResult r = pd_decide<GL, SK, pd_chunk_full<SK>(), PD_SB_FULL>(sh[w], X + i * ldx, d, vec_x, C, vec_c,
+                                                                             sw, vec_b, cur, cv, rel, false, true);
       if (bnd_u && lane <= kappa) bnd_lb[i * (kappa + 1) + lane] = r.lb;
       if (lane == 0) {
         lab_out[i] = r.label;
@@ -529,8 +531,10 @@ __global__ __launch_bounds__(256) void k_assign_pd(
 // NS listed samples per wavefront and step: the loads of each dependent level
 // (list entries; own labels and graph rows; neighbour labels; changed flags
 // of the candidate clusters) are issued for all NS samples before any is
-// used, then the samples are decided one after the other.  Same outputs as
-// k_assign_list.
+// used, then the samples are decided one after the other.  nlab (nullable):
+// the labels of the graph entries (row-major, n x kappa, equal to lab_in of
+// the entries' ids), read in place of the graph row and the scattered
+// neighbour labels.  Same outputs as k_assign_list.
 template <int GL, int NS, int SK>
 __global__ __launch_bounds__(256) void k_assign_list_pd(
     const float* __restrict__ X, int d, int64_t ldx, const float* __restrict__ C, int k,
@@ -539,7 +543,8 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
     const int32_t* __restrict__ list, const int32_t* __restrict__ count, double rel, int vec_x, int vec_c,
     const int* __restrict__ job_of, const int* __restrict__ kbase, uint8_t* __restrict__ act_out,
     int64_t* __restrict__ n_listed, const uint32_t* __restrict__ cbits, float* __restrict__ bnd_u,
-    float* __restrict__ bnd_lb, const float* __restrict__ delta, CShadow sw, int vec_b) {
+    float* __restrict__ bnd_lb, const float* __restrict__ delta, CShadow sw, int vec_b,
+    const int32_t* __restrict__ nlab) {
   __shared__ PDWave sh[4];
   __shared__ unsigned int block_moved, block_eval;
   if (threadIdx.x == 0) {
@@ -575,7 +580,9 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
         kb[p] = kbase[q];
         kc[p] = kbase[q + 1] - kb[p];
       }
-      nb[p] = (live[p] && lane >= 1 && lane <= kappa) ? G[i * kappa + (lane - 1)] : -1;
+      // (with the graph-entry labels nb holds the entry's label, not its id)
+      const bool ent = live[p] && lane >= 1 && lane <= kappa;
+      nb[p] = !ent ? -1 : (nlab ? nlab[i * kappa + (lane - 1)] : G[i * kappa + (lane - 1)]);
     }
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
@@ -588,7 +595,7 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
         const int v = kb[p] + lane - 1;
         cv[p] = lane >= kc[p] ? -1 : (v < cur[p] ? v : v + 1);
       } else {
-        cv[p] = nb[p] >= 0 ? lab_in[nb[p]] : -1;
+        cv[p] = nlab ? nb[p] : (nb[p] >= 0 ? lab_in[nb[p]] : -1);
       }
     }
 #pragma unroll
@@ -657,9 +664,8 @@ __global__ __launch_bounds__(256) void k_assign_list_pd(
         }
       }
       // (a listed sample mostly stays: no pilot)
-      const PDResult r = pd_decide<GL, SK, pd_chunk_list<SK>()>(sh[w], X + i * ldx, d, vec_x, C, vec_c, sw, vec_b,
-                                                                 own, c, rel, skip,
-                                           false);
+      const PDResult r = pd_decide<GL, SK, pd_chunk_list<SK>(), PD_SB_LIST>(sh[w], X + i * ldx, d, vec_x, C, vec_c,
+                                                                             sw, vec_b, own, c, rel, skip, false);
       if (bnd_u && lane <= kappa) {
         // skipped entries keep their drifted bounds (the chosen cluster is at
         // least as close as the own one, so they remain valid lower bounds)
@@ -735,7 +741,7 @@ knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, 
                           const int32_t* order, const int32_t* job_of, const int32_t* kbase,
                           const uint8_t* act_in, uint8_t* act_out, const int32_t* list, const int32_t* list_count,
                           int64_t* n_listed, const uint32_t* cbits, int pb, float* bnd_u, float* bnd_lb,
-                          const float* delta, CShadow sw) {
+                          const float* delta, CShadow sw, const int32_t* nlab) {
   if ((bnd_u != nullptr) != (bnd_lb != nullptr) || (list && bnd_u && cbits && !delta))
     return knnkm_fail(ctx, KNNKM_EINVAL, "knn_assign (wide rows): incomplete drift bounds");
   if (sw.kind < 0 || sw.kind > 2 || (sw.kind && (!sw.rows || !sw.eps || (sw.kind == 2 && !sw.scale))))
@@ -753,7 +759,7 @@ knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, 
   k_assign_list_pd<8, NS, SK><<<grid, 256, 0, ctx->stream>>>(X, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, \
                                                         acc, eacc, list, list_count, rel, vec_x ? 1 : 0,      \
                                                         vec_c ? 1 : 0, job_of, kbase, act_out, n_listed,      \
-                                                        cbits, bnd_u, bnd_lb, delta, sw, vec_b ? 1 : 0)
+                                                        cbits, bnd_u, bnd_lb, delta, sw, vec_b ? 1 : 0, nlab)
 #define LPD_K(NS)            \
   switch (sw.kind) {         \
     case 1: LPD(NS, 1); break; \

@@ -266,7 +266,7 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        int64_t* n_active = nullptr, int32_t* list_count = nullptr,
                        int32_t* list_count_other = nullptr, bool zero_moved = true,
                        const int32_t* cdirty = nullptr, float* bnd_u = nullptr, float* bnd_lb = nullptr,
-                       const float* cdelta = nullptr, CShadow sw = {});
+                       const float* cdelta = nullptr, CShadow sw = {}, const int32_t* nlab = nullptr);
 // Exact all-pairs refinement of the clusters with smin < s <= smax members
 // (smax <= 128; one block per cluster, rows of the graph updated in place).
 knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, int32_t kappa, int32_t k,
@@ -288,7 +288,7 @@ knnkm_status ks_assign_pd(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, 
                           const int32_t* order, const int32_t* job_of, const int32_t* kbase,
                           const uint8_t* act_in, uint8_t* act_out, const int32_t* list, const int32_t* list_count,
                           int64_t* n_listed, const uint32_t* cbits, int pb, float* bnd_u, float* bnd_lb,
-                          const float* delta, CShadow sw = {});
+                          const float* delta, CShadow sw = {}, const int32_t* nlab = nullptr);
 knnkm_status ks_twomeans(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k, uint64_t seed, int32_t round_tag, int32_t iters,
                          int32_t* labels);
@@ -328,7 +328,8 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off,
                           const int32_t* rev_src, uint8_t* act_out, int32_t* dirty_clear,
-                          float* delta, int64_t* mass = nullptr, CShadow sw = {}, double* C64 = nullptr);
+                          float* delta, int64_t* mass = nullptr, CShadow sw = {}, double* C64 = nullptr,
+                          int32_t* nlab = nullptr, const uint8_t* rev_pos = nullptr, int32_t kappa = 0);
 // Exact fixed-point D of every cluster from its members (CSR), and the
 // centroids, float64 means and Eqn. 2 terms of every cluster from D.
 knnkm_status ks_fx_exact_sums(knnkm_ctx* ctx, const float* X, int64_t ldx, int32_t d, int32_t K, const int32_t* off,
@@ -358,7 +359,11 @@ knnkm_status ks_mark_dirty(knnkm_ctx* ctx, int64_t n, const int32_t* lab, const 
                            const int32_t* rev_off, const int32_t* rev_src, uint8_t* act_out, const int64_t* mass,
                            int64_t all_at, const int32_t* job_of, const int32_t* kbase, int32_t kappa);
 // Reverse lists of an n x kappa graph: rev_off (n + 1), rev_src (n * kappa).
+// rev_pos (nullable): the position of each reverse-list entry in its row.
 knnkm_status ks_reverse_graph(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, int32_t* rev_off,
-                              int32_t* rev_src);
+                              int32_t* rev_src, uint8_t* rev_pos = nullptr);
+// Labels of the graph entries: nlab[e] = lab[G[e]] (-1 past [0, n)).
+knnkm_status ks_entry_labels(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, const int32_t* lab,
+                             int32_t* nlab);
 knnkm_status ks_fill_i64(knnkm_ctx* ctx, int64_t* p, int64_t count, int64_t v);
 knnkm_status ks_fill_i32(knnkm_ctx* ctx, int32_t* p, int64_t count, int32_t v);

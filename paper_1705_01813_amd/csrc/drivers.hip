@@ -153,13 +153,42 @@ __global__ __launch_bounds__(1024) void k_range_sum(const double* __restrict__ v
 }
 
 // E of every job = (sum ||x||^2 - sum of the Eqn. 2 terms) / n_q (Eqn. 4
-// through the Eqn. 2 identity), the terms summed as in k_range_sum
-__global__ __launch_bounds__(1024) void k_range_trace(const double* __restrict__ Iterm, const int64_t* __restrict__ k_off,
-                                                      const double* __restrict__ sxx,
-                                                      const int64_t* __restrict__ n_off, double* __restrict__ dst) {
-  const int q = blockIdx.x;
-  const double s = block_range_sum(Iterm, k_off[q], k_off[q + 1]);
-  if (threadIdx.x == 0) dst[q] = (sxx[q] - s) / (double)(n_off[q + 1] - n_off[q]);
+// through the Eqn. 2 identity).  The terms of job q are summed in S_q slices
+// of its cluster range (S_q = TR_SLICES from TR_BIG clusters on, else 1; it
+// depends on the job's own size, so a job's value is the same alone and in
+// a batch): block (s, q) sums slice s as in k_range_sum, then k_range_trace
+// adds the slices in order.
+constexpr int TR_SLICES = 64;
+constexpr int64_t TR_BIG = 65536;
+__device__ inline int tr_slices(int64_t len) { return len >= TR_BIG ? TR_SLICES : 1; }
+__global__ __launch_bounds__(1024) void k_range_part(const double* __restrict__ Iterm,
+                                                     const int64_t* __restrict__ k_off, double* __restrict__ part) {
+  const int q = blockIdx.y, sl = blockIdx.x;
+  const int64_t a = k_off[q], len = k_off[q + 1] - a;
+  const int S = tr_slices(len);
+  if (sl >= S) return;  // block-uniform
+  const double s = block_range_sum(Iterm, a + len * sl / S, a + len * (sl + 1) / S);
+  if (threadIdx.x == 0) part[(int64_t)q * TR_SLICES + sl] = s;
+}
+__global__ void k_range_trace(const double* __restrict__ part, const int64_t* __restrict__ k_off,
+                              const double* __restrict__ sxx, const int64_t* __restrict__ n_off, int m,
+                              double* __restrict__ dst) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) {
+    const int S = tr_slices(k_off[q + 1] - k_off[q]);
+    double s = 0.0;
+    for (int sl = 0; sl < S; ++sl) s += part[(int64_t)q * TR_SLICES + sl];
+    dst[q] = (sxx[q] - s) / (double)(n_off[q + 1] - n_off[q]);
+  }
+}
+
+// The distortion of every job into dst (m values); kmax: the largest job's
+// cluster count (host), part: m * TR_SLICES doubles of workspace.
+static knnkm_status launch_trace(knnkm_ctx* ctx, const double* Iterm, const int64_t* k_off, const double* sxx,
+                                 const int64_t* n_off, int m, int64_t kmax, double* part, double* dst) {
+  const dim3 grid(kmax >= TR_BIG ? TR_SLICES : 1, m);
+  k_range_part<<<grid, 1024, 0, ctx->stream>>>(Iterm, k_off, part);
+  k_range_trace<<<grid_for(m, 256, 1024), 256, 0, ctx->stream>>>(part, k_off, sxx, n_off, m, dst);
+  return knnkm_check(ctx, "distortion trace");
 }
 
 __global__ void k_local_labels(const int32_t* __restrict__ glab, const int32_t* __restrict__ job,
@@ -371,6 +400,9 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   int32_t *k32, K;
   int64_t* k64;
   KNNKM_TRY(upload_koff(ctx, kq, "fit", &k32, &k64, &K));
+  int64_t kmax = 0;
+  for (int32_t v : kq) kmax = std::max<int64_t>(kmax, v);
+  KNNKM_WS(ctx, trpart, double, "fit_trace_part", (int64_t)m * TR_SLICES);
   bool all_dense = true;
   for (int q = 0; q < m; ++q) all_dense = all_dense && kappa >= kq[q];
   KNNKM_WS(ctx, lab2, int32_t, "fit_labels2", n);
@@ -403,7 +435,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   KNNKM_TRY(ks_label_sort(ctx, labels, n, K, counts, off, mem));
   KNNKM_WS(ctx, sums0, double, "fit_sums0", (int64_t)K * d);
   KNNKM_TRY(ks_segsum(ctx, X, n, d, ldx, K, counts, off, mem, C, sums0, Iterm));
-  k_range_trace<<<m, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, trace_dev);
+  KNNKM_TRY(launch_trace(ctx, Iterm, k64, sxx, J.n_off, m, kmax, trpart, trace_dev));
   KNNKM_TRY(knnkm_check(ctx, "fit initialisation"));
   // the sweeps update the composite vectors D_r incrementally (exact
   // fixed point, one scale exponent per job)
@@ -455,6 +487,10 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   const bool use_act = ctx->active_sets && use_graph && n * (int64_t)kappa < INT32_MAX;
   int32_t *rev_off = nullptr, *rev_src = nullptr;
   uint8_t *act_p = nullptr, *act_2 = nullptr;
+  // wide rows: the labels of the graph entries, kept current by the updates,
+  // which the active-set sweeps read in place of scattered neighbour labels
+  int32_t* nlab = nullptr;
+  uint8_t* rev_pos = nullptr;
   int32_t* lcnt = nullptr;  // list counters, one per flag array
   int64_t* dmass = nullptr;  // members of the clusters an update made dirty
   if (use_act) {
@@ -467,7 +503,12 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     act_p = (uint8_t*)knnkm_ws(ctx, "fit_act_p", (size_t)(n + 3) / 4 * 4);
     act_2 = (uint8_t*)knnkm_ws(ctx, "fit_act_2", (size_t)(n + 3) / 4 * 4);
     if (!rev_off || !rev_src || !act_p || !act_2) return KNNKM_ENOMEM;
-    KNNKM_TRY(ks_reverse_graph(ctx, Gp, n, kappa, rev_off, rev_src));
+    if (ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense) {
+      nlab = (int32_t*)knnkm_ws(ctx, "fit_nlab", sizeof(int32_t) * (size_t)n * kappa);
+      rev_pos = (uint8_t*)knnkm_ws(ctx, "fit_rev_pos", (size_t)n * kappa);
+      if (!nlab || !rev_pos) return KNNKM_ENOMEM;
+    }
+    KNNKM_TRY(ks_reverse_graph(ctx, Gp, n, kappa, rev_off, rev_src, rev_pos));
     // both flag arrays start clear (the first sweep writes every flag of
     // its output array; the padding bytes stay zero)
     KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)act_p, (n + 3) / 4, 0));
@@ -510,12 +551,13 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     return ks_assign(ctx, Xp, n, d, d, C, K, Gp, kappa, cu, nx, nullptr, mv, nullptr, m == 1 && all_dense,
                      J.job_of, k32, first ? KS_USE_FIT_FIRST : KS_USE_FIT, ev, first ? nullptr : act_for(cu),
                      drift ? nullptr : act_for(nx), ac, cnt_for(cu), cnt_for(nx), false, first ? nullptr : dirty_for(cu), bnd_u,
-                     bnd_lb, first ? nullptr : cdelta, sw);
+                     bnd_lb, first ? nullptr : cdelta, sw, first ? nullptr : nlab);
   };
   // The first sweep moves a large share of the samples away from the
   // initial partition: its update rebuilds the sums from a label sort and
   // the segmented float64 sums (as at initialisation) and converts them to
-  // fixed point; later sweeps apply only their moves.
+  // fixed point (and so does the second's when it still moves more than
+  // n/8); later sweeps apply only their moves.
   auto update = [&](int32_t* cu, const int32_t* nx, double* tr, bool full, const int64_t* mv) -> knnkm_status {
     if (full) {
       KNNKM_TRY(ks_label_sort(ctx, nx, n, K, counts, off, mem));
@@ -529,19 +571,21 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(nx), K, 1));
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(cu), K, 0));
       KNNKM_TRY(ks_c_shadow(ctx, C, K, d, nullptr, sw));
+      if (nlab) KNNKM_TRY(ks_entry_labels(ctx, Gp, n, kappa, nx, nlab));
       if (drift)
         KNNKM_TRY(ks_mark_dirty(ctx, n, nx, dirty_for(nx), rev_off, rev_src, act_for(nx), nullptr, 0, J.job_of, k32,
                                 kappa));
     } else {
       KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty_for(nx), C, Iterm, rev_off, rev_src,
-                             act_for(nx), dirty_for(cu), cdelta, drift ? dmass : nullptr, sw));
+                             act_for(nx), dirty_for(cu), cdelta, drift ? dmass : nullptr, sw, nullptr, nlab, rev_pos,
+                             kappa));
       // scattered marks while the dirty clusters' members and the rows
       // listing them stay below about 2n; every sample beyond that
       if (drift)
         KNNKM_TRY(ks_mark_dirty(ctx, n, nx, dirty_for(nx), rev_off, rev_src, act_for(nx), dmass,
                                 2 * n / (kappa + 1), J.job_of, k32, kappa));
     }
-    k_range_trace<<<m, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, tr);
+    KNNKM_TRY(launch_trace(ctx, Iterm, k64, sxx, J.n_off, m, kmax, trpart, tr));
     return knnkm_check(ctx, "fit iteration");
   };
   ctx->fit_evals = nullptr;
@@ -566,7 +610,17 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       mark(7 + 2 * (t - 1));
       ctx->assign_n = t;
     }
-    KNNKM_TRY(update(cur, nxt, trace_dev + (int64_t)t * m, t == 1, moved + t));
+    // the first sweep's update rebuilds the sums; so does the second's when
+    // it moved more than n/8 samples (decided on the host, and only for the
+    // eagerly run sweeps, so every path of the fit takes the same updates)
+    bool full = t == 1;
+    if (t == 2) {
+      int64_t mv = 0;
+      KNNKM_HIP(ctx, hipMemcpyAsync(&mv, moved + t, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+      KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      full = mv > n / 8;
+    }
+    KNNKM_TRY(update(cur, nxt, trace_dev + (int64_t)t * m, full, moved + t));
     std::swap(cur, nxt);
     it = t;
     return KNNKM_OK;
@@ -830,7 +884,8 @@ static knnkm_status boost_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
   KNNKM_WS(ctx, Iterm, double, "fit_iterm", K);
   KNNKM_TRY(ks_fx_exact_sums(ctx, X, ldx, d, K, off, mem, cs, Dfx));
   KNNKM_TRY(ks_fx_finalize_all(ctx, Dfx, K, d, cs, counts, C, Iterm, C64));
-  k_range_trace<<<1, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, trace_dev);
+  KNNKM_WS(ctx, trpart, double, "fit_trace_part", TR_SLICES);
+  KNNKM_TRY(launch_trace(ctx, Iterm, k64, sxx, J.n_off, 1, K, trpart, trace_dev));
   KNNKM_TRY(knnkm_check(ctx, "boost initialisation"));
   // the moves read rows by position with stride d: a contiguous copy when
   // the caller's rows are strided
@@ -875,7 +930,7 @@ static knnkm_status boost_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
                             kappa));
     KNNKM_TRY(ks_act_compact(ctx, n, act, list, lcount));
     std::swap(dset, dclear);
-    k_range_trace<<<1, 1024, 0, ctx->stream>>>(Iterm, k64, sxx, J.n_off, trace_dev + t);
+    KNNKM_TRY(launch_trace(ctx, Iterm, k64, sxx, J.n_off, 1, K, trpart, trace_dev + t));
     int64_t np = 0;
     KNNKM_HIP(ctx, hipMemcpyAsync(&np, nprop + t, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
     KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));

@@ -138,10 +138,15 @@ __device__ inline void mark_one(uint8_t* __restrict__ act_out, int64_t x) { act_
 // position p and `moved`), the wave's marks laid end to end over the lanes
 // (sample q owns entries [ex_q, ex_q + 1 + its reverse-list length); its
 // first entry is the sample itself), so all of them are in flight at once.
+// With nlab (the labels of every graph entry, row-major n x kappa) the
+// entries that list a selected sample also receive its new label lab_new
+// (rev_pos: the position of each reverse-list entry in its row).
 template <int BIT = 2>
 __device__ inline void mark_moved_wave(bool moved, int64_t p, const int32_t* __restrict__ rev_off,
                                        const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out,
-                                       int lane) {
+                                       int lane, int32_t* __restrict__ nlab = nullptr,
+                                       const uint8_t* __restrict__ rev_pos = nullptr, int kappa = 0,
+                                       int lab_new = 0) {
   int32_t r0 = 0, c = 0;
   if (moved) {
     r0 = rev_off[p];
@@ -164,7 +169,12 @@ __device__ inline void mark_moved_wave(bool moved, int64_t p, const int32_t* __r
     const int32_t local = e - (__shfl(inc, q, 64) - __shfl(c, q, 64));
     const int32_t rq = __shfl(r0, q, 64);
     const int64_t pq = __shfl(p, q, 64);
-    if (e < total) mark_one<BIT>(act_out, local == 0 ? pq : (int64_t)rev_src[rq + local - 1]);
+    const int32_t src = e < total && local > 0 ? rev_src[rq + local - 1] : 0;
+    if (e < total) mark_one<BIT>(act_out, local == 0 ? pq : (int64_t)src);
+    if (nlab) {  // wave-uniform
+      const int lq = __shfl(lab_new, q, 64);
+      if (e < total && local > 0) nlab[(int64_t)src * kappa + rev_pos[rq + local - 1]] = lq;
+    }
   }
 }
 
@@ -176,9 +186,10 @@ __device__ inline void add128(uint64_t& h, uint64_t& l, uint64_t bh, uint64_t bl
 }
 
 // Every moved sample: its row out of D[old], into D[new]; sizes and dirty
-// flags of both clusters.  With act_out (active sets) also its marks, and
-// its new label written over the old one in cur, so that the two label
-// arrays agree outside the samples the next sweep writes.  A wavefront scans
+// flags of both clusters.  With act_out (active sets) also its marks, its
+// new label written over the old one in cur, so that the two label arrays
+// agree outside the samples the next sweep writes, and (nlab non-null) into
+// the graph-entry labels of the rows that list it.  A wavefront scans
 // 64 positions and takes its moved samples in order, lanes over the
 // dimensions (DPL per lane); consecutive moved samples that leave the same
 // cluster (or join the same one), common in the cluster-ordered working
@@ -190,7 +201,9 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
                                                   const int32_t* __restrict__ cs, uint64_t* __restrict__ D,
                                                   int32_t* __restrict__ counts, int32_t* __restrict__ dirty,
                                                   const int32_t* __restrict__ rev_off,
-                                                  const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out) {
+                                                  const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out,
+                                                  int32_t* __restrict__ nlab, const uint8_t* __restrict__ rev_pos,
+                                                  int kappa) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -211,7 +224,7 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
     }
     uint64_t M = __ballot(moved);
     if (!M) continue;  // wave-uniform
-    if (act_out) mark_moved_wave(moved, p, rev_off, rev_src, act_out, lane);
+    if (act_out) mark_moved_wave(moved, p, rev_off, rev_src, act_out, lane, nlab, rev_pos, kappa, b);
     int run_from = -1, run_to = -1;
     uint64_t fh[DPL], fl[DPL], th[DPL], tl[DPL];
 #pragma unroll
@@ -339,12 +352,23 @@ __global__ void k_rev_count(const int32_t* __restrict__ G, int64_t ne, int64_t n
   }
 }
 __global__ void k_rev_fill(const int32_t* __restrict__ G, int64_t ne, int64_t n, int kappa,
-                           const int32_t* __restrict__ off, int32_t* __restrict__ cursor, int32_t* __restrict__ src) {
+                           const int32_t* __restrict__ off, int32_t* __restrict__ cursor, int32_t* __restrict__ src,
+                           uint8_t* __restrict__ pos_in_row) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t t = G[e];
     if (t < 0 || t >= n) continue;
     const int32_t pos = atomicAdd(&cursor[t], 1);
     src[off[t] + pos] = (int32_t)(e / kappa);
+    if (pos_in_row) pos_in_row[off[t] + pos] = (uint8_t)(e % kappa);
+  }
+}
+
+// Label of every graph entry: nlab[e] = lab[G[e]] (-1 for ids outside [0, n)).
+__global__ void k_entry_labels(const int32_t* __restrict__ G, int64_t ne, int64_t n, const int32_t* __restrict__ lab,
+                               int32_t* __restrict__ nlab) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t t = G[e];
+    nlab[e] = t >= 0 && t < n ? lab[t] : -1;
   }
 }
 
@@ -453,11 +477,11 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off, const int32_t* rev_src,
                           uint8_t* act_out, int32_t* dirty_clear, float* delta, int64_t* mass, CShadow sw,
-                          double* C64) {
+                          double* C64, int32_t* nlab, const uint8_t* rev_pos, int32_t kappa) {
   if (mass) KNNKM_TRY(ks_fill_i64(ctx, mass, 1, 0));
 #define MV(DD)                                                                                           \
   k_fx_moves<DD><<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty, \
-                                                                  rev_off, rev_src, act_out)
+                                                                  rev_off, rev_src, act_out, nlab, rev_pos, kappa)
   if (d <= 64)
     MV(1);
   else if (d <= 128)
@@ -523,8 +547,15 @@ knnkm_status ks_mark_dirty(knnkm_ctx* ctx, int64_t n, const int32_t* lab, const 
   return knnkm_check(ctx, "active-set marks of changed centroids");
 }
 
+knnkm_status ks_entry_labels(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, const int32_t* lab,
+                             int32_t* nlab) {
+  const int64_t ne = n * (int64_t)kappa;
+  k_entry_labels<<<grid_for(ne, 256, 16384), 256, 0, ctx->stream>>>(G, ne, n, lab, nlab);
+  return knnkm_check(ctx, "graph-entry labels");
+}
+
 knnkm_status ks_reverse_graph(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, int32_t* rev_off,
-                              int32_t* rev_src) {
+                              int32_t* rev_src, uint8_t* rev_pos) {
   KNNKM_WS(ctx, cursor, int32_t, "rev_cursor", n);
   const int64_t ne = n * (int64_t)kappa;
   KNNKM_TRY(ks_fill_i32(ctx, rev_off, n + 1, 0));
@@ -532,6 +563,6 @@ knnkm_status ks_reverse_graph(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32
   k_rev_count<<<grid_for(ne, 256, 16384), 256, 0, ctx->stream>>>(G, ne, n, rev_off);
   KNNKM_TRY(knnkm_check(ctx, "reverse graph counts"));
   KNNKM_TRY(ks_scan_exclusive(ctx, rev_off, rev_off, n, true));
-  k_rev_fill<<<grid_for(ne, 256, 16384), 256, 0, ctx->stream>>>(G, ne, n, kappa, rev_off, cursor, rev_src);
+  k_rev_fill<<<grid_for(ne, 256, 16384), 256, 0, ctx->stream>>>(G, ne, n, kappa, rev_off, cursor, rev_src, rev_pos);
   return knnkm_check(ctx, "reverse graph");
 }
