@@ -215,8 +215,9 @@ knnkm_status knn_kmeans_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d
  * including KNNKM_INIT_LABELS).  Outputs labels (n), C (k x d, the float32
  * means; clusters left empty keep the initial centroid), counts (k);
  * trace_host (max_iters + 1 doubles) receives E_0..E_t (Eqn. 4);
- * rounds_run_host the rounds done.  G_ids: n x kappa, required.
- * Synchronous (one host read per round). */
+ * rounds_run_host the rounds done.  G_ids: n x kappa, required;
+ * n * kappa < 2^31 (else KNNKM_EUNSUPPORTED).  Synchronous (one host read
+ * per round). */
 knnkm_status knn_boost_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int32_t k,
                            const int32_t* G_ids, const knnkm_params* params, int32_t* labels, float* C,
                            int32_t* counts, double* trace_host, int32_t* rounds_run_host);

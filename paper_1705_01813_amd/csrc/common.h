@@ -329,7 +329,7 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off,
                           const int32_t* rev_src, uint8_t* act_out, int32_t* dirty_clear,
                           float* delta, int64_t* mass = nullptr, CShadow sw = {}, double* C64 = nullptr,
-                          int32_t* nlab = nullptr, const uint8_t* rev_pos = nullptr, int32_t kappa = 0);
+                          int32_t* nlab = nullptr, int32_t kappa = 0);
 // Exact fixed-point D of every cluster from its members (CSR), and the
 // centroids, float64 means and Eqn. 2 terms of every cluster from D.
 knnkm_status ks_fx_exact_sums(knnkm_ctx* ctx, const float* X, int64_t ldx, int32_t d, int32_t K, const int32_t* off,
@@ -351,7 +351,8 @@ knnkm_status ks_act_compact(knnkm_ctx* ctx, int64_t n, uint8_t* act, int32_t* li
 // Active-set marks of the samples moved between cur and nxt and of the rows
 // listing them (reverse lists of the graph); moved labels copied into cur.
 knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,
-                           const int32_t* rev_src, uint8_t* act_out, const int64_t* moved, int64_t all_at);
+                           const int32_t* rev_src, uint8_t* act_out, const int64_t* moved, int64_t all_at,
+                           int32_t kappa);
 // Active-set marks (bit 0) of the samples with a dirty cluster among their
 // candidates and of the samples of jobs with at most kappa clusters; every
 // sample when mass is null or *mass >= all_at.
@@ -359,9 +360,10 @@ knnkm_status ks_mark_dirty(knnkm_ctx* ctx, int64_t n, const int32_t* lab, const 
                            const int32_t* rev_off, const int32_t* rev_src, uint8_t* act_out, const int64_t* mass,
                            int64_t all_at, const int32_t* job_of, const int32_t* kbase, int32_t kappa);
 // Reverse lists of an n x kappa graph: rev_off (n + 1), rev_src (n * kappa).
-// rev_pos (nullable): the position of each reverse-list entry in its row.
+// Reverse lists: rev_src holds graph entries (row * kappa + position; needs
+// n * kappa < 2^31).
 knnkm_status ks_reverse_graph(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, int32_t* rev_off,
-                              int32_t* rev_src, uint8_t* rev_pos = nullptr);
+                              int32_t* rev_src);
 // Labels of the graph entries: nlab[e] = lab[G[e]] (-1 past [0, n)).
 knnkm_status ks_entry_labels(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, const int32_t* lab,
                              int32_t* nlab);

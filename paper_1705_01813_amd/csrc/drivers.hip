@@ -490,7 +490,6 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   // wide rows: the labels of the graph entries, kept current by the updates,
   // which the active-set sweeps read in place of scattered neighbour labels
   int32_t* nlab = nullptr;
-  uint8_t* rev_pos = nullptr;
   int32_t* lcnt = nullptr;  // list counters, one per flag array
   int64_t* dmass = nullptr;  // members of the clusters an update made dirty
   if (use_act) {
@@ -505,10 +504,9 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
     if (!rev_off || !rev_src || !act_p || !act_2) return KNNKM_ENOMEM;
     if (ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense) {
       nlab = (int32_t*)knnkm_ws(ctx, "fit_nlab", sizeof(int32_t) * (size_t)n * kappa);
-      rev_pos = (uint8_t*)knnkm_ws(ctx, "fit_rev_pos", (size_t)n * kappa);
-      if (!nlab || !rev_pos) return KNNKM_ENOMEM;
+      if (!nlab) return KNNKM_ENOMEM;
     }
-    KNNKM_TRY(ks_reverse_graph(ctx, Gp, n, kappa, rev_off, rev_src, rev_pos));
+    KNNKM_TRY(ks_reverse_graph(ctx, Gp, n, kappa, rev_off, rev_src));
     // both flag arrays start clear (the first sweep writes every flag of
     // its output array; the padding bytes stay zero)
     KNNKM_TRY(ks_fill_i32(ctx, (int32_t*)act_p, (n + 3) / 4, 0));
@@ -566,7 +564,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
       // the moves' marks, or every row once the moved samples' reverse
       // lists (kappa entries each on average) would cover n
       if (use_act)
-        KNNKM_TRY(ks_mark_moved(ctx, n, cu, nx, rev_off, rev_src, act_for(nx), mv, (n + kappa) / (kappa + 1)));
+        KNNKM_TRY(ks_mark_moved(ctx, n, cu, nx, rev_off, rev_src, act_for(nx), mv, (n + kappa) / (kappa + 1), kappa));
       // every centroid was recomputed
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(nx), K, 1));
       KNNKM_TRY(ks_fill_i32(ctx, dirty_for(cu), K, 0));
@@ -577,8 +575,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
                                 kappa));
     } else {
       KNNKM_TRY(ks_fx_update(ctx, Xp, n, d, cu, nx, cs, Dfx, K, counts, dirty_for(nx), C, Iterm, rev_off, rev_src,
-                             act_for(nx), dirty_for(cu), cdelta, drift ? dmass : nullptr, sw, nullptr, nlab, rev_pos,
-                             kappa));
+                             act_for(nx), dirty_for(cu), cdelta, drift ? dmass : nullptr, sw, nullptr, nlab, kappa));
       // scattered marks while the dirty clusters' members and the rows
       // listing them stay below about 2n; every sample beyond that
       if (drift)
@@ -901,6 +898,8 @@ static knnkm_status boost_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
   // active lists: after a round only the samples with a changed cluster
   // among their own and their neighbours' (members of a dirty cluster and
   // the samples listing one in their graph rows) propose again
+  if (n * (int64_t)kappa >= INT32_MAX)
+    return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "knn_boost_fit: n * kappa must stay below 2^31");
   KNNKM_WS(ctx, rev_off, int32_t, "fit_rev_off", n + 1);
   KNNKM_WS(ctx, rev_src, int32_t, "fit_rev_src", n * (int64_t)kappa);
   KNNKM_WS(ctx, act, uint8_t, "fit_act_p", (n + 3) / 4 * 4);

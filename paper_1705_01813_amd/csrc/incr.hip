@@ -138,15 +138,13 @@ __device__ inline void mark_one(uint8_t* __restrict__ act_out, int64_t x) { act_
 // position p and `moved`), the wave's marks laid end to end over the lanes
 // (sample q owns entries [ex_q, ex_q + 1 + its reverse-list length); its
 // first entry is the sample itself), so all of them are in flight at once.
-// With nlab (the labels of every graph entry, row-major n x kappa) the
-// entries that list a selected sample also receive its new label lab_new
-// (rev_pos: the position of each reverse-list entry in its row).
+// A reverse-list entry is the graph entry (row * kappa + position) that
+// lists the sample.  With nlab (the labels of every graph entry, row-major
+// n x kappa) those entries also receive the sample's new label lab_new.
 template <int BIT = 2>
 __device__ inline void mark_moved_wave(bool moved, int64_t p, const int32_t* __restrict__ rev_off,
                                        const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out,
-                                       int lane, int32_t* __restrict__ nlab = nullptr,
-                                       const uint8_t* __restrict__ rev_pos = nullptr, int kappa = 0,
-                                       int lab_new = 0) {
+                                       int lane, int kappa, int32_t* __restrict__ nlab = nullptr, int lab_new = 0) {
   int32_t r0 = 0, c = 0;
   if (moved) {
     r0 = rev_off[p];
@@ -170,10 +168,10 @@ __device__ inline void mark_moved_wave(bool moved, int64_t p, const int32_t* __r
     const int32_t rq = __shfl(r0, q, 64);
     const int64_t pq = __shfl(p, q, 64);
     const int32_t src = e < total && local > 0 ? rev_src[rq + local - 1] : 0;
-    if (e < total) mark_one<BIT>(act_out, local == 0 ? pq : (int64_t)src);
+    if (e < total) mark_one<BIT>(act_out, local == 0 ? pq : (int64_t)(src / kappa));
     if (nlab) {  // wave-uniform
       const int lq = __shfl(lab_new, q, 64);
-      if (e < total && local > 0) nlab[(int64_t)src * kappa + rev_pos[rq + local - 1]] = lq;
+      if (e < total && local > 0) nlab[src] = lq;
     }
   }
 }
@@ -202,8 +200,7 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
                                                   int32_t* __restrict__ counts, int32_t* __restrict__ dirty,
                                                   const int32_t* __restrict__ rev_off,
                                                   const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out,
-                                                  int32_t* __restrict__ nlab, const uint8_t* __restrict__ rev_pos,
-                                                  int kappa) {
+                                                  int32_t* __restrict__ nlab, int kappa) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -224,7 +221,7 @@ __global__ __launch_bounds__(256) void k_fx_moves(const float* __restrict__ X, i
     }
     uint64_t M = __ballot(moved);
     if (!M) continue;  // wave-uniform
-    if (act_out) mark_moved_wave(moved, p, rev_off, rev_src, act_out, lane, nlab, rev_pos, kappa, b);
+    if (act_out) mark_moved_wave(moved, p, rev_off, rev_src, act_out, lane, kappa, nlab, b);
     int run_from = -1, run_to = -1;
     uint64_t fh[DPL], fl[DPL], th[DPL], tl[DPL];
 #pragma unroll
@@ -288,7 +285,7 @@ __global__ __launch_bounds__(256) void k_mark_moved(int64_t n, int32_t* __restri
                                                     const int32_t* __restrict__ nxt,
                                                     const int32_t* __restrict__ rev_off,
                                                     const int32_t* __restrict__ rev_src, uint8_t* __restrict__ act_out,
-                                                    const int64_t* __restrict__ moved, int64_t all_at) {
+                                                    const int64_t* __restrict__ moved, int64_t all_at, int kappa) {
   const int lane = threadIdx.x & 63;
   const bool all = *moved >= all_at;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -301,7 +298,7 @@ __global__ __launch_bounds__(256) void k_mark_moved(int64_t n, int32_t* __restri
     if (all) {
       if (p < n) mark_one<2>(act_out, p);
     } else if (__ballot(mv)) {
-      mark_moved_wave(mv, p, rev_off, rev_src, act_out, lane);
+      mark_moved_wave(mv, p, rev_off, rev_src, act_out, lane, kappa);
     }
   }
 }
@@ -338,13 +335,14 @@ __global__ __launch_bounds__(256) void k_mark_dirty(int64_t n, const int32_t* __
       const int q = job_of[p];
       sel = kappa >= kbase[q + 1] - kbase[q];
     }
-    if (__ballot(sel)) mark_moved_wave<1>(sel, p, rev_off, rev_src, act_out, lane);
+    if (__ballot(sel)) mark_moved_wave<1>(sel, p, rev_off, rev_src, act_out, lane, kappa);
   }
 }
 
 // Reverse lists of a graph of n rows with kappa ids each: rev_src holds, for
-// every target p in rev_off[p] .. rev_off[p+1], the rows that list p (in no
-// particular order).  Ids outside [0, n) are left out.
+// every target p in rev_off[p] .. rev_off[p+1], the graph entries (row *
+// kappa + position, n * kappa < 2^31) that list p (in no particular order).
+// Ids outside [0, n) are left out.
 __global__ void k_rev_count(const int32_t* __restrict__ G, int64_t ne, int64_t n, int32_t* __restrict__ cnt) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t t = G[e];
@@ -352,14 +350,12 @@ __global__ void k_rev_count(const int32_t* __restrict__ G, int64_t ne, int64_t n
   }
 }
 __global__ void k_rev_fill(const int32_t* __restrict__ G, int64_t ne, int64_t n, int kappa,
-                           const int32_t* __restrict__ off, int32_t* __restrict__ cursor, int32_t* __restrict__ src,
-                           uint8_t* __restrict__ pos_in_row) {
+                           const int32_t* __restrict__ off, int32_t* __restrict__ cursor, int32_t* __restrict__ src) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t t = G[e];
     if (t < 0 || t >= n) continue;
     const int32_t pos = atomicAdd(&cursor[t], 1);
-    src[off[t] + pos] = (int32_t)(e / kappa);
-    if (pos_in_row) pos_in_row[off[t] + pos] = (uint8_t)(e % kappa);
+    src[off[t] + pos] = (int32_t)e;
   }
 }
 
@@ -477,11 +473,11 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
                           const int32_t* nxt, const int32_t* cs, uint64_t* D, int32_t K, int32_t* counts,
                           int32_t* dirty, float* C, double* Iterm, const int32_t* rev_off, const int32_t* rev_src,
                           uint8_t* act_out, int32_t* dirty_clear, float* delta, int64_t* mass, CShadow sw,
-                          double* C64, int32_t* nlab, const uint8_t* rev_pos, int32_t kappa) {
+                          double* C64, int32_t* nlab, int32_t kappa) {
   if (mass) KNNKM_TRY(ks_fill_i64(ctx, mass, 1, 0));
 #define MV(DD)                                                                                           \
   k_fx_moves<DD><<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(Xp, n, d, cur, nxt, cs, D, counts, dirty, \
-                                                                  rev_off, rev_src, act_out, nlab, rev_pos, kappa)
+                                                                  rev_off, rev_src, act_out, nlab, kappa)
   if (d <= 64)
     MV(1);
   else if (d <= 128)
@@ -497,9 +493,10 @@ knnkm_status ks_fx_update(knnkm_ctx* ctx, const float* Xp, int64_t n, int32_t d,
 }
 
 knnkm_status ks_mark_moved(knnkm_ctx* ctx, int64_t n, int32_t* cur, const int32_t* nxt, const int32_t* rev_off,
-                           const int32_t* rev_src, uint8_t* act_out, const int64_t* moved, int64_t all_at) {
+                           const int32_t* rev_src, uint8_t* act_out, const int64_t* moved, int64_t all_at,
+                           int32_t kappa) {
   k_mark_moved<<<grid_for(n, 256, 8192), 256, 0, ctx->stream>>>(n, cur, nxt, rev_off, rev_src, act_out, moved,
-                                                                all_at);
+                                                                all_at, kappa);
   return knnkm_check(ctx, "active-set marks");
 }
 
@@ -555,7 +552,7 @@ knnkm_status ks_entry_labels(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_
 }
 
 knnkm_status ks_reverse_graph(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32_t kappa, int32_t* rev_off,
-                              int32_t* rev_src, uint8_t* rev_pos) {
+                              int32_t* rev_src) {
   KNNKM_WS(ctx, cursor, int32_t, "rev_cursor", n);
   const int64_t ne = n * (int64_t)kappa;
   KNNKM_TRY(ks_fill_i32(ctx, rev_off, n + 1, 0));
@@ -563,6 +560,6 @@ knnkm_status ks_reverse_graph(knnkm_ctx* ctx, const int32_t* G, int64_t n, int32
   k_rev_count<<<grid_for(ne, 256, 16384), 256, 0, ctx->stream>>>(G, ne, n, rev_off);
   KNNKM_TRY(knnkm_check(ctx, "reverse graph counts"));
   KNNKM_TRY(ks_scan_exclusive(ctx, rev_off, rev_off, n, true));
-  k_rev_fill<<<grid_for(ne, 256, 16384), 256, 0, ctx->stream>>>(G, ne, n, kappa, rev_off, cursor, rev_src, rev_pos);
+  k_rev_fill<<<grid_for(ne, 256, 16384), 256, 0, ctx->stream>>>(G, ne, n, kappa, rev_off, cursor, rev_src);
   return knnkm_check(ctx, "reverse graph");
 }
