@@ -166,14 +166,6 @@ __device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, 
                                                                     int cv, double rel, bool skip, bool pilot) {
   const float* __restrict__ eps = sw.eps;
   const int lane = threadIdx.x & 63;
-  // the row into LDS (lane j: dims [8j, 8j+8), read back by the same lane
-  // where the 64-lane layout is used)
-  {
-    float x[8];
-    load_row<8>(x, xrow, lane, d, vec_x);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) sh.x[lane * 8 + e] = x[e];
-  }
   // slots: 0 the own cluster, then the entries holding another one in entry
   // order; an entry holding the own cluster maps to slot 0
   const int mine = (cv >= 0 && !(skip && lane > 0)) ? cv : -1;
@@ -181,6 +173,17 @@ __device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, 
   const uint64_t cm = __ballot(isc);
   const int A0 = __popcll(cm);
   const int myslot = mine < 0 ? -1 : (isc ? 1 + __popcll(cm & lanes_below()) : 0);
+  // the own centroid in full, and with a pilot the first slot's: their rows
+  // are loaded together with the sample's row (lane j: dims [8j, 8j+8)),
+  // which then goes to LDS for the chunk steps; the distances are formed as
+  // pd_exact forms them
+  const int np = pilot ? min(A0, 1) : 0;
+  float x[8], co[8], cp[8];
+  load_row<8>(x, xrow, lane, d, vec_x);
+  load_row<8>(co, C + (int64_t)cur * d, lane, d, vec_c);
+  if (np) load_row<8>(cp, C + (int64_t)__builtin_amdgcn_readlane(mine, (int)__builtin_ctzll(cm)) * d, lane, d, vec_c);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) sh.x[lane * 8 + e] = x[e];
   sh.full[lane] = FLT_MAX;
   sh.lb[lane] = FLT_MAX;
   sh.part[lane] = 0.f;
@@ -190,9 +193,32 @@ __device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, 
   }
   if (lane == 0) sh.cand[0] = cur;
   wave_lds_sync();
-  // the own centroid in full, and the first slot with it with a pilot
-  const int np = pilot ? min(A0, 1) : 0;
-  pd_exact(sh, 1 + np, [](int e) { return e; }, C, d, vec_c, rel);
+  {
+    float acc = 0.f, accp = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float df = x[e] - co[e];
+      acc = fmaf(df, df, acc);
+    }
+    const float v = group_sum<64>(acc);
+    float vp = FLT_MAX;
+    if (np) {  // wave-uniform
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float df = x[e] - cp[e];
+        accp = fmaf(df, df, accp);
+      }
+      vp = group_sum<64>(accp);
+    }
+    if (lane == 0) {
+      sh.full[0] = v;
+      sh.lb[0] = f32_round_down((double)v * (1.0 - rel));
+      if (np) {
+        sh.full[1] = vp;
+        sh.lb[1] = f32_round_down((double)vp * (1.0 - rel));
+      }
+    }
+  }
   wave_lds_sync();
   const double ub = (double)fminf(sh.full[0], np ? sh.full[1] : FLT_MAX) * (1.0 + rel) + 1e-30;
   constexpr int NG = 64 / GL;        // candidates per batch
