@@ -409,11 +409,12 @@ knnkm_status knnkm_autotune(knnkm_ctx* ctx, int32_t on);
  * every candidate is summed 64 dimensions at a time and dropped once a
  * rigorous lower bound of its distance over those dimensions exceeds it; the
  * survivors get full float32 distances (float64 near ties).  on: 0 off, 1 on
- * (default), the graph build's and the fit's sweeps reading a shadow of the
- * centroids in 8-bit codes for the partial sums (a quarter of the bytes; one
- * code step per row, its largest magnitude / 127; the bound accounts for
- * each shadow row's distance to its float32 row), 2 on with the float32
- * centroids only, 3 on with a bfloat16 shadow (half the bytes).  Decisions
+ * (default), the sweeps of the graph build, of the fit and of knn_assign
+ * (which forms it from C on each call) reading a shadow of the centroids in
+ * 8-bit codes for the partial sums (a quarter of the bytes; one code step per
+ * row, its largest magnitude / 127; the bound accounts for each shadow row's
+ * distance to its float32 row), 2 on with the float32 centroids only, 3 on
+ * with a bfloat16 shadow (half the bytes).  Decisions
  * (labels, moved counts, active-set flags) are the same in every mode;
  * calls that request best_d2 use the full-distance kernels.  Other values:
  * KNNKM_EINVAL. */

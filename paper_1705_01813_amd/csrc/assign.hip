@@ -765,6 +765,30 @@ extern "C" knnkm_status knnkm_set_assign_shape(knnkm_ctx* ctx, int32_t gs, int32
   return KNNKM_OK;
 }
 
+// The centroid shadow of the context's kind (none: kind 0) for K rows of d
+// dimensions, in the workspace under names starting with `tag`.
+knnkm_status ks_shadow_alloc(knnkm_ctx* ctx, const char* tag, int32_t K, int32_t d, CShadow* sw) {
+  *sw = CShadow{};
+  if (ctx->pd_shadow == 0) return KNNKM_OK;
+  const size_t per = ctx->pd_shadow == 2 ? 1 : 2;  // bytes per element
+  char name[40];
+  snprintf(name, sizeof(name), "%s_cshadow", tag);
+  void* rows = knnkm_ws(ctx, name, per * (size_t)K * d);
+  snprintf(name, sizeof(name), "%s_ceps", tag);
+  float* eps = (float*)knnkm_ws(ctx, name, sizeof(float) * (size_t)K);
+  float* scale = nullptr;
+  if (ctx->pd_shadow == 2) {
+    snprintf(name, sizeof(name), "%s_cscale", tag);
+    scale = (float*)knnkm_ws(ctx, name, sizeof(float) * (size_t)K);
+  }
+  if (!rows || !eps || (ctx->pd_shadow == 2 && !scale)) return KNNKM_ENOMEM;
+  sw->rows = rows;
+  sw->eps = eps;
+  sw->scale = scale;
+  sw->kind = ctx->pd_shadow;
+  return KNNKM_OK;
+}
+
 knnkm_status ks_act_compact(knnkm_ctx* ctx, int64_t n, uint8_t* act, int32_t* list, int32_t* count) {
   KNNKM_TRY(ks_fill_i32(ctx, count, 1, 0));
   k_act_compact<<<(unsigned)((n + 4095) / 4096), 256, 0, ctx->stream>>>(n, act, list, count, nullptr);
@@ -881,9 +905,16 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   }
   };
 #undef LA
-  if (wide)
+  if (wide) {
+    // a caller's assignment reads the context's kind of shadow too, built
+    // here from its centroids
+    if (use == KS_USE_CALL && sw.kind == 0 && ctx->pd_shadow != 0) {
+      KNNKM_TRY(ks_shadow_alloc(ctx, "as", k, d, &sw));
+      KNNKM_TRY(ks_c_shadow(ctx, C, k, d, nullptr, sw));
+    }
     return ks_assign_pd(ctx, X, n, d, ldx, C, k, G_ids, kappa, labels_in, labels_out, acc, eacc, order, job_of,
                         kbase, act_in, act_out, nullptr, nullptr, nullptr, nullptr, 64, bnd_u, bnd_lb, nullptr, sw);
+  }
   // shape: tuned entry, else (large call, tuning allowed, not inside a
   // graph capture) time every candidate once, else the default
   const int Sb = S <= 1 ? 1 : (S <= 2 ? 2 : (S <= 4 ? 4 : 8));

@@ -279,6 +279,9 @@ knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
 // sw: the shadow of C (ks_c_shadow) read for the early-abandon steps, or
 // kind 0 (the float32 rows).
 bool ks_assign_pd_ok(int32_t d, int32_t kappa);
+// Workspace for the centroid shadow of the context's kind (kind 0: none) of
+// K rows of d dimensions, under names starting with `tag`.
+knnkm_status ks_shadow_alloc(knnkm_ctx* ctx, const char* tag, int32_t K, int32_t d, CShadow* sw);
 // Shadow (kind 1 or 2) of the centroid rows of C, all or those with dirty[r]
 // set, with its row bounds.
 knnkm_status ks_c_shadow(knnkm_ctx* ctx, const float* C, int32_t K, int32_t d, const int32_t* dirty, CShadow sw);

@@ -283,30 +283,6 @@ static knnkm_status upload_koff(knnkm_ctx* ctx, const std::vector<int32_t>& kq, 
   return KNNKM_OK;
 }
 
-// The centroid shadow of the context's kind (none: kind 0) for K rows of d
-// dimensions, in the workspace under names starting with `tag`.
-static knnkm_status shadow_alloc(knnkm_ctx* ctx, const char* tag, int32_t K, int32_t d, CShadow* sw) {
-  *sw = CShadow{};
-  if (ctx->pd_shadow == 0) return KNNKM_OK;
-  const size_t per = ctx->pd_shadow == 2 ? 1 : 2;  // bytes per element
-  char name[40];
-  snprintf(name, sizeof(name), "%s_cshadow", tag);
-  void* rows = knnkm_ws(ctx, name, per * (size_t)K * d);
-  snprintf(name, sizeof(name), "%s_ceps", tag);
-  float* eps = (float*)knnkm_ws(ctx, name, sizeof(float) * (size_t)K);
-  float* scale = nullptr;
-  if (ctx->pd_shadow == 2) {
-    snprintf(name, sizeof(name), "%s_cscale", tag);
-    scale = (float*)knnkm_ws(ctx, name, sizeof(float) * (size_t)K);
-  }
-  if (!rows || !eps || (ctx->pd_shadow == 2 && !scale)) return KNNKM_ENOMEM;
-  sw->rows = rows;
-  sw->eps = eps;
-  sw->scale = scale;
-  sw->kind = ctx->pd_shadow;
-  return KNNKM_OK;
-}
-
 // Alg. 3 for every job of J.
 static knnkm_status build_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, Jobs& J,
                                const knnkm_params* p, int32_t* G_ids, float* G_d2) {
@@ -342,7 +318,7 @@ static knnkm_status build_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_
     // wide rows: the centroid shadow the assignment's early-abandon steps read
     CShadow sw;
     if (ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense)
-      KNNKM_TRY(shadow_alloc(ctx, "kb", K0, d, &sw));
+      KNNKM_TRY(ks_shadow_alloc(ctx, "kb", K0, d, &sw));
     KNNKM_TRY(ks_row_norms(ctx, X, n, d, ldx, nrm));
     for (int t = 0; t < p->tau; ++t) {
       KNNKM_TRY(ks_twomeans_multi(ctx, X, d, ldx, J.n_host, k0, J.m > 1 ? J.seeds : nullptr, J.seed_host[0], t,
@@ -528,7 +504,7 @@ static knnkm_status fit_impl(knnkm_ctx* ctx, const float* X, int32_t d, int64_t 
   // and the shadow of the centroids read by the early-abandon steps
   CShadow sw;
   if (ctx->wide_pd && ks_assign_pd_ok(d, kappa) && !all_dense) {
-    KNNKM_TRY(shadow_alloc(ctx, "fit", K, d, &sw));
+    KNNKM_TRY(ks_shadow_alloc(ctx, "fit", K, d, &sw));
     KNNKM_TRY(ks_c_shadow(ctx, C, K, d, nullptr, sw));
   }
   if (drift) {

@@ -1239,10 +1239,11 @@ def test_refine_full_size_c3_sampled_clusters_bf16(ctx):
 @pytest.mark.parametrize("n,d,k,kappa", [(6000, 512, 300, 50), (5000, 300, 200, 63), (4099, 264, 500, 10),
                                          (3000, 384, 40, 20)])
 def test_assign_wide_partial_distances(ctx, n, d, k, kappa):
-    """Wide rows: the early-abandoned partial distances give the oracle's
-    labels and moved count, and the same labels as the full-distance kernel,
-    from random input labels (many candidates per sample and many moves) and
-    from the labels one sweep later (fewer moves)."""
+    """Wide rows: the early-abandoned partial distances (over the 8-bit
+    shadow, the bfloat16 shadow or the float32 rows) give the oracle's labels
+    and moved count, and the same labels as the full-distance kernel, from
+    random input labels (many candidates per sample and many moves) and from
+    the labels one sweep later (fewer moves)."""
     say("assign wide", n, d, k, kappa)
     X = datagen.mixture(n, d, max(2, k // 2), seed=d + k, sigma=0.5, centre="normal")
     rs = np.random.default_rng(d)
@@ -1254,22 +1255,25 @@ def test_assign_wide_partial_distances(ctx, n, d, k, kappa):
     for lab_in in (lab_rand, lab_near.astype(np.int32)):
         want, _, want_mv = gkmeans.gk_assign(X, C, lab_in, G)
         got = {}
-        for pd in (True, False):
-            knnkm.knnkm_enable_partial_distances(ctx, pd)
-            out = torch.empty(n, dtype=torch.int32, device=DEV)
-            mv = torch.zeros(1, dtype=torch.int64, device=DEV)
-            knnkm.knn_assign(ctx, Xd, Cd, Gd, dev(lab_in), out, None, mv)
-            got[pd] = (host(out), int(host(mv)[0]))
-        knnkm.knnkm_enable_partial_distances(ctx, True)
-        assert np.array_equal(got[True][0], want)
-        assert got[True][1] == want_mv
-        assert np.array_equal(got[True][0], got[False][0]) and got[True][1] == got[False][1]
+        try:
+            for pd in (1, 3, 2, 0):
+                knnkm.knnkm_enable_partial_distances(ctx, pd)
+                out = torch.empty(n, dtype=torch.int32, device=DEV)
+                mv = torch.zeros(1, dtype=torch.int64, device=DEV)
+                knnkm.knn_assign(ctx, Xd, Cd, Gd, dev(lab_in), out, None, mv)
+                got[pd] = (host(out), int(host(mv)[0]))
+        finally:
+            knnkm.knnkm_enable_partial_distances(ctx, True)
+        for pd in (1, 3, 2, 0):
+            assert np.array_equal(got[pd][0], want), pd
+            assert got[pd][1] == want_mv, pd
 
 
 def test_assign_wide_near_ties(ctx):
     """Wide rows whose candidates sit at equal or nearly equal distances
     (duplicated centroids, a centroid copied with one coordinate nudged by one
-    ulp): the float64 pass and the tie rule decide as in the oracle."""
+    ulp): the float64 pass and the tie rule decide as in the oracle, with the
+    partial distances over each shadow and over the float32 rows."""
     n, d, k, kappa = 2000, 512, 64, 30
     say("assign wide ties")
     X = datagen.mixture(n, d, 16, seed=5, sigma=0.5, centre="normal")
@@ -1280,11 +1284,16 @@ def test_assign_wide_near_ties(ctx):
     G = rand_graph(n, kappa, seed=8)
     lab_in = rs.integers(0, k, n).astype(np.int32)
     want, _, want_mv = gkmeans.gk_assign(X, C, lab_in, G)
-    out = torch.empty(n, dtype=torch.int32, device=DEV)
-    mv = torch.zeros(1, dtype=torch.int64, device=DEV)
-    knnkm.knn_assign(ctx, dev(X), dev(C), dev(G), dev(lab_in), out, None, mv)
-    assert np.array_equal(host(out), want)
-    assert int(host(mv)[0]) == want_mv
+    try:
+        for pd in (1, 3, 2):
+            knnkm.knnkm_enable_partial_distances(ctx, pd)
+            out = torch.empty(n, dtype=torch.int32, device=DEV)
+            mv = torch.zeros(1, dtype=torch.int64, device=DEV)
+            knnkm.knn_assign(ctx, dev(X), dev(C), dev(G), dev(lab_in), out, None, mv)
+            assert np.array_equal(host(out), want), pd
+            assert int(host(mv)[0]) == want_mv, pd
+    finally:
+        knnkm.knnkm_enable_partial_distances(ctx, True)
 
 
 @pytest.mark.parametrize("d", [512, 320])
