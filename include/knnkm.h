@@ -236,10 +236,10 @@ knnkm_status knn_boost_fit(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d,
  * (-1 / +inf past the end of a short list).  X: n x d (leading dimension
  * ldx), G_ids: n x kappa, Q: m x d (leading dimension ldq), all device.
  * Limits: ef <= KNNKM_SEARCH_MAX_EF, max_visits <= KNNKM_SEARCH_MAX_VISITS,
- * n_entry <= KNNKM_SEARCH_MAX_ENTRY (KNNKM_EINVAL beyond).  Up to 1,920
- * visits four queries share a workgroup; above that each query holds a
- * larger table of visited points and fewer queries run at once.
- * Asynchronous. */
+ * n_entry <= KNNKM_SEARCH_MAX_ENTRY (KNNKM_EINVAL beyond).  Above 1,920
+ * visits the tables of visited points live in the context's workspace
+ * (64 KB for each query in flight: 512 MB with 256 compute units; KNNKM_ENOMEM
+ * if it cannot grow).  Asynchronous. */
 #define KNNKM_SEARCH_MAX_EF 128
 #define KNNKM_SEARCH_MAX_VISITS 7680
 #define KNNKM_SEARCH_MAX_ENTRY 16

@@ -15,10 +15,11 @@
 // Points are compared by (d2, id), d2 the squared distance summed over the
 // dimensions in order in float64 with one rounding per operation, rounded
 // once to float32 (the keys of the graph) -- each distance by one lane.
-// Points seen are kept in an open-addressing hash in LDS, filled to at most
-// about half by the visit limit: 4,096 slots (four queries per workgroup)
-// for up to 1,920 visits, else 16,384 slots (one query per workgroup, two
-// workgroups per compute unit).
+// Points seen are kept in an open-addressing hash filled to at most about
+// half by the visit limit: up to 1,920 visits 4,096 slots in LDS; above,
+// 16,384 slots in global memory, one table per resident wavefront of a
+// persistent grid (cleared per query), so that the LDS holds only the query
+// and the list and many queries run at once.
 #include <cfloat>
 #include <climits>
 
@@ -28,11 +29,12 @@ namespace {
 
 constexpr uint64_t SR_PURPOSE = 5;  // random-number stream of the entry points
 constexpr int SR_SMALL_VISITS = 1920;  // visit limit of the 4,096-slot hash
+constexpr int SR_GH_BLOCKS_PER_CU = 8;  // workgroups of four queries per compute unit (global tables)
 
-template <int HB>  // log2 of the hash slots
+template <int HB>  // log2 of the hash slots in LDS (0: the hash is elsewhere)
 struct SRWave {
   float q[KNNKM_MAX_D];
-  int32_t hash[1 << HB];
+  int32_t hash[HB ? 1 << HB : 1];
   float lk[KNNKM_SEARCH_MAX_EF];
   int32_t li[KNNKM_SEARCH_MAX_EF];
   int32_t lx[KNNKM_SEARCH_MAX_EF];
@@ -125,19 +127,30 @@ __device__ inline void sr_merge(W& sh, bool in, float ck, int ci, int ef, int& c
   x1 = lane + 64 < cnt ? sh.lx[lane + 64] : 1;
 }
 
-template <int HB, int WPB>  // hash bits, queries (wavefronts) per workgroup
+// HB: log2 of the hash slots; WPB: queries (wavefronts) per workgroup; GH:
+// the hash in global memory (vis: 2^HB slots per wavefront of the grid),
+// else in LDS.
+template <int HB, int WPB, bool GH>
 __global__ __launch_bounds__(64 * WPB) void k_graph_search(const float* __restrict__ X, int64_t n, int d,
                                                            int64_t ldx, const int32_t* __restrict__ G, int kappa,
                                                            const float* __restrict__ Q, int64_t m, int64_t ldq,
                                                            int ef, int top_k, int max_visits, int n_entry,
                                                            uint64_t seed, int32_t* __restrict__ out_ids,
-                                                           float* __restrict__ out_d2) {
-  __shared__ SRWave<HB> shw[WPB];
+                                                           float* __restrict__ out_d2, int32_t* __restrict__ vis) {
+  __shared__ SRWave<GH ? 0 : HB> shw[WPB];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  SRWave<HB>& sh = shw[w];
+  SRWave<GH ? 0 : HB>& sh = shw[w];
+  int32_t* hash = GH ? vis + (((int64_t)blockIdx.x * WPB + w) << HB) : sh.hash;
   for (int64_t qi = (int64_t)blockIdx.x * WPB + w; qi < m; qi += (int64_t)gridDim.x * WPB) {
     for (int j = lane; j < d; j += 64) sh.q[j] = Q[qi * ldq + j];
-    for (int j = lane; j < (1 << HB); j += 64) sh.hash[j] = -1;
+    if constexpr (GH) {
+      // 16-byte stores, every one complete before the first insert (the
+      // table is this wavefront's alone: a workgroup-scope release suffices)
+      for (int j = lane * 4; j < (1 << HB); j += 256) *reinterpret_cast<int4*>(hash + j) = make_int4(-1, -1, -1, -1);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    } else {
+      for (int j = lane; j < (1 << HB); j += 64) hash[j] = -1;
+    }
     // entry points (Floyd's sampling, one draw per step)
     const int ne = (int)min<int64_t>(n_entry, n);
     if (lane == 0) {
@@ -161,7 +174,7 @@ __global__ __launch_bounds__(64 * WPB) void k_graph_search(const float* __restri
       float key = FLT_MAX;
       if (in) {
         id = sh.ent[lane];
-        sr_insert<HB>(sh.hash, id);
+        sr_insert<HB>(hash, id);
         key = sr_key(sh.q, X + (int64_t)id * ldx, d);
       }
       sr_merge(sh, in, key, id, ef, cnt, k0, i0, x0, k1, i1, x1);
@@ -190,7 +203,7 @@ __global__ __launch_bounds__(64 * WPB) void k_graph_search(const float* __restri
       for (int e0 = 0; e0 < kappa; e0 += 64) {
         const int e = e0 + lane;
         const int b = e < kappa ? G[(int64_t)c * kappa + e] : -1;
-        const bool fresh = b >= 0 && b < n && sr_insert<HB>(sh.hash, b);
+        const bool fresh = b >= 0 && b < n && sr_insert<HB>(hash, b);
         visited += __popcll(__ballot(fresh));
         float key = FLT_MAX;
         if (fresh) key = sr_key(sh.q, X + (int64_t)b * ldx, d);
@@ -233,11 +246,17 @@ extern "C" knnkm_status knn_graph_search(knnkm_ctx* ctx, const float* X, int64_t
     return knnkm_fail(ctx, KNNKM_EINVAL, "knn_graph_search: n_entry not in [1, %d]", KNNKM_SEARCH_MAX_ENTRY);
   if (ctx->dry || m == 0) return KNNKM_OK;
   KNNKM_HIP(ctx, hipSetDevice(ctx->device));
-  if (max_visits <= SR_SMALL_VISITS)
-    k_graph_search<12, 4><<<grid_for(m, 4, 65536), 256, 0, ctx->stream>>>(
-        X, n, d, ldx, G_ids, kappa, Q, m, ldq, ef, top_k, max_visits, n_entry, seed, out_ids, out_d2);
-  else
-    k_graph_search<14, 1><<<grid_for(m, 1, 65536), 64, 0, ctx->stream>>>(
-        X, n, d, ldx, G_ids, kappa, Q, m, ldq, ef, top_k, max_visits, n_entry, seed, out_ids, out_d2);
+  if (max_visits <= SR_SMALL_VISITS) {
+    k_graph_search<12, 4, false><<<grid_for(m, 4, 65536), 256, 0, ctx->stream>>>(
+        X, n, d, ldx, G_ids, kappa, Q, m, ldq, ef, top_k, max_visits, n_entry, seed, out_ids, out_d2, nullptr);
+  } else {
+    // a persistent grid of SR_GH_BLOCKS_PER_CU workgroups per compute unit,
+    // one 64 KB table per wavefront
+    const int blocks = grid_for(m, 4, std::max(1, ctx->num_cus) * SR_GH_BLOCKS_PER_CU);
+    int32_t* vis = (int32_t*)knnkm_ws(ctx, "search_visited", sizeof(int32_t) * ((size_t)blocks * 4 << 14));
+    if (!vis) return KNNKM_ENOMEM;
+    k_graph_search<14, 4, true><<<blocks, 256, 0, ctx->stream>>>(
+        X, n, d, ldx, G_ids, kappa, Q, m, ldq, ef, top_k, max_visits, n_entry, seed, out_ids, out_d2, vis);
+  }
   return knnkm_check(ctx, "knn_graph_search");
 }
