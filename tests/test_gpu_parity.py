@@ -850,6 +850,66 @@ def test_fit_update_exact_at_scale(ctx):
     assert np.array_equal(runs[0][2], runs[1][2])
 
 
+def test_fit_wide_paths_agree_at_scale(ctx):
+    """A wide-row fit at a size where the second sweep moves more than n/8
+    samples (its sums are rebuilt: the fit resumes from random labels), late
+    sweeps are driven by the changed-
+    centroid bits, the graph-entry labels and the drift bounds, and the
+    centroid shadow is refreshed by every update: the same labels, centroids,
+    counts and trace with the partial distances over the 8-bit shadow, the
+    bfloat16 shadow and the float32 rows, and with them switched off (the
+    full-distance kernels, none of those paths); every centroid is the float32
+    rounding of its members' mean and the last traced distortion the Eqn. 2
+    value of the returned partition."""
+    n, d, k, kappa, T = 400_000, 512, 40_000, 50, 12
+    say("wide fit paths at scale", n, d, k, kappa, T)
+    X = datagen.mixture_device(n, d, k, 77, centre="normal", sigma=0.5, device=DEV)
+    gi = torch.empty((n, kappa), dtype=torch.int32, device=DEV)
+    gd = torch.empty((n, kappa), dtype=torch.float32, device=DEV)
+    p = knnkm.default_params(kappa=kappa, tau=2, max_iters=T, seed=77, precision=knnkm.BF16_RERANK)
+    knnkm.knn_build(ctx, X, p, gi, gd)
+    p.init = knnkm.INIT_LABELS
+    lab0 = dev(np.random.default_rng(5).integers(0, k, n).astype(np.int32))
+    res = {}
+    try:
+        for pd in (1, 3, 2, 0):
+            knnkm.knnkm_enable_partial_distances(ctx, pd)
+            lab = lab0.clone()
+            C = torch.zeros((k, d), dtype=torch.float32, device=DEV)  # kept for clusters the labels leave empty
+            cnt = torch.empty(k, dtype=torch.int32, device=DEV)
+            if pd == 1:
+                knnkm.knnkm_enable_timing(ctx, 2)  # per-sweep counts
+            tr, it = knnkm.knn_kmeans_fit(ctx, X, k, gi, p, lab, C, cnt)
+            assert it == T
+            res[pd] = (lab, C, cnt, tr)
+            if pd == 1:
+                moved = knnkm.knnkm_sweep_stats(ctx)["moved"]
+                knnkm.knnkm_enable_timing(ctx, False)
+    finally:
+        knnkm.knnkm_enable_partial_distances(ctx, True)
+        knnkm.knnkm_enable_timing(ctx, False)
+    say("moved per sweep", moved)
+    assert moved[1] > n // 8 and moved[-1] < n // 100  # the rebuilt second update and sparse late ones
+    lab, C, cnt, tr = res[1]
+    for pd in (3, 2, 0):
+        assert torch.equal(lab, res[pd][0]), pd
+        assert torch.equal(C, res[pd][1]), pd
+        assert torch.equal(cnt, res[pd][2]), pd
+        assert np.array_equal(tr, res[pd][3]), pd
+    s = torch.zeros((k, d), dtype=torch.float64, device=DEV)
+    s.index_add_(0, lab.long(), X.double())
+    c = torch.bincount(lab.long(), minlength=k)
+    assert torch.equal(c.int(), cnt)
+    nz = c > 0
+    mean = s[nz] / c[nz, None].double()
+    ulp = torch.abs(mean.float()).double() * 2.0**-23 + 2.0**-149
+    assert bool((torch.abs(C[nz].double() - mean) <= 0.5 * ulp * (1 + 1e-6)).all())
+    sxx = float((X.double() ** 2).sum())
+    e_last = (sxx - float(((s[nz] ** 2).sum(1) / c[nz].double()).sum())) / n
+    assert abs(tr[-1] - e_last) <= 1e-12 * e_last, (tr[-1], e_last)
+    assert all(tr[t + 1] <= tr[t] * (1 + 1e-12) for t in range(T))
+
+
 @pytest.mark.parametrize("n,d,k,kappa,T,early", [(20000, 32, 200, 10, 12, False), (200_003, 128, 2000, 20, 9, False),
                                                  (30002, 16, 300, 8, 15, True), (5001, 512, 60, 20, 7, False),
                                                  (777, 3, 25, 6, 10, False)])
