@@ -988,6 +988,8 @@ def main():
         "sweeps": sw,
     }
     out["autotuned_shapes"] = [ln for ln in knnkm.knnkm_autotune_table().splitlines() if ln]
+    out["workspace_gb"] = {"held": ctx.workspace_bytes() / 1e9,
+                           "planning_estimate": knnkm.knnkm_workspace_estimate(n, d, k, p) / 1e9}
     if args.boost:
         pb = knnkm.Params.from_buffer_copy(p)
         pb.max_iters = args.boost
