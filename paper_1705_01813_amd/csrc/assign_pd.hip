@@ -58,6 +58,7 @@ constexpr int pd_chunk_list() { return SK ? 128 : 64; }
 constexpr int PD_SB_FULL = 4;
 constexpr int PD_SB_LIST = 6;
 constexpr int PD_EX = 4;      // full float32 rows in flight together
+constexpr int PD_DIRECT = 4;  // at most this many candidates: full distances at once
 
 struct alignas(16) PDWave {
   float x[512];       // the sample's row
@@ -231,6 +232,13 @@ __device__ __attribute__((always_inline)) inline PDResult pd_decide(PDWave& sh, 
   // are done).  With the shadow, the survivors of the last chunk go to the
   // next list for their float32 distances; without it they have them.
   int A = A0 - np, buf = 0;
+  if (A > 0 && A <= PD_DIRECT) {
+    // few candidates left: their float32 distances in one load level in
+    // place of the chunk steps, the bracket and the survivors' rows
+    pd_exact(sh, A, [&](int e) { return sh.al[0][e + np]; }, C, d, vec_c, rel);
+    wave_lds_sync();
+    A = 0;
+  }
   for (int ch = 0; ch < nch && A > 0; ++ch) {
     const bool last = ch == nch - 1;
     const int base = ch * CHK + jj * PL;
