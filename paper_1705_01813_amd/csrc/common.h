@@ -25,8 +25,12 @@ struct knnkm_ctx {
   std::string err;
   int num_cus = 256;
   std::unordered_map<std::string, knnkm_buf> ws;  // named workspace buffers
-  // cached two-means tree metadata (depends on n and k only)
-  struct TMPlan* tm_plan = nullptr;
+  // cached two-means tree metadata (depends on the job sizes and leaf
+  // counts only): two plans, so that a build's (k0 leaves) and a fit's (k
+  // leaves) both stay; the least recently used one is replaced
+  struct TMPlan* tm_plan[2] = {nullptr, nullptr};
+  uint64_t tm_plan_used[2] = {0, 0};
+  uint64_t tm_plan_clock = 0;
   // opt-in phase timing (HIP events on the context stream)
   int timing = 0;  // 1: phases; 2: also every assignment of the fit (sweeps run eagerly)
   std::vector<hipEvent_t> ev;  // pool

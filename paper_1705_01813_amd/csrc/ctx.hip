@@ -53,8 +53,10 @@ knnkm_status knnkm_ws_release(knnkm_ctx* ctx) {
   ctx->fit_evals = nullptr;
   ctx->fit_actives = nullptr;
   ctx->fit_moved = nullptr;
-  tm_plan_free(ctx->tm_plan);  // its device tables were workspace
-  ctx->tm_plan = nullptr;
+  for (auto& pl : ctx->tm_plan) {  // their device tables were workspace
+    tm_plan_free(pl);
+    pl = nullptr;
+  }
   KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return KNNKM_OK;
 }
@@ -121,7 +123,7 @@ extern "C" knnkm_status knnkm_destroy(knnkm_ctx* ctx) {
       if (kv.second.ptr) (void)hipFreeAsync(kv.second.ptr, ctx->stream);
     (void)hipStreamSynchronize(ctx->stream);
   }
-  tm_plan_free(ctx->tm_plan);
+  for (auto* pl : ctx->tm_plan) tm_plan_free(pl);
   for (hipEvent_t e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);

@@ -89,7 +89,8 @@ struct TMPlan {
   const TMFinOp* d_fin_ops;
 };
 
-// The device tables live in the context workspace ("tm_plan").
+// The device tables live in the context workspace ("tm_plan0", "tm_plan1":
+// one buffer per cached plan).
 void tm_plan_free(TMPlan* p) { delete p; }
 
 // Tree shapes of several independent jobs (job j: rows [off_j, off_j + n_j),
@@ -280,7 +281,7 @@ static void build_plan(TMPlan& P, const std::vector<int64_t>& jn, const std::vec
   P.leaf_off.push_back((int32_t)total);
 }
 
-static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P) {
+static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P, const char* ws_name) {
   std::vector<std::pair<const void*, size_t>> parts = {
       {P.split_off.data(), P.split_off.size() * 4},   {P.split_size.data(), P.split_size.size() * 4},
       {P.split_tile_begin.data(), P.split_tile_begin.size() * 4},
@@ -306,7 +307,7 @@ static knnkm_status upload_plan(knnkm_ctx* ctx, TMPlan& P) {
     total += p.second;
   }
   total += 16;
-  P.dev = knnkm_ws(ctx, "tm_plan", total);
+  P.dev = knnkm_ws(ctx, ws_name, total);
   if (!P.dev) return KNNKM_ENOMEM;
   P.dev_bytes = total;
   std::vector<char> host(total, 0);
@@ -1126,14 +1127,20 @@ knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_
     n += jn[q];
   }
   key.push_back(ctx->tm_finish_max);
-  if (!ctx->tm_plan || ctx->tm_plan->key != key) {
+  int slot = -1;
+  for (int s = 0; s < 2; ++s)
+    if (ctx->tm_plan[s] && ctx->tm_plan[s]->key == key) slot = s;
+  if (slot < 0) {
+    slot = !ctx->tm_plan[0] ? 0 : (!ctx->tm_plan[1] ? 1 : (ctx->tm_plan_used[0] <= ctx->tm_plan_used[1] ? 0 : 1));
+    // the replaced plan's tables may still be read by queued work
     KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    tm_plan_free(ctx->tm_plan);
-    ctx->tm_plan = new TMPlan();
-    build_plan(*ctx->tm_plan, jn, jk, ctx->tm_finish_max);
-    KNNKM_TRY(upload_plan(ctx, *ctx->tm_plan));
+    tm_plan_free(ctx->tm_plan[slot]);
+    ctx->tm_plan[slot] = new TMPlan();
+    build_plan(*ctx->tm_plan[slot], jn, jk, ctx->tm_finish_max);
+    KNNKM_TRY(upload_plan(ctx, *ctx->tm_plan[slot], slot == 0 ? "tm_plan0" : "tm_plan1"));
   }
-  const TMPlan& P = *ctx->tm_plan;
+  ctx->tm_plan_used[slot] = ++ctx->tm_plan_clock;
+  const TMPlan& P = *ctx->tm_plan[slot];
   const int32_t k = P.k;
   if (d > KNNKM_MAX_D) return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "twomeans: d=%d > %d", d, KNNKM_MAX_D);
   int gL, gV;
