@@ -85,8 +85,10 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
 #pragma unroll
   for (int q = 0; q < TPW; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
   __syncthreads();
-  float4 nxt[PER];
-  auto fetch = [&](int t0) {
+  // two slices' loads in flight in registers (ra, rb) while a third is read
+  // from LDS
+  float4 ra[PER], rb[PER];
+  auto fetch = [&](float4 (&nxt)[PER], int t0) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + 256 * u;
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
       nxt[u] = v;
     }
   };
-  auto store = [&](float* buf) {
+  auto store = [&](const float4 (&nxt)[PER], float* buf) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + 256 * u;
@@ -118,15 +120,15 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
       buf[(4 * q4 + 3) * XS + r] = nxt[u].w;
     }
   };
-  fetch(0);
-  store(xs);
+  const int nsl = (d + SL - 1) / SL;  // slices
+  fetch(ra, 0);
+  store(ra, xs);
+  if (nsl > 1) fetch(ra, SL);
+  if (nsl > 2) fetch(rb, 2 * SL);
   __syncthreads();
   int cur = 0;
   const int kr = lane >> 4, rc = lane & 15;  // MFMA operands: k row, tile row or column
-  for (int t0 = 0; t0 < d; t0 += SL) {
-    const bool more = t0 + SL < d;
-    if (more) fetch(t0 + SL);
-    const float* buf = xs + cur * (SL * XS);
+  auto gram_slice = [&](const float* buf) {
 #pragma unroll
     for (int kk = 0; kk < SL; kk += 4) {
       const float* kb = buf + (kk + kr) * XS + rc;
@@ -138,7 +140,18 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
         acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
       }
     }
-    if (more) store(xs + (cur ^ 1) * (SL * XS));
+  };
+  // slice i in LDS; the next two in ra / rb, their roles alternating
+  for (int i = 0; i < nsl; i += 2) {
+    gram_slice(xs + cur * (SL * XS));
+    if (i + 1 < nsl) store(ra, xs + (cur ^ 1) * (SL * XS));
+    if (i + 3 < nsl) fetch(ra, (i + 3) * SL);
+    __syncthreads();
+    cur ^= 1;
+    if (i + 1 >= nsl) break;
+    gram_slice(xs + cur * (SL * XS));
+    if (i + 2 < nsl) store(rb, xs + (cur ^ 1) * (SL * XS));
+    if (i + 4 < nsl) fetch(rb, (i + 4) * SL);
     __syncthreads();
     cur ^= 1;
   }
