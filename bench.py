@@ -315,11 +315,17 @@ ASSIGN_SOURCES = ("assign.hip", "assign_pd.hip")  # the fit assignment kernels
 
 
 def assign_source_sha256():
+    """Key of the assignment kernels' code: the sources with // comments and
+    blank lines left out (a comment edit keeps a measured traffic valid)."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in ASSIGN_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_1705_01813_amd", "csrc", f), "rb").read())
+        for line in open(os.path.join(ROOT, "paper_1705_01813_amd", "csrc", f), encoding="utf-8"):
+            code = re.sub(r"//.*$", "", line).strip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

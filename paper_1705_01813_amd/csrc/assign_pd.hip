@@ -18,13 +18,16 @@
 //    full sweep, of the first slot (the cluster of the nearest entry holding
 //    another one, the likeliest to be the closest; in the sweeps on active
 //    sets a sample mostly stays), their loads in flight together;
-//  * the candidates advance breadth first, 64 dimensions (a chunk) at a
-//    time, GL lanes per candidate and up to 32 candidates' loads in flight
-//    per wavefront, reading the bfloat16 shadow of the centroids when there
-//    is one (half the bytes; eps bounds each shadow row's distance to the
-//    float32 row) and the float32 rows otherwise: each chunk adds to a
-//    running float32 partial sum P, and a candidate is dropped as soon as a
-//    rigorous lower bound of its squared distance over the dimensions so far,
+//  * a sample with at most PD_DIRECT candidates left takes their full
+//    float32 distances at once (one load level);
+//  * otherwise the candidates advance breadth first, a chunk of dimensions
+//    at a time (pd_chunk_full / pd_chunk_list), GL lanes per candidate and
+//    PD_SB batches of candidates' loads in flight per wavefront, reading the
+//    shadow of the centroids when there is one (8-bit codes with a step per
+//    row, or bfloat16; eps bounds each shadow row's distance to the float32
+//    row) and the float32 rows otherwise: each chunk adds to a running
+//    float32 partial sum P, and a candidate is dropped as soon as a rigorous
+//    lower bound of its squared distance over the dimensions so far,
 //    (sqrt(P (1 - rel)) - eps)^2 by the triangle inequality, exceeds ub (the
 //    candidate then cannot be the closest nor tie with it);
 //  * with the shadow, a survivor of every chunk has its distance bracketed
