@@ -273,9 +273,9 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
                        const float* cdelta = nullptr, CShadow sw = {}, const int32_t* nlab = nullptr);
 // Exact all-pairs refinement of the clusters with smin < s <= smax members
 // (smax <= 128; one block per cluster, rows of the graph updated in place).
-knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, int32_t kappa, int32_t k,
-                             const int32_t* offsets, const int32_t* members, int32_t smin, int32_t smax,
-                             bool vec, int32_t* G_ids, float* G_d2);
+knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int32_t kappa,
+                             int32_t k, const int32_t* offsets, const int32_t* members, int32_t smin,
+                             int32_t smax, bool vec, int32_t* G_ids, float* G_d2);
 // Wide rows (256 < d <= 512, kappa <= 63): one wavefront per sample with
 // early-abandoned partial distances.  list != null: the active-set sweep over
 // the listed positions (list_count entries); else a full sweep in `order`

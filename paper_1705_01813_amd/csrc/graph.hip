@@ -908,7 +908,7 @@ knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   }
   KNNKM_TRY(knnkm_check(ctx, "graph refine merge"));
   if (rb1 < RX_MAX)
-    KNNKM_TRY(ks_refine_exact(ctx, X, d, ldx, kappa, k, off, mem, rb1, RX_MAX, vec, G_ids, G_d2));
+    KNNKM_TRY(ks_refine_exact(ctx, X, n, d, ldx, kappa, k, off, mem, rb1, RX_MAX, vec, G_ids, G_d2));
 #define RF(BF, LL, VV)                                                                                    \
   return launch_refine<BF, LL, VV>(ctx, X, n, d, ldx, dpad, kappa, k, off, mem, wb, rb1, rb2, err_c, vec, \
                                    G_ids, G_d2)

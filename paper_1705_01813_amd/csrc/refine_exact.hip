@@ -36,11 +36,16 @@ __device__ inline float f32_prev(float f) { return __uint_as_float(__float_as_ui
 
 constexpr int RX_UNC_CAP = 256;  // uncertified pairs listed per cluster
 
-template <int SMAX, int SL>
+// SPLIT: the keys go to global memory (keys, row r of the cluster at
+// member position c0 + r, stride SMAX; FLT_MAX past s and on the diagonal)
+// and k_refine_rows merges them, with the occupancy the Gram's registers and
+// LDS would deny the merge; else the block merges them itself.
+template <int SMAX, int SL, bool SPLIT>
 __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X, int d, int64_t ldx, int kappa,
                                                      int32_t k, const int32_t* __restrict__ offsets,
                                                      const int32_t* __restrict__ members, int smin, int vec,
-                                                     int32_t* __restrict__ G_ids, float* __restrict__ G_d2) {
+                                                     int32_t* __restrict__ G_ids, float* __restrict__ G_d2,
+                                                     float* __restrict__ keys) {
   constexpr int TG = SMAX / 16;              // tile rows of the Gram block
   constexpr int MAXT = TG * (TG + 1) / 2;    // tiles of its upper triangle
   constexpr int TPW = (MAXT + 3) / 4;        // tiles per wavefront
@@ -226,6 +231,14 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
     }
     __syncthreads();
   }
+  if constexpr (SPLIT) {
+    float* kout = keys + (int64_t)c0 * SMAX;
+    for (int e = tid; e < s * SMAX; e += 256) {
+      const int r = e / SMAX, c = e % SMAX;
+      kout[e] = c < s && c != r ? km[r * SMAX + c] : FLT_MAX;
+    }
+    return;
+  }
   // merge: one wavefront per member; lane l holds candidates l, l + 64, ...
   // (the next member's row is loaded while one is merged)
   MergeRow cur_row = {FLT_MAX, FLT_MAX, INT32_MAX, INT32_MAX};
@@ -253,18 +266,71 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
   }
 }
 
+// The merge of k_refine_gram<SMAX, SL, true>'s keys: one block per cluster
+// of smin < s <= SMAX members, one wavefront per member row (w, w + 4, ...),
+// the next row loaded while one is merged; the same merge, in the same
+// order per row, as the fused kernel.
+template <int SMAX>
+__global__ __launch_bounds__(256) void k_refine_rows(const float* __restrict__ keys, int32_t k,
+                                                     const int32_t* __restrict__ offsets,
+                                                     const int32_t* __restrict__ members, int smin, int kappa,
+                                                     int32_t* __restrict__ G_ids, float* __restrict__ G_d2) {
+  constexpr int NC = SMAX / 64;
+  __shared__ float mks[4][2 * KNNKM_MAX_KAPPA];
+  const int cl = blockIdx.x;
+  if (cl >= k) return;
+  const int c0 = offsets[cl];
+  const int s = offsets[cl + 1] - c0;
+  if (s <= smin || s > SMAX || s < 2) return;  // block-uniform
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  float* mk = mks[w];
+  MergeRow cur_row = {FLT_MAX, FLT_MAX, INT32_MAX, INT32_MAX};
+  if (w < s) {
+    const int64_t row = (int64_t)members[c0 + w] * kappa;
+    cur_row = merge_load(G_d2 + row, G_ids + row, kappa);
+  }
+  for (int r = w; r < s; r += 4) {
+    MergeRow nxt_row = cur_row;
+    if (r + 4 < s) {
+      const int64_t row = (int64_t)members[c0 + r + 4] * kappa;
+      nxt_row = merge_load(G_d2 + row, G_ids + row, kappa);
+    }
+    float ck[NC];
+    int cid[NC];
+    bool valid[NC];
+#pragma unroll
+    for (int h = 0; h < NC; ++h) {
+      const int c = lane + 64 * h;
+      valid[h] = c < s && c != r;
+      ck[h] = valid[h] ? keys[(int64_t)(c0 + r) * SMAX + c] : FLT_MAX;
+      cid[h] = valid[h] ? members[c0 + c] : -1;
+    }
+    const int64_t row = (int64_t)members[c0 + r] * kappa;
+    merge_row<NC>(G_d2 + row, G_ids + row, kappa, cur_row, ck, cid, valid, mk,
+                  reinterpret_cast<int32_t*>(mk + KNNKM_MAX_KAPPA));
+    cur_row = nxt_row;
+  }
+}
+
 }  // namespace
 
-knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int32_t d, int64_t ldx, int32_t kappa, int32_t k,
-                             const int32_t* offsets, const int32_t* members, int32_t smin, int32_t smax,
-                             bool vec, int32_t* G_ids, float* G_d2) {
+knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int32_t kappa,
+                             int32_t k, const int32_t* offsets, const int32_t* members, int32_t smin,
+                             int32_t smax, bool vec, int32_t* G_ids, float* G_d2) {
   if (smax > 128) return knnkm_fail(ctx, KNNKM_EINVAL, "refine_exact: clusters of at most 128 members");
   if (k <= 0 || smin >= smax) return KNNKM_OK;
   if (smin < 64)
-    k_refine_gram<64, 32><<<(unsigned)k, 256, 0, ctx->stream>>>(X, d, ldx, kappa, k, offsets, members, smin,
-                                                             vec ? 1 : 0, G_ids, G_d2);
-  if (smax > 64)
-    k_refine_gram<128, 8><<<(unsigned)k, 256, 0, ctx->stream>>>(X, d, ldx, kappa, k, offsets, members,
-                                                              std::max(smin, 64), vec ? 1 : 0, G_ids, G_d2);
+    k_refine_gram<64, 32, false><<<(unsigned)k, 256, 0, ctx->stream>>>(X, d, ldx, kappa, k, offsets, members, smin,
+                                                                    vec ? 1 : 0, G_ids, G_d2, nullptr);
+  if (smax > 64) {
+    // keys of every member row at stride 128 (a cluster's rows at its member
+    // positions), then the merge
+    float* keys = (float*)knnkm_ws(ctx, "rx_keys", sizeof(float) * (size_t)n * 128);
+    if (!keys) return KNNKM_ENOMEM;
+    const int s0 = std::max(smin, 64);
+    k_refine_gram<128, 8, true><<<(unsigned)k, 256, 0, ctx->stream>>>(X, d, ldx, kappa, k, offsets, members, s0,
+                                                                    vec ? 1 : 0, G_ids, G_d2, keys);
+    k_refine_rows<128><<<(unsigned)k, 256, 0, ctx->stream>>>(keys, k, offsets, members, s0, kappa, G_ids, G_d2);
+  }
   return knnkm_check(ctx, "graph refine (exact, mid-sized clusters)");
 }
