@@ -60,6 +60,7 @@ int64_t ws_estimate(int64_t n, int64_t d, int64_t k, int64_t k0, int64_t kappa, 
   b += 4 * (kappa + 1) * n + 4 * n + 8 * n;  // fit: reverse graph lists, active list, flag arrays
   b += 4 * (kappa + 2) * n + 4 * k;          // fit: drift bounds (wide rows)
   b += 4 * kappa * n + k / 8;                // fit: graph-entry labels, changed-cluster flag bits
+  b += 4 * 128 * n;                          // refinement: key rows of the 65-128-member clusters
   b += 2 * d * (k + k0) + 4 * (k + k0);      // bfloat16 centroid shadows (wide rows)
   b += 64 * m + 16 * (T + 1) * m;            // job tables and traces
   b += 1 << 20;                              // scans, partial sums, small tables
