@@ -30,6 +30,7 @@
 //   and its cluster, independent of the order in which pairs are examined.
 #include <cfloat>
 
+#include "merge.h"
 #include "rowgroup.h"
 
 // ------------------------------------------------------------- graph init --
@@ -404,52 +405,12 @@ __global__ __launch_bounds__(512) void k_refine_tile(const float* __restrict__ X
     for (int r = w; r < nrows; r += 8) {
       float* rowk = rk + r * kappa;
       int32_t* rowi = ri + r * kappa;
-      const float ck = lane < RB ? km[r * RB + lane] : FLT_MAX;
-      if (!__ballot(ck < FLT_MAX)) continue;  // no survivor for this row
-      const int cid = lane < RB ? ids_j[lane] : -1;
-      const float e0k = lane < kappa ? rowk[lane] : FLT_MAX;
-      const int e0i = lane < kappa ? rowi[lane] : INT32_MAX;
-      const float e1k = lane + 64 < kappa ? rowk[lane + 64] : FLT_MAX;
-      const int e1i = lane + 64 < kappa ? rowi[lane + 64] : INT32_MAX;
-      bool valid = ck < FLT_MAX;
-      for (int q = 0; q < kappa; ++q) {
-        const int qi = q < 64 ? __builtin_amdgcn_readlane(e0i, q) : __builtin_amdgcn_readlane(e1i, q - 64);
-        valid = valid && qi != cid;  // a visited pair is already in the row
-      }
-      uint64_t M = __ballot(valid);
-      if (!M) continue;
-      int pos_c = 0, add0 = 0, add1 = 0;
-      for (int q = 0; q < kappa; ++q) {
-        const float qk = q < 64 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e0k), q))
-                                : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e1k), q - 64));
-        const int qi = q < 64 ? __builtin_amdgcn_readlane(e0i, q) : __builtin_amdgcn_readlane(e1i, q - 64);
-        pos_c += key_lt(qk, qi, ck, cid) ? 1 : 0;
-      }
-      while (M) {
-        const int q = (int)__builtin_ctzll(M);
-        M &= M - 1;
-        const float qk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ck), q));
-        const int qi = __builtin_amdgcn_readlane(cid, q);
-        pos_c += key_lt(qk, qi, ck, cid) ? 1 : 0;
-        add0 += key_lt(qk, qi, e0k, e0i) ? 1 : 0;
-        add1 += key_lt(qk, qi, e1k, e1i) ? 1 : 0;
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (lane < kappa && lane + add0 < kappa) {
-        rowk[lane + add0] = e0k;
-        rowi[lane + add0] = e0i;
-        if (lane + add0 == kappa - 1) thr[r] = e0k;
-      }
-      if (lane + 64 < kappa && lane + 64 + add1 < kappa) {
-        rowk[lane + 64 + add1] = e1k;
-        rowi[lane + 64 + add1] = e1i;
-        if (lane + 64 + add1 == kappa - 1) thr[r] = e1k;
-      }
-      if (valid && pos_c < kappa) {
-        rowk[pos_c] = ck;
-        rowi[pos_c] = cid;
-        if (pos_c == kappa - 1) thr[r] = ck;
-      }
+      const float ck[1] = {lane < RB ? km[r * RB + lane] : FLT_MAX};
+      if (!__ballot(ck[0] < FLT_MAX)) continue;  // no survivor for this row
+      const int cid[1] = {lane < RB ? ids_j[lane] : -1};
+      const bool valid[1] = {ck[0] < FLT_MAX};
+      const MergeRow old = merge_load(rowk, rowi, kappa);
+      merge_row<1>(rowk, rowi, kappa, old, ck, cid, valid, thr + r);
       __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();

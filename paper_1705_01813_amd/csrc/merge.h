@@ -3,21 +3,41 @@
 // members of its cluster with their exact keys) whose ids it does not hold
 // yet (a pair already in the row was visited).
 //
-// Lane l holds candidate slots l, l + 64, ... (NC of them).  Only candidates
-// that come before the row's kappa-th entry can enter, so a row none of whose
-// candidates does is left as it is after one comparison per slot (the
-// kappa-th entry read from the lane holding it).  Otherwise the old row is
-// staged in LDS; each entering candidate finds its position
-// among the old entries by binary search and looks for its id among all of
-// them (a row passed in by the caller may hold any keys, so the search does
-// not rely on where its key would put the id); the entering candidates are
-// then ranked among themselves and the old entries shifted.
+// Lane l holds the row's entries l and l + 64 and candidate slots l, l + 64,
+// ... (NC of them).  Every (d2, id) is compared as one 64-bit integer whose
+// order is that of (d2, id) (mg_key).  Only candidates that come before the
+// row's kappa-th entry can enter, so a row none of whose candidates does is
+// left as it is after one comparison per slot.  Otherwise the entering
+// candidates are taken one at a time (broadcast from their lane): first the
+// visited ones are dropped (their id matched against every entry), then each
+// remaining one counts, in one pass, the old entries and the other entering
+// candidates before it (its position) and adds itself to the shift of every
+// old entry after it.  The row's old entries are in ascending (d2, id) order
+// (the graph's invariant), so these counts are the positions in the merged
+// row.
 #pragma once
 #include <cfloat>
+#include <cstdint>
 
 #include "common.h"
 
 __device__ inline bool mg_lt(float ka, int ia, float kb, int ib) { return ka < kb || (ka == kb && ia < ib); }
+
+// 64-bit key ordered as (d2, id) under mg_lt for every d2 that is not NaN:
+// the float's bits made monotone (negative values complemented, the sign bit
+// set on the others, -0 taken as +0) above the id with its sign bit flipped.
+__device__ inline uint64_t mg_key(float k, int id) {
+  uint32_t b = __float_as_uint(k);
+  if (b == 0x80000000u) b = 0u;
+  b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return ((uint64_t)b << 32) | (uint32_t)(id ^ (int)0x80000000);
+}
+
+__device__ inline uint64_t mg_readlane(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
 
 // The old entries of a row as the lanes hold them: lane l has entries l and
 // l + 64 (FLT_MAX / INT32_MAX past kappa).  Loaded by the caller, so that the
@@ -37,59 +57,45 @@ __device__ inline MergeRow merge_load(const float* __restrict__ rowk, const int3
   return m;
 }
 
-// rowk/rowi: the row (global memory), read and written by this wavefront
-// only; old: its entries (merge_load).  sk/si: LDS scratch of kappa floats
-// and ints for this wavefront.
+// rowk/rowi: the row (global memory or LDS), read and written by this
+// wavefront only; old: its entries (merge_load).  Candidate ids are
+// non-negative and below INT32_MAX where valid.  kth (optional): receives
+// the row's new kappa-th key when the row changes.
 template <int NC>
 __device__ inline void merge_row(float* __restrict__ rowk, int32_t* __restrict__ rowi, int kappa, const MergeRow& old,
                                  const float (&ck)[NC], const int (&cid)[NC], const bool (&valid)[NC],
-                                 float* __restrict__ sk, int32_t* __restrict__ si) {
+                                 float* kth = nullptr) {
   const int lane = threadIdx.x & 63;
-  const float e0k = old.e0k, e1k = old.e1k;
-  const int e0i = old.e0i, e1i = old.e1i;
+  const bool two = kappa > 64;  // wave-uniform: entries past 64 in use
+  const uint64_t o0 = mg_key(old.e0k, old.e0i);
+  const uint64_t o1 = two ? mg_key(old.e1k, old.e1i) : ~0ull;
   // the kappa-th entry, from the lane that holds it
-  const int tl = (kappa - 1) & 63;
-  const bool hi_half = kappa > 64;
-  const float tk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hi_half ? e1k : e0k), tl));
-  const int tid_ = __builtin_amdgcn_readlane(hi_half ? e1i : e0i, tl);
+  const uint64_t tk = mg_readlane(two ? o1 : o0, (kappa - 1) & 63);
+  uint64_t cq[NC];
   bool enter[NC];
   bool any = false;
 #pragma unroll
   for (int h = 0; h < NC; ++h) {
-    enter[h] = valid[h] && mg_lt(ck[h], cid[h], tk, tid_);
+    cq[h] = mg_key(ck[h], cid[h]);
+    enter[h] = valid[h] && cq[h] < tk;
     any = any || enter[h];
   }
   if (__ballot(any) == 0) return;  // nothing can enter: the row stays
-  if (lane < kappa) {
-    sk[lane] = e0k;
-    si[lane] = e0i;
+  // visited: the candidate's id is already in the row
+#pragma unroll
+  for (int g = 0; g < NC; ++g) {
+    uint64_t M = __ballot(enter[g]);
+    while (M) {
+      const int b = (int)__builtin_ctzll(M);
+      M &= M - 1;
+      const int qi = __builtin_amdgcn_readlane(cid[g], b);
+      if (__ballot(old.e0i == qi || (two && old.e1i == qi)) != 0 && lane == b) enter[g] = false;
+    }
   }
-  if (lane + 64 < kappa) {
-    sk[lane + 64] = e1k;
-    si[lane + 64] = e1i;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  // positions of the entering candidates, shifts of the old entries
   int pos[NC];
 #pragma unroll
-  for (int h = 0; h < NC; ++h) {
-    pos[h] = 0;
-    if (!enter[h]) continue;
-    // entries before (ck, cid): the first q with !(entry_q < cand)
-    int lo = 0, hi = kappa;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (mg_lt(sk[mid], si[mid], ck[h], cid[h])) lo = mid + 1; else hi = mid;
-    }
-    pos[h] = lo;
-  }
-  // visited: the id is already in the row (uniform LDS addresses: broadcast)
-  for (int q = 0; q < kappa; ++q) {
-    const int qi = si[q];
-#pragma unroll
-    for (int h = 0; h < NC; ++h) enter[h] = enter[h] && qi != cid[h];
-  }
-  // ranks among the entering candidates, shifts of the old entries
+  for (int h = 0; h < NC; ++h) pos[h] = 0;
   int add0 = 0, add1 = 0;
   bool anyin = false;
 #pragma unroll
@@ -99,28 +105,34 @@ __device__ inline void merge_row(float* __restrict__ rowk, int32_t* __restrict__
     while (M) {
       const int b = (int)__builtin_ctzll(M);
       M &= M - 1;
-      const float qk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ck[g]), b));
-      const int qi = __builtin_amdgcn_readlane(cid[g], b);
+      const uint64_t q = mg_readlane(cq[g], b);
 #pragma unroll
-      for (int h = 0; h < NC; ++h) pos[h] += mg_lt(qk, qi, ck[h], cid[h]) ? 1 : 0;
-      add0 += mg_lt(qk, qi, e0k, e0i) ? 1 : 0;
-      add1 += mg_lt(qk, qi, e1k, e1i) ? 1 : 0;
+      for (int h = 0; h < NC; ++h) pos[h] += q < cq[h] ? 1 : 0;
+      add0 += q < o0 ? 1 : 0;
+      int before = __builtin_popcountll(__ballot(o0 < q));
+      if (two) {
+        add1 += q < o1 ? 1 : 0;
+        before += __builtin_popcountll(__ballot(o1 < q));
+      }
+      if (lane == b) pos[g] += before;
     }
   }
   if (!anyin) return;  // wave-uniform: every entering candidate was visited
-  // every lane has read the row before any lane writes it
   if (lane < kappa && lane + add0 < kappa) {
-    rowk[lane + add0] = e0k;
-    rowi[lane + add0] = e0i;
+    rowk[lane + add0] = old.e0k;
+    rowi[lane + add0] = old.e0i;
+    if (kth && lane + add0 == kappa - 1) *kth = old.e0k;
   }
-  if (lane + 64 < kappa && lane + 64 + add1 < kappa) {
-    rowk[lane + 64 + add1] = e1k;
-    rowi[lane + 64 + add1] = e1i;
+  if (two && lane + 64 < kappa && lane + 64 + add1 < kappa) {
+    rowk[lane + 64 + add1] = old.e1k;
+    rowi[lane + 64 + add1] = old.e1i;
+    if (kth && lane + 64 + add1 == kappa - 1) *kth = old.e1k;
   }
 #pragma unroll
   for (int h = 0; h < NC; ++h)
     if (enter[h] && pos[h] < kappa) {
       rowk[pos[h]] = ck[h];
       rowi[pos[h]] = cid[h];
+      if (kth && pos[h] == kappa - 1) *kth = ck[h];
     }
 }

@@ -55,7 +55,6 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
   // slice row stride: the four k rows an MFMA operand read touches start 16
   // banks apart
   constexpr int XS = SMAX + 16;
-  static_assert(2 * SL * XS >= 8 * KNNKM_MAX_KAPPA, "merge scratch reuses the slice buffers");
   __shared__ __align__(16) float xs[2 * SL * XS];  // two slices, dimension-major
   __shared__ float km[SMAX * SMAX];                  // keys
   __shared__ double nrm[SMAX];                       // diagonal of the Gram block
@@ -258,42 +257,52 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
       cid[h] = valid[h] ? ids[c] : -1;
     }
     const int64_t row = (int64_t)ids[r] * kappa;
-    // merge scratch: this wavefront's part of the slice buffers, free now
-    float* mk = xs + 2 * KNNKM_MAX_KAPPA * w;
-    merge_row<NC>(G_d2 + row, G_ids + row, kappa, cur_row, ck, cid, valid, mk,
-                  reinterpret_cast<int32_t*>(mk + KNNKM_MAX_KAPPA));
+    merge_row<NC>(G_d2 + row, G_ids + row, kappa, cur_row, ck, cid, valid);
     cur_row = nxt_row;
   }
 }
 
 // The merge of k_refine_gram<SMAX, SL, true>'s keys: one block per cluster
 // of smin < s <= SMAX members, one wavefront per member row (w, w + 4, ...),
-// the next row loaded while one is merged; the same merge, in the same
-// order per row, as the fused kernel.
+// the next row's entries and keys loaded while one is merged; the same
+// merge, in the same order per row, as the fused kernel.
 template <int SMAX>
 __global__ __launch_bounds__(256) void k_refine_rows(const float* __restrict__ keys, int32_t k,
                                                      const int32_t* __restrict__ offsets,
                                                      const int32_t* __restrict__ members, int smin, int kappa,
                                                      int32_t* __restrict__ G_ids, float* __restrict__ G_d2) {
   constexpr int NC = SMAX / 64;
-  __shared__ float mks[4][2 * KNNKM_MAX_KAPPA];
   const int cl = blockIdx.x;
   if (cl >= k) return;
   const int c0 = offsets[cl];
   const int s = offsets[cl + 1] - c0;
   if (s <= smin || s > SMAX || s < 2) return;  // block-uniform
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  float* mk = mks[w];
+  // the cluster's member ids, candidate slot h of this lane
+  int mid[NC];
+#pragma unroll
+  for (int h = 0; h < NC; ++h) mid[h] = lane + 64 * h < s ? members[c0 + lane + 64 * h] : -1;
+  // keys of row r (FLT_MAX past s and on the diagonal, as stored)
+  auto load_keys = [&](int r, float (&out)[NC]) {
+#pragma unroll
+    for (int h = 0; h < NC; ++h) out[h] = keys[(int64_t)(c0 + r) * SMAX + lane + 64 * h];
+  };
   MergeRow cur_row = {FLT_MAX, FLT_MAX, INT32_MAX, INT32_MAX};
+  float cur_k[NC];
   if (w < s) {
     const int64_t row = (int64_t)members[c0 + w] * kappa;
     cur_row = merge_load(G_d2 + row, G_ids + row, kappa);
+    load_keys(w, cur_k);
   }
   for (int r = w; r < s; r += 4) {
     MergeRow nxt_row = cur_row;
+    float nxt_k[NC];
+#pragma unroll
+    for (int h = 0; h < NC; ++h) nxt_k[h] = cur_k[h];
     if (r + 4 < s) {
       const int64_t row = (int64_t)members[c0 + r + 4] * kappa;
       nxt_row = merge_load(G_d2 + row, G_ids + row, kappa);
+      load_keys(r + 4, nxt_k);
     }
     float ck[NC];
     int cid[NC];
@@ -302,13 +311,14 @@ __global__ __launch_bounds__(256) void k_refine_rows(const float* __restrict__ k
     for (int h = 0; h < NC; ++h) {
       const int c = lane + 64 * h;
       valid[h] = c < s && c != r;
-      ck[h] = valid[h] ? keys[(int64_t)(c0 + r) * SMAX + c] : FLT_MAX;
-      cid[h] = valid[h] ? members[c0 + c] : -1;
+      ck[h] = valid[h] ? cur_k[h] : FLT_MAX;
+      cid[h] = valid[h] ? mid[h] : -1;
     }
     const int64_t row = (int64_t)members[c0 + r] * kappa;
-    merge_row<NC>(G_d2 + row, G_ids + row, kappa, cur_row, ck, cid, valid, mk,
-                  reinterpret_cast<int32_t*>(mk + KNNKM_MAX_KAPPA));
+    merge_row<NC>(G_d2 + row, G_ids + row, kappa, cur_row, ck, cid, valid);
     cur_row = nxt_row;
+#pragma unroll
+    for (int h = 0; h < NC; ++h) cur_k[h] = nxt_k[h];
   }
 }
 
