@@ -163,10 +163,11 @@ __device__ inline bool key_lt(float ka, int ia, float kb, int ib) {
 //   xi [RB][ld] float rows, xj [RB][ld] (the same region when `single`),
 //   km [RB][RB] float exact keys, ni/nj/thr [RB] float, ids_i/ids_j [RB] int,
 //   pcount [4] int, plist [RB*RB] uint16 survivors, rk/ri [RB][kappa] the
-//   graph rows of the block (float keys, int ids).
+//   graph rows of the block (float keys, int ids), mh [8][MG_SLOTS] int the
+//   merge's id tables (one per wavefront).
 struct TileLayout {
   int ld;
-  size_t xi, xj, km, ni, nj, thr, ids_i, ids_j, pcount, plist, rk, ri, bytes;
+  size_t xi, xj, km, ni, nj, thr, ids_i, ids_j, pcount, plist, rk, ri, mh, bytes;
   __host__ __device__ TileLayout(int RB, int dpad, bool single, int kappa) {
     ld = dpad + 4;  // 16-byte aligned rows
     const size_t rows = (size_t)RB * ld * 4;
@@ -196,6 +197,8 @@ struct TileLayout {
     at += (size_t)RB * kappa * 4;
     ri = at;
     at += (size_t)RB * kappa * 4;
+    mh = at;
+    at += (size_t)8 * MG_SLOTS * 4;
     bytes = at;
   }
 };
@@ -285,6 +288,7 @@ __global__ __launch_bounds__(512) void k_refine_tile(const float* __restrict__ X
   int32_t* ids_j = (int32_t*)(smem + lay.ids_j);
   int32_t* pcount = (int32_t*)(smem + lay.pcount);
   uint16_t* plist = (uint16_t*)(smem + lay.plist);
+  int32_t* mh = (int32_t*)(smem + lay.mh);
 
   int cl, i0, s;
   if (SINGLE) {
@@ -316,6 +320,7 @@ __global__ __launch_bounds__(512) void k_refine_tile(const float* __restrict__ X
     thr[tid] = tid < nrows ? G_d2[(int64_t)id * kappa + kappa - 1] : -FLT_MAX;
   }
   stage_rows<RB>(xi, ld, X, ldx, members, c0, i0, nrows, d, dpad, vec);
+  for (int e = tid; e < 8 * MG_SLOTS; e += 512) mh[e] = -1;
   for (int e = tid; e < nrows * kappa; e += 512) {
     const int r = e / kappa, q = e % kappa;
     const int64_t g = (int64_t)members[c0 + i0 + r] * kappa + q;
@@ -410,7 +415,7 @@ __global__ __launch_bounds__(512) void k_refine_tile(const float* __restrict__ X
       const int cid[1] = {lane < RB ? ids_j[lane] : -1};
       const bool valid[1] = {ck[0] < FLT_MAX};
       const MergeRow old = merge_load(rowk, rowi, kappa);
-      merge_row<1>(rowk, rowi, kappa, old, ck, cid, valid, thr + r);
+      merge_row<1>(rowk, rowi, kappa, old, ck, cid, valid, mh + MG_SLOTS * w, thr + r);
       __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();

@@ -7,12 +7,13 @@
 // ... (NC of them).  Every (d2, id) is compared as one 64-bit integer whose
 // order is that of (d2, id) (mg_key).  Only candidates that come before the
 // row's kappa-th entry can enter, so a row none of whose candidates does is
-// left as it is after one comparison per slot.  Otherwise the entering
-// candidates are taken one at a time (broadcast from their lane): first the
-// visited ones are dropped (their id matched against every entry), then each
-// remaining one counts, in one pass, the old entries and the other entering
-// candidates before it (its position) and adds itself to the shift of every
-// old entry after it.  The row's old entries are in ascending (d2, id) order
+// left as it is after one comparison per slot.  Otherwise the visited
+// entering candidates are dropped in parallel -- the row's ids go into a
+// small open-addressing table in LDS, one per wavefront, which every
+// entering candidate probes for its id -- and the remaining ones are taken
+// one at a time (broadcast from their lane): each counts, in one pass, the
+// old entries and the other entering candidates before it (its position)
+// and adds itself to the shift of every old entry after it.  The row's old entries are in ascending (d2, id) order
 // (the graph's invariant), so these counts are the positions in the merged
 // row.
 #pragma once
@@ -31,6 +32,35 @@ __device__ inline uint64_t mg_key(float k, int id) {
   if (b == 0x80000000u) b = 0u;
   b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
   return ((uint64_t)b << 32) | (uint32_t)(id ^ (int)0x80000000);
+}
+
+// Per-wavefront id table: MG_SLOTS entries, -1 when empty (the caller fills
+// it with -1 once; merge_row leaves it empty).  At most KNNKM_MAX_KAPPA ids
+// are in it at a time, so a probe meets an empty slot; the loops are bounded
+// by the table size all the same.
+#define MG_SLOTS 256
+static_assert(MG_SLOTS >= 2 * KNNKM_MAX_KAPPA, "id table at most half full");
+
+__device__ inline int mg_slot(int id) { return (int)(((uint32_t)id * 2654435761u) >> 24) & (MG_SLOTS - 1); }
+
+__device__ inline int mg_insert(int32_t* hs, int id) {
+  int s = mg_slot(id);
+  for (int t = 0; t < MG_SLOTS; ++t) {
+    if (atomicCAS(&hs[s], -1, id) == -1) return s;
+    s = (s + 1) & (MG_SLOTS - 1);
+  }
+  return -1;
+}
+
+__device__ inline bool mg_has(const int32_t* hs, int id) {
+  int s = mg_slot(id);
+  for (int t = 0; t < MG_SLOTS; ++t) {
+    const int v = hs[s];
+    if (v == id) return true;
+    if (v == -1) return false;
+    s = (s + 1) & (MG_SLOTS - 1);
+  }
+  return false;
 }
 
 __device__ inline uint64_t mg_readlane(uint64_t v, int l) {
@@ -59,12 +89,13 @@ __device__ inline MergeRow merge_load(const float* __restrict__ rowk, const int3
 
 // rowk/rowi: the row (global memory or LDS), read and written by this
 // wavefront only; old: its entries (merge_load).  Candidate ids are
-// non-negative and below INT32_MAX where valid.  kth (optional): receives
-// the row's new kappa-th key when the row changes.
+// non-negative and below INT32_MAX where valid.  hs: this wavefront's id
+// table (LDS, MG_SLOTS entries, empty).  kth (optional): receives the row's
+// new kappa-th key when the row changes.
 template <int NC>
 __device__ inline void merge_row(float* __restrict__ rowk, int32_t* __restrict__ rowi, int kappa, const MergeRow& old,
                                  const float (&ck)[NC], const int (&cid)[NC], const bool (&valid)[NC],
-                                 float* kth = nullptr) {
+                                 int32_t* __restrict__ hs, float* kth = nullptr) {
   const int lane = threadIdx.x & 63;
   const bool two = kappa > 64;  // wave-uniform: entries past 64 in use
   const uint64_t o0 = mg_key(old.e0k, old.e0i);
@@ -82,16 +113,17 @@ __device__ inline void merge_row(float* __restrict__ rowk, int32_t* __restrict__
   }
   if (__ballot(any) == 0) return;  // nothing can enter: the row stays
   // visited: the candidate's id is already in the row
+  const int s0 = lane < kappa ? mg_insert(hs, old.e0i) : -1;
+  const int s1 = two && lane + 64 < kappa ? mg_insert(hs, old.e1i) : -1;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
-  for (int g = 0; g < NC; ++g) {
-    uint64_t M = __ballot(enter[g]);
-    while (M) {
-      const int b = (int)__builtin_ctzll(M);
-      M &= M - 1;
-      const int qi = __builtin_amdgcn_readlane(cid[g], b);
-      if (__ballot(old.e0i == qi || (two && old.e1i == qi)) != 0 && lane == b) enter[g] = false;
-    }
-  }
+  for (int h = 0; h < NC; ++h)
+    if (enter[h] && mg_has(hs, cid[h])) enter[h] = false;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (s0 >= 0) hs[s0] = -1;
+  if (s1 >= 0) hs[s1] = -1;
   // positions of the entering candidates, shifts of the old entries
   int pos[NC];
 #pragma unroll

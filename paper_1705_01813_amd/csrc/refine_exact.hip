@@ -239,7 +239,11 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
     return;
   }
   // merge: one wavefront per member; lane l holds candidates l, l + 64, ...
-  // (the next member's row is loaded while one is merged)
+  // (the next member's row is loaded while one is merged); the id tables in
+  // the slice buffers, free now
+  static_assert(2 * SL * XS >= 4 * MG_SLOTS, "id tables fit in the slice buffers");
+  int32_t* hs = reinterpret_cast<int32_t*>(xs) + MG_SLOTS * w;
+  for (int e = lane; e < MG_SLOTS; e += 64) hs[e] = -1;
   MergeRow cur_row = {FLT_MAX, FLT_MAX, INT32_MAX, INT32_MAX};
   if (w < s) cur_row = merge_load(G_d2 + (int64_t)ids[w] * kappa, G_ids + (int64_t)ids[w] * kappa, kappa);
   for (int r = w; r < s; r += 4) {
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
       cid[h] = valid[h] ? ids[c] : -1;
     }
     const int64_t row = (int64_t)ids[r] * kappa;
-    merge_row<NC>(G_d2 + row, G_ids + row, kappa, cur_row, ck, cid, valid);
+    merge_row<NC>(G_d2 + row, G_ids + row, kappa, cur_row, ck, cid, valid, hs);
     cur_row = nxt_row;
   }
 }
@@ -278,6 +282,9 @@ __global__ __launch_bounds__(256) void k_refine_rows(const float* __restrict__ k
   const int s = offsets[cl + 1] - c0;
   if (s <= smin || s > SMAX || s < 2) return;  // block-uniform
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ int32_t mgh[4][MG_SLOTS];
+  int32_t* hs = mgh[w];
+  for (int e = lane; e < MG_SLOTS; e += 64) hs[e] = -1;
   // the cluster's member ids, candidate slot h of this lane
   int mid[NC];
 #pragma unroll
@@ -315,7 +322,7 @@ __global__ __launch_bounds__(256) void k_refine_rows(const float* __restrict__ k
       cid[h] = valid[h] ? mid[h] : -1;
     }
     const int64_t row = (int64_t)members[c0 + r] * kappa;
-    merge_row<NC>(G_d2 + row, G_ids + row, kappa, cur_row, ck, cid, valid);
+    merge_row<NC>(G_d2 + row, G_ids + row, kappa, cur_row, ck, cid, valid, hs);
     cur_row = nxt_row;
 #pragma unroll
     for (int h = 0; h < NC; ++h) cur_k[h] = nxt_k[h];
