@@ -37,9 +37,10 @@ __device__ inline float f32_prev(float f) { return __uint_as_float(__float_as_ui
 constexpr int RX_UNC_CAP = 256;  // uncertified pairs listed per cluster
 
 // SPLIT: the keys go to global memory (keys, row r of the cluster at
-// member position c0 + r, stride SMAX; FLT_MAX past s and on the diagonal)
-// and k_refine_rows merges them, with the occupancy the Gram's registers and
-// LDS would deny the merge; else the block merges them itself.
+// member position c0 + r, stride SMAX; columns s and beyond and the diagonal
+// are left unwritten) and k_refine_rows merges them, with the occupancy the
+// Gram's registers would deny the merge; the block then needs no key block
+// in LDS.  Else the block merges them itself.
 template <int SMAX, int SL, bool SPLIT>
 __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X, int d, int64_t ldx, int kappa,
                                                      int32_t k, const int32_t* __restrict__ offsets,
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
   // banks apart
   constexpr int XS = SMAX + 16;
   __shared__ __align__(16) float xs[2 * SL * XS];  // two slices, dimension-major
-  __shared__ float km[SMAX * SMAX];                  // keys
+  __shared__ float km[SPLIT ? 1 : SMAX * SMAX];      // keys (in global memory with SPLIT)
   __shared__ double nrm[SMAX];                       // diagonal of the Gram block
   __shared__ int32_t ids[SMAX];
   __shared__ int nunc;                 // uncertified pairs
@@ -172,6 +173,20 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
   // (float64 Gram expansion over K summed products): at most
   // (2K + 16) 2^-53 (G_ii + G_jj).
   const double gam = (2.0 * (double)((d + SL - 1) / SL * SL) + 16.0) * 0x1p-53;
+  // f: the float32 rounding of d2 from the Gram entry g; true when certified
+  auto certify = [&](double g, int r, int c, float& f) {
+    const double nn = nrm[r] + nrm[c];
+    const double D = nn - 2.0 * g;
+    const double E = gam * nn + 1e-300;
+    f = (float)D;
+    bool ok = D - E > 0.0 && f > 0.f && f < FLT_MAX;
+    if (ok) {
+      const double lo = 0.5 * ((double)f32_prev(f) + (double)f);
+      const double hi = 0.5 * ((double)f + (double)f32_next(f));
+      ok = D - E > lo && D + E < hi;
+    }
+    return ok;
+  };
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
     if (ti[q] < 0) continue;
@@ -179,18 +194,12 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * ti[q] + kr + 4 * v, c = 16 * tj[q] + rc;
       if (r < c && c < s) {
-        const double nn = nrm[r] + nrm[c];
-        const double D = nn - 2.0 * acc[q][v];
-        const double E = gam * nn + 1e-300;
-        const float f = (float)D;
-        bool ok = D - E > 0.0 && f > 0.f && f < FLT_MAX;
-        if (ok) {
-          const double lo = 0.5 * ((double)f32_prev(f) + (double)f);
-          const double hi = 0.5 * ((double)f + (double)f32_next(f));
-          ok = D - E > lo && D + E < hi;
+        float f;
+        const bool ok = certify(acc[q][v], r, c, f);
+        if constexpr (!SPLIT) {
+          km[r * SMAX + c] = f;
+          km[c * SMAX + r] = f;
         }
-        km[r * SMAX + c] = f;
-        km[c * SMAX + r] = f;
         if (!ok) {
           const int u = atomicAdd(&nunc, 1);
           if (u < RX_UNC_CAP) unc[u] = (int16_t)(r * SMAX + c);
@@ -199,10 +208,30 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
     }
   }
   __syncthreads();
+  const int nu = nunc;  // block-uniform
+  // SPLIT: every key is written to global memory once -- the certified ones
+  // here (none when every pair is recomputed below), the others below
+  float* kout = SPLIT ? keys + (int64_t)c0 * SMAX : nullptr;
+  if constexpr (SPLIT) {
+    if (nu <= RX_UNC_CAP) {
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        if (ti[q] < 0) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * ti[q] + kr + 4 * v, c = 16 * tj[q] + rc;
+          float f;
+          if (r < c && c < s && certify(acc[q][v], r, c, f)) {
+            kout[r * SMAX + c] = f;
+            kout[c * SMAX + r] = f;
+          }
+        }
+      }
+    }
+  }
   // uncertified pairs: float64 direct difference of the two rows, one
   // wavefront per pair (lane j: dimensions j, j + 64, ...; fixed order).
   // Past the list's capacity every pair of the cluster is recomputed.
-  const int nu = nunc;  // block-uniform
   if (nu > 0) {
     const int np = nu <= RX_UNC_CAP ? nu : s * s;
     for (int p = w; p < np; p += 4) {
@@ -224,20 +253,18 @@ __global__ __launch_bounds__(256) void k_refine_gram(const float* __restrict__ X
       }
       a = wave_sum(a);
       if (lane == 0) {
-        km[pr * SMAX + pc] = (float)a;
-        km[pc * SMAX + pr] = (float)a;
+        if constexpr (SPLIT) {
+          kout[pr * SMAX + pc] = (float)a;
+          kout[pc * SMAX + pr] = (float)a;
+        } else {
+          km[pr * SMAX + pc] = (float)a;
+          km[pc * SMAX + pr] = (float)a;
+        }
       }
     }
-    __syncthreads();
+    if constexpr (!SPLIT) __syncthreads();
   }
-  if constexpr (SPLIT) {
-    float* kout = keys + (int64_t)c0 * SMAX;
-    for (int e = tid; e < s * SMAX; e += 256) {
-      const int r = e / SMAX, c = e % SMAX;
-      kout[e] = c < s && c != r ? km[r * SMAX + c] : FLT_MAX;
-    }
-    return;
-  }
+  if constexpr (SPLIT) return;
   // merge: one wavefront per member; lane l holds candidates l, l + 64, ...
   // (the next member's row is loaded while one is merged); the id tables in
   // the slice buffers, free now
@@ -289,7 +316,8 @@ __global__ __launch_bounds__(256) void k_refine_rows(const float* __restrict__ k
   int mid[NC];
 #pragma unroll
   for (int h = 0; h < NC; ++h) mid[h] = lane + 64 * h < s ? members[c0 + lane + 64 * h] : -1;
-  // keys of row r (FLT_MAX past s and on the diagonal, as stored)
+  // keys of row r (columns s and beyond and the diagonal unwritten; masked
+  // by valid below)
   auto load_keys = [&](int r, float (&out)[NC]) {
 #pragma unroll
     for (int h = 0; h < NC; ++h) out[h] = keys[(int64_t)(c0 + r) * SMAX + lane + 64 * h];

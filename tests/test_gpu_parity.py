@@ -442,6 +442,31 @@ def test_refine_parity(ctx, precision, n, d, kappa, k):
     assert not msg, "second pass changed rows: " + msg
 
 
+@pytest.mark.parametrize("n,d,k", [(1000, 64, 10), (1200, 128, 12), (1500, 512, 30), (900, 512, 30)])
+def test_refine_duplicate_rows(ctx, n, d, k):
+    """Clusters full of exact and near duplicates (integer rows, a few
+    coordinates moved by one): zero and tiny distances against large norms,
+    whose Gram keys cannot be certified, so the exact kernels recompute them
+    from the rows: clusters of about 100 (the 65-128-member kernels) hold more
+    such pairs than the list takes and recompute every pair, clusters of
+    about 50 and 30 at d = 512 (the 33-64-member and one-tile kernels) fewer."""
+    say("refine duplicate rows", n, d, k)
+    rng = np.random.default_rng(d + k)
+    base = rng.integers(100, 256, size=(6, d)).astype(np.float32)
+    X = base[rng.integers(0, 6, n)]
+    bump = (rng.random((n, d)) < 2.0 / d).astype(np.float32)
+    X = np.ascontiguousarray(X + bump * (rng.random(n) < 0.5)[:, None])
+    kappa = 20
+    gi0, gd0 = knng.graph_init(X, kappa, seed=7)
+    lab = rng.integers(0, k, n).astype(np.int32)
+    want_i, want_d = knng.refine(X, gi0, gd0, lab)
+    for precision in (knnkm.FP32, knnkm.BF16_RERANK):
+        gi, gd = dev(gi0), dev(gd0)
+        knnkm.knnkm_graph_refine(ctx, dev(X), dev(lab), k, precision, gi, gd)
+        msg = _graph_diff(host(gi), host(gd), want_i, want_d, lab)
+        assert not msg, msg
+
+
 @pytest.mark.parametrize("precision", [knnkm.FP32, knnkm.BF16_RERANK])
 def test_knn_build_parity(ctx, precision):
     n, d, kappa = 3000, 32, 10
