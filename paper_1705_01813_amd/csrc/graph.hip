@@ -820,16 +820,22 @@ knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   KNNKM_WS(ctx, slots, int32_t, "rf_survivors", n * SC_CAP);
   KNNKM_TRY(ks_label_sort(ctx, labels, n, k, counts, off, mem));
   const int dpad = (d + 31) / 32 * 32;
-  // clusters of rb1 < s <= hi: screen + merge, with the item count within
-  // int32 (items <= t_max * (n / 64 + k)); larger ones: row blocks of the
-  // multi-tile kernel
+  const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+  // clusters of RX_MAX < s <= RX_BIG_HI: the tiled exact kernels
+  static_assert(RX_BIG_LO == RX_MAX, "the tiled exact kernels take over where the mid-sized one ends");
+  bool big = false;
+  KNNKM_TRY(ks_refine_big(ctx, X, n, d, ldx, kappa, k, counts, off, mem, vec, G_ids, G_d2, &big));
+  // clusters of lo_screen < s <= hi: screen + merge, with the item count
+  // within int32 (items <= t_max * (n / 64 + k)); larger ones: row blocks of
+  // the multi-tile kernel
   const int64_t denom = n / SC_RB + k + 1;
   const int64_t t_max = std::max<int64_t>(1, std::min<int64_t>(46340, INT32_MAX / denom));
   const int hi = (int)std::min<int64_t>(t_max * SC_RB, INT32_MAX);
   // clusters of rb1 < s <= RX_MAX: exact all-pairs kernel (below)
-  const int lo_screen = std::max(rb1, RX_MAX);
+  const int lo_screen = big ? RX_BIG_HI : std::max(rb1, RX_MAX);
+  const int multi_lo = big ? std::max(hi, RX_BIG_HI) : hi;
   k_screen_items<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, lo_screen, hi, items);
-  k_row_blocks<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, hi, rb2, wb);
+  k_row_blocks<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, multi_lo, rb2, wb);
   KNNKM_TRY(knnkm_check(ctx, "refine blocks"));
   KNNKM_TRY(ks_scan_exclusive(ctx, items, items, k, true));
   KNNKM_TRY(ks_scan_exclusive(ctx, wb, wb, k, true));
@@ -841,7 +847,6 @@ knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   double err = (2.0 * dpad + 8.0) * u;
   if (precision == KNNKM_BF16_RERANK) err += 2.0 * (0x1p-7 + 0x1p-15);
   const float err_c = (float)(2.0 * err);
-  const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
   const float* nrm = norms;
   if (!nrm) {
     KNNKM_WS(ctx, own, float, "rf_norms", n);

@@ -91,9 +91,9 @@ __device__ inline MergeRow merge_load(const float* __restrict__ rowk, const int3
 // wavefront only; old: its entries (merge_load).  Candidate ids are
 // non-negative and below INT32_MAX where valid.  hs: this wavefront's id
 // table (LDS, MG_SLOTS entries, empty).  kth (optional): receives the row's
-// new kappa-th key when the row changes.
+// new kappa-th key when the row changes.  Returns whether it changed.
 template <int NC>
-__device__ inline void merge_row(float* __restrict__ rowk, int32_t* __restrict__ rowi, int kappa, const MergeRow& old,
+__device__ inline bool merge_row(float* __restrict__ rowk, int32_t* __restrict__ rowi, int kappa, const MergeRow& old,
                                  const float (&ck)[NC], const int (&cid)[NC], const bool (&valid)[NC],
                                  int32_t* __restrict__ hs, float* kth = nullptr) {
   const int lane = threadIdx.x & 63;
@@ -111,7 +111,7 @@ __device__ inline void merge_row(float* __restrict__ rowk, int32_t* __restrict__
     enter[h] = valid[h] && cq[h] < tk;
     any = any || enter[h];
   }
-  if (__ballot(any) == 0) return;  // nothing can enter: the row stays
+  if (__ballot(any) == 0) return false;  // nothing can enter: the row stays
   // visited: the candidate's id is already in the row
   const int s0 = lane < kappa ? mg_insert(hs, old.e0i) : -1;
   const int s1 = two && lane + 64 < kappa ? mg_insert(hs, old.e1i) : -1;
@@ -149,7 +149,7 @@ __device__ inline void merge_row(float* __restrict__ rowk, int32_t* __restrict__
       if (lane == b) pos[g] += before;
     }
   }
-  if (!anyin) return;  // wave-uniform: every entering candidate was visited
+  if (!anyin) return false;  // wave-uniform: every entering candidate was visited
   if (lane < kappa && lane + add0 < kappa) {
     rowk[lane + add0] = old.e0k;
     rowi[lane + add0] = old.e0i;
@@ -167,4 +167,5 @@ __device__ inline void merge_row(float* __restrict__ rowk, int32_t* __restrict__
       rowi[pos[h]] = cid[h];
       if (kth && pos[h] == kappa - 1) *kth = ck[h];
     }
+  return true;
 }

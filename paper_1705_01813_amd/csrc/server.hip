@@ -61,6 +61,8 @@ int64_t ws_estimate(int64_t n, int64_t d, int64_t k, int64_t k0, int64_t kappa, 
   b += 4 * (kappa + 2) * n + 4 * k;          // fit: drift bounds (wide rows)
   b += 4 * kappa * n + k / 8;                // fit: graph-entry labels, changed-cluster flag bits
   b += 4 * 128 * n;                          // refinement: key rows of the 65-128-member clusters
+  if (k0 > 0 && 2 * (n / k0) > 128)          // and of the 129-1024-member ones (clusters of up to 4n/k0)
+    b += 4 * std::min<int64_t>(1024, (4 * (n / k0) + 63) / 64 * 64) * n;
   b += 2 * d * (k + k0) + 4 * (k + k0);      // bfloat16 centroid shadows (wide rows)
   b += 64 * m + 16 * (T + 1) * m;            // job tables and traces
   b += 1 << 20;                              // scans, partial sums, small tables

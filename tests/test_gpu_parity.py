@@ -423,7 +423,7 @@ def _graph_diff(got_i, got_d, want_i, want_d, lab=None):
 @pytest.mark.parametrize("precision", [knnkm.FP32, knnkm.BF16_RERANK])
 @pytest.mark.parametrize("n,d,kappa,k", [(2000, 32, 10, 40), (3000, 128, 20, 60), (600, 512, 20, 10),
                                          (600, 512, 50, 10), (1000, 256, 50, 12), (1500, 20, 8, 3),
-                                         (400, 64, 30, 1)])
+                                         (400, 64, 30, 1), (3000, 512, 50, 10), (2500, 16, 10, 2)])
 def test_refine_parity(ctx, precision, n, d, kappa, k):
     say("refine", precision, n, d, kappa, k)
     X = datagen.mixture(n, d, 12, seed=d + k)
@@ -442,14 +442,16 @@ def test_refine_parity(ctx, precision, n, d, kappa, k):
     assert not msg, "second pass changed rows: " + msg
 
 
-@pytest.mark.parametrize("n,d,k", [(1000, 64, 10), (1200, 128, 12), (1500, 512, 30), (900, 512, 30)])
+@pytest.mark.parametrize("n,d,k", [(1000, 64, 10), (1200, 128, 12), (1500, 512, 30), (900, 512, 30),
+                                   (1200, 64, 4)])
 def test_refine_duplicate_rows(ctx, n, d, k):
     """Clusters full of exact and near duplicates (integer rows, a few
     coordinates moved by one): zero and tiny distances against large norms,
     whose Gram keys cannot be certified, so the exact kernels recompute them
     from the rows: clusters of about 100 (the 65-128-member kernels) hold more
     such pairs than the list takes and recompute every pair, clusters of
-    about 50 and 30 at d = 512 (the 33-64-member and one-tile kernels) fewer."""
+    about 50 and 30 at d = 512 (the 33-64-member and one-tile kernels) fewer;
+    clusters of about 300 take the tiled kernels for 129-1024 members."""
     say("refine duplicate rows", n, d, k)
     rng = np.random.default_rng(d + k)
     base = rng.integers(100, 256, size=(6, d)).astype(np.float32)
