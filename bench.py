@@ -720,9 +720,10 @@ def xi_sweep(n, seed, log, xis=(50, 100, 256, 512), kappa=50):
     the 10M x 512 recipe, for cluster sizes xi: the clusters are a TwoMeans
     partition into n / xi leaves, the graph the random initial lists.  Per xi
     and screen precision: the round's time, the dense Gram flops of the
-    clusters (2 xi d per member), the rate against the MFMA peaks, and the
-    ceiling the round's bytes put on it (member rows and graph rows read once:
-    4d + 8 kappa per member)."""
+    clusters (2 xi d per member), the rate against the MFMA peaks -- also the
+    float64 one: clusters of 33 to 1024 members form their Gram in float64 on
+    MFMA whatever the screen precision -- and the ceiling the round's bytes put
+    on it (member rows and graph rows read once: 4d + 8 kappa per member)."""
     import torch
 
     from paper_1705_01813_amd import datagen, knnkm
@@ -738,7 +739,7 @@ def xi_sweep(n, seed, log, xis=(50, 100, 256, 512), kappa=50):
     knnkm.knnkm_graph_init(ctx, X, kappa, seed, gi0, gd0)
     lab = torch.empty(n, dtype=torch.int32, device=dev)
     out = []
-    peaks = {"fp32": 157.3, "bf16": 2500.0}
+    peaks = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}
     for xi in xis:
         k0 = max(1, n // xi)
         knnkm.knnkm_twomeans(ctx, X, k0, seed, 0, 2, lab)
@@ -758,7 +759,7 @@ def xi_sweep(n, seed, log, xis=(50, 100, 256, 512), kappa=50):
             tf = flops / (ms * 1e-3) / 1e12
             cap = min(1.0, (flops / bytes_) * HBM_PEAK_GBS / 1e3 / peaks[name])
             row[name] = {"refine_ms": ms, "gram_tflops": tf, "frac_of_mfma_peak": tf / peaks[name],
-                         "hbm_ceiling_frac_of_mfma_peak": cap}
+                         "frac_of_fp64_mfma_peak": tf / peaks["fp64"], "hbm_ceiling_frac_of_mfma_peak": cap}
             log(f"xi {xi}: k0 {k0}, {name} screen: {ms:.2f} ms, {tf:.2f} TFLOP/s")
         out.append(row)
     ctx.close()

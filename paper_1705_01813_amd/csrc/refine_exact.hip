@@ -1,6 +1,7 @@
 // Exhaustive comparison inside mid-sized clusters (Alg. 3 inner loops) with
 // exact keys for every pair: one block of 256 threads per cluster of
-// smin < s <= SMAX members (SMAX = 64 or 128).
+// smin < s <= SMAX members (SMAX = 64 or 128); further down, the same keys
+// tiled over pairs of 64-member blocks for clusters of up to 1024 members.
 //
 // At the cluster sizes graph construction produces (about xi = 50 members)
 // a screen of the Gram block leaves too many survivors for a separate exact
