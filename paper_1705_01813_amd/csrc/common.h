@@ -275,12 +275,13 @@ knnkm_status ks_assign(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
 // (tiled float64 Gram; counts/offsets/members as from ks_label_sort).  Reads
 // the clusters' total size back to the host (one stream synchronisation) to
 // size its key rows; *handled is false when it leaves those clusters to the
-// screen path (inside a graph capture, or a launch too large).
+// screen path (inside a graph capture, or a launch too large); *above is
+// false when no cluster has more than RX_BIG_HI members.
 #define RX_BIG_LO 128
 #define RX_BIG_HI 1024
 knnkm_status ks_refine_big(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int32_t kappa,
                            int32_t k, const int32_t* counts, const int32_t* offsets, const int32_t* members,
-                           bool vec, int32_t* G_ids, float* G_d2, bool* handled);
+                           bool vec, int32_t* G_ids, float* G_d2, bool* handled, bool* above);
 // Exact all-pairs refinement of the clusters with smin < s <= smax members
 // (smax <= 128; one block per cluster, rows of the graph updated in place).
 knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int32_t kappa,

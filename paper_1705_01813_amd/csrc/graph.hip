@@ -774,7 +774,7 @@ template <bool BF16, int L, int V>
 static knnkm_status launch_refine(knnkm_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, int dpad,
                                   int kappa, int32_t k, const int32_t* off, const int32_t* mem,
                                   const int32_t* wb, int rb1, int rb2, float err_c, bool vec,
-                                  int32_t* G_ids, float* G_d2) {
+                                  int32_t* G_ids, float* G_d2, bool multi) {
   // one tile per cluster of at most rb1 members; with 64-row tiles, the
   // clusters of at most 32 members take the 32-row kernel (less LDS, more
   // blocks per CU; the lists do not depend on the tile size)
@@ -787,6 +787,7 @@ static knnkm_status launch_refine(knnkm_ctx* ctx, const float* X, int64_t n, int
     default: launch_tile<BF16, L, V, 16, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, 0, err_c, vec, G_ids, G_d2); break;
   }
   KNNKM_TRY(knnkm_check(ctx, "graph refine (one-tile clusters)"));
+  if (!multi) return KNNKM_OK;
   // larger clusters: blocks of rb2 rows walking blocks of rb2 columns; the
   // sum over clusters of ceil(s / rb2) is at most n / rb2 + k
   const int64_t max_items = n / rb2 + k + 1;
@@ -823,23 +824,11 @@ knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
   // clusters of RX_MAX < s <= RX_BIG_HI: the tiled exact kernels
   static_assert(RX_BIG_LO == RX_MAX, "the tiled exact kernels take over where the mid-sized one ends");
-  bool big = false;
-  KNNKM_TRY(ks_refine_big(ctx, X, n, d, ldx, kappa, k, counts, off, mem, vec, G_ids, G_d2, &big));
-  // clusters of lo_screen < s <= hi: screen + merge, with the item count
-  // within int32 (items <= t_max * (n / 64 + k)); larger ones: row blocks of
-  // the multi-tile kernel
-  const int64_t denom = n / SC_RB + k + 1;
-  const int64_t t_max = std::max<int64_t>(1, std::min<int64_t>(46340, INT32_MAX / denom));
-  const int hi = (int)std::min<int64_t>(t_max * SC_RB, INT32_MAX);
-  // clusters of rb1 < s <= RX_MAX: exact all-pairs kernel (below)
-  const int lo_screen = big ? RX_BIG_HI : std::max(rb1, RX_MAX);
-  const int multi_lo = big ? std::max(hi, RX_BIG_HI) : hi;
-  k_screen_items<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, lo_screen, hi, items);
-  k_row_blocks<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, multi_lo, rb2, wb);
-  KNNKM_TRY(knnkm_check(ctx, "refine blocks"));
-  KNNKM_TRY(ks_scan_exclusive(ctx, items, items, k, true));
-  KNNKM_TRY(ks_scan_exclusive(ctx, wb, wb, k, true));
-  KNNKM_TRY(ks_fill_i32(ctx, cnt, n, 0));
+  bool big = false, above = true;
+  KNNKM_TRY(ks_refine_big(ctx, X, n, d, ldx, kappa, k, counts, off, mem, vec, G_ids, G_d2, &big, &above));
+  // with no cluster past the tiled kernels' range, the screen, its merge and
+  // the multi-tile kernel have nothing to do
+  const bool rest = !big || above;
   // Screening bound (squared-distance units, relative to ||x||^2 + ||y||^2):
   // twice the worst-case rounding of the float32 Gram, the float32 norms and
   // the final additions; plus the bfloat16 rounding of both operands.
@@ -847,42 +836,59 @@ knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   double err = (2.0 * dpad + 8.0) * u;
   if (precision == KNNKM_BF16_RERANK) err += 2.0 * (0x1p-7 + 0x1p-15);
   const float err_c = (float)(2.0 * err);
-  const float* nrm = norms;
-  if (!nrm) {
-    KNNKM_WS(ctx, own, float, "rf_norms", n);
-    KNNKM_TRY(ks_row_norms(ctx, X, n, d, ldx, own));
-    nrm = own;
-  }
-  const unsigned gs = (unsigned)std::max(1, ctx->num_cus * 8);
-  if (precision == KNNKM_BF16_RERANK)
-    k_refine_screen<true><<<gs, 256, 0, ctx->stream>>>(X, d, ldx, dpad, kappa, k, off, mem, items, nrm, err_c,
-                                                       vec ? 1 : 0, G_d2, cnt, slots);
-  else
-    k_refine_screen<false><<<gs, 256, 0, ctx->stream>>>(X, d, ldx, dpad, kappa, k, off, mem, items, nrm, err_c,
-                                                        vec ? 1 : 0, G_d2, cnt, slots);
-  KNNKM_TRY(knnkm_check(ctx, "graph refine screen"));
   int gL, gV;
   pick_group(d, 1, &gL, &gV);
-  {
-    const unsigned gm = (unsigned)grid_for(n, 4, 16384);
-#define RM(LL)                                                                                       \
-  k_refine_merge<LL><<<gm, 256, 0, ctx->stream>>>(X, d, ldx, kappa, labels, off, mem, n, cnt, slots, \
-                                                  vec ? 1 : 0, G_ids, G_d2)
-    switch (gL) {
-      case 4: RM(4); break;
-      case 8: RM(8); break;
-      case 16: RM(16); break;
-      case 32: RM(32); break;
-      default: RM(64); break;
+  if (rest) {
+    // clusters of lo_screen < s <= hi: screen + merge, with the item count
+    // within int32 (items <= t_max * (n / 64 + k)); larger ones: row blocks of
+    // the multi-tile kernel
+    const int64_t denom = n / SC_RB + k + 1;
+    const int64_t t_max = std::max<int64_t>(1, std::min<int64_t>(46340, INT32_MAX / denom));
+    const int hi = (int)std::min<int64_t>(t_max * SC_RB, INT32_MAX);
+    // clusters of rb1 < s <= RX_MAX: exact all-pairs kernel (below)
+    const int lo_screen = big ? RX_BIG_HI : std::max(rb1, RX_MAX);
+    const int multi_lo = big ? std::max(hi, RX_BIG_HI) : hi;
+    k_screen_items<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, lo_screen, hi, items);
+    k_row_blocks<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, multi_lo, rb2, wb);
+    KNNKM_TRY(knnkm_check(ctx, "refine blocks"));
+    KNNKM_TRY(ks_scan_exclusive(ctx, items, items, k, true));
+    KNNKM_TRY(ks_scan_exclusive(ctx, wb, wb, k, true));
+    KNNKM_TRY(ks_fill_i32(ctx, cnt, n, 0));
+    const float* nrm = norms;
+    if (!nrm) {
+      KNNKM_WS(ctx, own, float, "rf_norms", n);
+      KNNKM_TRY(ks_row_norms(ctx, X, n, d, ldx, own));
+      nrm = own;
     }
+    const unsigned gs = (unsigned)std::max(1, ctx->num_cus * 8);
+    if (precision == KNNKM_BF16_RERANK)
+      k_refine_screen<true><<<gs, 256, 0, ctx->stream>>>(X, d, ldx, dpad, kappa, k, off, mem, items, nrm, err_c,
+                                                         vec ? 1 : 0, G_d2, cnt, slots);
+    else
+      k_refine_screen<false><<<gs, 256, 0, ctx->stream>>>(X, d, ldx, dpad, kappa, k, off, mem, items, nrm, err_c,
+                                                          vec ? 1 : 0, G_d2, cnt, slots);
+    KNNKM_TRY(knnkm_check(ctx, "graph refine screen"));
+    {
+      const unsigned gm = (unsigned)grid_for(n, 4, 16384);
+#define RM(LL)                                                                                       \
+    k_refine_merge<LL><<<gm, 256, 0, ctx->stream>>>(X, d, ldx, kappa, labels, off, mem, n, cnt, slots, \
+                                                    vec ? 1 : 0, G_ids, G_d2)
+      switch (gL) {
+        case 4: RM(4); break;
+        case 8: RM(8); break;
+        case 16: RM(16); break;
+        case 32: RM(32); break;
+        default: RM(64); break;
+      }
 #undef RM
+    }
+    KNNKM_TRY(knnkm_check(ctx, "graph refine merge"));
   }
-  KNNKM_TRY(knnkm_check(ctx, "graph refine merge"));
   if (rb1 < RX_MAX)
     KNNKM_TRY(ks_refine_exact(ctx, X, n, d, ldx, kappa, k, off, mem, rb1, RX_MAX, vec, G_ids, G_d2));
 #define RF(BF, LL, VV)                                                                                    \
   return launch_refine<BF, LL, VV>(ctx, X, n, d, ldx, dpad, kappa, k, off, mem, wb, rb1, rb2, err_c, vec, \
-                                   G_ids, G_d2)
+                                   G_ids, G_d2, rest)
 #define RF_L(BF, VV)                \
   switch (gL) {                     \
     case 4: RF(BF, 4, VV);          \

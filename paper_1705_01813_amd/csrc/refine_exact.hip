@@ -602,32 +602,38 @@ __global__ __launch_bounds__(256) void k_refine_gram_big(const float* __restrict
   }
 }
 
-// The merge of k_refine_gram_big's keys: one block per cluster of
-// lo < s <= hi members, one wavefront per member row (w, w + 4, ...); the row
-// is held in LDS and merged with 64 candidates at a time (keys of the next
-// 64 loaded while one group is merged), then written back if it changed --
-// the same list as any other order of comparison.
+// The merge of k_refine_gram_big's keys: one wavefront per member row of
+// the clusters (rows at row_off, in cluster order; four per block, the grid
+// striding over them); the row is held in LDS and merged with 64 candidates
+// at a time (keys of the next 64 loaded while one group is merged), then
+// written back if it changed -- the same list as any other order of
+// comparison.
 __global__ __launch_bounds__(256) void k_refine_rows_big(const float* __restrict__ keys, int sw, int32_t k,
                                                          const int32_t* __restrict__ offsets,
                                                          const int32_t* __restrict__ members,
-                                                         const int32_t* __restrict__ row_off, int lo, int hi,
-                                                         int kappa, int32_t* __restrict__ G_ids,
-                                                         float* __restrict__ G_d2) {
+                                                         const int32_t* __restrict__ row_off, int kappa,
+                                                         int32_t* __restrict__ G_ids, float* __restrict__ G_d2) {
   __shared__ float rks[4][KNNKM_MAX_KAPPA];
   __shared__ int32_t ris[4][KNNKM_MAX_KAPPA];
   __shared__ int32_t mgh[4][MG_SLOTS];
-  const int cl = blockIdx.x;
-  if (cl >= k) return;
-  const int c0 = offsets[cl];
-  const int s = offsets[cl + 1] - c0;
-  if (s <= lo || s > hi) return;  // block-uniform
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   float* rowk = rks[w];
   int32_t* rowi = ris[w];
   int32_t* hs = mgh[w];
   for (int e = lane; e < MG_SLOTS; e += 64) hs[e] = -1;
-  const float* kb = keys + (int64_t)row_off[cl] * sw;
-  for (int r = w; r < s; r += 4) {
+  const int64_t total = row_off[k];
+  // wave-uniform loop (no block barrier inside)
+  for (int64_t gr = (int64_t)blockIdx.x * 4 + w; gr < total; gr += (int64_t)gridDim.x * 4) {
+    int lo = 0, hi = k;  // the cluster: the last c with row_off[c] <= gr
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (row_off[mid] <= gr) lo = mid; else hi = mid;
+    }
+    const int cl = lo;
+    const int c0 = offsets[cl];
+    const int s = offsets[cl + 1] - c0;
+    const int r = (int)(gr - row_off[cl]);
+    const float* kr = keys + ((int64_t)row_off[cl] + r) * sw;
     const int64_t g = (int64_t)members[c0 + r] * kappa;
     for (int q = lane; q < kappa; q += 64) {
       rowk[q] = G_d2[g + q];
@@ -636,10 +642,10 @@ __global__ __launch_bounds__(256) void k_refine_rows_big(const float* __restrict
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     bool changed = false;
-    float nk = kb[(int64_t)r * sw + lane];
+    float nk = kr[lane];
     for (int cb = 0; cb < s; cb += 64) {
       const float kv = nk;
-      if (cb + 64 < s) nk = kb[(int64_t)r * sw + cb + 64 + lane];
+      if (cb + 64 < s) nk = kr[cb + 64 + lane];
       const int c = cb + lane;
       const bool valid[1] = {c < s && c != r};
       const float ck[1] = {valid[0] ? kv : FLT_MAX};
@@ -659,15 +665,17 @@ __global__ __launch_bounds__(256) void k_refine_rows_big(const float* __restrict
   }
 }
 
+// tot[2]: the largest size in (lo, hi]; tot[3]: clusters above hi
 __global__ void k_big_items(const int32_t* __restrict__ counts, int32_t k, int lo, int hi, int32_t* items,
-                            int32_t* rows, int32_t* smax) {
+                            int32_t* rows, int32_t* tot) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < k; c += (int64_t)gridDim.x * blockDim.x) {
     const int s = counts[c];
     const bool in = s > lo && s <= hi;
     const int t = (s + BX_RB - 1) / BX_RB;
     items[c] = in ? t * (t + 1) / 2 : 0;
     rows[c] = in ? s : 0;
-    if (in) atomicMax(smax, s);
+    if (in) atomicMax(&tot[2], s);
+    if (s > hi) atomicAdd(&tot[3], 1);
   }
 }
 
@@ -704,15 +712,16 @@ knnkm_status ks_refine_exact(knnkm_ctx* ctx, const float* X, int64_t n, int32_t 
 
 knnkm_status ks_refine_big(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx, int32_t kappa,
                            int32_t k, const int32_t* counts, const int32_t* offsets, const int32_t* members,
-                           bool vec, int32_t* G_ids, float* G_d2, bool* handled) {
+                           bool vec, int32_t* G_ids, float* G_d2, bool* handled, bool* above) {
   *handled = false;
+  *above = true;
   if (ctx->capturing || k <= 0) return KNNKM_OK;
   KNNKM_WS(ctx, items, int32_t, "bx_items", (int64_t)k + 1);
   KNNKM_WS(ctx, rows, int32_t, "bx_rows", (int64_t)k + 1);
   KNNKM_WS(ctx, tot, int32_t, "bx_tot", 4);
   KNNKM_TRY(ks_fill_i32(ctx, tot, 4, 0));
   k_big_items<<<grid_for(k, 256, 4096), 256, 0, ctx->stream>>>(counts, k, RX_BIG_LO, RX_BIG_HI, items, rows,
-                                                               tot + 2);
+                                                               tot);
   KNNKM_TRY(knnkm_check(ctx, "refine (large clusters): items"));
   KNNKM_TRY(ks_scan_exclusive(ctx, items, items, k, true));
   KNNKM_TRY(ks_scan_exclusive(ctx, rows, rows, k, true));
@@ -721,6 +730,7 @@ knnkm_status ks_refine_big(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d,
   KNNKM_HIP(ctx, hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
   KNNKM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   *handled = true;  // the screen path now leaves these clusters alone
+  *above = h[3] > 0;
   if (h[0] == 0) return KNNKM_OK;
   // one launch of at most 2^32 threads
   if ((int64_t)h[0] * 256 >= ((int64_t)1 << 32)) {
@@ -733,7 +743,7 @@ knnkm_status ks_refine_big(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d,
   k_refine_gram_big<8><<<(unsigned)h[0], 256, 0, ctx->stream>>>(X, d, ldx, k, offsets, members, items, rows, sw,
                                                               vec ? 1 : 0, keys);
   KNNKM_TRY(knnkm_check(ctx, "refine (large clusters): keys"));
-  k_refine_rows_big<<<(unsigned)k, 256, 0, ctx->stream>>>(keys, sw, k, offsets, members, rows, RX_BIG_LO,
-                                                          RX_BIG_HI, kappa, G_ids, G_d2);
+  const unsigned gm = (unsigned)std::min<int64_t>(((int64_t)h[1] + 3) / 4, (int64_t)1 << 20);
+  k_refine_rows_big<<<gm, 256, 0, ctx->stream>>>(keys, sw, k, offsets, members, rows, kappa, G_ids, G_d2);
   return knnkm_check(ctx, "refine (large clusters): merge");
 }
