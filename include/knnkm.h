@@ -21,9 +21,13 @@
  *    (id, d2) entries ordered by (d2, id) ascending; d2 is the float32
  *    rounding of the pair's squared distance.
  *  - Kernel-level calls (knn_assign, centroid_update, distortion,
- *    knnkm_twomeans, knnkm_graph_init, knnkm_graph_refine, knn_build) are
- *    asynchronous on the context's HIP stream.  knn_kmeans_fit synchronises
- *    the stream before returning because it writes host memory.
+ *    knnkm_graph_init, knn_graph_search) are asynchronous on the context's
+ *    HIP stream.  knnkm_twomeans (when its cached split plan does not match
+ *    the call), knnkm_graph_refine (it reads the sizes of clusters above 128
+ *    members back to the host) and knn_build (both, and the small host
+ *    tables it uploads) synchronise the stream on the way.  knn_kmeans_fit
+ *    synchronises the stream before returning because it writes host
+ *    memory.
  *  - Every call returns a knnkm_status; nothing throws or aborts across the
  *    ABI.  Arguments are validated on the host before any launch; on a
  *    non-OK status the outputs are unspecified and knnkm_last_error() holds a
@@ -161,10 +165,13 @@ knnkm_status knnkm_graph_init(knnkm_ctx* ctx, const float* X, int64_t n, int32_t
 /* Alg. 3 inner loops for one partition: for every cluster S_m of `labels`
  * (values in [0,k)), every pair <i,j> of S_m updates G[i] and G[j]: a pair
  * whose id is not yet in the row enters it if its (d2, id) is among the
- * kappa smallest.  Pair distances are screened on MFMA (float32, or bfloat16
- * with precision = KNNKM_BF16_RERANK) with a rigorous error margin against
- * the row's current kappa-th distance; survivors are re-evaluated exactly.
- * Both precisions give identical graphs.  G_ids/G_d2 are updated in place. */
+ * kappa smallest.  Clusters of at most 32 members and of more than 1024:
+ * pair distances screened on MFMA (float32, or bfloat16 with precision =
+ * KNNKM_BF16_RERANK) with a rigorous error margin against the row's current
+ * kappa-th distance, survivors re-evaluated exactly; 33-1024 members: every
+ * pair's key from a float64 Gram on MFMA, certified or recomputed from the
+ * rows.  Both precisions give identical graphs.  G_ids/G_d2 are updated in
+ * place.  Synchronises the stream once (see above). */
 knnkm_status knnkm_graph_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                                 const int32_t* labels, int32_t k, int32_t precision,
                                 int32_t* G_ids, float* G_d2, int32_t kappa);
