@@ -442,6 +442,24 @@ def test_refine_parity(ctx, precision, n, d, kappa, k):
     assert not msg, "second pass changed rows: " + msg
 
 
+@pytest.mark.parametrize("n,k", [(1500, 60), (2000, 40), (4000, 50), (3000, 6)])
+def test_refine_parity_long_lists(ctx, n, k):
+    """kappa = 100 (every lane of a merging wavefront holds two list entries)
+    for clusters of about 25, 50, 80 and 500 members: the one-tile kernel,
+    the two mid-sized kernels and the tiled one."""
+    d, kappa = 24, 100
+    say("refine long lists", n, d, kappa, k)
+    X = datagen.mixture(n, d, 9, seed=k)
+    gi0, gd0 = knng.graph_init(X, kappa, seed=11)
+    lab = np.random.default_rng(k).integers(0, k, n).astype(np.int32)
+    want_i, want_d = knng.refine(X, gi0, gd0, lab)
+    for precision in (knnkm.FP32, knnkm.BF16_RERANK):
+        gi, gd = dev(gi0), dev(gd0)
+        knnkm.knnkm_graph_refine(ctx, dev(X), dev(lab), k, precision, gi, gd)
+        msg = _graph_diff(host(gi), host(gd), want_i, want_d, lab)
+        assert not msg, msg
+
+
 @pytest.mark.parametrize("n,d,k", [(1000, 64, 10), (1200, 128, 12), (1500, 512, 30), (900, 512, 30),
                                    (1200, 64, 4)])
 def test_refine_duplicate_rows(ctx, n, d, k):
