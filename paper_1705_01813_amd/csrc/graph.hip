@@ -775,12 +775,9 @@ static knnkm_status launch_refine(knnkm_ctx* ctx, const float* X, int64_t n, int
                                   int kappa, int32_t k, const int32_t* off, const int32_t* mem,
                                   const int32_t* wb, int rb1, int rb2, float err_c, bool vec,
                                   int32_t* G_ids, float* G_d2, bool multi) {
-  // one tile per cluster of at most rb1 (32 or 16) members; the lists do not
-  // depend on the tile size
-  switch (rb1) {
-    case 32: launch_tile<BF16, L, V, 32, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, 0, err_c, vec, G_ids, G_d2); break;
-    default: launch_tile<BF16, L, V, 16, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, 0, err_c, vec, G_ids, G_d2); break;
-  }
+  // one tile per cluster of at most rb1 = 16 members
+  launch_tile<BF16, L, V, 16, true>(ctx, k, X, d, ldx, dpad, kappa, k, off, mem, nullptr, 0, 0, err_c, vec, G_ids,
+                                    G_d2);
   KNNKM_TRY(knnkm_check(ctx, "graph refine (one-tile clusters)"));
   if (!multi) return KNNKM_OK;
   // larger clusters: blocks of rb2 rows walking blocks of rb2 columns; the
@@ -803,10 +800,10 @@ knnkm_status ks_row_norms(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, 
 knnkm_status ks_refine(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                        const int32_t* labels, int32_t k, int32_t precision, int32_t* G_ids,
                        float* G_d2, int32_t kappa, const float* norms) {
-  // one-tile kernel for clusters of at most 32 members; 33-128 members take
-  // the float64 Gram kernels (measured faster for 33-64 members at d = 128
+  // one-tile kernel for clusters of at most 16 members; 17-128 members take
+  // the float64 Gram kernels (measured faster for 17-64 members at d = 128
   // and d = 512)
-  const int rb1 = std::min(32, pick_rb(d, true, kappa)), rb2 = pick_rb(d, false, kappa);
+  const int rb1 = std::min(16, pick_rb(d, true, kappa)), rb2 = pick_rb(d, false, kappa);
   if (!rb1 || !rb2)
     return knnkm_fail(ctx, KNNKM_EUNSUPPORTED, "graph refine: d=%d with kappa=%d does not fit in LDS", d,
                       kappa);

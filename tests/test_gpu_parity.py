@@ -423,7 +423,8 @@ def _graph_diff(got_i, got_d, want_i, want_d, lab=None):
 @pytest.mark.parametrize("precision", [knnkm.FP32, knnkm.BF16_RERANK])
 @pytest.mark.parametrize("n,d,kappa,k", [(2000, 32, 10, 40), (3000, 128, 20, 60), (600, 512, 20, 10),
                                          (600, 512, 50, 10), (1000, 256, 50, 12), (1500, 20, 8, 3),
-                                         (400, 64, 30, 1), (3000, 512, 50, 10), (2500, 16, 10, 2)])
+                                         (400, 64, 30, 1), (3000, 512, 50, 10), (2500, 16, 10, 2),
+                                         (1200, 32, 10, 100), (1000, 512, 20, 80)])
 def test_refine_parity(ctx, precision, n, d, kappa, k):
     say("refine", precision, n, d, kappa, k)
     X = datagen.mixture(n, d, 12, seed=d + k)
@@ -442,11 +443,12 @@ def test_refine_parity(ctx, precision, n, d, kappa, k):
     assert not msg, "second pass changed rows: " + msg
 
 
-@pytest.mark.parametrize("n,k", [(1500, 60), (2000, 40), (4000, 50), (3000, 6)])
+@pytest.mark.parametrize("n,k", [(1500, 100), (2000, 40), (4000, 50), (3000, 6)])
 def test_refine_parity_long_lists(ctx, n, k):
     """kappa = 100 (every lane of a merging wavefront holds two list entries)
-    for clusters of about 25, 50, 80 and 500 members: the one-tile kernel,
-    the two mid-sized kernels and the tiled one."""
+    for clusters of about 15, 50, 80 and 500 members: the one-tile kernel
+    (at most 16 members) and the 17-64-member one, the 65-128-member kernels
+    and the tiled one."""
     d, kappa = 24, 100
     say("refine long lists", n, d, kappa, k)
     X = datagen.mixture(n, d, 9, seed=k)
@@ -468,8 +470,8 @@ def test_refine_duplicate_rows(ctx, n, d, k):
     whose Gram keys cannot be certified, so the exact kernels recompute them
     from the rows: clusters of about 100 (the 65-128-member kernels) hold more
     such pairs than the list takes and recompute every pair, clusters of
-    about 50 and 30 at d = 512 (the 33-64-member and one-tile kernels) fewer;
-    clusters of about 300 take the tiled kernels for 129-1024 members."""
+    about 50 and 30 at d = 512 (the 17-64-member kernel) fewer; clusters of
+    about 300 take the tiled kernels for 129-1024 members."""
     say("refine duplicate rows", n, d, k)
     rng = np.random.default_rng(d + k)
     base = rng.integers(100, 256, size=(6, d)).astype(np.float32)
