@@ -539,21 +539,40 @@ __global__ __launch_bounds__(256) void k_tm_chunk(int d, const int32_t* __restri
 
 // One block per split node: new centroids from its partials (tiles, or
 // chunks of tiles for nodes with many tiles), added in a fixed order.
+// One block per (split node, 64 of its 2d mean coordinates): the same
+// ordered sum per coordinate as tm_sum_range (wavefront w over the node's
+// tiles or chunks w, w + 4, ..., then ((w0 + w1) + w2) + w3), spread over
+// more blocks.
 __global__ __launch_bounds__(256) void k_tm_final(int d, const int32_t* __restrict__ s_tb,
                                                   const int32_t* __restrict__ s_te,
                                                   const double* __restrict__ partial,
                                                   const int32_t* __restrict__ pcnt,
                                                   float* __restrict__ cent) {
-  __shared__ double sh[4 * 2 * KNNKM_MAX_D];
+  __shared__ double sh[4][64];
   __shared__ int32_t shc[8];
   const int js = blockIdx.x;
-  tm_sum_range(d, s_tb[js], s_te[js], partial, pcnt, sh, shc);
-  const int cu_n = shc[0] + shc[2] + shc[4] + shc[6];
-  const int cv_n = shc[1] + shc[3] + shc[5] + shc[7];
-  for (int e = threadIdx.x; e < 2 * d; e += 256) {
-    const double s = ((sh[e] + sh[2 * d + e]) + sh[4 * d + e]) + sh[6 * d + e];
-    const int cnt = e < d ? cu_n : cv_n;
-    if (cnt > 0) cent[(int64_t)js * 2 * d + e] = (float)(s / (double)cnt);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tb = s_tb[js], te = s_te[js];
+  const int e = 64 * blockIdx.y + lane;
+  if (e < 2 * d) {
+    double a = 0.0;
+    for (int t = tb + w; t < te; t += 4) a += partial[(int64_t)t * 2 * d + e];
+    sh[w][lane] = a;
+  }
+  if (lane == 0) {
+    int nu = 0, nv = 0;
+    for (int t = tb + w; t < te; t += 4) {
+      nu += pcnt[2 * t];
+      nv += pcnt[2 * t + 1];
+    }
+    shc[2 * w] = nu;
+    shc[2 * w + 1] = nv;
+  }
+  __syncthreads();
+  if (w == 0 && e < 2 * d) {
+    const int cnt = e < d ? shc[0] + shc[2] + shc[4] + shc[6] : shc[1] + shc[3] + shc[5] + shc[7];
+    const double a = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+    if (cnt > 0) cent[(int64_t)js * 2 * d + e] = (float)(a / (double)cnt);
   }
 }
 
@@ -1179,12 +1198,11 @@ knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_
         k_tm_chunk<<<L.nchunks, 256, 0, ctx->stream>>>(d, P.d_chunk_tb + L.chunk_base,
                                                        P.d_chunk_te + L.chunk_base, partial, pcnt, cpart,
                                                        ccnt);
-        k_tm_final<<<L.nsplit, 256, 0, ctx->stream>>>(d, P.d_split_cb + L.split_base,
-                                                      P.d_split_ce + L.split_base, cpart, ccnt, cent);
+        k_tm_final<<<dim3(L.nsplit, (2 * d + 63) / 64), 256, 0, ctx->stream>>>(
+            d, P.d_split_cb + L.split_base, P.d_split_ce + L.split_base, cpart, ccnt, cent);
       } else {
-        k_tm_final<<<L.nsplit, 256, 0, ctx->stream>>>(d, P.d_split_tile_begin + L.split_base,
-                                                      P.d_split_tile_end + L.split_base, partial, pcnt,
-                                                      cent);
+        k_tm_final<<<dim3(L.nsplit, (2 * d + 63) / 64), 256, 0, ctx->stream>>>(
+            d, P.d_split_tile_begin + L.split_base, P.d_split_tile_end + L.split_base, partial, pcnt, cent);
       }
     }
     if (L.nsplit) TM_DISPATCH(launch_delta, ctx, P, L, X, d, ldx, perm, cent, keys, vec);
