@@ -498,51 +498,45 @@ __global__ __launch_bounds__(256) void k_tm_accum(const float* __restrict__ X, i
   }
 }
 
-// Partial sums of the entries [tb, te) of `src` in a fixed order: wave w adds
-// entries w, w+4, ... in order into sh[w][.] and its counts into shc[w][.];
-// callers add the four wave sums in wave order.
-__device__ void tm_sum_range(int d, int tb, int te, const double* __restrict__ src,
-                             const int32_t* __restrict__ scnt, double* sh /*[4][2d]*/, int32_t* shc /*[4][2]*/) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int e = lane; e < 2 * d; e += 64) {
-    double s = 0.0;
-    for (int t = tb + w; t < te; t += 4) s += src[(int64_t)t * 2 * d + e];
-    sh[w * 2 * d + e] = s;
-  }
-  if (lane == 0) {
-    int nu = 0, nv = 0;
-    for (int t = tb + w; t < te; t += 4) {
-      nu += scnt[2 * t];
-      nv += scnt[2 * t + 1];
-    }
-    shc[2 * w] = nu;
-    shc[2 * w + 1] = nv;
-  }
-  __syncthreads();
-}
-
-// One block per chunk of tiles: chunk partial = ordered sum of its tiles.
+// Chunk partial = ordered sum of its tiles: one block per (chunk, 64 of the
+// 2d coordinates); per coordinate wavefront w sums tiles w, w + 4, ... in
+// order, then ((w0 + w1) + w2) + w3.
 __global__ __launch_bounds__(256) void k_tm_chunk(int d, const int32_t* __restrict__ c_tb,
                                                   const int32_t* __restrict__ c_te,
                                                   const double* __restrict__ partial,
                                                   const int32_t* __restrict__ pcnt,
                                                   double* __restrict__ cpart, int32_t* __restrict__ ccnt) {
-  __shared__ double sh[4 * 2 * KNNKM_MAX_D];
+  __shared__ double sh[4][64];
   __shared__ int32_t shc[8];
   const int c = blockIdx.x;
-  tm_sum_range(d, c_tb[c], c_te[c], partial, pcnt, sh, shc);
-  for (int e = threadIdx.x; e < 2 * d; e += 256)
-    cpart[(int64_t)c * 2 * d + e] = ((sh[e] + sh[2 * d + e]) + sh[4 * d + e]) + sh[6 * d + e];
-  if (threadIdx.x < 2)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tb = c_tb[c], te = c_te[c];
+  const int e = 64 * blockIdx.y + lane;
+  if (e < 2 * d) {
+    double a = 0.0;
+    for (int t = tb + w; t < te; t += 4) a += partial[(int64_t)t * 2 * d + e];
+    sh[w][lane] = a;
+  }
+  if (blockIdx.y == 0 && lane == 0) {
+    int nu = 0, nv = 0;
+    for (int t = tb + w; t < te; t += 4) {
+      nu += pcnt[2 * t];
+      nv += pcnt[2 * t + 1];
+    }
+    shc[2 * w] = nu;
+    shc[2 * w + 1] = nv;
+  }
+  __syncthreads();
+  if (w == 0 && e < 2 * d) cpart[(int64_t)c * 2 * d + e] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+  if (blockIdx.y == 0 && threadIdx.x < 2)
     ccnt[2 * c + threadIdx.x] = shc[threadIdx.x] + shc[2 + threadIdx.x] + shc[4 + threadIdx.x] + shc[6 + threadIdx.x];
 }
 
-// One block per split node: new centroids from its partials (tiles, or
-// chunks of tiles for nodes with many tiles), added in a fixed order.
-// One block per (split node, 64 of its 2d mean coordinates): the same
-// ordered sum per coordinate as tm_sum_range (wavefront w over the node's
-// tiles or chunks w, w + 4, ..., then ((w0 + w1) + w2) + w3), spread over
-// more blocks.
+// New centroids of the split nodes from their partials (tiles, or chunks of
+// tiles for nodes with many tiles), added in a fixed order: one block per
+// (split node, 64 of its 2d mean coordinates); per coordinate wavefront w
+// sums the node's tiles or chunks w, w + 4, ... in order, then
+// ((w0 + w1) + w2) + w3.
 __global__ __launch_bounds__(256) void k_tm_final(int d, const int32_t* __restrict__ s_tb,
                                                   const int32_t* __restrict__ s_te,
                                                   const double* __restrict__ partial,
@@ -1195,9 +1189,8 @@ knnkm_status ks_twomeans_multi(knnkm_ctx* ctx, const float* X, int32_t d, int64_
       TM_DISPATCH(launch_accum, ctx, P, L, X, d, ldx, perm, cent, partial, pcnt, vec);
       if (L.max_node_tiles > TM_CHUNK) {
         // nodes with many tiles: tiles -> chunks -> node, each stage in fixed order
-        k_tm_chunk<<<L.nchunks, 256, 0, ctx->stream>>>(d, P.d_chunk_tb + L.chunk_base,
-                                                       P.d_chunk_te + L.chunk_base, partial, pcnt, cpart,
-                                                       ccnt);
+        k_tm_chunk<<<dim3(L.nchunks, (2 * d + 63) / 64), 256, 0, ctx->stream>>>(
+            d, P.d_chunk_tb + L.chunk_base, P.d_chunk_te + L.chunk_base, partial, pcnt, cpart, ccnt);
         k_tm_final<<<dim3(L.nsplit, (2 * d + 63) / 64), 256, 0, ctx->stream>>>(
             d, P.d_split_cb + L.split_base, P.d_split_ce + L.split_base, cpart, ccnt, cent);
       } else {
