@@ -124,6 +124,32 @@ __device__ inline bool merge_row(float* __restrict__ rowk, int32_t* __restrict__
   __builtin_amdgcn_wave_barrier();
   if (s0 >= 0) hs[s0] = -1;
   if (s1 >= 0) hs[s1] = -1;
+  // young lists (far more entering candidates than the list holds): drop the
+  // candidates whose key's high word exceeds t, the least value with at least
+  // kappa keys (old entries and entering candidates) of high word <= t --
+  // kappa keys precede each of them, so none can enter and none moves an
+  // entry that stays.  t by bisection between 0 and the kappa-th entry's.
+  int ne = 0;
+#pragma unroll
+  for (int g = 0; g < NC; ++g) ne += __builtin_popcountll(__ballot(enter[g]));
+  if (ne > kappa + 24) {
+    const uint32_t oh0 = lane < kappa ? (uint32_t)(o0 >> 32) : 0xFFFFFFFFu;
+    const uint32_t oh1 = two && lane + 64 < kappa ? (uint32_t)(o1 >> 32) : 0xFFFFFFFFu;
+    uint32_t ch[NC];
+#pragma unroll
+    for (int h = 0; h < NC; ++h) ch[h] = enter[h] ? (uint32_t)(cq[h] >> 32) : 0xFFFFFFFFu;
+    uint32_t lo = 0, hi = (uint32_t)(tk >> 32);
+    for (int it = 0; it < 32 && lo < hi; ++it) {
+      const uint32_t mid = lo + (hi - lo) / 2;
+      int cnt = __builtin_popcountll(__ballot(oh0 <= mid)) + __builtin_popcountll(__ballot(oh1 <= mid));
+#pragma unroll
+      for (int h = 0; h < NC; ++h) cnt += __builtin_popcountll(__ballot(ch[h] <= mid));
+      if (cnt >= kappa) hi = mid; else lo = mid + 1;
+    }
+#pragma unroll
+    for (int h = 0; h < NC; ++h)
+      if (enter[h] && ch[h] > lo) enter[h] = false;
+  }
   // positions of the entering candidates, shifts of the old entries
   int pos[NC];
 #pragma unroll
