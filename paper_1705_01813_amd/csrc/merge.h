@@ -10,12 +10,14 @@
 // left as it is after one comparison per slot.  Otherwise the visited
 // entering candidates are dropped in parallel -- the row's ids go into a
 // small open-addressing table in LDS, one per wavefront, which every
-// entering candidate probes for its id -- and the remaining ones are taken
+// entering candidate probes for its id.  With many more entering than the
+// row holds, those that cannot be among the kappa smallest are dropped
+// after a bisection on the keys' high words.  The remaining ones are taken
 // one at a time (broadcast from their lane): each counts, in one pass, the
 // old entries and the other entering candidates before it (its position)
-// and adds itself to the shift of every old entry after it.  The row's old entries are in ascending (d2, id) order
-// (the graph's invariant), so these counts are the positions in the merged
-// row.
+// and adds itself to the shift of every old entry after it.  The row's old
+// entries are in ascending (d2, id) order (the graph's invariant), so these
+// counts are the positions in the merged row.
 #pragma once
 #include <cfloat>
 #include <cstdint>
