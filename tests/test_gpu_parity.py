@@ -443,6 +443,23 @@ def test_refine_parity(ctx, precision, n, d, kappa, k):
     assert not msg, "second pass changed rows: " + msg
 
 
+@pytest.mark.parametrize("n,k", [(1000, 80), (1500, 30), (1200, 12), (1500, 5)])
+def test_refine_parity_odd_d(ctx, n, k):
+    """d = 13 (rows read element by element, not in 16-byte pieces) for
+    clusters of about 12, 50, 100 and 300 members: every refinement path."""
+    d, kappa = 13, 10
+    say("refine odd d", n, d, kappa, k)
+    X = datagen.mixture(n, d, 7, seed=k + 1)
+    gi0, gd0 = knng.graph_init(X, kappa, seed=13)
+    lab = np.random.default_rng(k + 1).integers(0, k, n).astype(np.int32)
+    want_i, want_d = knng.refine(X, gi0, gd0, lab)
+    for precision in (knnkm.FP32, knnkm.BF16_RERANK):
+        gi, gd = dev(gi0), dev(gd0)
+        knnkm.knnkm_graph_refine(ctx, dev(X), dev(lab), k, precision, gi, gd)
+        msg = _graph_diff(host(gi), host(gd), want_i, want_d, lab)
+        assert not msg, msg
+
+
 @pytest.mark.parametrize("n,k", [(1500, 100), (2000, 40), (4000, 50), (3000, 6)])
 def test_refine_parity_long_lists(ctx, n, k):
     """kappa = 100 (every lane of a merging wavefront holds two list entries)
