@@ -210,6 +210,80 @@ __global__ __launch_bounds__(256) void k_seg_partial(const float* __restrict__ X
   }
 }
 
+// Wide rows (d > 256, rows 16-byte aligned): the same chunk sums, each lane
+// reading four consecutive dimensions per 16-byte load (dimensions
+// 4 lane + 256 t + j); every dimension is still summed over the chunk's
+// members in order, so the partials are those of k_seg_partial.
+template <int T4>
+__global__ __launch_bounds__(256) void k_seg_partial4(const float* __restrict__ X, int d, int64_t ldx,
+                                                      int32_t k, const int32_t* __restrict__ offsets,
+                                                      const int32_t* __restrict__ members,
+                                                      const int32_t* __restrict__ chunk_off,
+                                                      int64_t max_chunks, double* __restrict__ partial) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= max_chunks) return;
+  const int32_t total = chunk_off[k];
+  if (c >= total) return;
+  int lo = 0, hi = k;  // cluster r: chunk_off[r] <= c < chunk_off[r+1]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (chunk_off[mid] <= c) lo = mid; else hi = mid;
+  }
+  const int r = lo;
+  const int64_t p0 = offsets[r] + (c - chunk_off[r]) * SEG_CHUNK;
+  const int64_t p1 = min((int64_t)offsets[r + 1], p0 + SEG_CHUNK);
+  double acc[T4][4];
+#pragma unroll
+  for (int t = 0; t < T4; ++t) acc[t][0] = acc[t][1] = acc[t][2] = acc[t][3] = 0.0;
+  auto add = [&](double (&a)[4], float4 v) {
+    a[0] += (double)v.x;
+    a[1] += (double)v.y;
+    a[2] += (double)v.z;
+    a[3] += (double)v.w;
+  };
+  int64_t p = p0;
+  for (; p + 4 <= p1; p += 4) {
+    const float* r0 = X + (int64_t)members[p] * ldx;
+    const float* r1 = X + (int64_t)members[p + 1] * ldx;
+    const float* r2 = X + (int64_t)members[p + 2] * ldx;
+    const float* r3 = X + (int64_t)members[p + 3] * ldx;
+#pragma unroll
+    for (int t = 0; t < T4; ++t) {
+      const int dim = 4 * lane + 256 * t;
+      if (dim < d) {
+        const float4 v0 = *reinterpret_cast<const float4*>(r0 + dim);
+        const float4 v1 = *reinterpret_cast<const float4*>(r1 + dim);
+        const float4 v2 = *reinterpret_cast<const float4*>(r2 + dim);
+        const float4 v3 = *reinterpret_cast<const float4*>(r3 + dim);
+        add(acc[t], v0);
+        add(acc[t], v1);
+        add(acc[t], v2);
+        add(acc[t], v3);
+      }
+    }
+  }
+  for (; p < p1; ++p) {
+    const float* r0 = X + (int64_t)members[p] * ldx;
+#pragma unroll
+    for (int t = 0; t < T4; ++t) {
+      const int dim = 4 * lane + 256 * t;
+      if (dim < d) add(acc[t], *reinterpret_cast<const float4*>(r0 + dim));
+    }
+  }
+  double* out = partial + c * d;
+#pragma unroll
+  for (int t = 0; t < T4; ++t) {
+    const int dim = 4 * lane + 256 * t;
+    if (dim < d) {
+      out[dim] = acc[t][0];
+      out[dim + 1] = acc[t][1];
+      out[dim + 2] = acc[t][2];
+      out[dim + 3] = acc[t][3];
+    }
+  }
+}
+
 template <int T>
 __global__ __launch_bounds__(256) void k_seg_final(int d, int32_t k, const int32_t* __restrict__ counts,
                                                    const int32_t* __restrict__ chunk_off,
@@ -269,9 +343,14 @@ knnkm_status ks_segsum(knnkm_ctx* ctx, const float* X, int64_t n, int32_t d, int
   KNNKM_WS(ctx, partial, double, "seg_partial", max_chunks * d);
   const int T = (d + 63) / 64;
   const unsigned gp = (unsigned)((max_chunks + 3) / 4), gf = (unsigned)((k + 3) / 4);
+  const bool wide4 = d > 256 && d % 4 == 0 && ldx % 4 == 0 && (uintptr_t)X % 16 == 0;
 #define SEG(TT)                                                                                        \
-  k_seg_partial<TT><<<gp, 256, 0, ctx->stream>>>(X, d, ldx, k, offsets, members, cc, max_chunks,      \
-                                                 partial);                                             \
+  if (wide4)                                                                                           \
+    k_seg_partial4<2><<<gp, 256, 0, ctx->stream>>>(X, d, ldx, k, offsets, members, cc, max_chunks,    \
+                                                   partial);                                           \
+  else                                                                                                 \
+    k_seg_partial<TT><<<gp, 256, 0, ctx->stream>>>(X, d, ldx, k, offsets, members, cc, max_chunks,    \
+                                                   partial);                                           \
   k_seg_final<TT><<<gf, 256, 0, ctx->stream>>>(d, k, counts, cc, partial, C, sums, Iterm, delta)
   switch (T) {
     case 1: SEG(1); break;
